@@ -1,0 +1,454 @@
+"""FP64 CPU oracle for the wide-range scattering simulation (arXiv 2303.13435).
+
+TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the benchmark's
+CPU-baseline leg may import this package.  It is the plain, slow, obviously
+correct statement of the computation, written from the paper:
+
+* O1  unit-cell density (workflow step 1; "Electron density generation")
+* O2  ED-1 = tiled cell x particle mask (workflow step 2)
+* O3  zoomed-out ED-2/ED-3 by block integration and zero padding (step 3)
+* O4  3D transform, eq. 1 (axis by axis, as eq. 2 separates it)
+* O5-O8  |Q| map, integer-threshold bins, per-bin mean and SEM (step 5)
+* O9  merge of zoom levels into one curve (step 6; reading in ``merge``)
+* O10 chi^2 misfit of a binned curve and its gradients (derived from eq. 1)
+* O11 low-frequency Fourier coefficients by direct summation (eq. 1/eq. 2)
+
+The heavy loops live in ``ur_oracle.c`` (plain C, FP64, OpenMP over
+independent lines); this module marshals numpy arrays and holds the small
+per-bin arithmetic (merge, chi^2) written out in numpy.
+
+It shares no code with the HIP library; the only common import is the seeded
+input generator package ``workloads``, which holds none of the arithmetic.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+from typing import Dict, List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "ur_oracle.c")
+_LIBPATH = os.path.join(_HERE, "liboracle.so")
+_LIB = None
+
+_D = ctypes.POINTER(ctypes.c_double)
+_LL = ctypes.POINTER(ctypes.c_longlong)
+
+
+def build(force: bool = True) -> str:
+    """Compile the C oracle with gcc (FP64, no FMA contraction, OpenMP)."""
+    if force or not os.path.exists(_LIBPATH):
+        tmp = _LIBPATH + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
+               "-fPIC", "-shared", "-D_GNU_SOURCE", _SRC, "-o", tmp, "-lm"]
+        subprocess.check_call(cmd)
+        os.replace(tmp, _LIBPATH)
+    return _LIBPATH
+
+
+def lib():
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(_LIBPATH):
+            build(force=False)
+        L = ctypes.CDLL(_LIBPATH)
+        L.or_atom_profile.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, _D]
+        L.or_cell_synth.argtypes = [ctypes.c_int, ctypes.c_int, _D, _D, _D, ctypes.c_double, _D]
+        L.or_mask_inside.argtypes = [ctypes.c_int] + [ctypes.c_longlong] * 5
+        L.or_mask_inside.restype = ctypes.c_int
+        L.or_ed1.argtypes = [ctypes.c_int, ctypes.c_int, _D, ctypes.c_int, ctypes.c_longlong,
+                             ctypes.c_longlong, _D]
+        L.or_zoom.argtypes = [ctypes.c_int, ctypes.c_int, _D, ctypes.c_int, ctypes.c_longlong,
+                              ctypes.c_longlong, ctypes.c_int, ctypes.c_int, _D]
+        L.or_fft3d.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_int]
+        L.or_fft1d_batch.argtypes = [ctypes.c_int, ctypes.c_longlong, ctypes.c_void_p, ctypes.c_int]
+        L.or_thresholds.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_int, _D, _LL]
+        L.or_bin.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_double, ctypes.c_int, _D,
+                             _D, _D, _D, _D, _D, _D]
+        L.or_bin_counts.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_int, _D, _D]
+        L.or_lowfreq_dft.argtypes = [ctypes.c_int, ctypes.c_int, _D, ctypes.c_int, ctypes.c_longlong,
+                                     ctypes.c_longlong, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                     ctypes.c_void_p]
+        L.or_density_moments.argtypes = [ctypes.c_int, ctypes.c_int, _D, ctypes.c_int,
+                                         ctypes.c_longlong, ctypes.c_longlong, ctypes.c_int,
+                                         ctypes.c_int, _D]
+        L.or_num_threads.restype = ctypes.c_int
+        L.or_set_num_threads.argtypes = [ctypes.c_int]
+        _LIB = L
+    return _LIB
+
+
+def _dp(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(_D)
+
+
+def num_threads() -> int:
+    return int(lib().or_num_threads())
+
+
+def set_num_threads(t: int) -> None:
+    lib().or_set_num_threads(int(t))
+
+
+# ---------------------------------------------------------------------------
+# O1  unit cell
+# ---------------------------------------------------------------------------
+
+def atom_profile(c: int, x: float, sigma: float) -> np.ndarray:
+    """Voxel-integrated periodic Gaussian along one axis (sums to 1)."""
+    p = np.zeros(c)
+    lib().or_atom_profile(int(c), float(x), float(sigma), _dp(p))
+    return p
+
+
+def atom_profiles(cell) -> np.ndarray:
+    """(n_atoms, 3, c) array of per-axis profiles."""
+    out = np.zeros((cell.n_atoms, 3, cell.c))
+    for a in range(cell.n_atoms):
+        for d in range(3):
+            out[a, d] = atom_profile(cell.c, cell.xyz[a, d], cell.sigma[a])
+    return out
+
+
+def cell_synth(cell) -> np.ndarray:
+    c = int(cell.c)
+    out = np.zeros((c, c, c))
+    xyz = np.ascontiguousarray(cell.xyz, dtype=np.float64).reshape(-1)
+    amp = np.ascontiguousarray(cell.amp, dtype=np.float64)
+    sig = np.ascontiguousarray(cell.sigma, dtype=np.float64)
+    if xyz.size == 0:
+        xyz = np.zeros(3)
+        amp = np.zeros(1)
+        sig = np.ones(1)
+        lib().or_cell_synth(c, 0, _dp(xyz), _dp(amp), _dp(sig), float(cell.background), _dp(out))
+    else:
+        lib().or_cell_synth(c, cell.n_atoms, _dp(xyz), _dp(amp), _dp(sig), float(cell.background),
+                            _dp(out))
+    return out
+
+
+# ---------------------------------------------------------------------------
+# O2/O3  densities
+# ---------------------------------------------------------------------------
+
+def mask_inside(mask, dx: int, dy: int, dz: int) -> bool:
+    return bool(lib().or_mask_inside(int(mask.kind), int(mask.p0), int(mask.p1), int(dx), int(dy), int(dz)))
+
+
+def ed1(n: int, cell_grid: np.ndarray, mask) -> np.ndarray:
+    c = cell_grid.shape[0]
+    cg = np.ascontiguousarray(cell_grid, dtype=np.float64)
+    out = np.empty((n, n, n))
+    lib().or_ed1(int(n), int(c), _dp(cg), int(mask.kind), int(mask.p0), int(mask.p1), _dp(out))
+    return out
+
+
+def zoomed(n1: int, cell_grid: np.ndarray, mask, f: int, nk: int) -> np.ndarray:
+    c = cell_grid.shape[0]
+    cg = np.ascontiguousarray(cell_grid, dtype=np.float64)
+    out = np.empty((nk, nk, nk))
+    lib().or_zoom(int(n1), int(c), _dp(cg), int(mask.kind), int(mask.p0), int(mask.p1), int(f),
+                  int(nk), _dp(out))
+    return out
+
+
+def density(wl, cell_grid: Optional[np.ndarray] = None) -> np.ndarray:
+    """Real-space box of a workload: ED-1 (factor 1) or a zoomed level."""
+    if cell_grid is None:
+        cell_grid = cell_synth(wl.cell)
+    if wl.zoom.factor == 1 and wl.zoom.n1 == wl.n:
+        return ed1(wl.n, cell_grid, wl.mask)
+    return zoomed(wl.zoom.n1, cell_grid, wl.mask, wl.zoom.factor, wl.n)
+
+
+# ---------------------------------------------------------------------------
+# O4  transform
+# ---------------------------------------------------------------------------
+
+def fft3d(a: np.ndarray, sign: int = -1) -> np.ndarray:
+    """Unnormalised 3D DFT (sign -1 forward, +1 inverse) of an n^3 array."""
+    n = a.shape[0]
+    assert a.shape == (n, n, n)
+    z = np.ascontiguousarray(a, dtype=np.complex128).copy()
+    lib().or_fft3d(int(n), z.ctypes.data_as(ctypes.c_void_p), int(sign))
+    return z
+
+
+def fft1d(a: np.ndarray, sign: int = -1) -> np.ndarray:
+    """Unnormalised 1D DFT along the last axis."""
+    n = a.shape[-1]
+    z = np.ascontiguousarray(a, dtype=np.complex128).copy()
+    lib().or_fft1d_batch(int(n), int(z.size // n), z.ctypes.data_as(ctypes.c_void_p), int(sign))
+    return z
+
+
+def forward(rho: np.ndarray) -> np.ndarray:
+    """F of eq. 1: the forward DFT scaled by 1/(M N L)."""
+    n = rho.shape[0]
+    return fft3d(rho, -1) / float(n) ** 3
+
+
+# ---------------------------------------------------------------------------
+# O5-O8  binning
+# ---------------------------------------------------------------------------
+
+def thresholds(n: int, voxel: float, edges: np.ndarray) -> np.ndarray:
+    e = np.ascontiguousarray(edges, dtype=np.float64)
+    U = np.zeros(e.size, dtype=np.int64)
+    lib().or_thresholds(int(n), float(voxel), int(e.size - 1), _dp(e), U.ctypes.data_as(_LL))
+    return U
+
+
+def bin_spectrum(F: np.ndarray, voxel: float, edges: np.ndarray) -> Dict[str, np.ndarray]:
+    """Per-bin count / sum / sumsq / mean / sem of I = |F|^2 over the full
+    (n^3) spectrum F, plus totals = [sum of all I, Re F(0), Im F(0)]."""
+    n = F.shape[0]
+    Fc = np.ascontiguousarray(F, dtype=np.complex128)
+    e = np.ascontiguousarray(edges, dtype=np.float64)
+    nb = e.size - 1
+    out = {k: np.zeros(nb) for k in ("count", "sum", "sumsq", "mean", "sem")}
+    tot = np.zeros(3)
+    lib().or_bin(int(n), Fc.ctypes.data_as(ctypes.c_void_p), float(voxel), int(nb), _dp(e),
+                 _dp(out["count"]), _dp(out["sum"]), _dp(out["sumsq"]), _dp(out["mean"]),
+                 _dp(out["sem"]), _dp(tot))
+    out["totals"] = tot
+    return out
+
+
+def bin_counts(n: int, voxel: float, edges: np.ndarray) -> np.ndarray:
+    e = np.ascontiguousarray(edges, dtype=np.float64)
+    out = np.zeros(e.size - 1)
+    lib().or_bin_counts(int(n), float(voxel), int(e.size - 1), _dp(e), _dp(out))
+    return out
+
+
+def simulate(wl, return_fields: bool = False):
+    """Whole forward path of one box: density -> eq. 1 -> per-bin statistics.
+    Also reports the density moments sum(rho) and sum(rho^2)."""
+    cg = cell_synth(wl.cell)
+    rho = density(wl, cg)
+    F = forward(rho)
+    res = bin_spectrum(F, wl.voxel, wl.edges)
+    res["rho_sum"] = float(rho.sum(dtype=np.float64))
+    res["rho_sumsq"] = float(np.sum(rho * rho))
+    if return_fields:
+        res["rho"] = rho
+        res["F"] = F
+        res["cell"] = cg
+    return res
+
+
+# ---------------------------------------------------------------------------
+# O11  low-frequency coefficients by direct summation
+# ---------------------------------------------------------------------------
+
+def lowfreq_dft(wl, K: int, cell_grid: Optional[np.ndarray] = None) -> np.ndarray:
+    """F(h, k, l) of eq. 1 for |h|,|k|,|l| <= K, array index [h+K][k+K][l+K]."""
+    if cell_grid is None:
+        cell_grid = cell_synth(wl.cell)
+    cg = np.ascontiguousarray(cell_grid, dtype=np.float64)
+    nf = 2 * K + 1
+    out = np.zeros((nf, nf, nf), dtype=np.complex128)
+    lib().or_lowfreq_dft(int(wl.zoom.n1), int(cg.shape[0]), _dp(cg), int(wl.mask.kind),
+                         int(wl.mask.p0), int(wl.mask.p1), int(wl.zoom.factor), int(wl.n), int(K),
+                         out.ctypes.data_as(ctypes.c_void_p))
+    return out
+
+
+def density_moments(wl, cell_grid: Optional[np.ndarray] = None):
+    if cell_grid is None:
+        cell_grid = cell_synth(wl.cell)
+    cg = np.ascontiguousarray(cell_grid, dtype=np.float64)
+    out = np.zeros(2)
+    lib().or_density_moments(int(wl.zoom.n1), int(cg.shape[0]), _dp(cg), int(wl.mask.kind),
+                             int(wl.mask.p0), int(wl.mask.p1), int(wl.zoom.factor), int(wl.n),
+                             _dp(out))
+    return float(out[0]), float(out[1])
+
+
+def lowfreq_bins(wl, K: int, cell_grid: Optional[np.ndarray] = None):
+    """Exact per-bin count/sum/mean for every bin whose voxels all satisfy
+    |h|,|k|,|l| <= K (i.e. bins lying wholly below n2 = (K+1)^2).  Returns
+    (bin indices, count, sum, mean)."""
+    F = lowfreq_dft(wl, K, cell_grid)
+    U = thresholds(wl.n, wl.voxel, wl.edges)
+    nb = wl.nbins
+    r = np.arange(-K, K + 1)
+    h2 = r[:, None, None] ** 2 + r[None, :, None] ** 2 + r[None, None, :] ** 2
+    I = np.abs(F) ** 2
+    limit = (K + 1) ** 2      # every voxel with n2 < limit lies inside the cube
+    sel = [b for b in range(nb) if U[b + 1] <= limit and U[b + 1] > U[b]]
+    cnt = np.zeros(len(sel))
+    s = np.zeros(len(sel))
+    for i, b in enumerate(sel):
+        m = (h2 >= U[b]) & (h2 < U[b + 1])
+        cnt[i] = m.sum()
+        s[i] = I[m].sum()
+    mean = np.where(cnt > 0, s / np.maximum(cnt, 1), np.nan)
+    return np.array(sel, dtype=np.int64), cnt, s, mean
+
+
+# ---------------------------------------------------------------------------
+# O9  merge of zoom levels
+# ---------------------------------------------------------------------------
+MERGE_FINEST, MERGE_POOLED, MERGE_IVW = 0, 1, 2
+
+
+def bin_centres(edges: np.ndarray) -> np.ndarray:
+    lo, hi = edges[:-1], edges[1:]
+    return np.where(lo > 0, np.sqrt(np.abs(lo * hi)), 0.5 * (lo + hi))
+
+
+def sem_from_sums(count, s, s2):
+    count = np.asarray(count, dtype=np.float64)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        var = (np.asarray(s2) - np.asarray(s) ** 2 / count) / (count - 1.0)
+        var = np.maximum(var, 0.0)
+        return np.where(count > 1, np.sqrt(var / count), np.nan)
+
+
+def merge(levels: Sequence[dict], edges: np.ndarray, mode: int = MERGE_FINEST, n_min: float = 32.0):
+    """One curve from several zoom levels (workflow step 6).
+
+    The paper merges with dataMerge, whose rule it does not give.  Reading
+    taken here: each level's eq.-1 intensities are scaled back to absolute
+    |sum rho e^{-iqx}|^2 by s_k = (n_k^3)^2; a level is *valid* for a bin when
+    the bin centre lies in [dq_k, Q_cut,k], Q_cut,k = sqrt(3) pi / (2 voxel_k)
+    (beyond half the corner frequency artefacts appear, Fig. 2 caption) and
+    the bin holds at least ``n_min`` voxels at that level.
+
+    * FINEST: the finest valid level owns the bin (mean and SEM scaled by s_k)
+    * POOLED: pooled scaled sums and counts over the valid levels
+    * IVW:    inverse-variance weighted mean of the valid levels' means
+
+    ``levels``: dicts with n, voxel, count, sum, sumsq (per bin).  Returns
+    (mean, sem, owner) with owner = -1 / NaN where no level is valid; for
+    POOLED and IVW owner is the number of contributing levels.
+    """
+    nb = edges.size - 1
+    qc = bin_centres(np.asarray(edges, dtype=np.float64))
+    order = sorted(range(len(levels)), key=lambda k: levels[k]["voxel"])
+    mean = np.full(nb, np.nan)
+    sem = np.full(nb, np.nan)
+    owner = np.full(nb, -1, dtype=np.int64)
+    for b in range(nb):
+        valid = []
+        for k in order:
+            L = levels[k]
+            dq = 2.0 * math.pi / (L["n"] * L["voxel"])
+            qcut = math.sqrt(3.0) * math.pi / (2.0 * L["voxel"])
+            if dq <= qc[b] <= qcut and L["count"][b] >= n_min:
+                valid.append(k)
+        if not valid:
+            continue
+        if mode == MERGE_FINEST:
+            k = valid[0]
+            L = levels[k]
+            s = float(L["n"]) ** 6
+            cnt, sm, s2 = L["count"][b], L["sum"][b], L["sumsq"][b]
+            mean[b] = s * sm / cnt
+            sem[b] = s * float(sem_from_sums(np.array([cnt]), np.array([sm]), np.array([s2]))[0])
+            owner[b] = k
+        elif mode == MERGE_POOLED:
+            C = S1 = S2 = 0.0
+            for k in valid:
+                L = levels[k]
+                s = float(L["n"]) ** 6
+                C += L["count"][b]
+                S1 += s * L["sum"][b]
+                S2 += s * s * L["sumsq"][b]
+            mean[b] = S1 / C
+            sem[b] = float(sem_from_sums(np.array([C]), np.array([S1]), np.array([S2]))[0])
+            owner[b] = len(valid)
+        else:
+            W = WM = 0.0
+            for k in valid:
+                L = levels[k]
+                s = float(L["n"]) ** 6
+                cnt = L["count"][b]
+                m = s * L["sum"][b] / cnt
+                e = s * float(sem_from_sums(np.array([cnt]), np.array([L["sum"][b]]),
+                                            np.array([L["sumsq"][b]]))[0])
+                if not (e > 0.0 and np.isfinite(e)):
+                    continue
+                W += 1.0 / (e * e)
+                WM += m / (e * e)
+            if W > 0.0:
+                mean[b] = WM / W
+                sem[b] = 1.0 / math.sqrt(W)
+                owner[b] = len(valid)
+    return mean, sem, owner
+
+
+# ---------------------------------------------------------------------------
+# O10  chi^2 misfit and gradients (derived from eq. 1)
+# ---------------------------------------------------------------------------
+
+def chi2(mean: np.ndarray, count: np.ndarray, target: np.ndarray, rel_sigma: float = 0.01) -> float:
+    """chi^2 = sum over populated bins of ((I_b - T_b) / (rel_sigma T_b))^2."""
+    m = count > 0
+    r = (mean[m] - target[m]) / (rel_sigma * target[m])
+    return float(np.sum(r * r))
+
+
+def chi2_bin_grad(mean, count, target, rel_sigma: float = 0.01) -> np.ndarray:
+    """d chi^2 / d I_b = 2 (I_b - T_b) / (rel_sigma T_b)^2 (0 for empty bins)."""
+    g = np.zeros_like(mean)
+    m = count > 0
+    g[m] = 2.0 * (mean[m] - target[m]) / (rel_sigma * target[m]) ** 2
+    return g
+
+
+def grad_rho(F: np.ndarray, voxel: float, edges: np.ndarray, count: np.ndarray,
+             g_bin: np.ndarray) -> np.ndarray:
+    """Gradient of L(I_b) with respect to every voxel density, given
+    g_b = dL/dI_b.  With I_b = (1/count_b) sum_{q in b} |F(q)|^2 and eq. 1,
+    dI_b/drho(x) = (2/count_b) sum_q Re(conj F(q) e^{-iqx}) / n^3, hence
+    grad = 2 Re(IFFT(G * F)) with G(q) = g_{b(q)}/count_{b(q)} (0 for
+    unbinned q) and IFFT carrying 1/n^3."""
+    n = F.shape[0]
+    U = thresholds(n, voxel, edges)
+    nb = edges.size - 1
+    idx = np.arange(n)
+    h = np.where(idx < n // 2, idx, idx - n)
+    n2 = h[:, None, None] ** 2 + h[None, :, None] ** 2 + h[None, None, :] ** 2
+    b = np.searchsorted(U, n2, side="right") - 1
+    ok = (n2 >= U[0]) & (n2 < U[nb])
+    Gb = np.where(count > 0, g_bin / np.maximum(count, 1.0), 0.0)
+    G = np.zeros(n2.shape)
+    G[ok] = Gb[b[ok]]
+    H = fft3d(G * F, +1) / float(n) ** 3
+    return 2.0 * H.real
+
+
+def fold_to_cell(grad: np.ndarray, n1: int, c: int, mask) -> np.ndarray:
+    """Sum of a per-voxel field over every inside voxel that maps to each
+    cell voxel (the adjoint of tiling + masking, O2)."""
+    n = grad.shape[0]
+    assert n == n1
+    h = n // 2
+    inside = ed1(n, np.ones((c, c, c)), mask)       # mask as 0/1 field
+    g = grad * inside
+    out = np.zeros((c, c, c))
+    idx = (np.arange(n) - h) % c
+    for i in range(c):
+        gi = g[idx == i]
+        for j in range(c):
+            gij = gi[:, idx == j]
+            for k in range(c):
+                out[i, j, k] = gij[:, :, idx == k].sum()
+    return out
+
+
+def grad_amp(grad_rho_field: np.ndarray, cell, mask) -> np.ndarray:
+    """d L / d amp_a = sum over inside voxels of grad_rho(x) * p_a(cell(x)),
+    p_a the atom's separable voxel profile (O1)."""
+    n = grad_rho_field.shape[0]
+    folded = fold_to_cell(grad_rho_field, n, cell.c, mask)
+    P = atom_profiles(cell)
+    return np.einsum("ijk,ai,aj,ak->a", folded, P[:, 0], P[:, 1], P[:, 2])

@@ -1,0 +1,446 @@
+"""Pins of the FP64 oracle against facts fixed by the paper and by mathematics.
+
+Each pin is chosen so that a plausible slip in the oracle (a dropped term, a
+wrong sign or index, a transposed operand, an off-by-one in a threshold)
+breaks at least one of them.  None of them re-types the oracle's own code.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def brute_dft3(rho):
+    """eq. 1 evaluated as a plain triple sum (with its 1/(MNL) factor),
+    written as three explicit DFT-matrix contractions."""
+    n = rho.shape[0]
+    k = np.arange(n)
+    Wm = np.exp(-2j * np.pi * np.outer(k, k) / n)
+    return np.einsum("ux,vy,wz,xyz->uvw", Wm, Wm, Wm, rho.astype(np.complex128)) / n ** 3
+
+
+def r3_table():
+    vals = []
+    with open(os.path.join(GOLDEN, "r3_sum_of_three_squares.txt")) as fh:
+        for line in fh:
+            if line.startswith("#") or not line.strip():
+                continue
+            vals += [int(t) for t in line.split()]
+    return np.array(vals)
+
+
+# ---------------------------------------------------------------------------
+# O4  transform
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n", [8, 16])
+def test_fft3d_matches_brute_force_dft(oracle_lib, n):
+    rng = np.random.default_rng(n)
+    rho = rng.standard_normal((n, n, n))
+    F = oracle_lib.forward(rho)
+    ref = brute_dft3(rho)
+    assert np.max(np.abs(F - ref)) <= 1e-14 * np.max(np.abs(ref)) * n
+
+
+@pytest.mark.parametrize("n", [2, 4, 8, 32, 256, 4096])
+def test_fft1d_matches_library_routine(oracle_lib, n):
+    rng = np.random.default_rng(n)
+    a = rng.standard_normal((3, n)) + 1j * rng.standard_normal((3, n))
+    ours = oracle_lib.fft1d(a, -1)
+    lib = np.fft.fft(a, axis=-1)
+    assert np.max(np.abs(ours - lib)) <= 1e-13 * np.max(np.abs(lib))
+    back = oracle_lib.fft1d(ours, +1) / n
+    assert np.max(np.abs(back - a)) <= 1e-14 * np.max(np.abs(a)) * math.log2(max(n, 2))
+
+
+@pytest.mark.parametrize("n", [32, 64])
+def test_fft3d_matches_library_fftn(oracle_lib, n):
+    rng = np.random.default_rng(100 + n)
+    rho = rng.standard_normal((n, n, n))
+    F = oracle_lib.fft3d(rho, -1)
+    ref = np.fft.fftn(rho)
+    assert np.max(np.abs(F - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+def test_parseval_and_delta(oracle_lib):
+    n = 32
+    rng = np.random.default_rng(5)
+    rho = rng.standard_normal((n, n, n))
+    F = oracle_lib.forward(rho)
+    # eq. 1 carries 1/n^3, so sum|F|^2 = sum rho^2 / n^3
+    assert abs(np.sum(np.abs(F) ** 2) - np.sum(rho ** 2) / n ** 3) <= 1e-13 * np.sum(rho ** 2) / n ** 3
+    d = np.zeros((n, n, n))
+    d[3, 7, 11] = 1.0
+    I = np.abs(oracle_lib.forward(d)) ** 2
+    assert np.allclose(I, n ** -6.0, rtol=1e-13, atol=0)
+    # a single delta has a pure phase: F(u,v,w) = exp(-2 pi i (3u+7v+11w)/n) / n^3
+    Fd = oracle_lib.forward(d)
+    assert abs(Fd[1, 0, 0] - np.exp(-2j * np.pi * 3 / n) / n ** 3) < 1e-18
+    assert abs(Fd[0, 0, 1] - np.exp(-2j * np.pi * 11 / n) / n ** 3) < 1e-18
+
+
+# ---------------------------------------------------------------------------
+# O1  unit cell
+# ---------------------------------------------------------------------------
+
+def test_atom_profile_integrates_gaussian(oracle_lib):
+    from scipy.integrate import quad
+    c, x, s = 8, 6.7, 0.55
+    p = oracle_lib.atom_profile(c, x, s)
+    assert abs(p.sum() - 1.0) < 1e-14
+    g = lambda t: math.exp(-0.5 * ((t - x) / s) ** 2) / (s * math.sqrt(2 * math.pi))
+    for i in range(c):
+        # periodic images: voxel i collects the Gaussian over i + m*c
+        ref = sum(quad(g, i - 0.5 + m * c, i + 0.5 + m * c, epsabs=1e-15, epsrel=1e-13)[0]
+                  for m in (-1, 0, 1))
+        assert abs(p[i] - ref) < 1e-12
+
+
+def test_cell_electron_count_and_symmetry(oracle_lib):
+    cell = W.draw_atoms(11, 7, 16, background=0.25)
+    g = oracle_lib.cell_synth(cell)
+    assert abs(g.sum() - (0.25 * 16 ** 3 + cell.amp.sum())) < 1e-11
+    # an atom at the cell centre gives a mirror-symmetric cell about that centre
+    one = W.single_atom_cell(8, 3.0, 0.7, 0.0, pos=(4.0, 4.0, 4.0))
+    h = oracle_lib.cell_synth(one)
+    idx = (8 - np.arange(8)) % 8
+    assert np.allclose(h, h[idx][:, idx][:, :, idx], rtol=0, atol=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# O2  tiling and masks
+# ---------------------------------------------------------------------------
+
+def test_unmasked_tiling_is_a_comb(oracle_lib):
+    """Without a mask the box is the cell repeated n/c times per axis: the
+    spectrum vanishes off the comb u = 0 mod n/c and on the comb equals the
+    cell's own DFT / c^3 (Bragg peaks at Q = 2 pi h / (c voxel))."""
+    n, c = 32, 8
+    cell = W.draw_atoms(3, 5, c)
+    g = oracle_lib.cell_synth(cell)
+    rho = oracle_lib.ed1(n, g, W.no_mask())
+    F = oracle_lib.forward(rho)
+    step = n // c
+    on = np.zeros((n, n, n), dtype=bool)
+    on[::step, ::step, ::step] = True
+    assert np.max(np.abs(F[~on])) < 1e-14 * np.max(np.abs(F))
+    Fc = brute_dft3(g)     # = DFT_c(cell) / c^3
+    sign = (-1.0) ** (np.add.outer(np.add.outer(np.arange(c), np.arange(c)), np.arange(c)) * step)
+    assert np.max(np.abs(F[::step, ::step, ::step] - Fc * sign)) < 1e-13 * np.max(np.abs(Fc))
+
+
+def test_mask_voxel_counts_are_lattice_point_counts(oracle_lib):
+    n = 64
+    ones = np.ones((4, 4, 4))
+    for R2 in (0, 1, 2, 3, 50, 144, 300):
+        rho = oracle_lib.ed1(n, ones, W.Mask(W.MASK_SPHERE, R2))
+        # points of Z^3 in the ball |d|^2 <= R2: sum of r3 over shells
+        r3 = r3_table()
+        if R2 < len(r3):
+            assert rho.sum() == r3[: R2 + 1].sum()
+        # and a direct count over (dx, dy) with an integer root for dz
+        cnt = 0
+        R = int(math.isqrt(R2))
+        for dx in range(-R, R + 1):
+            for dy in range(-R, R + 1):
+                rem = R2 - dx * dx - dy * dy
+                if rem >= 0:
+                    cnt += 2 * math.isqrt(rem) + 1
+        assert rho.sum() == cnt
+    # truncated octahedron: max|d| <= a and sum|d| <= b
+    a, b = 5, 8
+    rho = oracle_lib.ed1(n, ones, W.Mask(W.MASK_TRUNC_OCT, a, b))
+    cnt = sum(1 for x in range(-a, a + 1) for y in range(-a, a + 1) for z in range(-a, a + 1)
+              if abs(x) + abs(y) + abs(z) <= b)
+    assert rho.sum() == cnt
+    assert rho[n // 2 + a, n // 2, n // 2] == 1 and rho[n // 2 + a + 1, n // 2, n // 2] == 0
+    assert oracle_lib.ed1(n, ones, W.Mask(W.MASK_SPHERE, -1)).sum() == 0
+
+
+def test_cube_mask_dirichlet_closed_form(oracle_lib):
+    """Uniform cube of half-width h: |F|^2 = prod_axes D(u)^2 with the Dirichlet
+    kernel D(u) = sin(pi u (2h+1)/n) / (n sin(pi u / n)), D(0) = (2h+1)/n."""
+    n, h = 32, 5
+    rho = oracle_lib.ed1(n, np.ones((4, 4, 4)), W.cube(h))
+    I = np.abs(oracle_lib.forward(rho)) ** 2
+    u = np.arange(n)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        D = np.sin(np.pi * u * (2 * h + 1) / n) / (n * np.sin(np.pi * u / n))
+    D[0] = (2 * h + 1) / n
+    ref = (D[:, None, None] * D[None, :, None] * D[None, None, :]) ** 2
+    assert np.max(np.abs(I - ref)) < 1e-15
+
+
+# ---------------------------------------------------------------------------
+# O3  zoom
+# ---------------------------------------------------------------------------
+
+def test_zoom_block_sum(oracle_lib):
+    n1, f, nk, c = 32, 4, 16, 8
+    cell = W.draw_atoms(9, 6, c)
+    g = oracle_lib.cell_synth(cell)
+    mask = W.sphere(11.0)
+    rho1 = oracle_lib.ed1(n1, g, mask)
+    rk = oracle_lib.zoomed(n1, g, mask, f, nk)
+    m = n1 // f
+    o = (nk - m) // 2
+    blocks = rho1.reshape(m, f, m, f, m, f).sum(axis=(1, 3, 5))
+    ref = np.zeros((nk, nk, nk))
+    ref[o:o + m, o:o + m, o:o + m] = blocks
+    assert np.max(np.abs(rk - ref)) < 1e-12
+    assert abs(rk.sum() - rho1.sum()) < 1e-10 * abs(rho1.sum())
+
+
+# ---------------------------------------------------------------------------
+# O5-O8  binning
+# ---------------------------------------------------------------------------
+
+def test_linear_bin_thresholds_closed_form(oracle_lib):
+    """C1 bins: 64 linear bins on [0, pi/voxel] of a 64^3 box are half a
+    frequency step wide, so edge b sits at n2 = b^2/4: U_b = ceil(b^2/4)."""
+    wl = W.c1()
+    U = oracle_lib.thresholds(wl.n, wl.voxel, wl.edges)
+    b = np.arange(64)
+    assert np.array_equal(U[:64], -((-(b * b)) // 4))
+    assert U[64] == 32 * 32 + 1      # last edge inclusive: n2 = 1024 is in
+    # log bins from dq to the corner: first threshold 1, last 3 n^2/4 inclusive
+    wl2 = W.small(64, nbins=50)
+    U2 = oracle_lib.thresholds(64, 1.0, wl2.edges)
+    assert U2[0] == 1 and U2[-1] == 3 * 32 * 32 + 1
+
+
+def test_bin_counts_are_shell_counts(oracle_lib):
+    n = 32
+    edges = W.lin_edges(0.0, math.pi, 64)     # U_b = ceil(b^2/4) as above
+    cnt = oracle_lib.bin_counts(n, 1.0, edges)
+    U = oracle_lib.thresholds(n, 1.0, edges)
+    r3 = r3_table()
+    for b in range(64):
+        if U[b + 1] - 1 < len(r3):
+            assert cnt[b] == r3[U[b]:U[b + 1]].sum(), b
+    # every voxel is binned once or left out: total = voxels with n2 <= 256
+    h = np.where(np.arange(n) < n // 2, np.arange(n), np.arange(n) - n)
+    n2 = h[:, None, None] ** 2 + h[None, :, None] ** 2 + h[None, None, :] ** 2
+    assert cnt.sum() == np.count_nonzero(n2 <= 256)
+
+
+def test_bin_statistics_of_constructed_spectra(oracle_lib):
+    n = 16
+    edges = W.lin_edges(0.0, math.pi, 16)
+    # constant |F|: every populated bin has mean |c|^2 and zero spread
+    F = np.full((n, n, n), 0.3 - 0.4j)
+    r = oracle_lib.bin_spectrum(F, 1.0, edges)
+    pop = r["count"] > 0
+    assert np.allclose(r["mean"][pop], 0.25, rtol=1e-15)
+    assert np.all(r["sem"][r["count"] > 1] < 1e-16)
+    assert np.all(np.isnan(r["mean"][~pop]))
+    assert abs(r["totals"][0] - 0.25 * n ** 3) < 1e-10
+    # |F|^2 = n2: the mean over a bin is the mean of n2 over its shells,
+    # sum_m m r3(m) / sum_m r3(m)
+    h = np.where(np.arange(n) < n // 2, np.arange(n), np.arange(n) - n)
+    n2 = (h[:, None, None] ** 2 + h[None, :, None] ** 2 + h[None, None, :] ** 2).astype(float)
+    r = oracle_lib.bin_spectrum(np.sqrt(n2).astype(complex), 1.0, edges)
+    U = oracle_lib.thresholds(n, 1.0, edges)
+    r3 = r3_table()
+    for b in range(16):
+        if U[b + 1] > len(r3):
+            break
+        m = np.arange(U[b], U[b + 1])
+        w = r3[m]
+        if w.sum() > 0:
+            assert abs(r["mean"][b] - (m * w).sum() / w.sum()) < 1e-12
+            assert r["count"][b] == w.sum()
+
+
+def test_circular_shift_leaves_bins_unchanged(oracle_lib):
+    wl = W.small(32, c=8, n_atoms=5, radius=9.0, nbins=40)
+    g = oracle_lib.cell_synth(wl.cell)
+    rho = oracle_lib.ed1(32, g, wl.mask)
+    a = oracle_lib.bin_spectrum(oracle_lib.forward(rho), 1.0, wl.edges)
+    b = oracle_lib.bin_spectrum(oracle_lib.forward(np.roll(rho, (3, -5, 7), axis=(0, 1, 2))),
+                                1.0, wl.edges)
+    pop = a["count"] > 0
+    assert np.allclose(a["mean"][pop], b["mean"][pop], rtol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# whole forward path against physics
+# ---------------------------------------------------------------------------
+
+def test_uniform_sphere_form_factor(oracle_lib):
+    """A uniform voxelised sphere follows the continuous form factor
+    [3 (sin qR - qR cos qR)/(qR)^3]^2 at low q (R from the voxel volume)."""
+    n, R = 128, 16.0
+    wl = W.Workload("sph", n, 1.0, W.PREC_F64, "r2c", W.empty_cell(4, 1.0), W.sphere(R),
+                    W.Zoom(n, 1), W.lin_edges(0.0, math.pi, 64))
+    rho = oracle_lib.density(wl)
+    F = oracle_lib.forward(rho)
+    V = rho.sum()
+    Reff = (3.0 * V / (4.0 * math.pi)) ** (1.0 / 3.0)
+    I0 = (V / n ** 3) ** 2
+    assert abs(abs(F[0, 0, 0]) ** 2 - I0) < 1e-12 * I0
+    dq = 2 * math.pi / n
+    for (u, v, w) in [(1, 0, 0), (0, 2, 0), (2, 2, 1), (3, 0, 0), (0, 4, 3)]:
+        q = dq * math.sqrt(u * u + v * v + w * w)
+        x = q * Reff
+        ff = (3 * (math.sin(x) - x * math.cos(x)) / x ** 3) ** 2
+        assert abs(abs(F[u, v, w]) ** 2 / I0 - ff) < 0.02 * max(ff, 0.05), (u, v, w)
+    # the first zero of the form factor sits at qR = 4.493: deep minimum there
+    u0 = 4.493 / Reff / dq
+    near = np.abs(F[int(round(u0)), 0, 0]) ** 2 / I0
+    assert near < 0.02
+
+
+def test_lowfreq_direct_sum_matches_transform(oracle_lib):
+    """O11 (direct summation in the order of eq. 2) against O4 (recursive
+    FFT): two independent routes to the same coefficients."""
+    wl = W.small(32, c=8, n_atoms=6, radius=10.0, nbins=30)
+    g = oracle_lib.cell_synth(wl.cell)
+    F = oracle_lib.forward(oracle_lib.density(wl, g))
+    K = 3
+    D = oracle_lib.lowfreq_dft(wl, K, g)
+    r = np.arange(-K, K + 1) % 32
+    ref = F[np.ix_(r, r, r)]
+    assert np.max(np.abs(D - ref)) < 1e-14 * np.max(np.abs(ref)) * 10
+    # zoomed level (factor 2 into a 32 box from a 32 ED-1)
+    wz = W.Workload("z", 32, 2.0, W.PREC_F64, "r2c", wl.cell, wl.mask, W.Zoom(32, 2), wl.edges)
+    Fz = oracle_lib.forward(oracle_lib.density(wz, g))
+    Dz = oracle_lib.lowfreq_dft(wz, K, g)
+    assert np.max(np.abs(Dz - Fz[np.ix_(r, r, r)])) < 1e-13 * np.max(np.abs(Fz))
+    s1, s2 = oracle_lib.density_moments(wz, g)
+    rz = oracle_lib.density(wz, g)
+    assert abs(s1 - rz.sum()) < 1e-11 * abs(s1) and abs(s2 - (rz ** 2).sum()) < 1e-11 * s2
+
+
+def test_lowfreq_bins_match_full_binning(oracle_lib):
+    wl = W.small(32, c=8, n_atoms=6, radius=10.0, nbins=200)
+    g = oracle_lib.cell_synth(wl.cell)
+    full = oracle_lib.bin_spectrum(oracle_lib.forward(oracle_lib.density(wl, g)), wl.voxel, wl.edges)
+    sel, cnt, s, mean = oracle_lib.lowfreq_bins(wl, 4, g)
+    assert len(sel) > 10
+    assert np.array_equal(cnt, full["count"][sel])
+    assert np.allclose(mean, full["mean"][sel], rtol=1e-12, equal_nan=True)
+
+
+# ---------------------------------------------------------------------------
+# O9  merge
+# ---------------------------------------------------------------------------
+
+def _level(n, voxel, count, mean, spread):
+    count = np.asarray(count, dtype=float)
+    s = count * mean
+    s2 = count * (mean ** 2 + spread ** 2)
+    return {"n": n, "voxel": voxel, "count": count, "sum": s, "sumsq": s2}
+
+
+def test_merge_rules_on_constructed_levels(oracle_lib):
+    edges = np.array([0.002, 0.004, 0.02, 0.2, 1.0, 2.0, 4.0])
+    nb = 6
+    # fine level: n=64, voxel 1  -> dq = 0.098, qcut = 2.72
+    # coarse level: n=64, voxel 8 -> dq = 0.0123, qcut = 0.34
+    fine = _level(64, 1.0, [0, 0, 40, 100, 100, 100], np.full(nb, 2.0) / 64.0 ** 6, 0.5 / 64.0 ** 6)
+    coarse = _level(64, 8.0, [0, 40, 40, 40, 40, 40], np.full(nb, 3.0) / 64.0 ** 6, 0.5 / 64.0 ** 6)
+    mean, sem, owner = oracle_lib.merge([coarse, fine], edges, oracle_lib.MERGE_FINEST, 32)
+    qc = oracle_lib.bin_centres(edges)
+    # bin 0: centre 0.0028 below both dq -> no owner
+    assert owner[0] == -1 and np.isnan(mean[0])
+    # bin 1 (centre 0.0089 < dq_coarse 0.0123): no owner either
+    assert owner[1] == -1
+    # bin 2 (0.063): coarse valid (0.0123..0.34), fine not (below 0.098) -> coarse
+    assert owner[2] == 0 and abs(mean[2] - 3.0) < 1e-12
+    # bin 3 (0.447): beyond coarse qcut, fine valid -> fine
+    assert owner[3] == 1 and abs(mean[3] - 2.0) < 1e-12
+    # SEM of the owner: sqrt(var * c/(c-1) / c) with var = spread^2
+    c = 100.0
+    assert abs(sem[3] - math.sqrt(0.25 * c / (c - 1) / c)) < 1e-12
+    # bin 5 (2.83) beyond the fine cut 2.72 -> no owner
+    assert qc[5] > math.sqrt(3) * math.pi / 2 and owner[5] == -1
+    # pooled with a single valid level equals that level; IVW likewise
+    mp, sp, op = oracle_lib.merge([coarse, fine], edges, oracle_lib.MERGE_POOLED, 32)
+    assert abs(mp[3] - 2.0) < 1e-12 and op[3] == 1
+    # n_min above the available counts removes the owner
+    m2, _, o2 = oracle_lib.merge([coarse, fine], edges, oracle_lib.MERGE_FINEST, 101)
+    assert o2[3] == -1
+
+
+def test_merge_pooled_and_ivw_two_levels(oracle_lib):
+    """Two levels both valid for one bin (centre 0.141): a (n 256, voxel 0.2:
+    dq 0.123, cut 13.6) and b (n 128, voxel 0.5: dq 0.098, cut 5.44)."""
+    edges = np.array([0.1, 0.2])
+    a = _level(256, 0.2, [50], np.array([4.0]) / 256.0 ** 6, 1.0 / 256.0 ** 6)
+    b = _level(128, 0.5, [150], np.array([2.0]) / 128.0 ** 6, 2.0 / 128.0 ** 6)
+    mp, sp, op = oracle_lib.merge([a, b], edges, oracle_lib.MERGE_POOLED, 32)
+    assert op[0] == 2
+    assert abs(mp[0] - (50 * 4.0 + 150 * 2.0) / 200.0) < 1e-12
+    # pooled spread: (sum of count*(m^2+s^2) - C*mean^2) / (C-1), SEM = sqrt(var/C)
+    var = (50 * 17.0 + 150 * 8.0 - 200 * 2.5 ** 2) / 199.0
+    assert abs(sp[0] - math.sqrt(var / 200.0)) < 1e-12
+    mi, si, oi = oracle_lib.merge([a, b], edges, oracle_lib.MERGE_IVW, 32)
+    ea = 1.0 / math.sqrt(49.0)          # SEM = spread / sqrt(count - 1)
+    eb = 2.0 / math.sqrt(149.0)
+    wa, wb = 1 / ea ** 2, 1 / eb ** 2
+    assert abs(mi[0] - (wa * 4.0 + wb * 2.0) / (wa + wb)) < 1e-10
+    assert abs(si[0] - 1 / math.sqrt(wa + wb)) < 1e-10
+    mf, _, of = oracle_lib.merge([a, b], edges, oracle_lib.MERGE_FINEST, 32)
+    assert of[0] == 0 and abs(mf[0] - 4.0) < 1e-12    # a has the smaller voxel
+
+
+# ---------------------------------------------------------------------------
+# O10  chi^2 gradients against finite differences of the forward oracle
+# ---------------------------------------------------------------------------
+
+def _forward_curve(oracle_lib, rho, wl):
+    F = oracle_lib.forward(rho)
+    r = oracle_lib.bin_spectrum(F, wl.voxel, wl.edges)
+    return F, r
+
+
+def test_grad_rho_matches_central_differences(oracle_lib):
+    wl = W.small(16, c=4, n_atoms=3, radius=5.0, nbins=12)
+    g = oracle_lib.cell_synth(wl.cell)
+    rho = oracle_lib.density(wl, g)
+    rng = np.random.default_rng(1)
+    target_rho = rho * (1 + 0.05 * rng.standard_normal(rho.shape))
+    _, tr = _forward_curve(oracle_lib, target_rho, wl)
+    T = np.where(tr["count"] > 0, tr["mean"], 1.0)
+    F, r = _forward_curve(oracle_lib, rho, wl)
+    gb = oracle_lib.chi2_bin_grad(r["mean"], r["count"], T)
+    grad = oracle_lib.grad_rho(F, wl.voxel, wl.edges, r["count"], gb)
+    h = 1e-4
+    for (x, y, z) in [(8, 8, 8), (5, 9, 7), (0, 0, 0), (12, 3, 8)]:
+        rp = rho.copy(); rp[x, y, z] += h
+        rm = rho.copy(); rm[x, y, z] -= h
+        _, a = _forward_curve(oracle_lib, rp, wl)
+        _, b = _forward_curve(oracle_lib, rm, wl)
+        fd = (oracle_lib.chi2(a["mean"], a["count"], T) - oracle_lib.chi2(b["mean"], b["count"], T)) / (2 * h)
+        assert abs(fd - grad[x, y, z]) <= 1e-6 * max(1.0, abs(fd)), (x, y, z, fd, grad[x, y, z])
+
+
+def test_grad_amp_matches_central_differences(oracle_lib):
+    wl = W.small(16, c=4, n_atoms=3, radius=5.0, nbins=12)
+    cell = wl.cell
+    tgt = cell.with_amp(cell.amp * np.array([1.05, 0.97, 1.02]))
+    wt = W.Workload("t", wl.n, wl.voxel, wl.prec, wl.transform, tgt, wl.mask, wl.zoom, wl.edges)
+    tr = oracle_lib.simulate(wt)
+    T = np.where(tr["count"] > 0, tr["mean"], 1.0)
+
+    def loss(c):
+        w2 = W.Workload("x", wl.n, wl.voxel, wl.prec, wl.transform, c, wl.mask, wl.zoom, wl.edges)
+        r = oracle_lib.simulate(w2, return_fields=True)
+        return oracle_lib.chi2(r["mean"], r["count"], T), r
+
+    L0, r = loss(cell)
+    gb = oracle_lib.chi2_bin_grad(r["mean"], r["count"], T)
+    grho = oracle_lib.grad_rho(r["F"], wl.voxel, wl.edges, r["count"], gb)
+    ga = oracle_lib.grad_amp(grho, cell, wl.mask)
+    h = 1e-4
+    for a in range(cell.n_atoms):
+        up = cell.amp.copy(); up[a] += h
+        dn = cell.amp.copy(); dn[a] -= h
+        fd = (loss(cell.with_amp(up))[0] - loss(cell.with_amp(dn))[0]) / (2 * h)
+        assert abs(fd - ga[a]) <= 1e-6 * max(1.0, abs(fd)), (a, fd, ga[a])

@@ -1,0 +1,278 @@
+"""Seeded synthetic inputs for the wide-range scattering simulation.
+
+This package only *draws and lays out inputs*: unit-cell atom lists, particle
+mask parameters, bin edges, zoom geometry and the named workload recipes.  It
+holds none of the method's arithmetic (no density synthesis, no Fourier
+transform, no binning, no merging), so both the FP64 oracle and the HIP path
+can consume it without sharing any computation.
+
+The paper's own inputs (a DFT electron density of a ZIF-8 unit cell, 630^3
+voxels, block-reduced to 105^3; Methodology, "Electron density generation")
+are not available.  They are stood in for by cubic unit cells filled with
+isotropic Gaussian "atoms" whose positions, electron counts and widths are
+drawn from a seeded ``numpy.random.default_rng``.
+
+Random draws happen in a fixed order per recipe: positions U[0, c)^3,
+amplitudes U[1, 30), widths U[0.3, 0.8).  The arrays are passed as data to
+both sides, so no random number generator is reimplemented anywhere.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field, replace
+from typing import List, Optional
+
+import numpy as np
+
+# Mask kinds (integer codes shared by the C ABI header and the oracle API).
+MASK_NONE = 0
+MASK_SPHERE = 1
+MASK_CUBE = 2
+MASK_TRUNC_OCT = 3
+
+PREC_F32 = 0
+PREC_F64 = 1
+
+
+@dataclass(frozen=True)
+class Cell:
+    """Unit cell of edge ``c`` voxels holding Gaussian atoms.
+
+    ``xyz`` are atom centres in cell-voxel units in [0, c) (voxel i spans
+    [i - 1/2, i + 1/2]); ``amp`` is the electron count carried by each atom;
+    ``sigma`` the Gaussian width in voxels; ``background`` a uniform density
+    added to every cell voxel.
+    """
+
+    c: int
+    xyz: np.ndarray
+    amp: np.ndarray
+    sigma: np.ndarray
+    background: float = 0.0
+
+    @property
+    def n_atoms(self) -> int:
+        return int(self.amp.shape[0])
+
+    def with_amp(self, amp: np.ndarray) -> "Cell":
+        return replace(self, amp=np.ascontiguousarray(amp, dtype=np.float64))
+
+
+@dataclass(frozen=True)
+class Mask:
+    """Particle shape, centred on voxel (N1/2, N1/2, N1/2) of the ED-1 grid.
+
+    Integer parameters so that the inside test is exact integer arithmetic on
+    the offset d = (x, y, z) - N1/2:
+
+    * SPHERE:    d.d <= p0                       (p0 = floor(R^2))
+    * CUBE:      max |d_i| <= p0                 (p0 = half-width)
+    * TRUNC_OCT: max |d_i| <= p0 and sum |d_i| <= p1
+                 (p0 = floor(2R/sqrt5), p1 = floor(3R/sqrt5): the truncated
+                 octahedron inscribed in a sphere of radius R)
+    * NONE:      every voxel inside (p0, p1 ignored)
+
+    An empty particle is expressed with p0 < 0.
+    """
+
+    kind: int
+    p0: int = 0
+    p1: int = 0
+
+
+@dataclass(frozen=True)
+class Zoom:
+    """Zoom level: the ED-1 grid of edge ``n1`` block-summed by ``factor``
+    per axis and centred in the box of the level that uses it."""
+
+    n1: int
+    factor: int = 1
+
+
+@dataclass(frozen=True)
+class Workload:
+    name: str
+    n: int                 # box edge (voxels)
+    voxel: float           # voxel edge of this box, nm (or unit-less 1.0)
+    prec: int              # PREC_F32 / PREC_F64
+    transform: str         # "r2c" or "c2c"
+    cell: Cell
+    mask: Mask
+    zoom: Zoom
+    edges: np.ndarray      # nbins + 1 strictly increasing bin edges (nm^-1)
+    notes: str = ""
+
+    @property
+    def nbins(self) -> int:
+        return int(self.edges.shape[0] - 1)
+
+
+# ----------------------------------------------------------------------------
+# primitive draws / parameter helpers
+# ----------------------------------------------------------------------------
+
+def draw_atoms(seed: int, n_atoms: int, c: int, background: float = 0.0) -> Cell:
+    """Gaussian atoms for a cubic cell of edge ``c``: positions U[0,c)^3,
+    amplitudes U[1,30) electrons, widths U[0.3,0.8) voxel, in that order."""
+    rng = np.random.default_rng(seed)
+    xyz = rng.uniform(0.0, float(c), size=(n_atoms, 3))
+    amp = rng.uniform(1.0, 30.0, size=n_atoms)
+    sigma = rng.uniform(0.3, 0.8, size=n_atoms)
+    return Cell(c=c, xyz=np.ascontiguousarray(xyz), amp=np.ascontiguousarray(amp),
+                sigma=np.ascontiguousarray(sigma), background=float(background))
+
+
+def single_atom_cell(c: int, amp: float, sigma: float, background: float,
+                     pos=(0.0, 0.0, 0.0)) -> Cell:
+    return Cell(c=c, xyz=np.array([pos], dtype=np.float64),
+                amp=np.array([amp], dtype=np.float64),
+                sigma=np.array([sigma], dtype=np.float64), background=float(background))
+
+
+def empty_cell(c: int, background: float = 1.0) -> Cell:
+    z = np.zeros((0,), dtype=np.float64)
+    return Cell(c=c, xyz=np.zeros((0, 3)), amp=z, sigma=z.copy(), background=float(background))
+
+
+def sphere(radius: float) -> Mask:
+    return Mask(MASK_SPHERE, int(math.floor(radius * radius + 1e-9)), 0)
+
+
+def cube(half_width: int) -> Mask:
+    return Mask(MASK_CUBE, int(half_width), 0)
+
+
+def trunc_oct(radius: float) -> Mask:
+    return Mask(MASK_TRUNC_OCT, int(math.floor(2.0 * radius / math.sqrt(5.0))),
+                int(math.floor(3.0 * radius / math.sqrt(5.0))))
+
+
+def no_mask() -> Mask:
+    return Mask(MASK_NONE, 0, 0)
+
+
+def log_edges(lo: float, hi: float, nbins: int) -> np.ndarray:
+    i = np.arange(nbins + 1, dtype=np.float64)
+    e = lo * (hi / lo) ** (i / nbins)
+    e[0], e[-1] = lo, hi
+    return e
+
+
+def lin_edges(lo: float, hi: float, nbins: int) -> np.ndarray:
+    i = np.arange(nbins + 1, dtype=np.float64)
+    return lo + (hi - lo) * i / nbins
+
+
+def q_step(n: int, voxel: float) -> float:
+    """Frequency spacing 2*pi/(n*voxel) of a box: the bin-range recipe uses it
+    to choose edges (it is an input choice, not part of the computation)."""
+    return 2.0 * math.pi / (n * voxel)
+
+
+def default_log_edges(n: int, voxel: float, nbins: int) -> np.ndarray:
+    """Log bins from the first shell to the box corner: [dq, sqrt(3)*pi/voxel]."""
+    return log_edges(q_step(n, voxel), math.sqrt(3.0) * math.pi / voxel, nbins)
+
+
+def random_voxels(seed: int, n: int, count: int) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    return rng.integers(0, n, size=(count, 3), dtype=np.int64)
+
+
+def perturbed_amplitudes(cell: Cell, seed: int, rel: float = 0.05) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    return cell.amp * (1.0 + rel * rng.standard_normal(cell.n_atoms))
+
+
+def random_density(seed: int, n: int, dtype=np.float64) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((n, n, n)).astype(dtype)
+
+
+# ----------------------------------------------------------------------------
+# named workloads
+# ----------------------------------------------------------------------------
+
+def c1() -> Workload:
+    """64^3 FP64 box, voxel 0.5 nm: uniform sphere (R = 12 voxels, density
+    1.0) with a simple-cubic lattice (period 4) of Gaussian blobs
+    (sigma 0.6 voxel, 2.0 electrons) inside; 64 linear bins [0, pi/voxel]."""
+    cell = single_atom_cell(4, 2.0, 0.6, 1.0)
+    return Workload("C1", 64, 0.5, PREC_F64, "c2c", cell, sphere(12.0), Zoom(64, 1),
+                    lin_edges(0.0, math.pi / 0.5, 64), "full complex transform")
+
+
+def lattice_sphere(name: str, n: int, c: int, n_atoms: int, seed: int, radius: float,
+                   nbins: int, prec: int = PREC_F32, voxel: float = 1.0) -> Workload:
+    cell = draw_atoms(seed, n_atoms, c)
+    return Workload(name, n, voxel, prec, "r2c", cell, sphere(radius), Zoom(n, 1),
+                    default_log_edges(n, voxel, nbins))
+
+
+def c2() -> Workload:
+    """512^3 FP32: 16-voxel cell with 40 atoms (seed 2), sphere R = 200,
+    512 log bins."""
+    return lattice_sphere("C2", 512, 16, 40, 2, 200.0, 512)
+
+
+def m1024(prec: int = PREC_F32) -> Workload:
+    """1024^3 headline box: the C2 recipe scaled by two (sphere R = 400),
+    512 log bins."""
+    return lattice_sphere("M1024" + ("_f64" if prec == PREC_F64 else ""), 1024, 16, 40, 2,
+                          400.0, 512, prec)
+
+
+def c4() -> Workload:
+    """256^3 FP32 differentiable box: 40 atoms (seed 4), sphere R = 100,
+    256 log bins."""
+    return lattice_sphere("C4", 256, 16, 40, 4, 100.0, 256)
+
+
+def c3_levels() -> List[Workload]:
+    """Multi-zoom batch: ED-1 2048^3 (64-voxel cell, 40 atoms, seed 3, sphere
+    R = 900), ED-2 1024^3 (block factor 4) and ED-3 512^3 (factor 16), all
+    binned on one set of 1024 log edges spanning four decades that end at the
+    ED-1 corner frequency sqrt(3)*pi/voxel1."""
+    cell = draw_atoms(3, 40, 64)
+    mask = sphere(900.0)
+    hi = math.sqrt(3.0) * math.pi / 1.0
+    edges = log_edges(hi * 1e-4, hi, 1024)
+    out = []
+    for name, n, f in (("C3-ED1", 2048, 1), ("C3-ED2", 1024, 4), ("C3-ED3", 512, 16)):
+        out.append(Workload(name, n, float(f), PREC_F32, "r2c", cell, mask, Zoom(2048, f), edges))
+    return out
+
+
+def zoom_levels(n1: int, c: int, n_atoms: int, seed: int, radius: float, levels, nbins: int,
+                decades: float = 4.0) -> List[Workload]:
+    """Scaled-down multi-zoom family with the C3 structure: ``levels`` is a
+    list of (box edge, block factor)."""
+    cell = draw_atoms(seed, n_atoms, c)
+    mask = sphere(radius)
+    hi = math.sqrt(3.0) * math.pi
+    edges = log_edges(hi * 10.0 ** (-decades), hi, nbins)
+    return [Workload(f"Z{n}f{f}", n, float(f), PREC_F32, "r2c", cell, mask, Zoom(n1, f), edges)
+            for (n, f) in levels]
+
+
+def c5(n: int = 4096) -> Workload:
+    """Out-of-core box: 128-voxel cell with 200 atoms (seed 5), truncated
+    octahedron inscribed in R = 1900 (scaled with n), 2048 log bins."""
+    cell = draw_atoms(5, 200, 128)
+    r = 1900.0 * n / 4096
+    return Workload(f"C5_{n}", n, 1.0, PREC_F32, "r2c", cell, trunc_oct(r), Zoom(n, 1),
+                    default_log_edges(n, 1.0, 2048 if n >= 2048 else 512))
+
+
+def small(n: int, c: int = 8, n_atoms: int = 10, seed: int = 7, radius: Optional[float] = None,
+          nbins: int = 64, prec: int = PREC_F32, mask: Optional[Mask] = None,
+          voxel: float = 1.0, transform: str = "r2c") -> Workload:
+    """Small lattice-in-sphere box for parity tests."""
+    cell = draw_atoms(seed, n_atoms, c)
+    if mask is None:
+        mask = sphere(radius if radius is not None else 0.39 * n)
+    return Workload(f"S{n}", n, voxel, prec, transform, cell, mask, Zoom(n, 1),
+                    default_log_edges(n, voxel, nbins))
+
+
+CONFIGS = {"C1": c1, "C2": c2, "M1024": m1024, "C4": c4}
