@@ -1,0 +1,230 @@
+/*
+ * ultima.h -- C ABI of the MI355X (gfx950) wide-range scattering simulator.
+ *
+ * The library computes, on one GPU, the hot path of the "Ultima Ratio"
+ * method (Pauw et al., arXiv 2303.13435):
+ *
+ *   1. electron density (ED) of a particle: a unit-cell density tiled over a
+ *      box and multiplied by a particle mask (Methodology, general workflow
+ *      steps 1-2, "Electron density generation"), optionally block-summed
+ *      into a zoomed-out level ED-2/ED-3 (step 3);
+ *   2. its 3D Fourier transform, eq. 1, evaluated as 1D transforms along z,
+ *      y and x (the separation of eq. 2);
+ *   3. the intensity |F|^2 averaged into |Q| bins (step 5, "Q-calculation and
+ *      spherical averaging");
+ *   4. the merge of several zoom levels into one curve (step 6);
+ *   5. the adjoint of 1-3: gradients of a loss on the binned curve with
+ *      respect to voxel densities and atom amplitudes (derived from eq. 1).
+ *
+ * General conventions
+ *   - Every call returns ur_status (UR_OK = 0).  On failure nothing has been
+ *     enqueued, and ur_last_error() describes the problem (thread-local text,
+ *     valid until the next call on the same thread).  No C++ exception and no
+ *     abort crosses this boundary.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ *     device work is enqueued on it asynchronously; outputs are valid after
+ *     the stream is synchronised.  A plan must not run on two streams at once.
+ *   - Pointers documented as DEVICE point to memory of the current HIP
+ *     device, owned by the caller; HOST pointers are read during the call
+ *     only.  The library never frees caller memory.
+ *   - Box layout: real densities are [x][y][z] row-major, z fastest, edge n
+ *     (a power of two, 16 <= n <= 4096).  The particle and the lattice are
+ *     centred on voxel (n1/2, n1/2, n1/2) of the ED-1 grid.
+ *   - Spectra exchanged through ur_fft3d_exec / ur_intensity_bin use the
+ *     transposed layout [kz][ky][kx] (kx fastest, complex interleaved), with
+ *     kz in [0, n/2] for real transforms and [0, n) for complex ones.  This is
+ *     the order in which the last transform pass produces them.
+ *   - Frequencies: u in [0, n) stands for the signed index h = u (u < n/2) or
+ *     u - n; |Q| = dq * sqrt(h^2 + k^2 + l^2) with dq = 2 pi / (n voxel).
+ */
+#ifndef ULTIMA_H
+#define ULTIMA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  UR_OK = 0,
+  UR_ERR_INVALID = 1,      /* bad argument (null pointer, size, range)        */
+  UR_ERR_UNSUPPORTED = 2,  /* valid request this build does not implement     */
+  UR_ERR_OOM = 3,          /* device allocation failed                        */
+  UR_ERR_HIP = 4,          /* a HIP runtime call failed                       */
+  UR_ERR_STATE = 6         /* call out of order (e.g. no bins set on the plan) */
+} ur_status;
+
+typedef enum { UR_F32 = 0, UR_F64 = 1 } ur_prec;
+
+/* plan flags */
+#define UR_R2C 0u         /* real input, half spectrum (default)              */
+#define UR_C2C 1u         /* full complex transform of a real or complex box  */
+
+/* mask kinds (integer parameters make the inside test exact):
+ *   UR_MASK_SPHERE     d.d <= p0
+ *   UR_MASK_CUBE       max|d_i| <= p0
+ *   UR_MASK_TRUNC_OCT  max|d_i| <= p0 and |d_x|+|d_y|+|d_z| <= p1
+ * with d the voxel offset from the particle centre.  p0 < 0 gives an empty
+ * particle.  (Methodology, "Electron density generation": the per-plane
+ * circular mask that builds up a spherical particle.) */
+#define UR_MASK_NONE 0
+#define UR_MASK_SPHERE 1
+#define UR_MASK_CUBE 2
+#define UR_MASK_TRUNC_OCT 3
+
+typedef struct { int32_t kind; int64_t p0; int64_t p1; } ur_mask;
+
+/* Unit cell ("ED-Unit", workflow step 1).  Edge c voxels (power of two
+ * dividing n1/2); n_atoms Gaussian atoms.  DEVICE arrays, FP64:
+ * xyz[3*n_atoms] centres in cell-voxel units, amp[n_atoms] electrons per atom,
+ * sigma[n_atoms] widths in voxels.  Each voxel holds the Gaussian integrated
+ * over it, with periodic images, plus `background`. */
+typedef struct {
+  int32_t c;
+  int32_t n_atoms;
+  const double* xyz;
+  const double* amp;
+  const double* sigma;
+  double background;
+} ur_cell;
+
+/* Zoom level (workflow step 3): the ED-1 grid of edge n1 is block-summed by
+ * `factor` per axis and centred in this plan's box (offset
+ * (n - n1/factor)/2).  factor = 1 and n1 = n is ED-1 itself. */
+typedef struct { int32_t n1; int32_t factor; } ur_zoom;
+
+/* Per-bin statistics, DEVICE arrays of nbins doubles each, written by the
+ * library: sum of w*I, sum of w*I^2 and sum of w over the voxels of the bin
+ * (w counts a voxel of the half spectrum twice when it stands for its
+ * conjugate partner too, so every statistic is that of the full n^3 box).
+ * totals (DEVICE, 4 doubles): [0] sum of I over every voxel (binned or not),
+ * [1] Re F(0), [2] Im F(0), [3] sum of rho^2 over the box (0 when the density
+ * was not generated or loaded by the call).  I = |F|^2 with F of eq. 1. */
+typedef struct { double* sum; double* sumsq; double* count; double* totals; } ur_hist;
+
+typedef struct ur_plan ur_plan;
+
+/* Create a plan for an n^3 box of voxel edge `voxel` (nm, > 0) in precision
+ * `prec`.  flags: UR_R2C or UR_C2C.  Allocates the plan's device tables
+ * (twiddles) with hipMalloc; the large work buffers are either attached with
+ * ur_plan_set_workspace or allocated lazily on first use. */
+ur_status ur_plan_create(int32_t n, double voxel, int32_t prec, uint32_t flags, ur_plan** out);
+void ur_plan_destroy(ur_plan* plan);
+
+/* Bytes of device workspace the plan needs for `nbins` bins (transform
+ * buffers, partial histograms, cell tables). */
+ur_status ur_plan_workspace_size(const ur_plan* plan, int32_t nbins, size_t* bytes);
+/* Attach caller-owned device workspace (>= the size above, 256-B aligned). */
+ur_status ur_plan_set_workspace(ur_plan* plan, void* dev_ptr, size_t bytes);
+
+/* Set the |Q| bins: nbins >= 1 strictly increasing edges (HOST, nm^-1).  The
+ * edges become integer thresholds on n2 = h^2+k^2+l^2: t = (e/dq)^2 snapped
+ * to the nearest integer within 1e-9 relative; bin b holds
+ * ceil(t_b) <= n2 < ceil(t_b+1); the last upper edge is inclusive.  Copies a
+ * small table to the device synchronously; call before capture. */
+ur_status ur_plan_set_bins(ur_plan* plan, int32_t nbins, const double* edges);
+
+/* Unit-cell density: writes the c^3 values (DEVICE, FP64, [i][j][k]) of the
+ * cell, using the plan's scratch for the per-atom profiles. */
+ur_status ur_cell_synth(ur_plan* plan, const ur_cell* cell, double* cell_out, void* stream);
+
+/* Materialise the ED of this plan's box (tiled cell x mask, optionally
+ * zoomed) as n^3 reals of the plan precision at `rho` (DEVICE). */
+ur_status ur_rho_generate(ur_plan* plan, const ur_cell* cell, const ur_mask* mask,
+                          const ur_zoom* zoom, void* rho, void* stream);
+
+/* 3D transform of eq. 1.  dir = -1: forward, scaled by 1/n^3; input `in`
+ * real [x][y][z] (UR_R2C) or complex [x][y][z] (UR_C2C); output `out`
+ * spectrum [kz][ky][kx].  dir = +1: inverse, unscaled; input spectrum, output
+ * real (UR_R2C, the half spectrum is taken as Hermitian) or complex box.
+ * in and out must not overlap. */
+ur_status ur_fft3d_exec(ur_plan* plan, const void* in, void* out, int32_t dir, void* stream);
+
+/* Bin I = |F|^2 of a spectrum already in the [kz][ky][kx] layout (DEVICE). */
+ur_status ur_intensity_bin(ur_plan* plan, const void* spectrum, const ur_hist* hist, void* stream);
+
+/* Fused forward path from the unit cell: generate ED (tile + mask + zoom)
+ * inside the first transform pass, transform, and bin |F|^2 inside the last
+ * pass; planes, pencils and rows that lie outside the particle are skipped.
+ * The cell is synthesised on the device from its atoms in the same call. */
+ur_status ur_simulate(ur_plan* plan, const ur_cell* cell, const ur_mask* mask,
+                      const ur_zoom* zoom, const ur_hist* hist, void* stream);
+
+/* Fused forward path from a given density (DEVICE, n^3 reals of the plan
+ * precision, [x][y][z]). */
+ur_status ur_simulate_rho(ur_plan* plan, const void* rho, const ur_hist* hist, void* stream);
+
+/* Out-of-core forward path (the 2D + 1D separation of eq. 2): `rho_host` is
+ * HOST memory (pinned, e.g. hipHostMalloc, for full PCIe speed) holding the
+ * n^3 density [x][y][z].  Planes outside [x_lo, x_hi] are taken as zero and
+ * never copied ("only the slices with nonzero density"); slabs of planes
+ * are copied to the device on a copy stream, double buffered, while the
+ * previous slab goes through the z and y passes on `stream`; the x pass with
+ * binning runs once every slab is in.  Only one slab of the first
+ * intermediate and the x-range of the final spectrum live in HBM.  The host
+ * buffer must stay valid until the stream is synchronised.  *h2d_bytes (when
+ * non-null) receives the bytes copied host to device. */
+ur_status ur_simulate_host(ur_plan* plan, const void* rho_host, int32_t x_lo, int32_t x_hi,
+                           const ur_hist* hist, void* stream, size_t* h2d_bytes);
+/* Device workspace of the out-of-core path for planes [x_lo, x_hi]. */
+ur_status ur_plan_workspace_size_host(const ur_plan* plan, int32_t nbins, int32_t x_lo, int32_t x_hi,
+                                      size_t* bytes);
+
+/* Adjoint of the binned forward path (derived from eq. 1).  Given
+ * g_bin[b] = dL/dI_b (DEVICE, nbins doubles) with I_b = sum/count of the
+ * forward histogram `fwd`, computes
+ *     grad_rho(x) = 2 Re( IFFT( G(q) F(q) ) ),  G(q) = g_bin[b(q)] / count_b,
+ * (IFFT carrying 1/n^3, F of eq. 1) and, when a cell is given,
+ *     grad_amp[a] = sum over inside voxels of grad_rho(x) p_a(cell(x)),
+ * p_a the atom's voxel-integrated profile.  The forward transform is
+ * recomputed, not stored.  Exactly one of rho (DEVICE density) and cell
+ * (with mask and zoom factor 1) describes the density.  grad_rho (DEVICE, n^3
+ * reals of the plan precision) and grad_amp (DEVICE, n_atoms doubles) may
+ * each be NULL when not wanted. */
+ur_status ur_adjoint(ur_plan* plan, const void* rho, const ur_cell* cell, const ur_mask* mask,
+                     const ur_hist* fwd, const double* g_bin, void* grad_rho, double* grad_amp,
+                     void* stream);
+
+/* Merge modes (workflow step 6; dataMerge's rule is not given in the paper,
+ * the rule below is this library's reading):
+ *   each level's eq.-1 intensities are scaled back to absolute units by
+ *   s_k = (n_k^3)^2; a level is valid for a bin when the bin centre lies in
+ *   [dq_k, sqrt(3) pi / (2 voxel_k)] and its count >= n_min.
+ *   UR_MERGE_FINEST  the valid level with the smallest voxel owns the bin
+ *   UR_MERGE_POOLED  pooled scaled sums over the valid levels
+ *   UR_MERGE_IVW     inverse-variance weighted mean of the valid levels */
+#define UR_MERGE_FINEST 0
+#define UR_MERGE_POOLED 1
+#define UR_MERGE_IVW 2
+
+/* levels: HOST array of nlevels (<= 8) histograms (their arrays DEVICE),
+ * with box edges n[] and voxel sizes voxel[] (HOST).  edges: DEVICE, nbins+1
+ * values shared by every level.  Outputs DEVICE: mean[nbins], sem[nbins],
+ * owner[nbins] (level index for FINEST, number of contributing levels
+ * otherwise, -1 with NaN mean/sem when no level is valid). */
+ur_status ur_merge_zooms(int32_t nlevels, const ur_hist* levels, const int32_t* n,
+                         const double* voxel, int32_t nbins, const double* edges, int32_t mode,
+                         double n_min, double* mean, double* sem, int32_t* owner, void* stream);
+
+/* Record the work enqueued on `stream` between begin and end into a HIP
+ * graph, instantiate it, and return the executable graph (as void*); replay
+ * it with ur_graph_launch and release it with ur_graph_destroy.  Every entry
+ * point above except ur_plan_create / set_bins / set_workspace may be
+ * recorded. */
+ur_status ur_graph_begin(void* stream);
+ur_status ur_graph_end(void* stream, void** graph_exec);
+ur_status ur_graph_launch(void* graph_exec, void* stream);
+ur_status ur_graph_destroy(void* graph_exec);
+
+/* Thread-local description of the last failure on this thread. */
+const char* ur_last_error(void);
+
+/* Library version string. */
+const char* ur_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ULTIMA_H */

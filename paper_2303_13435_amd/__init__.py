@@ -1,0 +1,390 @@
+"""Python binding of the gfx950 wide-range scattering simulator.
+
+Thin ctypes marshalling over ``include/ultima.h``: torch tensors supply
+device memory and the current HIP stream; every step of the computation runs
+in the HIP kernels of ``libultima.so``.  There is no CPU fallback: when the
+library is missing, or no GPU is present, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(HERE, "libultima.so")
+
+UR_F32, UR_F64 = 0, 1
+UR_R2C, UR_C2C = 0, 1
+MERGE_FINEST, MERGE_POOLED, MERGE_IVW = 0, 1, 2
+
+_c = ctypes
+_vp = _c.c_void_p
+
+
+class UrMask(_c.Structure):
+    _fields_ = [("kind", _c.c_int32), ("p0", _c.c_int64), ("p1", _c.c_int64)]
+
+
+class UrCell(_c.Structure):
+    _fields_ = [("c", _c.c_int32), ("n_atoms", _c.c_int32), ("xyz", _vp), ("amp", _vp),
+                ("sigma", _vp), ("background", _c.c_double)]
+
+
+class UrZoom(_c.Structure):
+    _fields_ = [("n1", _c.c_int32), ("factor", _c.c_int32)]
+
+
+class UrHist(_c.Structure):
+    _fields_ = [("sum", _vp), ("sumsq", _vp), ("count", _vp), ("totals", _vp)]
+
+
+_LIB = None
+
+# (name, argtypes)
+_SIGS = {
+    "ur_plan_create": [_c.c_int32, _c.c_double, _c.c_int32, _c.c_uint32, _c.POINTER(_vp)],
+    "ur_plan_destroy": [_vp],
+    "ur_plan_workspace_size": [_vp, _c.c_int32, _c.POINTER(_c.c_size_t)],
+    "ur_plan_workspace_size_host": [_vp, _c.c_int32, _c.c_int32, _c.c_int32, _c.POINTER(_c.c_size_t)],
+    "ur_plan_set_workspace": [_vp, _vp, _c.c_size_t],
+    "ur_plan_set_bins": [_vp, _c.c_int32, _c.POINTER(_c.c_double)],
+    "ur_cell_synth": [_vp, _c.POINTER(UrCell), _vp, _vp],
+    "ur_rho_generate": [_vp, _c.POINTER(UrCell), _c.POINTER(UrMask), _c.POINTER(UrZoom), _vp, _vp],
+    "ur_fft3d_exec": [_vp, _vp, _vp, _c.c_int32, _vp],
+    "ur_intensity_bin": [_vp, _vp, _c.POINTER(UrHist), _vp],
+    "ur_simulate": [_vp, _c.POINTER(UrCell), _c.POINTER(UrMask), _c.POINTER(UrZoom), _c.POINTER(UrHist), _vp],
+    "ur_simulate_rho": [_vp, _vp, _c.POINTER(UrHist), _vp],
+    "ur_simulate_host": [_vp, _vp, _c.c_int32, _c.c_int32, _c.POINTER(UrHist), _vp, _c.POINTER(_c.c_size_t)],
+    "ur_adjoint": [_vp, _vp, _c.POINTER(UrCell), _c.POINTER(UrMask), _c.POINTER(UrHist), _vp, _vp, _vp, _vp],
+    "ur_merge_zooms": [_c.c_int32, _c.POINTER(UrHist), _c.POINTER(_c.c_int32), _c.POINTER(_c.c_double),
+                       _c.c_int32, _vp, _c.c_int32, _c.c_double, _vp, _vp, _vp, _vp],
+    "ur_graph_begin": [_vp],
+    "ur_graph_end": [_vp, _c.POINTER(_vp)],
+    "ur_graph_launch": [_vp, _vp],
+    "ur_graph_destroy": [_vp],
+    "ur_last_error": [],
+    "ur_version": [],
+}
+
+# every symbol include/ultima.h declares
+EXPORTS = tuple(_SIGS.keys())
+
+
+def lib():
+    """Load libultima.so (built in-tree by ``__graft_entry__.build()``)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIBPATH):
+            raise RuntimeError(f"{LIBPATH} is not built; run __graft_entry__.build() (hipcc, gfx950)")
+        L = _c.CDLL(LIBPATH)
+        for name, args in _SIGS.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = _c.c_int if name not in ("ur_plan_destroy", "ur_last_error", "ur_version") else None
+        L.ur_last_error.restype = _c.c_char_p
+        L.ur_version.restype = _c.c_char_p
+        L.ur_plan_destroy.restype = None
+        _LIB = L
+    return _LIB
+
+
+class UltimaError(RuntimeError):
+    pass
+
+
+def _check(st: int, what: str) -> None:
+    if st != 0:
+        raise UltimaError(f"{what}: status {st}: {lib().ur_last_error().decode()}")
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise UltimaError("no HIP device available: the scattering kernels run on the GPU only")
+    return torch
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else int(t.data_ptr())
+
+
+def _stream(stream=None) -> int:
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _require(t, dtype, numel: Optional[int] = None, what: str = "tensor"):
+    torch = _torch()
+    if t.device.type != "cuda" or not t.is_contiguous() or t.dtype != dtype:
+        raise UltimaError(f"{what} must be a contiguous {dtype} tensor on the GPU")
+    if numel is not None and t.numel() != numel:
+        raise UltimaError(f"{what} has {t.numel()} elements, expected {numel}")
+    return t
+
+
+# ---------------------------------------------------------------------------
+# marshalled inputs
+# ---------------------------------------------------------------------------
+
+@dataclass
+class DeviceCell:
+    """Unit cell with its atom arrays in device memory (FP64)."""
+    c: int
+    xyz: "object"
+    amp: "object"
+    sigma: "object"
+    background: float
+
+    @staticmethod
+    def from_host(cell) -> "DeviceCell":
+        torch = _torch()
+        dev = torch.device("cuda")
+        n = int(cell.amp.shape[0])
+        xyz = torch.as_tensor(np.ascontiguousarray(cell.xyz, dtype=np.float64).reshape(-1), device=dev)
+        amp = torch.as_tensor(np.ascontiguousarray(cell.amp, dtype=np.float64), device=dev)
+        sig = torch.as_tensor(np.ascontiguousarray(cell.sigma, dtype=np.float64), device=dev)
+        if n == 0:
+            xyz = torch.zeros(3, dtype=torch.float64, device=dev)
+            amp = torch.zeros(1, dtype=torch.float64, device=dev)
+            sig = torch.ones(1, dtype=torch.float64, device=dev)
+        return DeviceCell(int(cell.c), xyz, amp, sig, float(cell.background))
+
+    def struct(self, amp=None) -> UrCell:
+        a = self.amp if amp is None else amp
+        n = int(a.numel()) if self.xyz.numel() == 3 * a.numel() else 0
+        return UrCell(self.c, n, _ptr(self.xyz), _ptr(a), _ptr(self.sigma), self.background)
+
+
+def mask_struct(mask) -> UrMask:
+    return UrMask(int(mask.kind), int(mask.p0), int(mask.p1))
+
+
+class Hist:
+    """Per-bin sums (device, FP64) written by the library."""
+
+    def __init__(self, nbins: int):
+        torch = _torch()
+        dev = torch.device("cuda")
+        self.nbins = nbins
+        self.sum = torch.zeros(nbins, dtype=torch.float64, device=dev)
+        self.sumsq = torch.zeros(nbins, dtype=torch.float64, device=dev)
+        self.count = torch.zeros(nbins, dtype=torch.float64, device=dev)
+        self.totals = torch.zeros(4, dtype=torch.float64, device=dev)
+
+    def struct(self) -> UrHist:
+        return UrHist(_ptr(self.sum), _ptr(self.sumsq), _ptr(self.count), _ptr(self.totals))
+
+    def numpy(self) -> dict:
+        out = {k: getattr(self, k).cpu().numpy() for k in ("sum", "sumsq", "count", "totals")}
+        with np.errstate(invalid="ignore", divide="ignore"):
+            out["mean"] = np.where(out["count"] > 0, out["sum"] / np.maximum(out["count"], 1.0), np.nan)
+        return out
+
+
+class Plan:
+    """An n^3 box plan (precision, transform kind, bins, workspace)."""
+
+    def __init__(self, n: int, voxel: float = 1.0, prec: int = UR_F32, c2c: bool = False,
+                 workspace: bool = True):
+        _torch()
+        h = _vp()
+        _check(lib().ur_plan_create(int(n), float(voxel), int(prec), UR_C2C if c2c else UR_R2C, _c.byref(h)),
+               "ur_plan_create")
+        self.h = h
+        self.n, self.voxel, self.prec, self.c2c = int(n), float(voxel), int(prec), bool(c2c)
+        self.nbins = 0
+        self._ws = None
+        self._use_torch_ws = workspace
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None) is not None and _LIB is not None:
+                _LIB.ur_plan_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+    @property
+    def real_dtype(self):
+        torch = _torch()
+        return torch.float32 if self.prec == UR_F32 else torch.float64
+
+    @property
+    def complex_dtype(self):
+        torch = _torch()
+        return torch.complex64 if self.prec == UR_F32 else torch.complex128
+
+    def set_bins(self, edges: np.ndarray) -> None:
+        e = np.ascontiguousarray(edges, dtype=np.float64)
+        _check(lib().ur_plan_set_bins(self.h, int(e.size - 1), e.ctypes.data_as(_c.POINTER(_c.c_double))),
+               "ur_plan_set_bins")
+        self.nbins = int(e.size - 1)
+        self._attach(self.workspace_size())
+
+    def workspace_size(self, nbins: Optional[int] = None) -> int:
+        v = _c.c_size_t()
+        _check(lib().ur_plan_workspace_size(self.h, int(nbins or max(self.nbins, 1)), _c.byref(v)),
+               "ur_plan_workspace_size")
+        return int(v.value)
+
+    def workspace_size_host(self, x_lo: int, x_hi: int) -> int:
+        v = _c.c_size_t()
+        _check(lib().ur_plan_workspace_size_host(self.h, int(max(self.nbins, 1)), int(x_lo), int(x_hi),
+                                                 _c.byref(v)), "ur_plan_workspace_size_host")
+        return int(v.value)
+
+    def _attach(self, nbytes: int) -> None:
+        """Workspace from torch's allocator (256-byte aligned)."""
+        if not self._use_torch_ws:
+            return
+        torch = _torch()
+        if self._ws is not None and self._ws.numel() >= nbytes:
+            return
+        self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+        base = int(self._ws.data_ptr())
+        aligned = (base + 255) & ~255
+        _check(lib().ur_plan_set_workspace(self.h, _vp(aligned), _c.c_size_t(nbytes)), "ur_plan_set_workspace")
+
+    # -- entry points -------------------------------------------------------
+    def simulate(self, cell: DeviceCell, mask, zoom, hist: Hist, stream=None, amp=None) -> Hist:
+        cs = cell.struct(amp)
+        ms = mask_struct(mask)
+        zs = UrZoom(int(zoom.n1), int(zoom.factor))
+        hs = hist.struct()
+        _check(lib().ur_simulate(self.h, _c.byref(cs), _c.byref(ms), _c.byref(zs), _c.byref(hs), _stream(stream)),
+               "ur_simulate")
+        return hist
+
+    def simulate_rho(self, rho, hist: Hist, stream=None) -> Hist:
+        n = self.n
+        _require(rho, self.complex_dtype if self.c2c else self.real_dtype, n ** 3, "rho")
+        hs = hist.struct()
+        _check(lib().ur_simulate_rho(self.h, _ptr(rho), _c.byref(hs), _stream(stream)), "ur_simulate_rho")
+        return hist
+
+    def simulate_host(self, rho_host, x_lo: int, x_hi: int, hist: Hist, stream=None) -> int:
+        """rho_host: pinned CPU tensor (n^3 reals). Returns the H2D byte count."""
+        if rho_host.device.type != "cpu" or not rho_host.is_contiguous() or rho_host.dtype != self.real_dtype \
+                or rho_host.numel() != self.n ** 3:
+            raise UltimaError("rho_host must be a contiguous CPU tensor of n^3 reals of the plan precision")
+        if self._use_torch_ws:
+            self._attach(self.workspace_size_host(x_lo, x_hi))
+        hs = hist.struct()
+        nb = _c.c_size_t()
+        _check(lib().ur_simulate_host(self.h, _ptr(rho_host), int(x_lo), int(x_hi), _c.byref(hs), _stream(stream),
+                                      _c.byref(nb)), "ur_simulate_host")
+        return int(nb.value)
+
+    def rho_generate(self, cell: DeviceCell, mask, zoom, out=None, stream=None):
+        torch = _torch()
+        if out is None:
+            out = torch.empty((self.n,) * 3, dtype=self.real_dtype, device="cuda")
+        _require(out, self.real_dtype, self.n ** 3, "out")
+        cs, ms, zs = cell.struct(), mask_struct(mask), UrZoom(int(zoom.n1), int(zoom.factor))
+        _check(lib().ur_rho_generate(self.h, _c.byref(cs), _c.byref(ms), _c.byref(zs), _ptr(out), _stream(stream)),
+               "ur_rho_generate")
+        return out
+
+    def cell_synth(self, cell: DeviceCell, out=None, stream=None):
+        torch = _torch()
+        if out is None:
+            out = torch.empty((cell.c,) * 3, dtype=torch.float64, device="cuda")
+        cs = cell.struct()
+        _check(lib().ur_cell_synth(self.h, _c.byref(cs), _ptr(out), _stream(stream)), "ur_cell_synth")
+        return out
+
+    def nkz(self) -> int:
+        return self.n if self.c2c else self.n // 2 + 1
+
+    def fft3d(self, x, out=None, direction: int = -1, stream=None):
+        """eq. 1 forward (1/n^3) into the [kz][ky][kx] layout, or its inverse."""
+        torch = _torch()
+        n = self.n
+        if direction < 0:
+            _require(x, self.complex_dtype if self.c2c else self.real_dtype, n ** 3, "input")
+            if out is None:
+                out = torch.empty((self.nkz(), n, n), dtype=self.complex_dtype, device="cuda")
+            _require(out, self.complex_dtype, self.nkz() * n * n, "output")
+        else:
+            _require(x, self.complex_dtype, self.nkz() * n * n, "spectrum")
+            if out is None:
+                out = torch.empty((n, n, n), dtype=self.complex_dtype if self.c2c else self.real_dtype, device="cuda")
+            _require(out, self.complex_dtype if self.c2c else self.real_dtype, n ** 3, "output")
+        if self.nbins == 0:
+            self._attach(self.workspace_size(1))
+        _check(lib().ur_fft3d_exec(self.h, _ptr(x), _ptr(out), int(direction), _stream(stream)), "ur_fft3d_exec")
+        return out
+
+    def intensity_bin(self, spectrum, hist: Hist, stream=None) -> Hist:
+        _require(spectrum, self.complex_dtype, self.nkz() * self.n ** 2, "spectrum")
+        hs = hist.struct()
+        _check(lib().ur_intensity_bin(self.h, _ptr(spectrum), _c.byref(hs), _stream(stream)), "ur_intensity_bin")
+        return hist
+
+    def adjoint(self, fwd: Hist, g_bin, rho=None, cell: Optional[DeviceCell] = None, mask=None,
+                grad_rho=None, grad_amp=None, stream=None, amp=None):
+        _require(g_bin, _torch().float64, self.nbins, "g_bin")
+        hs = fwd.struct()
+        cs = cell.struct(amp) if cell is not None else None
+        ms = mask_struct(mask) if mask is not None else None
+        _check(lib().ur_adjoint(self.h, _ptr(rho), _c.byref(cs) if cs is not None else None,
+                                _c.byref(ms) if ms is not None else None, _c.byref(hs), _ptr(g_bin),
+                                _ptr(grad_rho), _ptr(grad_amp), _stream(stream)), "ur_adjoint")
+        return grad_rho, grad_amp
+
+
+def merge_zooms(hists: Sequence[Hist], ns: Sequence[int], voxels: Sequence[float], edges_dev, mode: int = MERGE_FINEST,
+                n_min: float = 32.0, stream=None):
+    torch = _torch()
+    k = len(hists)
+    nb = hists[0].nbins
+    arr = (UrHist * k)(*[h.struct() for h in hists])
+    n_arr = (_c.c_int32 * k)(*[int(v) for v in ns])
+    v_arr = (_c.c_double * k)(*[float(v) for v in voxels])
+    _require(edges_dev, torch.float64, nb + 1, "edges")
+    mean = torch.empty(nb, dtype=torch.float64, device="cuda")
+    sem = torch.empty(nb, dtype=torch.float64, device="cuda")
+    owner = torch.empty(nb, dtype=torch.int32, device="cuda")
+    _check(lib().ur_merge_zooms(k, arr, n_arr, v_arr, nb, _ptr(edges_dev), int(mode), float(n_min), _ptr(mean),
+                                _ptr(sem), _ptr(owner), _stream(stream)), "ur_merge_zooms")
+    return mean, sem, owner
+
+
+class Graph:
+    """HIP graph recorded from the calls made between begin() and end()."""
+
+    def __init__(self, stream):
+        self.stream = stream
+        self.h = None
+
+    def __enter__(self):
+        _check(lib().ur_graph_begin(int(self.stream.cuda_stream)), "ur_graph_begin")
+        return self
+
+    def __exit__(self, et, ev, tb):
+        h = _vp()
+        st = lib().ur_graph_end(int(self.stream.cuda_stream), _c.byref(h))
+        if et is None:
+            _check(st, "ur_graph_end")
+            self.h = h
+        return False
+
+    def launch(self):
+        _check(lib().ur_graph_launch(self.h, int(self.stream.cuda_stream)), "ur_graph_launch")
+
+    def __del__(self):
+        try:
+            if self.h is not None and _LIB is not None:
+                _LIB.ur_graph_destroy(self.h)
+        except Exception:
+            pass
+
+
+def version() -> str:
+    return lib().ur_version().decode()

@@ -1,0 +1,764 @@
+// C ABI of the gfx950 scattering simulator: plans, validation, integer bin
+// thresholds, workspace, and the orchestration of the transform passes.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/ultima.h"
+#include "ur_geom.hpp"
+#include "ur_kernels.hpp"
+
+using namespace ur;
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_err;
+
+static ur_status fail(ur_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+#define UR_HIP(call)                                                                         \
+  do {                                                                                       \
+    hipError_t e_ = (call);                                                                  \
+    if (e_ != hipSuccess) return fail(UR_ERR_HIP, "%s failed: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+#define UR_TRY(expr)                 \
+  do {                               \
+    ur_status s_ = (expr);           \
+    if (s_ != UR_OK) return s_;      \
+  } while (0)
+
+static bool is_pow2(long long v) { return v > 0 && (v & (v - 1)) == 0; }
+static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// ---------------------------------------------------------------------------
+// plan
+// ---------------------------------------------------------------------------
+struct ur_plan {
+  int n = 0;
+  double voxel = 0.0;
+  int prec = 0;
+  unsigned flags = 0;
+  int nkz = 0;
+  size_t cs = 0;             // bytes per complex element
+  size_t rs = 0;             // bytes per real element
+  int device = 0;
+
+  void* tw = nullptr;        // n twiddles (device)
+
+  int nbins = 0;
+  int* dU = nullptr;         // nbins + 1 thresholds (device)
+  std::vector<long long> U;
+
+  // workspace
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  bool ws_owned = false;
+
+  // cell scratch (library owned, grown on demand)
+  char* cs_buf = nullptr;
+  size_t cs_bytes = 0;
+
+  // out-of-core
+  hipStream_t copy_stream = nullptr;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  void* stage = nullptr;     // two pinned-side staging buffers on the device
+  size_t stage_bytes = 0;
+};
+
+static int x_blocks_for(int nbins) { return nbins > 1024 ? 512 : 1024; }
+static int x_blocks(const ur_plan* p) { return x_blocks_for(p->nbins); }
+
+// largest ZMode tile over the modes the plan can run
+static int zt(const ur_plan* p) { return z_tile(p->prec, p->n, p->flags & UR_C2C); }
+static int ntiles(const ur_plan* p) { return p->n / zt(p); }
+
+struct Layout {
+  size_t A, B, part, mom, f0, total;
+};
+
+static Layout layout_incore(const ur_plan* p, int nbins) {
+  Layout L;
+  size_t n = p->n;
+  size_t plane = (size_t)p->nkz * n * p->cs;
+  L.A = 0;
+  L.B = align256(L.A + n * plane);
+  L.part = align256(L.B + (size_t)p->nkz * n * n * p->cs);
+  L.mom = align256(L.part + (size_t)x_blocks_for(nbins) * (3 * (size_t)std::max(nbins, 1) + 1) * 8);
+  L.f0 = align256(L.mom + n * (size_t)ntiles(p) * 16);
+  L.total = align256(L.f0 + 64);
+  return L;
+}
+
+// out-of-core layout: one slab of the first intermediate, B over [xlo, xhi]
+static Layout layout_host(const ur_plan* p, int nbins, int xlo, int xhi) {
+  Layout L;
+  size_t n = p->n;
+  int tx = y_tile(p->prec, p->n);
+  size_t plane = (size_t)p->nkz * n * p->cs;
+  long long xt0 = xlo / tx, xt1 = xhi / tx;
+  size_t bs = (size_t)(xt1 - xt0 + 1) * tx;
+  L.A = 0;
+  L.B = align256(L.A + (size_t)tx * plane);
+  L.part = align256(L.B + (size_t)p->nkz * n * bs * p->cs);
+  L.mom = align256(L.part + (size_t)x_blocks_for(nbins) * (3 * (size_t)std::max(nbins, 1) + 1) * 8);
+  L.f0 = align256(L.mom + n * (size_t)ntiles(p) * 16);
+  L.total = align256(L.f0 + 64);
+  return L;
+}
+
+static ur_status ensure_ws(ur_plan* p, size_t need, hipStream_t s) {
+  if (p->ws && p->ws_bytes >= need) return UR_OK;
+  if (p->ws && !p->ws_owned)
+    return fail(UR_ERR_STATE, "attached workspace holds %zu bytes, this call needs %zu", p->ws_bytes, need);
+  hipStreamCaptureStatus cst = hipStreamCaptureStatusNone;
+  if (s) (void)hipStreamIsCapturing(s, &cst);
+  if (cst != hipStreamCaptureStatusNone)
+    return fail(UR_ERR_STATE, "workspace must be allocated (first call) before graph capture");
+  if (p->ws) { UR_HIP(hipDeviceSynchronize()); UR_HIP(hipFree(p->ws)); p->ws = nullptr; p->ws_bytes = 0; }
+  void* ptr = nullptr;
+  if (hipMalloc(&ptr, need) != hipSuccess) { (void)hipGetLastError(); return fail(UR_ERR_OOM, "hipMalloc(%zu) failed", need); }
+  p->ws = (char*)ptr;
+  p->ws_bytes = need;
+  p->ws_owned = true;
+  return UR_OK;
+}
+
+static ur_status ensure_cell_scratch(ur_plan* p, size_t need, hipStream_t s) {
+  if (p->cs_buf && p->cs_bytes >= need) return UR_OK;
+  hipStreamCaptureStatus cst = hipStreamCaptureStatusNone;
+  if (s) (void)hipStreamIsCapturing(s, &cst);
+  if (cst != hipStreamCaptureStatusNone)
+    return fail(UR_ERR_STATE, "cell scratch must be allocated (first call) before graph capture");
+  if (p->cs_buf) { UR_HIP(hipDeviceSynchronize()); UR_HIP(hipFree(p->cs_buf)); p->cs_buf = nullptr; }
+  void* ptr = nullptr;
+  if (hipMalloc(&ptr, need) != hipSuccess) { (void)hipGetLastError(); return fail(UR_ERR_OOM, "hipMalloc(%zu) failed", need); }
+  p->cs_buf = (char*)ptr;
+  p->cs_bytes = need;
+  return UR_OK;
+}
+
+// twiddles exp(-2 pi i k / n), evaluated in long double, rounded once
+static ur_status make_twiddles(ur_plan* p) {
+  const long double PI = 3.14159265358979323846264338327950288L;
+  size_t n = p->n;
+  if (p->prec == UR_F32) {
+    std::vector<float> h(2 * n);
+    for (size_t k = 0; k < n; ++k) {
+      long double a = 2.0L * PI * (long double)k / (long double)n;
+      h[2 * k] = (float)cosl(a);
+      h[2 * k + 1] = (float)(-sinl(a));
+    }
+    UR_HIP(hipMalloc(&p->tw, 2 * n * sizeof(float)));
+    UR_HIP(hipMemcpy(p->tw, h.data(), 2 * n * sizeof(float), hipMemcpyHostToDevice));
+  } else {
+    std::vector<double> h(2 * n);
+    for (size_t k = 0; k < n; ++k) {
+      long double a = 2.0L * PI * (long double)k / (long double)n;
+      h[2 * k] = (double)cosl(a);
+      h[2 * k + 1] = (double)(-sinl(a));
+    }
+    UR_HIP(hipMalloc(&p->tw, 2 * n * sizeof(double)));
+    UR_HIP(hipMemcpy(p->tw, h.data(), 2 * n * sizeof(double), hipMemcpyHostToDevice));
+  }
+  return UR_OK;
+}
+
+// Integer threshold of a bin edge: t = (e/dq)^2 snapped to the nearest
+// integer when within 1e-9 relative.  Evaluated without fused multiply-add
+// so that every implementation of the rule gets the same bits.
+#pragma clang fp contract(off)
+static double snap_threshold(double e, double dq) {
+  double r = e / dq;
+  double t = r * r;
+  double rt = nearbyint(t);
+  if (fabs(t - rt) <= 1e-9 * fmax(1.0, t)) t = rt;
+  return t;
+}
+static void thresholds(int n, double voxel, int nbins, const double* edges, std::vector<long long>& U) {
+  double dq = 2.0 * M_PI / ((double)n * voxel);
+  U.assign(nbins + 1, 0);
+  for (int b = 0; b < nbins; ++b) {
+    double t = snap_threshold(edges[b], dq);
+    U[b] = t <= 0.0 ? 0 : (long long)ceil(t);
+  }
+  double tl = snap_threshold(edges[nbins], dq);
+  U[nbins] = tl < 0.0 ? 0 : (long long)floor(tl) + 1;
+}
+#pragma clang fp contract(on)
+
+extern "C" {
+
+const char* ur_last_error(void) { return g_err.c_str(); }
+const char* ur_version(void) { return "ultima-gfx950 0.1"; }
+
+ur_status ur_plan_create(int32_t n, double voxel, int32_t prec, uint32_t flags, ur_plan** out) {
+  if (!out) return fail(UR_ERR_INVALID, "out is null");
+  *out = nullptr;
+  if (!is_pow2(n) || n < 16) return fail(UR_ERR_INVALID, "n = %d must be a power of two >= 16", n);
+  if (n > 1024) return fail(UR_ERR_UNSUPPORTED, "n = %d: this build runs boxes up to 1024^3", n);
+  if (!(voxel > 0.0) || !isfinite(voxel)) return fail(UR_ERR_INVALID, "voxel must be positive");
+  if (prec != UR_F32 && prec != UR_F64) return fail(UR_ERR_INVALID, "prec must be UR_F32 or UR_F64");
+  if (flags & ~1u) return fail(UR_ERR_INVALID, "unknown flags 0x%x", flags);
+  ur_plan* p = new (std::nothrow) ur_plan();
+  if (!p) return fail(UR_ERR_OOM, "plan allocation failed");
+  p->n = n;
+  p->voxel = voxel;
+  p->prec = prec;
+  p->flags = flags;
+  p->nkz = (flags & UR_C2C) ? n : n / 2 + 1;
+  p->rs = prec == UR_F32 ? 4 : 8;
+  p->cs = 2 * p->rs;
+  if (hipGetDevice(&p->device) != hipSuccess) { delete p; return fail(UR_ERR_HIP, "hipGetDevice failed"); }
+  ur_status st = make_twiddles(p);
+  if (st != UR_OK) { ur_plan_destroy(p); return st; }
+  *out = p;
+  return UR_OK;
+}
+
+void ur_plan_destroy(ur_plan* p) {
+  if (!p) return;
+  (void)hipDeviceSynchronize();
+  if (p->tw) (void)hipFree(p->tw);
+  if (p->dU) (void)hipFree(p->dU);
+  if (p->ws && p->ws_owned) (void)hipFree(p->ws);
+  if (p->cs_buf) (void)hipFree(p->cs_buf);
+  if (p->stage) (void)hipFree(p->stage);
+  for (auto& e : p->ev) if (e) (void)hipEventDestroy(e);
+  if (p->copy_stream) (void)hipStreamDestroy(p->copy_stream);
+  delete p;
+}
+
+ur_status ur_plan_workspace_size(const ur_plan* p, int32_t nbins, size_t* bytes) {
+  if (!p || !bytes) return fail(UR_ERR_INVALID, "null argument");
+  if (nbins < 1) return fail(UR_ERR_INVALID, "nbins must be >= 1");
+  *bytes = layout_incore(p, nbins).total;
+  return UR_OK;
+}
+
+ur_status ur_plan_workspace_size_host(const ur_plan* p, int32_t nbins, int32_t x_lo, int32_t x_hi, size_t* bytes) {
+  if (!p || !bytes) return fail(UR_ERR_INVALID, "null argument");
+  if (nbins < 1) return fail(UR_ERR_INVALID, "nbins must be >= 1");
+  if (x_lo < 0 || x_hi >= p->n || x_lo > x_hi) return fail(UR_ERR_INVALID, "plane range [%d, %d] outside the box", x_lo, x_hi);
+  *bytes = layout_host(p, nbins, x_lo, x_hi).total;
+  return UR_OK;
+}
+
+ur_status ur_plan_set_workspace(ur_plan* p, void* dev_ptr, size_t bytes) {
+  if (!p || !dev_ptr) return fail(UR_ERR_INVALID, "null argument");
+  if (((uintptr_t)dev_ptr) & 255) return fail(UR_ERR_INVALID, "workspace must be 256-byte aligned");
+  if (p->ws && p->ws_owned) { UR_HIP(hipDeviceSynchronize()); UR_HIP(hipFree(p->ws)); }
+  p->ws = (char*)dev_ptr;
+  p->ws_bytes = bytes;
+  p->ws_owned = false;
+  return UR_OK;
+}
+
+ur_status ur_plan_set_bins(ur_plan* p, int32_t nbins, const double* edges) {
+  if (!p || !edges) return fail(UR_ERR_INVALID, "null argument");
+  if (nbins < 1 || nbins > 4096) return fail(UR_ERR_INVALID, "nbins = %d outside [1, 4096]", nbins);
+  for (int b = 0; b <= nbins; ++b)
+    if (!isfinite(edges[b]) || (b > 0 && !(edges[b] > edges[b - 1])))
+      return fail(UR_ERR_INVALID, "bin edges must be finite and strictly increasing (edge %d)", b);
+  std::vector<long long> U;
+  thresholds(p->n, p->voxel, nbins, edges, U);
+  long long n2max = 3ll * (p->n / 2) * (p->n / 2);
+  std::vector<int> Ui(nbins + 1);
+  for (int b = 0; b <= nbins; ++b) Ui[b] = (int)std::min<long long>(U[b], n2max + 1);
+  if (p->dU && p->nbins < nbins) { UR_HIP(hipFree(p->dU)); p->dU = nullptr; }
+  if (!p->dU) UR_HIP(hipMalloc(&p->dU, (nbins + 1) * sizeof(int)));
+  UR_HIP(hipMemcpy(p->dU, Ui.data(), (nbins + 1) * sizeof(int), hipMemcpyHostToDevice));
+  p->nbins = nbins;
+  p->U = U;
+  return UR_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// shared pieces of the forward path
+// ---------------------------------------------------------------------------
+static ur_status check_hist(const ur_hist* h) {
+  if (!h || !h->sum || !h->sumsq || !h->count || !h->totals) return fail(UR_ERR_INVALID, "histogram pointers must be non-null");
+  return UR_OK;
+}
+
+static ur_status check_cell(const ur_cell* c) {
+  if (!c) return fail(UR_ERR_INVALID, "cell is null");
+  if (!is_pow2(c->c) || c->c > 256) return fail(UR_ERR_INVALID, "cell edge %d must be a power of two <= 256", c->c);
+  if (c->n_atoms < 0 || c->n_atoms > (1 << 20)) return fail(UR_ERR_INVALID, "n_atoms = %d out of range", c->n_atoms);
+  if (c->n_atoms > 0 && (!c->xyz || !c->amp || !c->sigma)) return fail(UR_ERR_INVALID, "atom arrays must be non-null");
+  if (!isfinite(c->background)) return fail(UR_ERR_INVALID, "background must be finite");
+  return UR_OK;
+}
+
+static ur_status check_level(const ur_plan* p, const ur_cell* cell, const ur_mask* m, const ur_zoom* z, Level& L, MaskP& mp) {
+  if (!m || !z) return fail(UR_ERR_INVALID, "mask and zoom must be non-null");
+  if (m->kind < 0 || m->kind > 3) return fail(UR_ERR_INVALID, "mask kind %d unknown", m->kind);
+  if (m->p0 > (1ll << 40) || m->p1 > (1ll << 40)) return fail(UR_ERR_INVALID, "mask parameters too large");
+  if (!is_pow2(z->n1) || !is_pow2(z->factor)) return fail(UR_ERR_INVALID, "zoom n1 and factor must be powers of two");
+  if (z->factor > 1 && z->factor > z->n1 / 2) return fail(UR_ERR_INVALID, "zoom factor %d too large for n1 = %d", z->factor, z->n1);
+  if (z->n1 / z->factor > p->n) return fail(UR_ERR_INVALID, "reduced particle region %d exceeds the box %d", z->n1 / z->factor, p->n);
+  if (z->factor > 1 && cell->c > z->n1) return fail(UR_ERR_INVALID, "cell larger than the ED-1 grid");
+  L = make_level(p->n, z->n1, z->factor, cell->c);
+  mp.kind = m->kind;
+  mp.p0 = m->p0;
+  mp.p1 = m->p1;
+  return UR_OK;
+}
+
+struct CellTables {
+  double* prof;
+  double* cell64;
+  void* cellT;
+  double* pre;
+  void* cb;
+  double* gcell;
+  double* fold_part;
+  int cbn;
+};
+
+static const int kFoldBlocks = 256;
+
+// cell synthesis + tables for the generator (a1 of the path)
+static ur_status prepare_cell(ur_plan* p, const ur_cell* cell, int f, CellTables& t, hipStream_t s) {
+  const size_t c = cell->c, c3 = c * c * c;
+  t.cbn = f <= (int)c ? (int)c / f : 1;
+  const size_t nb = (size_t)t.cbn * t.cbn * t.cbn;
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
+  size_t o_prof = take(std::max<size_t>(1, (size_t)cell->n_atoms * 3 * c) * 8);
+  size_t o_cell = take(c3 * 8);
+  size_t o_cellT = take(c3 * p->rs);
+  size_t o_pre = take(c * c * (c + 1) * 8);
+  size_t o_cb = take(nb * p->rs);
+  size_t o_g = take(c3 * 8);
+  size_t o_fp = take((c <= 16 ? (size_t)kFoldBlocks * c3 : 1) * 8);
+  UR_TRY(ensure_cell_scratch(p, off, s));
+  char* b = p->cs_buf;
+  t.prof = (double*)(b + o_prof);
+  t.cell64 = (double*)(b + o_cell);
+  t.cellT = b + o_cellT;
+  t.pre = (double*)(b + o_pre);
+  t.cb = b + o_cb;
+  t.gcell = (double*)(b + o_g);
+  t.fold_part = (double*)(b + o_fp);
+  UR_HIP(launch_cell_profiles(cell->c, cell->n_atoms, cell->xyz, cell->sigma, t.prof, s));
+  UR_HIP(launch_cell_sum(cell->c, cell->n_atoms, cell->amp, t.prof, cell->background, t.cell64, s));
+  UR_HIP(launch_cell_tables(p->prec, cell->c, f, t.cell64, t.cellT, t.pre, t.cb, t.cbn, s));
+  return UR_OK;
+}
+
+// passes Y and X + finalize, given A written for planes [xlo, xhi]
+struct FwdGeom {
+  int xlo, xhi;          // planes of A that hold data
+  long long ax0;         // first plane held by A
+  int gen;               // A rows limited to the particle row range
+  Level L;
+  MaskP m;
+};
+
+static ur_status run_y_x(ur_plan* p, const FwdGeom& g, char* A, char* B, const Layout& lay,
+                         const ur_hist* h, int nzb, hipStream_t s) {
+  const int n = p->n, tx = y_tile(p->prec, n);
+  long long xt0 = 0, xt1 = -1, bx0 = 0, bs = tx;
+  if (g.xlo <= g.xhi) {
+    xt0 = g.xlo / tx;
+    xt1 = g.xhi / tx;
+    bx0 = xt0 * tx;
+    bs = (xt1 - xt0 + 1) * tx;
+    YArgs ya{};
+    ya.A = A; ya.ax0 = g.ax0; ya.B = B; ya.bx0 = bx0; ya.bs = bs; ya.tw = p->tw;
+    ya.L = g.L; ya.m = g.m; ya.gen = g.gen; ya.nkz = p->nkz; ya.xlo = g.xlo; ya.xhi = g.xhi;
+    ya.xt0 = (int)xt0; ya.nxt = (int)(xt1 - xt0 + 1); ya.ty = zt(p);
+    UR_HIP(launch_pass_y(p->prec, n, ya, s));
+  }
+  XArgs xa{};
+  xa.B = B; xa.bx0 = bx0; xa.bs = bs; xa.out = nullptr; xa.tw = p->tw;
+  xa.nkz = p->nkz; xa.r2c = !(p->flags & UR_C2C);
+  xa.xa = (int)bx0; xa.xb = g.xlo <= g.xhi ? (int)(bx0 + bs - 1) : -1;
+  xa.iscale = 1.0 / ((double)n * n * n) / ((double)n * n * n);
+  xa.oscale = 1.0; xa.nbins = p->nbins; xa.U = p->dU;
+  xa.part = (double*)(p->ws + lay.part); xa.f0 = (double*)(p->ws + lay.f0);
+  xa.ncols = p->nkz * n;
+  const int nxb = x_blocks(p);
+  UR_HIP(launch_pass_x(p->prec, n, X_FFT_BIN, -1, xa, nxb, s));
+  FinArgs fa{};
+  fa.part = xa.part; fa.nblk = nxb; fa.nbins = p->nbins;
+  fa.mom = nzb > 0 ? (const double*)(p->ws + lay.mom) : nullptr; fa.nzb = nzb;
+  fa.f0 = xa.f0; fa.sum = h->sum; fa.sumsq = h->sumsq; fa.count = h->count; fa.totals = h->totals;
+  UR_HIP(launch_finalize(fa, s));
+  return UR_OK;
+}
+
+extern "C" {
+
+ur_status ur_cell_synth(ur_plan* p, const ur_cell* cell, double* cell_out, void* stream) {
+  if (!p || !cell_out) return fail(UR_ERR_INVALID, "null argument");
+  UR_TRY(check_cell(cell));
+  hipStream_t s = (hipStream_t)stream;
+  size_t need = align256(std::max<size_t>(1, (size_t)cell->n_atoms * 3 * cell->c) * 8);
+  UR_TRY(ensure_cell_scratch(p, std::max(need, p->cs_bytes), s));
+  double* prof = (double*)p->cs_buf;
+  UR_HIP(launch_cell_profiles(cell->c, cell->n_atoms, cell->xyz, cell->sigma, prof, s));
+  UR_HIP(launch_cell_sum(cell->c, cell->n_atoms, cell->amp, prof, cell->background, cell_out, s));
+  return UR_OK;
+}
+
+ur_status ur_rho_generate(ur_plan* p, const ur_cell* cell, const ur_mask* mask, const ur_zoom* zoom, void* rho, void* stream) {
+  if (!p || !rho) return fail(UR_ERR_INVALID, "null argument");
+  UR_TRY(check_cell(cell));
+  Level L;
+  MaskP m;
+  UR_TRY(check_level(p, cell, mask, zoom, L, m));
+  hipStream_t s = (hipStream_t)stream;
+  CellTables t;
+  UR_TRY(prepare_cell(p, cell, zoom->factor, t, s));
+  ZArgs za{};
+  za.cellT = t.cellT; za.cb = t.cb; za.pre = t.pre; za.L = L; za.m = m; za.cbn = t.cbn;
+  UR_HIP(launch_rho_generate(p->prec, p->n, za, rho, s));
+  return UR_OK;
+}
+
+ur_status ur_simulate(ur_plan* p, const ur_cell* cell, const ur_mask* mask, const ur_zoom* zoom, const ur_hist* h, void* stream) {
+  if (!p) return fail(UR_ERR_INVALID, "plan is null");
+  if (p->nbins < 1) return fail(UR_ERR_STATE, "no bins set on the plan");
+  UR_TRY(check_hist(h));
+  UR_TRY(check_cell(cell));
+  FwdGeom g;
+  UR_TRY(check_level(p, cell, mask, zoom, g.L, g.m));
+  hipStream_t s = (hipStream_t)stream;
+  Layout lay = layout_incore(p, p->nbins);
+  UR_TRY(ensure_ws(p, lay.total, s));
+  CellTables t;
+  UR_TRY(prepare_cell(p, cell, zoom->factor, t, s));
+
+  long long xlo, xhi;
+  plane_range(g.L, g.m, xlo, xhi);
+  if (xlo < 0) xlo = 0;
+  if (xhi > p->n - 1) xhi = p->n - 1;
+  g.xlo = (int)xlo; g.xhi = (int)xhi; g.ax0 = xlo; g.gen = 1;
+  int nzb = 0;
+  if (xlo <= xhi) {
+    ZArgs za{};
+    za.A = p->ws + lay.A; za.ax0 = xlo; za.cellT = t.cellT; za.cb = t.cb; za.pre = t.pre; za.tw = p->tw;
+    za.mom = (double*)(p->ws + lay.mom); za.L = g.L; za.m = g.m; za.nkz = p->nkz; za.x0 = (int)xlo;
+    za.ntiles = ntiles(p); za.cbn = t.cbn;
+    nzb = (int)((xhi - xlo + 1) * za.ntiles);
+    UR_HIP(launch_pass_z(p->prec, p->n, (p->flags & UR_C2C) ? Z_GEN_C2C : Z_GEN_R2C, za, nzb, s));
+  }
+  return run_y_x(p, g, p->ws + lay.A, p->ws + lay.B, lay, h, nzb, s);
+}
+
+ur_status ur_simulate_rho(ur_plan* p, const void* rho, const ur_hist* h, void* stream) {
+  if (!p || !rho) return fail(UR_ERR_INVALID, "null argument");
+  if (p->nbins < 1) return fail(UR_ERR_STATE, "no bins set on the plan");
+  UR_TRY(check_hist(h));
+  hipStream_t s = (hipStream_t)stream;
+  Layout lay = layout_incore(p, p->nbins);
+  UR_TRY(ensure_ws(p, lay.total, s));
+  FwdGeom g{};
+  g.xlo = 0; g.xhi = p->n - 1; g.ax0 = 0; g.gen = 0;
+  g.L = make_level(p->n, p->n, 1, 1);
+  ZArgs za{};
+  za.A = p->ws + lay.A; za.ax0 = 0; za.rho = rho; za.rho_x0 = 0; za.tw = p->tw;
+  za.mom = (double*)(p->ws + lay.mom); za.L = g.L; za.nkz = p->nkz; za.x0 = 0; za.ntiles = ntiles(p);
+  int nzb = p->n * za.ntiles;
+  UR_HIP(launch_pass_z(p->prec, p->n, (p->flags & UR_C2C) ? Z_LOAD_C2C : Z_LOAD_R2C, za, nzb, s));
+  return run_y_x(p, g, p->ws + lay.A, p->ws + lay.B, lay, h, nzb, s);
+}
+
+ur_status ur_fft3d_exec(ur_plan* p, const void* in, void* out, int32_t dir, void* stream) {
+  if (!p || !in || !out) return fail(UR_ERR_INVALID, "null argument");
+  if (dir != -1 && dir != 1) return fail(UR_ERR_INVALID, "dir must be -1 or +1");
+  if (in == out) return fail(UR_ERR_INVALID, "in and out must differ");
+  hipStream_t s = (hipStream_t)stream;
+  Layout lay = layout_incore(p, std::max(p->nbins, 1));
+  UR_TRY(ensure_ws(p, lay.total, s));
+  const int n = p->n, c2c = (p->flags & UR_C2C) ? 1 : 0;
+  char* A = p->ws + lay.A;
+  char* B = p->ws + lay.B;
+  const int tx = y_tile(p->prec, n);
+  if (dir < 0) {
+    ZArgs za{};
+    za.A = A; za.ax0 = 0; za.rho = in; za.rho_x0 = 0; za.tw = p->tw; za.mom = nullptr;
+    za.L = make_level(n, n, 1, 1); za.nkz = p->nkz; za.x0 = 0; za.ntiles = ntiles(p);
+    UR_HIP(launch_pass_z(p->prec, n, c2c ? Z_LOAD_C2C : Z_LOAD_R2C, za, n * za.ntiles, s));
+    YArgs ya{};
+    ya.A = A; ya.ax0 = 0; ya.B = B; ya.bx0 = 0; ya.bs = n; ya.tw = p->tw; ya.L = za.L; ya.gen = 0;
+    ya.nkz = p->nkz; ya.xlo = 0; ya.xhi = n - 1; ya.xt0 = 0; ya.nxt = n / tx; ya.ty = zt(p);
+    UR_HIP(launch_pass_y(p->prec, n, ya, s));
+    XArgs xa{};
+    xa.B = B; xa.bx0 = 0; xa.bs = n; xa.out = out; xa.tw = p->tw; xa.nkz = p->nkz; xa.r2c = !c2c;
+    xa.xa = 0; xa.xb = n - 1; xa.oscale = 1.0 / ((double)n * n * n); xa.ncols = p->nkz * n;
+    UR_HIP(launch_pass_x(p->prec, n, X_FFT_STORE, -1, xa, x_blocks(p), s));
+  } else {
+    XArgs xa{};
+    xa.B = in; xa.bx0 = 0; xa.bs = n; xa.out = B; xa.tw = p->tw; xa.nkz = p->nkz; xa.r2c = !c2c;
+    xa.xa = 0; xa.xb = n - 1; xa.oscale = 1.0; xa.ncols = p->nkz * n;
+    UR_HIP(launch_pass_x(p->prec, n, X_FFT_STORE, +1, xa, x_blocks(p), s));
+    YInvArgs yi{};
+    yi.B = B; yi.A = A; yi.tw = p->tw; yi.nkz = p->nkz; yi.xt0 = 0; yi.nxt = n / tx;
+    UR_HIP(launch_pass_y_inv(p->prec, n, yi, s));
+    ZInvArgs zi{};
+    zi.A = A; zi.out = out; zi.tw = p->tw; zi.nkz = p->nkz; zi.ntiles = n / zinv_tile(p->prec, n, c2c); zi.scale = 1.0;
+    UR_HIP(launch_pass_z_inv(p->prec, n, c2c, zi, s));
+  }
+  return UR_OK;
+}
+
+ur_status ur_intensity_bin(ur_plan* p, const void* spectrum, const ur_hist* h, void* stream) {
+  if (!p || !spectrum) return fail(UR_ERR_INVALID, "null argument");
+  if (p->nbins < 1) return fail(UR_ERR_STATE, "no bins set on the plan");
+  UR_TRY(check_hist(h));
+  hipStream_t s = (hipStream_t)stream;
+  Layout lay = layout_incore(p, p->nbins);
+  UR_TRY(ensure_ws(p, lay.total, s));
+  const int n = p->n;
+  XArgs xa{};
+  xa.B = spectrum; xa.bx0 = 0; xa.bs = n; xa.tw = p->tw; xa.nkz = p->nkz; xa.r2c = !(p->flags & UR_C2C);
+  xa.xa = 0; xa.xb = n - 1; xa.iscale = 1.0; xa.nbins = p->nbins; xa.U = p->dU;
+  xa.part = (double*)(p->ws + lay.part); xa.f0 = (double*)(p->ws + lay.f0); xa.ncols = p->nkz * n;
+  UR_HIP(launch_pass_x(p->prec, n, X_BIN_ONLY, -1, xa, x_blocks(p), s));
+  FinArgs fa{};
+  fa.part = xa.part; fa.nblk = x_blocks(p); fa.nbins = p->nbins; fa.mom = nullptr; fa.nzb = 0;
+  fa.f0 = xa.f0; fa.sum = h->sum; fa.sumsq = h->sumsq; fa.count = h->count; fa.totals = h->totals;
+  UR_HIP(launch_finalize(fa, s));
+  return UR_OK;
+}
+
+ur_status ur_simulate_host(ur_plan* p, const void* rho_host, int32_t x_lo, int32_t x_hi, const ur_hist* h,
+                           void* stream, size_t* h2d_bytes) {
+  if (!p || !rho_host) return fail(UR_ERR_INVALID, "null argument");
+  if (p->nbins < 1) return fail(UR_ERR_STATE, "no bins set on the plan");
+  if (p->flags & UR_C2C) return fail(UR_ERR_UNSUPPORTED, "the out-of-core path takes real densities (UR_R2C plans)");
+  if (x_lo < 0 || x_hi >= p->n || x_lo > x_hi) return fail(UR_ERR_INVALID, "plane range [%d, %d] outside the box", x_lo, x_hi);
+  UR_TRY(check_hist(h));
+  hipStream_t s = (hipStream_t)stream;
+  hipStreamCaptureStatus cst = hipStreamCaptureStatusNone;
+  if (s) (void)hipStreamIsCapturing(s, &cst);
+  if (cst != hipStreamCaptureStatusNone) return fail(UR_ERR_STATE, "the out-of-core path is a host-driven pipeline and cannot be captured");
+  const int n = p->n, tx = y_tile(p->prec, n);
+  Layout lay = layout_host(p, p->nbins, x_lo, x_hi);
+  UR_TRY(ensure_ws(p, lay.total, s));
+  const size_t plane_bytes = (size_t)n * n * p->rs;
+  const size_t slab_bytes = (size_t)tx * plane_bytes;
+  if (!p->stage || p->stage_bytes < 2 * slab_bytes) {
+    UR_HIP(hipDeviceSynchronize());
+    if (p->stage) UR_HIP(hipFree(p->stage));
+    p->stage = nullptr;
+    if (hipMalloc(&p->stage, 2 * slab_bytes) != hipSuccess) { (void)hipGetLastError(); return fail(UR_ERR_OOM, "staging allocation failed"); }
+    p->stage_bytes = 2 * slab_bytes;
+  }
+  if (!p->copy_stream) UR_HIP(hipStreamCreateWithFlags(&p->copy_stream, hipStreamNonBlocking));
+  for (auto& e : p->ev) if (!e) UR_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+
+  FwdGeom g{};
+  g.xlo = x_lo; g.xhi = x_hi; g.gen = 0; g.L = make_level(n, n, 1, 1);
+  const long long xt0 = x_lo / tx, xt1 = x_hi / tx;
+  const long long bx0 = xt0 * tx, bs = (xt1 - xt0 + 1) * tx;
+  char* A = p->ws + lay.A;
+  char* B = p->ws + lay.B;
+  size_t copied = 0;
+  // events: ev[0], ev[1] = slab copied into stage buffer 0/1; ev[2], ev[3] = stage buffer 0/1 consumed
+  UR_HIP(hipEventRecord(p->ev[2], s));
+  UR_HIP(hipEventRecord(p->ev[3], s));
+  const int ntl = ntiles(p);
+  int zb = 0;
+  for (long long xt = xt0; xt <= xt1; ++xt) {
+    const int buf = (int)((xt - xt0) & 1);
+    char* st = (char*)p->stage + buf * slab_bytes;
+    const long long sx0 = xt * tx;
+    const long long lo = std::max<long long>(sx0, x_lo), hi = std::min<long long>(sx0 + tx - 1, x_hi);
+    // wait until the previous user of this staging buffer is done, then copy
+    UR_HIP(hipStreamWaitEvent(p->copy_stream, p->ev[2 + buf], 0));
+    UR_HIP(hipMemcpyAsync(st + (lo - sx0) * plane_bytes, (const char*)rho_host + (size_t)lo * plane_bytes,
+                          (size_t)(hi - lo + 1) * plane_bytes, hipMemcpyHostToDevice, p->copy_stream));
+    copied += (size_t)(hi - lo + 1) * plane_bytes;
+    UR_HIP(hipEventRecord(p->ev[buf], p->copy_stream));
+    UR_HIP(hipStreamWaitEvent(s, p->ev[buf], 0));
+    // z pass over the planes of this slab, then y pass of this x tile
+    ZArgs za{};
+    za.A = A; za.ax0 = sx0; za.rho = st; za.rho_x0 = sx0; za.tw = p->tw;
+    za.mom = (double*)(p->ws + lay.mom) + 2 * (size_t)zb; za.L = g.L; za.nkz = p->nkz; za.x0 = (int)lo; za.ntiles = ntl;
+    const int nb = (int)((hi - lo + 1) * ntl);
+    UR_HIP(launch_pass_z(p->prec, n, Z_LOAD_R2C, za, nb, s));
+    zb += nb;
+    UR_HIP(hipEventRecord(p->ev[2 + buf], s));
+    YArgs ya{};
+    ya.A = A; ya.ax0 = sx0; ya.B = B; ya.bx0 = bx0; ya.bs = bs; ya.tw = p->tw; ya.L = g.L; ya.gen = 0;
+    ya.nkz = p->nkz; ya.xlo = (int)lo; ya.xhi = (int)hi; ya.xt0 = (int)xt; ya.nxt = 1; ya.ty = zt(p);
+    UR_HIP(launch_pass_y(p->prec, n, ya, s));
+  }
+  if (h2d_bytes) *h2d_bytes = copied;
+  // x pass over the whole spectrum + finalize
+  XArgs xa{};
+  xa.B = B; xa.bx0 = bx0; xa.bs = bs; xa.tw = p->tw; xa.nkz = p->nkz; xa.r2c = 1;
+  xa.xa = (int)bx0; xa.xb = (int)(bx0 + bs - 1);
+  xa.iscale = 1.0 / ((double)n * n * n) / ((double)n * n * n);
+  xa.nbins = p->nbins; xa.U = p->dU; xa.part = (double*)(p->ws + lay.part); xa.f0 = (double*)(p->ws + lay.f0);
+  xa.ncols = p->nkz * n;
+  UR_HIP(launch_pass_x(p->prec, n, X_FFT_BIN, -1, xa, x_blocks(p), s));
+  FinArgs fa{};
+  fa.part = xa.part; fa.nblk = x_blocks(p); fa.nbins = p->nbins; fa.mom = (const double*)(p->ws + lay.mom); fa.nzb = zb;
+  fa.f0 = xa.f0; fa.sum = h->sum; fa.sumsq = h->sumsq; fa.count = h->count; fa.totals = h->totals;
+  UR_HIP(launch_finalize(fa, s));
+  return UR_OK;
+}
+
+ur_status ur_adjoint(ur_plan* p, const void* rho, const ur_cell* cell, const ur_mask* mask, const ur_hist* fwd,
+                     const double* g_bin, void* grad_rho, double* grad_amp, void* stream) {
+  if (!p || !fwd || !fwd->count || !g_bin) return fail(UR_ERR_INVALID, "null argument");
+  if (p->nbins < 1) return fail(UR_ERR_STATE, "no bins set on the plan");
+  if ((rho != nullptr) == (cell != nullptr)) return fail(UR_ERR_INVALID, "give exactly one of rho and cell");
+  if (grad_amp && !cell) return fail(UR_ERR_INVALID, "grad_amp needs the cell description");
+  if (!grad_rho && !grad_amp) return UR_OK;
+  hipStream_t s = (hipStream_t)stream;
+  Layout lay = layout_incore(p, p->nbins);
+  UR_TRY(ensure_ws(p, lay.total, s));
+  const int n = p->n, c2c = (p->flags & UR_C2C) ? 1 : 0, tx = y_tile(p->prec, n);
+  char* A = p->ws + lay.A;
+  char* B = p->ws + lay.B;
+  FwdGeom g{};
+  CellTables t{};
+  ZArgs za{};
+  int zmode;
+  if (cell) {
+    UR_TRY(check_cell(cell));
+    ur_zoom z1{n, 1};
+    UR_TRY(check_level(p, cell, mask, &z1, g.L, g.m));
+    UR_TRY(prepare_cell(p, cell, 1, t, s));
+    long long xlo, xhi;
+    plane_range(g.L, g.m, xlo, xhi);
+    if (xlo < 0) xlo = 0;
+    if (xhi > n - 1) xhi = n - 1;
+    g.xlo = (int)xlo; g.xhi = (int)xhi; g.gen = 1;
+    za.cellT = t.cellT; za.cb = t.cb; za.pre = t.pre; za.cbn = t.cbn;
+    zmode = c2c ? Z_GEN_C2C : Z_GEN_R2C;
+  } else {
+    g.xlo = 0; g.xhi = n - 1; g.gen = 0; g.L = make_level(n, n, 1, 1);
+    za.rho = rho; za.rho_x0 = 0;
+    zmode = c2c ? Z_LOAD_C2C : Z_LOAD_R2C;
+  }
+  g.ax0 = 0;
+  // forward transform along z and y (recomputed; nothing stored from the forward call)
+  long long bx0 = 0;
+  if (g.xlo <= g.xhi) {
+    za.A = A; za.ax0 = 0; za.tw = p->tw; za.mom = nullptr; za.L = g.L; za.m = g.m; za.nkz = p->nkz;
+    za.x0 = g.xlo; za.ntiles = ntiles(p);
+    UR_HIP(launch_pass_z(p->prec, n, zmode, za, (g.xhi - g.xlo + 1) * za.ntiles, s));
+    YArgs ya{};
+    ya.A = A; ya.ax0 = 0; ya.B = B; ya.bx0 = 0; ya.bs = n; ya.tw = p->tw; ya.L = g.L; ya.m = g.m; ya.gen = g.gen;
+    ya.nkz = p->nkz; ya.xlo = g.xlo; ya.xhi = g.xhi; ya.xt0 = g.xlo / tx; ya.nxt = g.xhi / tx - g.xlo / tx + 1; ya.ty = zt(p);
+    UR_HIP(launch_pass_y(p->prec, n, ya, s));
+    bx0 = (long long)(g.xlo / tx) * tx;
+  }
+  // x: transform, weight by G(|q|) 2/n^6, inverse transform (all rows)
+  XAdjArgs xj{};
+  xj.B = B; xj.tw = p->tw; xj.nkz = p->nkz; xj.r2c = !c2c;
+  xj.xa = (int)bx0; xj.xb = g.xlo <= g.xhi ? (int)((g.xhi / tx) * tx + tx - 1) : -1;
+  xj.nbins = p->nbins; xj.U = p->dU; xj.g_bin = g_bin; xj.count = fwd->count;
+  xj.gscale = 2.0 / ((double)n * n * n) / ((double)n * n * n); xj.ncols = p->nkz * n;
+  UR_HIP(launch_pass_x_adj(p->prec, n, xj, x_blocks(p), s));
+  YInvArgs yi{};
+  yi.B = B; yi.A = A; yi.tw = p->tw; yi.nkz = p->nkz; yi.xt0 = 0; yi.nxt = n / tx;
+  UR_HIP(launch_pass_y_inv(p->prec, n, yi, s));
+  // the inverse z pass writes grad_rho, or the free B buffer when only grad_amp is wanted
+  void* gr = grad_rho ? grad_rho : (void*)B;
+  ZInvArgs zi{};
+  zi.A = A; zi.out = gr; zi.tw = p->tw; zi.nkz = p->nkz; zi.ntiles = n / zinv_tile(p->prec, n, c2c); zi.scale = 1.0;
+  UR_HIP(launch_pass_z_inv(p->prec, n, c2c, zi, s));
+  if (grad_amp) {
+    if (c2c) return fail(UR_ERR_UNSUPPORTED, "amplitude gradients need an UR_R2C plan");
+    const int c = cell->c, c3 = c * c * c;
+    FoldArgs fo{};
+    fo.g = gr; fo.L = g.L; fo.m = g.m; fo.gcell = t.gcell; fo.part = t.fold_part; fo.npencils = n * n;
+    if (c <= 16) {
+      UR_HIP(launch_fold(p->prec, n, fo, kFoldBlocks, s));
+      UR_HIP(launch_fold_reduce(c3, t.fold_part, kFoldBlocks, t.gcell, s));
+    } else {
+      UR_HIP(launch_zero(t.gcell, (size_t)c3 * 8, s));
+      UR_HIP(launch_fold(p->prec, n, fo, kFoldBlocks, s));
+    }
+    UR_HIP(launch_grad_amp(c, cell->n_atoms, t.prof, t.gcell, grad_amp, s));
+  }
+  return UR_OK;
+}
+
+ur_status ur_merge_zooms(int32_t nlevels, const ur_hist* levels, const int32_t* n, const double* voxel, int32_t nbins,
+                         const double* edges, int32_t mode, double n_min, double* mean, double* sem, int32_t* owner,
+                         void* stream) {
+  if (nlevels < 1 || nlevels > 8) return fail(UR_ERR_INVALID, "nlevels = %d outside [1, 8]", nlevels);
+  if (!levels || !n || !voxel || !edges || !mean || !sem || !owner) return fail(UR_ERR_INVALID, "null argument");
+  if (nbins < 1) return fail(UR_ERR_INVALID, "nbins must be >= 1");
+  if (mode < 0 || mode > 2) return fail(UR_ERR_INVALID, "unknown merge mode %d", mode);
+  MergeArgs a{};
+  a.nlevels = nlevels;
+  std::vector<int> ord(nlevels);
+  for (int k = 0; k < nlevels; ++k) {
+    if (!levels[k].sum || !levels[k].sumsq || !levels[k].count) return fail(UR_ERR_INVALID, "level %d histogram is null", k);
+    if (n[k] < 1 || !(voxel[k] > 0.0)) return fail(UR_ERR_INVALID, "level %d geometry invalid", k);
+    a.sum[k] = levels[k].sum;
+    a.sumsq[k] = levels[k].sumsq;
+    a.count[k] = levels[k].count;
+    double n3 = (double)n[k] * n[k] * n[k];
+    a.scale[k] = n3 * n3;
+    a.dq[k] = 2.0 * M_PI / ((double)n[k] * voxel[k]);
+    a.qcut[k] = sqrt(3.0) * M_PI / (2.0 * voxel[k]);
+    ord[k] = k;
+  }
+  std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return voxel[x] < voxel[y]; });
+  for (int k = 0; k < nlevels; ++k) a.order[k] = ord[k];
+  a.mode = mode; a.n_min = n_min; a.nbins = nbins; a.edges = edges; a.mean = mean; a.sem = sem; a.owner = owner;
+  UR_HIP(launch_merge(a, (hipStream_t)stream));
+  return UR_OK;
+}
+
+ur_status ur_graph_begin(void* stream) {
+  if (!stream) return fail(UR_ERR_INVALID, "capture needs a non-null stream");
+  UR_HIP(hipStreamBeginCapture((hipStream_t)stream, hipStreamCaptureModeThreadLocal));
+  return UR_OK;
+}
+
+ur_status ur_graph_end(void* stream, void** graph_exec) {
+  if (!stream || !graph_exec) return fail(UR_ERR_INVALID, "null argument");
+  hipGraph_t g = nullptr;
+  UR_HIP(hipStreamEndCapture((hipStream_t)stream, &g));
+  hipGraphExec_t ex = nullptr;
+  hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return fail(UR_ERR_HIP, "hipGraphInstantiate failed: %s", hipGetErrorString(e));
+  *graph_exec = (void*)ex;
+  return UR_OK;
+}
+
+ur_status ur_graph_launch(void* graph_exec, void* stream) {
+  if (!graph_exec) return fail(UR_ERR_INVALID, "null graph");
+  UR_HIP(hipGraphLaunch((hipGraphExec_t)graph_exec, (hipStream_t)stream));
+  return UR_OK;
+}
+
+ur_status ur_graph_destroy(void* graph_exec) {
+  if (!graph_exec) return UR_OK;
+  UR_HIP(hipGraphExecDestroy((hipGraphExec_t)graph_exec));
+  return UR_OK;
+}
+
+}  // extern "C"

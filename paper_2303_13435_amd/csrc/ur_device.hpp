@@ -1,0 +1,173 @@
+// Device building blocks for the gfx950 scattering-simulation kernels:
+// complex arithmetic, in-register radix-2/4/8/16 DFTs, and a Stockham
+// (self-sorting) FFT of length N executed by a group of G = N/E lanes of one
+// wavefront, with the data exchanged through LDS between radix stages.
+//
+// The transform computed is the discrete Fourier transform of eq. 1 along one
+// axis (unnormalised; the caller applies the 1/(MNL) factor where needed), and
+// its inverse (DIR = +1).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ur {
+
+template <typename T> struct cx { T x, y; };
+
+template <typename T> __device__ __forceinline__ cx<T> mk(T a, T b) { cx<T> r; r.x = a; r.y = b; return r; }
+template <typename T> __device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) { return mk(a.x + b.x, a.y + b.y); }
+template <typename T> __device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) { return mk(a.x - b.x, a.y - b.y); }
+template <typename T> __device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) { return mk(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+// a * conj(b)
+template <typename T> __device__ __forceinline__ cx<T> cmulc(cx<T> a, cx<T> b) { return mk(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y); }
+template <typename T> __device__ __forceinline__ cx<T> conjg(cx<T> a) { return mk(a.x, -a.y); }
+template <typename T> __device__ __forceinline__ cx<T> scale(cx<T> a, T s) { return mk(a.x * s, a.y * s); }
+
+// LDS ordering between the lanes of one wavefront: the fences keep the
+// compiler (and the memory model) from moving LDS accesses across the point.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// multiply by exp(DIR * 2 pi i m / 16), m in [0, 8)
+template <typename T, int DIR>
+__device__ __forceinline__ cx<T> rot16(cx<T> a, int m) {
+  const T c1 = (T)0.92387953251128675613;   // cos(pi/8)
+  const T s1 = (T)0.38268343236508977173;   // sin(pi/8)
+  const T s2 = (T)0.70710678118654752440;   // cos(pi/4)
+  const T D = (T)DIR;
+  switch (m) {
+    case 0: return a;
+    case 4: return mk(-D * a.y, D * a.x);                                 // * (D i)
+    case 2: return mk(s2 * (a.x - D * a.y), s2 * (a.y + D * a.x));        // * (1 + D i)/sqrt2
+    case 6: return mk(-s2 * (a.x + D * a.y), s2 * (D * a.x - a.y));       // * (-1 + D i)/sqrt2
+    case 1: return mk(a.x * c1 - a.y * (D * s1), a.x * (D * s1) + a.y * c1);
+    case 3: return mk(a.x * s1 - a.y * (D * c1), a.x * (D * c1) + a.y * s1);
+    case 5: return mk(-a.x * s1 - a.y * (D * c1), a.x * (D * c1) - a.y * s1);
+    default: return mk(-a.x * c1 - a.y * (D * s1), a.x * (D * s1) - a.y * c1);  // m == 7
+  }
+}
+
+// In-register DFT of size R (power of two <= 16), natural order in and out:
+// X_k = sum_r v_r exp(DIR 2 pi i r k / R). Radix-2 decimation in time.
+template <typename T, int R, int DIR> struct DFT {
+  static __device__ __forceinline__ void run(cx<T>* v) {
+    cx<T> e[R / 2], o[R / 2];
+#pragma unroll
+    for (int i = 0; i < R / 2; ++i) { e[i] = v[2 * i]; o[i] = v[2 * i + 1]; }
+    DFT<T, R / 2, DIR>::run(e);
+    DFT<T, R / 2, DIR>::run(o);
+#pragma unroll
+    for (int k = 0; k < R / 2; ++k) {
+      cx<T> t = rot16<T, DIR>(o[k], k * (16 / R));
+      v[k] = e[k] + t;
+      v[k + R / 2] = e[k] - t;
+    }
+  }
+};
+template <typename T, int DIR> struct DFT<T, 1, DIR> {
+  static __device__ __forceinline__ void run(cx<T>*) {}
+};
+
+// Padded LDS index: one spare element every 16 breaks the power-of-two
+// strides of the Stockham write pattern across LDS banks.
+__device__ __forceinline__ int pad(int i) { return i + (i >> 4); }
+template <int N> struct Padded { static constexpr int size = N + N / 16; };
+
+// Elements per lane for a length-N column; G = N / E lanes per column, G <= 64
+// so that a column never spans two wavefronts.
+template <int N> struct Geo {
+  static constexpr int E = N <= 16 ? N : (N == 512 ? 8 : (N <= 1024 ? 16 : (N == 2048 ? 32 : 64)));
+  static constexpr int G = N / E;
+  static_assert(G >= 1 && G <= 64, "column group must fit one wavefront");
+};
+
+// radix of the stage with sub-transform length L: at most 16 and at most the
+// per-lane element count, so each lane runs whole butterflies
+template <int N, int L> struct Radix {
+  static constexpr int cap = Geo<N>::E < 16 ? Geo<N>::E : 16;
+  static constexpr int r = (N / L) < cap ? (N / L) : cap;
+};
+
+// One Stockham radix-R stage with sub-transform length L (inputs read from
+// the LDS column s, outputs written back to s, in place through registers).
+// Lane g of the group performs butterflies b = g + G*i, i < E/R.
+template <typename T, int N, int L, int DIR>
+__device__ __forceinline__ void stage_lds(cx<T>* s, int g, const cx<T>* __restrict__ tw) {
+  constexpr int E = Geo<N>::E, G = Geo<N>::G, R = Radix<N, L>::r, NB = E / R;
+  static_assert(NB * R == E, "radix must divide the per-lane count");
+  cx<T> v[NB][R];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    int b = g + G * i;
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[i][r] = s[pad(b + r * (N / R))];
+  }
+  wave_sync();
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    int b = g + G * i;
+    int j = b % L;
+    if (L > 1) {
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        cx<T> w = tw[(r * j) * (N / (L * R))];     // exp(-2 pi i r j / (L R))
+        v[i][r] = DIR < 0 ? cmul(v[i][r], w) : cmulc(v[i][r], w);
+      }
+    }
+    DFT<T, R, DIR>::run(v[i]);
+    int o = (b / L) * L * R + j;
+#pragma unroll
+    for (int r = 0; r < R; ++r) s[pad(o + r * L)] = v[i][r];
+  }
+  wave_sync();
+}
+
+template <typename T, int N, int L, int DIR>
+__device__ __forceinline__ void stages_from(cx<T>* s, int g, const cx<T>* __restrict__ tw) {
+  if constexpr (L < N) {
+    stage_lds<T, N, L, DIR>(s, g, tw);
+    stages_from<T, N, L * Radix<N, L>::r, DIR>(s, g, tw);
+  }
+}
+
+// First stage fed from registers. The caller provides, for lane g, the E
+// inputs in the order v[i*R0 + r] = x[b + r*(N/R0)], b = g + G*i, with R0 the
+// first radix. Results of the whole transform are left in natural order in
+// the LDS column s (padded indexing).
+template <typename T, int N, int DIR>
+__device__ __forceinline__ void fft_column(cx<T>* s, int g, const cx<T>* __restrict__ tw, cx<T>* v) {
+  constexpr int E = Geo<N>::E, G = Geo<N>::G, R = Radix<N, 1>::r, NB = E / R;
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    int b = g + G * i;
+    DFT<T, R, DIR>::run(v + i * R);
+#pragma unroll
+    for (int r = 0; r < R; ++r) s[pad(b * R + r)] = v[i * R + r];
+  }
+  wave_sync();
+  stages_from<T, N, R, DIR>(s, g, tw);
+}
+
+// Index of the r-th input of lane g's i-th first-stage butterfly.
+template <int N>
+__device__ __forceinline__ int first_index(int g, int i, int r) {
+  constexpr int G = Geo<N>::G, R = Radix<N, 1>::r;
+  return (g + G * i) + r * (N / R);
+}
+
+// signed frequency index of u in [0, n)
+__device__ __forceinline__ int sidx(int u, int n) { return u < n / 2 ? u : u - n; }
+
+// exact integer square root (largest r with r*r <= v), v >= 0
+__device__ __host__ __forceinline__ long long isqrt_ll(long long v) {
+  if (v <= 0) return 0;
+  long long r = (long long)sqrt((double)v);
+  while (r * r > v) --r;
+  while ((r + 1) * (r + 1) <= v) ++r;
+  return r;
+}
+
+}  // namespace ur

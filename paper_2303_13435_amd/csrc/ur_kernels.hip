@@ -1,0 +1,1106 @@
+// gfx950 kernels of the scattering-simulation hot path (arXiv 2303.13435):
+//   pass Z  : ED generation (tiled cell x mask, zoom block sums) fused with
+//             the first 1D transform (r2c, two real pencils per complex FFT),
+//             written transposed as [x][kz][y] in 128-byte row segments;
+//   pass Y  : contiguous column FFTs along y, written transposed as
+//             [kz][ky][x] in 128-byte segments;
+//   pass X  : contiguous column FFTs along x with |F|^2 and integer-threshold
+//             |Q| binning fused (persistent blocks, LDS histograms);
+//   finalize: fixed-order compensated reduction of the block histograms;
+//   merge   : zoom-level merge per bin;
+//   inverse passes and the adjoint column pass for the gradients.
+// eq. 1 defines the transform; eq. 2 is the axis-by-axis separation used.
+#include <hip/hip_runtime.h>
+
+#include "ur_device.hpp"
+#include "ur_geom.hpp"
+#include "ur_kernels.hpp"
+
+namespace ur {
+
+// ---------------------------------------------------------------------------
+// block configuration
+// ---------------------------------------------------------------------------
+template <typename T> struct Seg { static constexpr int cols = 128 / (int)sizeof(cx<T>); };  // 16 f32, 8 f64
+
+// z pass: groups per block (each group = one complex FFT = two real pencils in r2c)
+template <typename T, int N, bool C2C> struct ZCfg {
+  static constexpr int G = Geo<N>::G;
+  static constexpr int want = C2C ? Seg<T>::cols : Seg<T>::cols / 2;
+  static constexpr int fill = 256 / G > 0 ? 256 / G : 1;
+  static constexpr int ng0 = want > fill ? want : fill;
+  static constexpr int cap = C2C ? N : N / 2;
+  static constexpr int NG = ng0 < cap ? ng0 : cap;
+  static constexpr int TY = C2C ? NG : 2 * NG;
+  static constexpr int threads = NG * G;
+};
+// y pass: x planes per block
+template <typename T, int N> struct YCfg {
+  static constexpr int G = Geo<N>::G;
+  static constexpr int TX = Seg<T>::cols < N ? Seg<T>::cols : N;
+  static constexpr int threads = TX * G;
+};
+// x pass: columns per block
+template <int N> struct XCfg {
+  static constexpr int G = Geo<N>::G;
+  static constexpr int NG = 256 / G > 0 ? (256 / G < 64 ? 256 / G : 64) : 1;
+  static constexpr int threads = NG * G;
+};
+template <int N> struct CS { static constexpr int v = Padded<N>::size + 1; };   // column stride in LDS
+
+// ---------------------------------------------------------------------------
+// reductions
+// ---------------------------------------------------------------------------
+template <int W = 64>
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = W / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, W);
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// cell synthesis: voxel-integrated Gaussians with periodic images
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double phi_cdf(double t) { return 0.5 * erfc(-t * 0.70710678118654752440); }
+
+__global__ void k_cell_profiles(int c, int n_atoms, const double* __restrict__ xyz,
+                                const double* __restrict__ sigma, double* __restrict__ prof) {
+  long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  long long total = (long long)n_atoms * 3 * c;
+  if (t >= total) return;
+  int i = (int)(t % c);
+  long long ad = t / c;
+  int d = (int)(ad % 3);
+  long long a = ad / 3;
+  double x = xyz[3 * a + d], s = sigma[a];
+  double acc = 0.0;
+  if (s > 0.0) {
+    int M = (int)ceil(8.0 * s / c) + 1;
+    if (M > 64) M = 64;
+    for (int m = -M; m <= M; ++m) {
+      double base = (double)i - x + (double)m * c;
+      acc += phi_cdf((base + 0.5) / s) - phi_cdf((base - 0.5) / s);
+    }
+  }
+  prof[t] = acc;
+}
+
+__global__ void k_cell_sum(int c, int n_atoms, const double* __restrict__ amp,
+                           const double* __restrict__ prof, double bg, double* __restrict__ cell) {
+  long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  long long c3 = (long long)c * c * c;
+  if (v >= c3) return;
+  int k = (int)(v % c), j = (int)((v / c) % c), i = (int)(v / ((long long)c * c));
+  double acc = bg;
+  for (int a = 0; a < n_atoms; ++a) {
+    const double* p = prof + (size_t)a * 3 * c;
+    acc += amp[a] * p[i] * p[c + j] * p[2 * c + k];
+  }
+  cell[v] = acc;
+}
+
+template <typename T>
+__global__ void k_cell_tables(int c, int f, const double* __restrict__ cell, T* __restrict__ cellT,
+                              double* __restrict__ pre, T* __restrict__ cb, int cbn) {
+  long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  long long c3 = (long long)c * c * c;
+  if (t < c3) cellT[t] = (T)cell[t];
+  if (f > 1) {
+    // row prefix sums: pre[(i c + j)(c+1) + k] = sum_{k' < k} cell[i][j][k']
+    if (t < (long long)c * c) {
+      const double* row = cell + t * c;
+      double* pr = pre + t * (c + 1);
+      double s = 0.0;
+      pr[0] = 0.0;
+      for (int k = 0; k < c; ++k) { s += row[k]; pr[k + 1] = s; }
+    }
+    long long nb = (long long)cbn * cbn * cbn;
+    if (t < nb) {
+      int K = (int)(t % cbn), J = (int)((t / cbn) % cbn), I = (int)(t / ((long long)cbn * cbn));
+      double s = 0.0;
+      for (int a = 0; a < f; ++a)
+        for (int b = 0; b < f; ++b)
+          for (int d = 0; d < f; ++d)
+            s += cell[((size_t)((I * f + a) % c) * c + (size_t)((J * f + b) % c)) * c + (size_t)((K * f + d) % c)];
+      cb[t] = (T)s;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// density of one pencil (x, y) along z: tiled cell x mask, block-summed for
+// zoomed levels.  Exact integer geometry; values from the cell tables.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int pmodi(long long a, int m) { long long r = a % m; return (int)(r < 0 ? r + m : r); }
+
+template <typename T>
+struct Pencil {
+  long long zlo, zhi;       // coarse z range that can hold density
+  // f == 1
+  const T* row;             // cell row of this pencil (c values)
+  int zres0;                // residue offset: cell index of z is (z - o - h) mod c
+  // f > 1
+  long long rin;            // blocks with max|dz| <= rin are fully inside
+  int I, J;                 // block-table indices of this pencil
+  long long fx0, fy0;       // first fine x, y of the pencil's block column
+  bool live;
+
+  __device__ __forceinline__ void init(const ZArgs& a, long long X, long long Y) {
+    const Level& L = a.L;
+    col_range(L, a.m, X, Y, zlo, zhi);
+    live = zlo <= zhi;
+    if (!live) return;
+    if (L.f == 1) {
+      int i = pmodi(X - L.o - L.h, L.c), j = pmodi(Y - L.o - L.h, L.c);
+      row = (const T*)a.cellT + ((size_t)i * L.c + j) * L.c;
+    } else {
+      long long ax, bx, ay, by;
+      block_dist(L, X, ax, bx);
+      block_dist(L, Y, ay, by);
+      rin = mask_reach(a.m, bx, by);
+      fx0 = (long long)L.f * (X - L.o);
+      fy0 = (long long)L.f * (Y - L.o);
+      if (L.f <= L.c) {
+        I = pmodi(fx0 - L.h, L.c) / L.f;
+        J = pmodi(fy0 - L.h, L.c) / L.f;
+      } else {
+        I = J = 0;
+      }
+    }
+  }
+
+  // sum of the periodic cell row (i, j) over fine z in [za, zb]
+  __device__ __forceinline__ double rowsum(const ZArgs& a, int i, int j, long long za, long long zb) const {
+    const Level& L = a.L;
+    const int c = L.c;
+    const double* P = a.pre + ((size_t)i * c + j) * (c + 1);
+    int ka = pmodi(za - L.h, c);
+    long long len = zb - za + 1;
+    long long q = len / c;
+    int rem = (int)(len - q * c);
+    double s = (double)q * P[c];
+    if (ka + rem <= c) s += P[ka + rem] - P[ka];
+    else s += (P[c] - P[ka]) + P[ka + rem - c];
+    return s;
+  }
+
+  __device__ __forceinline__ T value(const ZArgs& a, long long X, long long Y, long long Z) const {
+    if (!live || Z < zlo || Z > zhi) return (T)0;
+    if (a.L.f == 1) return row[pmodi(Z - a.L.o - a.L.h, a.L.c)];
+    return value_zoom(a, Z);
+  }
+
+  __device__ __noinline__ T value_zoom(const ZArgs& a, long long Z) const {
+    const Level& L = a.L;
+    long long cz, dz;
+    block_dist(L, Z, cz, dz);
+    if (rin >= 0 && dz <= rin) {            // whole block inside: block table
+      int K = L.f <= L.c ? pmodi((long long)L.f * (Z - L.o) - L.h, L.c) / L.f : 0;
+      return ((const T*)a.cb)[((size_t)I * a.cbn + J) * a.cbn + K];
+    }
+    // boundary block: sum the inside part of every fine pencil of the block
+    const long long fz0 = (long long)L.f * (Z - L.o);
+    double s = 0.0;
+    for (int u = 0; u < L.f; ++u) {
+      long long fx = fx0 + u, dxa = fx - L.h < 0 ? L.h - fx : fx - L.h;
+      int i = pmodi(fx - L.h, L.c);
+      for (int w = 0; w < L.f; ++w) {
+        long long fy = fy0 + w, dya = fy - L.h < 0 ? L.h - fy : fy - L.h;
+        long long r = mask_reach(a.m, dxa, dya);
+        if (r < 0) continue;
+        long long za = fz0 > L.h - r ? fz0 : L.h - r;
+        long long zb = fz0 + L.f - 1 < L.h + r ? fz0 + L.f - 1 : L.h + r;
+        if (za > zb) continue;
+        s += rowsum(a, i, pmodi(fy - L.h, L.c), za, zb);
+      }
+    }
+    return (T)s;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// pass Z: density -> 1D transform along z -> A[x][kz][y]
+// ---------------------------------------------------------------------------
+template <typename T, int N, int MODE>
+__global__ void __launch_bounds__((ZCfg<T, N, (MODE >= 2)>::threads))
+k_pass_z(ZArgs a) {
+  constexpr bool C2C = MODE >= 2;
+  constexpr bool GEN = MODE == Z_GEN_R2C || MODE == Z_GEN_C2C;
+  using C = ZCfg<T, N, C2C>;
+  constexpr int G = C::G, NG = C::NG, TY = C::TY, E = Geo<N>::E;
+  constexpr int R0 = Radix<N, 1>::r, NB0 = E / R0, PS = CS<N>::v;
+  __shared__ cx<T> sm[NG * PS];
+  __shared__ double red[2 * (C::threads / 64 + 1)];
+
+  const int tile = blockIdx.x % a.ntiles;
+  const long long X = a.x0 + blockIdx.x / a.ntiles;
+  const int y0 = tile * TY;
+  const cx<T>* tw = (const cx<T>*)a.tw;
+  cx<T>* A = (cx<T>*)a.A;
+
+  if (GEN) {
+    long long ylo, yhi;
+    row_range(a.L, a.m, X, ylo, yhi);
+    if (ylo > yhi || y0 + TY - 1 < ylo || y0 > yhi) {   // no density in this tile
+      if (a.mom && threadIdx.x == 0) { a.mom[2 * blockIdx.x] = 0.0; a.mom[2 * blockIdx.x + 1] = 0.0; }
+      return;
+    }
+  }
+  const int q = threadIdx.x / G, g = threadIdx.x % G;
+  cx<T>* s = sm + q * PS;
+  cx<T> v[E];
+  double m1 = 0.0, m2 = 0.0;
+
+  if (!C2C) {
+    const long long yA = y0 + 2 * q, yB = yA + 1;
+    if (GEN) {
+      Pencil<T> pa, pb;
+      pa.init(a, X, yA);
+      pb.init(a, X, yB);
+#pragma unroll
+      for (int i = 0; i < NB0; ++i)
+#pragma unroll
+        for (int r = 0; r < R0; ++r) {
+          long long z = first_index<N>(g, i, r);
+          T ra = pa.value(a, X, yA, z), rb = pb.value(a, X, yB, z);
+          v[i * R0 + r] = mk(ra, rb);
+          m1 += (double)ra + (double)rb;
+          m2 += (double)ra * ra + (double)rb * rb;
+        }
+    } else {
+      const T* rho = (const T*)a.rho + ((size_t)(X - a.rho_x0) * N) * N;
+#pragma unroll
+      for (int i = 0; i < NB0; ++i)
+#pragma unroll
+        for (int r = 0; r < R0; ++r) {
+          int z = first_index<N>(g, i, r);
+          T ra = rho[(size_t)yA * N + z], rb = rho[(size_t)yB * N + z];
+          v[i * R0 + r] = mk(ra, rb);
+          m1 += (double)ra + (double)rb;
+          m2 += (double)ra * ra + (double)rb * rb;
+        }
+    }
+  } else {
+    const long long y = y0 + q;
+    if (GEN) {
+      Pencil<T> p;
+      p.init(a, X, y);
+#pragma unroll
+      for (int i = 0; i < NB0; ++i)
+#pragma unroll
+        for (int r = 0; r < R0; ++r) {
+          long long z = first_index<N>(g, i, r);
+          T ra = p.value(a, X, y, z);
+          v[i * R0 + r] = mk(ra, (T)0);
+          m1 += (double)ra;
+          m2 += (double)ra * ra;
+        }
+    } else {
+      const cx<T>* rho = (const cx<T>*)a.rho + ((size_t)(X - a.rho_x0) * N) * N;
+#pragma unroll
+      for (int i = 0; i < NB0; ++i)
+#pragma unroll
+        for (int r = 0; r < R0; ++r) {
+          int z = first_index<N>(g, i, r);
+          cx<T> e = rho[(size_t)y * N + z];
+          v[i * R0 + r] = e;
+          m1 += (double)e.x;
+          m2 += (double)e.x * e.x + (double)e.y * e.y;
+        }
+    }
+  }
+
+  fft_column<T, N, -1>(s, g, tw, v);
+
+  if (a.mom) {
+    constexpr int W = C::threads < 64 ? C::threads : 64;
+    m1 = wave_sum<W>(m1);
+    m2 = wave_sum<W>(m2);
+    if ((threadIdx.x & 63) == 0) { red[2 * (threadIdx.x >> 6)] = m1; red[2 * (threadIdx.x >> 6) + 1] = m2; }
+  }
+  __syncthreads();
+  if (a.mom && threadIdx.x == 0) {
+    double s1 = 0.0, s2 = 0.0;
+    for (int w = 0; w < (C::threads + 63) / 64; ++w) { s1 += red[2 * w]; s2 += red[2 * w + 1]; }
+    a.mom[2 * blockIdx.x] = s1;
+    a.mom[2 * blockIdx.x + 1] = s2;
+  }
+
+  cx<T>* Ap = A + ((size_t)(X - a.ax0) * a.nkz) * N + y0;
+  if (!C2C) {
+    // unpack the two real transforms: A_k = (Z_k + conj Z_{N-k}) / 2,
+    // B_k = (Z_k - conj Z_{N-k}) / (2i), k in [0, N/2]
+    for (int idx = threadIdx.x; idx < TY * (N / 2 + 1); idx += C::threads) {
+      const int j = idx % TY, kz = idx / TY;
+      const cx<T>* col = sm + (j >> 1) * PS;
+      const cx<T> zk = col[pad(kz)], zm = col[pad((N - kz) & (N - 1))];
+      cx<T> o;
+      if ((j & 1) == 0) o = mk((zk.x + zm.x) * (T)0.5, (zk.y - zm.y) * (T)0.5);
+      else              o = mk((zk.y + zm.y) * (T)0.5, (zm.x - zk.x) * (T)0.5);
+      Ap[(size_t)kz * N + j] = o;
+    }
+  } else {
+    for (int idx = threadIdx.x; idx < TY * N; idx += C::threads) {
+      const int j = idx % TY, kz = idx / TY;
+      Ap[(size_t)kz * N + j] = sm[j * PS + pad(kz)];
+    }
+  }
+}
+
+// ED materialisation (tile + mask + zoom) into a real [x][y][z] box: one
+// thread per voxel row segment, same generator as the z pass.
+template <typename T>
+__global__ void __launch_bounds__(256) k_rho_generate(ZArgs a, int n, T* __restrict__ rho) {
+  const long long t = blockIdx.x;                 // one block per pencil
+  const long long X = t / n, Y = t % n;
+  Pencil<T> p;
+  p.init(a, X, Y);
+  T* row = rho + t * n;
+  for (long long z = threadIdx.x; z < n; z += 256) row[z] = p.value(a, X, Y, z);
+}
+
+// ---------------------------------------------------------------------------
+// pass Y: A[x][kz][y] columns -> transform along y -> B[kz][ky][x]
+// ---------------------------------------------------------------------------
+template <typename T, int N>
+__global__ void __launch_bounds__((YCfg<T, N>::threads))
+k_pass_y(YArgs a) {
+  using C = YCfg<T, N>;
+  constexpr int G = C::G, TX = C::TX, E = Geo<N>::E;
+  constexpr int R0 = Radix<N, 1>::r, NB0 = E / R0, PS = CS<N>::v;
+  __shared__ cx<T> sm[TX * PS];
+
+  const int kz = blockIdx.x % a.nkz;
+  const int xt = a.xt0 + blockIdx.x / a.nkz;
+  const int xbase = xt * TX;
+  const int q = threadIdx.x / G, g = threadIdx.x % G;
+  const long long X = xbase + q;
+  const cx<T>* tw = (const cx<T>*)a.tw;
+  cx<T>* s = sm + q * PS;
+
+  long long ylo = 0, yhi = N - 1;
+  if (X < a.xlo || X > a.xhi) { ylo = 1; yhi = 0; }
+  else if (a.gen) {
+    row_range(a.L, a.m, X, ylo, yhi);
+    if (ylo <= yhi) { ylo = (ylo / a.ty) * a.ty; yhi = (yhi / a.ty) * a.ty + a.ty - 1; }
+  }
+  if (ylo > yhi) {
+    for (int i = g; i < N; i += G) s[pad(i)] = mk((T)0, (T)0);
+    wave_sync();
+  } else {
+    const cx<T>* col = (const cx<T>*)a.A + ((size_t)(X - a.ax0) * a.nkz + kz) * N;
+    cx<T> v[E];
+#pragma unroll
+    for (int i = 0; i < NB0; ++i)
+#pragma unroll
+      for (int r = 0; r < R0; ++r) {
+        int y = first_index<N>(g, i, r);
+        v[i * R0 + r] = (y >= ylo && y <= yhi) ? col[y] : mk((T)0, (T)0);
+      }
+    fft_column<T, N, -1>(s, g, tw, v);
+  }
+  __syncthreads();
+  cx<T>* Bp = (cx<T>*)a.B + ((size_t)kz * N) * a.bs + (xbase - a.bx0);
+  for (int idx = threadIdx.x; idx < TX * N; idx += C::threads) {
+    const int j = idx % TX, ky = idx / TX;
+    Bp[(size_t)ky * a.bs + j] = sm[j * PS + pad(ky)];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// binning helpers: thresholds U[0..nbins] in LDS; bin b holds U[b] <= n2 < U[b+1]
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int bin_search(const int* U, int nbins, long long n2) {
+  if (n2 < U[0]) return -1;
+  if (n2 >= U[nbins]) return nbins;
+  int lo = 0, hi = nbins;
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if ((long long)U[mid] <= n2) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ int bin_advance(const int* U, int nbins, int b, long long n2) {
+  while (b < nbins && n2 >= (long long)U[b + 1]) ++b;
+  return b;
+}
+
+// ---------------------------------------------------------------------------
+// pass X: B columns -> transform along x -> |F|^2 -> bins (or store)
+// ---------------------------------------------------------------------------
+template <typename T, int N, int MODE, int DIR>
+__global__ void __launch_bounds__((XCfg<N>::threads))
+k_pass_x(XArgs a) {
+  using C = XCfg<N>;
+  constexpr int G = C::G, NG = C::NG, E = Geo<N>::E;
+  constexpr int R0 = Radix<N, 1>::r, NB0 = E / R0, PS = CS<N>::v;
+  __shared__ cx<T> sm[NG * PS];
+  extern __shared__ double dyn[];
+  double* hist = dyn;                                  // 3 * nbins
+  int* U = (int*)(dyn + 3 * (size_t)a.nbins + 1);      // nbins + 1
+  double* tot_s = dyn + 3 * (size_t)a.nbins;
+
+  const int q = threadIdx.x / G, g = threadIdx.x % G;
+  cx<T>* s = sm + q * PS;
+  const cx<T>* tw = (const cx<T>*)a.tw;
+  constexpr bool BIN = MODE != X_FFT_STORE;
+
+  if (BIN) {
+    for (int i = threadIdx.x; i < 3 * a.nbins + 1; i += C::threads) dyn[i] = 0.0;
+    for (int i = threadIdx.x; i <= a.nbins; i += C::threads) U[i] = a.U[i];
+    __syncthreads();
+  }
+  double tot = 0.0;
+
+  for (long long col = (long long)blockIdx.x * NG + q; col < a.ncols; col += (long long)gridDim.x * NG) {
+    const int kz = (int)(col / N), ky = (int)(col % N);
+    const cx<T>* src = (const cx<T>*)a.B + (size_t)col * a.bs - a.bx0;
+    if (MODE == X_BIN_ONLY) {
+      for (int i = g; i < N; i += G) s[pad(i)] = (i >= a.xa && i <= a.xb) ? src[i] : mk((T)0, (T)0);
+      wave_sync();
+    } else {
+      cx<T> v[E];
+#pragma unroll
+      for (int i = 0; i < NB0; ++i)
+#pragma unroll
+        for (int r = 0; r < R0; ++r) {
+          int x = first_index<N>(g, i, r);
+          v[i * R0 + r] = (x >= a.xa && x <= a.xb) ? src[x] : mk((T)0, (T)0);
+        }
+      fft_column<T, N, DIR>(s, g, tw, v);
+    }
+    if (!BIN) {
+      cx<T>* dst = (cx<T>*)a.out + (size_t)col * N;
+      for (int i = g; i < N; i += G) dst[i] = scale(s[pad(i)], (T)a.oscale);
+      wave_sync();
+      continue;
+    }
+    // |F|^2 and bins. Lane g walks |h| over its own range in increasing
+    // order, so n2 and the bin index never decrease along the walk.
+    const int k = sidx(ky, N);
+    const int l = a.r2c ? kz : sidx(kz, N);
+    const double w = (a.r2c && kz != 0 && kz != N / 2) ? 2.0 : 1.0;
+    const long long base = (long long)k * k + (long long)l * l;
+    int hlo, hhi;
+    if (G == 1) { hlo = 0; hhi = N / 2 + 1; }
+    else { hlo = g * (E / 2); hhi = (g == G - 1) ? N / 2 + 1 : hlo + E / 2; }
+    int b = bin_search(U, a.nbins, (long long)hlo * hlo + base);
+    int cb = b;
+    double cs = 0.0, cs2 = 0.0, cc = 0.0;
+    for (int ha = hlo; ha < hhi; ++ha) {
+      const long long n2 = (long long)ha * ha + base;
+      b = bin_advance(U, a.nbins, b, n2);
+      double I1, I2 = 0.0, m;
+      {
+        cx<T> f = s[pad(ha)];
+        I1 = ((double)f.x * f.x + (double)f.y * f.y) * a.iscale;
+      }
+      if (ha != 0 && ha != N / 2) {
+        cx<T> f = s[pad(N - ha)];
+        I2 = ((double)f.x * f.x + (double)f.y * f.y) * a.iscale;
+        m = 2.0;
+      } else {
+        m = 1.0;
+      }
+      tot += w * (I1 + I2);
+      if (b != cb) {
+        if (cb >= 0 && cb < a.nbins && cc > 0.0) {
+          atomicAdd(&hist[3 * cb + 0], cs);
+          atomicAdd(&hist[3 * cb + 1], cs2);
+          atomicAdd(&hist[3 * cb + 2], cc);
+        }
+        cb = b; cs = cs2 = cc = 0.0;
+      }
+      cs += w * (I1 + I2);
+      cs2 += w * (I1 * I1 + I2 * I2);
+      cc += w * m;
+    }
+    if (cb >= 0 && cb < a.nbins && cc > 0.0) {
+      atomicAdd(&hist[3 * cb + 0], cs);
+      atomicAdd(&hist[3 * cb + 1], cs2);
+      atomicAdd(&hist[3 * cb + 2], cc);
+    }
+    if (col == 0 && g == 0 && a.f0) {
+      cx<T> f = s[pad(0)];
+      a.f0[0] = (double)f.x * sqrt(a.iscale);
+      a.f0[1] = (double)f.y * sqrt(a.iscale);
+    }
+    wave_sync();
+  }
+  if (!BIN) return;
+  tot = wave_sum(tot);
+  if ((threadIdx.x & 63) == 0) atomicAdd(tot_s, tot);
+  __syncthreads();
+  double* out = a.part + (size_t)blockIdx.x * (3 * (size_t)a.nbins + 1);
+  for (int i = threadIdx.x; i < 3 * a.nbins + 1; i += C::threads) out[i] = dyn[i];
+}
+
+// ---------------------------------------------------------------------------
+// finalize: fixed-order compensated sums over the block partials
+// ---------------------------------------------------------------------------
+struct Kahan {
+  double s = 0.0, c = 0.0;
+  __device__ __forceinline__ void add(double v) {
+    double t = s + v;
+    if (fabs(s) >= fabs(v)) c += (s - t) + v; else c += (v - t) + s;
+    s = t;
+  }
+  __device__ __forceinline__ double val() const { return s + c; }
+};
+
+// block b < nvb: 8 values x 32 phases; the last block reduces the z-pass moments
+__global__ void __launch_bounds__(256) k_finalize(FinArgs a) {
+  __shared__ double ls[256], lc[256];
+  const int nv = 3 * a.nbins + 1;
+  const int nvb = (nv + 7) / 8;
+  const int t = threadIdx.x;
+  if ((int)blockIdx.x < nvb) {
+    const int vv = t % 8, p = t / 8;
+    const int v = blockIdx.x * 8 + vv;
+    Kahan k;
+    if (v < nv) {
+      int w = p;
+      for (; w + 3 * 32 < a.nblk; w += 4 * 32) {
+        double x0 = a.part[(size_t)w * nv + v];
+        double x1 = a.part[(size_t)(w + 32) * nv + v];
+        double x2 = a.part[(size_t)(w + 64) * nv + v];
+        double x3 = a.part[(size_t)(w + 96) * nv + v];
+        k.add(x0); k.add(x1); k.add(x2); k.add(x3);
+      }
+      for (; w < a.nblk; w += 32) k.add(a.part[(size_t)w * nv + v]);
+    }
+    ls[t] = k.s;
+    lc[t] = k.c;
+    __syncthreads();
+    if (p == 0 && v < nv) {
+      Kahan r;
+      for (int pp = 0; pp < 32; ++pp) { r.add(ls[pp * 8 + vv]); r.add(lc[pp * 8 + vv]); }
+      double val = r.val();
+      if (v == nv - 1) {
+        a.totals[0] = val;
+        a.totals[1] = a.f0 ? a.f0[0] : 0.0;
+        a.totals[2] = a.f0 ? a.f0[1] : 0.0;
+      } else {
+        const int bb = v / 3, st = v % 3;
+        (st == 0 ? a.sum : st == 1 ? a.sumsq : a.count)[bb] = val;
+      }
+    }
+  } else {
+    // moments: thread t sums entries t, t+256, ... then fixed-order combine
+    Kahan k;
+    if (a.mom) for (int i = t; i < a.nzb; i += 256) k.add(a.mom[2 * (size_t)i + 1]);
+    ls[t] = k.s;
+    lc[t] = k.c;
+    __syncthreads();
+    if (t == 0) {
+      Kahan r;
+      for (int i = 0; i < 256; ++i) { r.add(ls[i]); r.add(lc[i]); }
+      a.totals[3] = r.val();
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// merge of zoom levels, one thread per bin
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double sem_from_sums(double cnt, double s, double s2) {
+  if (!(cnt > 1.0)) return NAN;
+  double var = (s2 - s * s / cnt) / (cnt - 1.0);
+  if (var < 0.0) var = 0.0;
+  return sqrt(var / cnt);
+}
+
+__global__ void k_merge(MergeArgs a) {
+  int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= a.nbins) return;
+  double lo = a.edges[b], hi = a.edges[b + 1];
+  double qc = lo > 0.0 ? sqrt(fabs(lo * hi)) : 0.5 * (lo + hi);
+  int valid[8];
+  int nv = 0;
+  for (int i = 0; i < a.nlevels; ++i) {
+    int k = a.order[i];
+    if (a.dq[k] <= qc && qc <= a.qcut[k] && a.count[k][b] >= a.n_min) valid[nv++] = k;
+  }
+  double mean = NAN, sem = NAN;
+  int owner = -1;
+  if (nv > 0) {
+    if (a.mode == 0) {
+      int k = valid[0];
+      double s = a.scale[k], cnt = a.count[k][b];
+      mean = s * a.sum[k][b] / cnt;
+      sem = s * sem_from_sums(cnt, a.sum[k][b], a.sumsq[k][b]);
+      owner = k;
+    } else if (a.mode == 1) {
+      double Cn = 0.0, S1 = 0.0, S2 = 0.0;
+      for (int i = 0; i < nv; ++i) {
+        int k = valid[i];
+        double s = a.scale[k];
+        Cn += a.count[k][b];
+        S1 += s * a.sum[k][b];
+        S2 += s * s * a.sumsq[k][b];
+      }
+      mean = S1 / Cn;
+      sem = sem_from_sums(Cn, S1, S2);
+      owner = nv;
+    } else {
+      double W = 0.0, WM = 0.0;
+      for (int i = 0; i < nv; ++i) {
+        int k = valid[i];
+        double s = a.scale[k], cnt = a.count[k][b];
+        double m = s * a.sum[k][b] / cnt;
+        double e = s * sem_from_sums(cnt, a.sum[k][b], a.sumsq[k][b]);
+        if (!(e > 0.0) || !isfinite(e)) continue;
+        W += 1.0 / (e * e);
+        WM += m / (e * e);
+      }
+      if (W > 0.0) { mean = WM / W; sem = 1.0 / sqrt(W); owner = nv; }
+    }
+  }
+  a.mean[b] = mean;
+  a.sem[b] = sem;
+  a.owner[b] = owner;
+}
+
+// ---------------------------------------------------------------------------
+// adjoint column pass along x: FFT_x, multiply by G(|q|) * gscale, IFFT_x
+// ---------------------------------------------------------------------------
+template <typename T, int N>
+__global__ void __launch_bounds__((XCfg<N>::threads))
+k_pass_x_adj(XAdjArgs a) {
+  using C = XCfg<N>;
+  constexpr int G = C::G, NG = C::NG, E = Geo<N>::E;
+  constexpr int R0 = Radix<N, 1>::r, NB0 = E / R0, PS = CS<N>::v;
+  __shared__ cx<T> sm[NG * PS];
+  extern __shared__ double dyn[];
+  double* Gb = dyn;                                   // nbins
+  int* U = (int*)(dyn + a.nbins);                     // nbins + 1
+  for (int i = threadIdx.x; i < a.nbins; i += C::threads)
+    Gb[i] = a.count[i] > 0.0 ? a.g_bin[i] / a.count[i] * a.gscale : 0.0;
+  for (int i = threadIdx.x; i <= a.nbins; i += C::threads) U[i] = a.U[i];
+  __syncthreads();
+  const int q = threadIdx.x / G, g = threadIdx.x % G;
+  cx<T>* s = sm + q * PS;
+  const cx<T>* tw = (const cx<T>*)a.tw;
+
+  for (long long col = (long long)blockIdx.x * NG + q; col < a.ncols; col += (long long)gridDim.x * NG) {
+    const int kz = (int)(col / N), ky = (int)(col % N);
+    cx<T>* src = (cx<T>*)a.B + (size_t)col * N;
+    cx<T> v[E];
+#pragma unroll
+    for (int i = 0; i < NB0; ++i)
+#pragma unroll
+      for (int r = 0; r < R0; ++r) {
+        int x = first_index<N>(g, i, r);
+        v[i * R0 + r] = (x >= a.xa && x <= a.xb) ? src[x] : mk((T)0, (T)0);
+      }
+    fft_column<T, N, -1>(s, g, tw, v);
+    const int k = sidx(ky, N);
+    const int l = a.r2c ? kz : sidx(kz, N);
+    const long long base = (long long)k * k + (long long)l * l;
+    int hlo, hhi;
+    if (G == 1) { hlo = 0; hhi = N / 2 + 1; }
+    else { hlo = g * (E / 2); hhi = (g == G - 1) ? N / 2 + 1 : hlo + E / 2; }
+    int b = bin_search(U, a.nbins, (long long)hlo * hlo + base);
+    for (int ha = hlo; ha < hhi; ++ha) {
+      const long long n2 = (long long)ha * ha + base;
+      b = bin_advance(U, a.nbins, b, n2);
+      const double gv = (b >= 0 && b < a.nbins) ? Gb[b] : 0.0;
+      cx<T> f = s[pad(ha)];
+      s[pad(ha)] = mk((T)(f.x * gv), (T)(f.y * gv));
+      if (ha != 0 && ha != N / 2) {
+        cx<T> f2 = s[pad(N - ha)];
+        s[pad(N - ha)] = mk((T)(f2.x * gv), (T)(f2.y * gv));
+      }
+    }
+    wave_sync();
+    stages_from<T, N, 1, +1>(s, g, tw);
+    for (int i = g; i < N; i += G) src[i] = s[pad(i)];
+    wave_sync();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// inverse pass Y: B[kz][ky][x] -> inverse transform along y -> A[x][kz][y]
+// ---------------------------------------------------------------------------
+template <typename T, int N>
+__global__ void __launch_bounds__((YCfg<T, N>::threads))
+k_pass_y_inv(YInvArgs a) {
+  using C = YCfg<T, N>;
+  constexpr int G = C::G, TX = C::TX, PS = CS<N>::v;
+  __shared__ cx<T> sm[TX * PS];
+  const int kz = blockIdx.x % a.nkz;
+  const int xt = a.xt0 + blockIdx.x / a.nkz;
+  const int xbase = xt * TX;
+  const cx<T>* Bp = (const cx<T>*)a.B + ((size_t)kz * N) * N + xbase;
+  for (int idx = threadIdx.x; idx < TX * N; idx += C::threads) {
+    const int j = idx % TX, ky = idx / TX;
+    sm[j * PS + pad(ky)] = Bp[(size_t)ky * N + j];
+  }
+  __syncthreads();
+  const int q = threadIdx.x / G, g = threadIdx.x % G;
+  cx<T>* s = sm + q * PS;
+  stages_from<T, N, 1, +1>(s, g, (const cx<T>*)a.tw);
+  cx<T>* col = (cx<T>*)a.A + ((size_t)(xbase + q) * a.nkz + kz) * N;
+  for (int i = g; i < N; i += G) col[i] = s[pad(i)];
+}
+
+// ---------------------------------------------------------------------------
+// inverse pass Z: A[x][kz][y] -> inverse transform along z -> real (c2r) or
+// complex box [x][y][z], times `scale`
+// ---------------------------------------------------------------------------
+template <typename T, int N, bool C2C>
+struct ZICfg {
+  static constexpr int G = Geo<N>::G;
+  static constexpr int TY = ZCfg<T, N, C2C>::TY;
+  static constexpr int NG = ZCfg<T, N, C2C>::NG;
+  static constexpr int threads = NG * G;
+  static constexpr int HS = C2C ? N : N / 2 + 1;       // staged rows per pencil
+};
+
+template <typename T, int N, bool C2C>
+__global__ void __launch_bounds__((ZICfg<T, N, C2C>::threads))
+k_pass_z_inv(ZInvArgs a) {
+  using C = ZICfg<T, N, C2C>;
+  constexpr int G = C::G, NG = C::NG, TY = C::TY, HS = C::HS, E = Geo<N>::E;
+  constexpr int R0 = Radix<N, 1>::r, NB0 = E / R0, PS = CS<N>::v;
+  constexpr int HP = HS + 1;                            // staged pencil stride (r2c)
+  // r2c: staged half spectra of TY pencils, then NG separate FFT columns;
+  // c2c: every staged pencil is its own group's FFT column (padded layout)
+  constexpr int LDS_ELEMS = C2C ? TY * PS : TY * HP + NG * PS;
+  __shared__ cx<T> lds[LDS_ELEMS];
+  const int tile = blockIdx.x % a.ntiles;
+  const long long X = blockIdx.x / a.ntiles;
+  const int y0 = tile * TY;
+  const cx<T>* Ap = (const cx<T>*)a.A + ((size_t)X * a.nkz) * N + y0;
+  for (int idx = threadIdx.x; idx < TY * HS; idx += C::threads) {
+    const int j = idx % TY, kz = idx / TY;
+    if (C2C) lds[j * PS + pad(kz)] = Ap[(size_t)kz * N + j];
+    else lds[j * HP + kz] = Ap[(size_t)kz * N + j];
+  }
+  __syncthreads();
+  const int q = threadIdx.x / G, g = threadIdx.x % G;
+  cx<T>* s = C2C ? lds + q * PS : lds + TY * HP + q * PS;
+  cx<T> v[E];
+  if (!C2C) {
+    const cx<T>* ha = lds + (2 * q) * HP;
+    const cx<T>* hb = lds + (2 * q + 1) * HP;
+#pragma unroll
+    for (int i = 0; i < NB0; ++i)
+#pragma unroll
+      for (int r = 0; r < R0; ++r) {
+        int k = first_index<N>(g, i, r);
+        cx<T> A_, B_;
+        if (k <= N / 2) {
+          A_ = ha[k]; B_ = hb[k];
+          if (k == 0 || k == N / 2) { A_.y = (T)0; B_.y = (T)0; }   // self-conjugate bins are real
+        } else {
+          A_ = conjg(ha[N - k]); B_ = conjg(hb[N - k]);
+        }
+        v[i * R0 + r] = mk(A_.x - B_.y, A_.y + B_.x);                  // A + i B
+      }
+  } else {
+#pragma unroll
+    for (int i = 0; i < NB0; ++i)
+#pragma unroll
+      for (int r = 0; r < R0; ++r) v[i * R0 + r] = s[pad(first_index<N>(g, i, r))];
+    wave_sync();
+  }
+  fft_column<T, N, +1>(s, g, (const cx<T>*)a.tw, v);
+  const T sc = (T)a.scale;
+  if (!C2C) {
+    T* outA = (T*)a.out + ((size_t)X * N + (y0 + 2 * q)) * N;
+    T* outB = outA + N;
+    for (int i = g; i < N; i += G) {
+      cx<T> z = s[pad(i)];
+      outA[i] = z.x * sc;
+      outB[i] = z.y * sc;
+    }
+  } else {
+    cx<T>* o = (cx<T>*)a.out + ((size_t)X * N + (y0 + q)) * N;
+    for (int i = g; i < N; i += G) o[i] = scale(s[pad(i)], sc);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// fold of a voxel field over the inside voxels onto the cell (adjoint of
+// tiling + masking), ED-1 geometry (factor 1)
+// ---------------------------------------------------------------------------
+template <typename T, bool LDS>
+__global__ void __launch_bounds__(256) k_fold(FoldArgs a, int n) {
+  extern __shared__ double acc[];
+  const int c = a.L.c, c3 = c * c * c;
+  if (LDS) {
+    for (int i = threadIdx.x; i < c3; i += 256) acc[i] = 0.0;
+    __syncthreads();
+  }
+  for (long long pc = blockIdx.x; pc < a.npencils; pc += gridDim.x) {
+    const long long X = pc / n, Y = pc % n;
+    long long zlo, zhi;
+    col_range(a.L, a.m, X, Y, zlo, zhi);
+    if (zlo > zhi) continue;
+    const int i = pmodi(X - a.L.o - a.L.h, c), j = pmodi(Y - a.L.o - a.L.h, c);
+    const T* gp = (const T*)a.g + (size_t)pc * n;
+    for (long long z = zlo + threadIdx.x; z <= zhi; z += 256) {
+      const int k = pmodi(z - a.L.o - a.L.h, c);
+      const double val = (double)gp[z];
+      if (LDS) atomicAdd(&acc[(i * c + j) * c + k], val);
+      else atomicAdd(&a.gcell[(i * c + j) * c + k], val);
+    }
+  }
+  if (LDS) {
+    __syncthreads();
+    double* out = a.part + (size_t)blockIdx.x * c3;
+    for (int i = threadIdx.x; i < c3; i += 256) out[i] = acc[i];
+  }
+}
+
+__global__ void k_fold_reduce(int c3, const double* __restrict__ part, int nblk, double* __restrict__ gcell) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= c3) return;
+  Kahan k;
+  for (int b = 0; b < nblk; ++b) k.add(part[(size_t)b * c3 + v]);
+  gcell[v] = k.val();
+}
+
+// grad_amp[a] = sum_j gcell[j] p_a,x[jx] p_a,y[jy] p_a,z[jz]; one block per atom
+__global__ void __launch_bounds__(256) k_grad_amp(int c, const double* __restrict__ prof,
+                                                  const double* __restrict__ gcell, double* __restrict__ ga) {
+  __shared__ double red[4];
+  const int at = blockIdx.x;
+  const double* p = prof + (size_t)at * 3 * c;
+  const int c3 = c * c * c;
+  double s = 0.0;
+  for (int v = threadIdx.x; v < c3; v += 256) {
+    int k = v % c, j = (v / c) % c, i = v / (c * c);
+    s += gcell[v] * p[i] * p[c + j] * p[2 * c + k];
+  }
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) ga[at] = red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ void k_zero(double* p, size_t n) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+#define UR_DISPATCH_N(n, MACRO)                  \
+  switch (n) {                                   \
+    case 16: MACRO(16); break;                   \
+    case 32: MACRO(32); break;                   \
+    case 64: MACRO(64); break;                   \
+    case 128: MACRO(128); break;                 \
+    case 256: MACRO(256); break;                 \
+    case 512: MACRO(512); break;                 \
+    case 1024: MACRO(1024); break;               \
+    default: return hipErrorInvalidValue;        \
+  }
+
+static unsigned nblk_of(long long total, int threads) { return (unsigned)((total + threads - 1) / threads); }
+
+hipError_t launch_cell_profiles(int c, int n_atoms, const double* xyz, const double* sigma, double* prof, hipStream_t s) {
+  long long total = (long long)n_atoms * 3 * c;
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cell_profiles, dim3(nblk_of(total, 256)), dim3(256), 0, s, c, n_atoms, xyz, sigma, prof);
+  return hipGetLastError();
+}
+
+hipError_t launch_cell_sum(int c, int n_atoms, const double* amp, const double* prof, double bg, double* cell, hipStream_t s) {
+  long long c3 = (long long)c * c * c;
+  hipLaunchKernelGGL(k_cell_sum, dim3(nblk_of(c3, 256)), dim3(256), 0, s, c, n_atoms, amp, prof, bg, cell);
+  return hipGetLastError();
+}
+
+hipError_t launch_cell_tables(int prec, int c, int f, const double* cell, void* cellT, double* pre, void* cb, int cbn, hipStream_t s) {
+  long long c3 = (long long)c * c * c;
+  long long nb = (long long)cbn * cbn * cbn;
+  long long total = c3 > nb ? c3 : nb;
+  if ((long long)c * c > total) total = (long long)c * c;
+  if (prec == 0)
+    hipLaunchKernelGGL(k_cell_tables<float>, dim3(nblk_of(total, 256)), dim3(256), 0, s, c, f, cell, (float*)cellT, pre, (float*)cb, cbn);
+  else
+    hipLaunchKernelGGL(k_cell_tables<double>, dim3(nblk_of(total, 256)), dim3(256), 0, s, c, f, cell, (double*)cellT, pre, (double*)cb, cbn);
+  return hipGetLastError();
+}
+
+template <typename T, int N>
+static hipError_t pass_z_t(int mode, const ZArgs& a, int nblocks, hipStream_t s) {
+  if (nblocks <= 0) return hipSuccess;
+  switch (mode) {
+    case Z_GEN_R2C: hipLaunchKernelGGL((k_pass_z<T, N, Z_GEN_R2C>), dim3(nblocks), dim3(ZCfg<T, N, false>::threads), 0, s, a); break;
+    case Z_LOAD_R2C: hipLaunchKernelGGL((k_pass_z<T, N, Z_LOAD_R2C>), dim3(nblocks), dim3(ZCfg<T, N, false>::threads), 0, s, a); break;
+    case Z_GEN_C2C: hipLaunchKernelGGL((k_pass_z<T, N, Z_GEN_C2C>), dim3(nblocks), dim3(ZCfg<T, N, true>::threads), 0, s, a); break;
+    case Z_LOAD_C2C: hipLaunchKernelGGL((k_pass_z<T, N, Z_LOAD_C2C>), dim3(nblocks), dim3(ZCfg<T, N, true>::threads), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_pass_z(int prec, int n, int mode, const ZArgs& a, int nblocks, hipStream_t s) {
+#define UR_Z(NN) return prec == 0 ? pass_z_t<float, NN>(mode, a, nblocks, s) : pass_z_t<double, NN>(mode, a, nblocks, s)
+  UR_DISPATCH_N(n, UR_Z);
+#undef UR_Z
+}
+
+template <typename T, int N>
+static hipError_t pass_y_t(const YArgs& a, hipStream_t s) {
+  long long nb = (long long)a.nkz * a.nxt;
+  if (nb <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_pass_y<T, N>), dim3((unsigned)nb), dim3(YCfg<T, N>::threads), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_pass_y(int prec, int n, const YArgs& a, hipStream_t s) {
+#define UR_Y(NN) return prec == 0 ? pass_y_t<float, NN>(a, s) : pass_y_t<double, NN>(a, s)
+  UR_DISPATCH_N(n, UR_Y);
+#undef UR_Y
+}
+
+template <typename T, int N>
+static hipError_t pass_x_t(int mode, int dir, const XArgs& a, int nblocks, hipStream_t s) {
+  size_t shm = mode == X_FFT_STORE ? 0 : (3 * (size_t)a.nbins + 1) * sizeof(double) + ((size_t)a.nbins + 1) * sizeof(int);
+  dim3 grid(nblocks), blk(XCfg<N>::threads);
+  if (mode == X_FFT_BIN) hipLaunchKernelGGL((k_pass_x<T, N, X_FFT_BIN, -1>), grid, blk, shm, s, a);
+  else if (mode == X_BIN_ONLY) hipLaunchKernelGGL((k_pass_x<T, N, X_BIN_ONLY, -1>), grid, blk, shm, s, a);
+  else if (dir < 0) hipLaunchKernelGGL((k_pass_x<T, N, X_FFT_STORE, -1>), grid, blk, shm, s, a);
+  else hipLaunchKernelGGL((k_pass_x<T, N, X_FFT_STORE, +1>), grid, blk, shm, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_pass_x(int prec, int n, int mode, int dir, const XArgs& a, int nblocks, hipStream_t s) {
+#define UR_X(NN) return prec == 0 ? pass_x_t<float, NN>(mode, dir, a, nblocks, s) : pass_x_t<double, NN>(mode, dir, a, nblocks, s)
+  UR_DISPATCH_N(n, UR_X);
+#undef UR_X
+}
+
+hipError_t launch_finalize(const FinArgs& a, hipStream_t s) {
+  int nv = 3 * a.nbins + 1;
+  int nvb = (nv + 7) / 8;
+  hipLaunchKernelGGL(k_finalize, dim3(nvb + 1), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_merge(const MergeArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_merge, dim3(nblk_of(a.nbins, 256)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+template <typename T, int N>
+static hipError_t pass_x_adj_t(const XAdjArgs& a, int nblocks, hipStream_t s) {
+  size_t shm = (size_t)a.nbins * sizeof(double) + ((size_t)a.nbins + 1) * sizeof(int);
+  hipLaunchKernelGGL((k_pass_x_adj<T, N>), dim3(nblocks), dim3(XCfg<N>::threads), shm, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_pass_x_adj(int prec, int n, const XAdjArgs& a, int nblocks, hipStream_t s) {
+#define UR_XA(NN) return prec == 0 ? pass_x_adj_t<float, NN>(a, nblocks, s) : pass_x_adj_t<double, NN>(a, nblocks, s)
+  UR_DISPATCH_N(n, UR_XA);
+#undef UR_XA
+}
+
+template <typename T, int N>
+static hipError_t pass_y_inv_t(const YInvArgs& a, hipStream_t s) {
+  long long nb = (long long)a.nkz * a.nxt;
+  if (nb <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_pass_y_inv<T, N>), dim3((unsigned)nb), dim3(YCfg<T, N>::threads), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_pass_y_inv(int prec, int n, const YInvArgs& a, hipStream_t s) {
+#define UR_YI(NN) return prec == 0 ? pass_y_inv_t<float, NN>(a, s) : pass_y_inv_t<double, NN>(a, s)
+  UR_DISPATCH_N(n, UR_YI);
+#undef UR_YI
+}
+
+template <typename T, int N>
+static hipError_t pass_z_inv_t(int c2c, const ZInvArgs& a, hipStream_t s) {
+  unsigned nb = (unsigned)((long long)N * a.ntiles);
+  if (c2c) hipLaunchKernelGGL((k_pass_z_inv<T, N, true>), dim3(nb), dim3(ZICfg<T, N, true>::threads), 0, s, a);
+  else hipLaunchKernelGGL((k_pass_z_inv<T, N, false>), dim3(nb), dim3(ZICfg<T, N, false>::threads), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_pass_z_inv(int prec, int n, int c2c, const ZInvArgs& a, hipStream_t s) {
+#define UR_ZI(NN) return prec == 0 ? pass_z_inv_t<float, NN>(c2c, a, s) : pass_z_inv_t<double, NN>(c2c, a, s)
+  UR_DISPATCH_N(n, UR_ZI);
+#undef UR_ZI
+}
+
+hipError_t launch_fold(int prec, int n, const FoldArgs& a, int nblocks, hipStream_t s) {
+  const int c3 = a.L.c * a.L.c * a.L.c;
+  const bool lds = a.L.c <= 16;
+  size_t shm = lds ? (size_t)c3 * sizeof(double) : 0;
+  if (prec == 0) {
+    if (lds) hipLaunchKernelGGL((k_fold<float, true>), dim3(nblocks), dim3(256), shm, s, a, n);
+    else hipLaunchKernelGGL((k_fold<float, false>), dim3(nblocks), dim3(256), shm, s, a, n);
+  } else {
+    if (lds) hipLaunchKernelGGL((k_fold<double, true>), dim3(nblocks), dim3(256), shm, s, a, n);
+    else hipLaunchKernelGGL((k_fold<double, false>), dim3(nblocks), dim3(256), shm, s, a, n);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_fold_reduce(int c3, const double* part, int nblk, double* gcell, hipStream_t s) {
+  hipLaunchKernelGGL(k_fold_reduce, dim3(nblk_of(c3, 256)), dim3(256), 0, s, c3, part, nblk, gcell);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_amp(int c, int n_atoms, const double* prof, const double* gcell, double* grad_amp, hipStream_t s) {
+  if (n_atoms <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_grad_amp, dim3(n_atoms), dim3(256), 0, s, c, prof, gcell, grad_amp);
+  return hipGetLastError();
+}
+
+hipError_t launch_rho_generate(int prec, int n, const ZArgs& a, void* rho, hipStream_t s) {
+  unsigned nn = (unsigned)((long long)n * n);
+  if (prec == 0) hipLaunchKernelGGL(k_rho_generate<float>, dim3(nn), dim3(256), 0, s, a, n, (float*)rho);
+  else hipLaunchKernelGGL(k_rho_generate<double>, dim3(nn), dim3(256), 0, s, a, n, (double*)rho);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
+  size_t n = bytes / sizeof(double);
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, (double*)p, n);
+  return hipGetLastError();
+}
+
+// tile geometry for the planner
+#define UR_TILE(NN) { if (prec == 0) return c2c ? ZCfg<float, NN, true>::TY : ZCfg<float, NN, false>::TY; \
+                      return c2c ? ZCfg<double, NN, true>::TY : ZCfg<double, NN, false>::TY; }
+int z_tile(int prec, int n, int c2c) {
+  switch (n) {
+    case 16: UR_TILE(16) case 32: UR_TILE(32) case 64: UR_TILE(64) case 128: UR_TILE(128)
+    case 256: UR_TILE(256) case 512: UR_TILE(512) case 1024: UR_TILE(1024)
+    default: return 0;
+  }
+}
+#undef UR_TILE
+int zinv_tile(int prec, int n, int c2c) { return z_tile(prec, n, c2c); }
+
+#define UR_YT(NN) return prec == 0 ? YCfg<float, NN>::TX : YCfg<double, NN>::TX
+int y_tile(int prec, int n) {
+  switch (n) {
+    case 16: UR_YT(16); case 32: UR_YT(32); case 64: UR_YT(64); case 128: UR_YT(128);
+    case 256: UR_YT(256); case 512: UR_YT(512); case 1024: UR_YT(1024);
+    default: return 0;
+  }
+}
+#undef UR_YT
+
+#define UR_XG(NN) return XCfg<NN>::NG
+int x_groups(int n) {
+  switch (n) {
+    case 16: UR_XG(16); case 32: UR_XG(32); case 64: UR_XG(64); case 128: UR_XG(128);
+    case 256: UR_XG(256); case 512: UR_XG(512); case 1024: UR_XG(1024);
+    default: return 0;
+  }
+}
+#undef UR_XG
+
+}  // namespace ur

@@ -1,0 +1,165 @@
+// Kernel argument blocks and host launchers of the gfx950 hot path.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "ur_geom.hpp"
+
+namespace ur {
+
+// Density source of the first (z) pass.
+enum ZMode { Z_GEN_R2C = 0, Z_LOAD_R2C = 1, Z_GEN_C2C = 2, Z_LOAD_C2C = 3 };
+// What the last (x) pass does with each transformed column.
+enum XMode { X_FFT_BIN = 0, X_BIN_ONLY = 1, X_FFT_STORE = 2 };
+
+struct ZArgs {
+  void* A;                  // out: [x - ax0][kz][y] complex
+  long long ax0;            // first plane held by A
+  const void* rho;          // LOAD: real (r2c) or complex (c2c) [x][y][z], planes from rho_x0
+  long long rho_x0;
+  const void* cellT;        // GEN: c^3 cell in the working precision
+  const void* cb;           // GEN, f > 1: block-summed cell, cbn^3
+  const double* pre;        // GEN, f > 1: per-row prefix sums of the FP64 cell, c^2 (c+1)
+  const void* tw;           // n twiddles exp(-2 pi i k / n)
+  double* mom;              // per block: sum rho, sum rho^2 (may be null)
+  Level L;
+  MaskP m;
+  int nkz;                  // rows per plane of A
+  int x0;                   // first plane of this launch
+  int ntiles;               // y tiles per plane
+  int cbn;                  // edge of the block table
+};
+
+struct YArgs {
+  const void* A;            // [x - ax0][kz][y]
+  long long ax0;
+  void* B;                  // out: [kz][ky][x - bx0], column stride bs
+  long long bx0;
+  long long bs;
+  const void* tw;
+  Level L;
+  MaskP m;
+  int gen;                  // rows of A hold density only inside the particle's row range
+  int nkz;
+  int xlo, xhi;             // planes written by the z pass
+  int xt0;                  // first x tile of the launch
+  int nxt;                  // number of x tiles
+  int ty;                   // y tile height of the z pass
+};
+
+struct XArgs {
+  const void* B;            // [kz][ky][x - bx0] columns of stride bs
+  long long bx0;
+  long long bs;
+  void* out;                // X_FFT_STORE: out columns [kz][ky][kx], stride n
+  const void* tw;
+  int nkz;
+  int r2c;                  // half spectrum (weights 1/2) or full
+  int xa, xb;               // rows of each column that hold data (others are zero)
+  double iscale;            // intensity scale: I = |v|^2 * iscale
+  double oscale;            // store scale
+  int nbins;
+  const int* U;             // nbins + 1 integer thresholds on n2
+  double* part;             // per block: 3*nbins hist + 1 total
+  double* f0;               // F(0) (2 doubles), written by the block holding it
+  int ncols;
+};
+
+struct FinArgs {
+  const double* part;       // nblk x (3 nbins + 1)
+  int nblk;
+  int nbins;
+  const double* mom;        // nzb x 2 (may be null)
+  int nzb;
+  const double* f0;
+  double* sum;
+  double* sumsq;
+  double* count;
+  double* totals;
+};
+
+struct MergeArgs {
+  int nlevels;
+  const double* sum[8];
+  const double* sumsq[8];
+  const double* count[8];
+  double scale[8];
+  double dq[8];
+  double qcut[8];
+  int order[8];             // level indices, finest voxel first
+  int mode;
+  double n_min;
+  int nbins;
+  const double* edges;      // device, nbins + 1
+  double* mean;
+  double* sem;
+  int* owner;
+};
+
+// adjoint, inverse passes
+struct XAdjArgs {
+  void* B;                  // columns, transformed in place (all n rows written)
+  const void* tw;
+  int nkz;
+  int r2c;
+  int xa, xb;
+  int nbins;
+  const int* U;
+  const double* g_bin;      // dL/dI_b
+  const double* count;      // forward bin counts
+  double gscale;            // 2 / n^6
+  int ncols;
+};
+
+struct YInvArgs {
+  const void* B;            // [kz][ky][x]
+  void* A;                  // out [x][kz][y]
+  const void* tw;
+  int nkz;
+  int xt0, nxt;
+};
+
+struct ZInvArgs {
+  const void* A;            // [x][kz][y]
+  void* out;                // real [x][y][z] (r2c) or complex (c2c)
+  const void* tw;
+  int nkz;
+  int ntiles;
+  double scale;
+};
+
+struct FoldArgs {
+  const void* g;            // real [x][y][z], n^3
+  Level L;
+  MaskP m;
+  double* gcell;            // c^3 accumulators (global atomics when c > 16)
+  double* part;             // per block c^3 (LDS path)
+  int npencils;
+};
+
+// host launchers (return hipError_t of the launch)
+hipError_t launch_cell_profiles(int c, int n_atoms, const double* xyz, const double* sigma, double* prof, hipStream_t s);
+hipError_t launch_cell_sum(int c, int n_atoms, const double* amp, const double* prof, double bg, double* cell, hipStream_t s);
+hipError_t launch_cell_tables(int prec, int c, int f, const double* cell, void* cellT, double* pre, void* cb, int cbn, hipStream_t s);
+hipError_t launch_pass_z(int prec, int n, int mode, const ZArgs& a, int nblocks, hipStream_t s);
+hipError_t launch_pass_y(int prec, int n, const YArgs& a, hipStream_t s);
+hipError_t launch_pass_x(int prec, int n, int mode, int dir, const XArgs& a, int nblocks, hipStream_t s);
+hipError_t launch_finalize(const FinArgs& a, hipStream_t s);
+hipError_t launch_merge(const MergeArgs& a, hipStream_t s);
+hipError_t launch_pass_x_adj(int prec, int n, const XAdjArgs& a, int nblocks, hipStream_t s);
+hipError_t launch_pass_y_inv(int prec, int n, const YInvArgs& a, hipStream_t s);
+hipError_t launch_pass_z_inv(int prec, int n, int c2c, const ZInvArgs& a, hipStream_t s);
+hipError_t launch_fold(int prec, int n, const FoldArgs& a, int nblocks, hipStream_t s);
+hipError_t launch_fold_reduce(int c3, const double* part, int nblk, double* gcell, hipStream_t s);
+hipError_t launch_grad_amp(int c, int n_atoms, const double* prof, const double* gcell, double* grad_amp, hipStream_t s);
+hipError_t launch_rho_generate(int prec, int n, const ZArgs& a, void* rho, hipStream_t s);
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
+
+// tile geometry used by the host planner (must match the kernels)
+int z_tile(int prec, int n, int c2c);     // y pencils per z-pass block
+int y_tile(int prec, int n);              // x planes per y-pass block
+int zinv_tile(int prec, int n, int c2c);  // y pencils per inverse z-pass block
+int x_groups(int n);                      // columns per x-pass block
+
+}  // namespace ur

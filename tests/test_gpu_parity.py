@@ -1,0 +1,229 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Tolerances (stated per comparison):
+* bin assignment and voxel counts: bit-exact (integer thresholds on n2);
+* FP64 path: bin means within 1e-12 relative; spectra within 1e-12 of max|F|;
+* FP32 path: bin means within 1e-5 relative; spectra within 2e-6 of max|F|
+  (single-precision butterflies, error ~ eps32 * sqrt(log2 n^3) in norm).
+"""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+F32_BIN = 1e-5
+F64_BIN = 1e-12
+
+
+@pytest.fixture(scope="module")
+def ur():
+    import torch
+    import paper_2303_13435_amd as ur
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return ur
+
+
+@pytest.fixture(scope="module")
+def orc():
+    import oracle
+    oracle.lib()
+    return oracle
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def run_simulate(ur, wl, prec=None):
+    import torch
+    p = wl.prec if prec is None else prec
+    plan = ur.Plan(wl.n, wl.voxel, p, c2c=(wl.transform == "c2c"))
+    plan.set_bins(wl.edges)
+    cell = ur.DeviceCell.from_host(wl.cell)
+    h = ur.Hist(wl.nbins)
+    plan.simulate(cell, wl.mask, wl.zoom, h)
+    torch.cuda.synchronize()
+    return h.numpy()
+
+
+def compare_bins(got, ref, tol, what="", n=None):
+    """Counts bit-exact; means within `tol` relative.  Bins whose exact mean
+    sits at the rounding level of the transform (e.g. exact zeros off the
+    Bragg comb of an unmasked lattice) are compared against an absolute floor
+    floor = (8 eps)^2 * Ibar, Ibar = mean intensity over the box, eps the unit
+    roundoff of the precision the GPU path ran in."""
+    assert np.array_equal(got["count"], ref["count"]), f"{what}: counts differ"
+    pop = ref["count"] > 0
+    m_ref = ref["mean"][pop]
+    m_got = got["mean"][pop]
+    eps = 6e-8 if tol >= 1e-6 else 1.2e-16
+    nvox = float(n) ** 3 if n is not None else float(np.sum(ref["count"]))
+    ibar = ref["totals"][0] / nvox
+    floor = (8.0 * eps) ** 2 * ibar
+    err = np.abs(m_got - m_ref)
+    den = np.maximum(np.abs(m_ref), floor)
+    rel = np.where(den > 0, err / np.where(den > 0, den, 1.0), 0.0)
+    worst = int(np.argmax(rel)) if rel.size else 0
+    _say(f"  {what}: {pop.sum()} bins, max rel err {rel.max() if rel.size else 0:.3e}")
+    assert rel.size == 0 or rel.max() <= tol, f"{what}: max rel err {rel.max():.3e} at bin {np.flatnonzero(pop)[worst]}"
+    return rel
+
+
+# ---------------------------------------------------------------------------
+# transform alone
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n", [16, 32, 64, 128])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_fft3d_r2c_forward_and_inverse(ur, orc, n, prec):
+    import torch
+    _say(f"fft3d r2c n={n} prec={prec}")
+    rho = W.random_density(1000 + n, n)
+    F = orc.forward(rho)                        # eq. 1, full spectrum [u][v][w]
+    ref = F[:, :, : n // 2 + 1].transpose(2, 1, 0)
+    plan = ur.Plan(n, 1.0, prec)
+    dt = torch.float32 if prec == 0 else torch.float64
+    x = torch.as_tensor(rho, dtype=dt, device="cuda").contiguous()
+    out = plan.fft3d(x)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+    _say(f"  spectrum rel err {err:.3e}")
+    assert err <= (2e-6 if prec == 0 else 1e-13)
+    back = plan.fft3d(out, direction=+1)
+    torch.cuda.synchronize()
+    err2 = np.max(np.abs(back.cpu().numpy() - rho)) / np.max(np.abs(rho))
+    assert err2 <= (2e-6 if prec == 0 else 1e-13)
+
+
+@pytest.mark.parametrize("n", [16, 64])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_fft3d_c2c(ur, orc, n, prec):
+    import torch
+    rng = np.random.default_rng(n)
+    z = rng.standard_normal((n, n, n)) + 1j * rng.standard_normal((n, n, n))
+    F = orc.fft3d(z, -1) / n ** 3
+    plan = ur.Plan(n, 1.0, prec, c2c=True)
+    dt = torch.complex64 if prec == 0 else torch.complex128
+    out = plan.fft3d(torch.as_tensor(z, dtype=dt, device="cuda").contiguous())
+    torch.cuda.synchronize()
+    err = np.max(np.abs(out.cpu().numpy() - F.transpose(2, 1, 0))) / np.max(np.abs(F))
+    assert err <= (2e-6 if prec == 0 else 1e-13)
+    back = plan.fft3d(out, direction=+1)
+    torch.cuda.synchronize()
+    assert np.max(np.abs(back.cpu().numpy() - z)) / np.max(np.abs(z)) <= (2e-6 if prec == 0 else 1e-13)
+
+
+# ---------------------------------------------------------------------------
+# fused forward path
+# ---------------------------------------------------------------------------
+
+SMALL_CASES = [
+    # (name, workload factory)
+    ("sphere64", lambda p: W.small(64, c=8, n_atoms=10, seed=7, radius=25.0, nbins=64, prec=p)),
+    ("sphere32_ragged", lambda p: W.small(32, c=4, n_atoms=3, seed=8, radius=11.3, nbins=40, prec=p)),
+    ("cube64", lambda p: W.small(64, c=8, n_atoms=5, seed=9, mask=W.cube(17), nbins=64, prec=p)),
+    ("troct64", lambda p: W.small(64, c=16, n_atoms=20, seed=10, mask=W.trunc_oct(27.0), nbins=64, prec=p)),
+    ("nomask32", lambda p: W.small(32, c=8, n_atoms=4, seed=12, mask=W.no_mask(), nbins=30, prec=p)),
+    ("sphere128", lambda p: W.small(128, c=16, n_atoms=40, seed=13, radius=50.0, nbins=128, prec=p)),
+    ("tiny16", lambda p: W.small(16, c=4, n_atoms=2, seed=14, radius=5.0, nbins=10, prec=p)),
+]
+
+
+@pytest.mark.parametrize("name,factory", SMALL_CASES)
+@pytest.mark.parametrize("prec", [0, 1])
+def test_simulate_small(ur, orc, name, factory, prec):
+    wl = factory(prec)
+    _say(f"simulate {name} prec={prec}")
+    ref = orc.simulate(wl)
+    got = run_simulate(ur, wl)
+    compare_bins(got, ref, F32_BIN if prec == 0 else F64_BIN, name, n=wl.n)
+    tol = 1e-6 if prec == 0 else 1e-12
+    assert abs(got["totals"][0] - ref["totals"][0]) <= tol * ref["totals"][0]          # sum of all I
+    assert abs(got["totals"][1] - ref["totals"][1]) <= tol * abs(ref["totals"][1])     # Re F(0)
+    assert abs(got["totals"][3] - ref["rho_sumsq"]) <= tol * ref["rho_sumsq"]          # sum rho^2
+    # Parseval on the GPU result alone
+    assert abs(got["totals"][0] - got["totals"][3] / wl.n ** 3) <= (1e-6 if prec == 0 else 1e-12) * got["totals"][0]
+
+
+def test_c1_full_complex_fp64(ur, orc):
+    wl = W.c1()
+    _say("C1 64^3 FP64 c2c")
+    ref = orc.simulate(wl)
+    got = run_simulate(ur, wl)
+    compare_bins(got, ref, F64_BIN, "C1", n=wl.n)
+
+
+def test_empty_particle(ur, orc):
+    wl = W.small(32, c=4, n_atoms=2, mask=W.Mask(W.MASK_SPHERE, -1), nbins=20)
+    got = run_simulate(ur, wl)
+    ref = orc.simulate(wl)
+    assert np.array_equal(got["count"], ref["count"])
+    assert np.all(got["sum"] == 0.0) and got["totals"][0] == 0.0
+
+
+@pytest.mark.parametrize("f,n,n1", [(2, 32, 32), (4, 32, 64), (8, 32, 128), (4, 64, 64)])
+def test_simulate_zoom_levels(ur, orc, f, n, n1):
+    """ED-2/ED-3 style levels: block sums of a larger ED-1 centred in a box."""
+    cell = W.draw_atoms(21, 12, 16 if f <= 4 else 8)
+    wl = W.Workload(f"zoom{f}", n, float(f), W.PREC_F64, "r2c", cell, W.sphere(0.42 * n1), W.Zoom(n1, f),
+                    W.default_log_edges(n, float(f), 48))
+    _say(f"zoom f={f} n={n} n1={n1}")
+    ref = orc.simulate(wl)
+    got = run_simulate(ur, wl)
+    compare_bins(got, ref, F64_BIN, f"zoom f={f}", n=n)
+    assert abs(got["totals"][3] - ref["rho_sumsq"]) <= 1e-12 * ref["rho_sumsq"]
+    got32 = run_simulate(ur, wl, prec=0)
+    compare_bins(got32, ref, F32_BIN, f"zoom f={f} fp32", n=n)
+
+
+def test_simulate_rho_and_intensity_bin(ur, orc):
+    import torch
+    wl = W.small(64, c=8, n_atoms=9, seed=31, radius=22.0, nbins=50, prec=1)
+    ref = orc.simulate(wl, return_fields=True)
+    plan = ur.Plan(wl.n, wl.voxel, 1)
+    plan.set_bins(wl.edges)
+    rho = torch.as_tensor(ref["rho"], device="cuda").contiguous()
+    h = ur.Hist(wl.nbins)
+    plan.simulate_rho(rho, h)
+    torch.cuda.synchronize()
+    compare_bins(h.numpy(), ref, F64_BIN, "simulate_rho", n=wl.n)
+    spec = torch.as_tensor(np.ascontiguousarray(ref["F"][:, :, : wl.n // 2 + 1].transpose(2, 1, 0)), device="cuda")
+    h2 = ur.Hist(wl.nbins)
+    plan.intensity_bin(spec, h2)
+    torch.cuda.synchronize()
+    compare_bins(h2.numpy(), ref, F64_BIN, "intensity_bin", n=wl.n)
+
+
+def test_rho_generate_matches_oracle_density(ur, orc):
+    import torch
+    for (n, f, n1) in [(64, 1, 64), (32, 4, 64)]:
+        cell = W.draw_atoms(41, 7, 8)
+        wl = W.Workload("g", n, 1.0, 1, "r2c", cell, W.trunc_oct(0.4 * n1), W.Zoom(n1, f), W.default_log_edges(n, 1.0, 8))
+        ref = orc.density(wl)
+        plan = ur.Plan(n, 1.0, 1)
+        got = plan.rho_generate(ur.DeviceCell.from_host(cell), wl.mask, wl.zoom)
+        torch.cuda.synchronize()
+        assert np.max(np.abs(got.cpu().numpy() - ref)) <= 1e-13 * np.max(np.abs(ref))
+        cg = plan.cell_synth(ur.DeviceCell.from_host(cell))
+        torch.cuda.synchronize()
+        assert np.max(np.abs(cg.cpu().numpy() - orc.cell_synth(cell))) <= 1e-14 * np.max(orc.cell_synth(cell))
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_c4_size_256(ur, orc, prec):
+    wl = W.c4()
+    if prec == 1:
+        wl = W.Workload(wl.name, wl.n, wl.voxel, 1, wl.transform, wl.cell, wl.mask, wl.zoom, wl.edges)
+    _say(f"C4 256^3 prec={prec}")
+    ref = orc.simulate(wl)
+    got = run_simulate(ur, wl)
+    compare_bins(got, ref, F32_BIN if prec == 0 else F64_BIN, "C4", n=wl.n)
