@@ -1,0 +1,204 @@
+#!/usr/bin/env python3
+"""Benchmark of the fused ED-generation -> 3D FFT -> |F|^2 -> |Q|-bin path.
+
+Workload (default): the 1024^3 FP32 headline box -- a 16-voxel cubic unit
+cell holding 40 seeded Gaussian atoms, tiled and masked by a sphere of radius
+400 voxels, r2c transform, 512 log-spaced |Q| bins.  Synthetic data stands in
+for the paper's DFT electron density of a ZIF-8 unit cell.
+
+A step is one call of the fused forward path on inputs already resident in
+HBM: cell synthesis from the atoms, the generating z pass, the y pass, the x
+pass with |F|^2 and binning, and the fixed-order finalize.  The line printed
+also carries, for the same box, the FP64 path and the forward+adjoint time,
+the roofline of the dominant kernel (per-pass HIP events on the launch
+stream, algorithmic bytes from the pruned geometry) and the FP64 CPU oracle
+timed on this host on a bounded sample of the workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0      # MI355X HBM3E
+PROFILES = os.path.join(ROOT, "profiles")
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("ur_kernels.hip", "ur_device.hpp", "ur_geom.hpp", "ur_kernels.hpp"):
+        with open(os.path.join(ROOT, "paper_2303_13435_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, or None when absent or taken from different kernel sources."""
+    path = os.path.join(PROFILES, f"traffic_{kernel}_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    if d.get("kernel_sources_sha256_16") != kernel_hash():
+        return None
+    return d.get("traffic_bytes_per_launch")
+
+
+def time_steps(fn, steps, warmup, torch):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return e0.elapsed_time(e1) / steps, wall
+
+
+def cpu_baseline(budget_s: float = 30.0):
+    """FP64 oracle, as it stands, on C2 (the headline recipe at half scale,
+    512^3): full path density -> eq. 1 -> binning.  Reported as voxels/s."""
+    import oracle
+    import workloads as W
+    oracle.lib()
+    wl = W.c2()
+    t0 = time.perf_counter()
+    oracle.simulate(wl)
+    dt = time.perf_counter() - t0
+    return {"value": wl.n ** 3 / dt, "unit": "voxels/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"C2 box 512^3 (same cell recipe, sphere R=200, 512 log bins), whole oracle path "
+                      f"in {dt:.1f} s; FFT lines on {oracle.num_threads()} OpenMP threads, binning on 1"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the FP64 and adjoint measurements")
+    ap.add_argument("--n", type=int, default=1024, help="box edge (1024 = the headline workload)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (reference kernel for HBM byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported by this build "
+              f"(the path runs on a single MI355X; multi-GPU sharding is design-only)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    if args.copy_calibration:
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")     # 1 GiB
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": a.numel() * 4, "copy_bytes_written": b.numel() * 4, "launches": 3}))
+        return
+    import paper_2303_13435_amd as ur
+    import workloads as W
+    if not os.path.exists(ur.LIBPATH):
+        from paper_2303_13435_amd import build as _b
+        _b.build()
+
+    n = args.n
+    wl = W.m1024() if n == 1024 else W.lattice_sphere(f"S{n}", n, 16, 40, 2, 400.0 * n / 1024, 512)
+    plan = ur.Plan(wl.n, wl.voxel, ur.UR_F32)
+    plan.set_bins(wl.edges)
+    cell = ur.DeviceCell.from_host(wl.cell)
+    hist = ur.Hist(wl.nbins)
+    step = lambda: plan.simulate(cell, wl.mask, wl.zoom, hist)
+    ms, wall = time_steps(step, args.steps, args.warmup, torch)
+    value = wl.n ** 3 / (ms * 1e-3)
+
+    # per-pass timing (HIP events on the launch stream) and algorithmic bytes
+    plan.set_timing(True)
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    passes = plan.read_timing()
+    plan.set_timing(False)
+    kernels = {}
+    for name, d in passes.items():
+        if d["launches"] == 0:
+            continue
+        avg = d["ms"] / d["launches"]
+        kernels[name] = {"avg_ms": round(avg, 5), "alg_bytes": d["bytes"],
+                         "alg_GBps": round(d["bytes"] / (avg * 1e-3) / 1e9, 1) if avg > 0 else None}
+    dom = max((k for k in kernels if k.startswith("pass_")), key=lambda k: kernels[k]["avg_ms"])
+    dk = kernels[dom]
+    achieved = dk["alg_GBps"]
+    traffic = measured_traffic(dom, wl.name)
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic}
+    path_bytes = sum(kernels[k]["alg_bytes"] for k in kernels)
+    path_ms = sum(kernels[k]["avg_ms"] for k in kernels)
+
+    extras = {"kernels": kernels, "path_alg_bytes": path_bytes,
+              "path_alg_GBps": round(path_bytes / (ms * 1e-3) / 1e9, 1),
+              "sum_kernel_ms": round(path_ms, 4)}
+    if not args.no_extras:
+        # FP64 path on the same box
+        wl64 = W.m1024(ur.UR_F64) if n == 1024 else wl
+        p64 = ur.Plan(wl.n, wl.voxel, ur.UR_F64)
+        p64.set_bins(wl.edges)
+        h64 = ur.Hist(wl.nbins)
+        ms64, _ = time_steps(lambda: p64.simulate(cell, wl.mask, wl.zoom, h64), max(3, args.steps // 2), 2, torch)
+        extras["fp64"] = {"ms_per_step": round(ms64, 4), "voxels_per_s": wl.n ** 3 / (ms64 * 1e-3)}
+        del p64
+        # forward + adjoint (chi^2 gradient w.r.t. the atom amplitudes), FP32
+        d = hist.numpy()
+        g_bin = torch.as_tensor(np.where(d["count"] > 0, 1.0, 0.0), device="cuda")
+        gamp = torch.empty(wl.cell.n_atoms, dtype=torch.float64, device="cuda")
+
+        def fwd_adj():
+            plan.simulate(cell, wl.mask, wl.zoom, hist)
+            plan.adjoint(hist, g_bin, cell=cell, mask=wl.mask, grad_amp=gamp)
+
+        ms_fa, _ = time_steps(fwd_adj, max(3, args.steps // 2), 2, torch)
+        extras["fwd_adjoint_ms"] = round(ms_fa, 4)
+        torch.cuda.synchronize()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline()
+
+    line = {
+        "metric": "voxels/s, FFT->|F|^2->Q-bin at 1024^3 FP32 (FP64 and fwd+adjoint ms in extras)",
+        "value": value,
+        "unit": "voxels/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{wl.name}: {wl.n}^3 FP32 r2c, 16-voxel cell x 40 Gaussian atoms (seed 2), "
+                               f"sphere R={int(round(400 * n / 1024))}, {wl.nbins} log |Q| bins",
+                   "box": wl.n, "nbins": wl.nbins, "parallelism": "single GPU"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "extras": extras,
+        "wall_s": round(wall, 3),
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -218,6 +218,17 @@ ur_status ur_graph_end(void* stream, void** graph_exec);
 ur_status ur_graph_launch(void* graph_exec, void* stream);
 ur_status ur_graph_destroy(void* graph_exec);
 
+/* Per-pass timing of the plan's own launches: when enabled, the forward path
+ * records a HIP event pair on the call's stream around each of its passes
+ * (0 cell tables, 1 z pass, 2 y pass, 3 x pass, 4 finalize).
+ * ur_plan_read_timing waits for those events and returns, per pass, the
+ * summed elapsed ms, the algorithmic HBM bytes of one launch (the bytes the
+ * pruned pass must read and write: spectrum elements moved x element size,
+ * plus partial histograms) and the number of timed launches since the last
+ * read.  Arrays hold npass (<= 5) entries. */
+ur_status ur_plan_set_timing(ur_plan* plan, int32_t enable);
+ur_status ur_plan_read_timing(ur_plan* plan, int32_t npass, double* ms, double* bytes, int32_t* launches);
+
 /* Thread-local description of the last failure on this thread. */
 const char* ur_last_error(void);
 

@@ -353,22 +353,31 @@ void or_bin(int n, const cdouble* F, double voxel, int nbins, const double* edge
     free(U); free(ks); free(kq); free(kv); free(cnt);
 }
 
-/* number of voxels of an n^3 box whose n2 falls in each bin (geometry only) */
+/* number of voxels of an n^3 box whose n2 falls in each bin (geometry only);
+ * integer counts, so the per-plane split over threads is exact */
 void or_bin_counts(int n, double voxel, int nbins, const double* edges, double* count)
 {
     long long* U = (long long*)malloc(sizeof(long long) * (nbins + 1));
     or_thresholds(n, voxel, nbins, edges, U);
     long long* cnt = (long long*)calloc((size_t)nbins, sizeof(long long));
-    for (long long u = 0; u < n; ++u) {
-        long long h = sgn_index(u, n);
-        for (long long v = 0; v < n; ++v) {
-            long long k = sgn_index(v, n);
-            for (long long w = 0; w < n; ++w) {
-                long long l = sgn_index(w, n);
-                int b = find_bin(h * h + k * k + l * l, nbins, U);
-                if (b >= 0) cnt[b] += 1;
+#pragma omp parallel
+    {
+        long long* mine = (long long*)calloc((size_t)nbins, sizeof(long long));
+#pragma omp for schedule(static)
+        for (long long u = 0; u < n; ++u) {
+            long long h = sgn_index(u, n);
+            for (long long v = 0; v < n; ++v) {
+                long long k = sgn_index(v, n);
+                for (long long w = 0; w < n; ++w) {
+                    long long l = sgn_index(w, n);
+                    int b = find_bin(h * h + k * k + l * l, nbins, U);
+                    if (b >= 0) mine[b] += 1;
+                }
             }
         }
+#pragma omp critical
+        for (int b = 0; b < nbins; ++b) cnt[b] += mine[b];
+        free(mine);
     }
     for (int b = 0; b < nbins; ++b) count[b] = (double)cnt[b];
     free(U); free(cnt);

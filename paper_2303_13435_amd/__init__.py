@@ -67,6 +67,9 @@ _SIGS = {
     "ur_graph_end": [_vp, _c.POINTER(_vp)],
     "ur_graph_launch": [_vp, _vp],
     "ur_graph_destroy": [_vp],
+    "ur_plan_set_timing": [_vp, _c.c_int32],
+    "ur_plan_read_timing": [_vp, _c.c_int32, _c.POINTER(_c.c_double), _c.POINTER(_c.c_double),
+                            _c.POINTER(_c.c_int32)],
     "ur_last_error": [],
     "ur_version": [],
 }
@@ -250,6 +253,21 @@ class Plan:
         base = int(self._ws.data_ptr())
         aligned = (base + 255) & ~255
         _check(lib().ur_plan_set_workspace(self.h, _vp(aligned), _c.c_size_t(nbytes)), "ur_plan_set_workspace")
+
+    # -- timing -------------------------------------------------------------
+    PASSES = ("cell", "pass_z", "pass_y", "pass_x", "finalize")
+
+    def set_timing(self, on: bool) -> None:
+        _check(lib().ur_plan_set_timing(self.h, 1 if on else 0), "ur_plan_set_timing")
+
+    def read_timing(self) -> dict:
+        """Per pass: summed ms, algorithmic bytes of one launch, launches."""
+        k = len(self.PASSES)
+        ms = (_c.c_double * k)()
+        by = (_c.c_double * k)()
+        nl = (_c.c_int32 * k)()
+        _check(lib().ur_plan_read_timing(self.h, k, ms, by, nl), "ur_plan_read_timing")
+        return {name: {"ms": ms[i], "bytes": by[i], "launches": nl[i]} for i, name in enumerate(self.PASSES)}
 
     # -- entry points -------------------------------------------------------
     def simulate(self, cell: DeviceCell, mask, zoom, hist: Hist, stream=None, amp=None) -> Hist:

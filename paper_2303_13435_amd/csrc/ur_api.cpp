@@ -63,8 +63,11 @@ struct ur_plan {
 
   void* tw = nullptr;        // n twiddles (device)
 
+  int ncu = 256;             // compute units of the device
   int nbins = 0;
   int* dU = nullptr;         // nbins + 1 thresholds (device)
+  double* dCount = nullptr;  // per-bin voxel counts (device), computed with the bins
+  unsigned long long* dCountTmp = nullptr;
   std::vector<long long> U;
 
   // workspace
@@ -81,10 +84,55 @@ struct ur_plan {
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   void* stage = nullptr;     // two pinned-side staging buffers on the device
   size_t stage_bytes = 0;
+
+  // per-pass timing
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_open;
+  double pass_bytes[5] = {0, 0, 0, 0, 0};
+  int xres[3][2] = {{0, 0}, {0, 0}, {0, 0}};   // resident x-pass blocks per CU, by mode and direction
+  int xres_nbins = -1;
 };
 
-static int x_blocks_for(int nbins) { return nbins > 1024 ? 512 : 1024; }
-static int x_blocks(const ur_plan* p) { return x_blocks_for(p->nbins); }
+enum { P_CELL = 0, P_Z = 1, P_Y = 2, P_X = 3, P_FIN = 4 };
+
+// event pair around one pass launch (no-op unless timing is on)
+struct PassTimer {
+  ur_plan* p;
+  int pass;
+  hipStream_t s;
+  hipEvent_t a = nullptr, b = nullptr;
+  PassTimer(ur_plan* p_, int pass_, hipStream_t s_) : p(p_), pass(pass_), s(s_) {
+    if (!p->timing) return;
+    a = take();
+    b = take();
+    if (a) (void)hipEventRecord(a, s);
+  }
+  hipEvent_t take() {
+    if (!p->ev_pool.empty()) { hipEvent_t e = p->ev_pool.back(); p->ev_pool.pop_back(); return e; }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+  ~PassTimer() {
+    if (!p->timing || !a || !b) return;
+    (void)hipEventRecord(b, s);
+    p->ev_open.push_back({pass, {a, b}});
+  }
+};
+
+// x pass: persistent blocks = resident blocks per CU x CUs (at most kMaxXBlocks)
+static const int kMaxXBlocks = 1024;
+static int x_blocks_for(int) { return kMaxXBlocks; }
+static int x_blocks(ur_plan* p, int mode = X_FFT_BIN, int dir = -1) {
+  if (p->xres_nbins != p->nbins) {
+    for (auto& m : p->xres) m[0] = m[1] = 0;
+    p->xres_nbins = p->nbins;
+  }
+  int& r = p->xres[mode][dir < 0 ? 0 : 1];
+  if (r == 0) r = x_resident(p->prec, p->n, mode, dir, std::max(p->nbins, 1));
+  return std::max(1, std::min(r * p->ncu, kMaxXBlocks));
+}
 
 // largest ZMode tile over the modes the plan can run
 static int zt(const ur_plan* p) { return z_tile(p->prec, p->n, p->flags & UR_C2C); }
@@ -101,7 +149,7 @@ static Layout layout_incore(const ur_plan* p, int nbins) {
   L.A = 0;
   L.B = align256(L.A + n * plane);
   L.part = align256(L.B + (size_t)p->nkz * n * n * p->cs);
-  L.mom = align256(L.part + (size_t)x_blocks_for(nbins) * (3 * (size_t)std::max(nbins, 1) + 1) * 8);
+  L.mom = align256(L.part + (size_t)x_blocks_for(nbins) * (2 * (size_t)std::max(nbins, 1) + 1) * 8);
   L.f0 = align256(L.mom + n * (size_t)ntiles(p) * 16);
   L.total = align256(L.f0 + 64);
   return L;
@@ -118,7 +166,7 @@ static Layout layout_host(const ur_plan* p, int nbins, int xlo, int xhi) {
   L.A = 0;
   L.B = align256(L.A + (size_t)tx * plane);
   L.part = align256(L.B + (size_t)p->nkz * n * bs * p->cs);
-  L.mom = align256(L.part + (size_t)x_blocks_for(nbins) * (3 * (size_t)std::max(nbins, 1) + 1) * 8);
+  L.mom = align256(L.part + (size_t)x_blocks_for(nbins) * (2 * (size_t)std::max(nbins, 1) + 1) * 8);
   L.f0 = align256(L.mom + n * (size_t)ntiles(p) * 16);
   L.total = align256(L.f0 + 64);
   return L;
@@ -155,28 +203,32 @@ static ur_status ensure_cell_scratch(ur_plan* p, size_t need, hipStream_t s) {
   return UR_OK;
 }
 
-// twiddles exp(-2 pi i k / n), evaluated in long double, rounded once
+// per-stage twiddle tables exp(-2 pi i r j / (L R)), evaluated in long double
+// and rounded once to the working precision
 static ur_status make_twiddles(ur_plan* p) {
   const long double PI = 3.14159265358979323846264338327950288L;
-  size_t n = p->n;
+  int Ls[32], Rs[32];
+  const int ns = fft_stages(p->n, Ls, Rs);
+  if (ns <= 0) return fail(UR_ERR_UNSUPPORTED, "no transform stages for n = %d", p->n);
+  std::vector<long double> re, im;
+  for (int k = 0; k < ns; ++k)
+    for (int j = 0; j < Ls[k]; ++j)
+      for (int r = 1; r < Rs[k]; ++r) {
+        long double a = 2.0L * PI * (long double)(r * j) / (long double)(Ls[k] * Rs[k]);
+        re.push_back(cosl(a));
+        im.push_back(-sinl(a));
+      }
+  const size_t m = re.size() ? re.size() : 1;
   if (p->prec == UR_F32) {
-    std::vector<float> h(2 * n);
-    for (size_t k = 0; k < n; ++k) {
-      long double a = 2.0L * PI * (long double)k / (long double)n;
-      h[2 * k] = (float)cosl(a);
-      h[2 * k + 1] = (float)(-sinl(a));
-    }
-    UR_HIP(hipMalloc(&p->tw, 2 * n * sizeof(float)));
-    UR_HIP(hipMemcpy(p->tw, h.data(), 2 * n * sizeof(float), hipMemcpyHostToDevice));
+    std::vector<float> h(2 * m, 0.f);
+    for (size_t i = 0; i < re.size(); ++i) { h[2 * i] = (float)re[i]; h[2 * i + 1] = (float)im[i]; }
+    UR_HIP(hipMalloc(&p->tw, 2 * m * sizeof(float)));
+    UR_HIP(hipMemcpy(p->tw, h.data(), 2 * m * sizeof(float), hipMemcpyHostToDevice));
   } else {
-    std::vector<double> h(2 * n);
-    for (size_t k = 0; k < n; ++k) {
-      long double a = 2.0L * PI * (long double)k / (long double)n;
-      h[2 * k] = (double)cosl(a);
-      h[2 * k + 1] = (double)(-sinl(a));
-    }
-    UR_HIP(hipMalloc(&p->tw, 2 * n * sizeof(double)));
-    UR_HIP(hipMemcpy(p->tw, h.data(), 2 * n * sizeof(double), hipMemcpyHostToDevice));
+    std::vector<double> h(2 * m, 0.0);
+    for (size_t i = 0; i < re.size(); ++i) { h[2 * i] = (double)re[i]; h[2 * i + 1] = (double)im[i]; }
+    UR_HIP(hipMalloc(&p->tw, 2 * m * sizeof(double)));
+    UR_HIP(hipMemcpy(p->tw, h.data(), 2 * m * sizeof(double), hipMemcpyHostToDevice));
   }
   return UR_OK;
 }
@@ -227,6 +279,7 @@ ur_status ur_plan_create(int32_t n, double voxel, int32_t prec, uint32_t flags, 
   p->rs = prec == UR_F32 ? 4 : 8;
   p->cs = 2 * p->rs;
   if (hipGetDevice(&p->device) != hipSuccess) { delete p; return fail(UR_ERR_HIP, "hipGetDevice failed"); }
+  if (hipDeviceGetAttribute(&p->ncu, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess || p->ncu < 1) p->ncu = 256;
   ur_status st = make_twiddles(p);
   if (st != UR_OK) { ur_plan_destroy(p); return st; }
   *out = p;
@@ -238,11 +291,15 @@ void ur_plan_destroy(ur_plan* p) {
   (void)hipDeviceSynchronize();
   if (p->tw) (void)hipFree(p->tw);
   if (p->dU) (void)hipFree(p->dU);
+  if (p->dCount) (void)hipFree(p->dCount);
+  if (p->dCountTmp) (void)hipFree(p->dCountTmp);
   if (p->ws && p->ws_owned) (void)hipFree(p->ws);
   if (p->cs_buf) (void)hipFree(p->cs_buf);
   if (p->stage) (void)hipFree(p->stage);
   for (auto& e : p->ev) if (e) (void)hipEventDestroy(e);
   if (p->copy_stream) (void)hipStreamDestroy(p->copy_stream);
+  for (auto& e : p->ev_open) { (void)hipEventDestroy(e.second.first); (void)hipEventDestroy(e.second.second); }
+  for (auto& e : p->ev_pool) (void)hipEventDestroy(e);
   delete p;
 }
 
@@ -271,6 +328,28 @@ ur_status ur_plan_set_workspace(ur_plan* p, void* dev_ptr, size_t bytes) {
   return UR_OK;
 }
 
+ur_status ur_plan_set_timing(ur_plan* p, int32_t enable) {
+  if (!p) return fail(UR_ERR_INVALID, "plan is null");
+  p->timing = enable != 0;
+  return UR_OK;
+}
+
+ur_status ur_plan_read_timing(ur_plan* p, int32_t npass, double* ms, double* bytes, int32_t* launches) {
+  if (!p || !ms || !bytes || !launches) return fail(UR_ERR_INVALID, "null argument");
+  if (npass < 1 || npass > 5) return fail(UR_ERR_INVALID, "npass must be in [1, 5]");
+  for (int i = 0; i < npass; ++i) { ms[i] = 0.0; bytes[i] = p->pass_bytes[i]; launches[i] = 0; }
+  for (auto& e : p->ev_open) {
+    UR_HIP(hipEventSynchronize(e.second.second));
+    float t = 0.f;
+    UR_HIP(hipEventElapsedTime(&t, e.second.first, e.second.second));
+    if (e.first < npass) { ms[e.first] += t; launches[e.first] += 1; }
+    p->ev_pool.push_back(e.second.first);
+    p->ev_pool.push_back(e.second.second);
+  }
+  p->ev_open.clear();
+  return UR_OK;
+}
+
 ur_status ur_plan_set_bins(ur_plan* p, int32_t nbins, const double* edges) {
   if (!p || !edges) return fail(UR_ERR_INVALID, "null argument");
   if (nbins < 1 || nbins > 4096) return fail(UR_ERR_INVALID, "nbins = %d outside [1, 4096]", nbins);
@@ -282,9 +361,20 @@ ur_status ur_plan_set_bins(ur_plan* p, int32_t nbins, const double* edges) {
   long long n2max = 3ll * (p->n / 2) * (p->n / 2);
   std::vector<int> Ui(nbins + 1);
   for (int b = 0; b <= nbins; ++b) Ui[b] = (int)std::min<long long>(U[b], n2max + 1);
-  if (p->dU && p->nbins < nbins) { UR_HIP(hipFree(p->dU)); p->dU = nullptr; }
-  if (!p->dU) UR_HIP(hipMalloc(&p->dU, (nbins + 1) * sizeof(int)));
+  if (p->dU && p->nbins < nbins) {
+    UR_HIP(hipFree(p->dU)); p->dU = nullptr;
+    UR_HIP(hipFree(p->dCount)); p->dCount = nullptr;
+    UR_HIP(hipFree(p->dCountTmp)); p->dCountTmp = nullptr;
+  }
+  if (!p->dU) {
+    UR_HIP(hipMalloc(&p->dU, (nbins + 1) * sizeof(int)));
+    UR_HIP(hipMalloc(&p->dCount, nbins * sizeof(double)));
+    UR_HIP(hipMalloc(&p->dCountTmp, nbins * sizeof(unsigned long long)));
+  }
   UR_HIP(hipMemcpy(p->dU, Ui.data(), (nbins + 1) * sizeof(int), hipMemcpyHostToDevice));
+  // voxel counts per bin: pure geometry of the box and the thresholds
+  UR_HIP(launch_bin_counts(p->n, p->nkz, !(p->flags & UR_C2C), nbins, p->dU, p->dCountTmp, p->dCount, nullptr));
+  UR_HIP(hipDeviceSynchronize());
   p->nbins = nbins;
   p->U = U;
   return UR_OK;
@@ -375,9 +465,24 @@ struct FwdGeom {
   MaskP m;
 };
 
+// rows of the first intermediate that hold data, summed over planes
+static double live_rows(const ur_plan* p, const FwdGeom& g) {
+  if (g.xlo > g.xhi) return 0.0;
+  if (!g.gen) return (double)(g.xhi - g.xlo + 1) * p->n;
+  const int ty = zt(p);
+  double rows = 0.0;
+  for (long long x = g.xlo; x <= g.xhi; ++x) {
+    long long lo, hi;
+    row_range(g.L, g.m, x, lo, hi);
+    if (lo <= hi) rows += (double)((hi / ty - lo / ty + 1) * ty);
+  }
+  return rows;
+}
+
 static ur_status run_y_x(ur_plan* p, const FwdGeom& g, char* A, char* B, const Layout& lay,
                          const ur_hist* h, int nzb, hipStream_t s) {
   const int n = p->n, tx = y_tile(p->prec, n);
+  const double rows = live_rows(p, g);
   long long xt0 = 0, xt1 = -1, bx0 = 0, bs = tx;
   if (g.xlo <= g.xhi) {
     xt0 = g.xlo / tx;
@@ -388,8 +493,15 @@ static ur_status run_y_x(ur_plan* p, const FwdGeom& g, char* A, char* B, const L
     ya.A = A; ya.ax0 = g.ax0; ya.B = B; ya.bx0 = bx0; ya.bs = bs; ya.tw = p->tw;
     ya.L = g.L; ya.m = g.m; ya.gen = g.gen; ya.nkz = p->nkz; ya.xlo = g.xlo; ya.xhi = g.xhi;
     ya.xt0 = (int)xt0; ya.nxt = (int)(xt1 - xt0 + 1); ya.ty = zt(p);
+    PassTimer tm(p, P_Y, s);
     UR_HIP(launch_pass_y(p->prec, n, ya, s));
   }
+  const double spec_x = (double)p->nkz * n * (double)bs * p->cs;      // B over the live x range
+  const int nxb = x_blocks(p);
+  const double part_bytes = (double)nxb * (2.0 * p->nbins + 1.0) * 8.0;
+  p->pass_bytes[P_Y] = g.xlo <= g.xhi ? rows * p->nkz * p->cs + spec_x : 0.0;
+  p->pass_bytes[P_X] = (g.xlo <= g.xhi ? spec_x : 0.0) + part_bytes;
+  p->pass_bytes[P_FIN] = part_bytes + 16.0 * nzb + 24.0 * p->nbins;
   XArgs xa{};
   xa.B = B; xa.bx0 = bx0; xa.bs = bs; xa.out = nullptr; xa.tw = p->tw;
   xa.nkz = p->nkz; xa.r2c = !(p->flags & UR_C2C);
@@ -398,13 +510,18 @@ static ur_status run_y_x(ur_plan* p, const FwdGeom& g, char* A, char* B, const L
   xa.oscale = 1.0; xa.nbins = p->nbins; xa.U = p->dU;
   xa.part = (double*)(p->ws + lay.part); xa.f0 = (double*)(p->ws + lay.f0);
   xa.ncols = p->nkz * n;
-  const int nxb = x_blocks(p);
-  UR_HIP(launch_pass_x(p->prec, n, X_FFT_BIN, -1, xa, nxb, s));
+  {
+    PassTimer tm(p, P_X, s);
+    UR_HIP(launch_pass_x(p->prec, n, X_FFT_BIN, -1, xa, nxb, s));
+  }
   FinArgs fa{};
   fa.part = xa.part; fa.nblk = nxb; fa.nbins = p->nbins;
   fa.mom = nzb > 0 ? (const double*)(p->ws + lay.mom) : nullptr; fa.nzb = nzb;
-  fa.f0 = xa.f0; fa.sum = h->sum; fa.sumsq = h->sumsq; fa.count = h->count; fa.totals = h->totals;
-  UR_HIP(launch_finalize(fa, s));
+  fa.f0 = xa.f0; fa.cnt = p->dCount; fa.sum = h->sum; fa.sumsq = h->sumsq; fa.count = h->count; fa.totals = h->totals;
+  {
+    PassTimer tm(p, P_FIN, s);
+    UR_HIP(launch_finalize(fa, s));
+  }
   return UR_OK;
 }
 
@@ -448,7 +565,14 @@ ur_status ur_simulate(ur_plan* p, const ur_cell* cell, const ur_mask* mask, cons
   Layout lay = layout_incore(p, p->nbins);
   UR_TRY(ensure_ws(p, lay.total, s));
   CellTables t;
-  UR_TRY(prepare_cell(p, cell, zoom->factor, t, s));
+  {
+    PassTimer tm(p, P_CELL, s);
+    UR_TRY(prepare_cell(p, cell, zoom->factor, t, s));
+  }
+  {
+    const double c = cell->c;
+    p->pass_bytes[P_CELL] = 8.0 * (3.0 * c * cell->n_atoms) * 2.0 + c * c * c * (16.0 + p->rs);
+  }
 
   long long xlo, xhi;
   plane_range(g.L, g.m, xlo, xhi);
@@ -462,8 +586,11 @@ ur_status ur_simulate(ur_plan* p, const ur_cell* cell, const ur_mask* mask, cons
     za.mom = (double*)(p->ws + lay.mom); za.L = g.L; za.m = g.m; za.nkz = p->nkz; za.x0 = (int)xlo;
     za.ntiles = ntiles(p); za.cbn = t.cbn;
     nzb = (int)((xhi - xlo + 1) * za.ntiles);
-    UR_HIP(launch_pass_z(p->prec, p->n, (p->flags & UR_C2C) ? Z_GEN_C2C : Z_GEN_R2C, za, nzb, s));
+    PassTimer tm(p, P_Z, s);
+    const int zm = zoom->factor > 1 ? ((p->flags & UR_C2C) ? Z_ZOOM_C2C : Z_ZOOM_R2C) : ((p->flags & UR_C2C) ? Z_GEN_C2C : Z_GEN_R2C);
+    UR_HIP(launch_pass_z(p->prec, p->n, zm, za, nzb, s));
   }
+  p->pass_bytes[P_Z] = live_rows(p, g) * p->nkz * p->cs + 16.0 * nzb;
   return run_y_x(p, g, p->ws + lay.A, p->ws + lay.B, lay, h, nzb, s);
 }
 
@@ -481,7 +608,13 @@ ur_status ur_simulate_rho(ur_plan* p, const void* rho, const ur_hist* h, void* s
   za.A = p->ws + lay.A; za.ax0 = 0; za.rho = rho; za.rho_x0 = 0; za.tw = p->tw;
   za.mom = (double*)(p->ws + lay.mom); za.L = g.L; za.nkz = p->nkz; za.x0 = 0; za.ntiles = ntiles(p);
   int nzb = p->n * za.ntiles;
-  UR_HIP(launch_pass_z(p->prec, p->n, (p->flags & UR_C2C) ? Z_LOAD_C2C : Z_LOAD_R2C, za, nzb, s));
+  {
+    PassTimer tm(p, P_Z, s);
+    UR_HIP(launch_pass_z(p->prec, p->n, (p->flags & UR_C2C) ? Z_LOAD_C2C : Z_LOAD_R2C, za, nzb, s));
+  }
+  p->pass_bytes[P_CELL] = 0.0;
+  p->pass_bytes[P_Z] = (double)p->n * p->n * p->n * ((p->flags & UR_C2C) ? p->cs : p->rs) +
+                       (double)p->n * p->nkz * p->n * p->cs + 16.0 * nzb;
   return run_y_x(p, g, p->ws + lay.A, p->ws + lay.B, lay, h, nzb, s);
 }
 
@@ -508,12 +641,12 @@ ur_status ur_fft3d_exec(ur_plan* p, const void* in, void* out, int32_t dir, void
     XArgs xa{};
     xa.B = B; xa.bx0 = 0; xa.bs = n; xa.out = out; xa.tw = p->tw; xa.nkz = p->nkz; xa.r2c = !c2c;
     xa.xa = 0; xa.xb = n - 1; xa.oscale = 1.0 / ((double)n * n * n); xa.ncols = p->nkz * n;
-    UR_HIP(launch_pass_x(p->prec, n, X_FFT_STORE, -1, xa, x_blocks(p), s));
+    UR_HIP(launch_pass_x(p->prec, n, X_FFT_STORE, -1, xa, x_blocks(p, X_FFT_STORE, -1), s));
   } else {
     XArgs xa{};
     xa.B = in; xa.bx0 = 0; xa.bs = n; xa.out = B; xa.tw = p->tw; xa.nkz = p->nkz; xa.r2c = !c2c;
     xa.xa = 0; xa.xb = n - 1; xa.oscale = 1.0; xa.ncols = p->nkz * n;
-    UR_HIP(launch_pass_x(p->prec, n, X_FFT_STORE, +1, xa, x_blocks(p), s));
+    UR_HIP(launch_pass_x(p->prec, n, X_FFT_STORE, +1, xa, x_blocks(p, X_FFT_STORE, +1), s));
     YInvArgs yi{};
     yi.B = B; yi.A = A; yi.tw = p->tw; yi.nkz = p->nkz; yi.xt0 = 0; yi.nxt = n / tx;
     UR_HIP(launch_pass_y_inv(p->prec, n, yi, s));
@@ -536,10 +669,11 @@ ur_status ur_intensity_bin(ur_plan* p, const void* spectrum, const ur_hist* h, v
   xa.B = spectrum; xa.bx0 = 0; xa.bs = n; xa.tw = p->tw; xa.nkz = p->nkz; xa.r2c = !(p->flags & UR_C2C);
   xa.xa = 0; xa.xb = n - 1; xa.iscale = 1.0; xa.nbins = p->nbins; xa.U = p->dU;
   xa.part = (double*)(p->ws + lay.part); xa.f0 = (double*)(p->ws + lay.f0); xa.ncols = p->nkz * n;
-  UR_HIP(launch_pass_x(p->prec, n, X_BIN_ONLY, -1, xa, x_blocks(p), s));
+  const int nxb = x_blocks(p, X_BIN_ONLY);
+  UR_HIP(launch_pass_x(p->prec, n, X_BIN_ONLY, -1, xa, nxb, s));
   FinArgs fa{};
-  fa.part = xa.part; fa.nblk = x_blocks(p); fa.nbins = p->nbins; fa.mom = nullptr; fa.nzb = 0;
-  fa.f0 = xa.f0; fa.sum = h->sum; fa.sumsq = h->sumsq; fa.count = h->count; fa.totals = h->totals;
+  fa.part = xa.part; fa.nblk = nxb; fa.nbins = p->nbins; fa.mom = nullptr; fa.nzb = 0;
+  fa.f0 = xa.f0; fa.cnt = p->dCount; fa.sum = h->sum; fa.sumsq = h->sumsq; fa.count = h->count; fa.totals = h->totals;
   UR_HIP(launch_finalize(fa, s));
   return UR_OK;
 }
@@ -618,7 +752,7 @@ ur_status ur_simulate_host(ur_plan* p, const void* rho_host, int32_t x_lo, int32
   UR_HIP(launch_pass_x(p->prec, n, X_FFT_BIN, -1, xa, x_blocks(p), s));
   FinArgs fa{};
   fa.part = xa.part; fa.nblk = x_blocks(p); fa.nbins = p->nbins; fa.mom = (const double*)(p->ws + lay.mom); fa.nzb = zb;
-  fa.f0 = xa.f0; fa.sum = h->sum; fa.sumsq = h->sumsq; fa.count = h->count; fa.totals = h->totals;
+  fa.f0 = xa.f0; fa.cnt = p->dCount; fa.sum = h->sum; fa.sumsq = h->sumsq; fa.count = h->count; fa.totals = h->totals;
   UR_HIP(launch_finalize(fa, s));
   return UR_OK;
 }

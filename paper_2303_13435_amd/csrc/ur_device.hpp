@@ -86,41 +86,66 @@ template <int N> struct Geo {
 
 // radix of the stage with sub-transform length L: at most 16 and at most the
 // per-lane element count, so each lane runs whole butterflies
-template <int N, int L> struct Radix {
-  static constexpr int cap = Geo<N>::E < 16 ? Geo<N>::E : 16;
-  static constexpr int r = (N / L) < cap ? (N / L) : cap;
-};
+template <int N> constexpr int radix_at(int L) {
+  constexpr int cap = Geo<N>::E < 16 ? Geo<N>::E : 16;
+  return (N / L) < cap ? (N / L) : cap;
+}
+template <int N, int L> struct Radix { static constexpr int r = radix_at<N>(L); };
+
+// Twiddle tables: stage (L, R) owns L*(R-1) entries exp(-2 pi i r j/(L R)),
+// laid out [j][r-1], after the tables of the earlier stages.
+template <int N> constexpr int tw_off(int L) {
+  int off = 0, l = 1;
+  while (l < L) { const int r = radix_at<N>(l); off += l * (r - 1); l *= r; }
+  return off;
+}
+
+// Padded offset of a compile-time displacement k from a padded base whose
+// low four index bits plus those of k stay below 16 (true for every access
+// pattern below: the displacements are multiples of 16, or the base is
+// aligned to the span of the displacements).
+template <int K> struct PadOff { static constexpr int v = K + (K >> 4); };
 
 // One Stockham radix-R stage with sub-transform length L (inputs read from
 // the LDS column s, outputs written back to s, in place through registers).
-// Lane g of the group performs butterflies b = g + G*i, i < E/R.
+// Lane g of the group performs butterflies b = g + G*i, i < E/R: inputs
+// x[b + r N/R], twiddles exp(DIR 2 pi i r j/(L R)) with j = b mod L, outputs
+// y[(b/L) L R + j + r L].  Every LDS address is one padded base per
+// butterfly plus a compile-time offset.
 template <typename T, int N, int L, int DIR>
 __device__ __forceinline__ void stage_lds(cx<T>* s, int g, const cx<T>* __restrict__ tw) {
   constexpr int E = Geo<N>::E, G = Geo<N>::G, R = Radix<N, L>::r, NB = E / R;
+  constexpr int NR = N / R;
   static_assert(NB * R == E, "radix must divide the per-lane count");
   cx<T> v[NB][R];
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
-    int b = g + G * i;
+    if constexpr (NR % 16 == 0) {                        // displacements are multiples of 16
+      const cx<T>* base = s + pad(g + G * i);
 #pragma unroll
-    for (int r = 0; r < R; ++r) v[i][r] = s[pad(b + r * (N / R))];
+      for (int r = 0; r < R; ++r) v[i][r] = base[r * (NR + NR / 16)];
+    } else {
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[i][r] = s[pad(g + G * i + r * NR)];
+    }
   }
   wave_sync();
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
-    int b = g + G * i;
-    int j = b % L;
+    const int b = g + G * i;
+    const int j = b % L;
     if (L > 1) {
+      const cx<T>* wp = tw + (tw_off<N>(L) + j * (R - 1));
 #pragma unroll
       for (int r = 1; r < R; ++r) {
-        cx<T> w = tw[(r * j) * (N / (L * R))];     // exp(-2 pi i r j / (L R))
+        const cx<T> w = wp[r - 1];                 // exp(-2 pi i r j / (L R))
         v[i][r] = DIR < 0 ? cmul(v[i][r], w) : cmulc(v[i][r], w);
       }
     }
     DFT<T, R, DIR>::run(v[i]);
-    int o = (b / L) * L * R + j;
+    cx<T>* out = s + pad((b / L) * L * R + j);
 #pragma unroll
-    for (int r = 0; r < R; ++r) s[pad(o + r * L)] = v[i][r];
+    for (int r = 0; r < R; ++r) out[(r * L) + ((r * L) >> 4)] = v[i][r];
   }
   wave_sync();
 }
@@ -142,10 +167,11 @@ __device__ __forceinline__ void fft_column(cx<T>* s, int g, const cx<T>* __restr
   constexpr int E = Geo<N>::E, G = Geo<N>::G, R = Radix<N, 1>::r, NB = E / R;
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
-    int b = g + G * i;
+    const int b = g + G * i;
     DFT<T, R, DIR>::run(v + i * R);
+    cx<T>* out = s + pad(b * R);                       // R | 16: the R outputs share one 16-block
 #pragma unroll
-    for (int r = 0; r < R; ++r) s[pad(b * R + r)] = v[i * R + r];
+    for (int r = 0; r < R; ++r) out[r] = v[i * R + r];
   }
   wave_sync();
   stages_from<T, N, R, DIR>(s, g, tw);

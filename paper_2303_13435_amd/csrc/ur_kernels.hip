@@ -34,10 +34,17 @@ template <typename T, int N, bool C2C> struct ZCfg {
   static constexpr int TY = C2C ? NG : 2 * NG;
   static constexpr int threads = NG * G;
 };
-// y pass: x planes per block
+// y pass: x planes per block (two per group)
 template <typename T, int N> struct YCfg {
   static constexpr int G = Geo<N>::G;
   static constexpr int TX = Seg<T>::cols < N ? Seg<T>::cols : N;
+  static constexpr int NS = TX / 2;
+  static constexpr int threads = NS * G;
+};
+// inverse y pass: every plane of the tile has its own LDS column
+template <typename T, int N> struct YICfg {
+  static constexpr int G = Geo<N>::G;
+  static constexpr int TX = YCfg<T, N>::TX;
   static constexpr int threads = TX * G;
 };
 // x pass: columns per block
@@ -46,7 +53,15 @@ template <int N> struct XCfg {
   static constexpr int NG = 256 / G > 0 ? (256 / G < 64 ? 256 / G : 64) : 1;
   static constexpr int threads = NG * G;
 };
-template <int N> struct CS { static constexpr int v = Padded<N>::size + 1; };   // column stride in LDS
+// LDS column stride: a multiple of 32 elements plus 4, so that reading the
+// same few consecutive rows from 8 neighbouring columns (the transposed
+// write-outs) touches 32 distinct 8-byte bank pairs
+template <int N> struct CS {
+  static constexpr int v = ((Padded<N>::size + 31) / 32) * 32 + 4;
+};
+// minimum resident waves per SIMD the streaming passes are compiled for
+// (caps VGPRs at 128 for FP32 and 256 for FP64)
+template <typename T> struct MinW { static constexpr int v = sizeof(T) == 4 ? 4 : 2; };
 
 // ---------------------------------------------------------------------------
 // reductions
@@ -135,24 +150,27 @@ __device__ __forceinline__ int pmodi(long long a, int m) { long long r = a % m; 
 
 template <typename T>
 struct Pencil {
-  long long zlo, zhi;       // coarse z range that can hold density
-  // f == 1
-  const T* row;             // cell row of this pencil (c values)
-  int zres0;                // residue offset: cell index of z is (z - o - h) mod c
+  int zlo, zhi;             // coarse z range that can hold density (zlo > zhi: empty)
+  // f == 1: value(z) = row[(z + zoff) & cmask] inside [zlo, zhi]
+  const T* row;
+  int zoff, cmask;
   // f > 1
   long long rin;            // blocks with max|dz| <= rin are fully inside
   int I, J;                 // block-table indices of this pencil
   long long fx0, fy0;       // first fine x, y of the pencil's block column
-  bool live;
 
   __device__ __forceinline__ void init(const ZArgs& a, long long X, long long Y) {
     const Level& L = a.L;
-    col_range(L, a.m, X, Y, zlo, zhi);
-    live = zlo <= zhi;
-    if (!live) return;
+    long long lo, hi;
+    col_range(L, a.m, X, Y, lo, hi);
+    zlo = (int)lo;
+    zhi = (int)hi;
+    if (lo > hi) { zlo = 1; zhi = 0; }
+    cmask = L.c - 1;                                   // c is a power of two
     if (L.f == 1) {
-      int i = pmodi(X - L.o - L.h, L.c), j = pmodi(Y - L.o - L.h, L.c);
+      const int i = (int)(X - L.o - L.h) & cmask, j = (int)(Y - L.o - L.h) & cmask;
       row = (const T*)a.cellT + ((size_t)i * L.c + j) * L.c;
+      zoff = -(L.o + L.h);
     } else {
       long long ax, bx, ay, by;
       block_dist(L, X, ax, bx);
@@ -167,6 +185,11 @@ struct Pencil {
         I = J = 0;
       }
     }
+  }
+
+  // ED-1 voxel (factor 1): tiled cell inside the mask, exact integer test
+  __device__ __forceinline__ T value1(int z) const {
+    return (z >= zlo && z <= zhi) ? row[(z + zoff) & cmask] : (T)0;
   }
 
   // sum of the periodic cell row (i, j) over fine z in [za, zb]
@@ -184,13 +207,9 @@ struct Pencil {
     return s;
   }
 
-  __device__ __forceinline__ T value(const ZArgs& a, long long X, long long Y, long long Z) const {
-    if (!live || Z < zlo || Z > zhi) return (T)0;
-    if (a.L.f == 1) return row[pmodi(Z - a.L.o - a.L.h, a.L.c)];
-    return value_zoom(a, Z);
-  }
-
+  // zoomed level (factor f > 1): block sum of ED-1 over the f^3 fine voxels
   __device__ __noinline__ T value_zoom(const ZArgs& a, long long Z) const {
+    if (Z < zlo || Z > zhi) return (T)0;
     const Level& L = a.L;
     long long cz, dz;
     block_dist(L, Z, cz, dz);
@@ -216,16 +235,21 @@ struct Pencil {
     }
     return (T)s;
   }
+
+  __device__ __forceinline__ T value(const ZArgs& a, long long Z) const {
+    return a.L.f == 1 ? value1((int)Z) : value_zoom(a, Z);
+  }
 };
 
 // ---------------------------------------------------------------------------
 // pass Z: density -> 1D transform along z -> A[x][kz][y]
 // ---------------------------------------------------------------------------
 template <typename T, int N, int MODE>
-__global__ void __launch_bounds__((ZCfg<T, N, (MODE >= 2)>::threads))
+__global__ void __launch_bounds__((ZCfg<T, N, (MODE == Z_GEN_C2C || MODE == Z_LOAD_C2C || MODE == Z_ZOOM_C2C)>::threads), MinW<T>::v)
 k_pass_z(ZArgs a) {
-  constexpr bool C2C = MODE >= 2;
-  constexpr bool GEN = MODE == Z_GEN_R2C || MODE == Z_GEN_C2C;
+  constexpr bool C2C = MODE == Z_GEN_C2C || MODE == Z_LOAD_C2C || MODE == Z_ZOOM_C2C;
+  constexpr bool ZOOM = MODE == Z_ZOOM_R2C || MODE == Z_ZOOM_C2C;
+  constexpr bool GEN = MODE == Z_GEN_R2C || MODE == Z_GEN_C2C || ZOOM;
   using C = ZCfg<T, N, C2C>;
   constexpr int G = C::G, NG = C::NG, TY = C::TY, E = Geo<N>::E;
   constexpr int R0 = Radix<N, 1>::r, NB0 = E / R0, PS = CS<N>::v;
@@ -257,16 +281,28 @@ k_pass_z(ZArgs a) {
       Pencil<T> pa, pb;
       pa.init(a, X, yA);
       pb.init(a, X, yB);
+      if (!ZOOM) {
 #pragma unroll
-      for (int i = 0; i < NB0; ++i)
+        for (int i = 0; i < NB0; ++i)
 #pragma unroll
-        for (int r = 0; r < R0; ++r) {
-          long long z = first_index<N>(g, i, r);
-          T ra = pa.value(a, X, yA, z), rb = pb.value(a, X, yB, z);
-          v[i * R0 + r] = mk(ra, rb);
-          m1 += (double)ra + (double)rb;
-          m2 += (double)ra * ra + (double)rb * rb;
-        }
+          for (int r = 0; r < R0; ++r) {
+            const int z = first_index<N>(g, i, r);
+            v[i * R0 + r] = mk(pa.value1(z), pb.value1(z));
+          }
+      } else {
+#pragma unroll
+        for (int i = 0; i < NB0; ++i)
+#pragma unroll
+          for (int r = 0; r < R0; ++r) {
+            const int z = first_index<N>(g, i, r);
+            v[i * R0 + r] = mk(pa.value_zoom(a, z), pb.value_zoom(a, z));
+          }
+      }
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        m1 += (double)v[e].x + (double)v[e].y;
+        m2 += (double)v[e].x * v[e].x + (double)v[e].y * v[e].y;
+      }
     } else {
       const T* rho = (const T*)a.rho + ((size_t)(X - a.rho_x0) * N) * N;
 #pragma unroll
@@ -289,8 +325,8 @@ k_pass_z(ZArgs a) {
       for (int i = 0; i < NB0; ++i)
 #pragma unroll
         for (int r = 0; r < R0; ++r) {
-          long long z = first_index<N>(g, i, r);
-          T ra = p.value(a, X, y, z);
+          const int z = first_index<N>(g, i, r);
+          const T ra = ZOOM ? p.value_zoom(a, z) : p.value1(z);
           v[i * R0 + r] = mk(ra, (T)0);
           m1 += (double)ra;
           m2 += (double)ra * ra;
@@ -356,54 +392,78 @@ __global__ void __launch_bounds__(256) k_rho_generate(ZArgs a, int n, T* __restr
   Pencil<T> p;
   p.init(a, X, Y);
   T* row = rho + t * n;
-  for (long long z = threadIdx.x; z < n; z += 256) row[z] = p.value(a, X, Y, z);
+  for (int z = threadIdx.x; z < n; z += 256) row[z] = p.value(a, z);
 }
 
 // ---------------------------------------------------------------------------
 // pass Y: A[x][kz][y] columns -> transform along y -> B[kz][ky][x]
+// Each group transforms two x planes of the block's TX-plane tile one after
+// the other (results of the first kept in registers), so only TX/2 LDS
+// columns are needed and two blocks fit a CU; the transposed write leaves in
+// chunks of G rows, every row a TX-element (128-byte) segment.
 // ---------------------------------------------------------------------------
 template <typename T, int N>
-__global__ void __launch_bounds__((YCfg<T, N>::threads))
-k_pass_y(YArgs a) {
-  using C = YCfg<T, N>;
-  constexpr int G = C::G, TX = C::TX, E = Geo<N>::E;
-  constexpr int R0 = Radix<N, 1>::r, NB0 = E / R0, PS = CS<N>::v;
-  __shared__ cx<T> sm[TX * PS];
-
-  const int kz = blockIdx.x % a.nkz;
-  const int xt = a.xt0 + blockIdx.x / a.nkz;
-  const int xbase = xt * TX;
-  const int q = threadIdx.x / G, g = threadIdx.x % G;
-  const long long X = xbase + q;
-  const cx<T>* tw = (const cx<T>*)a.tw;
-  cx<T>* s = sm + q * PS;
-
+__device__ __forceinline__ void y_load_column(const YArgs& a, long long X, int kz, int g, cx<T>* v) {
+  constexpr int G = Geo<N>::G, E = Geo<N>::E, R0 = Radix<N, 1>::r, NB0 = E / R0;
   long long ylo = 0, yhi = N - 1;
   if (X < a.xlo || X > a.xhi) { ylo = 1; yhi = 0; }
   else if (a.gen) {
     row_range(a.L, a.m, X, ylo, yhi);
     if (ylo <= yhi) { ylo = (ylo / a.ty) * a.ty; yhi = (yhi / a.ty) * a.ty + a.ty - 1; }
   }
-  if (ylo > yhi) {
-    for (int i = g; i < N; i += G) s[pad(i)] = mk((T)0, (T)0);
-    wave_sync();
-  } else {
-    const cx<T>* col = (const cx<T>*)a.A + ((size_t)(X - a.ax0) * a.nkz + kz) * N;
+  const cx<T>* col = (const cx<T>*)a.A + ((size_t)(X - a.ax0) * a.nkz + kz) * N;
+#pragma unroll
+  for (int i = 0; i < NB0; ++i)
+#pragma unroll
+    for (int r = 0; r < R0; ++r) {
+      const int y = first_index<N>(g, i, r);
+      v[i * R0 + r] = (y >= ylo && y <= yhi) ? col[y] : mk((T)0, (T)0);
+    }
+}
+
+template <typename T, int N>
+__global__ void __launch_bounds__((YCfg<T, N>::threads), MinW<T>::v)
+k_pass_y(YArgs a) {
+  using C = YCfg<T, N>;
+  constexpr int G = C::G, TX = C::TX, NS = C::NS, E = Geo<N>::E, PS = CS<N>::v;
+  constexpr int SS = NS + 1;                               // staging row stride
+  __shared__ cx<T> sm[NS * PS + G * SS];
+  cx<T>* stg = sm + NS * PS;
+
+  const int kz = blockIdx.x % a.nkz;
+  const int xt = a.xt0 + blockIdx.x / a.nkz;
+  const int xbase = xt * TX;
+  const int q = threadIdx.x / G, g = threadIdx.x % G;
+  const cx<T>* tw = (const cx<T>*)a.tw;
+  cx<T>* s = sm + q * PS;
+  cx<T> keep[E];
+  {
     cx<T> v[E];
+    y_load_column<T, N>(a, xbase + q, kz, g, v);
+    fft_column<T, N, -1>(s, g, tw, v);
+    if constexpr (G % 16 == 0) {
+      const cx<T>* kp = s + pad(g);
 #pragma unroll
-    for (int i = 0; i < NB0; ++i)
+      for (int t = 0; t < E; ++t) keep[t] = kp[t * (G + G / 16)];   // rows g + G t
+    } else {
 #pragma unroll
-      for (int r = 0; r < R0; ++r) {
-        int y = first_index<N>(g, i, r);
-        v[i * R0 + r] = (y >= ylo && y <= yhi) ? col[y] : mk((T)0, (T)0);
-      }
+      for (int t = 0; t < E; ++t) keep[t] = s[pad(g + G * t)];
+    }
+    wave_sync();
+    y_load_column<T, N>(a, xbase + NS + q, kz, g, v);
     fft_column<T, N, -1>(s, g, tw, v);
   }
   __syncthreads();
   cx<T>* Bp = (cx<T>*)a.B + ((size_t)kz * N) * a.bs + (xbase - a.bx0);
-  for (int idx = threadIdx.x; idx < TX * N; idx += C::threads) {
-    const int j = idx % TX, ky = idx / TX;
-    Bp[(size_t)ky * a.bs + j] = sm[j * PS + pad(ky)];
+#pragma unroll
+  for (int t = 0; t < E; ++t) {
+    stg[g * SS + q] = keep[t];                             // row ky = g + G t, plane q
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < G * TX; idx += C::threads) {
+      const int j = idx % TX, r = idx / TX, ky = G * t + r;
+      Bp[(size_t)ky * a.bs + j] = j < NS ? stg[r * SS + j] : sm[(j - NS) * PS + pad(ky)];
+    }
+    __syncthreads();
   }
 }
 
@@ -428,18 +488,35 @@ __device__ __forceinline__ int bin_advance(const int* U, int nbins, int b, long 
 
 // ---------------------------------------------------------------------------
 // pass X: B columns -> transform along x -> |F|^2 -> bins (or store)
+// Persistent blocks sized to the resident count; after each column FFT a
+// group issues the loads of its next column, which stay in flight while it
+// bins the current one.  The LDS
+// histogram holds sum w I and sum w I^2 per bin (the voxel counts are pure
+// geometry, computed once per bin set).
 // ---------------------------------------------------------------------------
+template <typename T, int N>
+__device__ __forceinline__ void x_load_column(const XArgs& a, long long col, int g, cx<T>* v) {
+  constexpr int E = Geo<N>::E, R0 = Radix<N, 1>::r, NB0 = E / R0;
+  const cx<T>* src = (const cx<T>*)a.B + (size_t)col * a.bs - a.bx0;
+#pragma unroll
+  for (int i = 0; i < NB0; ++i)
+#pragma unroll
+    for (int r = 0; r < R0; ++r) {
+      const int x = first_index<N>(g, i, r);
+      v[i * R0 + r] = (x >= a.xa && x <= a.xb) ? src[x] : mk((T)0, (T)0);
+    }
+}
+
 template <typename T, int N, int MODE, int DIR>
 __global__ void __launch_bounds__((XCfg<N>::threads))
 k_pass_x(XArgs a) {
   using C = XCfg<N>;
-  constexpr int G = C::G, NG = C::NG, E = Geo<N>::E;
-  constexpr int R0 = Radix<N, 1>::r, NB0 = E / R0, PS = CS<N>::v;
+  constexpr int G = C::G, NG = C::NG, E = Geo<N>::E, PS = CS<N>::v;
   __shared__ cx<T> sm[NG * PS];
   extern __shared__ double dyn[];
-  double* hist = dyn;                                  // 3 * nbins
-  int* U = (int*)(dyn + 3 * (size_t)a.nbins + 1);      // nbins + 1
-  double* tot_s = dyn + 3 * (size_t)a.nbins;
+  double* hist = dyn;                                  // 2 * nbins
+  double* tot_s = dyn + 2 * (size_t)a.nbins;
+  int* U = (int*)(dyn + 2 * (size_t)a.nbins + 1);      // nbins + 2 (last: sentinel)
 
   const int q = threadIdx.x / G, g = threadIdx.x % G;
   cx<T>* s = sm + q * PS;
@@ -447,28 +524,25 @@ k_pass_x(XArgs a) {
   constexpr bool BIN = MODE != X_FFT_STORE;
 
   if (BIN) {
-    for (int i = threadIdx.x; i < 3 * a.nbins + 1; i += C::threads) dyn[i] = 0.0;
+    for (int i = threadIdx.x; i < 2 * a.nbins + 1; i += C::threads) dyn[i] = 0.0;
     for (int i = threadIdx.x; i <= a.nbins; i += C::threads) U[i] = a.U[i];
+    if (threadIdx.x == 0) U[a.nbins + 1] = 0x7fffffff;
     __syncthreads();
   }
   double tot = 0.0;
-
-  for (long long col = (long long)blockIdx.x * NG + q; col < a.ncols; col += (long long)gridDim.x * NG) {
+  const long long stride = (long long)gridDim.x * NG;
+  long long col = (long long)blockIdx.x * NG + q;
+  cx<T> v[E];
+  if (MODE != X_BIN_ONLY && col < a.ncols) x_load_column<T, N>(a, col, g, v);
+  for (; col < a.ncols; col += stride) {
     const int kz = (int)(col / N), ky = (int)(col % N);
-    const cx<T>* src = (const cx<T>*)a.B + (size_t)col * a.bs - a.bx0;
     if (MODE == X_BIN_ONLY) {
+      const cx<T>* src = (const cx<T>*)a.B + (size_t)col * a.bs - a.bx0;
       for (int i = g; i < N; i += G) s[pad(i)] = (i >= a.xa && i <= a.xb) ? src[i] : mk((T)0, (T)0);
       wave_sync();
     } else {
-      cx<T> v[E];
-#pragma unroll
-      for (int i = 0; i < NB0; ++i)
-#pragma unroll
-        for (int r = 0; r < R0; ++r) {
-          int x = first_index<N>(g, i, r);
-          v[i * R0 + r] = (x >= a.xa && x <= a.xb) ? src[x] : mk((T)0, (T)0);
-        }
       fft_column<T, N, DIR>(s, g, tw, v);
+      if (col + stride < a.ncols) x_load_column<T, N>(a, col + stride, g, v);   // in flight during the binning
     }
     if (!BIN) {
       cx<T>* dst = (cx<T>*)a.out + (size_t)col * N;
@@ -481,48 +555,53 @@ k_pass_x(XArgs a) {
     const int k = sidx(ky, N);
     const int l = a.r2c ? kz : sidx(kz, N);
     const double w = (a.r2c && kz != 0 && kz != N / 2) ? 2.0 : 1.0;
-    const long long base = (long long)k * k + (long long)l * l;
-    int hlo, hhi;
-    if (G == 1) { hlo = 0; hhi = N / 2 + 1; }
-    else { hlo = g * (E / 2); hhi = (g == G - 1) ? N / 2 + 1 : hlo + E / 2; }
+    const int base = k * k + l * l;
+    // lane g owns |h| in [hlo, hlo + NH) (both signs), the last lane also
+    // |h| = N/2; NH consecutive |h| stay inside one 16-element LDS block
+    constexpr int NH = G == 1 ? N / 2 : E / 2;
+    const int hlo = G == 1 ? 0 : g * NH;
     int b = bin_search(U, a.nbins, (long long)hlo * hlo + base);
+    int nextU = U[b + 1];
     int cb = b;
-    double cs = 0.0, cs2 = 0.0, cc = 0.0;
-    for (int ha = hlo; ha < hhi; ++ha) {
-      const long long n2 = (long long)ha * ha + base;
-      b = bin_advance(U, a.nbins, b, n2);
-      double I1, I2 = 0.0, m;
-      {
-        cx<T> f = s[pad(ha)];
-        I1 = ((double)f.x * f.x + (double)f.y * f.y) * a.iscale;
-      }
-      if (ha != 0 && ha != N / 2) {
-        cx<T> f = s[pad(N - ha)];
-        I2 = ((double)f.x * f.x + (double)f.y * f.y) * a.iscale;
-        m = 2.0;
-      } else {
-        m = 1.0;
-      }
-      tot += w * (I1 + I2);
-      if (b != cb) {
-        if (cb >= 0 && cb < a.nbins && cc > 0.0) {
-          atomicAdd(&hist[3 * cb + 0], cs);
-          atomicAdd(&hist[3 * cb + 1], cs2);
-          atomicAdd(&hist[3 * cb + 2], cc);
+    double cs = 0.0, cs2 = 0.0;
+    const cx<T>* sp = s + pad(hlo);
+    auto take = [&](int ha, double I1, double I2) {
+      const int n2 = ha * ha + base;
+      if (n2 >= nextU) {
+        if (cb >= 0 && cb < a.nbins) {
+          atomicAdd(&hist[2 * cb + 0], cs);
+          atomicAdd(&hist[2 * cb + 1], cs2);
         }
-        cb = b; cs = cs2 = cc = 0.0;
+        cs = cs2 = 0.0;
+        do { ++b; nextU = U[b + 1]; } while (n2 >= nextU);
+        cb = b;
       }
       cs += w * (I1 + I2);
       cs2 += w * (I1 * I1 + I2 * I2);
-      cc += w * m;
+      tot += w * (I1 + I2);
+    };
+#pragma unroll
+    for (int t = 0; t < NH; ++t) {
+      const int ha = hlo + t;
+      const cx<T> f1 = (NH <= 16 || G == 1) ? sp[t + (G == 1 ? (t >> 4) : 0)] : s[pad(ha)];
+      const double I1 = ((double)f1.x * f1.x + (double)f1.y * f1.y) * a.iscale;
+      double I2 = 0.0;
+      if (ha != 0) {
+        const cx<T> f2 = s[pad(N - ha)];
+        I2 = ((double)f2.x * f2.x + (double)f2.y * f2.y) * a.iscale;
+      }
+      take(ha, I1, I2);
     }
-    if (cb >= 0 && cb < a.nbins && cc > 0.0) {
-      atomicAdd(&hist[3 * cb + 0], cs);
-      atomicAdd(&hist[3 * cb + 1], cs2);
-      atomicAdd(&hist[3 * cb + 2], cc);
+    if (g == G - 1) {                                      // |h| = N/2 (kx = N/2 only)
+      const cx<T> f1 = s[pad(N / 2)];
+      take(N / 2, ((double)f1.x * f1.x + (double)f1.y * f1.y) * a.iscale, 0.0);
+    }
+    if (cb >= 0 && cb < a.nbins) {
+      atomicAdd(&hist[2 * cb + 0], cs);
+      atomicAdd(&hist[2 * cb + 1], cs2);
     }
     if (col == 0 && g == 0 && a.f0) {
-      cx<T> f = s[pad(0)];
+      const cx<T> f = s[pad(0)];
       a.f0[0] = (double)f.x * sqrt(a.iscale);
       a.f0[1] = (double)f.y * sqrt(a.iscale);
     }
@@ -532,8 +611,48 @@ k_pass_x(XArgs a) {
   tot = wave_sum(tot);
   if ((threadIdx.x & 63) == 0) atomicAdd(tot_s, tot);
   __syncthreads();
-  double* out = a.part + (size_t)blockIdx.x * (3 * (size_t)a.nbins + 1);
-  for (int i = threadIdx.x; i < 3 * a.nbins + 1; i += C::threads) out[i] = dyn[i];
+  double* out = a.part + (size_t)blockIdx.x * (2 * (size_t)a.nbins + 1);
+  for (int i = threadIdx.x; i < 2 * a.nbins + 1; i += C::threads) out[i] = dyn[i];
+}
+
+// voxel count per bin (geometry only): one thread per (ky, kz) column walks
+// |h| upward; integer LDS histogram, integer global totals
+__global__ void __launch_bounds__(256) k_bin_counts(int n, int nkz, int r2c, int nbins, const int* __restrict__ Ug,
+                                                    unsigned long long* __restrict__ out) {
+  extern __shared__ unsigned long long hc[];
+  int* U = (int*)(hc + nbins);
+  for (int i = threadIdx.x; i < nbins; i += 256) hc[i] = 0ull;
+  for (int i = threadIdx.x; i <= nbins; i += 256) U[i] = Ug[i];
+  if (threadIdx.x == 0) U[nbins + 1] = 0x7fffffff;
+  __syncthreads();
+  const long long col = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (col < (long long)nkz * n) {
+    const int kz = (int)(col / n), ky = (int)(col % n);
+    const int k = sidx(ky, n), l = r2c ? kz : sidx(kz, n);
+    const unsigned long long w = (r2c && kz != 0 && kz != n / 2) ? 2ull : 1ull;
+    const int base = k * k + l * l;
+    int b = bin_search(U, nbins, base);
+    int nextU = U[b + 1];
+    unsigned long long acc = 0ull;
+    for (int ha = 0; ha <= n / 2; ++ha) {
+      const int n2 = ha * ha + base;
+      if (n2 >= nextU) {
+        if (b >= 0 && b < nbins && acc) atomicAdd(&hc[b], acc);
+        acc = 0ull;
+        do { ++b; nextU = U[b + 1]; } while (n2 >= nextU);
+      }
+      acc += w * ((ha == 0 || ha == n / 2) ? 1ull : 2ull);
+    }
+    if (b >= 0 && b < nbins && acc) atomicAdd(&hc[b], acc);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nbins; i += 256)
+    if (hc[i]) atomicAdd(&out[i], hc[i]);
+}
+
+__global__ void k_counts_to_double(int nbins, const unsigned long long* __restrict__ c, double* __restrict__ out) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nbins) out[i] = (double)c[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -549,10 +668,11 @@ struct Kahan {
   __device__ __forceinline__ double val() const { return s + c; }
 };
 
-// block b < nvb: 8 values x 32 phases; the last block reduces the z-pass moments
+// block b < nvb: 8 values x 32 phases; the last block reduces the z-pass
+// moments and copies the (geometric) bin counts
 __global__ void __launch_bounds__(256) k_finalize(FinArgs a) {
   __shared__ double ls[256], lc[256];
-  const int nv = 3 * a.nbins + 1;
+  const int nv = 2 * a.nbins + 1;
   const int nvb = (nv + 7) / 8;
   const int t = threadIdx.x;
   if ((int)blockIdx.x < nvb) {
@@ -582,12 +702,11 @@ __global__ void __launch_bounds__(256) k_finalize(FinArgs a) {
         a.totals[1] = a.f0 ? a.f0[0] : 0.0;
         a.totals[2] = a.f0 ? a.f0[1] : 0.0;
       } else {
-        const int bb = v / 3, st = v % 3;
-        (st == 0 ? a.sum : st == 1 ? a.sumsq : a.count)[bb] = val;
+        (v % 2 == 0 ? a.sum : a.sumsq)[v / 2] = val;
       }
     }
   } else {
-    // moments: thread t sums entries t, t+256, ... then fixed-order combine
+    for (int i = t; i < a.nbins; i += 256) a.count[i] = a.cnt[i];
     Kahan k;
     if (a.mom) for (int i = t; i < a.nzb; i += 256) k.add(a.mom[2 * (size_t)i + 1]);
     ls[t] = k.s;
@@ -724,9 +843,9 @@ k_pass_x_adj(XAdjArgs a) {
 // inverse pass Y: B[kz][ky][x] -> inverse transform along y -> A[x][kz][y]
 // ---------------------------------------------------------------------------
 template <typename T, int N>
-__global__ void __launch_bounds__((YCfg<T, N>::threads))
+__global__ void __launch_bounds__((YICfg<T, N>::threads))
 k_pass_y_inv(YInvArgs a) {
-  using C = YCfg<T, N>;
+  using C = YICfg<T, N>;
   constexpr int G = C::G, TX = C::TX, PS = CS<N>::v;
   __shared__ cx<T> sm[TX * PS];
   const int kz = blockIdx.x % a.nkz;
@@ -901,6 +1020,7 @@ __global__ void k_zero(double* p, size_t n) {
     default: return hipErrorInvalidValue;        \
   }
 
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 static unsigned nblk_of(long long total, int threads) { return (unsigned)((total + threads - 1) / threads); }
 
 hipError_t launch_cell_profiles(int c, int n_atoms, const double* xyz, const double* sigma, double* prof, hipStream_t s) {
@@ -936,6 +1056,8 @@ static hipError_t pass_z_t(int mode, const ZArgs& a, int nblocks, hipStream_t s)
     case Z_LOAD_R2C: hipLaunchKernelGGL((k_pass_z<T, N, Z_LOAD_R2C>), dim3(nblocks), dim3(ZCfg<T, N, false>::threads), 0, s, a); break;
     case Z_GEN_C2C: hipLaunchKernelGGL((k_pass_z<T, N, Z_GEN_C2C>), dim3(nblocks), dim3(ZCfg<T, N, true>::threads), 0, s, a); break;
     case Z_LOAD_C2C: hipLaunchKernelGGL((k_pass_z<T, N, Z_LOAD_C2C>), dim3(nblocks), dim3(ZCfg<T, N, true>::threads), 0, s, a); break;
+    case Z_ZOOM_R2C: hipLaunchKernelGGL((k_pass_z<T, N, Z_ZOOM_R2C>), dim3(nblocks), dim3(ZCfg<T, N, false>::threads), 0, s, a); break;
+    case Z_ZOOM_C2C: hipLaunchKernelGGL((k_pass_z<T, N, Z_ZOOM_C2C>), dim3(nblocks), dim3(ZCfg<T, N, true>::threads), 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -961,9 +1083,48 @@ hipError_t launch_pass_y(int prec, int n, const YArgs& a, hipStream_t s) {
 #undef UR_Y
 }
 
+static size_t x_shm(int mode, int nbins) {
+  return mode == X_FFT_STORE ? 0 : (2 * (size_t)nbins + 1) * sizeof(double) + ((size_t)nbins + 2) * sizeof(int);
+}
+
+template <typename T, int N>
+static int x_resident_t(int mode, int dir, int nbins) {
+  int nb = 0;
+  hipError_t e;
+  size_t shm = x_shm(mode, nbins);
+  if (mode == X_FFT_BIN) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pass_x<T, N, X_FFT_BIN, -1>, XCfg<N>::threads, shm);
+  else if (mode == X_BIN_ONLY) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pass_x<T, N, X_BIN_ONLY, -1>, XCfg<N>::threads, shm);
+  else if (dir < 0) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pass_x<T, N, X_FFT_STORE, -1>, XCfg<N>::threads, shm);
+  else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pass_x<T, N, X_FFT_STORE, +1>, XCfg<N>::threads, shm);
+  if (e != hipSuccess) { (void)hipGetLastError(); return 1; }
+  return nb > 0 ? nb : 1;
+}
+
+int x_resident(int prec, int n, int mode, int dir, int nbins) {
+#define UR_XR(NN) return prec == 0 ? x_resident_t<float, NN>(mode, dir, nbins) : x_resident_t<double, NN>(mode, dir, nbins)
+  switch (n) {
+    case 16: UR_XR(16); case 32: UR_XR(32); case 64: UR_XR(64); case 128: UR_XR(128);
+    case 256: UR_XR(256); case 512: UR_XR(512); case 1024: UR_XR(1024);
+    default: return 1;
+  }
+#undef UR_XR
+}
+
+hipError_t launch_bin_counts(int n, int nkz, int r2c, int nbins, const int* U, unsigned long long* tmp, double* out, hipStream_t s) {
+  long long ncols = (long long)nkz * n;
+  size_t shm = (size_t)nbins * sizeof(unsigned long long) + ((size_t)nbins + 2) * sizeof(int);
+  hipError_t e = launch_zero(tmp, (size_t)nbins * sizeof(unsigned long long), s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_bin_counts, dim3((unsigned)((ncols + 255) / 256)), dim3(256), shm, s, n, nkz, r2c, nbins, U, tmp);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_counts_to_double, dim3((nbins + 255) / 256), dim3(256), 0, s, nbins, tmp, out);
+  return hipGetLastError();
+}
+
 template <typename T, int N>
 static hipError_t pass_x_t(int mode, int dir, const XArgs& a, int nblocks, hipStream_t s) {
-  size_t shm = mode == X_FFT_STORE ? 0 : (3 * (size_t)a.nbins + 1) * sizeof(double) + ((size_t)a.nbins + 1) * sizeof(int);
+  size_t shm = x_shm(mode, a.nbins);
   dim3 grid(nblocks), blk(XCfg<N>::threads);
   if (mode == X_FFT_BIN) hipLaunchKernelGGL((k_pass_x<T, N, X_FFT_BIN, -1>), grid, blk, shm, s, a);
   else if (mode == X_BIN_ONLY) hipLaunchKernelGGL((k_pass_x<T, N, X_BIN_ONLY, -1>), grid, blk, shm, s, a);
@@ -979,7 +1140,7 @@ hipError_t launch_pass_x(int prec, int n, int mode, int dir, const XArgs& a, int
 }
 
 hipError_t launch_finalize(const FinArgs& a, hipStream_t s) {
-  int nv = 3 * a.nbins + 1;
+  int nv = 2 * a.nbins + 1;
   int nvb = (nv + 7) / 8;
   hipLaunchKernelGGL(k_finalize, dim3(nvb + 1), dim3(256), 0, s, a);
   return hipGetLastError();
@@ -992,6 +1153,7 @@ hipError_t launch_merge(const MergeArgs& a, hipStream_t s) {
 
 template <typename T, int N>
 static hipError_t pass_x_adj_t(const XAdjArgs& a, int nblocks, hipStream_t s) {
+  if (nblocks <= 0) return hipSuccess;
   size_t shm = (size_t)a.nbins * sizeof(double) + ((size_t)a.nbins + 1) * sizeof(int);
   hipLaunchKernelGGL((k_pass_x_adj<T, N>), dim3(nblocks), dim3(XCfg<N>::threads), shm, s, a);
   return hipGetLastError();
@@ -1007,7 +1169,7 @@ template <typename T, int N>
 static hipError_t pass_y_inv_t(const YInvArgs& a, hipStream_t s) {
   long long nb = (long long)a.nkz * a.nxt;
   if (nb <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_pass_y_inv<T, N>), dim3((unsigned)nb), dim3(YCfg<T, N>::threads), 0, s, a);
+  hipLaunchKernelGGL((k_pass_y_inv<T, N>), dim3((unsigned)nb), dim3(YICfg<T, N>::threads), 0, s, a);
   return hipGetLastError();
 }
 
@@ -1068,6 +1230,23 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_zero, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, (double*)p, n);
   return hipGetLastError();
+}
+
+// Stockham stage sequence (L, R) of a length-n column, as the kernels run it
+template <int N>
+static int stages_t(int* Ls, int* Rs) {
+  int k = 0;
+  for (int l = 1; l < N; l *= radix_at<N>(l)) { Ls[k] = l; Rs[k] = radix_at<N>(l); ++k; }
+  return k;
+}
+int fft_stages(int n, int* Ls, int* Rs) {
+  switch (n) {
+    case 16: return stages_t<16>(Ls, Rs); case 32: return stages_t<32>(Ls, Rs);
+    case 64: return stages_t<64>(Ls, Rs); case 128: return stages_t<128>(Ls, Rs);
+    case 256: return stages_t<256>(Ls, Rs); case 512: return stages_t<512>(Ls, Rs);
+    case 1024: return stages_t<1024>(Ls, Rs);
+    default: return 0;
+  }
 }
 
 // tile geometry for the planner

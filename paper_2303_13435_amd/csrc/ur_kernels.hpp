@@ -9,7 +9,8 @@
 namespace ur {
 
 // Density source of the first (z) pass.
-enum ZMode { Z_GEN_R2C = 0, Z_LOAD_R2C = 1, Z_GEN_C2C = 2, Z_LOAD_C2C = 3 };
+// GEN: ED-1 voxels (block factor 1); ZOOM: block-summed zoom levels.
+enum ZMode { Z_GEN_R2C = 0, Z_LOAD_R2C = 1, Z_GEN_C2C = 2, Z_LOAD_C2C = 3, Z_ZOOM_R2C = 4, Z_ZOOM_C2C = 5 };
 // What the last (x) pass does with each transformed column.
 enum XMode { X_FFT_BIN = 0, X_BIN_ONLY = 1, X_FFT_STORE = 2 };
 
@@ -61,18 +62,19 @@ struct XArgs {
   double oscale;            // store scale
   int nbins;
   const int* U;             // nbins + 1 integer thresholds on n2
-  double* part;             // per block: 3*nbins hist + 1 total
+  double* part;             // per block: 2*nbins (sum, sumsq) + 1 total
   double* f0;               // F(0) (2 doubles), written by the block holding it
   int ncols;
 };
 
 struct FinArgs {
-  const double* part;       // nblk x (3 nbins + 1)
+  const double* part;       // nblk x (2 nbins + 1)
   int nblk;
   int nbins;
   const double* mom;        // nzb x 2 (may be null)
   int nzb;
   const double* f0;
+  const double* cnt;        // per-bin voxel counts (geometry, computed with the bins)
   double* sum;
   double* sumsq;
   double* count;
@@ -155,6 +157,13 @@ hipError_t launch_fold_reduce(int c3, const double* part, int nblk, double* gcel
 hipError_t launch_grad_amp(int c, int n_atoms, const double* prof, const double* gcell, double* grad_amp, hipStream_t s);
 hipError_t launch_rho_generate(int prec, int n, const ZArgs& a, void* rho, hipStream_t s);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
+hipError_t launch_bin_counts(int n, int nkz, int r2c, int nbins, const int* U, unsigned long long* tmp, double* out, hipStream_t s);
+int x_resident(int prec, int n, int mode, int dir, int nbins);   // resident x-pass blocks per CU
+
+// Stockham stages (L, R) the kernels run for a length-n column; returns the
+// count (the twiddle table of stage (L, R) holds exp(-2 pi i r j/(L R)) for
+// j < L, 1 <= r < R, laid out [j][r-1], stages back to back)
+int fft_stages(int n, int* Ls, int* Rs);
 
 // tile geometry used by the host planner (must match the kernels)
 int z_tile(int prec, int n, int c2c);     // y pencils per z-pass block

@@ -1,0 +1,291 @@
+"""GPU parity of the remaining rows of the path against the FP64 oracle:
+adjoint (voxel and amplitude gradients), zoom merge, out-of-core streaming,
+graph replay, and the full-size boxes (512^3 whole, 1024^3 sampled).
+
+Tolerances are written per test; bin counts are always bit-exact.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ur():
+    import torch
+    import paper_2303_13435_amd as ur
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return ur
+
+
+@pytest.fixture(scope="module")
+def orc():
+    import oracle
+    oracle.lib()
+    return oracle
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _hist_from(ur, d):
+    import torch
+    h = ur.Hist(len(d["count"]))
+    for k in ("sum", "sumsq", "count"):
+        getattr(h, k).copy_(torch.as_tensor(np.ascontiguousarray(d[k], dtype=np.float64)))
+    return h
+
+
+# ---------------------------------------------------------------------------
+# adjoint
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("prec", [1, 0])
+@pytest.mark.parametrize("n,c,radius", [(32, 8, 11.0), (64, 16, 24.0)])
+def test_adjoint_matches_oracle(ur, orc, prec, n, c, radius):
+    import torch
+    wl = W.small(n, c=c, n_atoms=6, seed=50 + n, radius=radius, nbins=40, prec=prec)
+    _say(f"adjoint n={n} prec={prec}")
+    ref = orc.simulate(wl, return_fields=True)
+    rng = np.random.default_rng(60 + n)
+    g_bin = rng.standard_normal(wl.nbins) * 1e3
+    g_bin[ref["count"] == 0] = 0.0
+    grad_ref = orc.grad_rho(ref["F"], wl.voxel, wl.edges, ref["count"], g_bin)
+    amp_ref = orc.grad_amp(grad_ref, wl.cell, wl.mask)
+
+    plan = ur.Plan(n, wl.voxel, prec)
+    plan.set_bins(wl.edges)
+    cell = ur.DeviceCell.from_host(wl.cell)
+    fwd = ur.Hist(wl.nbins)
+    plan.simulate(cell, wl.mask, wl.zoom, fwd)
+    gb = torch.as_tensor(g_bin, device="cuda")
+    grad = torch.empty((n, n, n), dtype=plan.real_dtype, device="cuda")
+    gamp = torch.empty(wl.cell.n_atoms, dtype=torch.float64, device="cuda")
+    plan.adjoint(fwd, gb, cell=cell, mask=wl.mask, grad_rho=grad, grad_amp=gamp)
+    torch.cuda.synchronize()
+    assert np.array_equal(fwd.numpy()["count"], ref["count"])
+    g = grad.cpu().numpy().astype(np.float64)
+    err = np.max(np.abs(g - grad_ref)) / np.max(np.abs(grad_ref))
+    ga = gamp.cpu().numpy()
+    err_a = np.max(np.abs(ga - amp_ref)) / np.max(np.abs(amp_ref))
+    _say(f"  grad_rho rel err {err:.3e}, grad_amp rel err {err_a:.3e}")
+    tol = 1e-10 if prec == 1 else 2e-5
+    assert err <= tol and err_a <= tol
+
+    # density given as a tensor: same gradient
+    rho = torch.as_tensor(ref["rho"], dtype=plan.real_dtype, device="cuda").contiguous()
+    grad2 = torch.empty_like(grad)
+    plan.adjoint(fwd, gb, rho=rho, grad_rho=grad2)
+    torch.cuda.synchronize()
+    err2 = np.max(np.abs(grad2.cpu().numpy() - grad_ref)) / np.max(np.abs(grad_ref))
+    assert err2 <= tol
+
+
+def test_adjoint_dot_product_identity(ur):
+    """<d I_b / d rho . v, g> = <v, adjoint(g)>: the adjoint of the linearised
+    forward map, checked with the FP64 path by a central difference along v."""
+    import torch
+    n = 32
+    wl = W.small(n, c=8, n_atoms=5, seed=71, radius=11.0, nbins=30, prec=1)
+    plan = ur.Plan(n, 1.0, 1)
+    plan.set_bins(wl.edges)
+    cell = ur.DeviceCell.from_host(wl.cell)
+    rho = plan.rho_generate(cell, wl.mask, wl.zoom)
+    rng = np.random.default_rng(3)
+    v = torch.as_tensor(rng.standard_normal((n, n, n)), device="cuda")
+    g = torch.as_tensor(rng.standard_normal(wl.nbins), device="cuda")
+
+    def means(r):
+        h = ur.Hist(wl.nbins)
+        plan.simulate_rho(r.contiguous(), h)
+        torch.cuda.synchronize()
+        d = h.numpy()
+        return np.where(d["count"] > 0, d["sum"] / np.maximum(d["count"], 1), 0.0), h
+
+    m0, h0 = means(rho)
+    gg = torch.as_tensor(np.where(h0.numpy()["count"] > 0, g.cpu().numpy(), 0.0), device="cuda")
+    grad = torch.empty_like(rho)
+    plan.adjoint(h0, gg, rho=rho, grad_rho=grad)
+    torch.cuda.synchronize()
+    eps = 1e-4
+    mp, _ = means(rho + eps * v)
+    mm, _ = means(rho - eps * v)
+    lhs = float(np.dot((mp - mm) / (2 * eps), gg.cpu().numpy()))
+    rhs = float(torch.sum(grad * v).item())
+    _say(f"  dot test lhs {lhs:.10e} rhs {rhs:.10e}")
+    assert abs(lhs - rhs) <= 1e-7 * max(abs(lhs), abs(rhs))
+
+
+# ---------------------------------------------------------------------------
+# merge
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_merge_matches_oracle(ur, orc, mode):
+    import torch
+    levels = W.zoom_levels(64, 8, 8, 91, 26.0, [(64, 1), (32, 4), (32, 8)], 80, decades=3.0)
+    refs = []
+    for wl in levels:
+        r = orc.simulate(wl)
+        refs.append({"n": wl.n, "voxel": wl.voxel, "count": r["count"], "sum": r["sum"], "sumsq": r["sumsq"]})
+    edges = levels[0].edges
+    mean_ref, sem_ref, own_ref = orc.merge(refs, edges, mode, 8.0)
+    hists = [_hist_from(ur, r) for r in refs]
+    e_dev = torch.as_tensor(edges, device="cuda")
+    mean, sem, owner = ur.merge_zooms(hists, [r["n"] for r in refs], [r["voxel"] for r in refs], e_dev, mode, 8.0)
+    torch.cuda.synchronize()
+    mean, sem, owner = mean.cpu().numpy(), sem.cpu().numpy(), owner.cpu().numpy()
+    assert np.array_equal(owner, own_ref)
+    ok = ~np.isnan(mean_ref)
+    assert np.array_equal(np.isnan(mean), np.isnan(mean_ref))
+    assert np.all(np.abs(mean[ok] - mean_ref[ok]) <= 1e-12 * np.abs(mean_ref[ok]))
+    oks = ~np.isnan(sem_ref)
+    assert np.all(np.abs(sem[oks] - sem_ref[oks]) <= 1e-9 * np.abs(sem_ref[oks]) + 1e-300)
+    assert ok.sum() > 20
+
+
+def test_zoom_levels_end_to_end_merge(ur, orc):
+    """GPU levels (simulate) merged on the GPU vs oracle levels merged by the
+    oracle: FP64 path within 1e-11."""
+    import torch
+    levels = W.zoom_levels(64, 8, 8, 92, 26.0, [(64, 1), (32, 4)], 60, decades=3.0)
+    refs, hists = [], []
+    for wl in levels:
+        wl = W.Workload(wl.name, wl.n, wl.voxel, 1, wl.transform, wl.cell, wl.mask, wl.zoom, wl.edges)
+        r = orc.simulate(wl)
+        refs.append({"n": wl.n, "voxel": wl.voxel, "count": r["count"], "sum": r["sum"], "sumsq": r["sumsq"]})
+        plan = ur.Plan(wl.n, wl.voxel, 1)
+        plan.set_bins(wl.edges)
+        h = ur.Hist(wl.nbins)
+        plan.simulate(ur.DeviceCell.from_host(wl.cell), wl.mask, wl.zoom, h)
+        hists.append(h)
+    mean_ref, _, own_ref = orc.merge(refs, levels[0].edges, 0, 8.0)
+    mean, _, owner = ur.merge_zooms(hists, [r["n"] for r in refs], [r["voxel"] for r in refs],
+                                    torch.as_tensor(levels[0].edges, device="cuda"), 0, 8.0)
+    torch.cuda.synchronize()
+    assert np.array_equal(owner.cpu().numpy(), own_ref)
+    ok = ~np.isnan(mean_ref)
+    assert np.all(np.abs(mean.cpu().numpy()[ok] - mean_ref[ok]) <= 1e-11 * np.abs(mean_ref[ok]))
+
+
+# ---------------------------------------------------------------------------
+# out-of-core streaming and graph replay
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,prec", [(64, 1), (128, 0)])
+def test_out_of_core_matches_oracle(ur, orc, n, prec):
+    import torch
+    wl = W.small(n, c=8, n_atoms=7, seed=81, mask=W.trunc_oct(0.4 * n), nbins=60, prec=prec)
+    ref = orc.simulate(wl, return_fields=True)
+    rho = ref["rho"]
+    nz = np.flatnonzero(np.any(rho != 0.0, axis=(1, 2)))
+    x_lo, x_hi = int(nz.min()), int(nz.max())
+    host = torch.empty((n, n, n), dtype=torch.float32 if prec == 0 else torch.float64, pin_memory=True)
+    host.copy_(torch.as_tensor(rho))
+    plan = ur.Plan(n, 1.0, prec)
+    plan.set_bins(wl.edges)
+    h = ur.Hist(wl.nbins)
+    nbytes = plan.simulate_host(host, x_lo, x_hi, h)
+    torch.cuda.synchronize()
+    got = h.numpy()
+    assert nbytes == (x_hi - x_lo + 1) * n * n * host.element_size()
+    assert np.array_equal(got["count"], ref["count"])
+    pop = ref["count"] > 0
+    ibar = ref["totals"][0] / n ** 3
+    floor = (8 * (6e-8 if prec == 0 else 1.2e-16)) ** 2 * ibar
+    rel = np.abs(got["mean"][pop] - ref["mean"][pop]) / np.maximum(np.abs(ref["mean"][pop]), floor)
+    assert rel.max() <= (1e-5 if prec == 0 else 1e-12)
+    assert abs(got["totals"][3] - ref["rho_sumsq"]) <= 1e-6 * ref["rho_sumsq"]
+
+
+def test_graph_replay_matches_eager(ur):
+    import torch
+    wl = W.small(64, c=8, n_atoms=10, seed=7, radius=25.0, nbins=64)
+    plan = ur.Plan(64, 1.0, 0)
+    plan.set_bins(wl.edges)
+    cell = ur.DeviceCell.from_host(wl.cell)
+    eager = ur.Hist(wl.nbins)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        plan.simulate(cell, wl.mask, wl.zoom, eager)     # first call allocates
+    torch.cuda.synchronize()
+    ref = eager.numpy()
+    h = ur.Hist(wl.nbins)
+    g = ur.Graph(s)
+    with torch.cuda.stream(s):
+        with g:
+            plan.simulate(cell, wl.mask, wl.zoom, h, stream=s)
+    for rep in range(4):
+        h.sum.fill_(-1.0)                                 # eager work between replays
+        torch.cuda.synchronize()
+        g.launch()
+        torch.cuda.synchronize()
+        got = h.numpy()
+        assert np.array_equal(got["count"], ref["count"])
+        pop = ref["count"] > 0
+        assert np.allclose(got["sum"][pop], ref["sum"][pop], rtol=1e-12, atol=0), rep
+
+
+# ---------------------------------------------------------------------------
+# full-size boxes
+# ---------------------------------------------------------------------------
+
+def test_c2_full_512(ur, orc):
+    """C2: 512^3 FP32 r2c, 512 log bins, against the whole FP64 oracle."""
+    import torch
+    wl = W.c2()
+    _say("C2 512^3: oracle ...")
+    ref = orc.simulate(wl)
+    plan = ur.Plan(wl.n, wl.voxel, 0)
+    plan.set_bins(wl.edges)
+    h = ur.Hist(wl.nbins)
+    plan.simulate(ur.DeviceCell.from_host(wl.cell), wl.mask, wl.zoom, h)
+    torch.cuda.synchronize()
+    got = h.numpy()
+    assert np.array_equal(got["count"], ref["count"])
+    pop = ref["count"] > 0
+    rel = np.abs(got["mean"][pop] - ref["mean"][pop]) / np.abs(ref["mean"][pop])
+    _say(f"  C2 max rel err {rel.max():.3e} (median {np.median(rel):.3e})")
+    assert rel.max() <= 1e-5
+    assert abs(got["totals"][0] - ref["totals"][0]) <= 1e-6 * ref["totals"][0]
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_m1024_full_size_sampled(ur, orc, prec):
+    """1024^3 headline box in the launch configuration the benchmark times:
+    every bin count bit-exact; every bin whose shells lie within |h|,|k|,|l|
+    <= 6 compared against direct summation of eq. 1; Parseval and F(0)
+    against the density moments from the definition."""
+    import torch
+    wl = W.m1024(prec)
+    plan = ur.Plan(wl.n, wl.voxel, prec)
+    plan.set_bins(wl.edges)
+    h = ur.Hist(wl.nbins)
+    plan.simulate(ur.DeviceCell.from_host(wl.cell), wl.mask, wl.zoom, h)
+    torch.cuda.synchronize()
+    got = h.numpy()
+    _say("M1024: oracle counts ...")
+    cnt = orc.bin_counts(wl.n, wl.voxel, wl.edges)
+    assert np.array_equal(got["count"], cnt)
+    g = orc.cell_synth(wl.cell)
+    s1, s2 = orc.density_moments(wl, g)
+    tol = 1e-6 if prec == 0 else 1e-12
+    n3 = float(wl.n) ** 3
+    assert abs(got["totals"][3] - s2) <= tol * s2
+    assert abs(got["totals"][0] - s2 / n3) <= tol * s2 / n3                # Parseval
+    assert abs(got["totals"][1] - s1 / n3) <= tol * s1 / n3                # F(0) = sum rho / n^3
+    _say("M1024: oracle low-frequency coefficients ...")
+    sel, c_ref, s_ref, m_ref = orc.lowfreq_bins(wl, 6, g)
+    assert np.array_equal(got["count"][sel], c_ref)
+    ok = c_ref > 0
+    rel = np.abs(got["mean"][sel][ok] - m_ref[ok]) / np.abs(m_ref[ok])
+    _say(f"  M1024 prec={prec}: {ok.sum()} low-Q bins, max rel err {rel.max():.3e}")
+    assert ok.sum() >= 30 and rel.max() <= (1e-5 if prec == 0 else 1e-12)
