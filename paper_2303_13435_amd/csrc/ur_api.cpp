@@ -151,7 +151,7 @@ static Layout layout_incore(const ur_plan* p, int nbins) {
   L.part = align256(L.B + (size_t)p->nkz * n * n * p->cs);
   L.mom = align256(L.part + (size_t)x_blocks_for(nbins) * (2 * (size_t)std::max(nbins, 1) + 1) * 8);
   L.f0 = align256(L.mom + n * (size_t)ntiles(p) * 16);
-  L.total = align256(L.f0 + 64);
+  L.total = align256(L.f0 + 64 + 256 * 8);
   return L;
 }
 
@@ -168,7 +168,7 @@ static Layout layout_host(const ur_plan* p, int nbins, int xlo, int xhi) {
   L.part = align256(L.B + (size_t)p->nkz * n * bs * p->cs);
   L.mom = align256(L.part + (size_t)x_blocks_for(nbins) * (2 * (size_t)std::max(nbins, 1) + 1) * 8);
   L.f0 = align256(L.mom + n * (size_t)ntiles(p) * 16);
-  L.total = align256(L.f0 + 64);
+  L.total = align256(L.f0 + 64 + 256 * 8);
   return L;
 }
 
@@ -517,7 +517,7 @@ static ur_status run_y_x(ur_plan* p, const FwdGeom& g, char* A, char* B, const L
   FinArgs fa{};
   fa.part = xa.part; fa.nblk = nxb; fa.nbins = p->nbins;
   fa.mom = nzb > 0 ? (const double*)(p->ws + lay.mom) : nullptr; fa.nzb = nzb;
-  fa.f0 = xa.f0; fa.cnt = p->dCount; fa.sum = h->sum; fa.sumsq = h->sumsq; fa.count = h->count; fa.totals = h->totals;
+  fa.mpart = (double*)(p->ws + lay.f0 + 64); fa.f0 = xa.f0; fa.cnt = p->dCount; fa.sum = h->sum; fa.sumsq = h->sumsq; fa.count = h->count; fa.totals = h->totals;
   {
     PassTimer tm(p, P_FIN, s);
     UR_HIP(launch_finalize(fa, s));
@@ -673,7 +673,7 @@ ur_status ur_intensity_bin(ur_plan* p, const void* spectrum, const ur_hist* h, v
   UR_HIP(launch_pass_x(p->prec, n, X_BIN_ONLY, -1, xa, nxb, s));
   FinArgs fa{};
   fa.part = xa.part; fa.nblk = nxb; fa.nbins = p->nbins; fa.mom = nullptr; fa.nzb = 0;
-  fa.f0 = xa.f0; fa.cnt = p->dCount; fa.sum = h->sum; fa.sumsq = h->sumsq; fa.count = h->count; fa.totals = h->totals;
+  fa.mpart = (double*)(p->ws + lay.f0 + 64); fa.f0 = xa.f0; fa.cnt = p->dCount; fa.sum = h->sum; fa.sumsq = h->sumsq; fa.count = h->count; fa.totals = h->totals;
   UR_HIP(launch_finalize(fa, s));
   return UR_OK;
 }
@@ -752,7 +752,7 @@ ur_status ur_simulate_host(ur_plan* p, const void* rho_host, int32_t x_lo, int32
   UR_HIP(launch_pass_x(p->prec, n, X_FFT_BIN, -1, xa, x_blocks(p), s));
   FinArgs fa{};
   fa.part = xa.part; fa.nblk = x_blocks(p); fa.nbins = p->nbins; fa.mom = (const double*)(p->ws + lay.mom); fa.nzb = zb;
-  fa.f0 = xa.f0; fa.cnt = p->dCount; fa.sum = h->sum; fa.sumsq = h->sumsq; fa.count = h->count; fa.totals = h->totals;
+  fa.mpart = (double*)(p->ws + lay.f0 + 64); fa.f0 = xa.f0; fa.cnt = p->dCount; fa.sum = h->sum; fa.sumsq = h->sumsq; fa.count = h->count; fa.totals = h->totals;
   UR_HIP(launch_finalize(fa, s));
   return UR_OK;
 }
