@@ -358,7 +358,9 @@ class Plan:
 
 
 def merge_zooms(hists: Sequence[Hist], ns: Sequence[int], voxels: Sequence[float], edges_dev, mode: int = MERGE_FINEST,
-                n_min: float = 32.0, stream=None):
+                n_min: float = 32.0, stream=None, out=None):
+    """One curve from several zoom levels; `out` = (mean, sem, owner) device
+    tensors to write (allocated here when None -- pass them under capture)."""
     torch = _torch()
     k = len(hists)
     nb = hists[0].nbins
@@ -366,9 +368,14 @@ def merge_zooms(hists: Sequence[Hist], ns: Sequence[int], voxels: Sequence[float
     n_arr = (_c.c_int32 * k)(*[int(v) for v in ns])
     v_arr = (_c.c_double * k)(*[float(v) for v in voxels])
     _require(edges_dev, torch.float64, nb + 1, "edges")
-    mean = torch.empty(nb, dtype=torch.float64, device="cuda")
-    sem = torch.empty(nb, dtype=torch.float64, device="cuda")
-    owner = torch.empty(nb, dtype=torch.int32, device="cuda")
+    if out is None:
+        out = (torch.empty(nb, dtype=torch.float64, device="cuda"),
+               torch.empty(nb, dtype=torch.float64, device="cuda"),
+               torch.empty(nb, dtype=torch.int32, device="cuda"))
+    mean, sem, owner = out
+    _require(mean, torch.float64, nb, "mean")
+    _require(sem, torch.float64, nb, "sem")
+    _require(owner, torch.int32, nb, "owner")
     _check(lib().ur_merge_zooms(k, arr, n_arr, v_arr, nb, _ptr(edges_dev), int(mode), float(n_min), _ptr(mean),
                                 _ptr(sem), _ptr(owner), _stream(stream)), "ur_merge_zooms")
     return mean, sem, owner

@@ -265,7 +265,8 @@ ur_status ur_plan_create(int32_t n, double voxel, int32_t prec, uint32_t flags, 
   if (!out) return fail(UR_ERR_INVALID, "out is null");
   *out = nullptr;
   if (!is_pow2(n) || n < 16) return fail(UR_ERR_INVALID, "n = %d must be a power of two >= 16", n);
-  if (n > 1024) return fail(UR_ERR_UNSUPPORTED, "n = %d: this build runs boxes up to 1024^3", n);
+  if (n > 2048) return fail(UR_ERR_UNSUPPORTED, "n = %d: this build runs boxes up to 2048^3", n);
+  if (n > 1024 && (flags & UR_C2C)) return fail(UR_ERR_UNSUPPORTED, "complex transforms run up to 1024^3");
   if (!(voxel > 0.0) || !isfinite(voxel)) return fail(UR_ERR_INVALID, "voxel must be positive");
   if (prec != UR_F32 && prec != UR_F64) return fail(UR_ERR_INVALID, "prec must be UR_F32 or UR_F64");
   if (flags & ~1u) return fail(UR_ERR_INVALID, "unknown flags 0x%x", flags);
@@ -621,6 +622,7 @@ ur_status ur_simulate_rho(ur_plan* p, const void* rho, const ur_hist* h, void* s
 ur_status ur_fft3d_exec(ur_plan* p, const void* in, void* out, int32_t dir, void* stream) {
   if (!p || !in || !out) return fail(UR_ERR_INVALID, "null argument");
   if (dir != -1 && dir != 1) return fail(UR_ERR_INVALID, "dir must be -1 or +1");
+  if (dir > 0 && p->n > 1024) return fail(UR_ERR_UNSUPPORTED, "inverse transforms run up to 1024^3");
   if (in == out) return fail(UR_ERR_INVALID, "in and out must differ");
   hipStream_t s = (hipStream_t)stream;
   Layout lay = layout_incore(p, std::max(p->nbins, 1));
@@ -764,6 +766,7 @@ ur_status ur_adjoint(ur_plan* p, const void* rho, const ur_cell* cell, const ur_
   if ((rho != nullptr) == (cell != nullptr)) return fail(UR_ERR_INVALID, "give exactly one of rho and cell");
   if (grad_amp && !cell) return fail(UR_ERR_INVALID, "grad_amp needs the cell description");
   if (!grad_rho && !grad_amp) return UR_OK;
+  if (p->n > 1024) return fail(UR_ERR_UNSUPPORTED, "the adjoint runs up to 1024^3");
   hipStream_t s = (hipStream_t)stream;
   Layout lay = layout_incore(p, p->nbins);
   UR_TRY(ensure_ws(p, lay.total, s));

@@ -1035,8 +1035,19 @@ __global__ void k_zero(double* p, size_t n) {
     case 256: MACRO(256); break;                 \
     case 512: MACRO(512); break;                 \
     case 1024: MACRO(1024); break;               \
+    case 2048: MACRO(2048); break;               \
     default: return hipErrorInvalidValue;        \
   }
+
+// LDS budget of one block (gfx950: 160 KB per CU); kernels whose
+// configuration would exceed it are not instantiated for that size
+constexpr size_t kLdsBytes = 160 * 1024;
+template <typename T, int N, bool C2C> constexpr bool z_fits() {
+  return (size_t)ZCfg<T, N, C2C>::NG * CS<N>::v * sizeof(cx<T>) + 1024 <= kLdsBytes;
+}
+template <typename T, int N> constexpr bool inv_fits() {      // inverse y / z passes
+  return (size_t)YCfg<T, N>::TX * CS<N>::v * sizeof(cx<T>) <= kLdsBytes && N <= 1024;
+}
 
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 static unsigned nblk_of(long long total, int threads) { return (unsigned)((total + threads - 1) / threads); }
@@ -1069,6 +1080,16 @@ hipError_t launch_cell_tables(int prec, int c, int f, const double* cell, void* 
 template <typename T, int N>
 static hipError_t pass_z_t(int mode, const ZArgs& a, int nblocks, hipStream_t s) {
   if (nblocks <= 0) return hipSuccess;
+  if constexpr (!z_fits<T, N, true>()) {
+    if (mode == Z_GEN_C2C || mode == Z_LOAD_C2C || mode == Z_ZOOM_C2C) return hipErrorNotSupported;
+    switch (mode) {
+      case Z_GEN_R2C: hipLaunchKernelGGL((k_pass_z<T, N, Z_GEN_R2C>), dim3(nblocks), dim3(ZCfg<T, N, false>::threads), 0, s, a); break;
+      case Z_LOAD_R2C: hipLaunchKernelGGL((k_pass_z<T, N, Z_LOAD_R2C>), dim3(nblocks), dim3(ZCfg<T, N, false>::threads), 0, s, a); break;
+      case Z_ZOOM_R2C: hipLaunchKernelGGL((k_pass_z<T, N, Z_ZOOM_R2C>), dim3(nblocks), dim3(ZCfg<T, N, false>::threads), 0, s, a); break;
+      default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  } else
   switch (mode) {
     case Z_GEN_R2C: hipLaunchKernelGGL((k_pass_z<T, N, Z_GEN_R2C>), dim3(nblocks), dim3(ZCfg<T, N, false>::threads), 0, s, a); break;
     case Z_LOAD_R2C: hipLaunchKernelGGL((k_pass_z<T, N, Z_LOAD_R2C>), dim3(nblocks), dim3(ZCfg<T, N, false>::threads), 0, s, a); break;
@@ -1122,7 +1143,7 @@ int x_resident(int prec, int n, int mode, int dir, int nbins) {
 #define UR_XR(NN) return prec == 0 ? x_resident_t<float, NN>(mode, dir, nbins) : x_resident_t<double, NN>(mode, dir, nbins)
   switch (n) {
     case 16: UR_XR(16); case 32: UR_XR(32); case 64: UR_XR(64); case 128: UR_XR(128);
-    case 256: UR_XR(256); case 512: UR_XR(512); case 1024: UR_XR(1024);
+    case 256: UR_XR(256); case 512: UR_XR(512); case 1024: UR_XR(1024); case 2048: UR_XR(2048);
     default: return 1;
   }
 #undef UR_XR
@@ -1177,9 +1198,11 @@ hipError_t launch_merge(const MergeArgs& a, hipStream_t s) {
 template <typename T, int N>
 static hipError_t pass_x_adj_t(const XAdjArgs& a, int nblocks, hipStream_t s) {
   if (nblocks <= 0) return hipSuccess;
+  if constexpr (!inv_fits<T, N>()) { return hipErrorNotSupported; } else {
   size_t shm = (size_t)a.nbins * sizeof(double) + ((size_t)a.nbins + 1) * sizeof(int);
   hipLaunchKernelGGL((k_pass_x_adj<T, N>), dim3(nblocks), dim3(XCfg<N>::threads), shm, s, a);
   return hipGetLastError();
+  }
 }
 
 hipError_t launch_pass_x_adj(int prec, int n, const XAdjArgs& a, int nblocks, hipStream_t s) {
@@ -1190,10 +1213,12 @@ hipError_t launch_pass_x_adj(int prec, int n, const XAdjArgs& a, int nblocks, hi
 
 template <typename T, int N>
 static hipError_t pass_y_inv_t(const YInvArgs& a, hipStream_t s) {
+  if constexpr (!inv_fits<T, N>()) { return hipErrorNotSupported; } else {
   long long nb = (long long)a.nkz * a.nxt;
   if (nb <= 0) return hipSuccess;
   hipLaunchKernelGGL((k_pass_y_inv<T, N>), dim3((unsigned)nb), dim3(YICfg<T, N>::threads), 0, s, a);
   return hipGetLastError();
+  }
 }
 
 hipError_t launch_pass_y_inv(int prec, int n, const YInvArgs& a, hipStream_t s) {
@@ -1204,10 +1229,12 @@ hipError_t launch_pass_y_inv(int prec, int n, const YInvArgs& a, hipStream_t s) 
 
 template <typename T, int N>
 static hipError_t pass_z_inv_t(int c2c, const ZInvArgs& a, hipStream_t s) {
+  if constexpr (!inv_fits<T, N>()) { return hipErrorNotSupported; } else {
   unsigned nb = (unsigned)((long long)N * a.ntiles);
   if (c2c) hipLaunchKernelGGL((k_pass_z_inv<T, N, true>), dim3(nb), dim3(ZICfg<T, N, true>::threads), 0, s, a);
   else hipLaunchKernelGGL((k_pass_z_inv<T, N, false>), dim3(nb), dim3(ZICfg<T, N, false>::threads), 0, s, a);
   return hipGetLastError();
+  }
 }
 
 hipError_t launch_pass_z_inv(int prec, int n, int c2c, const ZInvArgs& a, hipStream_t s) {
@@ -1267,7 +1294,7 @@ int fft_stages(int n, int* Ls, int* Rs) {
     case 16: return stages_t<16>(Ls, Rs); case 32: return stages_t<32>(Ls, Rs);
     case 64: return stages_t<64>(Ls, Rs); case 128: return stages_t<128>(Ls, Rs);
     case 256: return stages_t<256>(Ls, Rs); case 512: return stages_t<512>(Ls, Rs);
-    case 1024: return stages_t<1024>(Ls, Rs);
+    case 1024: return stages_t<1024>(Ls, Rs); case 2048: return stages_t<2048>(Ls, Rs);
     default: return 0;
   }
 }
@@ -1278,7 +1305,7 @@ int fft_stages(int n, int* Ls, int* Rs) {
 int z_tile(int prec, int n, int c2c) {
   switch (n) {
     case 16: UR_TILE(16) case 32: UR_TILE(32) case 64: UR_TILE(64) case 128: UR_TILE(128)
-    case 256: UR_TILE(256) case 512: UR_TILE(512) case 1024: UR_TILE(1024)
+    case 256: UR_TILE(256) case 512: UR_TILE(512) case 1024: UR_TILE(1024) case 2048: UR_TILE(2048)
     default: return 0;
   }
 }
@@ -1289,7 +1316,7 @@ int zinv_tile(int prec, int n, int c2c) { return z_tile(prec, n, c2c); }
 int y_tile(int prec, int n) {
   switch (n) {
     case 16: UR_YT(16); case 32: UR_YT(32); case 64: UR_YT(64); case 128: UR_YT(128);
-    case 256: UR_YT(256); case 512: UR_YT(512); case 1024: UR_YT(1024);
+    case 256: UR_YT(256); case 512: UR_YT(512); case 1024: UR_YT(1024); case 2048: UR_YT(2048);
     default: return 0;
   }
 }
@@ -1299,7 +1326,7 @@ int y_tile(int prec, int n) {
 int x_groups(int n) {
   switch (n) {
     case 16: UR_XG(16); case 32: UR_XG(32); case 64: UR_XG(64); case 128: UR_XG(128);
-    case 256: UR_XG(256); case 512: UR_XG(512); case 1024: UR_XG(1024);
+    case 256: UR_XG(256); case 512: UR_XG(512); case 1024: UR_XG(1024); case 2048: UR_XG(2048);
     default: return 0;
   }
 }

@@ -289,3 +289,97 @@ def test_m1024_full_size_sampled(ur, orc, prec):
     rel = np.abs(got["mean"][sel][ok] - m_ref[ok]) / np.abs(m_ref[ok])
     _say(f"  M1024 prec={prec}: {ok.sum()} low-Q bins, max rel err {rel.max():.3e}")
     assert ok.sum() >= 30 and rel.max() <= (1e-5 if prec == 0 else 1e-12)
+
+
+# ---------------------------------------------------------------------------
+# multi-zoom batch at full size: ED-1 2048^3, ED-2 1024^3 (f 4), ED-3 512^3 (f 16)
+# ---------------------------------------------------------------------------
+
+def test_zoom_generation_matches_oracle_midsize(ur, orc):
+    """ED-2/ED-3 style levels from a 256^3 ED-1 (factors 4 and 16, as in the
+    full-size batch) against the whole oracle."""
+    levels = W.zoom_levels(256, 64, 20, 33, 112.0, [(128, 4), (64, 16)], 120, decades=4.0)
+    for wl in levels:
+        ref = orc.simulate(wl)
+        plan = ur.Plan(wl.n, wl.voxel, 0)
+        plan.set_bins(wl.edges)
+        h = ur.Hist(wl.nbins)
+        plan.simulate(ur.DeviceCell.from_host(wl.cell), wl.mask, wl.zoom, h)
+        import torch
+        torch.cuda.synchronize()
+        got = h.numpy()
+        assert np.array_equal(got["count"], ref["count"])
+        pop = ref["count"] > 0
+        rel = np.abs(got["mean"][pop] - ref["mean"][pop]) / np.abs(ref["mean"][pop])
+        _say(f"  {wl.name}: max rel err {rel.max():.3e}")
+        assert rel.max() <= 1e-5
+        assert abs(got["totals"][3] - ref["rho_sumsq"]) <= 1e-6 * ref["rho_sumsq"]
+
+
+def test_c3_batch_full_size_graph(ur, orc):
+    """The three C3 levels and their merge recorded in one HIP graph: replay
+    equals the eager calls; per level every bin count is bit-exact, Parseval
+    and F(0) match the oracle's density moments, and the lowest bins match
+    direct summation of eq. 1."""
+    import torch
+    levels = W.c3_levels()
+    s = torch.cuda.Stream()
+    plans, hists, cells = [], [], []
+    for wl in levels:
+        p = ur.Plan(wl.n, wl.voxel, 0)
+        p.set_bins(wl.edges)
+        plans.append(p)
+        hists.append(ur.Hist(wl.nbins))
+        cells.append(ur.DeviceCell.from_host(wl.cell))
+    edges = torch.as_tensor(levels[0].edges, device="cuda")
+    with torch.cuda.stream(s):
+        for p, h, c, wl in zip(plans, hists, cells, levels):       # eager (allocates)
+            p.simulate(c, wl.mask, wl.zoom, h, stream=s)
+        m_e, s_e, o_e = ur.merge_zooms(hists, [w.n for w in levels], [w.voxel for w in levels], edges, 0, 32.0, stream=s)
+    torch.cuda.synchronize()
+    eager = [h.numpy() for h in hists]
+    m_e, o_e = m_e.cpu().numpy(), o_e.cpu().numpy()
+    nb = levels[0].nbins
+    outs = (torch.empty(nb, dtype=torch.float64, device="cuda"), torch.empty(nb, dtype=torch.float64, device="cuda"),
+            torch.empty(nb, dtype=torch.int32, device="cuda"))
+    g = ur.Graph(s)
+    with torch.cuda.stream(s):
+        with g:
+            for p, h, c, wl in zip(plans, hists, cells, levels):
+                p.simulate(c, wl.mask, wl.zoom, h, stream=s)
+            m_g, s_g, o_g = ur.merge_zooms(hists, [w.n for w in levels], [w.voxel for w in levels], edges, 0, 32.0,
+                                           stream=s, out=outs)
+    for rep in range(2):
+        for h in hists:
+            h.sum.fill_(0.0)
+        torch.cuda.synchronize()
+        g.launch()
+        torch.cuda.synchronize()
+        for h, e in zip(hists, eager):
+            d = h.numpy()
+            assert np.array_equal(d["count"], e["count"])
+            pop = e["count"] > 0
+            assert np.allclose(d["sum"][pop], e["sum"][pop], rtol=1e-12, atol=0)
+        assert np.array_equal(o_g.cpu().numpy(), o_e)
+    # owners: the finest level owns high Q, the coarsest the lowest populated bins
+    own = o_e[o_e >= 0]
+    assert set(own.tolist()) == {0, 1, 2}
+    assert own[0] == 2 and own[-1] == 0
+    # per level against the oracle
+    g1 = orc.cell_synth(levels[0].cell)
+    for wl, d in zip(levels, eager):
+        _say(f"  {wl.name}: oracle counts / moments ...")
+        cnt = orc.bin_counts(wl.n, wl.voxel, wl.edges)
+        assert np.array_equal(d["count"], cnt)
+        s1, s2 = orc.density_moments(wl, g1)
+        n3 = float(wl.n) ** 3
+        assert abs(d["totals"][3] - s2) <= 1e-6 * s2
+        assert abs(d["totals"][0] - s2 / n3) <= 1e-6 * s2 / n3
+        assert abs(d["totals"][1] - s1 / n3) <= 1e-6 * s1 / n3
+        sel, c_ref, s_ref, m_ref = orc.lowfreq_bins(wl, 2, g1)
+        ok = c_ref > 0
+        assert np.array_equal(d["count"][sel], c_ref)
+        if ok.any():
+            rel = np.abs(d["mean"][sel][ok] - m_ref[ok]) / np.abs(m_ref[ok])
+            _say(f"    {ok.sum()} low-Q bins, max rel err {rel.max():.3e}")
+            assert rel.max() <= 1e-5
