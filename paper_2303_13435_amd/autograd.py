@@ -1,0 +1,63 @@
+"""torch.autograd bindings of the binned forward path and its adjoint.
+
+``BinnedIntensity.apply(amp, plan, cell, mask, zoom)`` returns the mean
+intensity of every |Q| bin (0 for empty bins) of the box generated from the
+unit cell with atom amplitudes ``amp``; its backward calls ``ur_adjoint``,
+which gives dL/d amp from dL/dI_b (the gradient of eq. 1's |F|^2 averaged per
+bin, folded back through tiling and masking).  ``BinnedIntensityRho`` does
+the same for a given voxel density.  Both run entirely in the HIP kernels;
+the Python here only moves pointers.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import DeviceCell, Hist, Plan
+
+
+def _means(h: Hist) -> torch.Tensor:
+    cnt = h.count
+    return torch.where(cnt > 0, h.sum / torch.clamp(cnt, min=1.0), torch.zeros_like(h.sum))
+
+
+class BinnedIntensity(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, amp: torch.Tensor, plan: Plan, cell: DeviceCell, mask, zoom):
+        if zoom.factor != 1 or zoom.n1 != plan.n:
+            raise ValueError("amplitude gradients are defined for ED-1 boxes (zoom factor 1)")
+        a = amp.detach().contiguous().to(torch.float64)
+        h = Hist(plan.nbins)
+        plan.simulate(cell, mask, zoom, h, amp=a)
+        ctx.plan, ctx.cell, ctx.mask, ctx.hist, ctx.amp = plan, cell, mask, h, a
+        return _means(h)
+
+    @staticmethod
+    def backward(ctx, g_mean: torch.Tensor):
+        g = torch.where(ctx.hist.count > 0, g_mean.to(torch.float64), torch.zeros_like(g_mean, dtype=torch.float64))
+        grad = torch.empty_like(ctx.amp)
+        ctx.plan.adjoint(ctx.hist, g.contiguous(), cell=ctx.cell, mask=ctx.mask, grad_amp=grad, amp=ctx.amp)
+        return grad, None, None, None, None
+
+
+class BinnedIntensityRho(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, rho: torch.Tensor, plan: Plan):
+        r = rho.detach().contiguous()
+        h = Hist(plan.nbins)
+        plan.simulate_rho(r, h)
+        ctx.plan, ctx.hist, ctx.rho = plan, h, r
+        return _means(h)
+
+    @staticmethod
+    def backward(ctx, g_mean: torch.Tensor):
+        g = torch.where(ctx.hist.count > 0, g_mean.to(torch.float64), torch.zeros_like(g_mean, dtype=torch.float64))
+        grad = torch.empty_like(ctx.rho)
+        ctx.plan.adjoint(ctx.hist, g.contiguous(), rho=ctx.rho, grad_rho=grad)
+        return grad, None
+
+
+def chi2(mean: torch.Tensor, target: torch.Tensor, count: torch.Tensor, rel_sigma: float = 0.01) -> torch.Tensor:
+    """sum over populated bins of ((I_b - T_b) / (rel_sigma T_b))^2."""
+    m = count > 0
+    r = (mean[m] - target[m]) / (rel_sigma * target[m])
+    return torch.sum(r * r)

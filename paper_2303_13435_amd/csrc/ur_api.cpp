@@ -426,7 +426,7 @@ struct CellTables {
   int cbn;
 };
 
-static const int kFoldBlocks = 256;
+static const int kFoldBlocks = 512;
 
 // cell synthesis + tables for the generator (a1 of the path)
 static ur_status prepare_cell(ur_plan* p, const ur_cell* cell, int f, CellTables& t, hipStream_t s) {
@@ -650,7 +650,7 @@ ur_status ur_fft3d_exec(ur_plan* p, const void* in, void* out, int32_t dir, void
     xa.xa = 0; xa.xb = n - 1; xa.oscale = 1.0; xa.ncols = p->nkz * n;
     UR_HIP(launch_pass_x(p->prec, n, X_FFT_STORE, +1, xa, x_blocks(p, X_FFT_STORE, +1), s));
     YInvArgs yi{};
-    yi.B = B; yi.A = A; yi.tw = p->tw; yi.nkz = p->nkz; yi.xt0 = 0; yi.nxt = n / tx;
+    yi.B = B; yi.bx0 = 0; yi.bs = n; yi.A = A; yi.tw = p->tw; yi.nkz = p->nkz; yi.xt0 = 0; yi.nxt = n / tx;
     UR_HIP(launch_pass_y_inv(p->prec, n, yi, s));
     ZInvArgs zi{};
     zi.A = A; zi.out = out; zi.tw = p->tw; zi.nkz = p->nkz; zi.ntiles = n / zinv_tile(p->prec, n, c2c); zi.scale = 1.0;
@@ -795,28 +795,56 @@ ur_status ur_adjoint(ur_plan* p, const void* rho, const ur_cell* cell, const ur_
     zmode = c2c ? Z_LOAD_C2C : Z_LOAD_R2C;
   }
   g.ax0 = 0;
+  // Only the amplitude gradient wanted: every inverse pass is pruned to the
+  // particle exactly like the forward ones, and the inverse z pass folds
+  // straight onto the cell (the n^3 gradient box is never written).
+  const bool amp_only = cell && grad_amp && !grad_rho && !c2c;
+  long long bx0 = 0, bs = n, xt0 = 0, xt1 = n / tx - 1;
+  if (amp_only && g.xlo <= g.xhi) {
+    xt0 = g.xlo / tx;
+    xt1 = g.xhi / tx;
+    bx0 = xt0 * tx;
+    bs = (xt1 - xt0 + 1) * tx;
+  }
   // forward transform along z and y (recomputed; nothing stored from the forward call)
-  long long bx0 = 0;
   if (g.xlo <= g.xhi) {
     za.A = A; za.ax0 = 0; za.tw = p->tw; za.mom = nullptr; za.L = g.L; za.m = g.m; za.nkz = p->nkz;
     za.x0 = g.xlo; za.ntiles = ntiles(p);
     UR_HIP(launch_pass_z(p->prec, n, zmode, za, (g.xhi - g.xlo + 1) * za.ntiles, s));
     YArgs ya{};
-    ya.A = A; ya.ax0 = 0; ya.B = B; ya.bx0 = 0; ya.bs = n; ya.tw = p->tw; ya.L = g.L; ya.m = g.m; ya.gen = g.gen;
+    ya.A = A; ya.ax0 = 0; ya.B = B; ya.bx0 = bx0; ya.bs = bs; ya.tw = p->tw; ya.L = g.L; ya.m = g.m; ya.gen = g.gen;
     ya.nkz = p->nkz; ya.xlo = g.xlo; ya.xhi = g.xhi; ya.xt0 = g.xlo / tx; ya.nxt = g.xhi / tx - g.xlo / tx + 1; ya.ty = zt(p);
     UR_HIP(launch_pass_y(p->prec, n, ya, s));
-    bx0 = (long long)(g.xlo / tx) * tx;
   }
-  // x: transform, weight by G(|q|) 2/n^6, inverse transform (all rows)
+  // x: transform, weight by G(|q|) 2/n^6, inverse transform
   XAdjArgs xj{};
-  xj.B = B; xj.tw = p->tw; xj.nkz = p->nkz; xj.r2c = !c2c;
-  xj.xa = (int)bx0; xj.xb = g.xlo <= g.xhi ? (int)((g.xhi / tx) * tx + tx - 1) : -1;
+  xj.B = B; xj.bx0 = bx0; xj.bs = bs; xj.tw = p->tw; xj.nkz = p->nkz; xj.r2c = !c2c;
+  const long long fx0 = (long long)(g.xlo / tx) * tx;
+  xj.xa = (int)fx0; xj.xb = g.xlo <= g.xhi ? (int)((g.xhi / tx) * tx + tx - 1) : -1;
+  xj.oa = amp_only ? (int)bx0 : 0;
+  xj.ob = amp_only ? (int)(bx0 + bs - 1) : n - 1;
   xj.nbins = p->nbins; xj.U = p->dU; xj.g_bin = g_bin; xj.count = fwd->count;
   xj.gscale = 2.0 / ((double)n * n * n) / ((double)n * n * n); xj.ncols = p->nkz * n;
   UR_HIP(launch_pass_x_adj(p->prec, n, xj, x_blocks(p), s));
   YInvArgs yi{};
-  yi.B = B; yi.A = A; yi.tw = p->tw; yi.nkz = p->nkz; yi.xt0 = 0; yi.nxt = n / tx;
-  UR_HIP(launch_pass_y_inv(p->prec, n, yi, s));
+  yi.B = B; yi.bx0 = bx0; yi.bs = bs; yi.A = A; yi.tw = p->tw; yi.nkz = p->nkz;
+  yi.xt0 = (int)xt0; yi.nxt = (int)(xt1 - xt0 + 1);
+  if (!amp_only || g.xlo <= g.xhi) UR_HIP(launch_pass_y_inv(p->prec, n, yi, s));
+  const int c = cell ? cell->c : 1, c3 = c * c * c;
+  if (amp_only) {
+    if (c > 16) UR_HIP(launch_zero(t.gcell, (size_t)c3 * 8, s));
+    if (g.xlo <= g.xhi) {
+      ZFoldArgs zf{};
+      zf.A = A; zf.tw = p->tw; zf.L = g.L; zf.m = g.m; zf.nkz = p->nkz; zf.xlo = g.xlo; zf.xhi = g.xhi;
+      zf.ntiles = n / zinv_tile(p->prec, n, 0); zf.scale = 1.0; zf.part = t.fold_part; zf.gcell = t.gcell;
+      UR_HIP(launch_pass_z_fold(p->prec, n, zf, kFoldBlocks, s));
+      if (c <= 16) UR_HIP(launch_fold_reduce(c3, t.fold_part, kFoldBlocks, t.gcell, s));
+    } else if (c <= 16) {
+      UR_HIP(launch_zero(t.gcell, (size_t)c3 * 8, s));
+    }
+    UR_HIP(launch_grad_amp(c, cell->n_atoms, t.prof, t.gcell, grad_amp, s));
+    return UR_OK;
+  }
   // the inverse z pass writes grad_rho, or the free B buffer when only grad_amp is wanted
   void* gr = grad_rho ? grad_rho : (void*)B;
   ZInvArgs zi{};
@@ -824,7 +852,6 @@ ur_status ur_adjoint(ur_plan* p, const void* rho, const ur_cell* cell, const ur_
   UR_HIP(launch_pass_z_inv(p->prec, n, c2c, zi, s));
   if (grad_amp) {
     if (c2c) return fail(UR_ERR_UNSUPPORTED, "amplitude gradients need an UR_R2C plan");
-    const int c = cell->c, c3 = c * c * c;
     FoldArgs fo{};
     fo.g = gr; fo.L = g.L; fo.m = g.m; fo.gcell = t.gcell; fo.part = t.fold_part; fo.npencils = n * n;
     if (c <= 16) {

@@ -822,7 +822,7 @@ k_pass_x_adj(XAdjArgs a) {
 
   for (long long col = (long long)blockIdx.x * NG + q; col < a.ncols; col += (long long)gridDim.x * NG) {
     const int kz = (int)(col / N), ky = (int)(col % N);
-    cx<T>* src = (cx<T>*)a.B + (size_t)col * N;
+    cx<T>* src = (cx<T>*)a.B + (size_t)col * a.bs - a.bx0;
     cx<T> v[E];
 #pragma unroll
     for (int i = 0; i < NB0; ++i)
@@ -852,7 +852,7 @@ k_pass_x_adj(XAdjArgs a) {
     }
     wave_sync();
     stages_from<T, N, 1, +1>(s, g, tw);
-    for (int i = g; i < N; i += G) src[i] = s[pad(i)];
+    for (int i = a.oa + g; i <= a.ob; i += G) src[i] = s[pad(i)];
     wave_sync();
   }
 }
@@ -869,10 +869,10 @@ k_pass_y_inv(YInvArgs a) {
   const int kz = blockIdx.x % a.nkz;
   const int xt = a.xt0 + blockIdx.x / a.nkz;
   const int xbase = xt * TX;
-  const cx<T>* Bp = (const cx<T>*)a.B + ((size_t)kz * N) * N + xbase;
+  const cx<T>* Bp = (const cx<T>*)a.B + ((size_t)kz * N) * a.bs + (xbase - a.bx0);
   for (int idx = threadIdx.x; idx < TX * N; idx += C::threads) {
     const int j = idx % TX, ky = idx / TX;
-    sm[j * PS + pad(ky)] = Bp[(size_t)ky * N + j];
+    sm[j * PS + pad(ky)] = Bp[(size_t)ky * a.bs + j];
   }
   __syncthreads();
   const int q = threadIdx.x / G, g = threadIdx.x % G;
@@ -956,6 +956,90 @@ k_pass_z_inv(ZInvArgs a) {
   } else {
     cx<T>* o = (cx<T>*)a.out + ((size_t)X * N + (y0 + q)) * N;
     for (int i = g; i < N; i += G) o[i] = scale(s[pad(i)], sc);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// inverse z pass fused with the fold onto the unit cell: for every pencil of
+// the particle's rows, the c2r transform along z of the weighted spectrum
+// gives grad rho(x, y, :); its inside voxels are summed into the cell voxel
+// they tile from (adjoint of tiling + masking), in LDS per block.  Persistent
+// blocks walk the (plane, y tile) list; the r2c half spectra of a tile are
+// staged, then the same LDS holds the transform columns.
+// ---------------------------------------------------------------------------
+template <typename T, int N>
+__global__ void __launch_bounds__((ZICfg<T, N, false>::threads))
+k_pass_z_fold(ZFoldArgs a) {
+  using C = ZICfg<T, N, false>;
+  constexpr int G = C::G, NG = C::NG, TY = C::TY, HS = C::HS, E = Geo<N>::E;
+  constexpr int R0 = Radix<N, 1>::r, NB0 = E / R0, PS = CS<N>::v;
+  constexpr int HP = HS + 1;
+  constexpr int STG = TY * HP > NG * PS ? TY * HP : NG * PS;
+  __shared__ cx<T> lds[STG];
+  extern __shared__ double acc[];                      // c^3 (c <= 16)
+  const int c = a.L.c, c3 = c * c * c, cm = c - 1;
+  const bool use_lds = c <= 16;
+  if (use_lds) for (int i = threadIdx.x; i < c3; i += C::threads) acc[i] = 0.0;
+  __syncthreads();
+  const int q = threadIdx.x / G, g = threadIdx.x % G;
+  const long long ntile = (long long)(a.xhi - a.xlo + 1) * a.ntiles;
+  for (long long t = blockIdx.x; t < ntile; t += gridDim.x) {
+    const long long X = a.xlo + t / a.ntiles;
+    const int y0 = (int)(t % a.ntiles) * TY;
+    long long ylo, yhi;
+    row_range(a.L, a.m, X, ylo, yhi);
+    if (ylo > yhi || y0 + TY - 1 < ylo || y0 > yhi) continue;   // uniform per block
+    const cx<T>* Ap = (const cx<T>*)a.A + ((size_t)X * a.nkz) * N + y0;
+    for (int idx = threadIdx.x; idx < TY * HS; idx += C::threads) {
+      const int j = idx % TY, kz = idx / TY;
+      lds[j * HP + kz] = Ap[(size_t)kz * N + j];
+    }
+    __syncthreads();
+    cx<T> v[E];
+    {
+      const cx<T>* ha = lds + (2 * q) * HP;
+      const cx<T>* hb = lds + (2 * q + 1) * HP;
+#pragma unroll
+      for (int i = 0; i < NB0; ++i)
+#pragma unroll
+        for (int r = 0; r < R0; ++r) {
+          const int k = first_index<N>(g, i, r);
+          cx<T> A_, B_;
+          if (k <= N / 2) {
+            A_ = ha[k]; B_ = hb[k];
+            if (k == 0 || k == N / 2) { A_.y = (T)0; B_.y = (T)0; }
+          } else {
+            A_ = conjg(ha[N - k]); B_ = conjg(hb[N - k]);
+          }
+          v[i * R0 + r] = mk(A_.x - B_.y, A_.y + B_.x);
+        }
+    }
+    __syncthreads();                                   // staging consumed: reuse it for the columns
+    cx<T>* s = lds + q * PS;
+    fft_column<T, N, +1>(s, g, (const cx<T>*)a.tw, v);
+    // fold the two pencils' inside voxels
+    const long long yA = y0 + 2 * q;
+#pragma unroll
+    for (int p2 = 0; p2 < 2; ++p2) {
+      const long long Y = yA + p2;
+      long long zlo, zhi;
+      col_range(a.L, a.m, X, Y, zlo, zhi);
+      const int ci = (int)(X - a.L.o - a.L.h) & cm, cj = (int)(Y - a.L.o - a.L.h) & cm;
+      const int zoff = -(a.L.o + a.L.h);
+      for (int z = (int)zlo + g; z <= (int)zhi; z += G) {
+        const cx<T> f = s[pad(z)];
+        const double val = (double)(p2 == 0 ? f.x : f.y) * a.scale;
+        const int idx = (ci * c + cj) * c + ((z + zoff) & cm);
+        if (use_lds) atomicAdd(&acc[idx], val);
+        else atomicAdd(&a.gcell[idx], val);
+      }
+    }
+    __syncthreads();                                   // columns done before the next staging
+  }
+  if (use_lds) {
+    __syncthreads();
+    double* out = a.part + (size_t)blockIdx.x * c3;
+    for (int i = threadIdx.x; i < c3; i += C::threads) out[i] = acc[i];
   }
 }
 
@@ -1255,6 +1339,22 @@ hipError_t launch_fold(int prec, int n, const FoldArgs& a, int nblocks, hipStrea
     else hipLaunchKernelGGL((k_fold<double, false>), dim3(nblocks), dim3(256), shm, s, a, n);
   }
   return hipGetLastError();
+}
+
+template <typename T, int N>
+static hipError_t pass_z_fold_t(const ZFoldArgs& a, int nblocks, hipStream_t s) {
+  if constexpr (!inv_fits<T, N>()) { return hipErrorNotSupported; } else {
+    const int c3 = a.L.c * a.L.c * a.L.c;
+    size_t shm = a.L.c <= 16 ? (size_t)c3 * sizeof(double) : 0;
+    hipLaunchKernelGGL((k_pass_z_fold<T, N>), dim3(nblocks), dim3(ZICfg<T, N, false>::threads), shm, s, a);
+    return hipGetLastError();
+  }
+}
+
+hipError_t launch_pass_z_fold(int prec, int n, const ZFoldArgs& a, int nblocks, hipStream_t s) {
+#define UR_ZF(NN) return prec == 0 ? pass_z_fold_t<float, NN>(a, nblocks, s) : pass_z_fold_t<double, NN>(a, nblocks, s)
+  UR_DISPATCH_N(n, UR_ZF);
+#undef UR_ZF
 }
 
 hipError_t launch_fold_reduce(int c3, const double* part, int nblk, double* gcell, hipStream_t s) {

@@ -102,11 +102,13 @@ struct MergeArgs {
 
 // adjoint, inverse passes
 struct XAdjArgs {
-  void* B;                  // columns, transformed in place (all n rows written)
+  void* B;                  // columns [kz][ky][x - bx0] of stride bs, transformed in place
+  long long bx0, bs;
   const void* tw;
   int nkz;
   int r2c;
-  int xa, xb;
+  int xa, xb;               // rows holding the forward data (others zero)
+  int oa, ob;               // rows written back
   int nbins;
   const int* U;
   const double* g_bin;      // dL/dI_b
@@ -116,11 +118,26 @@ struct XAdjArgs {
 };
 
 struct YInvArgs {
-  const void* B;            // [kz][ky][x]
+  const void* B;            // [kz][ky][x - bx0], column stride bs
+  long long bx0, bs;
   void* A;                  // out [x][kz][y]
   const void* tw;
   int nkz;
   int xt0, nxt;
+};
+
+// inverse z pass fused with the fold onto the unit cell (amplitude gradients)
+struct ZFoldArgs {
+  const void* A;            // [x][kz][y] (r2c half spectra)
+  const void* tw;
+  Level L;
+  MaskP m;
+  int nkz;
+  int xlo, xhi;             // planes holding particle voxels
+  int ntiles;               // y tiles per plane
+  double scale;
+  double* part;             // per block c^3 partial folds (c <= 16)
+  double* gcell;            // c^3 global accumulators (c > 16)
 };
 
 struct ZInvArgs {
@@ -154,6 +171,7 @@ hipError_t launch_pass_x_adj(int prec, int n, const XAdjArgs& a, int nblocks, hi
 hipError_t launch_pass_y_inv(int prec, int n, const YInvArgs& a, hipStream_t s);
 hipError_t launch_pass_z_inv(int prec, int n, int c2c, const ZInvArgs& a, hipStream_t s);
 hipError_t launch_fold(int prec, int n, const FoldArgs& a, int nblocks, hipStream_t s);
+hipError_t launch_pass_z_fold(int prec, int n, const ZFoldArgs& a, int nblocks, hipStream_t s);
 hipError_t launch_fold_reduce(int c3, const double* part, int nblk, double* gcell, hipStream_t s);
 hipError_t launch_grad_amp(int c, int n_atoms, const double* prof, const double* gcell, double* grad_amp, hipStream_t s);
 hipError_t launch_rho_generate(int prec, int n, const ZArgs& a, void* rho, hipStream_t s);
