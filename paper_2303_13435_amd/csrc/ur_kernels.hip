@@ -273,7 +273,7 @@ k_pass_z(ZArgs a) {
   const int q = threadIdx.x / G, g = threadIdx.x % G;
   cx<T>* s = sm + q * PS;
   cx<T> v[E];
-  double m1 = 0.0, m2 = 0.0;
+  double m2 = 0.0;                                       // sum of rho^2 (the finalize uses it)
 
   if (!C2C) {
     const long long yA = y0 + 2 * q, yB = yA + 1;
@@ -282,13 +282,27 @@ k_pass_z(ZArgs a) {
       pa.init(a, X, yA);
       pb.init(a, X, yB);
       if (!ZOOM) {
+        // the cell residue of z = b + r N/R0 does not depend on r when the
+        // cell edge divides N/R0: one cell load per pencil and butterfly
+        const bool one_load = ((N / R0) & pa.cmask) == 0;
 #pragma unroll
-        for (int i = 0; i < NB0; ++i)
+        for (int i = 0; i < NB0; ++i) {
+          const int b = g + Geo<N>::G * i;
+          if (one_load) {
+            const T ca = pa.row[(b + pa.zoff) & pa.cmask], cb = pb.row[(b + pb.zoff) & pb.cmask];
 #pragma unroll
-          for (int r = 0; r < R0; ++r) {
-            const int z = first_index<N>(g, i, r);
-            v[i * R0 + r] = mk(pa.value1(z), pb.value1(z));
+            for (int r = 0; r < R0; ++r) {
+              const int z = b + r * (N / R0);
+              v[i * R0 + r] = mk((z >= pa.zlo && z <= pa.zhi) ? ca : (T)0, (z >= pb.zlo && z <= pb.zhi) ? cb : (T)0);
+            }
+          } else {
+#pragma unroll
+            for (int r = 0; r < R0; ++r) {
+              const int z = b + r * (N / R0);
+              v[i * R0 + r] = mk(pa.value1(z), pb.value1(z));
+            }
           }
+        }
       } else {
 #pragma unroll
         for (int i = 0; i < NB0; ++i)
@@ -298,11 +312,11 @@ k_pass_z(ZArgs a) {
             v[i * R0 + r] = mk(pa.value_zoom(a, z), pb.value_zoom(a, z));
           }
       }
+      // sum of rho^2 of the two pencils (per pencil in the working precision)
+      T qa = (T)0, qb = (T)0;
 #pragma unroll
-      for (int e = 0; e < E; ++e) {
-        m1 += (double)v[e].x + (double)v[e].y;
-        m2 += (double)v[e].x * v[e].x + (double)v[e].y * v[e].y;
-      }
+      for (int e = 0; e < E; ++e) { qa += v[e].x * v[e].x; qb += v[e].y * v[e].y; }
+      m2 += (double)qa + (double)qb;
     } else {
       const T* rho = (const T*)a.rho + ((size_t)(X - a.rho_x0) * N) * N;
 #pragma unroll
@@ -312,7 +326,6 @@ k_pass_z(ZArgs a) {
           int z = first_index<N>(g, i, r);
           T ra = rho[(size_t)yA * N + z], rb = rho[(size_t)yB * N + z];
           v[i * R0 + r] = mk(ra, rb);
-          m1 += (double)ra + (double)rb;
           m2 += (double)ra * ra + (double)rb * rb;
         }
     }
@@ -328,7 +341,6 @@ k_pass_z(ZArgs a) {
           const int z = first_index<N>(g, i, r);
           const T ra = ZOOM ? p.value_zoom(a, z) : p.value1(z);
           v[i * R0 + r] = mk(ra, (T)0);
-          m1 += (double)ra;
           m2 += (double)ra * ra;
         }
     } else {
@@ -340,7 +352,6 @@ k_pass_z(ZArgs a) {
           int z = first_index<N>(g, i, r);
           cx<T> e = rho[(size_t)y * N + z];
           v[i * R0 + r] = e;
-          m1 += (double)e.x;
           m2 += (double)e.x * e.x + (double)e.y * e.y;
         }
     }
@@ -350,9 +361,8 @@ k_pass_z(ZArgs a) {
 
   if (a.mom) {
     constexpr int W = C::threads < 64 ? C::threads : 64;
-    m1 = wave_sum<W>(m1);
     m2 = wave_sum<W>(m2);
-    if ((threadIdx.x & 63) == 0) { red[2 * (threadIdx.x >> 6)] = m1; red[2 * (threadIdx.x >> 6) + 1] = m2; }
+    if ((threadIdx.x & 63) == 0) { red[2 * (threadIdx.x >> 6)] = 0.0; red[2 * (threadIdx.x >> 6) + 1] = m2; }
   }
   __syncthreads();
   if (a.mom && threadIdx.x == 0) {
@@ -363,23 +373,38 @@ k_pass_z(ZArgs a) {
   }
 
   cx<T>* Ap = A + ((size_t)(X - a.ax0) * a.nkz) * N + y0;
-  if (!C2C) {
+  // each thread keeps one tile column j and walks kz with a fixed stride
+  // (needs at least one thread per column: KS >= 1)
+  constexpr int KS = C::threads / TY;
+  const int j = threadIdx.x % TY;
+  if constexpr (KS < 1 || C::threads % TY != 0) {
+    constexpr int NK = C2C ? N : N / 2 + 1;
+    for (int idx = threadIdx.x; idx < TY * NK; idx += C::threads) {
+      const int jj = idx % TY, kz = idx / TY;
+      if (!C2C) {
+        const cx<T>* col = sm + (jj >> 1) * PS;
+        const cx<T> zk = col[pad(kz)], zm = col[pad((N - kz) & (N - 1))];
+        Ap[(size_t)kz * N + jj] = (jj & 1) ? mk((zk.y + zm.y) * (T)0.5, (zm.x - zk.x) * (T)0.5)
+                                           : mk((zk.x + zm.x) * (T)0.5, (zk.y - zm.y) * (T)0.5);
+      } else {
+        Ap[(size_t)kz * N + jj] = sm[jj * PS + pad(kz)];
+      }
+    }
+  } else if (!C2C) {
     // unpack the two real transforms: A_k = (Z_k + conj Z_{N-k}) / 2,
     // B_k = (Z_k - conj Z_{N-k}) / (2i), k in [0, N/2]
-    for (int idx = threadIdx.x; idx < TY * (N / 2 + 1); idx += C::threads) {
-      const int j = idx % TY, kz = idx / TY;
-      const cx<T>* col = sm + (j >> 1) * PS;
+    const cx<T>* col = sm + (j >> 1) * PS;
+    const bool second = (j & 1) != 0;
+    cx<T>* dst = Ap + (size_t)(threadIdx.x / TY) * N + j;
+    for (int kz = threadIdx.x / TY; kz <= N / 2; kz += KS, dst += (size_t)KS * N) {
       const cx<T> zk = col[pad(kz)], zm = col[pad((N - kz) & (N - 1))];
-      cx<T> o;
-      if ((j & 1) == 0) o = mk((zk.x + zm.x) * (T)0.5, (zk.y - zm.y) * (T)0.5);
-      else              o = mk((zk.y + zm.y) * (T)0.5, (zm.x - zk.x) * (T)0.5);
-      Ap[(size_t)kz * N + j] = o;
+      *dst = second ? mk((zk.y + zm.y) * (T)0.5, (zm.x - zk.x) * (T)0.5)
+                    : mk((zk.x + zm.x) * (T)0.5, (zk.y - zm.y) * (T)0.5);
     }
   } else {
-    for (int idx = threadIdx.x; idx < TY * N; idx += C::threads) {
-      const int j = idx % TY, kz = idx / TY;
-      Ap[(size_t)kz * N + j] = sm[j * PS + pad(kz)];
-    }
+    const cx<T>* col = sm + j * PS;
+    cx<T>* dst = Ap + (size_t)(threadIdx.x / TY) * N + j;
+    for (int kz = threadIdx.x / TY; kz < N; kz += KS, dst += (size_t)KS * N) *dst = col[pad(kz)];
   }
 }
 
@@ -455,15 +480,37 @@ k_pass_y(YArgs a) {
   }
   __syncthreads();
   cx<T>* Bp = (cx<T>*)a.B + ((size_t)kz * N) * a.bs + (xbase - a.bx0);
+  constexpr int RS = C::threads / TX;                      // rows per pass of the block
+  if constexpr (G % 16 == 0 && RS % 16 == 0 && (G * TX) % C::threads == 0) {
+    // thread = (plane j, row r0 + k RS of the chunk): one LDS base and one
+    // global base per thread, compile-time offsets per (chunk, k)
+    const int j = threadIdx.x % TX, r0 = threadIdx.x / TX;
+    const bool from_stg = j < NS;
+    const cx<T>* src = from_stg ? stg + r0 * SS + j : sm + (j - NS) * PS + pad(r0);
+    cx<T>* dst = Bp + (size_t)r0 * a.bs + j;
+    const size_t rstride = (size_t)a.bs;
 #pragma unroll
-  for (int t = 0; t < E; ++t) {
-    stg[g * SS + q] = keep[t];                             // row ky = g + G t, plane q
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < G * TX; idx += C::threads) {
-      const int j = idx % TX, r = idx / TX, ky = G * t + r;
-      Bp[(size_t)ky * a.bs + j] = j < NS ? stg[r * SS + j] : sm[(j - NS) * PS + pad(ky)];
+    for (int t = 0; t < E; ++t) {
+      stg[g * SS + q] = keep[t];                           // row ky = g + G t, plane q
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < G / RS; ++k) {
+        const int off = from_stg ? k * RS * SS : t * (G + G / 16) + k * (RS + RS / 16);
+        dst[(size_t)(G * t + k * RS) * rstride] = src[off];
+      }
+      __syncthreads();
     }
-    __syncthreads();
+  } else {
+#pragma unroll
+    for (int t = 0; t < E; ++t) {
+      stg[g * SS + q] = keep[t];                           // row ky = g + G t, plane q
+      __syncthreads();
+      for (int idx = threadIdx.x; idx < G * TX; idx += C::threads) {
+        const int j = idx % TX, r = idx / TX, ky = G * t + r;
+        Bp[(size_t)ky * a.bs + j] = j < NS ? stg[r * SS + j] : sm[(j - NS) * PS + pad(ky)];
+      }
+      __syncthreads();
+    }
   }
 }
 
@@ -557,49 +604,57 @@ k_pass_x(XArgs a) {
     const double w = (a.r2c && kz != 0 && kz != N / 2) ? 2.0 : 1.0;
     const int base = k * k + l * l;
     // lane g owns |h| in [hlo, hlo + NH) (both signs), the last lane also
-    // |h| = N/2; NH consecutive |h| stay inside one 16-element LDS block
+    // |h| = N/2; NH consecutive |h| stay inside one 16-element LDS block.
+    // Within a run of equal bins, |X|^2 is summed in the working precision
+    // (at most 2 NH + 1 terms) and |X|^4 in FP64; the scale 1/n^6 of eq. 1
+    // and the conjugate weight w are applied once per run.
     constexpr int NH = G == 1 ? N / 2 : E / 2;
     const int hlo = G == 1 ? 0 : g * NH;
     int b = bin_search(U, a.nbins, (long long)hlo * hlo + base);
     int nextU = U[b + 1];
     int cb = b;
-    double cs = 0.0, cs2 = 0.0;
+    T cs = (T)0, ct = (T)0;
+    double cs2 = 0.0;
+    const double ws = w * a.iscale, ws2 = w * a.iscale * a.iscale;
     const cx<T>* sp = s + pad(hlo);
-    auto take = [&](int ha, double I1, double I2) {
+    auto take = [&](int ha, T q1, T q2) {
       const int n2 = ha * ha + base;
       if (n2 >= nextU) {
         if (cb >= 0 && cb < a.nbins) {
-          atomicAdd(&hist[2 * cb + 0], cs);
-          atomicAdd(&hist[2 * cb + 1], cs2);
+          atomicAdd(&hist[2 * cb + 0], (double)cs * ws);
+          atomicAdd(&hist[2 * cb + 1], cs2 * ws2);
         }
-        cs = cs2 = 0.0;
+        ct += cs;
+        cs = (T)0;
+        cs2 = 0.0;
         do { ++b; nextU = U[b + 1]; } while (n2 >= nextU);
         cb = b;
       }
-      cs += w * (I1 + I2);
-      cs2 += w * (I1 * I1 + I2 * I2);
-      tot += w * (I1 + I2);
+      const double d1 = (double)q1, d2 = (double)q2;
+      cs += q1 + q2;
+      cs2 += d1 * d1 + d2 * d2;
     };
 #pragma unroll
     for (int t = 0; t < NH; ++t) {
       const int ha = hlo + t;
       const cx<T> f1 = (NH <= 16 || G == 1) ? sp[t + (G == 1 ? (t >> 4) : 0)] : s[pad(ha)];
-      const double I1 = ((double)f1.x * f1.x + (double)f1.y * f1.y) * a.iscale;
-      double I2 = 0.0;
+      const T q1 = f1.x * f1.x + f1.y * f1.y;
+      T q2 = (T)0;
       if (ha != 0) {
         const cx<T> f2 = s[pad(N - ha)];
-        I2 = ((double)f2.x * f2.x + (double)f2.y * f2.y) * a.iscale;
+        q2 = f2.x * f2.x + f2.y * f2.y;
       }
-      take(ha, I1, I2);
+      take(ha, q1, q2);
     }
     if (g == G - 1) {                                      // |h| = N/2 (kx = N/2 only)
       const cx<T> f1 = s[pad(N / 2)];
-      take(N / 2, ((double)f1.x * f1.x + (double)f1.y * f1.y) * a.iscale, 0.0);
+      take(N / 2, f1.x * f1.x + f1.y * f1.y, (T)0);
     }
     if (cb >= 0 && cb < a.nbins) {
-      atomicAdd(&hist[2 * cb + 0], cs);
-      atomicAdd(&hist[2 * cb + 1], cs2);
+      atomicAdd(&hist[2 * cb + 0], (double)cs * ws);
+      atomicAdd(&hist[2 * cb + 1], cs2 * ws2);
     }
+    tot += (double)(ct + cs) * ws;
     if (col == 0 && g == 0 && a.f0) {
       const cx<T> f = s[pad(0)];
       a.f0[0] = (double)f.x * sqrt(a.iscale);
