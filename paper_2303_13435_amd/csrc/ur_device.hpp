@@ -13,6 +13,8 @@
 namespace ur {
 
 template <typename T> struct cx { T x, y; };
+// two adjacent complex values, aligned for one wide store
+template <typename T> struct alignas(4 * sizeof(T)) cx2 { cx<T> a, b; };
 
 template <typename T> __device__ __forceinline__ cx<T> mk(T a, T b) { cx<T> r; r.x = a; r.y = b; return r; }
 template <typename T> __device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) { return mk(a.x + b.x, a.y + b.y); }

@@ -73,7 +73,7 @@ __host__ __device__ inline void block_dist(const Level& L, long long X, long lon
 }
 
 __host__ __device__ inline bool in_region(const Level& L, long long X) {
-  return X >= L.o && X < L.o + L.n1 / L.f;
+  return X >= L.o && X < L.o + (L.f == 1 ? L.n1 : L.n1 / L.f);
 }
 
 // coarse index range [*lo, *hi] of the fine interval [h - r, h + r]
@@ -82,8 +82,13 @@ __host__ __device__ inline void coarse_range(const Level& L, long long r, long l
   long long a = L.h - r, b = L.h + r;
   if (a < 0) a = 0;
   if (b > L.n1 - 1) b = L.n1 - 1;
-  lo = a / L.f + L.o;
-  hi = b / L.f + L.o;
+  if (L.f == 1) {                          // ED-1: no division
+    lo = a + L.o;
+    hi = b + L.o;
+  } else {
+    lo = a / L.f + L.o;
+    hi = b / L.f + L.o;
+  }
 }
 
 // planes X that can hold density

@@ -270,7 +270,10 @@ k_pass_z(ZArgs a) {
       return;
     }
   }
-  const int q = threadIdx.x / G, g = threadIdx.x % G;
+  // with one group per wavefront the pencil index is wave-uniform: the
+  // pencil set-up (integer geometry) then runs on the scalar unit
+  const int q = G == 64 ? __builtin_amdgcn_readfirstlane(threadIdx.x / G) : threadIdx.x / G;
+  const int g = threadIdx.x % G;
   cx<T>* s = sm + q * PS;
   cx<T> v[E];
   double m2 = 0.0;                                       // sum of rho^2 (the finalize uses it)
@@ -391,15 +394,19 @@ k_pass_z(ZArgs a) {
       }
     }
   } else if (!C2C) {
-    // unpack the two real transforms: A_k = (Z_k + conj Z_{N-k}) / 2,
-    // B_k = (Z_k - conj Z_{N-k}) / (2i), k in [0, N/2]
-    const cx<T>* col = sm + (j >> 1) * PS;
-    const bool second = (j & 1) != 0;
-    cx<T>* dst = Ap + (size_t)(threadIdx.x / TY) * N + j;
-    for (int kz = threadIdx.x / TY; kz <= N / 2; kz += KS, dst += (size_t)KS * N) {
+    // unpack the two real transforms of column p: A_k = (Z_k + conj Z_{N-k}) / 2
+    // to tile column 2p, B_k = (Z_k - conj Z_{N-k}) / (2i) to column 2p + 1,
+    // k in [0, N/2]; one thread writes both (adjacent) outputs
+    constexpr int KP = C::threads / NG;                 // kz stride (>= 1: threads = NG G)
+    const int p = threadIdx.x % NG;
+    const cx<T>* col = sm + p * PS;
+    cx2<T>* dst = (cx2<T>*)(Ap + (size_t)(threadIdx.x / NG) * N + 2 * p);
+    for (int kz = threadIdx.x / NG; kz <= N / 2; kz += KP, dst += (size_t)KP * N / 2) {
       const cx<T> zk = col[pad(kz)], zm = col[pad((N - kz) & (N - 1))];
-      *dst = second ? mk((zk.y + zm.y) * (T)0.5, (zm.x - zk.x) * (T)0.5)
-                    : mk((zk.x + zm.x) * (T)0.5, (zk.y - zm.y) * (T)0.5);
+      cx2<T> o;
+      o.a = mk((zk.x + zm.x) * (T)0.5, (zk.y - zm.y) * (T)0.5);
+      o.b = mk((zk.y + zm.y) * (T)0.5, (zm.x - zk.x) * (T)0.5);
+      *dst = o;
     }
   } else {
     const cx<T>* col = sm + j * PS;
