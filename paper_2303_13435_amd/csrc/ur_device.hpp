@@ -9,6 +9,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <type_traits>
 
 namespace ur {
 
@@ -24,6 +25,17 @@ template <typename T> __device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) { 
 template <typename T> __device__ __forceinline__ cx<T> cmulc(cx<T> a, cx<T> b) { return mk(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y); }
 template <typename T> __device__ __forceinline__ cx<T> conjg(cx<T> a) { return mk(a.x, -a.y); }
 template <typename T> __device__ __forceinline__ cx<T> scale(cx<T> a, T s) { return mk(a.x * s, a.y * s); }
+
+// Compile-time loop: f(std::integral_constant<int, I>) for I in [I0, I1).
+// Guarantees constant indices into register arrays whatever the unroller
+// decides for a large body.
+template <int I0, int I1, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (I0 < I1) {
+    f(std::integral_constant<int, I0>{});
+    static_for<I0 + 1, I1>(f);
+  }
+}
 
 // LDS ordering between the lanes of one wavefront: the fences keep the
 // compiler (and the memory model) from moving LDS accesses across the point.

@@ -129,16 +129,34 @@ __global__ void k_cell_tables(int c, int f, const double* __restrict__ cell, T* 
       pr[0] = 0.0;
       for (int k = 0; k < c; ++k) { s += row[k]; pr[k + 1] = s; }
     }
-    long long nb = (long long)cbn * cbn * cbn;
-    if (t < nb) {
-      int K = (int)(t % cbn), J = (int)((t / cbn) % cbn), I = (int)(t / ((long long)cbn * cbn));
-      double s = 0.0;
-      for (int a = 0; a < f; ++a)
-        for (int b = 0; b < f; ++b)
-          for (int d = 0; d < f; ++d)
-            s += cell[((size_t)((I * f + a) % c) * c + (size_t)((J * f + b) % c)) * c + (size_t)((K * f + d) % c)];
-      cb[t] = (T)s;
-    }
+  }
+}
+
+// Block table of a zoomed level: cb[I][J][K] = sum of the cell over the
+// fe^3 voxels from (I fe, J fe, K fe), fe = min(f, c), times (f/fe)^3 (a block
+// larger than the cell holds (f/c)^3 whole cells).  One workgroup per entry,
+// fixed-order tree reduction.
+template <typename T>
+__global__ void __launch_bounds__(256) k_cell_blocks(int c, int f, const double* __restrict__ cell, T* __restrict__ cb, int cbn) {
+  __shared__ double red[256];
+  const int t = blockIdx.x;
+  const int K = t % cbn, J = (t / cbn) % cbn, I = t / (cbn * cbn);
+  const int fe = f < c ? f : c;
+  const int ne = fe * fe * fe;
+  double s = 0.0;
+  for (int e = threadIdx.x; e < ne; e += 256) {
+    const int d = e % fe, b = (e / fe) % fe, aa = e / (fe * fe);
+    s += cell[((size_t)(I * fe + aa) * c + (J * fe + b)) * c + (K * fe + d)];
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double m = (double)(f / fe);
+    cb[t] = (T)(red[0] * (m * m * m));
   }
 }
 
@@ -158,6 +176,7 @@ struct Pencil {
   long long rin;            // blocks with max|dz| <= rin are fully inside
   int I, J;                 // block-table indices of this pencil
   long long fx0, fy0;       // first fine x, y of the pencil's block column
+  int zin_lo, zin_hi;       // coarse z of the blocks wholly inside the mask
 
   __device__ __forceinline__ void init(const ZArgs& a, long long X, long long Y) {
     const Level& L = a.L;
@@ -184,7 +203,33 @@ struct Pencil {
       } else {
         I = J = 0;
       }
+      // block Z is wholly inside iff its fine z range [f(Z-o), f(Z-o)+f-1]
+      // lies in [h - rin, h + rin]; f is a power of two (floor division by
+      // an arithmetic shift)
+      zin_lo = 1; zin_hi = 0;
+      if (rin >= 0 && zlo <= zhi) {
+        const int lf = __builtin_ctz(L.f);
+        const long long lo2 = -((-(L.h - rin)) >> lf) + L.o;       // ceil((h - rin) / f) + o
+        const long long hi2 = ((L.h + rin - L.f + 1) >> lf) + L.o;  // floor((h + rin - f + 1) / f) + o
+        zin_lo = (int)(lo2 > zlo ? lo2 : zlo);
+        zin_hi = (int)(hi2 < zhi ? hi2 : zhi);
+      }
     }
+  }
+
+  // zoomed level, all but the boundary blocks: the block table for blocks
+  // wholly inside, zero outside [zlo, zhi]; *bnd flags a block that is
+  // partly inside (its value is left to the caller)
+  __device__ __forceinline__ T zoom_fast(const ZArgs& a, int Z, bool& bnd) const {
+    bnd = false;
+    if (Z < zlo || Z > zhi) return (T)0;
+    if (Z >= zin_lo && Z <= zin_hi) {
+      const Level& L = a.L;
+      const int K = L.f <= L.c ? (((L.f * (Z - L.o) - L.h) & (L.c - 1)) >> __builtin_ctz(L.f)) : 0;
+      return ((const T*)a.cb)[((size_t)I * a.cbn + J) * a.cbn + K];
+    }
+    bnd = true;
+    return (T)0;
   }
 
   // ED-1 voxel (factor 1): tiled cell inside the mask, exact integer test
@@ -240,6 +285,34 @@ struct Pencil {
     return a.L.f == 1 ? value1((int)Z) : value_zoom(a, Z);
   }
 };
+
+// Sum of ED-1 over the inside fine voxels of one zoom block whose fine
+// corner is (fx0, fy0, fz0), evaluated by all 64 lanes of the wavefront
+// together: lane l takes the fine pencils k = l, l + 64, ... of the f^2 in the
+// block, each an O(1) prefix-sum difference over its inside z segment; the
+// result is returned to every lane.  Cell edge c and factor f are powers of two.
+__device__ __forceinline__ double zoom_block_sum(const ZArgs& a, int fx0, int fy0, int fz0) {
+  const Level& L = a.L;
+  const int f = L.f, c = L.c, h = L.h, lf = __builtin_ctz(f), lc = __builtin_ctz(c);
+  double s = 0.0;
+  for (int k = __lane_id(); k < f * f; k += 64) {
+    const int fx = fx0 + (k >> lf), fy = fy0 + (k & (f - 1));
+    const long long r = mask_reach(a.m, fx < h ? h - fx : fx - h, fy < h ? h - fy : fy - h);
+    if (r < 0) continue;
+    const long long za = fz0 > h - r ? fz0 : h - r;
+    const long long zb = fz0 + f - 1 < h + r ? fz0 + f - 1 : h + r;
+    if (za > zb) continue;
+    const double* P = a.pre + ((size_t)((fx - h) & (c - 1)) * c + ((fy - h) & (c - 1))) * (c + 1);
+    const int ka = (int)((za - h) & (c - 1));
+    const long long len = zb - za + 1;
+    const int rem = (int)(len & (c - 1));
+    double t = (double)(len >> lc) * P[c];
+    if (ka + rem <= c) t += P[ka + rem] - P[ka];
+    else t += (P[c] - P[ka]) + P[ka + rem - c];
+    s += t;
+  }
+  return wave_sum<64>(s);
+}
 
 // ---------------------------------------------------------------------------
 // pass Z: density -> 1D transform along z -> A[x][kz][y]
@@ -306,6 +379,31 @@ k_pass_z(ZArgs a) {
             }
           }
         }
+      } else if constexpr (C::threads % 64 == 0) {
+        // table lookups per lane; each block that is only partly inside is
+        // summed by the whole wavefront (ballot, then one block at a time)
+        const int lane = __lane_id();
+#pragma unroll
+        for (int i = 0; i < NB0; ++i)
+#pragma unroll
+          for (int r = 0; r < R0; ++r) {
+            const int z = first_index<N>(g, i, r);
+            bool ba, bb;
+            T va = pa.zoom_fast(a, z, ba), vb = pb.zoom_fast(a, z, bb);
+            for (unsigned long long m = __ballot(ba); m; m &= m - 1) {
+              const int l = __builtin_ctzll(m);
+              const double t = zoom_block_sum(a, __builtin_amdgcn_readlane((int)pa.fx0, l), __builtin_amdgcn_readlane((int)pa.fy0, l),
+                                              a.L.f * (__builtin_amdgcn_readlane(z, l) - a.L.o));
+              if (lane == l) va = (T)t;
+            }
+            for (unsigned long long m = __ballot(bb); m; m &= m - 1) {
+              const int l = __builtin_ctzll(m);
+              const double t = zoom_block_sum(a, __builtin_amdgcn_readlane((int)pb.fx0, l), __builtin_amdgcn_readlane((int)pb.fy0, l),
+                                              a.L.f * (__builtin_amdgcn_readlane(z, l) - a.L.o));
+              if (lane == l) vb = (T)t;
+            }
+            v[i * R0 + r] = mk(va, vb);
+          }
       } else {
 #pragma unroll
         for (int i = 0; i < NB0; ++i)
@@ -342,7 +440,20 @@ k_pass_z(ZArgs a) {
 #pragma unroll
         for (int r = 0; r < R0; ++r) {
           const int z = first_index<N>(g, i, r);
-          const T ra = ZOOM ? p.value_zoom(a, z) : p.value1(z);
+          T ra;
+          if constexpr (ZOOM && C::threads % 64 == 0) {
+            bool bd;
+            ra = p.zoom_fast(a, z, bd);
+            const int lane = __lane_id();
+            for (unsigned long long m = __ballot(bd); m; m &= m - 1) {
+              const int l = __builtin_ctzll(m);
+              const double t = zoom_block_sum(a, __builtin_amdgcn_readlane((int)p.fx0, l), __builtin_amdgcn_readlane((int)p.fy0, l),
+                                              a.L.f * (__builtin_amdgcn_readlane(z, l) - a.L.o));
+              if (lane == l) ra = (T)t;
+            }
+          } else {
+            ra = ZOOM ? p.value_zoom(a, z) : p.value1(z);
+          }
           v[i * R0 + r] = mk(ra, (T)0);
           m2 += (double)ra * ra;
         }
@@ -434,6 +545,47 @@ __global__ void __launch_bounds__(256) k_rho_generate(ZArgs a, int n, T* __restr
 // columns are needed and two blocks fit a CU; the transposed write leaves in
 // chunks of G rows, every row a TX-element (128-byte) segment.
 // ---------------------------------------------------------------------------
+// Zero-extended column loads for one column per wavefront (G = 64), where
+// the column address is wave-uniform: a raw buffer resource whose size ends
+// at the last valid element makes the hardware return zero beyond it, and
+// lanes below the first valid element use offset 2^31, which is always out
+// of range.  Offsets are never negative, so a constant part folded into the
+// instruction offset cannot wrap.  No branch, no masked load.
+constexpr unsigned kOutOfRange = 0x80000000u;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t column_rsrc(const void* base, int bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, bytes, 0x00020000);
+}
+
+template <typename T>
+__device__ __forceinline__ cx<T> column_ld(__amdgpu_buffer_rsrc_t rs, unsigned off) {
+  if constexpr (sizeof(T) == 4) return __builtin_bit_cast(cx<T>, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)off, 0, 0));
+  else return __builtin_bit_cast(cx<T>, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off, 0, 0));
+}
+
+// v[i R0 + r] = col[p] for p = g + G i + r N/R0 inside [lo, hi], zero elsewhere
+// (col points at element 0; lo, hi and col are wave-uniform)
+template <typename T, int N>
+__device__ __forceinline__ void load_column_u(const cx<T>* col, int lo, int hi, int g, cx<T>* v) {
+  constexpr int G = Geo<N>::G, E = Geo<N>::E, R0 = Radix<N, 1>::r, NB0 = E / R0;
+  constexpr unsigned SZ = sizeof(cx<T>);
+  const __amdgpu_buffer_rsrc_t rs = column_rsrc(col, lo <= hi ? (hi + 1) * (int)SZ : 0);
+  const unsigned gb = (unsigned)g * SZ;
+#pragma unroll
+  for (int i = 0; i < NB0; ++i)
+#pragma unroll
+    for (int r = 0; r < R0; ++r) {
+      const int c = G * i + r * (N / R0);                // compile-time displacement
+      if (c + G - 1 < lo || c > hi) {                      // wave-uniform: no load at all
+        v[i * R0 + r] = mk((T)0, (T)0);
+      } else {
+        unsigned o = g >= lo - c ? gb : kOutOfRange;
+        asm("" : "+v"(o));   // keeps the constant out of the select: it becomes the instruction offset
+        v[i * R0 + r] = column_ld<T>(rs, o + (unsigned)c * SZ);
+      }
+    }
+}
+
 template <typename T, int N>
 __device__ __forceinline__ void y_load_column(const YArgs& a, long long X, int kz, int g, cx<T>* v) {
   constexpr int G = Geo<N>::G, E = Geo<N>::E, R0 = Radix<N, 1>::r, NB0 = E / R0;
@@ -441,16 +593,22 @@ __device__ __forceinline__ void y_load_column(const YArgs& a, long long X, int k
   if (X < a.xlo || X > a.xhi) { ylo = 1; yhi = 0; }
   else if (a.gen) {
     row_range(a.L, a.m, X, ylo, yhi);
-    if (ylo <= yhi) { ylo = (ylo / a.ty) * a.ty; yhi = (yhi / a.ty) * a.ty + a.ty - 1; }
+    // widen to whole z-pass tiles (the tile height is a power of two)
+    if (ylo <= yhi) { ylo &= ~(long long)(a.ty - 1); yhi |= (long long)(a.ty - 1); }
   }
   const cx<T>* col = (const cx<T>*)a.A + ((size_t)(X - a.ax0) * a.nkz + kz) * N;
+  if constexpr (G == 64) {
+    load_column_u<T, N>(col, (int)ylo, (int)yhi, g, v);
+  } else {
+    const int lo = (int)ylo, hi = (int)yhi;
 #pragma unroll
-  for (int i = 0; i < NB0; ++i)
+    for (int i = 0; i < NB0; ++i)
 #pragma unroll
-    for (int r = 0; r < R0; ++r) {
-      const int y = first_index<N>(g, i, r);
-      v[i * R0 + r] = (y >= ylo && y <= yhi) ? col[y] : mk((T)0, (T)0);
-    }
+      for (int r = 0; r < R0; ++r) {
+        const int y = first_index<N>(g, i, r);
+        v[i * R0 + r] = (y >= lo && y <= hi) ? col[y] : mk((T)0, (T)0);
+      }
+  }
 }
 
 template <typename T, int N>
@@ -465,7 +623,10 @@ k_pass_y(YArgs a) {
   const int kz = blockIdx.x % a.nkz;
   const int xt = a.xt0 + blockIdx.x / a.nkz;
   const int xbase = xt * TX;
-  const int q = threadIdx.x / G, g = threadIdx.x % G;
+  // one group per wavefront: the plane index is wave-uniform and the row
+  // range of the plane is computed on the scalar unit
+  const int q = G == 64 ? __builtin_amdgcn_readfirstlane(threadIdx.x / G) : threadIdx.x / G;
+  const int g = threadIdx.x % G;
   const cx<T>* tw = (const cx<T>*)a.tw;
   cx<T>* s = sm + q * PS;
   cx<T> keep[E];
@@ -494,22 +655,23 @@ k_pass_y(YArgs a) {
     const int j = threadIdx.x % TX, r0 = threadIdx.x / TX;
     const bool from_stg = j < NS;
     const cx<T>* src = from_stg ? stg + r0 * SS + j : sm + (j - NS) * PS + pad(r0);
+    // rows G t + k RS are visited in increasing order: one running pointer
     cx<T>* dst = Bp + (size_t)r0 * a.bs + j;
-    const size_t rstride = (size_t)a.bs;
-#pragma unroll
-    for (int t = 0; t < E; ++t) {
+    const size_t rstep = (size_t)RS * a.bs;
+    static_for<0, E>([&](auto tc) {
+      constexpr int t = decltype(tc)::value;
       stg[g * SS + q] = keep[t];                           // row ky = g + G t, plane q
       __syncthreads();
 #pragma unroll
-      for (int k = 0; k < G / RS; ++k) {
+      for (int k = 0; k < G / RS; ++k, dst += rstep) {
         const int off = from_stg ? k * RS * SS : t * (G + G / 16) + k * (RS + RS / 16);
-        dst[(size_t)(G * t + k * RS) * rstride] = src[off];
+        *dst = src[off];
       }
       __syncthreads();
-    }
+    });
   } else {
-#pragma unroll
-    for (int t = 0; t < E; ++t) {
+    static_for<0, E>([&](auto tc) {
+      constexpr int t = decltype(tc)::value;
       stg[g * SS + q] = keep[t];                           // row ky = g + G t, plane q
       __syncthreads();
       for (int idx = threadIdx.x; idx < G * TX; idx += C::threads) {
@@ -517,7 +679,7 @@ k_pass_y(YArgs a) {
         Bp[(size_t)ky * a.bs + j] = j < NS ? stg[r * SS + j] : sm[(j - NS) * PS + pad(ky)];
       }
       __syncthreads();
-    }
+    });
   }
 }
 
@@ -550,15 +712,19 @@ __device__ __forceinline__ int bin_advance(const int* U, int nbins, int b, long 
 // ---------------------------------------------------------------------------
 template <typename T, int N>
 __device__ __forceinline__ void x_load_column(const XArgs& a, long long col, int g, cx<T>* v) {
-  constexpr int E = Geo<N>::E, R0 = Radix<N, 1>::r, NB0 = E / R0;
-  const cx<T>* src = (const cx<T>*)a.B + (size_t)col * a.bs - a.bx0;
+  constexpr int G = Geo<N>::G, E = Geo<N>::E, R0 = Radix<N, 1>::r, NB0 = E / R0;
+  const cx<T>* src = (const cx<T>*)a.B + (size_t)col * a.bs - a.bx0;   // element x = 0
+  if constexpr (G == 64) {
+    load_column_u<T, N>(src, a.xa, a.xb, g, v);
+  } else {
 #pragma unroll
-  for (int i = 0; i < NB0; ++i)
+    for (int i = 0; i < NB0; ++i)
 #pragma unroll
-    for (int r = 0; r < R0; ++r) {
-      const int x = first_index<N>(g, i, r);
-      v[i * R0 + r] = (x >= a.xa && x <= a.xb) ? src[x] : mk((T)0, (T)0);
-    }
+      for (int r = 0; r < R0; ++r) {
+        const int x = first_index<N>(g, i, r);
+        v[i * R0 + r] = (x >= a.xa && x <= a.xb) ? src[x] : mk((T)0, (T)0);
+      }
+  }
 }
 
 template <typename T, int N, int MODE, int DIR>
@@ -572,7 +738,9 @@ k_pass_x(XArgs a) {
   double* tot_s = dyn + 2 * (size_t)a.nbins;
   int* U = (int*)(dyn + 2 * (size_t)a.nbins + 1);      // nbins + 2 (last: sentinel)
 
-  const int q = threadIdx.x / G, g = threadIdx.x % G;
+  // one column per wavefront for G = 64: wave-uniform column index
+  const int q = G == 64 ? __builtin_amdgcn_readfirstlane(threadIdx.x / G) : threadIdx.x / G;
+  const int g = threadIdx.x % G;
   cx<T>* s = sm + q * PS;
   const cx<T>* tw = (const cx<T>*)a.tw;
   constexpr bool BIN = MODE != X_FFT_STORE;
@@ -1212,14 +1380,18 @@ hipError_t launch_cell_sum(int c, int n_atoms, const double* amp, const double* 
 }
 
 hipError_t launch_cell_tables(int prec, int c, int f, const double* cell, void* cellT, double* pre, void* cb, int cbn, hipStream_t s) {
-  long long c3 = (long long)c * c * c;
-  long long nb = (long long)cbn * cbn * cbn;
-  long long total = c3 > nb ? c3 : nb;
-  if ((long long)c * c > total) total = (long long)c * c;
+  const long long c3 = (long long)c * c * c;
+  const long long nb = (long long)cbn * cbn * cbn;
   if (prec == 0)
-    hipLaunchKernelGGL(k_cell_tables<float>, dim3(nblk_of(total, 256)), dim3(256), 0, s, c, f, cell, (float*)cellT, pre, (float*)cb, cbn);
+    hipLaunchKernelGGL(k_cell_tables<float>, dim3(nblk_of(c3, 256)), dim3(256), 0, s, c, f, cell, (float*)cellT, pre, (float*)cb, cbn);
   else
-    hipLaunchKernelGGL(k_cell_tables<double>, dim3(nblk_of(total, 256)), dim3(256), 0, s, c, f, cell, (double*)cellT, pre, (double*)cb, cbn);
+    hipLaunchKernelGGL(k_cell_tables<double>, dim3(nblk_of(c3, 256)), dim3(256), 0, s, c, f, cell, (double*)cellT, pre, (double*)cb, cbn);
+  if (f > 1) {
+    if (prec == 0)
+      hipLaunchKernelGGL(k_cell_blocks<float>, dim3((unsigned)nb), dim3(256), 0, s, c, f, cell, (float*)cb, cbn);
+    else
+      hipLaunchKernelGGL(k_cell_blocks<double>, dim3((unsigned)nb), dim3(256), 0, s, c, f, cell, (double*)cb, cbn);
+  }
   return hipGetLastError();
 }
 
