@@ -90,13 +90,23 @@ template <typename T, int DIR> struct DFT<T, 1, DIR> {
 __device__ __forceinline__ int pad(int i) { return i + (i >> 4); }
 template <int N> struct Padded { static constexpr int size = N + N / 16; };
 
-// Elements per lane for a length-N column; G = N / E lanes per column, G <= 64
-// so that a column never spans two wavefronts.
+// Elements per lane for a length-N column; G = N / E lanes per column.  Up to
+// N = 1024 a column sits in one wavefront (G <= 64); N = 2048 takes two whole
+// wavefronts (G = 128), with 16 elements per lane as at 1024.
 template <int N> struct Geo {
-  static constexpr int E = N <= 16 ? N : (N == 512 ? 8 : (N <= 1024 ? 16 : (N == 2048 ? 32 : 64)));
+  static constexpr int E = N <= 16 ? N : (N == 512 ? 8 : 16);
   static constexpr int G = N / E;
-  static_assert(G >= 1 && G <= 64, "column group must fit one wavefront");
+  static_assert(G >= 1 && (G <= 64 || G == 128), "column group: part of one wavefront or two whole ones");
 };
+
+// Ordering of the LDS accesses of the lanes that share a column: the
+// wavefront-level fence when the column lies in one wavefront, otherwise the
+// workgroup barrier (every thread of the block must then reach it).
+template <int G>
+__device__ __forceinline__ void col_sync() {
+  if constexpr (G <= 64) wave_sync();
+  else __syncthreads();
+}
 
 // radix of the stage with sub-transform length L: at most 16 and at most the
 // per-lane element count, so each lane runs whole butterflies
@@ -143,7 +153,7 @@ __device__ __forceinline__ void stage_lds(cx<T>* s, int g, const cx<T>* __restri
       for (int r = 0; r < R; ++r) v[i][r] = s[pad(g + G * i + r * NR)];
     }
   }
-  wave_sync();
+  col_sync<G>();
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
     const int b = g + G * i;
@@ -161,7 +171,7 @@ __device__ __forceinline__ void stage_lds(cx<T>* s, int g, const cx<T>* __restri
 #pragma unroll
     for (int r = 0; r < R; ++r) out[(r * L) + ((r * L) >> 4)] = v[i][r];
   }
-  wave_sync();
+  col_sync<G>();
 }
 
 template <typename T, int N, int L, int DIR>
@@ -187,7 +197,7 @@ __device__ __forceinline__ void fft_column(cx<T>* s, int g, const cx<T>* __restr
 #pragma unroll
     for (int r = 0; r < R; ++r) out[r] = v[i * R + r];
   }
-  wave_sync();
+  col_sync<G>();
   stages_from<T, N, R, DIR>(s, g, tw);
 }
 

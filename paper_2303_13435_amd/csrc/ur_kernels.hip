@@ -343,9 +343,9 @@ k_pass_z(ZArgs a) {
       return;
     }
   }
-  // with one group per wavefront the pencil index is wave-uniform: the
-  // pencil set-up (integer geometry) then runs on the scalar unit
-  const int q = G == 64 ? __builtin_amdgcn_readfirstlane(threadIdx.x / G) : threadIdx.x / G;
+  // with G >= 64 every wavefront lies inside one group, so the pencil index
+  // is wave-uniform: the pencil set-up (integer geometry) runs on the scalar unit
+  const int q = G >= 64 ? __builtin_amdgcn_readfirstlane(threadIdx.x / G) : threadIdx.x / G;
   const int g = threadIdx.x % G;
   cx<T>* s = sm + q * PS;
   cx<T> v[E];
@@ -545,7 +545,7 @@ __global__ void __launch_bounds__(256) k_rho_generate(ZArgs a, int n, T* __restr
 // columns are needed and two blocks fit a CU; the transposed write leaves in
 // chunks of G rows, every row a TX-element (128-byte) segment.
 // ---------------------------------------------------------------------------
-// Zero-extended column loads for one column per wavefront (G = 64), where
+// Zero-extended column loads when every wavefront lies in one column (G >= 64), where
 // the column address is wave-uniform: a raw buffer resource whose size ends
 // at the last valid element makes the hardware return zero beyond it, and
 // lanes below the first valid element use offset 2^31, which is always out
@@ -597,7 +597,7 @@ __device__ __forceinline__ void y_load_column(const YArgs& a, long long X, int k
     if (ylo <= yhi) { ylo &= ~(long long)(a.ty - 1); yhi |= (long long)(a.ty - 1); }
   }
   const cx<T>* col = (const cx<T>*)a.A + ((size_t)(X - a.ax0) * a.nkz + kz) * N;
-  if constexpr (G == 64) {
+  if constexpr (G >= 64) {
     load_column_u<T, N>(col, (int)ylo, (int)yhi, g, v);
   } else {
     const int lo = (int)ylo, hi = (int)yhi;
@@ -623,9 +623,9 @@ k_pass_y(YArgs a) {
   const int kz = blockIdx.x % a.nkz;
   const int xt = a.xt0 + blockIdx.x / a.nkz;
   const int xbase = xt * TX;
-  // one group per wavefront: the plane index is wave-uniform and the row
-  // range of the plane is computed on the scalar unit
-  const int q = G == 64 ? __builtin_amdgcn_readfirstlane(threadIdx.x / G) : threadIdx.x / G;
+  // G >= 64: every wavefront lies in one group, the plane index is
+  // wave-uniform and the row range of the plane is computed on the scalar unit
+  const int q = G >= 64 ? __builtin_amdgcn_readfirstlane(threadIdx.x / G) : threadIdx.x / G;
   const int g = threadIdx.x % G;
   const cx<T>* tw = (const cx<T>*)a.tw;
   cx<T>* s = sm + q * PS;
@@ -642,7 +642,7 @@ k_pass_y(YArgs a) {
 #pragma unroll
       for (int t = 0; t < E; ++t) keep[t] = s[pad(g + G * t)];
     }
-    wave_sync();
+    col_sync<G>();
     y_load_column<T, N>(a, xbase + NS + q, kz, g, v);
     fft_column<T, N, -1>(s, g, tw, v);
   }
@@ -714,7 +714,7 @@ template <typename T, int N>
 __device__ __forceinline__ void x_load_column(const XArgs& a, long long col, int g, cx<T>* v) {
   constexpr int G = Geo<N>::G, E = Geo<N>::E, R0 = Radix<N, 1>::r, NB0 = E / R0;
   const cx<T>* src = (const cx<T>*)a.B + (size_t)col * a.bs - a.bx0;   // element x = 0
-  if constexpr (G == 64) {
+  if constexpr (G >= 64) {
     load_column_u<T, N>(src, a.xa, a.xb, g, v);
   } else {
 #pragma unroll
@@ -738,8 +738,11 @@ k_pass_x(XArgs a) {
   double* tot_s = dyn + 2 * (size_t)a.nbins;
   int* U = (int*)(dyn + 2 * (size_t)a.nbins + 1);      // nbins + 2 (last: sentinel)
 
-  // one column per wavefront for G = 64: wave-uniform column index
-  const int q = G == 64 ? __builtin_amdgcn_readfirstlane(threadIdx.x / G) : threadIdx.x / G;
+  // G >= 64: every wavefront lies in one column, wave-uniform column index.
+  // For G > 64 the column syncs are workgroup barriers: the launcher makes
+  // the number of columns a multiple of NG, so every group of a block runs
+  // the same iterations.
+  const int q = G >= 64 ? __builtin_amdgcn_readfirstlane(threadIdx.x / G) : threadIdx.x / G;
   const int g = threadIdx.x % G;
   cx<T>* s = sm + q * PS;
   const cx<T>* tw = (const cx<T>*)a.tw;
@@ -761,7 +764,7 @@ k_pass_x(XArgs a) {
     if (MODE == X_BIN_ONLY) {
       const cx<T>* src = (const cx<T>*)a.B + (size_t)col * a.bs - a.bx0;
       for (int i = g; i < N; i += G) s[pad(i)] = (i >= a.xa && i <= a.xb) ? src[i] : mk((T)0, (T)0);
-      wave_sync();
+      col_sync<G>();
     } else {
       fft_column<T, N, DIR>(s, g, tw, v);
       if (col + stride < a.ncols) x_load_column<T, N>(a, col + stride, g, v);   // in flight during the binning
@@ -769,7 +772,7 @@ k_pass_x(XArgs a) {
     if (!BIN) {
       cx<T>* dst = (cx<T>*)a.out + (size_t)col * N;
       for (int i = g; i < N; i += G) dst[i] = scale(s[pad(i)], (T)a.oscale);
-      wave_sync();
+      col_sync<G>();
       continue;
     }
     // |F|^2 and bins. Lane g walks |h| over its own range in increasing
@@ -835,7 +838,7 @@ k_pass_x(XArgs a) {
       a.f0[0] = (double)f.x * sqrt(a.iscale);
       a.f0[1] = (double)f.y * sqrt(a.iscale);
     }
-    wave_sync();
+    col_sync<G>();
   }
   if (!BIN) return;
   tot = wave_sum(tot);
@@ -1080,10 +1083,10 @@ k_pass_x_adj(XAdjArgs a) {
         s[pad(N - ha)] = mk((T)(f2.x * gv), (T)(f2.y * gv));
       }
     }
-    wave_sync();
+    col_sync<G>();
     stages_from<T, N, 1, +1>(s, g, tw);
     for (int i = a.oa + g; i <= a.ob; i += G) src[i] = s[pad(i)];
-    wave_sync();
+    col_sync<G>();
   }
 }
 
@@ -1171,7 +1174,7 @@ k_pass_z_inv(ZInvArgs a) {
     for (int i = 0; i < NB0; ++i)
 #pragma unroll
       for (int r = 0; r < R0; ++r) v[i * R0 + r] = s[pad(first_index<N>(g, i, r))];
-    wave_sync();
+    col_sync<G>();
   }
   fft_column<T, N, +1>(s, g, (const cx<T>*)a.tw, v);
   const T sc = (T)a.scale;
@@ -1482,6 +1485,9 @@ hipError_t launch_bin_counts(int n, int nkz, int r2c, int nbins, const int* U, u
 template <typename T, int N>
 static hipError_t pass_x_t(int mode, int dir, const XArgs& a, int nblocks, hipStream_t s) {
   size_t shm = x_shm(mode, a.nbins);
+  // columns spanning several wavefronts sync with workgroup barriers: every
+  // group of a block must run the same number of iterations
+  if (XCfg<N>::G > 64 && a.ncols % XCfg<N>::NG != 0) return hipErrorInvalidValue;
   dim3 grid(nblocks), blk(XCfg<N>::threads);
   if (mode == X_FFT_BIN) hipLaunchKernelGGL((k_pass_x<T, N, X_FFT_BIN, -1>), grid, blk, shm, s, a);
   else if (mode == X_BIN_ONLY) hipLaunchKernelGGL((k_pass_x<T, N, X_BIN_ONLY, -1>), grid, blk, shm, s, a);
