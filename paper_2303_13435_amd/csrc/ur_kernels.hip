@@ -26,7 +26,10 @@ template <typename T> struct Seg { static constexpr int cols = 128 / (int)sizeof
 // z pass: groups per block (each group = one complex FFT = two real pencils in r2c)
 template <typename T, int N, bool C2C> struct ZCfg {
   static constexpr int G = Geo<N>::G;
-  static constexpr int want = C2C ? Seg<T>::cols : Seg<T>::cols / 2;
+  // 2048-point columns span two wavefronts and sync with the workgroup
+  // barrier: half-width tiles keep two blocks per CU (measured faster than
+  // one block of full 128-byte rows)
+  static constexpr int want = N == 2048 ? (C2C ? Seg<T>::cols / 2 : Seg<T>::cols / 4) : (C2C ? Seg<T>::cols : Seg<T>::cols / 2);
   static constexpr int fill = 256 / G > 0 ? 256 / G : 1;
   static constexpr int ng0 = want > fill ? want : fill;
   static constexpr int cap = C2C ? N : N / 2;
@@ -634,13 +637,15 @@ k_pass_y(YArgs a) {
     cx<T> v[E];
     y_load_column<T, N>(a, xbase + q, kz, g, v);
     fft_column<T, N, -1>(s, g, tw, v);
+    // component-wise copies: a whole-struct copy between LDS and the register
+    // array becomes a memory copy that keeps the FP64 array out of registers
     if constexpr (G % 16 == 0) {
       const cx<T>* kp = s + pad(g);
 #pragma unroll
-      for (int t = 0; t < E; ++t) keep[t] = kp[t * (G + G / 16)];   // rows g + G t
+      for (int t = 0; t < E; ++t) keep[t] = mk(kp[t * (G + G / 16)].x, kp[t * (G + G / 16)].y);   // rows g + G t
     } else {
 #pragma unroll
-      for (int t = 0; t < E; ++t) keep[t] = s[pad(g + G * t)];
+      for (int t = 0; t < E; ++t) keep[t] = mk(s[pad(g + G * t)].x, s[pad(g + G * t)].y);
     }
     col_sync<G>();
     y_load_column<T, N>(a, xbase + NS + q, kz, g, v);
@@ -660,7 +665,8 @@ k_pass_y(YArgs a) {
     const size_t rstep = (size_t)RS * a.bs;
     static_for<0, E>([&](auto tc) {
       constexpr int t = decltype(tc)::value;
-      stg[g * SS + q] = keep[t];                           // row ky = g + G t, plane q
+      stg[g * SS + q].x = keep[t].x;                       // row ky = g + G t, plane q
+      stg[g * SS + q].y = keep[t].y;
       __syncthreads();
 #pragma unroll
       for (int k = 0; k < G / RS; ++k, dst += rstep) {
@@ -672,7 +678,8 @@ k_pass_y(YArgs a) {
   } else {
     static_for<0, E>([&](auto tc) {
       constexpr int t = decltype(tc)::value;
-      stg[g * SS + q] = keep[t];                           // row ky = g + G t, plane q
+      stg[g * SS + q].x = keep[t].x;                       // row ky = g + G t, plane q
+      stg[g * SS + q].y = keep[t].y;
       __syncthreads();
       for (int idx = threadIdx.x; idx < G * TX; idx += C::threads) {
         const int j = idx % TX, r = idx / TX, ky = G * t + r;
