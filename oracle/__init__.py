@@ -78,6 +78,8 @@ def lib():
                                          ctypes.c_int, _D]
         L.or_num_threads.restype = ctypes.c_int
         L.or_set_num_threads.argtypes = [ctypes.c_int]
+        L.or_dft_points.argtypes = [ctypes.c_int, ctypes.c_longlong, _LL, _D, ctypes.c_longlong, _LL,
+                                    ctypes.c_void_p]
         _LIB = L
     return _LIB
 
@@ -257,6 +259,19 @@ def lowfreq_dft(wl, K: int, cell_grid: Optional[np.ndarray] = None) -> np.ndarra
     lib().or_lowfreq_dft(int(wl.zoom.n1), int(cg.shape[0]), _dp(cg), int(wl.mask.kind),
                          int(wl.mask.p0), int(wl.mask.p1), int(wl.zoom.factor), int(wl.n), int(K),
                          out.ctypes.data_as(ctypes.c_void_p))
+    return out
+
+
+def dft_points(n: int, xyz: np.ndarray, values: np.ndarray, uvw: np.ndarray) -> np.ndarray:
+    """eq. 1 by direct summation over the nonzero voxels xyz[p] = (x, y, z)
+    with densities values[p], at the frequencies uvw[q] = (u, v, w)."""
+    xyz = np.ascontiguousarray(xyz, dtype=np.int64)
+    uvw = np.ascontiguousarray(uvw, dtype=np.int64)
+    val = np.ascontiguousarray(values, dtype=np.float64)
+    out = np.zeros(len(uvw), dtype=np.complex128)
+    lib().or_dft_points(int(n), len(val), xyz.ctypes.data_as(ctypes.POINTER(ctypes.c_longlong)), _dp(val),
+                        len(uvw), uvw.ctypes.data_as(ctypes.POINTER(ctypes.c_longlong)),
+                        out.ctypes.data_as(ctypes.c_void_p))
     return out
 
 

@@ -459,6 +459,26 @@ void or_lowfreq_dft(int n1, int c, const double* cell, int kind, long long p0, l
     free(G2);
 }
 
+/* eq. 1 at chosen frequencies for a density given by its nonzero voxels:
+ *     F(u, v, w) = (1/n^3) sum_p rho_p exp(-2 pi i (u x_p + v y_p + w z_p) / n)
+ * with the phase from the exact integer product reduced mod n.  Used to
+ * sample transforms of boxes too large for or_fft3d.                        */
+void or_dft_points(int n, long long npts, const long long* xyz, const double* val,
+                   long long nq, const long long* uvw, cdouble* out)
+{
+    const double norm = 1.0 / ((double)n * n * n);
+#pragma omp parallel for schedule(static)
+    for (long long q = 0; q < nq; ++q) {
+        const long long u = uvw[3 * q], v = uvw[3 * q + 1], w = uvw[3 * q + 2];
+        cdouble s = 0;
+        for (long long p = 0; p < npts; ++p) {
+            long long e = pmod(u * xyz[3 * p] + v * xyz[3 * p + 1] + w * xyz[3 * p + 2], n);
+            s += val[p] * cexp(-2.0 * M_PI * I * (double)e / (double)n);
+        }
+        out[q] = s * norm;
+    }
+}
+
 /* sum of rho and of rho^2 over the box of level (n1, f, nk), from the
  * definition (used for F(0) and for the Parseval check at sizes where the
  * full transform is not run) */

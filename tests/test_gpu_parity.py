@@ -104,6 +104,33 @@ def test_fft3d_r2c_forward_and_inverse(ur, orc, n, prec):
     assert err2 <= (2e-6 if prec == 0 else 1e-13)
 
 
+def test_fft3d_r2c_2048_sampled(ur, orc):
+    """The 2048-point transform (columns over two wavefronts) at full size:
+    a 2048^3 FP32 box that is zero except at 64 random voxels, so that every
+    coefficient is a sum of 64 plane waves; 516 coefficients (random, plus
+    the corners) against eq. 1 by direct summation.  FP32 bound as for the
+    small boxes: 2e-6 of max|F|."""
+    import torch
+    n = 2048
+    _say("fft3d r2c n=2048 sampled")
+    xyz, val = W.sparse_voxels(2048, n, 64, dtype=np.float32)
+    x = torch.zeros((n, n, n), dtype=torch.float32, device="cuda")
+    x[torch.as_tensor(xyz[:, 0], device="cuda"), torch.as_tensor(xyz[:, 1], device="cuda"),
+      torch.as_tensor(xyz[:, 2], device="cuda")] = torch.as_tensor(val, device="cuda")
+    plan = ur.Plan(n, 1.0, 0)
+    out = plan.fft3d(x)                                        # [kz][ky][kx]
+    del x
+    uvw = W.random_frequencies(2049, n, 512)                   # (kx, ky, kz), kz <= n/2
+    idx = torch.as_tensor(uvw, device="cuda")
+    got = out[idx[:, 2], idx[:, 1], idx[:, 0]].cpu().numpy().astype(np.complex128)
+    del out, plan
+    torch.cuda.empty_cache()
+    ref = orc.dft_points(n, xyz, val.astype(np.float64), uvw)
+    err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+    _say(f"  2048 sampled rel err {err:.3e}")
+    assert err <= 2e-6
+
+
 @pytest.mark.parametrize("n", [16, 64])
 @pytest.mark.parametrize("prec", [0, 1])
 def test_fft3d_c2c(ur, orc, n, prec):

@@ -444,3 +444,41 @@ def test_grad_amp_matches_central_differences(oracle_lib):
         dn = cell.amp.copy(); dn[a] -= h
         fd = (loss(cell.with_amp(up))[0] - loss(cell.with_amp(dn))[0]) / (2 * h)
         assert abs(fd - ga[a]) <= 1e-6 * max(1.0, abs(fd)), (a, fd, ga[a])
+
+
+# ---------------------------------------------------------------------------
+# eq. 1 at sampled frequencies for sparse densities (used to check boxes too
+# large for the full oracle transform)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n", [16, 32])
+def test_dft_points_matches_numpy_fftn(oracle_lib, n):
+    """Every frequency of a sparse box against numpy.fft.fftn / n^3 (pocketfft,
+    a library routine independent of the oracle)."""
+    import oracle
+    xyz, val = W.sparse_voxels(5 + n, n, 17, dtype=np.float64)
+    rho = np.zeros((n, n, n))
+    rho[xyz[:, 0], xyz[:, 1], xyz[:, 2]] = val
+    ref = np.fft.fftn(rho) / n ** 3
+    u, v, w = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    uvw = np.stack([u.ravel(), v.ravel(), w.ravel()], axis=1)
+    got = oracle.dft_points(n, xyz, val, uvw).reshape(n, n, n)
+    assert np.max(np.abs(got - ref)) <= 1e-14 * np.max(np.abs(ref))
+
+
+def test_dft_points_large_box_phase_reduction(oracle_lib):
+    """At n = 2048 the integer phase reduction must agree with the same
+    coefficients computed for the box embedded at 4x the resolution of a
+    16-voxel lattice: a density on every 128th voxel of a 2048 box is a 16^3
+    box, whose transform (numpy) repeats with period 16 in each frequency."""
+    import oracle
+    n, m = 2048, 16
+    xyz_c, val = W.sparse_voxels(77, m, 9, dtype=np.float64)
+    xyz = xyz_c * (n // m)
+    rho_c = np.zeros((m, m, m))
+    rho_c[xyz_c[:, 0], xyz_c[:, 1], xyz_c[:, 2]] = val
+    ref_c = np.fft.fftn(rho_c) / float(n) ** 3          # same sums, box normalisation 1/n^3
+    uvw = W.random_frequencies(78, n, 200, half_z=False)
+    got = oracle.dft_points(n, xyz, val, uvw)
+    ref = ref_c[uvw[:, 0] % m, uvw[:, 1] % m, uvw[:, 2] % m]
+    assert np.max(np.abs(got - ref)) <= 1e-13 * np.max(np.abs(ref))

@@ -189,6 +189,28 @@ def random_density(seed: int, n: int, dtype=np.float64) -> np.ndarray:
     return rng.standard_normal((n, n, n)).astype(dtype)
 
 
+def sparse_voxels(seed: int, n: int, npts: int, dtype=np.float32):
+    """A density that is zero except at npts distinct random voxels:
+    (xyz int64 [npts, 3], values [npts] in [0.5, 2) rounded to dtype)."""
+    rng = np.random.default_rng(seed)
+    flat = rng.choice(n * n * n, size=npts, replace=False)
+    xyz = np.stack([flat // (n * n), (flat // n) % n, flat % n], axis=1).astype(np.int64)
+    val = rng.uniform(0.5, 2.0, npts).astype(dtype)
+    return xyz, val
+
+
+def random_frequencies(seed: int, n: int, count: int, half_z: bool = True) -> np.ndarray:
+    """count random frequency triples (u, v, w) of an n^3 box, w in [0, n/2]
+    for a half spectrum, plus the corners (0,0,0) and (n/2, n/2, n/2)."""
+    rng = np.random.default_rng(seed)
+    u = rng.integers(0, n, count)
+    v = rng.integers(0, n, count)
+    w = rng.integers(0, n // 2 + 1 if half_z else n, count)
+    q = np.stack([u, v, w], axis=1).astype(np.int64)
+    extra = np.array([[0, 0, 0], [n // 2, n // 2, n // 2], [n - 1, 1, n // 2], [1, n - 1, 0]], dtype=np.int64)
+    return np.concatenate([extra, q], axis=0)
+
+
 # ----------------------------------------------------------------------------
 # named workloads
 # ----------------------------------------------------------------------------
