@@ -101,8 +101,12 @@ typedef struct { int32_t n1; int32_t factor; } ur_zoom;
  * conjugate partner too, so every statistic is that of the full n^3 box).
  * totals (DEVICE, 4 doubles): [0] sum of I over every voxel (binned or not),
  * [1] Re F(0), [2] Im F(0), [3] sum of rho^2 over the box (0 when the density
- * was not generated or loaded by the call).  I = |F|^2 with F of eq. 1. */
-typedef struct { double* sum; double* sumsq; double* count; double* totals; } ur_hist;
+ * was not generated or loaded by the call).  I = |F|^2 with F of eq. 1.
+ * mean, sem (DEVICE, nbins each, or NULL to skip): the per-bin mean sum/count
+ * and standard error of the mean sqrt((sumsq - sum^2/count)/(count-1)/count)
+ * of I (section "Q-calculation and spherical averaging"); NaN for an empty
+ * bin, and SEM NaN for a bin of one voxel. */
+typedef struct { double* sum; double* sumsq; double* count; double* totals; double* mean; double* sem; } ur_hist;
 
 typedef struct ur_plan ur_plan;
 

@@ -40,7 +40,7 @@ class UrZoom(_c.Structure):
 
 
 class UrHist(_c.Structure):
-    _fields_ = [("sum", _vp), ("sumsq", _vp), ("count", _vp), ("totals", _vp)]
+    _fields_ = [("sum", _vp), ("sumsq", _vp), ("count", _vp), ("totals", _vp), ("mean", _vp), ("sem", _vp)]
 
 
 _LIB = None
@@ -169,7 +169,10 @@ def mask_struct(mask) -> UrMask:
 
 
 class Hist:
-    """Per-bin sums (device, FP64) written by the library."""
+    """Per-bin statistics (device, FP64) written by the library: sums,
+    voxel counts, mean and standard error of the mean, and the totals."""
+
+    FIELDS = ("sum", "sumsq", "count", "totals", "mean", "sem")
 
     def __init__(self, nbins: int):
         torch = _torch()
@@ -179,15 +182,14 @@ class Hist:
         self.sumsq = torch.zeros(nbins, dtype=torch.float64, device=dev)
         self.count = torch.zeros(nbins, dtype=torch.float64, device=dev)
         self.totals = torch.zeros(4, dtype=torch.float64, device=dev)
+        self.mean = torch.zeros(nbins, dtype=torch.float64, device=dev)
+        self.sem = torch.zeros(nbins, dtype=torch.float64, device=dev)
 
     def struct(self) -> UrHist:
-        return UrHist(_ptr(self.sum), _ptr(self.sumsq), _ptr(self.count), _ptr(self.totals))
+        return UrHist(*[_ptr(getattr(self, k)) for k in self.FIELDS])
 
     def numpy(self) -> dict:
-        out = {k: getattr(self, k).cpu().numpy() for k in ("sum", "sumsq", "count", "totals")}
-        with np.errstate(invalid="ignore", divide="ignore"):
-            out["mean"] = np.where(out["count"] > 0, out["sum"] / np.maximum(out["count"], 1.0), np.nan)
-        return out
+        return {k: getattr(self, k).cpu().numpy() for k in self.FIELDS}
 
 
 class Plan:

@@ -16,8 +16,8 @@ from . import DeviceCell, Hist, Plan
 
 
 def _means(h: Hist) -> torch.Tensor:
-    cnt = h.count
-    return torch.where(cnt > 0, h.sum / torch.clamp(cnt, min=1.0), torch.zeros_like(h.sum))
+    """Per-bin means written by the finalize kernel, empty bins (NaN) as 0."""
+    return torch.nan_to_num(h.mean, nan=0.0)
 
 
 class BinnedIntensity(torch.autograd.Function):

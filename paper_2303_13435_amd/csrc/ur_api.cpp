@@ -518,7 +518,7 @@ static ur_status run_y_x(ur_plan* p, const FwdGeom& g, char* A, char* B, const L
   FinArgs fa{};
   fa.part = xa.part; fa.nblk = nxb; fa.nbins = p->nbins;
   fa.mom = nzb > 0 ? (const double*)(p->ws + lay.mom) : nullptr; fa.nzb = nzb;
-  fa.mpart = (double*)(p->ws + lay.f0 + 64); fa.f0 = xa.f0; fa.cnt = p->dCount; fa.sum = h->sum; fa.sumsq = h->sumsq; fa.count = h->count; fa.totals = h->totals;
+  fa.mpart = (double*)(p->ws + lay.f0 + 64); fa.f0 = xa.f0; fa.cnt = p->dCount; fa.sum = h->sum; fa.sumsq = h->sumsq; fa.count = h->count; fa.totals = h->totals; fa.mean = h->mean; fa.sem = h->sem;
   {
     PassTimer tm(p, P_FIN, s);
     UR_HIP(launch_finalize(fa, s));
@@ -675,7 +675,7 @@ ur_status ur_intensity_bin(ur_plan* p, const void* spectrum, const ur_hist* h, v
   UR_HIP(launch_pass_x(p->prec, n, X_BIN_ONLY, -1, xa, nxb, s));
   FinArgs fa{};
   fa.part = xa.part; fa.nblk = nxb; fa.nbins = p->nbins; fa.mom = nullptr; fa.nzb = 0;
-  fa.mpart = (double*)(p->ws + lay.f0 + 64); fa.f0 = xa.f0; fa.cnt = p->dCount; fa.sum = h->sum; fa.sumsq = h->sumsq; fa.count = h->count; fa.totals = h->totals;
+  fa.mpart = (double*)(p->ws + lay.f0 + 64); fa.f0 = xa.f0; fa.cnt = p->dCount; fa.sum = h->sum; fa.sumsq = h->sumsq; fa.count = h->count; fa.totals = h->totals; fa.mean = h->mean; fa.sem = h->sem;
   UR_HIP(launch_finalize(fa, s));
   return UR_OK;
 }
@@ -754,7 +754,7 @@ ur_status ur_simulate_host(ur_plan* p, const void* rho_host, int32_t x_lo, int32
   UR_HIP(launch_pass_x(p->prec, n, X_FFT_BIN, -1, xa, x_blocks(p), s));
   FinArgs fa{};
   fa.part = xa.part; fa.nblk = x_blocks(p); fa.nbins = p->nbins; fa.mom = (const double*)(p->ws + lay.mom); fa.nzb = zb;
-  fa.mpart = (double*)(p->ws + lay.f0 + 64); fa.f0 = xa.f0; fa.cnt = p->dCount; fa.sum = h->sum; fa.sumsq = h->sumsq; fa.count = h->count; fa.totals = h->totals;
+  fa.mpart = (double*)(p->ws + lay.f0 + 64); fa.f0 = xa.f0; fa.cnt = p->dCount; fa.sum = h->sum; fa.sumsq = h->sumsq; fa.count = h->count; fa.totals = h->totals; fa.mean = h->mean; fa.sem = h->sem;
   UR_HIP(launch_finalize(fa, s));
   return UR_OK;
 }

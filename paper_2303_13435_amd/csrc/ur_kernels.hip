@@ -911,7 +911,7 @@ struct Kahan {
 // block b < nvb: 8 values x 32 phases; the last block reduces the z-pass
 // moments and copies the (geometric) bin counts
 __global__ void __launch_bounds__(256) k_finalize(FinArgs a) {
-  __shared__ double ls[256], lc[256];
+  __shared__ double ls[256], lc[256], fin[8];
   const int nv = 2 * a.nbins + 1;
   const int nvb = (nv + 7) / 8;
   const int t = threadIdx.x;
@@ -937,6 +937,7 @@ __global__ void __launch_bounds__(256) k_finalize(FinArgs a) {
       Kahan r;
       for (int pp = 0; pp < 32; ++pp) { r.add(ls[pp * 8 + vv]); r.add(lc[pp * 8 + vv]); }
       double val = r.val();
+      fin[vv] = val;
       if (v == nv - 1) {
         a.totals[0] = val;
         a.totals[1] = a.f0 ? a.f0[0] : 0.0;
@@ -944,6 +945,21 @@ __global__ void __launch_bounds__(256) k_finalize(FinArgs a) {
       } else {
         (v % 2 == 0 ? a.sum : a.sumsq)[v / 2] = val;
       }
+    }
+    // mean and standard error of the mean of bin v/2: its sum and sum of
+    // squares (v, v + 1) were reduced by this block (8 values per block)
+    __syncthreads();
+    if ((a.mean || a.sem) && p == 0 && vv % 2 == 0 && v + 1 < nv) {
+      const int b = v / 2;
+      const double c = a.cnt[b], S = fin[vv], S2 = fin[vv + 1];
+      const double m = c > 0.0 ? S / c : __builtin_nan("");
+      double se = __builtin_nan("");
+      if (c > 1.0) {
+        const double ss = S2 - S * m;                    // sum of (I - mean)^2
+        se = sqrt((ss > 0.0 ? ss : 0.0) / (c - 1.0) / c);
+      }
+      if (a.mean) a.mean[b] = m;
+      if (a.sem) a.sem[b] = se;
     }
   } else {
     for (int i = t; i < a.nbins; i += 256) a.count[i] = a.cnt[i];

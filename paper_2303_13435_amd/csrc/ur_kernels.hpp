@@ -80,6 +80,8 @@ struct FinArgs {
   double* sumsq;
   double* count;
   double* totals;
+  double* mean;             // per-bin mean and SEM (may be null)
+  double* sem;
 };
 
 struct MergeArgs {

@@ -74,6 +74,20 @@ def compare_bins(got, ref, tol, what="", n=None):
     worst = int(np.argmax(rel)) if rel.size else 0
     _say(f"  {what}: {pop.sum()} bins, max rel err {rel.max() if rel.size else 0:.3e}")
     assert rel.size == 0 or rel.max() <= tol, f"{what}: max rel err {rel.max():.3e} at bin {np.flatnonzero(pop)[worst]}"
+    # empty bins: NaN mean (both sides)
+    assert np.all(np.isnan(got["mean"][~pop])), f"{what}: empty bins must have a NaN mean"
+    # SEM of the kernel (one pass over pooled sums) against the oracle's
+    # two-pass SEM: relative bound, plus a floor for bins whose intensities
+    # are (nearly) equal, where the one-pass difference sumsq - sum*mean is
+    # at its rounding level: sqrt(eps * (mean^2 + var)) / sqrt(count)
+    c = ref["count"][pop]
+    multi = c > 1
+    s_ref, s_got = ref["sem"][pop][multi], got["sem"][pop][multi]
+    t_rel, t_abs = (1e-5, 1e-5) if tol >= 1e-6 else (1e-9, 3e-8)
+    bound = t_rel * s_ref + (t_abs * np.abs(m_ref[multi]) + floor) / np.sqrt(c[multi])
+    serr = np.abs(s_got - s_ref)
+    assert np.all(serr <= bound), f"{what}: SEM error {np.max(serr / bound):.3g} x bound"
+    assert np.all(np.isnan(got["sem"][pop][~multi])), f"{what}: one-voxel bins must have a NaN SEM"
     return rel
 
 
