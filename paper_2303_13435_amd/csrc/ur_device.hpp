@@ -26,6 +26,26 @@ template <typename T> __device__ __forceinline__ cx<T> cmulc(cx<T> a, cx<T> b) {
 template <typename T> __device__ __forceinline__ cx<T> conjg(cx<T> a) { return mk(a.x, -a.y); }
 template <typename T> __device__ __forceinline__ cx<T> scale(cx<T> a, T s) { return mk(a.x * s, a.y * s); }
 
+// Streaming (non-temporal) stores of complex values: for intermediates that
+// are written once and read back only by the next pass, long after any cache
+// could hold them.
+template <typename T> __device__ __forceinline__ void st_nt(cx<T>* p, cx<T> v) {
+  typedef T v2 __attribute__((ext_vector_type(2)));
+  v2 t;
+  t.x = v.x;
+  t.y = v.y;
+  __builtin_nontemporal_store(t, (v2*)p);
+}
+template <typename T> __device__ __forceinline__ void st_nt2(cx2<T>* p, cx2<T> v) {
+  typedef T v4 __attribute__((ext_vector_type(4)));
+  v4 t;
+  t.x = v.a.x;
+  t.y = v.a.y;
+  t.z = v.b.x;
+  t.w = v.b.y;
+  __builtin_nontemporal_store(t, (v4*)p);
+}
+
 // Compile-time loop: f(std::integral_constant<int, I>) for I in [I0, I1).
 // Guarantees constant indices into register arrays whatever the unroller
 // decides for a large body.

@@ -520,7 +520,7 @@ k_pass_z(ZArgs a) {
       cx2<T> o;
       o.a = mk((zk.x + zm.x) * (T)0.5, (zk.y - zm.y) * (T)0.5);
       o.b = mk((zk.y + zm.y) * (T)0.5, (zm.x - zk.x) * (T)0.5);
-      *dst = o;
+      st_nt2(dst, o);
     }
   } else {
     const cx<T>* col = sm + j * PS;
@@ -560,10 +560,11 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t column_rsrc(const void* base, 
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, bytes, 0x00020000);
 }
 
+// The columns are read once per pass: non-temporal cache policy (aux bit 1).
 template <typename T>
 __device__ __forceinline__ cx<T> column_ld(__amdgpu_buffer_rsrc_t rs, unsigned off) {
-  if constexpr (sizeof(T) == 4) return __builtin_bit_cast(cx<T>, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)off, 0, 0));
-  else return __builtin_bit_cast(cx<T>, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off, 0, 0));
+  if constexpr (sizeof(T) == 4) return __builtin_bit_cast(cx<T>, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)off, 0, 2));
+  else return __builtin_bit_cast(cx<T>, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off, 0, 2));
 }
 
 // v[i R0 + r] = col[p] for p = g + G i + r N/R0 inside [lo, hi], zero elsewhere
@@ -623,8 +624,10 @@ k_pass_y(YArgs a) {
   __shared__ cx<T> sm[NS * PS + G * SS];
   cx<T>* stg = sm + NS * PS;
 
-  const int kz = blockIdx.x % a.nkz;
-  const int xt = a.xt0 + blockIdx.x / a.nkz;
+  // x tile fastest: the blocks resident at one time cover whole B rows
+  // (one kz, all x tiles), so their 128-byte row segments are contiguous
+  const int xt = a.xt0 + blockIdx.x % a.nxt;
+  const int kz = blockIdx.x / a.nxt;
   const int xbase = xt * TX;
   // G >= 64: every wavefront lies in one group, the plane index is
   // wave-uniform and the row range of the plane is computed on the scalar unit
@@ -671,7 +674,7 @@ k_pass_y(YArgs a) {
 #pragma unroll
       for (int k = 0; k < G / RS; ++k, dst += rstep) {
         const int off = from_stg ? k * RS * SS : t * (G + G / 16) + k * (RS + RS / 16);
-        *dst = src[off];
+        st_nt(dst, src[off]);
       }
       __syncthreads();
     });
