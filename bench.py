@@ -140,7 +140,9 @@ def out_of_core(ur, W, torch, wl, reps):
     host = torch.empty(rho.shape, dtype=torch.float32, pin_memory=True)
     host.copy_(rho)
     del rho
-    r = math.isqrt(int(wl.mask.p0))
+    # planes that can hold density: half-width of the mask (sphere: sqrt of
+    # the squared radius; cube and truncated octahedron: p0)
+    r = math.isqrt(int(wl.mask.p0)) if wl.mask.kind == W.MASK_SPHERE else int(wl.mask.p0)
     x_lo, x_hi = wl.n // 2 - r, wl.n // 2 + r
     h = ur.Hist(wl.nbins)
     nbytes = plan.simulate_host(host, x_lo, x_hi, h)
@@ -257,6 +259,10 @@ def main():
         extras["c3_batch"] = c3_batch(ur, W, torch, max(2, args.steps // 4))
         # out-of-core: the same box streamed from pinned host memory
         extras["out_of_core"] = out_of_core(ur, W, torch, wl, max(2, args.steps // 4))
+        torch.cuda.empty_cache()
+        # out-of-core at 2048^3 with the truncated-octahedron recipe of the
+        # out-of-core workload (its largest box that one GPU's transform runs)
+        extras["out_of_core_c5_2048"] = out_of_core(ur, W, torch, W.c5(2048), 2)
 
     cpu = None
     if not args.no_cpu_baseline:

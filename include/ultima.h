@@ -164,10 +164,12 @@ ur_status ur_simulate_rho(ur_plan* plan, const void* rho, const ur_hist* hist, v
  * HOST memory (pinned, e.g. hipHostMalloc, for full PCIe speed) holding the
  * n^3 density [x][y][z].  Planes outside [x_lo, x_hi] are taken as zero and
  * never copied ("only the slices with nonzero density"); slabs of planes
- * are copied to the device on a copy stream, double buffered, while the
- * previous slab goes through the z and y passes on `stream`; the x pass with
- * binning runs once every slab is in.  Only one slab of the first
- * intermediate and the x-range of the final spectrum live in HBM.  The host
+ * are copied to the device into four staging buffers, each on its own copy
+ * stream (several copies in flight), while earlier slabs go through the z
+ * and y passes on `stream`; the x pass with binning runs once every slab is
+ * in.  Only the staging slabs, one slab of the first intermediate and the
+ * x-range of the final spectrum live in HBM (the staging buffers are
+ * allocated by the plan on first use).  The host
  * buffer must stay valid until the stream is synchronised.  *h2d_bytes (when
  * non-null) receives the bytes copied host to device. */
 ur_status ur_simulate_host(ur_plan* plan, const void* rho_host, int32_t x_lo, int32_t x_hi,

@@ -80,8 +80,11 @@ struct ur_plan {
   size_t cs_bytes = 0;
 
   // out-of-core
-  hipStream_t copy_stream = nullptr;
-  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  // out-of-core staging: kStage slab buffers, each filled on its own copy
+  // stream (several host-to-device copies in flight keep PCIe busy)
+  static constexpr int kStage = 4;
+  hipStream_t copy_stream[kStage] = {};
+  hipEvent_t ev_copied[kStage] = {}, ev_free[kStage] = {};
   void* stage = nullptr;     // two pinned-side staging buffers on the device
   size_t stage_bytes = 0;
 
@@ -297,8 +300,9 @@ void ur_plan_destroy(ur_plan* p) {
   if (p->ws && p->ws_owned) (void)hipFree(p->ws);
   if (p->cs_buf) (void)hipFree(p->cs_buf);
   if (p->stage) (void)hipFree(p->stage);
-  for (auto& e : p->ev) if (e) (void)hipEventDestroy(e);
-  if (p->copy_stream) (void)hipStreamDestroy(p->copy_stream);
+  for (auto& e : p->ev_copied) if (e) (void)hipEventDestroy(e);
+  for (auto& e : p->ev_free) if (e) (void)hipEventDestroy(e);
+  for (auto& c : p->copy_stream) if (c) (void)hipStreamDestroy(c);
   for (auto& e : p->ev_open) { (void)hipEventDestroy(e.second.first); (void)hipEventDestroy(e.second.second); }
   for (auto& e : p->ev_pool) (void)hipEventDestroy(e);
   delete p;
@@ -696,15 +700,17 @@ ur_status ur_simulate_host(ur_plan* p, const void* rho_host, int32_t x_lo, int32
   UR_TRY(ensure_ws(p, lay.total, s));
   const size_t plane_bytes = (size_t)n * n * p->rs;
   const size_t slab_bytes = (size_t)tx * plane_bytes;
-  if (!p->stage || p->stage_bytes < 2 * slab_bytes) {
+  constexpr int K = ur_plan::kStage;
+  if (!p->stage || p->stage_bytes < K * slab_bytes) {
     UR_HIP(hipDeviceSynchronize());
     if (p->stage) UR_HIP(hipFree(p->stage));
     p->stage = nullptr;
-    if (hipMalloc(&p->stage, 2 * slab_bytes) != hipSuccess) { (void)hipGetLastError(); return fail(UR_ERR_OOM, "staging allocation failed"); }
-    p->stage_bytes = 2 * slab_bytes;
+    if (hipMalloc(&p->stage, K * slab_bytes) != hipSuccess) { (void)hipGetLastError(); return fail(UR_ERR_OOM, "staging allocation failed"); }
+    p->stage_bytes = K * slab_bytes;
   }
-  if (!p->copy_stream) UR_HIP(hipStreamCreateWithFlags(&p->copy_stream, hipStreamNonBlocking));
-  for (auto& e : p->ev) if (!e) UR_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  for (auto& c : p->copy_stream) if (!c) UR_HIP(hipStreamCreateWithFlags(&c, hipStreamNonBlocking));
+  for (auto& e : p->ev_copied) if (!e) UR_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  for (auto& e : p->ev_free) if (!e) UR_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
 
   FwdGeom g{};
   g.xlo = x_lo; g.xhi = x_hi; g.gen = 0; g.L = make_level(n, n, 1, 1);
@@ -713,23 +719,24 @@ ur_status ur_simulate_host(ur_plan* p, const void* rho_host, int32_t x_lo, int32
   char* A = p->ws + lay.A;
   char* B = p->ws + lay.B;
   size_t copied = 0;
-  // events: ev[0], ev[1] = slab copied into stage buffer 0/1; ev[2], ev[3] = stage buffer 0/1 consumed
-  UR_HIP(hipEventRecord(p->ev[2], s));
-  UR_HIP(hipEventRecord(p->ev[3], s));
+  // slab k goes to staging buffer k mod K on copy stream k mod K;
+  // ev_copied[b]: buffer b filled, ev_free[b]: buffer b consumed by the z pass
+  for (int b = 0; b < K; ++b) UR_HIP(hipEventRecord(p->ev_free[b], s));
   const int ntl = ntiles(p);
   int zb = 0;
   for (long long xt = xt0; xt <= xt1; ++xt) {
-    const int buf = (int)((xt - xt0) & 1);
+    const int buf = (int)((xt - xt0) % K);
+    hipStream_t cs = p->copy_stream[buf];
     char* st = (char*)p->stage + buf * slab_bytes;
     const long long sx0 = xt * tx;
     const long long lo = std::max<long long>(sx0, x_lo), hi = std::min<long long>(sx0 + tx - 1, x_hi);
     // wait until the previous user of this staging buffer is done, then copy
-    UR_HIP(hipStreamWaitEvent(p->copy_stream, p->ev[2 + buf], 0));
+    UR_HIP(hipStreamWaitEvent(cs, p->ev_free[buf], 0));
     UR_HIP(hipMemcpyAsync(st + (lo - sx0) * plane_bytes, (const char*)rho_host + (size_t)lo * plane_bytes,
-                          (size_t)(hi - lo + 1) * plane_bytes, hipMemcpyHostToDevice, p->copy_stream));
+                          (size_t)(hi - lo + 1) * plane_bytes, hipMemcpyHostToDevice, cs));
     copied += (size_t)(hi - lo + 1) * plane_bytes;
-    UR_HIP(hipEventRecord(p->ev[buf], p->copy_stream));
-    UR_HIP(hipStreamWaitEvent(s, p->ev[buf], 0));
+    UR_HIP(hipEventRecord(p->ev_copied[buf], cs));
+    UR_HIP(hipStreamWaitEvent(s, p->ev_copied[buf], 0));
     // z pass over the planes of this slab, then y pass of this x tile
     ZArgs za{};
     za.A = A; za.ax0 = sx0; za.rho = st; za.rho_x0 = sx0; za.tw = p->tw;
@@ -737,7 +744,7 @@ ur_status ur_simulate_host(ur_plan* p, const void* rho_host, int32_t x_lo, int32
     const int nb = (int)((hi - lo + 1) * ntl);
     UR_HIP(launch_pass_z(p->prec, n, Z_LOAD_R2C, za, nb, s));
     zb += nb;
-    UR_HIP(hipEventRecord(p->ev[2 + buf], s));
+    UR_HIP(hipEventRecord(p->ev_free[buf], s));
     YArgs ya{};
     ya.A = A; ya.ax0 = sx0; ya.B = B; ya.bx0 = bx0; ya.bs = bs; ya.tw = p->tw; ya.L = g.L; ya.gen = 0;
     ya.nkz = p->nkz; ya.xlo = (int)lo; ya.xhi = (int)hi; ya.xt0 = (int)xt; ya.nxt = 1; ya.ty = zt(p);
