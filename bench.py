@@ -128,6 +128,45 @@ def c3_batch(ur, W, torch, reps):
     return out
 
 
+def radii_batch(ur, W, torch, reps):
+    """32 particle radii (256^3 FP32 boxes, spheres R = 20..100) through one
+    plan, recorded in one HIP graph and replayed."""
+    levels = W.b_radii()
+    s = torch.cuda.Stream()
+    plan = ur.Plan(levels[0].n, 1.0, ur.UR_F32)
+    plan.set_bins(levels[0].edges)
+    cell = ur.DeviceCell.from_host(levels[0].cell)
+    hists = [ur.Hist(w.nbins) for w in levels]
+
+    def run():
+        for wl, h in zip(levels, hists):
+            plan.simulate(cell, wl.mask, wl.zoom, h, stream=s)
+
+    with torch.cuda.stream(s):
+        run()
+    torch.cuda.synchronize()
+    g = ur.Graph(s)
+    with torch.cuda.stream(s):
+        with g:
+            run()
+    g.launch()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        g.launch()
+    e1.record(s)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    out = {"ms_per_batch": round(ms, 3), "boxes": len(levels), "box": levels[0].n,
+           "radii": [round(float(w.mask.p0) ** 0.5, 1) for w in (levels[0], levels[-1])],
+           "voxels_per_s": len(levels) * levels[0].n ** 3 / (ms * 1e-3), "graph_launches": reps}
+    del g, plan, hists
+    torch.cuda.empty_cache()
+    return out
+
+
 def out_of_core(ur, W, torch, wl, reps):
     """The headline box with its density in pinned host memory: only the
     planes that hold density are copied, slab by slab, overlapped with the
@@ -257,6 +296,8 @@ def main():
         # multi-zoom batch: ED-1 2048^3 + ED-2 1024^3 (f 4) + ED-3 512^3 (f 16)
         # and the merge, recorded in one HIP graph and replayed
         extras["c3_batch"] = c3_batch(ur, W, torch, max(2, args.steps // 4))
+        # many particle sizes: 32 radii of 256^3 boxes in one graph
+        extras["radii_batch"] = radii_batch(ur, W, torch, max(2, args.steps // 4))
         # out-of-core: the same box streamed from pinned host memory
         extras["out_of_core"] = out_of_core(ur, W, torch, wl, max(2, args.steps // 4))
         torch.cuda.empty_cache()

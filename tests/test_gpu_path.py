@@ -250,6 +250,58 @@ def test_out_of_core_2048_c5_recipe(ur, orc):
     torch.cuda.empty_cache()
 
 
+def _radii_batch(ur, levels, s, plan, hists, cells):
+    for wl, h, c in zip(levels, hists, cells):
+        plan.simulate(c, wl.mask, wl.zoom, h, stream=s)
+
+
+@pytest.mark.parametrize("n,count,r_lo,r_hi,check", [(64, 5, 6.0, 28.0, "all"), (256, 32, 20.0, 100.0, "ends")])
+def test_radii_batch_in_one_graph(ur, orc, n, count, r_lo, r_hi, check):
+    """Many particle sizes through one plan in one HIP graph: every replay
+    equals the eager calls; boxes against the whole oracle (all boxes of the
+    small batch; smallest and largest radius of the 32-box 256^3 batch)."""
+    import torch
+    levels = W.b_radii(n, count, r_lo, r_hi, nbins=64 if n <= 64 else 256)
+    _say(f"radii batch {count} x {n}^3")
+    plan = ur.Plan(n, 1.0, 0)
+    plan.set_bins(levels[0].edges)
+    cell = ur.DeviceCell.from_host(levels[0].cell)
+    cells = [cell] * count
+    hists = [ur.Hist(wl.nbins) for wl in levels]
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        _radii_batch(ur, levels, s, plan, hists, cells)
+    torch.cuda.synchronize()
+    eager = [h.numpy() for h in hists]
+    g = ur.Graph(s)
+    with torch.cuda.stream(s):
+        with g:
+            _radii_batch(ur, levels, s, plan, hists, cells)
+    for rep in range(2):
+        for h in hists:
+            h.sum.fill_(0.0)
+            h.mean.fill_(0.0)
+        torch.cuda.synchronize()
+        g.launch()
+        torch.cuda.synchronize()
+        for h, e in zip(hists, eager):
+            d = h.numpy()
+            assert np.array_equal(d["count"], e["count"])
+            pop = e["count"] > 0
+            assert np.array_equal(d["sum"][pop], e["sum"][pop])
+            assert np.array_equal(d["mean"][pop], e["mean"][pop])
+    sel = range(count) if check == "all" else (0, count - 1)
+    for i in sel:
+        wl = levels[i]
+        ref = orc.simulate(wl)
+        d = eager[i]
+        assert np.array_equal(d["count"], ref["count"])
+        pop = ref["count"] > 0
+        rel = np.abs(d["mean"][pop] - ref["mean"][pop]) / np.abs(ref["mean"][pop])
+        _say(f"  {wl.name}: max rel err {rel.max():.3e}")
+        assert rel.max() <= 1e-5
+
+
 def test_graph_replay_matches_eager(ur):
     import torch
     wl = W.small(64, c=8, n_atoms=10, seed=7, radius=25.0, nbins=64)

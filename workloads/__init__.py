@@ -277,6 +277,20 @@ def zoom_levels(n1: int, c: int, n_atoms: int, seed: int, radius: float, levels,
             for (n, f) in levels]
 
 
+def b_radii(n: int = 256, count: int = 32, r_lo: float = 20.0, r_hi: float = 100.0, nbins: int = 256,
+            prec: int = PREC_F32) -> List[Workload]:
+    """Many particle sizes in one batch: the 16-voxel cell with 40 atoms of
+    seed 2 (the C2/M1024 cell) inside spheres of ``count`` radii log-spaced
+    on [r_lo, r_hi], each an n^3 box with ``nbins`` log bins on [dq, sqrt(3) pi]."""
+    cell = draw_atoms(2, 40, 16)
+    edges = default_log_edges(n, 1.0, nbins)
+    out = []
+    for i in range(count):
+        r = r_lo * (r_hi / r_lo) ** (i / max(count - 1, 1))
+        out.append(Workload(f"B{n}_R{r:.1f}", n, 1.0, prec, "r2c", cell, sphere(r), Zoom(n, 1), edges))
+    return out
+
+
 def c5(n: int = 4096) -> Workload:
     """Out-of-core box: 128-voxel cell with 200 atoms (seed 5), truncated
     octahedron inscribed in R = 1900 (scaled with n), 2048 log bins."""
