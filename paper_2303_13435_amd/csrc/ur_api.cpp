@@ -66,6 +66,8 @@ struct ur_plan {
   int ncu = 256;             // compute units of the device
   int nbins = 0;
   int* dU = nullptr;         // nbins + 1 thresholds (device)
+  short* dLut = nullptr;     // bin of n2 = s^2, s in [0, nlut) (device)
+  int nlut = 0;
   double* dCount = nullptr;  // per-bin voxel counts (device), computed with the bins
   unsigned long long* dCountTmp = nullptr;
   std::vector<long long> U;
@@ -295,6 +297,7 @@ void ur_plan_destroy(ur_plan* p) {
   (void)hipDeviceSynchronize();
   if (p->tw) (void)hipFree(p->tw);
   if (p->dU) (void)hipFree(p->dU);
+  if (p->dLut) (void)hipFree(p->dLut);
   if (p->dCount) (void)hipFree(p->dCount);
   if (p->dCountTmp) (void)hipFree(p->dCountTmp);
   if (p->ws && p->ws_owned) (void)hipFree(p->ws);
@@ -377,6 +380,22 @@ ur_status ur_plan_set_bins(ur_plan* p, int32_t nbins, const double* edges) {
     UR_HIP(hipMalloc(&p->dCountTmp, nbins * sizeof(unsigned long long)));
   }
   UR_HIP(hipMemcpy(p->dU, Ui.data(), (nbins + 1) * sizeof(int), hipMemcpyHostToDevice));
+  // start-of-walk table for the binning: the bin of n2 = s^2 for every
+  // s <= isqrt(n2max) (-1 below the first threshold, nbins above the last)
+  {
+    const int nl = lut_len(p->n);
+    std::vector<short> lut(nl);
+    int b = -1;
+    for (int sq = 0; sq < nl; ++sq) {
+      const long long v = (long long)sq * sq;
+      while (b < nbins && v >= (long long)Ui[b + 1]) ++b;
+      lut[sq] = (short)b;
+    }
+    if (p->dLut && p->nlut < nl) { UR_HIP(hipFree(p->dLut)); p->dLut = nullptr; }
+    if (!p->dLut) UR_HIP(hipMalloc(&p->dLut, nl * sizeof(short)));
+    UR_HIP(hipMemcpy(p->dLut, lut.data(), nl * sizeof(short), hipMemcpyHostToDevice));
+    p->nlut = nl;
+  }
   // voxel counts per bin: pure geometry of the box and the thresholds
   UR_HIP(launch_bin_counts(p->n, p->nkz, !(p->flags & UR_C2C), nbins, p->dU, p->dCountTmp, p->dCount, nullptr));
   UR_HIP(hipDeviceSynchronize());
@@ -512,7 +531,7 @@ static ur_status run_y_x(ur_plan* p, const FwdGeom& g, char* A, char* B, const L
   xa.nkz = p->nkz; xa.r2c = !(p->flags & UR_C2C);
   xa.xa = (int)bx0; xa.xb = g.xlo <= g.xhi ? (int)(bx0 + bs - 1) : -1;
   xa.iscale = 1.0 / ((double)n * n * n) / ((double)n * n * n);
-  xa.oscale = 1.0; xa.nbins = p->nbins; xa.U = p->dU;
+  xa.oscale = 1.0; xa.nbins = p->nbins; xa.U = p->dU; xa.lut = p->dLut; xa.nlut = p->nlut;
   xa.part = (double*)(p->ws + lay.part); xa.f0 = (double*)(p->ws + lay.f0);
   xa.ncols = p->nkz * n;
   {
@@ -673,7 +692,7 @@ ur_status ur_intensity_bin(ur_plan* p, const void* spectrum, const ur_hist* h, v
   const int n = p->n;
   XArgs xa{};
   xa.B = spectrum; xa.bx0 = 0; xa.bs = n; xa.tw = p->tw; xa.nkz = p->nkz; xa.r2c = !(p->flags & UR_C2C);
-  xa.xa = 0; xa.xb = n - 1; xa.iscale = 1.0; xa.nbins = p->nbins; xa.U = p->dU;
+  xa.xa = 0; xa.xb = n - 1; xa.iscale = 1.0; xa.nbins = p->nbins; xa.U = p->dU; xa.lut = p->dLut; xa.nlut = p->nlut;
   xa.part = (double*)(p->ws + lay.part); xa.f0 = (double*)(p->ws + lay.f0); xa.ncols = p->nkz * n;
   const int nxb = x_blocks(p, X_BIN_ONLY);
   UR_HIP(launch_pass_x(p->prec, n, X_BIN_ONLY, -1, xa, nxb, s));
@@ -756,7 +775,7 @@ ur_status ur_simulate_host(ur_plan* p, const void* rho_host, int32_t x_lo, int32
   xa.B = B; xa.bx0 = bx0; xa.bs = bs; xa.tw = p->tw; xa.nkz = p->nkz; xa.r2c = 1;
   xa.xa = (int)bx0; xa.xb = (int)(bx0 + bs - 1);
   xa.iscale = 1.0 / ((double)n * n * n) / ((double)n * n * n);
-  xa.nbins = p->nbins; xa.U = p->dU; xa.part = (double*)(p->ws + lay.part); xa.f0 = (double*)(p->ws + lay.f0);
+  xa.nbins = p->nbins; xa.U = p->dU; xa.lut = p->dLut; xa.nlut = p->nlut; xa.part = (double*)(p->ws + lay.part); xa.f0 = (double*)(p->ws + lay.f0);
   xa.ncols = p->nkz * n;
   UR_HIP(launch_pass_x(p->prec, n, X_FFT_BIN, -1, xa, x_blocks(p), s));
   FinArgs fa{};

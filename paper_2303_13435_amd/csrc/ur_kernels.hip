@@ -747,6 +747,7 @@ k_pass_x(XArgs a) {
   double* hist = dyn;                                  // 2 * nbins
   double* tot_s = dyn + 2 * (size_t)a.nbins;
   int* U = (int*)(dyn + 2 * (size_t)a.nbins + 1);      // nbins + 2 (last: sentinel)
+  short* Ls = (short*)(U + a.nbins + 2);               // nlut: bin of n2 = s^2
 
   // G >= 64: every wavefront lies in one column, wave-uniform column index.
   // For G > 64 the column syncs are workgroup barriers: the launcher makes
@@ -761,6 +762,7 @@ k_pass_x(XArgs a) {
   if (BIN) {
     for (int i = threadIdx.x; i < 2 * a.nbins + 1; i += C::threads) dyn[i] = 0.0;
     for (int i = threadIdx.x; i <= a.nbins; i += C::threads) U[i] = a.U[i];
+    for (int i = threadIdx.x; i < a.nlut; i += C::threads) Ls[i] = a.lut[i];
     if (threadIdx.x == 0) U[a.nbins + 1] = 0x7fffffff;
     __syncthreads();
   }
@@ -798,8 +800,15 @@ k_pass_x(XArgs a) {
     // and the conjugate weight w are applied once per run.
     constexpr int NH = G == 1 ? N / 2 : E / 2;
     const int hlo = G == 1 ? 0 : g * NH;
-    int b = bin_search(U, a.nbins, (long long)hlo * hlo + base);
+    // starting bin: the table entry of s = isqrt(n2) (the bin of s^2 <= n2),
+    // then forward over the few thresholds between s^2 and n2
+    const int n20 = hlo * hlo + base;
+    int sq = (int)sqrtf((float)n20);
+    if (sq * sq > n20) --sq;
+    else if ((sq + 1) * (sq + 1) <= n20) ++sq;
+    int b = Ls[sq];
     int nextU = U[b + 1];
+    while (n20 >= nextU) { ++b; nextU = U[b + 1]; }
     int cb = b;
     T cs = (T)0, ct = (T)0;
     double cs2 = 0.0;
@@ -1469,15 +1478,16 @@ hipError_t launch_pass_y(int prec, int n, const YArgs& a, hipStream_t s) {
 #undef UR_Y
 }
 
-static size_t x_shm(int mode, int nbins) {
-  return mode == X_FFT_STORE ? 0 : (2 * (size_t)nbins + 1) * sizeof(double) + ((size_t)nbins + 2) * sizeof(int);
+static size_t x_shm(int mode, int nbins, int n) {
+  return mode == X_FFT_STORE ? 0 : (2 * (size_t)nbins + 1) * sizeof(double) + ((size_t)nbins + 2) * sizeof(int)
+                                    + (size_t)lut_len(n) * sizeof(short);
 }
 
 template <typename T, int N>
 static int x_resident_t(int mode, int dir, int nbins) {
   int nb = 0;
   hipError_t e;
-  size_t shm = x_shm(mode, nbins);
+  size_t shm = x_shm(mode, nbins, N);
   if (mode == X_FFT_BIN) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pass_x<T, N, X_FFT_BIN, -1>, XCfg<N>::threads, shm);
   else if (mode == X_BIN_ONLY) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pass_x<T, N, X_BIN_ONLY, -1>, XCfg<N>::threads, shm);
   else if (dir < 0) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pass_x<T, N, X_FFT_STORE, -1>, XCfg<N>::threads, shm);
@@ -1510,7 +1520,7 @@ hipError_t launch_bin_counts(int n, int nkz, int r2c, int nbins, const int* U, u
 
 template <typename T, int N>
 static hipError_t pass_x_t(int mode, int dir, const XArgs& a, int nblocks, hipStream_t s) {
-  size_t shm = x_shm(mode, a.nbins);
+  size_t shm = x_shm(mode, a.nbins, N);
   // columns spanning several wavefronts sync with workgroup barriers: every
   // group of a block must run the same number of iterations
   if (XCfg<N>::G > 64 && a.ncols % XCfg<N>::NG != 0) return hipErrorInvalidValue;

@@ -49,6 +49,14 @@ struct YArgs {
   int ty;                   // y tile height of the z pass
 };
 
+// entries of the start-of-walk bin table of an n^3 box: s = 0 .. isqrt(3 (n/2)^2) + 1
+inline int lut_len(int n) {
+  const long long n2max = 3ll * (n / 2) * (n / 2);
+  long long s = 0;
+  while ((s + 1) * (s + 1) <= n2max) ++s;
+  return (int)s + 2;
+}
+
 struct XArgs {
   const void* B;            // [kz][ky][x - bx0] columns of stride bs
   long long bx0;
@@ -62,6 +70,8 @@ struct XArgs {
   double oscale;            // store scale
   int nbins;
   const int* U;             // nbins + 1 integer thresholds on n2
+  const short* lut;         // bin of n2 = s^2 for s in [0, nlut): start of the bin walk
+  int nlut;
   double* part;             // per block: 2*nbins (sum, sumsq) + 1 total
   double* f0;               // F(0) (2 doubles), written by the block holding it
   int ncols;
