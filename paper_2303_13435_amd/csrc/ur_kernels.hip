@@ -330,7 +330,7 @@ k_pass_z(ZArgs a) {
   constexpr int G = C::G, NG = C::NG, TY = C::TY, E = Geo<N>::E;
   constexpr int R0 = Radix<N, 1>::r, NB0 = E / R0, PS = CS<N>::v;
   __shared__ cx<T> sm[NG * PS];
-  __shared__ double red[2 * (C::threads / 64 + 1)];
+  __shared__ double red[C::threads];                   // per-lane sums of rho^2
 
   const int tile = blockIdx.x % a.ntiles;
   const long long X = a.x0 + blockIdx.x / a.ntiles;
@@ -476,17 +476,19 @@ k_pass_z(ZArgs a) {
 
   fft_column<T, N, -1>(s, g, tw, v);
 
-  if (a.mom) {
-    constexpr int W = C::threads < 64 ? C::threads : 64;
-    m2 = wave_sum<W>(m2);
-    if ((threadIdx.x & 63) == 0) { red[2 * (threadIdx.x >> 6)] = 0.0; red[2 * (threadIdx.x >> 6) + 1] = m2; }
-  }
+  // block sum of rho^2: lane partials through LDS (the barrier is needed by
+  // the write-out anyway), then one wavefront sums them in a fixed order
+  if (a.mom) red[threadIdx.x] = m2;
   __syncthreads();
-  if (a.mom && threadIdx.x == 0) {
-    double s1 = 0.0, s2 = 0.0;
-    for (int w = 0; w < (C::threads + 63) / 64; ++w) { s1 += red[2 * w]; s2 += red[2 * w + 1]; }
-    a.mom[2 * blockIdx.x] = s1;
-    a.mom[2 * blockIdx.x + 1] = s2;
+  if (a.mom && threadIdx.x < 64) {
+    constexpr int W = C::threads < 64 ? C::threads : 64;
+    double t = 0.0;
+    for (int i = threadIdx.x; i < C::threads; i += 64) t += red[i];
+    t = wave_sum<W>(t);
+    if (threadIdx.x == 0) {
+      a.mom[2 * blockIdx.x] = 0.0;
+      a.mom[2 * blockIdx.x + 1] = t;
+    }
   }
 
   cx<T>* Ap = A + ((size_t)(X - a.ax0) * a.nkz) * N + y0;
@@ -741,13 +743,18 @@ template <typename T, int N, int MODE, int DIR>
 __global__ void __launch_bounds__((XCfg<N>::threads))
 k_pass_x(XArgs a) {
   using C = XCfg<N>;
-  constexpr int G = C::G, NG = C::NG, E = Geo<N>::E, PS = CS<N>::v;
+  // every wavefront reads only its own column: no bank skew between columns
+  // is needed, the column stride is the padded length itself (this keeps
+  // the FP64 block within the LDS of two blocks per CU)
+  constexpr int G = C::G, NG = C::NG, E = Geo<N>::E, PS = Padded<N>::size;
   __shared__ cx<T> sm[NG * PS];
   extern __shared__ double dyn[];
-  double* hist = dyn;                                  // 2 * nbins
-  double* tot_s = dyn + 2 * (size_t)a.nbins;
-  int* U = (int*)(dyn + 2 * (size_t)a.nbins + 1);      // nbins + 2 (last: sentinel)
-  short* Ls = (short*)(U + a.nbins + 2);               // nlut: bin of n2 = s^2
+  // hist[2 b], hist[2 b + 1] for b in [-1, nbins]: the two outer slots take
+  // the runs below the first and above the last threshold (discarded)
+  double* hist = dyn + 2;
+  double* tot_s = dyn + 2 * ((size_t)a.nbins + 2);
+  int* U = (int*)(tot_s + 1);                          // nbins + 3 (last two: sentinels)
+  short* Ls = (short*)(U + a.nbins + 3);               // nlut: bin of n2 = s^2
 
   // G >= 64: every wavefront lies in one column, wave-uniform column index.
   // For G > 64 the column syncs are workgroup barriers: the launcher makes
@@ -760,10 +767,10 @@ k_pass_x(XArgs a) {
   constexpr bool BIN = MODE != X_FFT_STORE;
 
   if (BIN) {
-    for (int i = threadIdx.x; i < 2 * a.nbins + 1; i += C::threads) dyn[i] = 0.0;
+    for (int i = threadIdx.x; i < 2 * (a.nbins + 2) + 1; i += C::threads) dyn[i] = 0.0;
     for (int i = threadIdx.x; i <= a.nbins; i += C::threads) U[i] = a.U[i];
     for (int i = threadIdx.x; i < a.nlut; i += C::threads) Ls[i] = a.lut[i];
-    if (threadIdx.x == 0) U[a.nbins + 1] = 0x7fffffff;
+    if (threadIdx.x == 0) { U[a.nbins + 1] = 0x7fffffff; U[a.nbins + 2] = 0x7fffffff; }
     __syncthreads();
   }
   double tot = 0.0;
@@ -809,6 +816,7 @@ k_pass_x(XArgs a) {
     int b = Ls[sq];
     int nextU = U[b + 1];
     while (n20 >= nextU) { ++b; nextU = U[b + 1]; }
+    int nextU2 = U[b + 2];                               // one threshold ahead, off the critical path
     int cb = b;
     T cs = (T)0, ct = (T)0;
     double cs2 = 0.0;
@@ -817,14 +825,15 @@ k_pass_x(XArgs a) {
     auto take = [&](int ha, T q1, T q2) {
       const int n2 = ha * ha + base;
       if (n2 >= nextU) {
-        if (cb >= 0 && cb < a.nbins) {
-          atomicAdd(&hist[2 * cb + 0], (double)cs * ws);
-          atomicAdd(&hist[2 * cb + 1], cs2 * ws2);
-        }
+        atomicAdd(&hist[2 * cb + 0], (double)cs * ws);
+        atomicAdd(&hist[2 * cb + 1], cs2 * ws2);
         ct += cs;
         cs = (T)0;
         cs2 = 0.0;
-        do { ++b; nextU = U[b + 1]; } while (n2 >= nextU);
+        ++b;
+        nextU = nextU2;
+        while (n2 >= nextU) { ++b; nextU = U[b + 1]; }     // several thresholds at once (rare)
+        nextU2 = U[b + 2];
         cb = b;
       }
       const double d1 = (double)q1, d2 = (double)q2;
@@ -847,10 +856,8 @@ k_pass_x(XArgs a) {
       const cx<T> f1 = s[pad(N / 2)];
       take(N / 2, f1.x * f1.x + f1.y * f1.y, (T)0);
     }
-    if (cb >= 0 && cb < a.nbins) {
-      atomicAdd(&hist[2 * cb + 0], (double)cs * ws);
-      atomicAdd(&hist[2 * cb + 1], cs2 * ws2);
-    }
+    atomicAdd(&hist[2 * cb + 0], (double)cs * ws);
+    atomicAdd(&hist[2 * cb + 1], cs2 * ws2);
     tot += (double)(ct + cs) * ws;
     if (col == 0 && g == 0 && a.f0) {
       const cx<T> f = s[pad(0)];
@@ -864,7 +871,7 @@ k_pass_x(XArgs a) {
   if ((threadIdx.x & 63) == 0) atomicAdd(tot_s, tot);
   __syncthreads();
   double* out = a.part + (size_t)blockIdx.x * (2 * (size_t)a.nbins + 1);
-  for (int i = threadIdx.x; i < 2 * a.nbins + 1; i += C::threads) out[i] = dyn[i];
+  for (int i = threadIdx.x; i < 2 * a.nbins + 1; i += C::threads) out[i] = i < 2 * a.nbins ? hist[i] : *tot_s;
 }
 
 // voxel count per bin (geometry only): one thread per (ky, kz) column walks
@@ -1479,7 +1486,7 @@ hipError_t launch_pass_y(int prec, int n, const YArgs& a, hipStream_t s) {
 }
 
 static size_t x_shm(int mode, int nbins, int n) {
-  return mode == X_FFT_STORE ? 0 : (2 * (size_t)nbins + 1) * sizeof(double) + ((size_t)nbins + 2) * sizeof(int)
+  return mode == X_FFT_STORE ? 0 : (2 * (size_t)nbins + 5) * sizeof(double) + ((size_t)nbins + 3) * sizeof(int)
                                     + (size_t)lut_len(n) * sizeof(short);
 }
 
