@@ -849,7 +849,7 @@ ur_status ur_adjoint(ur_plan* p, const void* rho, const ur_cell* cell, const ur_
   xj.xa = (int)fx0; xj.xb = g.xlo <= g.xhi ? (int)((g.xhi / tx) * tx + tx - 1) : -1;
   xj.oa = amp_only ? (int)bx0 : 0;
   xj.ob = amp_only ? (int)(bx0 + bs - 1) : n - 1;
-  xj.nbins = p->nbins; xj.U = p->dU; xj.g_bin = g_bin; xj.count = fwd->count;
+  xj.nbins = p->nbins; xj.U = p->dU; xj.lut = p->dLut; xj.nlut = p->nlut; xj.g_bin = g_bin; xj.count = fwd->count;
   xj.gscale = 2.0 / ((double)n * n * n) / ((double)n * n * n); xj.ncols = p->nkz * n;
   UR_HIP(launch_pass_x_adj(p->prec, n, xj, x_blocks(p), s));
   YInvArgs yi{};

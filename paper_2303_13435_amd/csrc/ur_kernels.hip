@@ -1085,13 +1085,21 @@ k_pass_x_adj(XAdjArgs a) {
   constexpr int R0 = Radix<N, 1>::r, NB0 = E / R0, PS = CS<N>::v;
   __shared__ cx<T> sm[NG * PS];
   extern __shared__ double dyn[];
-  double* Gb = dyn;                                   // nbins
-  int* U = (int*)(dyn + a.nbins);                     // nbins + 1
-  for (int i = threadIdx.x; i < a.nbins; i += C::threads)
-    Gb[i] = a.count[i] > 0.0 ? a.g_bin[i] / a.count[i] * a.gscale : 0.0;
+  // G(b) for b in [-1, nbins] (the two outer slots are zero), thresholds with
+  // a sentinel, and the start-of-walk table of the bins (as in the x pass)
+  double* Gb = dyn + 1;
+  int* U = (int*)(dyn + a.nbins + 2);                 // nbins + 2
+  short* Ls = (short*)(U + a.nbins + 2);              // nlut
+  for (int i = threadIdx.x; i < a.nbins + 2; i += C::threads) {
+    const int b = i - 1;
+    dyn[i] = (b >= 0 && b < a.nbins && a.count[b] > 0.0) ? a.g_bin[b] / a.count[b] * a.gscale : 0.0;
+  }
   for (int i = threadIdx.x; i <= a.nbins; i += C::threads) U[i] = a.U[i];
+  for (int i = threadIdx.x; i < a.nlut; i += C::threads) Ls[i] = a.lut[i];
+  if (threadIdx.x == 0) U[a.nbins + 1] = 0x7fffffff;
   __syncthreads();
-  const int q = threadIdx.x / G, g = threadIdx.x % G;
+  const int q = G >= 64 ? __builtin_amdgcn_readfirstlane(threadIdx.x / G) : threadIdx.x / G;
+  const int g = threadIdx.x % G;
   cx<T>* s = sm + q * PS;
   const cx<T>* tw = (const cx<T>*)a.tw;
 
@@ -1099,31 +1107,52 @@ k_pass_x_adj(XAdjArgs a) {
     const int kz = (int)(col / N), ky = (int)(col % N);
     cx<T>* src = (cx<T>*)a.B + (size_t)col * a.bs - a.bx0;
     cx<T> v[E];
+    if constexpr (G >= 64) {
+      load_column_u<T, N>(src, a.xa, a.xb, g, v);
+    } else {
 #pragma unroll
-    for (int i = 0; i < NB0; ++i)
+      for (int i = 0; i < NB0; ++i)
 #pragma unroll
-      for (int r = 0; r < R0; ++r) {
-        int x = first_index<N>(g, i, r);
-        v[i * R0 + r] = (x >= a.xa && x <= a.xb) ? src[x] : mk((T)0, (T)0);
-      }
+        for (int r = 0; r < R0; ++r) {
+          int x = first_index<N>(g, i, r);
+          v[i * R0 + r] = (x >= a.xa && x <= a.xb) ? src[x] : mk((T)0, (T)0);
+        }
+    }
     fft_column<T, N, -1>(s, g, tw, v);
     const int k = sidx(ky, N);
     const int l = a.r2c ? kz : sidx(kz, N);
-    const long long base = (long long)k * k + (long long)l * l;
-    int hlo, hhi;
-    if (G == 1) { hlo = 0; hhi = N / 2 + 1; }
-    else { hlo = g * (E / 2); hhi = (g == G - 1) ? N / 2 + 1 : hlo + E / 2; }
-    int b = bin_search(U, a.nbins, (long long)hlo * hlo + base);
-    for (int ha = hlo; ha < hhi; ++ha) {
-      const long long n2 = (long long)ha * ha + base;
-      b = bin_advance(U, a.nbins, b, n2);
-      const double gv = (b >= 0 && b < a.nbins) ? Gb[b] : 0.0;
-      cx<T> f = s[pad(ha)];
-      s[pad(ha)] = mk((T)(f.x * gv), (T)(f.y * gv));
-      if (ha != 0 && ha != N / 2) {
-        cx<T> f2 = s[pad(N - ha)];
+    const int base = k * k + l * l;
+    // lane g owns |h| in [hlo, hlo + NH) (both signs), the last lane also
+    // |h| = N/2; the bin walk starts from the table entry of isqrt(n2)
+    constexpr int NH = G == 1 ? N / 2 : E / 2;
+    const int hlo = G == 1 ? 0 : g * NH;
+    const int n20 = hlo * hlo + base;
+    int sq = (int)sqrtf((float)n20);
+    if (sq * sq > n20) --sq;
+    else if ((sq + 1) * (sq + 1) <= n20) ++sq;
+    int b = Ls[sq];
+    int nextU = U[b + 1];
+    while (n20 >= nextU) { ++b; nextU = U[b + 1]; }
+    double gv = Gb[b];
+    cx<T>* sp = s + pad(hlo);
+#pragma unroll
+    for (int t = 0; t < NH; ++t) {
+      const int ha = hlo + t;
+      const int n2 = ha * ha + base;
+      while (n2 >= nextU) { ++b; nextU = U[b + 1]; gv = Gb[b]; }
+      cx<T>* p1 = (NH <= 16 || G == 1) ? sp + t + (G == 1 ? (t >> 4) : 0) : s + pad(ha);
+      const cx<T> f = *p1;
+      *p1 = mk((T)(f.x * gv), (T)(f.y * gv));
+      if (ha != 0) {
+        const cx<T> f2 = s[pad(N - ha)];
         s[pad(N - ha)] = mk((T)(f2.x * gv), (T)(f2.y * gv));
       }
+    }
+    if (g == G - 1) {                                      // |h| = N/2 (kx = N/2 only)
+      const int n2 = (N / 2) * (N / 2) + base;
+      while (n2 >= nextU) { ++b; nextU = U[b + 1]; gv = Gb[b]; }
+      const cx<T> f = s[pad(N / 2)];
+      s[pad(N / 2)] = mk((T)(f.x * gv), (T)(f.y * gv));
     }
     col_sync<G>();
     stages_from<T, N, 1, +1>(s, g, tw);
@@ -1141,13 +1170,30 @@ k_pass_y_inv(YInvArgs a) {
   using C = YICfg<T, N>;
   constexpr int G = C::G, TX = C::TX, PS = CS<N>::v;
   __shared__ cx<T> sm[TX * PS];
-  const int kz = blockIdx.x % a.nkz;
-  const int xt = a.xt0 + blockIdx.x / a.nkz;
+  // x tile fastest: the blocks resident together read whole B rows
+  const int xt = a.xt0 + blockIdx.x % a.nxt;
+  const int kz = blockIdx.x / a.nxt;
   const int xbase = xt * TX;
   const cx<T>* Bp = (const cx<T>*)a.B + ((size_t)kz * N) * a.bs + (xbase - a.bx0);
-  for (int idx = threadIdx.x; idx < TX * N; idx += C::threads) {
-    const int j = idx % TX, ky = idx / TX;
-    sm[j * PS + pad(ky)] = Bp[(size_t)ky * a.bs + j];
+  // transposed read of the tile: all loads of a thread are issued before
+  // its LDS stores (a load-store loop would wait on every load in turn)
+  {
+    constexpr int IT = TX * N / C::threads;
+    static_assert(IT * C::threads == TX * N, "the tile is a whole number of block sweeps");
+    T rx[IT], ry[IT];
+#pragma unroll
+    for (int k = 0; k < IT; ++k) {
+      const int idx = threadIdx.x + k * C::threads, j = idx % TX, ky = idx / TX;
+      const cx<T> e = Bp[(size_t)ky * a.bs + j];
+      rx[k] = e.x;
+      ry[k] = e.y;
+    }
+#pragma unroll
+    for (int k = 0; k < IT; ++k) {
+      const int idx = threadIdx.x + k * C::threads, j = idx % TX, ky = idx / TX;
+      sm[j * PS + pad(ky)].x = rx[k];
+      sm[j * PS + pad(ky)].y = ry[k];
+    }
   }
   __syncthreads();
   const int q = threadIdx.x / G, g = threadIdx.x % G;
@@ -1265,9 +1311,27 @@ k_pass_z_fold(ZFoldArgs a) {
     row_range(a.L, a.m, X, ylo, yhi);
     if (ylo > yhi || y0 + TY - 1 < ylo || y0 > yhi) continue;   // uniform per block
     const cx<T>* Ap = (const cx<T>*)a.A + ((size_t)X * a.nkz) * N + y0;
-    for (int idx = threadIdx.x; idx < TY * HS; idx += C::threads) {
-      const int j = idx % TY, kz = idx / TY;
-      lds[j * HP + kz] = Ap[(size_t)kz * N + j];
+    {
+      // all loads of a thread before its LDS stores
+      constexpr int NST = TY * HS, IT = (NST + C::threads - 1) / C::threads;
+      T rx[IT], ry[IT];
+#pragma unroll
+      for (int k = 0; k < IT; ++k) {
+        const int idx = threadIdx.x + k * C::threads;
+        if (idx < NST) {
+          const cx<T> e = Ap[(size_t)(idx / TY) * N + idx % TY];
+          rx[k] = e.x;
+          ry[k] = e.y;
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < IT; ++k) {
+        const int idx = threadIdx.x + k * C::threads;
+        if (idx < NST) {
+          lds[(idx % TY) * HP + idx / TY].x = rx[k];
+          lds[(idx % TY) * HP + idx / TY].y = ry[k];
+        }
+      }
     }
     __syncthreads();
     cx<T> v[E];
@@ -1301,12 +1365,23 @@ k_pass_z_fold(ZFoldArgs a) {
       col_range(a.L, a.m, X, Y, zlo, zhi);
       const int ci = (int)(X - a.L.o - a.L.h) & cm, cj = (int)(Y - a.L.o - a.L.h) & cm;
       const int zoff = -(a.L.o + a.L.h);
-      for (int z = (int)zlo + g; z <= (int)zhi; z += G) {
-        const cx<T> f = s[pad(z)];
-        const double val = (double)(p2 == 0 ? f.x : f.y) * a.scale;
-        const int idx = (ci * c + cj) * c + ((z + zoff) & cm);
-        if (use_lds) atomicAdd(&acc[idx], val);
-        else atomicAdd(&a.gcell[idx], val);
+      if (use_lds && G % c == 0) {
+        // the voxels of a lane (z = zlo + g + G m) share one cell residue:
+        // sum them in a register, one LDS atomic per lane and pencil
+        double sum = 0.0;
+        for (int z = (int)zlo + g; z <= (int)zhi; z += G) {
+          const cx<T> f = s[pad(z)];
+          sum += (double)(p2 == 0 ? f.x : f.y);
+        }
+        if ((int)zlo + g <= (int)zhi) atomicAdd(&acc[(ci * c + cj) * c + (((int)zlo + g + zoff) & cm)], sum * a.scale);
+      } else {
+        for (int z = (int)zlo + g; z <= (int)zhi; z += G) {
+          const cx<T> f = s[pad(z)];
+          const double val = (double)(p2 == 0 ? f.x : f.y) * a.scale;
+          const int idx = (ci * c + cj) * c + ((z + zoff) & cm);
+          if (use_lds) atomicAdd(&acc[idx], val);
+          else atomicAdd(&a.gcell[idx], val);
+        }
       }
     }
     __syncthreads();                                   // columns done before the next staging
@@ -1566,7 +1641,7 @@ template <typename T, int N>
 static hipError_t pass_x_adj_t(const XAdjArgs& a, int nblocks, hipStream_t s) {
   if (nblocks <= 0) return hipSuccess;
   if constexpr (!inv_fits<T, N>()) { return hipErrorNotSupported; } else {
-  size_t shm = (size_t)a.nbins * sizeof(double) + ((size_t)a.nbins + 1) * sizeof(int);
+  size_t shm = ((size_t)a.nbins + 2) * sizeof(double) + ((size_t)a.nbins + 2) * sizeof(int) + (size_t)a.nlut * sizeof(short);
   hipLaunchKernelGGL((k_pass_x_adj<T, N>), dim3(nblocks), dim3(XCfg<N>::threads), shm, s, a);
   return hipGetLastError();
   }

@@ -123,6 +123,8 @@ struct XAdjArgs {
   int oa, ob;               // rows written back
   int nbins;
   const int* U;
+  const short* lut;         // start-of-walk bin table (as in XArgs)
+  int nlut;
   const double* g_bin;      // dL/dI_b
   const double* count;      // forward bin counts
   double gscale;            // 2 / n^6
