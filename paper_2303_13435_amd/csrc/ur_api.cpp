@@ -864,7 +864,7 @@ ur_status ur_adjoint(ur_plan* p, const void* rho, const ur_cell* cell, const ur_
       zf.A = A; zf.tw = p->tw; zf.L = g.L; zf.m = g.m; zf.nkz = p->nkz; zf.xlo = g.xlo; zf.xhi = g.xhi;
       zf.ntiles = n / zinv_tile(p->prec, n, 0); zf.scale = 1.0; zf.part = t.fold_part; zf.gcell = t.gcell;
       UR_HIP(launch_pass_z_fold(p->prec, n, zf, kFoldBlocks, s));
-      if (c <= 16) UR_HIP(launch_fold_reduce(c3, t.fold_part, kFoldBlocks, t.gcell, s));
+      if (c <= 16) UR_HIP(launch_fold_reduce_classes(c, t.fold_part, kFoldBlocks, t.gcell, s));
     } else if (c <= 16) {
       UR_HIP(launch_zero(t.gcell, (size_t)c3 * 8, s));
     }

@@ -1297,15 +1297,24 @@ k_pass_z_fold(ZFoldArgs a) {
   constexpr int HP = HS + 1;
   constexpr int STG = TY * HP > NG * PS ? TY * HP : NG * PS;
   __shared__ cx<T> lds[STG];
-  extern __shared__ double acc[];                      // c^3 (c <= 16)
-  const int c = a.L.c, c3 = c * c * c, cm = c - 1;
+  extern __shared__ double acc[];                      // c^2 (c <= 16): [cj][k] of this block's ci
+  const int c = a.L.c, cm = c - 1;
   const bool use_lds = c <= 16;
-  if (use_lds) for (int i = threadIdx.x; i < c3; i += C::threads) acc[i] = 0.0;
+  if (use_lds) for (int i = threadIdx.x; i < c * c; i += C::threads) acc[i] = 0.0;
   __syncthreads();
   const int q = threadIdx.x / G, g = threadIdx.x % G;
-  const long long ntile = (long long)(a.xhi - a.xlo + 1) * a.ntiles;
-  for (long long t = blockIdx.x; t < ntile; t += gridDim.x) {
-    const long long X = a.xlo + t / a.ntiles;
+  // c <= 16: block b takes only the planes whose cell index is ci = b mod c
+  // (the grid is a multiple of c), so its accumulator is one c x c slice;
+  // otherwise every block strides over all tiles (global accumulation)
+  const int ci_b = use_lds ? (int)(blockIdx.x % c) : 0;
+  const long long X0 = use_lds ? a.xlo + ((ci_b - (a.xlo - a.L.o - a.L.h)) & cm) : a.xlo;
+  const long long xstep = use_lds ? c : 1;
+  const long long np = X0 <= a.xhi ? (a.xhi - X0) / xstep + 1 : 0;
+  const long long ntile = np * a.ntiles;
+  const long long t0 = use_lds ? blockIdx.x / c : blockIdx.x;
+  const long long tstep = use_lds ? gridDim.x / c : gridDim.x;
+  for (long long t = t0; t < ntile; t += tstep) {
+    const long long X = X0 + (t / a.ntiles) * xstep;
     const int y0 = (int)(t % a.ntiles) * TY;
     long long ylo, yhi;
     row_range(a.L, a.m, X, ylo, yhi);
@@ -1373,14 +1382,13 @@ k_pass_z_fold(ZFoldArgs a) {
           const cx<T> f = s[pad(z)];
           sum += (double)(p2 == 0 ? f.x : f.y);
         }
-        if ((int)zlo + g <= (int)zhi) atomicAdd(&acc[(ci * c + cj) * c + (((int)zlo + g + zoff) & cm)], sum * a.scale);
+        if ((int)zlo + g <= (int)zhi) atomicAdd(&acc[cj * c + (((int)zlo + g + zoff) & cm)], sum * a.scale);
       } else {
         for (int z = (int)zlo + g; z <= (int)zhi; z += G) {
           const cx<T> f = s[pad(z)];
           const double val = (double)(p2 == 0 ? f.x : f.y) * a.scale;
-          const int idx = (ci * c + cj) * c + ((z + zoff) & cm);
-          if (use_lds) atomicAdd(&acc[idx], val);
-          else atomicAdd(&a.gcell[idx], val);
+          if (use_lds) atomicAdd(&acc[cj * c + ((z + zoff) & cm)], val);
+          else atomicAdd(&a.gcell[(ci * c + cj) * c + ((z + zoff) & cm)], val);
         }
       }
     }
@@ -1388,8 +1396,8 @@ k_pass_z_fold(ZFoldArgs a) {
   }
   if (use_lds) {
     __syncthreads();
-    double* out = a.part + (size_t)blockIdx.x * c3;
-    for (int i = threadIdx.x; i < c3; i += C::threads) out[i] = acc[i];
+    double* out = a.part + (size_t)blockIdx.x * c * c;
+    for (int i = threadIdx.x; i < c * c; i += C::threads) out[i] = acc[i];
   }
 }
 
@@ -1702,8 +1710,8 @@ hipError_t launch_fold(int prec, int n, const FoldArgs& a, int nblocks, hipStrea
 template <typename T, int N>
 static hipError_t pass_z_fold_t(const ZFoldArgs& a, int nblocks, hipStream_t s) {
   if constexpr (!inv_fits<T, N>()) { return hipErrorNotSupported; } else {
-    const int c3 = a.L.c * a.L.c * a.L.c;
-    size_t shm = a.L.c <= 16 ? (size_t)c3 * sizeof(double) : 0;
+    if (a.L.c <= 16 && nblocks % a.L.c != 0) return hipErrorInvalidValue;   // blocks per cell class
+    size_t shm = a.L.c <= 16 ? (size_t)a.L.c * a.L.c * sizeof(double) : 0;
     hipLaunchKernelGGL((k_pass_z_fold<T, N>), dim3(nblocks), dim3(ZICfg<T, N, false>::threads), shm, s, a);
     return hipGetLastError();
   }
@@ -1713,6 +1721,23 @@ hipError_t launch_pass_z_fold(int prec, int n, const ZFoldArgs& a, int nblocks, 
 #define UR_ZF(NN) return prec == 0 ? pass_z_fold_t<float, NN>(a, nblocks, s) : pass_z_fold_t<double, NN>(a, nblocks, s)
   UR_DISPATCH_N(n, UR_ZF);
 #undef UR_ZF
+}
+
+// gcell[(ci c + cj) c + k] = sum over the blocks of class ci (b = r c + ci)
+// of their slice partial [cj][k], in a fixed order
+__global__ void k_fold_reduce_classes(int c, const double* __restrict__ part, int nblk, double* __restrict__ gcell) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  const int c2 = c * c;
+  if (v >= c2 * c) return;
+  const int ci = v / c2, rest = v % c2;
+  Kahan k;
+  for (int b = ci; b < nblk; b += c) k.add(part[(size_t)b * c2 + rest]);
+  gcell[v] = k.val();
+}
+
+hipError_t launch_fold_reduce_classes(int c, const double* part, int nblk, double* gcell, hipStream_t s) {
+  hipLaunchKernelGGL(k_fold_reduce_classes, dim3(nblk_of((long long)c * c * c, 256)), dim3(256), 0, s, c, part, nblk, gcell);
+  return hipGetLastError();
 }
 
 hipError_t launch_fold_reduce(int c3, const double* part, int nblk, double* gcell, hipStream_t s) {
