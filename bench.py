@@ -215,8 +215,9 @@ def main():
                     help="only run a plain 1 GiB device copy (reference kernel for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported by this build "
-              f"(the path runs on a single MI355X; multi-GPU sharding is design-only)", file=sys.stderr)
+        print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported "
+              f"(the path runs on a single MI355X; sharding over several GPUs is described, not built)",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -28,7 +28,8 @@
  *     device, owned by the caller; HOST pointers are read during the call
  *     only.  The library never frees caller memory.
  *   - Box layout: real densities are [x][y][z] row-major, z fastest, edge n
- *     (a power of two, 16 <= n <= 4096).  The particle and the lattice are
+ *     (a power of two, 16 <= n <= 2048; complex transforms, inverse
+ *     transforms and the adjoint: n <= 1024).  The particle and the lattice are
  *     centred on voxel (n1/2, n1/2, n1/2) of the ED-1 grid.
  *   - Spectra exchanged through ur_fft3d_exec / ur_intensity_bin use the
  *     transposed layout [kz][ky][kx] (kx fastest, complex interleaved), with
@@ -50,7 +51,7 @@ extern "C" {
 typedef enum {
   UR_OK = 0,
   UR_ERR_INVALID = 1,      /* bad argument (null pointer, size, range)        */
-  UR_ERR_UNSUPPORTED = 2,  /* valid request this build does not implement     */
+  UR_ERR_UNSUPPORTED = 2,  /* valid request the library does not implement  */
   UR_ERR_OOM = 3,          /* device allocation failed                        */
   UR_ERR_HIP = 4,          /* a HIP runtime call failed                       */
   UR_ERR_STATE = 6         /* call out of order (e.g. no bins set on the plan) */
@@ -113,7 +114,10 @@ typedef struct ur_plan ur_plan;
 /* Create a plan for an n^3 box of voxel edge `voxel` (nm, > 0) in precision
  * `prec`.  flags: UR_R2C or UR_C2C.  Allocates the plan's device tables
  * (twiddles) with hipMalloc; the large work buffers are either attached with
- * ur_plan_set_workspace or allocated lazily on first use. */
+ * ur_plan_set_workspace or allocated lazily on first use.  Errors:
+ * UR_ERR_INVALID for n not a power of two, a voxel that is not positive and
+ * finite, or an unknown precision; UR_ERR_UNSUPPORTED for n above 2048, or
+ * a complex (UR_C2C) plan above 1024. */
 ur_status ur_plan_create(int32_t n, double voxel, int32_t prec, uint32_t flags, ur_plan** out);
 void ur_plan_destroy(ur_plan* plan);
 

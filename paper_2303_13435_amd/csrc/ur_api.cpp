@@ -270,7 +270,7 @@ ur_status ur_plan_create(int32_t n, double voxel, int32_t prec, uint32_t flags, 
   if (!out) return fail(UR_ERR_INVALID, "out is null");
   *out = nullptr;
   if (!is_pow2(n) || n < 16) return fail(UR_ERR_INVALID, "n = %d must be a power of two >= 16", n);
-  if (n > 2048) return fail(UR_ERR_UNSUPPORTED, "n = %d: this build runs boxes up to 2048^3", n);
+  if (n > 2048) return fail(UR_ERR_UNSUPPORTED, "n = %d: boxes run up to 2048^3", n);
   if (n > 1024 && (flags & UR_C2C)) return fail(UR_ERR_UNSUPPORTED, "complex transforms run up to 1024^3");
   if (!(voxel > 0.0) || !isfinite(voxel)) return fail(UR_ERR_INVALID, "voxel must be positive");
   if (prec != UR_F32 && prec != UR_F64) return fail(UR_ERR_INVALID, "prec must be UR_F32 or UR_F64");
