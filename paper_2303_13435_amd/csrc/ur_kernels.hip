@@ -514,15 +514,34 @@ k_pass_z(ZArgs a) {
     // to tile column 2p, B_k = (Z_k - conj Z_{N-k}) / (2i) to column 2p + 1,
     // k in [0, N/2]; one thread writes both (adjacent) outputs
     constexpr int KP = C::threads / NG;                 // kz stride (>= 1: threads = NG G)
-    const int p = threadIdx.x % NG;
+    const int p = threadIdx.x % NG, kz0 = threadIdx.x / NG;
     const cx<T>* col = sm + p * PS;
-    cx2<T>* dst = (cx2<T>*)(Ap + (size_t)(threadIdx.x / NG) * N + 2 * p);
-    for (int kz = threadIdx.x / NG; kz <= N / 2; kz += KP, dst += (size_t)KP * N / 2) {
-      const cx<T> zk = col[pad(kz)], zm = col[pad((N - kz) & (N - 1))];
+    cx2<T>* dst = (cx2<T>*)(Ap + (size_t)kz0 * N + 2 * p);
+    auto unpack = [](cx<T> zk, cx<T> zm) {
       cx2<T> o;
       o.a = mk((zk.x + zm.x) * (T)0.5, (zk.y - zm.y) * (T)0.5);
       o.b = mk((zk.y + zm.y) * (T)0.5, (zm.x - zk.x) * (T)0.5);
-      st_nt2(dst, o);
+      return o;
+    };
+    if constexpr (KP % 16 == 0) {
+      // kz = kz0 + KP m and N - kz step by multiples of 16: both LDS reads
+      // are one padded base plus a compile-time offset
+      constexpr int M = (N / 2) / KP, DK = KP + KP / 16;
+      const cx<T>* zkb = col + pad(kz0);
+      const cx<T>* zmb = col + pad(N - kz0);             // kz0 = 0, m = 0 wraps to Z_0 (below)
+#pragma unroll
+      for (int m = 0; m < M; ++m, dst += (size_t)KP * N / 2) {
+        const cx<T> zk = zkb[m * DK];
+        const cx<T> zm = (m == 0 && kz0 == 0) ? col[0] : zmb[-m * DK];
+        st_nt2(dst, unpack(zk, zm));
+      }
+      if (kz0 == 0) {                                      // kz = N/2 (self-conjugate)
+        const cx<T> zh = col[pad(N / 2)];
+        st_nt2(dst, unpack(zh, zh));
+      }
+    } else {
+      for (int kz = kz0; kz <= N / 2; kz += KP, dst += (size_t)KP * N / 2)
+        st_nt2(dst, unpack(col[pad(kz)], col[pad((N - kz) & (N - 1))]));
     }
   } else {
     const cx<T>* col = sm + j * PS;
