@@ -79,7 +79,27 @@ def cpu_baseline(budget_s: float = 30.0):
     dt = time.perf_counter() - t0
     return {"value": wl.n ** 3 / dt, "unit": "voxels/s", "cores": oracle.num_threads(), "kind": "oracle",
             "sample": f"C2 box 512^3 (same cell recipe, sphere R=200, 512 log bins), whole oracle path "
-                      f"in {dt:.1f} s; FFT lines on {oracle.num_threads()} OpenMP threads, binning on 1"}
+                      f"in {dt:.1f} s; FFT lines on {oracle.num_threads()} OpenMP threads, binning on 1",
+            "host": host_info()}
+
+
+def host_info():
+    """CPU model, logical CPUs and memory of the host the oracle ran on."""
+    info = {"nproc": os.cpu_count()}
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    info["cpu"] = line.split(":", 1)[1].strip()
+                    break
+        with open("/proc/meminfo") as f:
+            for line in f:
+                if line.startswith("MemTotal"):
+                    info["ram_gib"] = round(int(line.split()[1]) / 2 ** 20, 1)
+                    break
+    except OSError:
+        pass
+    return info
 
 
 def c3_batch(ur, W, torch, reps):
