@@ -312,6 +312,13 @@ def main():
 
         ms_fa, _ = time_steps(fwd_adj, max(3, args.steps // 2), 2, torch)
         extras["fwd_adjoint_ms"] = round(ms_fa, 4)
+
+        def fwd_adj_keep():
+            plan.simulate(cell, wl.mask, wl.zoom, hist)
+            plan.adjoint_reuse(hist, g_bin, cell, wl.mask, gamp)
+
+        ms_fk, _ = time_steps(fwd_adj_keep, max(3, args.steps // 2), 2, torch)
+        extras["fwd_adjoint_keep_ms"] = round(ms_fk, 4)       # adjoint from the held y-pass output
         torch.cuda.synchronize()
         del fwd_adj
         # multi-zoom batch: ED-1 2048^3 + ED-2 1024^3 (f 4) + ED-3 512^3 (f 16)

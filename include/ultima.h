@@ -197,6 +197,18 @@ ur_status ur_adjoint(ur_plan* plan, const void* rho, const ur_cell* cell, const 
                      const ur_hist* fwd, const double* g_bin, void* grad_rho, double* grad_amp,
                      void* stream);
 
+/* The amplitude gradient of ur_adjoint, starting from the y-pass output that
+ * the preceding ur_simulate call on this plan left in the workspace instead
+ * of recomputing the z and y passes (the forward intermediate is kept rather
+ * than recomputed).  Valid when the last call on the plan was ur_simulate of
+ * an ED-1 box (zoom factor 1) with a real transform, with the same mask and
+ * cell edge (checked: UR_ERR_STATE otherwise) and the same cell contents and
+ * amplitudes (the caller's guarantee: device memory is not inspected).  The
+ * held output is consumed: a second call needs a new ur_simulate.  Arguments
+ * as for ur_adjoint; grad_amp (DEVICE, n_atoms doubles) is required. */
+ur_status ur_adjoint_reuse(ur_plan* plan, const ur_cell* cell, const ur_mask* mask, const ur_hist* fwd,
+                           const double* g_bin, double* grad_amp, void* stream);
+
 /* Merge modes (workflow step 6; dataMerge's rule is not given in the paper,
  * the rule below is this library's reading):
  *   each level's eq.-1 intensities are scaled back to absolute units by

@@ -61,6 +61,7 @@ _SIGS = {
     "ur_simulate_rho": [_vp, _vp, _c.POINTER(UrHist), _vp],
     "ur_simulate_host": [_vp, _vp, _c.c_int32, _c.c_int32, _c.POINTER(UrHist), _vp, _c.POINTER(_c.c_size_t)],
     "ur_adjoint": [_vp, _vp, _c.POINTER(UrCell), _c.POINTER(UrMask), _c.POINTER(UrHist), _vp, _vp, _vp, _vp],
+    "ur_adjoint_reuse": [_vp, _c.POINTER(UrCell), _c.POINTER(UrMask), _c.POINTER(UrHist), _vp, _vp, _vp],
     "ur_merge_zooms": [_c.c_int32, _c.POINTER(UrHist), _c.POINTER(_c.c_int32), _c.POINTER(_c.c_double),
                        _c.c_int32, _vp, _c.c_int32, _c.c_double, _vp, _vp, _vp, _vp],
     "ur_graph_begin": [_vp],
@@ -202,6 +203,7 @@ class Plan:
         _check(lib().ur_plan_create(int(n), float(voxel), int(prec), UR_C2C if c2c else UR_R2C, _c.byref(h)),
                "ur_plan_create")
         self.h = h
+        self.calls = 0          # library calls that touch this plan's workspace
         self.n, self.voxel, self.prec, self.c2c = int(n), float(voxel), int(prec), bool(c2c)
         self.nbins = 0
         self._ws = None
@@ -227,6 +229,7 @@ class Plan:
 
     def set_bins(self, edges: np.ndarray) -> None:
         e = np.ascontiguousarray(edges, dtype=np.float64)
+        self.calls += 1
         _check(lib().ur_plan_set_bins(self.h, int(e.size - 1), e.ctypes.data_as(_c.POINTER(_c.c_double))),
                "ur_plan_set_bins")
         self.nbins = int(e.size - 1)
@@ -254,6 +257,7 @@ class Plan:
         self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
         base = int(self._ws.data_ptr())
         aligned = (base + 255) & ~255
+        self.calls += 1
         _check(lib().ur_plan_set_workspace(self.h, _vp(aligned), _c.c_size_t(nbytes)), "ur_plan_set_workspace")
 
     # -- timing -------------------------------------------------------------
@@ -277,6 +281,7 @@ class Plan:
         ms = mask_struct(mask)
         zs = UrZoom(int(zoom.n1), int(zoom.factor))
         hs = hist.struct()
+        self.calls += 1
         _check(lib().ur_simulate(self.h, _c.byref(cs), _c.byref(ms), _c.byref(zs), _c.byref(hs), _stream(stream)),
                "ur_simulate")
         return hist
@@ -285,6 +290,7 @@ class Plan:
         n = self.n
         _require(rho, self.complex_dtype if self.c2c else self.real_dtype, n ** 3, "rho")
         hs = hist.struct()
+        self.calls += 1
         _check(lib().ur_simulate_rho(self.h, _ptr(rho), _c.byref(hs), _stream(stream)), "ur_simulate_rho")
         return hist
 
@@ -297,6 +303,7 @@ class Plan:
             self._attach(self.workspace_size_host(x_lo, x_hi))
         hs = hist.struct()
         nb = _c.c_size_t()
+        self.calls += 1
         _check(lib().ur_simulate_host(self.h, _ptr(rho_host), int(x_lo), int(x_hi), _c.byref(hs), _stream(stream),
                                       _c.byref(nb)), "ur_simulate_host")
         return int(nb.value)
@@ -307,6 +314,7 @@ class Plan:
             out = torch.empty((self.n,) * 3, dtype=self.real_dtype, device="cuda")
         _require(out, self.real_dtype, self.n ** 3, "out")
         cs, ms, zs = cell.struct(), mask_struct(mask), UrZoom(int(zoom.n1), int(zoom.factor))
+        self.calls += 1
         _check(lib().ur_rho_generate(self.h, _c.byref(cs), _c.byref(ms), _c.byref(zs), _ptr(out), _stream(stream)),
                "ur_rho_generate")
         return out
@@ -316,6 +324,7 @@ class Plan:
         if out is None:
             out = torch.empty((cell.c,) * 3, dtype=torch.float64, device="cuda")
         cs = cell.struct()
+        self.calls += 1
         _check(lib().ur_cell_synth(self.h, _c.byref(cs), _ptr(out), _stream(stream)), "ur_cell_synth")
         return out
 
@@ -338,12 +347,14 @@ class Plan:
             _require(out, self.complex_dtype if self.c2c else self.real_dtype, n ** 3, "output")
         if self.nbins == 0:
             self._attach(self.workspace_size(1))
+        self.calls += 1
         _check(lib().ur_fft3d_exec(self.h, _ptr(x), _ptr(out), int(direction), _stream(stream)), "ur_fft3d_exec")
         return out
 
     def intensity_bin(self, spectrum, hist: Hist, stream=None) -> Hist:
         _require(spectrum, self.complex_dtype, self.nkz() * self.n ** 2, "spectrum")
         hs = hist.struct()
+        self.calls += 1
         _check(lib().ur_intensity_bin(self.h, _ptr(spectrum), _c.byref(hs), _stream(stream)), "ur_intensity_bin")
         return hist
 
@@ -353,10 +364,22 @@ class Plan:
         hs = fwd.struct()
         cs = cell.struct(amp) if cell is not None else None
         ms = mask_struct(mask) if mask is not None else None
+        self.calls += 1
         _check(lib().ur_adjoint(self.h, _ptr(rho), _c.byref(cs) if cs is not None else None,
                                 _c.byref(ms) if ms is not None else None, _c.byref(hs), _ptr(g_bin),
                                 _ptr(grad_rho), _ptr(grad_amp), _stream(stream)), "ur_adjoint")
         return grad_rho, grad_amp
+
+    def adjoint_reuse(self, fwd: Hist, g_bin, cell: DeviceCell, mask, grad_amp, stream=None, amp=None):
+        """Amplitude gradient from the y-pass output held by the preceding
+        simulate call on this plan (no recomputation); raises UltimaError
+        when the plan holds none."""
+        _require(g_bin, _torch().float64, self.nbins, "g_bin")
+        hs, cs, ms = fwd.struct(), cell.struct(amp), mask_struct(mask)
+        self.calls += 1
+        _check(lib().ur_adjoint_reuse(self.h, _c.byref(cs), _c.byref(ms), _c.byref(hs), _ptr(g_bin), _ptr(grad_amp),
+                                      _stream(stream)), "ur_adjoint_reuse")
+        return grad_amp
 
 
 def merge_zooms(hists: Sequence[Hist], ns: Sequence[int], voxels: Sequence[float], edges_dev, mode: int = MERGE_FINEST,

@@ -4,7 +4,9 @@
 intensity of every |Q| bin (0 for empty bins) of the box generated from the
 unit cell with atom amplitudes ``amp``; its backward calls ``ur_adjoint``,
 which gives dL/d amp from dL/dI_b (the gradient of eq. 1's |F|^2 averaged per
-bin, folded back through tiling and masking).  ``BinnedIntensityRho`` does
+bin, folded back through tiling and masking); when nothing else ran on the
+plan since the forward call it starts from the plan's held y-pass output
+(``ur_adjoint_reuse``) instead of recomputing it.  ``BinnedIntensityRho`` does
 the same for a given voxel density.  Both run entirely in the HIP kernels;
 the Python here only moves pointers.
 """
@@ -29,13 +31,18 @@ class BinnedIntensity(torch.autograd.Function):
         h = Hist(plan.nbins)
         plan.simulate(cell, mask, zoom, h, amp=a)
         ctx.plan, ctx.cell, ctx.mask, ctx.hist, ctx.amp = plan, cell, mask, h, a
+        ctx.calls = plan.calls                  # the plan's workspace holds this forward's output
         return _means(h)
 
     @staticmethod
     def backward(ctx, g_mean: torch.Tensor):
         g = torch.where(ctx.hist.count > 0, g_mean.to(torch.float64), torch.zeros_like(g_mean, dtype=torch.float64))
         grad = torch.empty_like(ctx.amp)
-        ctx.plan.adjoint(ctx.hist, g.contiguous(), cell=ctx.cell, mask=ctx.mask, grad_amp=grad, amp=ctx.amp)
+        if ctx.plan.calls == ctx.calls and not ctx.plan.c2c:
+            # nothing ran on the plan since this forward: start from its held output
+            ctx.plan.adjoint_reuse(ctx.hist, g.contiguous(), ctx.cell, ctx.mask, grad, amp=ctx.amp)
+        else:
+            ctx.plan.adjoint(ctx.hist, g.contiguous(), cell=ctx.cell, mask=ctx.mask, grad_amp=grad, amp=ctx.amp)
         return grad, None, None, None, None
 
 

@@ -68,6 +68,11 @@ struct ur_plan {
   int* dU = nullptr;         // nbins + 1 thresholds (device)
   short* dLut = nullptr;     // bin of n2 = s^2, s in [0, nlut) (device)
   int nlut = 0;
+  // y-pass output of the last ur_simulate still held in the workspace (ED-1,
+  // real transform): its mask and cell edge; cleared by every other call
+  bool keep_valid = false;
+  MaskP keep_m{};
+  int keep_c = 0;
   double* dCount = nullptr;  // per-bin voxel counts (device), computed with the bins
   unsigned long long* dCountTmp = nullptr;
   std::vector<long long> U;
@@ -327,6 +332,7 @@ ur_status ur_plan_workspace_size_host(const ur_plan* p, int32_t nbins, int32_t x
 }
 
 ur_status ur_plan_set_workspace(ur_plan* p, void* dev_ptr, size_t bytes) {
+  if (p) p->keep_valid = false;
   if (!p || !dev_ptr) return fail(UR_ERR_INVALID, "null argument");
   if (((uintptr_t)dev_ptr) & 255) return fail(UR_ERR_INVALID, "workspace must be 256-byte aligned");
   if (p->ws && p->ws_owned) { UR_HIP(hipDeviceSynchronize()); UR_HIP(hipFree(p->ws)); }
@@ -359,6 +365,7 @@ ur_status ur_plan_read_timing(ur_plan* p, int32_t npass, double* ms, double* byt
 }
 
 ur_status ur_plan_set_bins(ur_plan* p, int32_t nbins, const double* edges) {
+  if (p) p->keep_valid = false;
   if (!p || !edges) return fail(UR_ERR_INVALID, "null argument");
   if (nbins < 1 || nbins > 4096) return fail(UR_ERR_INVALID, "nbins = %d outside [1, 4096]", nbins);
   for (int b = 0; b <= nbins; ++b)
@@ -552,6 +559,7 @@ static ur_status run_y_x(ur_plan* p, const FwdGeom& g, char* A, char* B, const L
 extern "C" {
 
 ur_status ur_cell_synth(ur_plan* p, const ur_cell* cell, double* cell_out, void* stream) {
+  if (p) p->keep_valid = false;
   if (!p || !cell_out) return fail(UR_ERR_INVALID, "null argument");
   UR_TRY(check_cell(cell));
   hipStream_t s = (hipStream_t)stream;
@@ -564,6 +572,7 @@ ur_status ur_cell_synth(ur_plan* p, const ur_cell* cell, double* cell_out, void*
 }
 
 ur_status ur_rho_generate(ur_plan* p, const ur_cell* cell, const ur_mask* mask, const ur_zoom* zoom, void* rho, void* stream) {
+  if (p) p->keep_valid = false;
   if (!p || !rho) return fail(UR_ERR_INVALID, "null argument");
   UR_TRY(check_cell(cell));
   Level L;
@@ -579,6 +588,7 @@ ur_status ur_rho_generate(ur_plan* p, const ur_cell* cell, const ur_mask* mask, 
 }
 
 ur_status ur_simulate(ur_plan* p, const ur_cell* cell, const ur_mask* mask, const ur_zoom* zoom, const ur_hist* h, void* stream) {
+  if (p) p->keep_valid = false;
   if (!p) return fail(UR_ERR_INVALID, "plan is null");
   if (p->nbins < 1) return fail(UR_ERR_STATE, "no bins set on the plan");
   UR_TRY(check_hist(h));
@@ -615,10 +625,17 @@ ur_status ur_simulate(ur_plan* p, const ur_cell* cell, const ur_mask* mask, cons
     UR_HIP(launch_pass_z(p->prec, p->n, zm, za, nzb, s));
   }
   p->pass_bytes[P_Z] = live_rows(p, g) * p->nkz * p->cs + 16.0 * nzb;
-  return run_y_x(p, g, p->ws + lay.A, p->ws + lay.B, lay, h, nzb, s);
+  const ur_status st = run_y_x(p, g, p->ws + lay.A, p->ws + lay.B, lay, h, nzb, s);
+  if (st == UR_OK && zoom->factor == 1 && zoom->n1 == p->n && !(p->flags & UR_C2C)) {
+    p->keep_valid = true;
+    p->keep_m = g.m;
+    p->keep_c = cell->c;
+  }
+  return st;
 }
 
 ur_status ur_simulate_rho(ur_plan* p, const void* rho, const ur_hist* h, void* stream) {
+  if (p) p->keep_valid = false;
   if (!p || !rho) return fail(UR_ERR_INVALID, "null argument");
   if (p->nbins < 1) return fail(UR_ERR_STATE, "no bins set on the plan");
   UR_TRY(check_hist(h));
@@ -643,6 +660,7 @@ ur_status ur_simulate_rho(ur_plan* p, const void* rho, const ur_hist* h, void* s
 }
 
 ur_status ur_fft3d_exec(ur_plan* p, const void* in, void* out, int32_t dir, void* stream) {
+  if (p) p->keep_valid = false;
   if (!p || !in || !out) return fail(UR_ERR_INVALID, "null argument");
   if (dir != -1 && dir != 1) return fail(UR_ERR_INVALID, "dir must be -1 or +1");
   if (dir > 0 && p->n > 1024) return fail(UR_ERR_UNSUPPORTED, "inverse transforms run up to 1024^3");
@@ -683,6 +701,7 @@ ur_status ur_fft3d_exec(ur_plan* p, const void* in, void* out, int32_t dir, void
 }
 
 ur_status ur_intensity_bin(ur_plan* p, const void* spectrum, const ur_hist* h, void* stream) {
+  if (p) p->keep_valid = false;
   if (!p || !spectrum) return fail(UR_ERR_INVALID, "null argument");
   if (p->nbins < 1) return fail(UR_ERR_STATE, "no bins set on the plan");
   UR_TRY(check_hist(h));
@@ -705,6 +724,7 @@ ur_status ur_intensity_bin(ur_plan* p, const void* spectrum, const ur_hist* h, v
 
 ur_status ur_simulate_host(ur_plan* p, const void* rho_host, int32_t x_lo, int32_t x_hi, const ur_hist* h,
                            void* stream, size_t* h2d_bytes) {
+  if (p) p->keep_valid = false;
   if (!p || !rho_host) return fail(UR_ERR_INVALID, "null argument");
   if (p->nbins < 1) return fail(UR_ERR_STATE, "no bins set on the plan");
   if (p->flags & UR_C2C) return fail(UR_ERR_UNSUPPORTED, "the out-of-core path takes real densities (UR_R2C plans)");
@@ -785,8 +805,33 @@ ur_status ur_simulate_host(ur_plan* p, const void* rho_host, int32_t x_lo, int32
   return UR_OK;
 }
 
+// The adjoint from the plan's state: with `reuse`, the y-pass output left by
+// the preceding ur_simulate (same density) stands in for the recomputed
+// z and y passes.
+static ur_status adjoint_run(ur_plan* p, const void* rho, const ur_cell* cell, const ur_mask* mask, const ur_hist* fwd,
+                             const double* g_bin, void* grad_rho, double* grad_amp, void* stream, bool reuse);
+
 ur_status ur_adjoint(ur_plan* p, const void* rho, const ur_cell* cell, const ur_mask* mask, const ur_hist* fwd,
                      const double* g_bin, void* grad_rho, double* grad_amp, void* stream) {
+  if (p) p->keep_valid = false;
+  return adjoint_run(p, rho, cell, mask, fwd, g_bin, grad_rho, grad_amp, stream, false);
+}
+
+ur_status ur_adjoint_reuse(ur_plan* p, const ur_cell* cell, const ur_mask* mask, const ur_hist* fwd,
+                           const double* g_bin, double* grad_amp, void* stream) {
+  if (!p || !cell || !mask || !fwd || !g_bin || !grad_amp) return fail(UR_ERR_INVALID, "null argument");
+  const bool held = p->keep_valid;
+  p->keep_valid = false;                               // the x pass below overwrites the held output
+  if (!held) return fail(UR_ERR_STATE, "no forward output held: the last call on this plan was not ur_simulate");
+  MaskP m{};
+  m.kind = mask->kind; m.p0 = mask->p0; m.p1 = mask->p1;
+  if (m.kind != p->keep_m.kind || m.p0 != p->keep_m.p0 || m.p1 != p->keep_m.p1 || cell->c != p->keep_c)
+    return fail(UR_ERR_STATE, "mask or cell edge differ from those of the held forward output");
+  return adjoint_run(p, nullptr, cell, mask, fwd, g_bin, nullptr, grad_amp, stream, true);
+}
+
+static ur_status adjoint_run(ur_plan* p, const void* rho, const ur_cell* cell, const ur_mask* mask, const ur_hist* fwd,
+                             const double* g_bin, void* grad_rho, double* grad_amp, void* stream, bool reuse) {
   if (!p || !fwd || !fwd->count || !g_bin) return fail(UR_ERR_INVALID, "null argument");
   if (p->nbins < 1) return fail(UR_ERR_STATE, "no bins set on the plan");
   if ((rho != nullptr) == (cell != nullptr)) return fail(UR_ERR_INVALID, "give exactly one of rho and cell");
@@ -832,8 +877,8 @@ ur_status ur_adjoint(ur_plan* p, const void* rho, const ur_cell* cell, const ur_
     bx0 = xt0 * tx;
     bs = (xt1 - xt0 + 1) * tx;
   }
-  // forward transform along z and y (recomputed; nothing stored from the forward call)
-  if (g.xlo <= g.xhi) {
+  // forward transform along z and y: recomputed, or held from the forward call
+  if (!reuse && g.xlo <= g.xhi) {
     za.A = A; za.ax0 = 0; za.tw = p->tw; za.mom = nullptr; za.L = g.L; za.m = g.m; za.nkz = p->nkz;
     za.x0 = g.xlo; za.ntiles = ntiles(p);
     UR_HIP(launch_pass_z(p->prec, n, zmode, za, (g.xhi - g.xlo + 1) * za.ntiles, s));

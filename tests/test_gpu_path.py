@@ -302,6 +302,49 @@ def test_radii_batch_in_one_graph(ur, orc, n, count, r_lo, r_hi, check):
         assert rel.max() <= 1e-5
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_adjoint_reuse_matches_recompute(ur, orc, prec):
+    """ur_adjoint_reuse (held forward output) gives the recomputing adjoint's
+    amplitude gradient, and refuses when the plan holds no matching output."""
+    import torch
+    wl = W.small(64, c=8, n_atoms=9, seed=61, radius=24.0, nbins=48, prec=prec)
+    plan = ur.Plan(wl.n, wl.voxel, prec)
+    plan.set_bins(wl.edges)
+    cell = ur.DeviceCell.from_host(wl.cell)
+    fwd = ur.Hist(wl.nbins)
+    plan.simulate(cell, wl.mask, wl.zoom, fwd)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(62)
+    g = torch.as_tensor(np.where(fwd.numpy()["count"] > 0, rng.standard_normal(wl.nbins), 0.0), device="cuda")
+    ga = torch.zeros(wl.cell.n_atoms, dtype=torch.float64, device="cuda")
+    plan.adjoint(fwd, g, cell=cell, mask=wl.mask, grad_amp=ga)
+    plan.simulate(cell, wl.mask, wl.zoom, fwd)
+    gb = torch.zeros_like(ga)
+    plan.adjoint_reuse(fwd, g, cell, wl.mask, gb)
+    torch.cuda.synchronize()
+    a, b = ga.cpu().numpy(), gb.cpu().numpy()
+    assert np.allclose(b, a, rtol=1e-6 if prec == 0 else 1e-12, atol=0.0), np.max(np.abs(b - a) / np.abs(a))
+    ref = orc.simulate(wl, return_fields=True)
+    g_np = g.cpu().numpy()
+    amp_ref = orc.grad_amp(orc.grad_rho(ref["F"], wl.voxel, wl.edges, ref["count"], g_np), wl.cell, wl.mask)
+    err = np.max(np.abs(b - amp_ref)) / np.max(np.abs(amp_ref))
+    _say(f"  adjoint_reuse prec={prec}: grad_amp rel err vs oracle {err:.3e}")
+    assert err < (2e-5 if prec == 0 else 1e-10)
+    # the held output is consumed by the first reuse
+    with pytest.raises(ur.UltimaError, match="status 6"):
+        plan.adjoint_reuse(fwd, g, cell, wl.mask, gb)
+    # any other call in between drops it
+    plan.simulate(cell, wl.mask, wl.zoom, fwd)
+    plan.rho_generate(cell, wl.mask, wl.zoom)
+    with pytest.raises(ur.UltimaError, match="status 6"):
+        plan.adjoint_reuse(fwd, g, cell, wl.mask, gb)
+    # a different mask is refused
+    plan.simulate(cell, wl.mask, wl.zoom, fwd)
+    with pytest.raises(ur.UltimaError, match="status 6"):
+        plan.adjoint_reuse(fwd, g, cell, W.sphere(20.0), gb)
+    torch.cuda.synchronize()
+
+
 def test_graph_replay_matches_eager(ur):
     import torch
     wl = W.small(64, c=8, n_atoms=10, seed=7, radius=25.0, nbins=64)
