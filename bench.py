@@ -187,22 +187,42 @@ def radii_batch(ur, W, torch, reps):
     return out
 
 
-def out_of_core(ur, W, torch, wl, reps):
-    """The headline box with its density in pinned host memory: only the
-    planes that hold density are copied, slab by slab, overlapped with the
-    z and y passes (eq. 2 split); reports the PCIe-inclusive rate."""
+def fill_host(ur, torch, plan, cell, wl, x_lo, x_hi, pinned, chunk=64):
+    """Planes x_lo..x_hi of the density in host memory (exactly-sized pinned
+    memory, or pageable memory when it exceeds what may be page-locked),
+    generated on the device chunk by chunk (a 4096^3 box does not fit HBM).
+    Returns (tensor, buffer to close or None)."""
+    shape = (x_hi - x_lo + 1, wl.n, wl.n)
+    hb = ur.HostBuffer(shape, torch.float32) if pinned else None
+    host = hb.tensor if pinned else torch.empty(shape, dtype=torch.float32)
+    for a in range(x_lo, x_hi + 1, chunk):
+        b = min(a + chunk - 1, x_hi)
+        host[a - x_lo:b - x_lo + 1].copy_(plan.rho_generate(cell, wl.mask, wl.zoom, x_lo=a, x_hi=b))
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return host, hb
+
+
+def mask_planes(W, wl):
+    """Planes that can hold density: half-width of the mask (sphere: sqrt of
+    the squared radius; cube and truncated octahedron: p0) about n/2."""
     import math
+    r = math.isqrt(int(wl.mask.p0)) if wl.mask.kind == W.MASK_SPHERE else int(wl.mask.p0)
+    return wl.n // 2 - r, wl.n // 2 + r
+
+
+def out_of_core(ur, W, torch, wl, reps, pinned=True):
+    """A box with its density in host memory: only the planes that hold
+    density are copied, slab by slab, overlapped with the z and y passes
+    (eq. 2 split); reports the PCIe-inclusive rate.  pinned=False keeps the
+    density in pageable memory (the plan's pinned bounce slabs carry it)."""
     plan = ur.Plan(wl.n, wl.voxel, ur.UR_F32)
     plan.set_bins(wl.edges)
     cell = ur.DeviceCell.from_host(wl.cell)
-    rho = plan.rho_generate(cell, wl.mask, wl.zoom)
-    host = torch.empty(rho.shape, dtype=torch.float32, pin_memory=True)
-    host.copy_(rho)
-    del rho
-    # planes that can hold density: half-width of the mask (sphere: sqrt of
-    # the squared radius; cube and truncated octahedron: p0)
-    r = math.isqrt(int(wl.mask.p0)) if wl.mask.kind == W.MASK_SPHERE else int(wl.mask.p0)
-    x_lo, x_hi = wl.n // 2 - r, wl.n // 2 + r
+    x_lo, x_hi = mask_planes(W, wl)
+    t_fill = time.perf_counter()
+    host, hb = fill_host(ur, torch, plan, cell, wl, x_lo, x_hi, pinned)
+    t_fill = time.perf_counter() - t_fill
     h = ur.Hist(wl.nbins)
     nbytes = plan.simulate_host(host, x_lo, x_hi, h)
     torch.cuda.synchronize()
@@ -218,8 +238,11 @@ def out_of_core(ur, W, torch, wl, reps):
     ms = e0.elapsed_time(e1) / reps
     out = {"ms_per_box": round(ms, 3), "h2d_bytes": nbytes, "pcie_GBps": round(nbytes / (ms * 1e-3) / 1e9, 2),
            "voxels_per_s_pcie_inclusive": wl.n ** 3 / (ms * 1e-3), "wall_ms": round(wall * 1e3, 3),
-           "planes": [x_lo, x_hi]}
+           "planes": [x_lo, x_hi], "host_fill_s": round(t_fill, 1), "host_memory": "pinned" if pinned else "pageable"}
     del host, plan
+    if hb is not None:
+        hb.close()
+    torch.cuda.empty_cache()
     return out
 
 
@@ -231,6 +254,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the FP64 and adjoint measurements")
     ap.add_argument("--n", type=int, default=1024, help="box edge (1024 = the headline workload)")
+    ap.add_argument("--ooc4096", action="store_true",
+                    help="also stream the 4096^3 out-of-core box (212 GiB of host memory, a few minutes)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (reference kernel for HBM byte counters)")
     args = ap.parse_args()
@@ -328,10 +353,17 @@ def main():
         extras["radii_batch"] = radii_batch(ur, W, torch, max(2, args.steps // 4))
         # out-of-core: the same box streamed from pinned host memory
         extras["out_of_core"] = out_of_core(ur, W, torch, wl, max(2, args.steps // 4))
+        # the same from pageable host memory (pinned bounce slabs)
+        extras["out_of_core_pageable"] = out_of_core(ur, W, torch, wl, 2, pinned=False)
         torch.cuda.empty_cache()
         # out-of-core at 2048^3 with the truncated-octahedron recipe of the
-        # out-of-core workload (its largest box that one GPU's transform runs)
+        # out-of-core workload
         extras["out_of_core_c5_2048"] = out_of_core(ur, W, torch, W.c5(2048), 2)
+        if args.ooc4096:
+            # the out-of-core workload itself: 4096^3, 3399 planes (212 GiB,
+            # more than a process may page-lock here: pageable memory through
+            # the bounce slabs), 229 GB of spectrum in HBM
+            extras["out_of_core_c5_4096"] = out_of_core(ur, W, torch, W.c5(4096), 2, pinned=False)
 
     cpu = None
     if not args.no_cpu_baseline:

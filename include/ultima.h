@@ -116,13 +116,16 @@ typedef struct ur_plan ur_plan;
  * (twiddles) with hipMalloc; the large work buffers are either attached with
  * ur_plan_set_workspace or allocated lazily on first use.  Errors:
  * UR_ERR_INVALID for n not a power of two, a voxel that is not positive and
- * finite, or an unknown precision; UR_ERR_UNSUPPORTED for n above 2048, or
- * a complex (UR_C2C) plan above 1024. */
+ * finite, or an unknown precision; UR_ERR_UNSUPPORTED for n above 4096, for
+ * n = 4096 in FP64 or complex, or for a complex (UR_C2C) plan above 1024.
+ * A 4096^3 plan runs only ur_plan_set_bins, ur_rho_generate, ur_cell_synth
+ * and the out-of-core path (ur_simulate_host and its workspace query); its
+ * other calls fail with UR_ERR_UNSUPPORTED. */
 ur_status ur_plan_create(int32_t n, double voxel, int32_t prec, uint32_t flags, ur_plan** out);
 void ur_plan_destroy(ur_plan* plan);
 
 /* Bytes of device workspace the plan needs for `nbins` bins (transform
- * buffers, partial histograms, cell tables). */
+ * buffers, partial histograms, cell tables) on the in-HBM paths. */
 ur_status ur_plan_workspace_size(const ur_plan* plan, int32_t nbins, size_t* bytes);
 /* Attach caller-owned device workspace (>= the size above, 256-B aligned). */
 ur_status ur_plan_set_workspace(ur_plan* plan, void* dev_ptr, size_t bytes);
@@ -138,10 +141,13 @@ ur_status ur_plan_set_bins(ur_plan* plan, int32_t nbins, const double* edges);
  * cell, using the plan's scratch for the per-atom profiles. */
 ur_status ur_cell_synth(ur_plan* plan, const ur_cell* cell, double* cell_out, void* stream);
 
-/* Materialise the ED of this plan's box (tiled cell x mask, optionally
- * zoomed) as n^3 reals of the plan precision at `rho` (DEVICE). */
+/* Materialise planes x_lo..x_hi of the ED of this plan's box (tiled cell x
+ * mask, optionally zoomed; section "Electron density generation") as
+ * (x_hi - x_lo + 1) n^2 reals of the plan precision at `rho` (DEVICE,
+ * [x - x_lo][y][z]); [0, n - 1] gives the whole box.  UR_ERR_INVALID for a
+ * range outside [0, n - 1]. */
 ur_status ur_rho_generate(ur_plan* plan, const ur_cell* cell, const ur_mask* mask,
-                          const ur_zoom* zoom, void* rho, void* stream);
+                          const ur_zoom* zoom, int32_t x_lo, int32_t x_hi, void* rho, void* stream);
 
 /* 3D transform of eq. 1.  dir = -1: forward, scaled by 1/n^3; input `in`
  * real [x][y][z] (UR_R2C) or complex [x][y][z] (UR_C2C); output `out`
@@ -165,9 +171,14 @@ ur_status ur_simulate(ur_plan* plan, const ur_cell* cell, const ur_mask* mask,
 ur_status ur_simulate_rho(ur_plan* plan, const void* rho, const ur_hist* hist, void* stream);
 
 /* Out-of-core forward path (the 2D + 1D separation of eq. 2): `rho_host` is
- * HOST memory (pinned, e.g. hipHostMalloc, for full PCIe speed) holding the
- * n^3 density [x][y][z].  Planes outside [x_lo, x_hi] are taken as zero and
- * never copied ("only the slices with nonzero density"); slabs of planes
+ * HOST memory holding planes x_lo..x_hi of the density, [x - x_lo][y][z],
+ * (x_hi - x_lo + 1) n^2 reals.  Page-locked memory (ur_host_alloc, or any
+ * hipHostMalloc buffer) is copied to the device directly; ordinary pageable
+ * memory goes through four pinned bounce slabs of the plan, filled by up to
+ * 16 host threads while earlier slabs are in flight (the call then returns
+ * once the last slab has been handed to the copy engine).  Planes outside
+ * [x_lo, x_hi] are taken as zero and never copied (the slices without
+ * density need no 2D transform); slabs of planes
  * are copied to the device into four staging buffers, each on its own copy
  * stream (several copies in flight), while earlier slabs go through the z
  * and y passes on `stream`; the x pass with binning runs once every slab is
@@ -181,6 +192,13 @@ ur_status ur_simulate_host(ur_plan* plan, const void* rho_host, int32_t x_lo, in
 /* Device workspace of the out-of-core path for planes [x_lo, x_hi]. */
 ur_status ur_plan_workspace_size_host(const ur_plan* plan, int32_t nbins, int32_t x_lo, int32_t x_hi,
                                       size_t* bytes);
+
+/* Page-locked HOST memory for the out-of-core input, allocated with
+ * hipHostMalloc at exactly `bytes` (no rounding up, so a box that takes most
+ * of the host memory still fits); *out receives the pointer.  UR_ERR_OOM
+ * when the allocation fails.  Free with ur_host_free (NULL is accepted). */
+ur_status ur_host_alloc(size_t bytes, void** out);
+ur_status ur_host_free(void* ptr);
 
 /* Adjoint of the binned forward path (derived from eq. 1).  Given
  * g_bin[b] = dL/dI_b (DEVICE, nbins doubles) with I_b = sum/count of the

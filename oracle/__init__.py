@@ -12,6 +12,7 @@ correct statement of the computation, written from the paper:
 * O9  merge of zoom levels into one curve (step 6; reading in ``merge``)
 * O10 chi^2 misfit of a binned curve and its gradients (derived from eq. 1)
 * O11 low-frequency Fourier coefficients by direct summation (eq. 1/eq. 2)
+* O12 per-bin counts and two-voxel intensities of boxes too large for O4-O8
 
 The heavy loops live in ``ur_oracle.c`` (plain C, FP64, OpenMP over
 independent lines); this module marshals numpy arrays and holds the small
@@ -80,6 +81,8 @@ def lib():
         L.or_set_num_threads.argtypes = [ctypes.c_int]
         L.or_dft_points.argtypes = [ctypes.c_int, ctypes.c_longlong, _LL, _D, ctypes.c_longlong, _LL,
                                     ctypes.c_void_p]
+        L.or_axis_pair_bins.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_int, _D, ctypes.c_longlong,
+                                        ctypes.c_double, ctypes.c_double, _D, _D]
         _LIB = L
     return _LIB
 
@@ -273,6 +276,44 @@ def dft_points(n: int, xyz: np.ndarray, values: np.ndarray, uvw: np.ndarray) -> 
                         len(uvw), uvw.ctypes.data_as(ctypes.POINTER(ctypes.c_longlong)),
                         out.ctypes.data_as(ctypes.c_void_p))
     return out
+
+
+def axis_pair_bins(n: int, voxel: float, edges: np.ndarray, d: int, rho1: float, rho2: float):
+    """O12: per-bin voxel count and sum of |F|^2 (eq. 1) over the n^3 box for
+    the density of two voxels, rho1 and rho2, d apart along one axis; the
+    count alone is the geometry of any density."""
+    e = np.ascontiguousarray(edges, dtype=np.float64)
+    nb = e.size - 1
+    count, s = np.zeros(nb), np.zeros(nb)
+    lib().or_axis_pair_bins(int(n), float(voxel), int(nb), _dp(e), int(d), float(rho1), float(rho2),
+                            _dp(count), _dp(s))
+    return count, s
+
+
+def lattice_points_below(m: int) -> np.ndarray:
+    """Every integer (h, k, l) with h^2 + k^2 + l^2 < m, as rows."""
+    r = math.isqrt(max(m - 1, 0))
+    a = np.arange(-r, r + 1, dtype=np.int64)
+    h, k, l = np.meshgrid(a, a, a, indexing="ij")
+    sel = h * h + k * k + l * l < m
+    return np.stack([h[sel], k[sel], l[sel]], axis=1)
+
+
+def sparse_low_bins(n: int, voxel: float, edges: np.ndarray, xyz: np.ndarray, values: np.ndarray, m: int):
+    """Exact count / sum / mean of |F|^2 (eq. 1, by direct summation over the
+    nonzero voxels) for every bin lying wholly below n2 = m, i.e. whose every
+    lattice point has h^2 + k^2 + l^2 < m (m <= (n/2)^2 keeps them inside the
+    box's frequency range).  Returns (bin indices, count, sum, mean)."""
+    assert m <= (n // 2) ** 2
+    U = thresholds(n, voxel, edges)
+    pts = lattice_points_below(m)
+    n2 = np.sum(pts * pts, axis=1)
+    I = np.abs(dft_points(n, xyz, values, pts)) ** 2
+    sel = [b for b in range(len(U) - 1) if U[b + 1] <= m and U[b + 1] > U[b]]
+    cnt = np.array([np.count_nonzero((n2 >= U[b]) & (n2 < U[b + 1])) for b in sel], dtype=np.float64)
+    s = np.array([I[(n2 >= U[b]) & (n2 < U[b + 1])].sum() for b in sel])
+    mean = np.where(cnt > 0, s / np.maximum(cnt, 1), np.nan)
+    return np.array(sel, dtype=np.int64), cnt, s, mean
 
 
 def density_moments(wl, cell_grid: Optional[np.ndarray] = None):

@@ -384,6 +384,54 @@ void or_bin_counts(int n, double voxel, int nbins, const double* edges, double* 
 }
 
 /* ------------------------------------------------------------------------ */
+/* O12  per-bin sums of boxes too large for the n^3 loops of O7.
+ *  (a) The voxel count of bin b is the number of lattice points (t, u, v),
+ *      each in [-n/2, n/2), with U_b <= t^2 + u^2 + v^2 < U_b+1.  Taking t
+ *      outermost: count_b = sum over t of P(U_b+1 - t^2) - P(U_b - t^2), with
+ *      P(m) the number of (u, v) with u^2 + v^2 < m, tabulated once.
+ *  (b) For a density of two voxels, rho1 at p and rho2 at p + d e_a (d along
+ *      one axis a), eq. 1 gives n^6 |F(q)|^2 = rho1^2 + rho2^2
+ *      + 2 rho1 rho2 cos(2 pi q_a d / n): the intensity depends on q only
+ *      through its a-component t, so the bin sum of |F|^2 is the same sum
+ *      over t, each term weighted by its intensity.  The phase t d is reduced
+ *      mod n in integers.  Outputs count[b] and sum[b] = sum of |F|^2.       */
+/* ------------------------------------------------------------------------ */
+void or_axis_pair_bins(int n, double voxel, int nbins, const double* edges, long long d,
+                       double rho1, double rho2, double* count, double* sum)
+{
+    long long* U = (long long*)malloc(sizeof(long long) * (nbins + 1));
+    or_thresholds(n, voxel, nbins, edges, U);
+    const long long h = n / 2;
+    const long long mtop = 2 * h * h + 1;            /* u^2 + v^2 < mtop for every (u, v) */
+    /* P[m] = #{(u, v) : u^2 + v^2 < m}, m in [0, mtop] */
+    long long* P = (long long*)calloc((size_t)mtop + 1, sizeof(long long));
+    for (long long u = -h; u < h; ++u)
+        for (long long v = -h; v < h; ++v) P[u * u + v * v + 1] += 1;
+    for (long long m = 1; m <= mtop; ++m) P[m] += P[m - 1];
+    const double norm = 1.0 / ((double)n * n * n) / ((double)n * n * n);
+#pragma omp parallel for schedule(dynamic, 8)
+    for (int b = 0; b < nbins; ++b) {
+        long long cnt = 0;
+        kahan_t acc = {0.0, 0.0};
+        for (long long t = -h; t < h; ++t) {
+            long long lo = U[b] - t * t, hi = U[b + 1] - t * t;
+            long long plo = lo <= 0 ? 0 : P[lo > mtop ? mtop : lo];
+            long long phi = hi <= 0 ? 0 : P[hi > mtop ? mtop : hi];
+            long long c = phi - plo;
+            if (c == 0) continue;
+            cnt += c;
+            long long e = pmod(t * d, n);
+            double inten = rho1 * rho1 + rho2 * rho2 + 2.0 * rho1 * rho2 * cos(2.0 * M_PI * (double)e / (double)n);
+            kadd(&acc, (double)c * inten);
+        }
+        count[b] = (double)cnt;
+        sum[b] = kval(&acc) * norm;
+    }
+    free(P);
+    free(U);
+}
+
+/* ------------------------------------------------------------------------ */
 /* O11  Fourier coefficients on a small cube of low frequencies
  *     |h|, |k|, |l| <= K of the box of level (n1, f, nk), straight from eq. 1
  *     summed in the order of eq. 2 (z, then y, then x), with the density

@@ -21,6 +21,7 @@ LIBPATH = os.path.join(HERE, "libultima.so")
 UR_F32, UR_F64 = 0, 1
 UR_R2C, UR_C2C = 0, 1
 MERGE_FINEST, MERGE_POOLED, MERGE_IVW = 0, 1, 2
+MAX_IN_CORE, MAX_OUT_OF_CORE = 2048, 4096     # box edges (include/ultima.h, ur_plan_create)
 
 _c = ctypes
 _vp = _c.c_void_p
@@ -54,7 +55,8 @@ _SIGS = {
     "ur_plan_set_workspace": [_vp, _vp, _c.c_size_t],
     "ur_plan_set_bins": [_vp, _c.c_int32, _c.POINTER(_c.c_double)],
     "ur_cell_synth": [_vp, _c.POINTER(UrCell), _vp, _vp],
-    "ur_rho_generate": [_vp, _c.POINTER(UrCell), _c.POINTER(UrMask), _c.POINTER(UrZoom), _vp, _vp],
+    "ur_rho_generate": [_vp, _c.POINTER(UrCell), _c.POINTER(UrMask), _c.POINTER(UrZoom), _c.c_int32, _c.c_int32,
+                        _vp, _vp],
     "ur_fft3d_exec": [_vp, _vp, _vp, _c.c_int32, _vp],
     "ur_intensity_bin": [_vp, _vp, _c.POINTER(UrHist), _vp],
     "ur_simulate": [_vp, _c.POINTER(UrCell), _c.POINTER(UrMask), _c.POINTER(UrZoom), _c.POINTER(UrHist), _vp],
@@ -68,6 +70,8 @@ _SIGS = {
     "ur_graph_end": [_vp, _c.POINTER(_vp)],
     "ur_graph_launch": [_vp, _vp],
     "ur_graph_destroy": [_vp],
+    "ur_host_alloc": [_c.c_size_t, _c.POINTER(_vp)],
+    "ur_host_free": [_vp],
     "ur_plan_set_timing": [_vp, _c.c_int32],
     "ur_plan_read_timing": [_vp, _c.c_int32, _c.POINTER(_c.c_double), _c.POINTER(_c.c_double),
                             _c.POINTER(_c.c_int32)],
@@ -233,7 +237,8 @@ class Plan:
         _check(lib().ur_plan_set_bins(self.h, int(e.size - 1), e.ctypes.data_as(_c.POINTER(_c.c_double))),
                "ur_plan_set_bins")
         self.nbins = int(e.size - 1)
-        self._attach(self.workspace_size())
+        if self.n <= MAX_IN_CORE:                # larger boxes run only out of core (own workspace size)
+            self._attach(self.workspace_size())
 
     def workspace_size(self, nbins: Optional[int] = None) -> int:
         v = _c.c_size_t()
@@ -295,10 +300,12 @@ class Plan:
         return hist
 
     def simulate_host(self, rho_host, x_lo: int, x_hi: int, hist: Hist, stream=None) -> int:
-        """rho_host: pinned CPU tensor (n^3 reals). Returns the H2D byte count."""
+        """rho_host: pinned CPU tensor holding planes x_lo..x_hi of the density
+        ((x_hi - x_lo + 1) n^2 reals). Returns the H2D byte count."""
         if rho_host.device.type != "cpu" or not rho_host.is_contiguous() or rho_host.dtype != self.real_dtype \
-                or rho_host.numel() != self.n ** 3:
-            raise UltimaError("rho_host must be a contiguous CPU tensor of n^3 reals of the plan precision")
+                or rho_host.numel() != (int(x_hi) - int(x_lo) + 1) * self.n ** 2:
+            raise UltimaError("rho_host must be a contiguous CPU tensor of (x_hi - x_lo + 1) n^2 reals of the plan "
+                              "precision")
         if self._use_torch_ws:
             self._attach(self.workspace_size_host(x_lo, x_hi))
         hs = hist.struct()
@@ -308,15 +315,19 @@ class Plan:
                                       _c.byref(nb)), "ur_simulate_host")
         return int(nb.value)
 
-    def rho_generate(self, cell: DeviceCell, mask, zoom, out=None, stream=None):
+    def rho_generate(self, cell: DeviceCell, mask, zoom, out=None, stream=None, x_lo: int = 0, x_hi=None):
+        """Planes x_lo..x_hi (default: the whole box) of the density, as a
+        device tensor [x - x_lo][y][z]."""
         torch = _torch()
+        x_hi = self.n - 1 if x_hi is None else int(x_hi)
+        planes = x_hi - int(x_lo) + 1
         if out is None:
-            out = torch.empty((self.n,) * 3, dtype=self.real_dtype, device="cuda")
-        _require(out, self.real_dtype, self.n ** 3, "out")
+            out = torch.empty((max(planes, 0), self.n, self.n), dtype=self.real_dtype, device="cuda")
+        _require(out, self.real_dtype, max(planes, 0) * self.n ** 2, "out")
         cs, ms, zs = cell.struct(), mask_struct(mask), UrZoom(int(zoom.n1), int(zoom.factor))
         self.calls += 1
-        _check(lib().ur_rho_generate(self.h, _c.byref(cs), _c.byref(ms), _c.byref(zs), _ptr(out), _stream(stream)),
-               "ur_rho_generate")
+        _check(lib().ur_rho_generate(self.h, _c.byref(cs), _c.byref(ms), _c.byref(zs), int(x_lo), x_hi, _ptr(out),
+                                     _stream(stream)), "ur_rho_generate")
         return out
 
     def cell_synth(self, cell: DeviceCell, out=None, stream=None):
@@ -432,6 +443,37 @@ class Graph:
         try:
             if self.h is not None and _LIB is not None:
                 _LIB.ur_graph_destroy(self.h)
+        except Exception:
+            pass
+
+
+class HostBuffer:
+    """Page-locked host memory of exactly the requested size (ur_host_alloc;
+    torch's pinned allocator rounds up to a power of two), exposed as the CPU
+    tensor ``.tensor``.  Views of it must not outlive the buffer: ``close()``
+    (or collection of the object) frees the memory."""
+
+    def __init__(self, shape, dtype):
+        torch = _torch()
+        self.shape = tuple(int(d) for d in shape)
+        count = int(np.prod(self.shape, dtype=np.int64))
+        np_dtype = {torch.float32: np.float32, torch.float64: np.float64}[dtype]
+        self.nbytes = count * np.dtype(np_dtype).itemsize
+        p = _vp()
+        _check(lib().ur_host_alloc(self.nbytes, _c.byref(p)), "ur_host_alloc")
+        self.ptr = p.value
+        raw = (_c.c_char * self.nbytes).from_address(self.ptr)
+        self.tensor = torch.from_numpy(np.frombuffer(raw, dtype=np_dtype, count=count).reshape(self.shape))
+
+    def close(self):
+        if getattr(self, "ptr", None):
+            self.tensor = None
+            lib().ur_host_free(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
         except Exception:
             pass
 

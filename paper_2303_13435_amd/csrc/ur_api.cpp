@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/ultima.h"
@@ -86,14 +87,16 @@ struct ur_plan {
   char* cs_buf = nullptr;
   size_t cs_bytes = 0;
 
-  // out-of-core
-  // out-of-core staging: kStage slab buffers, each filled on its own copy
-  // stream (several host-to-device copies in flight keep PCIe busy)
+  // out-of-core staging: kStage slab buffers on the device, each filled on
+  // its own copy stream (several host-to-device copies in flight keep PCIe
+  // busy); pageable input first goes through kStage pinned bounce slabs
   static constexpr int kStage = 4;
   hipStream_t copy_stream[kStage] = {};
   hipEvent_t ev_copied[kStage] = {}, ev_free[kStage] = {};
-  void* stage = nullptr;     // two pinned-side staging buffers on the device
+  void* stage = nullptr;
   size_t stage_bytes = 0;
+  void* bounce = nullptr;    // pinned host memory
+  size_t bounce_bytes = 0;
 
   // per-pass timing
   bool timing = false;
@@ -266,6 +269,45 @@ static void thresholds(int n, double voxel, int nbins, const double* edges, std:
 }
 #pragma clang fp contract(on)
 
+// True when `ptr` is page-locked host memory known to HIP (the device can
+// read it directly); false for ordinary pageable memory.
+static bool host_pinned(const void* ptr) {
+  hipPointerAttribute_t a;
+  if (hipPointerGetAttributes(&a, ptr) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return a.type == hipMemoryTypeHost;
+}
+
+// Host copy of `bytes` split over up to 16 threads (memory bandwidth, not
+// one core, then bounds the pageable-to-pinned step).
+static void parallel_copy(char* dst, const char* src, size_t bytes) {
+  const unsigned hc = std::thread::hardware_concurrency();
+  const size_t nt = std::max<size_t>(1, std::min<size_t>({16, hc ? hc : 1, bytes >> 22}));
+  if (nt == 1) { memcpy(dst, src, bytes); return; }
+  std::vector<std::thread> th;
+  th.reserve(nt);
+  const size_t part = (bytes / nt + 4095) & ~(size_t)4095;
+  for (size_t t = 0; t < nt; ++t) {
+    const size_t a = t * part;
+    if (a >= bytes) break;
+    const size_t len = std::min(part, bytes - a);
+    th.emplace_back([=] { memcpy(dst + a, src + a, len); });
+  }
+  for (auto& t : th) t.join();
+}
+
+// Boxes up to kMaxInCore^3 run every path; larger ones (kMaxOutOfCore^3,
+// FP32 real) run only the out-of-core forward path, whose spectrum in HBM
+// covers just the particle's planes.
+static ur_status need_in_core(const ur_plan* p) {
+  if (p->n > kMaxInCore)
+    return fail(UR_ERR_UNSUPPORTED, "n = %d runs only out of core (ur_simulate_host); in-HBM paths run up to %d^3",
+                p->n, kMaxInCore);
+  return UR_OK;
+}
+
 extern "C" {
 
 const char* ur_last_error(void) { return g_err.c_str(); }
@@ -275,7 +317,9 @@ ur_status ur_plan_create(int32_t n, double voxel, int32_t prec, uint32_t flags, 
   if (!out) return fail(UR_ERR_INVALID, "out is null");
   *out = nullptr;
   if (!is_pow2(n) || n < 16) return fail(UR_ERR_INVALID, "n = %d must be a power of two >= 16", n);
-  if (n > 2048) return fail(UR_ERR_UNSUPPORTED, "n = %d: boxes run up to 2048^3", n);
+  if (n > kMaxOutOfCore) return fail(UR_ERR_UNSUPPORTED, "n = %d: boxes run up to %d^3", n, kMaxOutOfCore);
+  if (n > kMaxInCore && (prec != UR_F32 || (flags & UR_C2C)))
+    return fail(UR_ERR_UNSUPPORTED, "n = %d: boxes above %d^3 are FP32 real (UR_F32, no UR_C2C)", n, kMaxInCore);
   if (n > 1024 && (flags & UR_C2C)) return fail(UR_ERR_UNSUPPORTED, "complex transforms run up to 1024^3");
   if (!(voxel > 0.0) || !isfinite(voxel)) return fail(UR_ERR_INVALID, "voxel must be positive");
   if (prec != UR_F32 && prec != UR_F64) return fail(UR_ERR_INVALID, "prec must be UR_F32 or UR_F64");
@@ -308,6 +352,7 @@ void ur_plan_destroy(ur_plan* p) {
   if (p->ws && p->ws_owned) (void)hipFree(p->ws);
   if (p->cs_buf) (void)hipFree(p->cs_buf);
   if (p->stage) (void)hipFree(p->stage);
+  if (p->bounce) (void)hipHostFree(p->bounce);
   for (auto& e : p->ev_copied) if (e) (void)hipEventDestroy(e);
   for (auto& e : p->ev_free) if (e) (void)hipEventDestroy(e);
   for (auto& c : p->copy_stream) if (c) (void)hipStreamDestroy(c);
@@ -319,6 +364,7 @@ void ur_plan_destroy(ur_plan* p) {
 ur_status ur_plan_workspace_size(const ur_plan* p, int32_t nbins, size_t* bytes) {
   if (!p || !bytes) return fail(UR_ERR_INVALID, "null argument");
   if (nbins < 1) return fail(UR_ERR_INVALID, "nbins must be >= 1");
+  UR_TRY(need_in_core(p));
   *bytes = layout_incore(p, nbins).total;
   return UR_OK;
 }
@@ -571,9 +617,11 @@ ur_status ur_cell_synth(ur_plan* p, const ur_cell* cell, double* cell_out, void*
   return UR_OK;
 }
 
-ur_status ur_rho_generate(ur_plan* p, const ur_cell* cell, const ur_mask* mask, const ur_zoom* zoom, void* rho, void* stream) {
+ur_status ur_rho_generate(ur_plan* p, const ur_cell* cell, const ur_mask* mask, const ur_zoom* zoom, int32_t x_lo,
+                          int32_t x_hi, void* rho, void* stream) {
   if (p) p->keep_valid = false;
   if (!p || !rho) return fail(UR_ERR_INVALID, "null argument");
+  if (x_lo < 0 || x_hi >= p->n || x_lo > x_hi) return fail(UR_ERR_INVALID, "plane range [%d, %d] outside the box", x_lo, x_hi);
   UR_TRY(check_cell(cell));
   Level L;
   MaskP m;
@@ -583,13 +631,14 @@ ur_status ur_rho_generate(ur_plan* p, const ur_cell* cell, const ur_mask* mask, 
   UR_TRY(prepare_cell(p, cell, zoom->factor, t, s));
   ZArgs za{};
   za.cellT = t.cellT; za.cb = t.cb; za.pre = t.pre; za.L = L; za.m = m; za.cbn = t.cbn;
-  UR_HIP(launch_rho_generate(p->prec, p->n, za, rho, s));
+  UR_HIP(launch_rho_generate(p->prec, p->n, x_lo, x_hi, za, rho, s));
   return UR_OK;
 }
 
 ur_status ur_simulate(ur_plan* p, const ur_cell* cell, const ur_mask* mask, const ur_zoom* zoom, const ur_hist* h, void* stream) {
   if (p) p->keep_valid = false;
   if (!p) return fail(UR_ERR_INVALID, "plan is null");
+  UR_TRY(need_in_core(p));
   if (p->nbins < 1) return fail(UR_ERR_STATE, "no bins set on the plan");
   UR_TRY(check_hist(h));
   UR_TRY(check_cell(cell));
@@ -637,6 +686,7 @@ ur_status ur_simulate(ur_plan* p, const ur_cell* cell, const ur_mask* mask, cons
 ur_status ur_simulate_rho(ur_plan* p, const void* rho, const ur_hist* h, void* stream) {
   if (p) p->keep_valid = false;
   if (!p || !rho) return fail(UR_ERR_INVALID, "null argument");
+  UR_TRY(need_in_core(p));
   if (p->nbins < 1) return fail(UR_ERR_STATE, "no bins set on the plan");
   UR_TRY(check_hist(h));
   hipStream_t s = (hipStream_t)stream;
@@ -662,6 +712,7 @@ ur_status ur_simulate_rho(ur_plan* p, const void* rho, const ur_hist* h, void* s
 ur_status ur_fft3d_exec(ur_plan* p, const void* in, void* out, int32_t dir, void* stream) {
   if (p) p->keep_valid = false;
   if (!p || !in || !out) return fail(UR_ERR_INVALID, "null argument");
+  UR_TRY(need_in_core(p));
   if (dir != -1 && dir != 1) return fail(UR_ERR_INVALID, "dir must be -1 or +1");
   if (dir > 0 && p->n > 1024) return fail(UR_ERR_UNSUPPORTED, "inverse transforms run up to 1024^3");
   if (in == out) return fail(UR_ERR_INVALID, "in and out must differ");
@@ -703,6 +754,7 @@ ur_status ur_fft3d_exec(ur_plan* p, const void* in, void* out, int32_t dir, void
 ur_status ur_intensity_bin(ur_plan* p, const void* spectrum, const ur_hist* h, void* stream) {
   if (p) p->keep_valid = false;
   if (!p || !spectrum) return fail(UR_ERR_INVALID, "null argument");
+  UR_TRY(need_in_core(p));
   if (p->nbins < 1) return fail(UR_ERR_STATE, "no bins set on the plan");
   UR_TRY(check_hist(h));
   hipStream_t s = (hipStream_t)stream;
@@ -747,6 +799,18 @@ ur_status ur_simulate_host(ur_plan* p, const void* rho_host, int32_t x_lo, int32
     if (hipMalloc(&p->stage, K * slab_bytes) != hipSuccess) { (void)hipGetLastError(); return fail(UR_ERR_OOM, "staging allocation failed"); }
     p->stage_bytes = K * slab_bytes;
   }
+  const bool pinned = host_pinned(rho_host);
+  if (!pinned && (!p->bounce || p->bounce_bytes < K * slab_bytes)) {
+    UR_HIP(hipDeviceSynchronize());
+    if (p->bounce) UR_HIP(hipHostFree(p->bounce));
+    p->bounce = nullptr;
+    if (hipHostMalloc(&p->bounce, K * slab_bytes, hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      p->bounce = nullptr;
+      return fail(UR_ERR_OOM, "pinned bounce allocation failed");
+    }
+    p->bounce_bytes = K * slab_bytes;
+  }
   for (auto& c : p->copy_stream) if (!c) UR_HIP(hipStreamCreateWithFlags(&c, hipStreamNonBlocking));
   for (auto& e : p->ev_copied) if (!e) UR_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   for (auto& e : p->ev_free) if (!e) UR_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
@@ -760,7 +824,10 @@ ur_status ur_simulate_host(ur_plan* p, const void* rho_host, int32_t x_lo, int32
   size_t copied = 0;
   // slab k goes to staging buffer k mod K on copy stream k mod K;
   // ev_copied[b]: buffer b filled, ev_free[b]: buffer b consumed by the z pass
-  for (int b = 0; b < K; ++b) UR_HIP(hipEventRecord(p->ev_free[b], s));
+  for (int b = 0; b < K; ++b) {
+    UR_HIP(hipEventRecord(p->ev_free[b], s));
+    UR_HIP(hipEventRecord(p->ev_copied[b], p->copy_stream[b]));   // after any earlier copy on that stream
+  }
   const int ntl = ntiles(p);
   int zb = 0;
   for (long long xt = xt0; xt <= xt1; ++xt) {
@@ -769,10 +836,20 @@ ur_status ur_simulate_host(ur_plan* p, const void* rho_host, int32_t x_lo, int32
     char* st = (char*)p->stage + buf * slab_bytes;
     const long long sx0 = xt * tx;
     const long long lo = std::max<long long>(sx0, x_lo), hi = std::min<long long>(sx0 + tx - 1, x_hi);
+    const char* src = (const char*)rho_host + (size_t)(lo - x_lo) * plane_bytes;
+    const size_t len = (size_t)(hi - lo + 1) * plane_bytes;
+    if (!pinned) {
+      // pageable input: once the previous copy out of this bounce slab has
+      // finished, the host copies the planes into it (the copies of the
+      // slabs before it and the z / y passes keep running meanwhile)
+      char* bb = (char*)p->bounce + buf * slab_bytes;
+      UR_HIP(hipEventSynchronize(p->ev_copied[buf]));
+      parallel_copy(bb, src, len);
+      src = bb;
+    }
     // wait until the previous user of this staging buffer is done, then copy
     UR_HIP(hipStreamWaitEvent(cs, p->ev_free[buf], 0));
-    UR_HIP(hipMemcpyAsync(st + (lo - sx0) * plane_bytes, (const char*)rho_host + (size_t)lo * plane_bytes,
-                          (size_t)(hi - lo + 1) * plane_bytes, hipMemcpyHostToDevice, cs));
+    UR_HIP(hipMemcpyAsync(st + (lo - sx0) * plane_bytes, src, len, hipMemcpyHostToDevice, cs));
     copied += (size_t)(hi - lo + 1) * plane_bytes;
     UR_HIP(hipEventRecord(p->ev_copied[buf], cs));
     UR_HIP(hipStreamWaitEvent(s, p->ev_copied[buf], 0));
@@ -810,6 +887,24 @@ ur_status ur_simulate_host(ur_plan* p, const void* rho_host, int32_t x_lo, int32
 // z and y passes.
 static ur_status adjoint_run(ur_plan* p, const void* rho, const ur_cell* cell, const ur_mask* mask, const ur_hist* fwd,
                              const double* g_bin, void* grad_rho, double* grad_amp, void* stream, bool reuse);
+
+ur_status ur_host_alloc(size_t bytes, void** out) {
+  if (!out) return fail(UR_ERR_INVALID, "out is null");
+  *out = nullptr;
+  if (bytes == 0) return fail(UR_ERR_INVALID, "bytes must be > 0");
+  if (hipHostMalloc(out, bytes, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    *out = nullptr;
+    return fail(UR_ERR_OOM, "pinned host allocation of %zu bytes failed", bytes);
+  }
+  return UR_OK;
+}
+
+ur_status ur_host_free(void* ptr) {
+  if (!ptr) return UR_OK;
+  UR_HIP(hipHostFree(ptr));
+  return UR_OK;
+}
 
 ur_status ur_adjoint(ur_plan* p, const void* rho, const ur_cell* cell, const ur_mask* mask, const ur_hist* fwd,
                      const double* g_bin, void* grad_rho, double* grad_amp, void* stream) {

@@ -111,12 +111,13 @@ __device__ __forceinline__ int pad(int i) { return i + (i >> 4); }
 template <int N> struct Padded { static constexpr int size = N + N / 16; };
 
 // Elements per lane for a length-N column; G = N / E lanes per column.  Up to
-// N = 1024 a column sits in one wavefront (G <= 64); N = 2048 takes two whole
-// wavefronts (G = 128), with 16 elements per lane as at 1024.
+// N = 1024 a column sits in one wavefront (G <= 64); N = 2048 and 4096 take
+// two and four whole wavefronts (G = 128, 256), with 16 elements per lane as
+// at 1024.
 template <int N> struct Geo {
   static constexpr int E = N <= 16 ? N : (N == 512 ? 8 : 16);
   static constexpr int G = N / E;
-  static_assert(G >= 1 && (G <= 64 || G == 128), "column group: part of one wavefront or two whole ones");
+  static_assert(G >= 1 && (G <= 64 || G == 128 || G == 256), "column group: part of one wavefront or whole ones");
 };
 
 // Ordering of the LDS accesses of the lanes that share a column: the

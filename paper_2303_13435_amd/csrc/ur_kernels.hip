@@ -28,8 +28,11 @@ template <typename T, int N, bool C2C> struct ZCfg {
   static constexpr int G = Geo<N>::G;
   // 2048-point columns span two wavefronts and sync with the workgroup
   // barrier: half-width tiles keep two blocks per CU (measured faster than
-  // one block of full 128-byte rows)
-  static constexpr int want = N == 2048 ? (C2C ? Seg<T>::cols / 2 : Seg<T>::cols / 4) : (C2C ? Seg<T>::cols : Seg<T>::cols / 2);
+  // one block of full 128-byte rows); 4096-point columns (four wavefronts)
+  // take quarter-width tiles for the same LDS budget
+  static constexpr int want = N >= 4096 ? (C2C ? Seg<T>::cols / 4 : Seg<T>::cols / 8)
+                            : N == 2048 ? (C2C ? Seg<T>::cols / 2 : Seg<T>::cols / 4)
+                                        : (C2C ? Seg<T>::cols : Seg<T>::cols / 2);
   static constexpr int fill = 256 / G > 0 ? 256 / G : 1;
   static constexpr int ng0 = want > fill ? want : fill;
   static constexpr int cap = C2C ? N : N / 2;
@@ -40,7 +43,8 @@ template <typename T, int N, bool C2C> struct ZCfg {
 // y pass: x planes per block (two per group)
 template <typename T, int N> struct YCfg {
   static constexpr int G = Geo<N>::G;
-  static constexpr int TX = Seg<T>::cols < N ? Seg<T>::cols : N;
+  // 4096-point columns: half-width tiles (1024 threads, 150 KB of LDS)
+  static constexpr int TX = N >= 4096 ? Seg<T>::cols / 2 : (Seg<T>::cols < N ? Seg<T>::cols : N);
   static constexpr int NS = TX / 2;
   static constexpr int threads = NS * G;
 };
@@ -53,7 +57,8 @@ template <typename T, int N> struct YICfg {
 // x pass: columns per block
 template <int N> struct XCfg {
   static constexpr int G = Geo<N>::G;
-  static constexpr int NG = 256 / G > 0 ? (256 / G < 64 ? 256 / G : 64) : 1;
+  // 4096-point columns: two per block, so that a CU holds eight wavefronts
+  static constexpr int NG = G > 128 ? 2 : (256 / G < 64 ? 256 / G : 64);
   static constexpr int threads = NG * G;
 };
 // LDS column stride: a multiple of 32 elements plus 4, so that reading the
@@ -550,12 +555,12 @@ k_pass_z(ZArgs a) {
   }
 }
 
-// ED materialisation (tile + mask + zoom) into a real [x][y][z] box: one
-// thread per voxel row segment, same generator as the z pass.
+// ED materialisation (tile + mask + zoom) of planes x0, x0 + 1, ... into a
+// real [x - x0][y][z] array: one block per pencil, same generator as the z pass.
 template <typename T>
-__global__ void __launch_bounds__(256) k_rho_generate(ZArgs a, int n, T* __restrict__ rho) {
+__global__ void __launch_bounds__(256) k_rho_generate(ZArgs a, int n, int x0, T* __restrict__ rho) {
   const long long t = blockIdx.x;                 // one block per pencil
-  const long long X = t / n, Y = t % n;
+  const long long X = x0 + t / n, Y = t % n;
   Pencil<T> p;
   p.init(a, X, Y);
   T* row = rho + t * n;
@@ -1567,7 +1572,18 @@ static hipError_t pass_z_t(int mode, const ZArgs& a, int nblocks, hipStream_t s)
   return hipGetLastError();
 }
 
+// 4096^3 boxes run only the out-of-core forward path in FP32: the z pass
+// from staged planes, the forward y pass and the binning x pass
+constexpr int kBig = kMaxOutOfCore;
+static_assert(kMaxInCore == 2048, "the in-HBM dispatch below instantiates sizes up to 2048");
+
 hipError_t launch_pass_z(int prec, int n, int mode, const ZArgs& a, int nblocks, hipStream_t s) {
+  if (n == kBig) {
+    if (prec != 0 || mode != Z_LOAD_R2C) return hipErrorNotSupported;
+    if (nblocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_pass_z<float, kBig, Z_LOAD_R2C>), dim3(nblocks), dim3(ZCfg<float, kBig, false>::threads), 0, s, a);
+    return hipGetLastError();
+  }
 #define UR_Z(NN) return prec == 0 ? pass_z_t<float, NN>(mode, a, nblocks, s) : pass_z_t<double, NN>(mode, a, nblocks, s)
   UR_DISPATCH_N(n, UR_Z);
 #undef UR_Z
@@ -1582,6 +1598,7 @@ static hipError_t pass_y_t(const YArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_pass_y(int prec, int n, const YArgs& a, hipStream_t s) {
+  if (n == kBig) return prec == 0 ? pass_y_t<float, kBig>(a, s) : hipErrorNotSupported;
 #define UR_Y(NN) return prec == 0 ? pass_y_t<float, NN>(a, s) : pass_y_t<double, NN>(a, s)
   UR_DISPATCH_N(n, UR_Y);
 #undef UR_Y
@@ -1598,6 +1615,7 @@ static int x_resident_t(int mode, int dir, int nbins) {
   hipError_t e;
   size_t shm = x_shm(mode, nbins, N);
   if (mode == X_FFT_BIN) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pass_x<T, N, X_FFT_BIN, -1>, XCfg<N>::threads, shm);
+  else if constexpr (N == kBig) return 1;
   else if (mode == X_BIN_ONLY) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pass_x<T, N, X_BIN_ONLY, -1>, XCfg<N>::threads, shm);
   else if (dir < 0) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pass_x<T, N, X_FFT_STORE, -1>, XCfg<N>::threads, shm);
   else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pass_x<T, N, X_FFT_STORE, +1>, XCfg<N>::threads, shm);
@@ -1606,6 +1624,7 @@ static int x_resident_t(int mode, int dir, int nbins) {
 }
 
 int x_resident(int prec, int n, int mode, int dir, int nbins) {
+  if (n == kBig) return prec == 0 && mode == X_FFT_BIN ? x_resident_t<float, kBig>(mode, dir, nbins) : 1;
 #define UR_XR(NN) return prec == 0 ? x_resident_t<float, NN>(mode, dir, nbins) : x_resident_t<double, NN>(mode, dir, nbins)
   switch (n) {
     case 16: UR_XR(16); case 32: UR_XR(32); case 64: UR_XR(64); case 128: UR_XR(128);
@@ -1635,6 +1654,7 @@ static hipError_t pass_x_t(int mode, int dir, const XArgs& a, int nblocks, hipSt
   if (XCfg<N>::G > 64 && a.ncols % XCfg<N>::NG != 0) return hipErrorInvalidValue;
   dim3 grid(nblocks), blk(XCfg<N>::threads);
   if (mode == X_FFT_BIN) hipLaunchKernelGGL((k_pass_x<T, N, X_FFT_BIN, -1>), grid, blk, shm, s, a);
+  else if constexpr (N == kBig) return hipErrorNotSupported;
   else if (mode == X_BIN_ONLY) hipLaunchKernelGGL((k_pass_x<T, N, X_BIN_ONLY, -1>), grid, blk, shm, s, a);
   else if (dir < 0) hipLaunchKernelGGL((k_pass_x<T, N, X_FFT_STORE, -1>), grid, blk, shm, s, a);
   else hipLaunchKernelGGL((k_pass_x<T, N, X_FFT_STORE, +1>), grid, blk, shm, s, a);
@@ -1642,6 +1662,10 @@ static hipError_t pass_x_t(int mode, int dir, const XArgs& a, int nblocks, hipSt
 }
 
 hipError_t launch_pass_x(int prec, int n, int mode, int dir, const XArgs& a, int nblocks, hipStream_t s) {
+  if (n == kBig) {
+    if (prec != 0 || mode != X_FFT_BIN) return hipErrorNotSupported;
+    return pass_x_t<float, kBig>(mode, dir, a, nblocks, s);
+  }
 #define UR_X(NN) return prec == 0 ? pass_x_t<float, NN>(mode, dir, a, nblocks, s) : pass_x_t<double, NN>(mode, dir, a, nblocks, s)
   UR_DISPATCH_N(n, UR_X);
 #undef UR_X
@@ -1770,10 +1794,10 @@ hipError_t launch_grad_amp(int c, int n_atoms, const double* prof, const double*
   return hipGetLastError();
 }
 
-hipError_t launch_rho_generate(int prec, int n, const ZArgs& a, void* rho, hipStream_t s) {
-  unsigned nn = (unsigned)((long long)n * n);
-  if (prec == 0) hipLaunchKernelGGL(k_rho_generate<float>, dim3(nn), dim3(256), 0, s, a, n, (float*)rho);
-  else hipLaunchKernelGGL(k_rho_generate<double>, dim3(nn), dim3(256), 0, s, a, n, (double*)rho);
+hipError_t launch_rho_generate(int prec, int n, int x_lo, int x_hi, const ZArgs& a, void* rho, hipStream_t s) {
+  const unsigned nn = (unsigned)((long long)(x_hi - x_lo + 1) * n);
+  if (prec == 0) hipLaunchKernelGGL(k_rho_generate<float>, dim3(nn), dim3(256), 0, s, a, n, x_lo, (float*)rho);
+  else hipLaunchKernelGGL(k_rho_generate<double>, dim3(nn), dim3(256), 0, s, a, n, x_lo, (double*)rho);
   return hipGetLastError();
 }
 
@@ -1797,6 +1821,7 @@ int fft_stages(int n, int* Ls, int* Rs) {
     case 64: return stages_t<64>(Ls, Rs); case 128: return stages_t<128>(Ls, Rs);
     case 256: return stages_t<256>(Ls, Rs); case 512: return stages_t<512>(Ls, Rs);
     case 1024: return stages_t<1024>(Ls, Rs); case 2048: return stages_t<2048>(Ls, Rs);
+    case kBig: return stages_t<kBig>(Ls, Rs);
     default: return 0;
   }
 }
@@ -1805,6 +1830,7 @@ int fft_stages(int n, int* Ls, int* Rs) {
 #define UR_TILE(NN) { if (prec == 0) return c2c ? ZCfg<float, NN, true>::TY : ZCfg<float, NN, false>::TY; \
                       return c2c ? ZCfg<double, NN, true>::TY : ZCfg<double, NN, false>::TY; }
 int z_tile(int prec, int n, int c2c) {
+  if (n == kBig) return prec == 0 && !c2c ? ZCfg<float, kBig, false>::TY : 0;
   switch (n) {
     case 16: UR_TILE(16) case 32: UR_TILE(32) case 64: UR_TILE(64) case 128: UR_TILE(128)
     case 256: UR_TILE(256) case 512: UR_TILE(512) case 1024: UR_TILE(1024) case 2048: UR_TILE(2048)
@@ -1816,6 +1842,7 @@ int zinv_tile(int prec, int n, int c2c) { return z_tile(prec, n, c2c); }
 
 #define UR_YT(NN) return prec == 0 ? YCfg<float, NN>::TX : YCfg<double, NN>::TX
 int y_tile(int prec, int n) {
+  if (n == kBig) return prec == 0 ? YCfg<float, kBig>::TX : 0;
   switch (n) {
     case 16: UR_YT(16); case 32: UR_YT(32); case 64: UR_YT(64); case 128: UR_YT(128);
     case 256: UR_YT(256); case 512: UR_YT(512); case 1024: UR_YT(1024); case 2048: UR_YT(2048);
@@ -1829,6 +1856,7 @@ int x_groups(int n) {
   switch (n) {
     case 16: UR_XG(16); case 32: UR_XG(32); case 64: UR_XG(64); case 128: UR_XG(128);
     case 256: UR_XG(256); case 512: UR_XG(512); case 1024: UR_XG(1024); case 2048: UR_XG(2048);
+    case kBig: UR_XG(kBig);
     default: return 0;
   }
 }

@@ -8,6 +8,11 @@
 
 namespace ur {
 
+// Box edges: every path up to kMaxInCore; FP32 real boxes up to
+// kMaxOutOfCore through the out-of-core forward path only.
+constexpr int kMaxInCore = 2048;
+constexpr int kMaxOutOfCore = 4096;
+
 // Density source of the first (z) pass.
 // GEN: ED-1 voxels (block factor 1); ZOOM: block-summed zoom levels.
 enum ZMode { Z_GEN_R2C = 0, Z_LOAD_R2C = 1, Z_GEN_C2C = 2, Z_LOAD_C2C = 3, Z_ZOOM_R2C = 4, Z_ZOOM_C2C = 5 };
@@ -189,7 +194,7 @@ hipError_t launch_pass_z_fold(int prec, int n, const ZFoldArgs& a, int nblocks, 
 hipError_t launch_fold_reduce_classes(int c, const double* part, int nblk, double* gcell, hipStream_t s);
 hipError_t launch_fold_reduce(int c3, const double* part, int nblk, double* gcell, hipStream_t s);
 hipError_t launch_grad_amp(int c, int n_atoms, const double* prof, const double* gcell, double* grad_amp, hipStream_t s);
-hipError_t launch_rho_generate(int prec, int n, const ZArgs& a, void* rho, hipStream_t s);
+hipError_t launch_rho_generate(int prec, int n, int x_lo, int x_hi, const ZArgs& a, void* rho, hipStream_t s);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 hipError_t launch_bin_counts(int n, int nkz, int r2c, int nbins, const int* U, unsigned long long* tmp, double* out, hipStream_t s);
 int x_resident(int prec, int n, int mode, int dir, int nbins);   // resident x-pass blocks per CU

@@ -180,16 +180,18 @@ def test_zoom_levels_end_to_end_merge(ur, orc):
 # out-of-core streaming and graph replay
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("n,prec", [(64, 1), (128, 0)])
-def test_out_of_core_matches_oracle(ur, orc, n, prec):
+@pytest.mark.parametrize("n,prec,pinned", [(64, 1, True), (128, 0, True), (64, 1, False), (128, 0, False)])
+def test_out_of_core_matches_oracle(ur, orc, n, prec, pinned):
+    """Streamed from host memory against the whole oracle, from page-locked
+    memory (direct copies) and from pageable memory (pinned bounce slabs)."""
     import torch
     wl = W.small(n, c=8, n_atoms=7, seed=81, mask=W.trunc_oct(0.4 * n), nbins=60, prec=prec)
     ref = orc.simulate(wl, return_fields=True)
     rho = ref["rho"]
     nz = np.flatnonzero(np.any(rho != 0.0, axis=(1, 2)))
     x_lo, x_hi = int(nz.min()), int(nz.max())
-    host = torch.empty((n, n, n), dtype=torch.float32 if prec == 0 else torch.float64, pin_memory=True)
-    host.copy_(torch.as_tensor(rho))
+    host = torch.empty((x_hi - x_lo + 1, n, n), dtype=torch.float32 if prec == 0 else torch.float64, pin_memory=pinned)
+    host.copy_(torch.as_tensor(rho[x_lo:x_hi + 1]))
     plan = ur.Plan(n, 1.0, prec)
     plan.set_bins(wl.edges)
     h = ur.Hist(wl.nbins)
@@ -223,12 +225,13 @@ def test_out_of_core_2048_c5_recipe(ur, orc):
     h_dev = ur.Hist(wl.nbins)
     plan.simulate_rho(rho, h_dev)
     torch.cuda.synchronize()
-    host = torch.empty((n, n, n), dtype=torch.float32, pin_memory=True)
-    host.copy_(rho)
-    del rho
-    torch.cuda.empty_cache()
     hw = int(wl.mask.p0)                                   # half-width of the truncated octahedron
     x_lo, x_hi = n // 2 - hw, n // 2 + hw
+    hb = ur.HostBuffer((x_hi - x_lo + 1, n, n), torch.float32)
+    host = hb.tensor
+    host.copy_(rho[x_lo:x_hi + 1])
+    del rho
+    torch.cuda.empty_cache()
     h_host = ur.Hist(wl.nbins)
     nbytes = plan.simulate_host(host, x_lo, x_hi, h_host)
     torch.cuda.synchronize()
@@ -247,6 +250,7 @@ def test_out_of_core_2048_c5_recipe(ur, orc):
     assert abs(a["totals"][1] - s1 / n3) <= 1e-6 * s1 / n3          # Re F(0)
     assert abs(a["totals"][3] - s2) <= 1e-6 * s2                    # sum of rho^2 of the streamed planes
     del host, plan
+    hb.close()
     torch.cuda.empty_cache()
 
 

@@ -482,3 +482,55 @@ def test_dft_points_large_box_phase_reduction(oracle_lib):
     got = oracle.dft_points(n, xyz, val, uvw)
     ref = ref_c[uvw[:, 0] % m, uvw[:, 1] % m, uvw[:, 2] % m]
     assert np.max(np.abs(got - ref)) <= 1e-13 * np.max(np.abs(ref))
+
+
+# ---------------------------------------------------------------------------
+# O12: per-bin counts and two-voxel intensities without the n^3 loops (used
+# at 4096^3, where neither the oracle transform nor its binning loop fits)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n", [16, 32, 64])
+def test_separable_counts_equal_voxel_loop(oracle_lib, n):
+    """Counts taken axis by axis against the n^3 voxel loop, for log bins
+    (last edge inclusive) and linear bins that end inside the box."""
+    import oracle
+    for edges in (W.default_log_edges(n, 1.0, 40), W.lin_edges(0.0, 0.8 * math.pi, 23)):
+        cnt, _ = oracle.axis_pair_bins(n, 1.0, edges, 3, 1.0, 0.5)
+        assert np.array_equal(cnt, oracle_lib.bin_counts(n, 1.0, edges))
+
+
+@pytest.mark.parametrize("n", [16, 32])
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_two_voxel_bin_sums_match_library_transform(oracle_lib, n, axis):
+    """Two voxels d apart along one axis: the closed form of O12 against
+    numpy.fft.fftn / n^3 binned voxel by voxel, for a d coprime to n (every
+    phase distinct) and d = n/2 (alternating signs)."""
+    import oracle
+    edges = W.default_log_edges(n, 1.0, 30)
+    for d in (3, n // 2):
+        p = np.array([5, 9, 2])
+        q = p.copy()
+        q[axis] = (q[axis] + d) % n
+        rho = np.zeros((n, n, n))
+        rho[tuple(p)] = 1.0
+        rho[tuple(q)] = 0.6
+        ref = oracle_lib.bin_spectrum(np.fft.fftn(rho) / float(n) ** 3, 1.0, edges)
+        cnt, s = oracle.axis_pair_bins(n, 1.0, edges, d, 1.0, 0.6)
+        assert np.array_equal(cnt, ref["count"])
+        assert np.max(np.abs(s - ref["sum"])) <= 1e-12 * np.max(ref["sum"])
+
+
+def test_sparse_low_bins_match_full_binning(oracle_lib):
+    """Bins below n2 = m from direct summation over the nonzero voxels
+    against numpy.fft.fftn / n^3 binned voxel by voxel."""
+    import oracle
+    n = 32
+    xyz, val = W.sparse_voxels(91, n, 23, dtype=np.float64)
+    rho = np.zeros((n, n, n))
+    np.add.at(rho, (xyz[:, 0], xyz[:, 1], xyz[:, 2]), val)
+    edges = W.default_log_edges(n, 1.0, 60)
+    ref = oracle_lib.bin_spectrum(np.fft.fftn(rho) / float(n) ** 3, 1.0, edges)
+    bins, cnt, s, mean = oracle.sparse_low_bins(n, 1.0, edges, xyz, val, (n // 2) ** 2)
+    assert len(bins) > 20
+    assert np.array_equal(cnt, ref["count"][bins])
+    assert np.allclose(s, ref["sum"][bins], rtol=1e-12, atol=0.0)

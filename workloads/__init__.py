@@ -199,6 +199,16 @@ def sparse_voxels(seed: int, n: int, npts: int, dtype=np.float32):
     return xyz, val
 
 
+def sparse_slab(seed: int, n: int, x_lo: int, planes: int, npts: int, dtype=np.float32):
+    """npts distinct random voxels of planes x_lo .. x_lo + planes - 1 of an
+    n^3 box (any y, z), values in [0.5, 2) rounded to dtype."""
+    rng = np.random.default_rng(seed)
+    flat = rng.choice(planes * n * n, size=npts, replace=False)
+    xyz = np.stack([x_lo + flat // (n * n), (flat // n) % n, flat % n], axis=1).astype(np.int64)
+    val = rng.uniform(0.5, 2.0, npts).astype(dtype)
+    return xyz, val
+
+
 def random_frequencies(seed: int, n: int, count: int, half_z: bool = True) -> np.ndarray:
     """count random frequency triples (u, v, w) of an n^3 box, w in [0, n/2]
     for a half spectrum, plus the corners (0,0,0) and (n/2, n/2, n/2)."""
