@@ -211,6 +211,11 @@ def mask_planes(W, wl):
     return wl.n // 2 - r, wl.n // 2 + r
 
 
+def note(msg):
+    """Progress on stderr (stdout carries only the JSON line)."""
+    print(f"# {msg}", file=sys.stderr, flush=True)
+
+
 def out_of_core(ur, W, torch, wl, reps, pinned=True):
     """A box with its density in host memory: only the planes that hold
     density are copied, slab by slab, overlapped with the z and y passes
@@ -223,6 +228,7 @@ def out_of_core(ur, W, torch, wl, reps, pinned=True):
     t_fill = time.perf_counter()
     host, hb = fill_host(ur, torch, plan, cell, wl, x_lo, x_hi, pinned)
     t_fill = time.perf_counter() - t_fill
+    note(f"out-of-core {wl.name}: host density filled in {t_fill:.1f} s")
     h = ur.Hist(wl.nbins)
     nbytes = plan.simulate_host(host, x_lo, x_hi, h)
     torch.cuda.synchronize()
@@ -325,6 +331,7 @@ def main():
         h64 = ur.Hist(wl.nbins)
         ms64, _ = time_steps(lambda: p64.simulate(cell, wl.mask, wl.zoom, h64), max(3, args.steps // 2), 2, torch)
         extras["fp64"] = {"ms_per_step": round(ms64, 4), "voxels_per_s": wl.n ** 3 / (ms64 * 1e-3)}
+        note("fp64 done")
         del p64
         # forward + adjoint (chi^2 gradient w.r.t. the atom amplitudes), FP32
         d = hist.numpy()
@@ -344,13 +351,16 @@ def main():
 
         ms_fk, _ = time_steps(fwd_adj_keep, max(3, args.steps // 2), 2, torch)
         extras["fwd_adjoint_keep_ms"] = round(ms_fk, 4)       # adjoint from the held y-pass output
+        note("fwd_adjoint_keep_ms done")
         torch.cuda.synchronize()
         del fwd_adj
         # multi-zoom batch: ED-1 2048^3 + ED-2 1024^3 (f 4) + ED-3 512^3 (f 16)
         # and the merge, recorded in one HIP graph and replayed
         extras["c3_batch"] = c3_batch(ur, W, torch, max(2, args.steps // 4))
+        note("c3_batch done")
         # many particle sizes: 32 radii of 256^3 boxes in one graph
         extras["radii_batch"] = radii_batch(ur, W, torch, max(2, args.steps // 4))
+        note("radii_batch done")
         # out-of-core: the same box streamed from pinned host memory
         extras["out_of_core"] = out_of_core(ur, W, torch, wl, max(2, args.steps // 4))
         # the same from pageable host memory (pinned bounce slabs)
