@@ -54,3 +54,9 @@ def test_version_and_errors_without_gpu(built_lib):
     assert b"power of two" in built_lib.ur_last_error()
     assert built_lib.ur_plan_create(64, -1.0, 0, 0, ctypes.byref(h)) == 1       # bad voxel
     assert built_lib.ur_plan_create(64, 1.0, 7, 0, ctypes.byref(h)) == 1        # bad precision
+    # box limits: 4096^3 only in FP32 real, nothing above; complex only up to 1024^3
+    assert built_lib.ur_plan_create(8192, 1.0, 0, 0, ctypes.byref(h)) == 2
+    assert built_lib.ur_plan_create(4096, 1.0, 1, 0, ctypes.byref(h)) == 2      # FP64
+    assert built_lib.ur_plan_create(4096, 1.0, 0, 1, ctypes.byref(h)) == 2      # complex
+    assert built_lib.ur_plan_create(2048, 1.0, 0, 1, ctypes.byref(h)) == 2      # complex above 1024
+    assert not h.value

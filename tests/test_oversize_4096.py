@@ -1,5 +1,5 @@
 """4096^3 boxes through the out-of-core forward path (the 2D + 1D split of
-eq. 2): the density lives in pinned host memory, only its planes are copied,
+eq. 2): the density lives in host memory, only its planes are copied,
 and the spectrum kept in HBM covers just those planes.
 
 Neither the oracle transform nor its n^3 binning loop fits this size, so the
@@ -67,6 +67,27 @@ def _check_totals(got, s1, s2):
     assert abs(got["totals"][1] - s1 / n3) <= 1e-6 * s1 / n3        # Re F(0)
     assert abs(got["totals"][2]) <= 1e-6 * s1 / n3                  # Im F(0)
     assert abs(got["totals"][3] - s2) <= 1e-6 * s2                  # sum of rho^2 streamed
+
+
+@pytest.mark.gpu
+def test_in_hbm_calls_refused(ur, edges):
+    """A 4096^3 plan runs only the out-of-core path: the in-HBM forward call
+    and the adjoint fail with UR_ERR_UNSUPPORTED before any launch."""
+    import torch
+    wl = W.c5(N)
+    plan = ur.Plan(N, 1.0, ur.UR_F32)
+    plan.set_bins(edges)
+    cell = ur.DeviceCell.from_host(wl.cell)
+    h = ur.Hist(len(edges) - 1)
+    with pytest.raises(ur.UltimaError, match="status 2"):
+        plan.simulate(cell, wl.mask, wl.zoom, h)
+    g = torch.zeros(len(edges) - 1, dtype=torch.float64, device="cuda")
+    ga = torch.zeros(wl.cell.n_atoms, dtype=torch.float64, device="cuda")
+    with pytest.raises(ur.UltimaError, match="status 2"):
+        plan.adjoint(h, g, cell=cell, mask=wl.mask, grad_amp=ga)
+    with pytest.raises(ur.UltimaError, match="status 2"):
+        plan.workspace_size()
+    torch.cuda.synchronize()
 
 
 @pytest.mark.gpu
