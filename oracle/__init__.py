@@ -13,6 +13,7 @@ correct statement of the computation, written from the paper:
 * O10 chi^2 misfit of a binned curve and its gradients (derived from eq. 1)
 * O11 low-frequency Fourier coefficients by direct summation (eq. 1/eq. 2)
 * O12 per-bin counts and two-voxel intensities of boxes too large for O4-O8
+* O13 per-bin intensities of a uniform cube at any box size (eq. 1 factorised)
 
 The heavy loops live in ``ur_oracle.c`` (plain C, FP64, OpenMP over
 independent lines); this module marshals numpy arrays and holds the small
@@ -83,6 +84,8 @@ def lib():
                                     ctypes.c_void_p]
         L.or_axis_pair_bins.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_int, _D, ctypes.c_longlong,
                                         ctypes.c_double, ctypes.c_double, _D, _D]
+        L.or_cube_bins.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_int, _D, ctypes.c_longlong,
+                                   ctypes.c_double, _D, _D]
         _LIB = L
     return _LIB
 
@@ -287,6 +290,16 @@ def axis_pair_bins(n: int, voxel: float, edges: np.ndarray, d: int, rho1: float,
     count, s = np.zeros(nb), np.zeros(nb)
     lib().or_axis_pair_bins(int(n), float(voxel), int(nb), _dp(e), int(d), float(rho1), float(rho2),
                             _dp(count), _dp(s))
+    return count, s
+
+
+def cube_bins(n: int, voxel: float, edges: np.ndarray, half_width: int, value: float = 1.0):
+    """O13: per-bin voxel count and sum of |F|^2 (eq. 1) over the n^3 box for
+    a uniform cube of the given value on max_i |x_i - n/2| <= half_width."""
+    e = np.ascontiguousarray(edges, dtype=np.float64)
+    nb = e.size - 1
+    count, s = np.zeros(nb), np.zeros(nb)
+    lib().or_cube_bins(int(n), float(voxel), int(nb), _dp(e), int(half_width), float(value), _dp(count), _dp(s))
     return count, s
 
 

@@ -432,6 +432,107 @@ void or_axis_pair_bins(int n, double voxel, int nbins, const double* edges, long
 }
 
 /* ------------------------------------------------------------------------ */
+/* O13  per-bin sums of a uniform cube (value v on every voxel with
+ *      max_i |x_i - n/2| <= hw, zero elsewhere) at any n.  The density is a
+ *      product of one indicator per axis, so eq. 1 factorises:
+ *      F(h, k, l) = v S(h) S(k) S(l) / n^3 with S(u) the sum of
+ *      exp(-2 pi i u x / n) over the 2 hw + 1 voxels of one axis, evaluated
+ *      here by direct summation (integer phase reduced mod n).  With
+ *      a(u) = |S(u)|^2, the sum of |F|^2 over bin b is
+ *      v^2 / n^6 * sum over (h, k) of a(h) a(k) * (sum of a(l) over the l with
+ *      U_b <= h^2 + k^2 + l^2 < U_b+1); the inner sum is a difference of the
+ *      running sums of a(l) over |l| <= r.  Outputs count[b] and sum[b].      */
+/* ------------------------------------------------------------------------ */
+static long long isqrt_floor(long long v)
+{
+    if (v <= 0) return 0;
+    long long r = (long long)sqrt((double)v);
+    while (r * r > v) --r;
+    while ((r + 1) * (r + 1) <= v) ++r;
+    return r;
+}
+
+void or_cube_bins(int n, double voxel, int nbins, const double* edges, long long hw, double v,
+                  double* count, double* sum)
+{
+    long long* U = (long long*)malloc(sizeof(long long) * (nbins + 1));
+    or_thresholds(n, voxel, nbins, edges, U);
+    const long long h2 = n / 2;
+    /* a[u + n/2] = |S(u)|^2 for u in [-n/2, n/2) */
+    double* a = (double*)malloc(sizeof(double) * n);
+#pragma omp parallel for schedule(static)
+    for (long long u = -h2; u < h2; ++u) {
+        cdouble s = 0;
+        for (long long x = h2 - hw; x <= h2 + hw; ++x) {
+            long long e = pmod(u * x, n);
+            s += cexp(-2.0 * M_PI * I * (double)e / (double)n);
+        }
+        a[u + h2] = creal(s) * creal(s) + cimag(s) * cimag(s);
+    }
+    /* P[r] = sum of a(l) over l in [-n/2, n/2) with |l| <= r, kept as an
+     * unevaluated pair Ph + Pl (exact two-sum accumulation): a bin's range
+     * sum P[r1] - P[r0] can be many orders below P itself, and a single
+     * rounded prefix would lose those digits.  Q[r] = number of such l.    */
+    double* Ph = (double*)malloc(sizeof(double) * (h2 + 1));
+    double* Pl = (double*)malloc(sizeof(double) * (h2 + 1));
+    long long* Q = (long long*)malloc(sizeof(long long) * (h2 + 1));
+    {
+        double hi = 0.0, lo = 0.0;
+#define OR_TWO_SUM_ADD(x) do { double t_ = hi + (x); double bp_ = t_ - hi; \
+        lo += (hi - (t_ - bp_)) + ((x) - bp_); hi = t_; } while (0)
+        OR_TWO_SUM_ADD(a[h2]);
+        Ph[0] = hi; Pl[0] = lo;
+        Q[0] = 1;
+        for (long long r = 1; r <= h2; ++r) {
+            if (r < h2) OR_TWO_SUM_ADD(a[h2 + r]);      /* l = +r exists only below n/2 */
+            OR_TWO_SUM_ADD(a[h2 - r]);
+            Ph[r] = hi; Pl[r] = lo;
+            Q[r] = Q[r - 1] + (r < h2 ? 2 : 1);
+        }
+#undef OR_TWO_SUM_ADD
+    }
+    const int nt = omp_get_max_threads();
+    long long* cnt_t = (long long*)calloc((size_t)nt * nbins, sizeof(long long));
+    kahan_t* sum_t = (kahan_t*)calloc((size_t)nt * nbins, sizeof(kahan_t));
+#pragma omp parallel
+    {
+        const int t = omp_get_thread_num();
+        long long* mc = cnt_t + (size_t)t * nbins;
+        kahan_t* ms = sum_t + (size_t)t * nbins;
+#pragma omp for schedule(dynamic, 16)
+        for (long long hh = -h2; hh < h2; ++hh)
+            for (long long kk = -h2; kk < h2; ++kk) {
+                const long long s2 = hh * hh + kk * kk;
+                const double w = a[hh + h2] * a[kk + h2];
+                /* first bin whose upper threshold exceeds s2 */
+                int lo = 0, hi = nbins;
+                while (lo < hi) { int mid = (lo + hi) / 2; if (U[mid + 1] <= s2) lo = mid + 1; else hi = mid; }
+                for (int b = lo; b < nbins && U[b] <= s2 + h2 * h2; ++b) {
+                    const long long m0 = U[b] - s2, m1 = U[b + 1] - s2;   /* l^2 in [m0, m1) */
+                    const long long r0 = m0 <= 0 ? -1 : (isqrt_floor(m0 - 1) < h2 ? isqrt_floor(m0 - 1) : h2);
+                    const long long r1 = m1 <= 0 ? -1 : (isqrt_floor(m1 - 1) < h2 ? isqrt_floor(m1 - 1) : h2);
+                    if (r1 <= r0) continue;
+                    mc[b] += Q[r1] - (r0 >= 0 ? Q[r0] : 0);
+                    const double d = r0 >= 0 ? (Ph[r1] - Ph[r0]) + (Pl[r1] - Pl[r0]) : Ph[r1] + Pl[r1];
+                    kadd(&ms[b], w * d);
+                }
+            }
+    }
+    const double norm = v * v / ((double)n * n * n) / ((double)n * n * n);
+    for (int b = 0; b < nbins; ++b) {
+        long long c = 0;
+        kahan_t k = {0, 0};
+        for (int t = 0; t < nt; ++t) {
+            c += cnt_t[(size_t)t * nbins + b];
+            kadd(&k, kval(&sum_t[(size_t)t * nbins + b]));
+        }
+        count[b] = (double)c;
+        sum[b] = kval(&k) * norm;
+    }
+    free(cnt_t); free(sum_t); free(Ph); free(Pl); free(Q); free(a); free(U);
+}
+
+/* ------------------------------------------------------------------------ */
 /* O11  Fourier coefficients on a small cube of low frequencies
  *     |h|, |k|, |l| <= K of the box of level (n1, f, nk), straight from eq. 1
  *     summed in the order of eq. 2 (z, then y, then x), with the density

@@ -434,6 +434,56 @@ def test_m1024_full_size_sampled(ur, orc, prec):
     assert ok.sum() >= 30 and rel.max() <= (1e-5 if prec == 0 else 1e-12)
 
 
+def bin_bound(n, mean, ibar, prec):
+    """Per-bin relative error bound of a transform in the given precision.
+    An FFT's rounding error is norm-wise, |dF| ~ eps sqrt(log2 n^3) |F|_rms,
+    so a coefficient whose intensity lies far below the box mean Ibar carries
+    a relative error up to ~ 2 eps sqrt(log2 n^3) sqrt(Ibar / I); for a
+    structured density (a cube) these errors are systematic across a shell
+    and do not average out over the bin.  Bound: 8 eps sqrt(log2 n^3)
+    sqrt(Ibar / I_b), never below the plain tolerance (1e-5 FP32, 1e-12 FP64)."""
+    eps, tol = (2.0 ** -24, 1e-5) if prec == 0 else (2.0 ** -53, 1e-12)
+    return np.maximum(tol, 8.0 * eps * math.sqrt(3 * math.log2(n)) * np.sqrt(ibar / mean))
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+def test_uniform_cube_every_bin_2048(ur, orc, prec):
+    """2048^3 in HBM (the in-HBM path's largest box): a uniform cube of
+    half-width 700, every one of 1024 bins against the factorised closed form
+    of eq. 1 (O13): counts bit-exact; means within 1e-5 (FP32) / 1e-12
+    (FP64), or the transform's error bound (bin_bound) where a bin's mean
+    lies far below the box mean."""
+    import torch
+    wl = W.uniform_cube(2048, 700, 1024, prec)
+    _say(f"uniform cube 2048^3 prec={prec}")
+    plan = ur.Plan(wl.n, wl.voxel, prec)
+    plan.set_bins(wl.edges)
+    h = ur.Hist(wl.nbins)
+    plan.simulate(ur.DeviceCell.from_host(wl.cell), wl.mask, wl.zoom, h)
+    torch.cuda.synchronize()
+    got = h.numpy()
+    del plan
+    torch.cuda.empty_cache()
+    cnt, s = orc.cube_bins(wl.n, 1.0, wl.edges, 700, 1.0)
+    assert np.array_equal(got["count"], cnt)
+    pop = cnt > 0
+    ref = s[pop] / cnt[pop]
+    n3 = float(wl.n) ** 3
+    w3 = float(2 * 700 + 1) ** 3
+    ibar = w3 / n3 / n3
+    rel = np.abs(got["mean"][pop] - ref) / ref
+    bound = bin_bound(wl.n, ref, ibar, prec)
+    tol = 1e-5 if prec == 0 else 1e-12
+    _say(f"  {pop.sum()} bins, max rel err {rel.max():.3e}, max err/bound {np.max(rel / bound):.3f}, "
+         f"bins above {tol:g}: {int(np.sum(rel > tol))}")
+    for i in np.argsort(rel / bound)[-4:]:
+        _say(f"    bin {np.flatnonzero(pop)[i]}: count {cnt[pop][i]:.0f}, I/Ibar {ref[i] / ibar:.3e}, "
+             f"rel err {rel[i]:.3e}, bound {bound[i]:.3e}")
+    assert np.all(rel <= bound)
+    assert abs(got["totals"][0] - w3 / n3) <= 1e-6 * w3 / n3                 # Parseval
+    assert abs(got["totals"][1] - w3 / n3) <= 1e-6 * w3 / n3                 # F(0)
+
+
 # ---------------------------------------------------------------------------
 # multi-zoom batch at full size: ED-1 2048^3, ED-2 1024^3 (f 4), ED-3 512^3 (f 16)
 # ---------------------------------------------------------------------------

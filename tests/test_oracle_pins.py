@@ -534,3 +534,42 @@ def test_sparse_low_bins_match_full_binning(oracle_lib):
     assert len(bins) > 20
     assert np.array_equal(cnt, ref["count"][bins])
     assert np.allclose(s, ref["sum"][bins], rtol=1e-12, atol=0.0)
+
+
+@pytest.mark.parametrize("n,hw", [(16, 0), (16, 3), (32, 5), (32, 15), (64, 20)])
+def test_cube_bin_sums_match_library_transform(oracle_lib, n, hw):
+    """O13 against numpy.fft.fftn / n^3 of the uniform cube binned voxel by
+    voxel: a single voxel (flat |F|^2), small and box-filling cubes."""
+    import oracle
+    edges = W.default_log_edges(n, 1.0, 40)
+    rho = np.zeros((n, n, n))
+    c = n // 2
+    rho[c - hw:c + hw + 1, c - hw:c + hw + 1, c - hw:c + hw + 1] = 1.5
+    ref = oracle_lib.bin_spectrum(np.fft.fftn(rho) / float(n) ** 3, 1.0, edges)
+    cnt, s = oracle.cube_bins(n, 1.0, edges, hw, 1.5)
+    assert np.array_equal(cnt, ref["count"])
+    assert np.max(np.abs(s - ref["sum"])) <= 1e-12 * np.max(ref["sum"])
+    # Parseval over the binned plus unbinned voxels: only n2 = 0 is unbinned
+    F0 = 1.5 * (2 * hw + 1) ** 3 / float(n) ** 3
+    assert abs(s.sum() + F0 ** 2 - 1.5 ** 2 * (2 * hw + 1) ** 3 / float(n) ** 3) <= 1e-12 * F0 ** 2
+
+
+def test_cube_bin_sums_per_bin_at_128(oracle_lib):
+    """O13 bin by bin at 128^3 against numpy.fft.fftn: the sum over the l of
+    one bin is a short range of a long running sum, so its relative accuracy
+    is checked per bin (to the library transform's own rounding level),
+    not against the largest bin."""
+    import oracle
+    n, hw = 128, 50
+    edges = W.default_log_edges(n, 1.0, 120)
+    rho = np.zeros((n, n, n))
+    c = n // 2
+    rho[c - hw:c + hw + 1, c - hw:c + hw + 1, c - hw:c + hw + 1] = 1.0
+    ref = oracle_lib.bin_spectrum(np.fft.fftn(rho) / float(n) ** 3, 1.0, edges)
+    cnt, s = oracle.cube_bins(n, 1.0, edges, hw, 1.0)
+    assert np.array_equal(cnt, ref["count"])
+    pop = cnt > 0
+    ibar = (2 * hw + 1) ** 3 / float(n) ** 6
+    mean = s[pop] / cnt[pop]
+    bound = np.maximum(1e-13, 8 * 2.0 ** -53 * math.sqrt(21.0) * np.sqrt(ibar / mean))
+    assert np.all(np.abs(mean - ref["mean"][pop]) / mean <= bound)

@@ -119,6 +119,47 @@ def test_two_voxels_every_bin(ur, orc, edges, axis):
 
 
 @pytest.mark.gpu
+def test_uniform_cube_every_bin(ur, orc, edges):
+    """A dense density at 4096^3: a uniform cube of half-width 300 (601
+    planes, 37.6 GiB of pageable host memory, generated on the device),
+    every one of the 2048 bins against the factorised closed form of eq. 1
+    (O13): counts bit-exact, means within 1e-5 or the FP32 transform's
+    norm-wise error bound where a bin's mean lies far below the box mean."""
+    import math
+    import torch
+    hw = 300
+    wl = W.uniform_cube(N, hw, 2048)
+    x_lo, x_hi = N // 2 - hw, N // 2 + hw
+    _say(f"4096^3 uniform cube, planes [{x_lo}, {x_hi}]")
+    plan = ur.Plan(N, 1.0, ur.UR_F32)
+    plan.set_bins(edges)
+    cell = ur.DeviceCell.from_host(wl.cell)
+    host = torch.empty((x_hi - x_lo + 1, N, N), dtype=torch.float32)
+    for a in range(x_lo, x_hi + 1, 64):
+        b = min(a + 63, x_hi)
+        host[a - x_lo:b - x_lo + 1].copy_(plan.rho_generate(cell, wl.mask, wl.zoom, x_lo=a, x_hi=b))
+    torch.cuda.synchronize()
+    del plan
+    torch.cuda.empty_cache()
+    got = _stream(ur, host, x_lo, x_hi, edges)
+    del host
+    cnt, s = orc.cube_bins(N, 1.0, edges, hw, 1.0)
+    assert np.array_equal(got["count"], cnt)
+    pop = cnt > 0
+    ref = s[pop] / cnt[pop]
+    w3 = float(2 * hw + 1) ** 3
+    ibar = w3 / float(N) ** 6
+    rel = np.abs(got["mean"][pop] - ref) / ref
+    # norm-wise FFT rounding error, systematic over a shell for a cube (see
+    # bin_bound in test_gpu_path.py)
+    bound = np.maximum(1e-5, 8.0 * 2.0 ** -24 * math.sqrt(36.0) * np.sqrt(ibar / ref))
+    _say(f"  {pop.sum()} bins, max rel err {rel.max():.3e}, max err/bound {np.max(rel / bound):.3f}, "
+         f"bins above 1e-5: {int(np.sum(rel > 1e-5))}")
+    assert np.all(rel <= bound)
+    _check_totals(got, w3, w3)
+
+
+@pytest.mark.gpu
 def test_sparse_slab_low_bins(ur, orc, edges):
     """48 random voxels in 16 planes (any y, z): every populated bin below
     n2 = 49^2 (mixing all three axes) against direct

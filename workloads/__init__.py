@@ -310,6 +310,15 @@ def c5(n: int = 4096) -> Workload:
                     default_log_edges(n, 1.0, 2048 if n >= 2048 else 512))
 
 
+def uniform_cube(n: int, half_width: int, nbins: int, prec: int = PREC_F32, value: float = 1.0) -> Workload:
+    """A cube of uniform density `value` (a cell without atoms, background
+    `value`) on max_i |x_i - n/2| <= half_width; log bins over the box."""
+    empty = np.zeros((0, 3))
+    cell = Cell(16, empty, np.zeros(0), np.zeros(0), float(value))
+    return Workload(f"cube{n}_{half_width}", n, 1.0, prec, "r2c", cell, cube(half_width), Zoom(n, 1),
+                    default_log_edges(n, 1.0, nbins))
+
+
 def small(n: int, c: int = 8, n_atoms: int = 10, seed: int = 7, radius: Optional[float] = None,
           nbins: int = 64, prec: int = PREC_F32, mask: Optional[Mask] = None,
           voxel: float = 1.0, transform: str = "r2c") -> Workload:
