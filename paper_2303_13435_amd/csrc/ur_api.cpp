@@ -103,7 +103,7 @@ struct ur_plan {
   std::vector<hipEvent_t> ev_pool;
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_open;
   double pass_bytes[5] = {0, 0, 0, 0, 0};
-  int xres[3][2] = {{0, 0}, {0, 0}, {0, 0}};   // resident x-pass blocks per CU, by mode and direction
+  int xres[4][2] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};   // resident x-pass blocks per CU, by mode and direction
   int xres_nbins = -1;
 };
 
@@ -991,10 +991,13 @@ static ur_status adjoint_run(ur_plan* p, const void* rho, const ur_cell* cell, c
   xj.ob = amp_only ? (int)(bx0 + bs - 1) : n - 1;
   xj.nbins = p->nbins; xj.U = p->dU; xj.lut = p->dLut; xj.nlut = p->nlut; xj.g_bin = g_bin; xj.count = fwd->count;
   xj.gscale = 2.0 / ((double)n * n * n) / ((double)n * n * n); xj.ncols = p->nkz * n;
-  UR_HIP(launch_pass_x_adj(p->prec, n, xj, x_blocks(p), s));
+  UR_HIP(launch_pass_x_adj(p->prec, n, xj, x_blocks(p, X_ADJ), s));
   YInvArgs yi{};
   yi.B = B; yi.bx0 = bx0; yi.bs = bs; yi.A = A; yi.tw = p->tw; yi.nkz = p->nkz;
   yi.xt0 = (int)xt0; yi.nxt = (int)(xt1 - xt0 + 1);
+  if (amp_only) {          // the fold reads only the particle's row tiles
+    yi.rows = 1; yi.ty = zinv_tile(p->prec, n, 0); yi.L = g.L; yi.m = g.m;
+  }
   if (!amp_only || g.xlo <= g.xhi) UR_HIP(launch_pass_y_inv(p->prec, n, yi, s));
   const int c = cell ? cell->c : 1, c3 = c * c * c;
   if (amp_only) {

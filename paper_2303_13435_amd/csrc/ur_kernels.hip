@@ -1127,10 +1127,11 @@ k_pass_x_adj(XAdjArgs a) {
   cx<T>* s = sm + q * PS;
   const cx<T>* tw = (const cx<T>*)a.tw;
 
-  for (long long col = (long long)blockIdx.x * NG + q; col < a.ncols; col += (long long)gridDim.x * NG) {
-    const int kz = (int)(col / N), ky = (int)(col % N);
-    cx<T>* src = (cx<T>*)a.B + (size_t)col * a.bs - a.bx0;
-    cx<T> v[E];
+  // After its forward transform a group issues the loads of its next column,
+  // which stay in flight during the weighting, the inverse transform and
+  // the write-back of the current one.
+  auto load = [&](long long c, cx<T>* v) {
+    const cx<T>* src = (const cx<T>*)a.B + (size_t)c * a.bs - a.bx0;
     if constexpr (G >= 64) {
       load_column_u<T, N>(src, a.xa, a.xb, g, v);
     } else {
@@ -1142,7 +1143,16 @@ k_pass_x_adj(XAdjArgs a) {
           v[i * R0 + r] = (x >= a.xa && x <= a.xb) ? src[x] : mk((T)0, (T)0);
         }
     }
+  };
+  const long long stride = (long long)gridDim.x * NG;
+  long long col = (long long)blockIdx.x * NG + q;
+  cx<T> v[E];
+  if (col < a.ncols) load(col, v);
+  for (; col < a.ncols; col += stride) {
+    const int kz = (int)(col / N), ky = (int)(col % N);
+    cx<T>* src = (cx<T>*)a.B + (size_t)col * a.bs - a.bx0;
     fft_column<T, N, -1>(s, g, tw, v);
+    if (col + stride < a.ncols) load(col + stride, v);
     const int k = sidx(ky, N);
     const int l = a.r2c ? kz : sidx(kz, N);
     const int base = k * k + l * l;
@@ -1157,26 +1167,27 @@ k_pass_x_adj(XAdjArgs a) {
     int b = Ls[sq];
     int nextU = U[b + 1];
     while (n20 >= nextU) { ++b; nextU = U[b + 1]; }
-    double gv = Gb[b];
+    // the weight is rounded to the working precision once per bin
+    T gv = (T)Gb[b];
     cx<T>* sp = s + pad(hlo);
 #pragma unroll
     for (int t = 0; t < NH; ++t) {
       const int ha = hlo + t;
       const int n2 = ha * ha + base;
-      while (n2 >= nextU) { ++b; nextU = U[b + 1]; gv = Gb[b]; }
+      while (n2 >= nextU) { ++b; nextU = U[b + 1]; gv = (T)Gb[b]; }
       cx<T>* p1 = (NH <= 16 || G == 1) ? sp + t + (G == 1 ? (t >> 4) : 0) : s + pad(ha);
       const cx<T> f = *p1;
-      *p1 = mk((T)(f.x * gv), (T)(f.y * gv));
+      *p1 = mk(f.x * gv, f.y * gv);
       if (ha != 0) {
         const cx<T> f2 = s[pad(N - ha)];
-        s[pad(N - ha)] = mk((T)(f2.x * gv), (T)(f2.y * gv));
+        s[pad(N - ha)] = mk(f2.x * gv, f2.y * gv);
       }
     }
     if (g == G - 1) {                                      // |h| = N/2 (kx = N/2 only)
       const int n2 = (N / 2) * (N / 2) + base;
-      while (n2 >= nextU) { ++b; nextU = U[b + 1]; gv = Gb[b]; }
+      while (n2 >= nextU) { ++b; nextU = U[b + 1]; gv = (T)Gb[b]; }
       const cx<T> f = s[pad(N / 2)];
-      s[pad(N / 2)] = mk((T)(f.x * gv), (T)(f.y * gv));
+      s[pad(N / 2)] = mk(f.x * gv, f.y * gv);
     }
     col_sync<G>();
     stages_from<T, N, 1, +1>(s, g, tw);
@@ -1224,7 +1235,14 @@ k_pass_y_inv(YInvArgs a) {
   cx<T>* s = sm + q * PS;
   stages_from<T, N, 1, +1>(s, g, (const cx<T>*)a.tw);
   cx<T>* col = (cx<T>*)a.A + ((size_t)(xbase + q) * a.nkz + kz) * N;
-  for (int i = g; i < N; i += G) col[i] = s[pad(i)];
+  int ylo = 0, yhi = N - 1;
+  if (a.rows) {
+    long long lo, hi;
+    row_range(a.L, a.m, xbase + q, lo, hi);
+    ylo = lo <= hi ? (int)(lo & ~(long long)(a.ty - 1)) : 1;
+    yhi = lo <= hi ? (int)(hi | (long long)(a.ty - 1)) : 0;
+  }
+  for (int i = ylo + g; i <= yhi; i += G) col[i] = s[pad(i)];
 }
 
 // ---------------------------------------------------------------------------
@@ -1313,7 +1331,7 @@ k_pass_z_inv(ZInvArgs a) {
 // staged, then the same LDS holds the transform columns.
 // ---------------------------------------------------------------------------
 template <typename T, int N>
-__global__ void __launch_bounds__((ZICfg<T, N, false>::threads))
+__global__ void __launch_bounds__((ZICfg<T, N, false>::threads), MinW<T>::v)
 k_pass_z_fold(ZFoldArgs a) {
   using C = ZICfg<T, N, false>;
   constexpr int G = C::G, NG = C::NG, TY = C::TY, HS = C::HS, E = Geo<N>::E;
@@ -1605,6 +1623,8 @@ hipError_t launch_pass_y(int prec, int n, const YArgs& a, hipStream_t s) {
 }
 
 static size_t x_shm(int mode, int nbins, int n) {
+  if (mode == X_ADJ)
+    return ((size_t)nbins + 2) * sizeof(double) + ((size_t)nbins + 2) * sizeof(int) + (size_t)lut_len(n) * sizeof(short);
   return mode == X_FFT_STORE ? 0 : (2 * (size_t)nbins + 5) * sizeof(double) + ((size_t)nbins + 3) * sizeof(int)
                                     + (size_t)lut_len(n) * sizeof(short);
 }
@@ -1616,6 +1636,10 @@ static int x_resident_t(int mode, int dir, int nbins) {
   size_t shm = x_shm(mode, nbins, N);
   if (mode == X_FFT_BIN) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pass_x<T, N, X_FFT_BIN, -1>, XCfg<N>::threads, shm);
   else if constexpr (N == kBig) return 1;
+  else if (mode == X_ADJ) {
+    if constexpr (inv_fits<T, N>()) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pass_x_adj<T, N>, XCfg<N>::threads, shm);
+    else return 1;
+  }
   else if (mode == X_BIN_ONLY) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pass_x<T, N, X_BIN_ONLY, -1>, XCfg<N>::threads, shm);
   else if (dir < 0) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pass_x<T, N, X_FFT_STORE, -1>, XCfg<N>::threads, shm);
   else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pass_x<T, N, X_FFT_STORE, +1>, XCfg<N>::threads, shm);

@@ -17,7 +17,7 @@ constexpr int kMaxOutOfCore = 4096;
 // GEN: ED-1 voxels (block factor 1); ZOOM: block-summed zoom levels.
 enum ZMode { Z_GEN_R2C = 0, Z_LOAD_R2C = 1, Z_GEN_C2C = 2, Z_LOAD_C2C = 3, Z_ZOOM_R2C = 4, Z_ZOOM_C2C = 5 };
 // What the last (x) pass does with each transformed column.
-enum XMode { X_FFT_BIN = 0, X_BIN_ONLY = 1, X_FFT_STORE = 2 };
+enum XMode { X_FFT_BIN = 0, X_BIN_ONLY = 1, X_FFT_STORE = 2, X_ADJ = 3 };   // X_ADJ: the adjoint column pass
 
 struct ZArgs {
   void* A;                  // out: [x - ax0][kz][y] complex
@@ -143,6 +143,11 @@ struct YInvArgs {
   const void* tw;
   int nkz;
   int xt0, nxt;
+  // rows != 0: write only the rows of plane x inside the particle's row
+  // range, widened to whole tiles of ty rows (all a fold onto the cell reads)
+  int rows, ty;
+  Level L;
+  MaskP m;
 };
 
 // inverse z pass fused with the fold onto the unit cell (amplitude gradients)
