@@ -130,7 +130,12 @@ struct PassTimer {
   ~PassTimer() {
     if (!p->timing || !a || !b) return;
     (void)hipEventRecord(b, s);
-    p->ev_open.push_back({pass, {a, b}});
+    try {
+      p->ev_open.push_back({pass, {a, b}});
+    } catch (...) {                      // no room to keep the pair: drop this sample
+      (void)hipEventDestroy(a);
+      (void)hipEventDestroy(b);
+    }
   }
 };
 
@@ -281,19 +286,23 @@ static bool host_pinned(const void* ptr) {
 }
 
 // Host copy of `bytes` split over up to 16 threads (memory bandwidth, not
-// one core, then bounds the pageable-to-pinned step).
+// one core, then bounds the pageable-to-pinned step).  Parts whose thread
+// cannot be started are copied by the calling thread (no exception leaves).
 static void parallel_copy(char* dst, const char* src, size_t bytes) {
   const unsigned hc = std::thread::hardware_concurrency();
   const size_t nt = std::max<size_t>(1, std::min<size_t>({16, hc ? hc : 1, bytes >> 22}));
   if (nt == 1) { memcpy(dst, src, bytes); return; }
   std::vector<std::thread> th;
-  th.reserve(nt);
   const size_t part = (bytes / nt + 4095) & ~(size_t)4095;
   for (size_t t = 0; t < nt; ++t) {
     const size_t a = t * part;
     if (a >= bytes) break;
     const size_t len = std::min(part, bytes - a);
-    th.emplace_back([=] { memcpy(dst + a, src + a, len); });
+    try {
+      th.emplace_back([=] { memcpy(dst + a, src + a, len); });
+    } catch (...) {
+      memcpy(dst + a, src + a, len);
+    }
   }
   for (auto& t : th) t.join();
 }
@@ -335,7 +344,12 @@ ur_status ur_plan_create(int32_t n, double voxel, int32_t prec, uint32_t flags, 
   p->cs = 2 * p->rs;
   if (hipGetDevice(&p->device) != hipSuccess) { delete p; return fail(UR_ERR_HIP, "hipGetDevice failed"); }
   if (hipDeviceGetAttribute(&p->ncu, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess || p->ncu < 1) p->ncu = 256;
-  ur_status st = make_twiddles(p);
+  ur_status st;
+  try {
+    st = make_twiddles(p);
+  } catch (...) {
+    st = fail(UR_ERR_OOM, "host allocation failed while building the twiddle tables");
+  }
   if (st != UR_OK) { ur_plan_destroy(p); return st; }
   *out = p;
   return UR_OK;
@@ -403,14 +417,31 @@ ur_status ur_plan_read_timing(ur_plan* p, int32_t npass, double* ms, double* byt
     float t = 0.f;
     UR_HIP(hipEventElapsedTime(&t, e.second.first, e.second.second));
     if (e.first < npass) { ms[e.first] += t; launches[e.first] += 1; }
-    p->ev_pool.push_back(e.second.first);
-    p->ev_pool.push_back(e.second.second);
+  }
+  for (auto& e : p->ev_open) {                 // back to the pool, or destroyed when it cannot grow
+    for (hipEvent_t ev : {e.second.first, e.second.second}) {
+      try {
+        p->ev_pool.push_back(ev);
+      } catch (...) {
+        (void)hipEventDestroy(ev);
+      }
+    }
   }
   p->ev_open.clear();
   return UR_OK;
 }
 
+static ur_status set_bins_impl(ur_plan* p, int32_t nbins, const double* edges);
+
 ur_status ur_plan_set_bins(ur_plan* p, int32_t nbins, const double* edges) {
+  try {
+    return set_bins_impl(p, nbins, edges);
+  } catch (...) {
+    return fail(UR_ERR_OOM, "host allocation failed while setting the bins");
+  }
+}
+
+static ur_status set_bins_impl(ur_plan* p, int32_t nbins, const double* edges) {
   if (p) p->keep_valid = false;
   if (!p || !edges) return fail(UR_ERR_INVALID, "null argument");
   if (nbins < 1 || nbins > 4096) return fail(UR_ERR_INVALID, "nbins = %d outside [1, 4096]", nbins);
@@ -1044,7 +1075,7 @@ ur_status ur_merge_zooms(int32_t nlevels, const ur_hist* levels, const int32_t* 
   if (mode < 0 || mode > 2) return fail(UR_ERR_INVALID, "unknown merge mode %d", mode);
   MergeArgs a{};
   a.nlevels = nlevels;
-  std::vector<int> ord(nlevels);
+  int ord[8];                                          // nlevels <= 8 (checked above)
   for (int k = 0; k < nlevels; ++k) {
     if (!levels[k].sum || !levels[k].sumsq || !levels[k].count) return fail(UR_ERR_INVALID, "level %d histogram is null", k);
     if (n[k] < 1 || !(voxel[k] > 0.0)) return fail(UR_ERR_INVALID, "level %d geometry invalid", k);
@@ -1057,7 +1088,7 @@ ur_status ur_merge_zooms(int32_t nlevels, const ur_hist* levels, const int32_t* 
     a.qcut[k] = sqrt(3.0) * M_PI / (2.0 * voxel[k]);
     ord[k] = k;
   }
-  std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return voxel[x] < voxel[y]; });
+  std::stable_sort(ord, ord + nlevels, [&](int x, int y) { return voxel[x] < voxel[y]; });
   for (int k = 0; k < nlevels; ++k) a.order[k] = ord[k];
   a.mode = mode; a.n_min = n_min; a.nbins = nbins; a.edges = edges; a.mean = mean; a.sem = sem; a.owner = owner;
   UR_HIP(launch_merge(a, (hipStream_t)stream));
