@@ -189,9 +189,21 @@ ur_status ur_simulate_rho(ur_plan* plan, const void* rho, const ur_hist* hist, v
  * non-null) receives the bytes copied host to device. */
 ur_status ur_simulate_host(ur_plan* plan, const void* rho_host, int32_t x_lo, int32_t x_hi,
                            const ur_hist* hist, void* stream, size_t* h2d_bytes);
-/* Device workspace of the out-of-core path for planes [x_lo, x_hi]. */
+/* Device workspace of the out-of-core path for planes [x_lo, x_hi] under
+ * the plan's HBM budget (the four staging slabs are extra: 4 y-tiles of
+ * planes).  UR_ERR_OOM when the budget cannot hold one kz row. */
 ur_status ur_plan_workspace_size_host(const ur_plan* plan, int32_t nbins, int32_t x_lo, int32_t x_hi,
                                       size_t* bytes);
+
+/* Limit the out-of-core workspace to `bytes` (0: no limit).  When the x
+ * range of the spectrum does not fit, ur_simulate_host runs the second stage
+ * of eq. 2 kz chunk by kz chunk: every pass streams the host planes again
+ * (the z pass is repeated, the y pass keeps that pass's kz rows, the x pass
+ * adds their bins to the block partials of the earlier passes), so
+ * host-to-device traffic grows with the number of passes while the results
+ * stay those of one pass up to the order of the FP64 sums.  Sizes below one
+ * kz row make ur_simulate_host fail with UR_ERR_OOM. */
+ur_status ur_plan_set_hbm_budget(ur_plan* plan, size_t bytes);
 
 /* Page-locked HOST memory for the out-of-core input, allocated with
  * hipHostMalloc at exactly `bytes` (no rounding up, so a box that takes most

@@ -53,6 +53,7 @@ _SIGS = {
     "ur_plan_workspace_size": [_vp, _c.c_int32, _c.POINTER(_c.c_size_t)],
     "ur_plan_workspace_size_host": [_vp, _c.c_int32, _c.c_int32, _c.c_int32, _c.POINTER(_c.c_size_t)],
     "ur_plan_set_workspace": [_vp, _vp, _c.c_size_t],
+    "ur_plan_set_hbm_budget": [_vp, _c.c_size_t],
     "ur_plan_set_bins": [_vp, _c.c_int32, _c.POINTER(_c.c_double)],
     "ur_cell_synth": [_vp, _c.POINTER(UrCell), _vp, _vp],
     "ur_rho_generate": [_vp, _c.POINTER(UrCell), _c.POINTER(UrMask), _c.POINTER(UrZoom), _c.c_int32, _c.c_int32,
@@ -212,6 +213,7 @@ class Plan:
         self.nbins = 0
         self._ws = None
         self._use_torch_ws = workspace
+        self._budget = 0
 
     def __del__(self):
         try:
@@ -237,7 +239,9 @@ class Plan:
         _check(lib().ur_plan_set_bins(self.h, int(e.size - 1), e.ctypes.data_as(_c.POINTER(_c.c_double))),
                "ur_plan_set_bins")
         self.nbins = int(e.size - 1)
-        if self.n <= MAX_IN_CORE:                # larger boxes run only out of core (own workspace size)
+        # larger boxes, and plans given an HBM budget, size their (out-of-core)
+        # workspace at the streaming call instead
+        if self.n <= MAX_IN_CORE and not self._budget:
             self._attach(self.workspace_size())
 
     def workspace_size(self, nbins: Optional[int] = None) -> int:
@@ -245,6 +249,12 @@ class Plan:
         _check(lib().ur_plan_workspace_size(self.h, int(nbins or max(self.nbins, 1)), _c.byref(v)),
                "ur_plan_workspace_size")
         return int(v.value)
+
+    def set_hbm_budget(self, nbytes: int) -> None:
+        """Out-of-core workspace limit in bytes (0: none); above it the path
+        runs in kz chunks, streaming the host planes once per chunk."""
+        _check(lib().ur_plan_set_hbm_budget(self.h, int(nbytes)), "ur_plan_set_hbm_budget")
+        self._budget = int(nbytes)
 
     def workspace_size_host(self, x_lo: int, x_hi: int) -> int:
         v = _c.c_size_t()

@@ -97,6 +97,7 @@ struct ur_plan {
   size_t stage_bytes = 0;
   void* bounce = nullptr;    // pinned host memory
   size_t bounce_bytes = 0;
+  size_t hbm_budget = 0;     // out-of-core workspace bytes allowed (0: no limit)
 
   // per-pass timing
   bool timing = false;
@@ -173,8 +174,10 @@ static Layout layout_incore(const ur_plan* p, int nbins) {
   return L;
 }
 
-// out-of-core layout: one slab of the first intermediate, B over [xlo, xhi]
-static Layout layout_host(const ur_plan* p, int nbins, int xlo, int xhi) {
+// out-of-core layout: one slab of the first intermediate, rows kz of B over
+// [xlo, xhi] for kzc values of kz at a time (the x passes of all kz chunks
+// add into one set of block partials)
+static Layout layout_host(const ur_plan* p, int nbins, int xlo, int xhi, int kzc) {
   Layout L;
   size_t n = p->n;
   int tx = y_tile(p->prec, p->n);
@@ -183,11 +186,34 @@ static Layout layout_host(const ur_plan* p, int nbins, int xlo, int xhi) {
   size_t bs = (size_t)(xt1 - xt0 + 1) * tx;
   L.A = 0;
   L.B = align256(L.A + (size_t)tx * plane);
-  L.part = align256(L.B + (size_t)p->nkz * n * bs * p->cs);
+  L.part = align256(L.B + (size_t)kzc * n * bs * p->cs);
   L.mom = align256(L.part + (size_t)x_blocks_for(nbins) * (2 * (size_t)std::max(nbins, 1) + 1) * 8);
   L.f0 = align256(L.mom + n * (size_t)ntiles(p) * 16);
   L.total = align256(L.f0 + 64 + 256 * 8);
   return L;
+}
+
+// Split of the kz rows of the out-of-core spectrum into passes whose
+// workspace fits the plan's HBM budget; every pass streams the host planes
+// again (eq. 2's second stage then runs kz chunk by kz chunk).
+struct OocSplit {
+  int kzc = 0, nchunks = 0;
+  Layout lay{};
+};
+static ur_status ooc_split(const ur_plan* p, int nbins, int xlo, int xhi, OocSplit& o) {
+  for (int nc = 1; nc <= p->nkz; ++nc) {
+    const int kzc = (p->nkz + nc - 1) / nc;
+    if (nc > 1 && (p->nkz + kzc - 1) / kzc != nc) continue;       // same split as a smaller count
+    Layout L = layout_host(p, nbins, xlo, xhi, kzc);
+    if (p->hbm_budget == 0 || L.total <= p->hbm_budget) {
+      o.kzc = kzc;
+      o.nchunks = nc;
+      o.lay = L;
+      return UR_OK;
+    }
+    if (p->hbm_budget == 0) break;
+  }
+  return fail(UR_ERR_OOM, "HBM budget of %zu bytes is below the out-of-core workspace of one kz row", p->hbm_budget);
 }
 
 static ur_status ensure_ws(ur_plan* p, size_t need, hipStream_t s) {
@@ -387,7 +413,15 @@ ur_status ur_plan_workspace_size_host(const ur_plan* p, int32_t nbins, int32_t x
   if (!p || !bytes) return fail(UR_ERR_INVALID, "null argument");
   if (nbins < 1) return fail(UR_ERR_INVALID, "nbins must be >= 1");
   if (x_lo < 0 || x_hi >= p->n || x_lo > x_hi) return fail(UR_ERR_INVALID, "plane range [%d, %d] outside the box", x_lo, x_hi);
-  *bytes = layout_host(p, nbins, x_lo, x_hi).total;
+  OocSplit o;
+  UR_TRY(ooc_split(p, nbins, x_lo, x_hi, o));
+  *bytes = o.lay.total;
+  return UR_OK;
+}
+
+ur_status ur_plan_set_hbm_budget(ur_plan* p, size_t bytes) {
+  if (!p) return fail(UR_ERR_INVALID, "plan is null");
+  p->hbm_budget = bytes;
   return UR_OK;
 }
 
@@ -818,7 +852,9 @@ ur_status ur_simulate_host(ur_plan* p, const void* rho_host, int32_t x_lo, int32
   if (s) (void)hipStreamIsCapturing(s, &cst);
   if (cst != hipStreamCaptureStatusNone) return fail(UR_ERR_STATE, "the out-of-core path is a host-driven pipeline and cannot be captured");
   const int n = p->n, tx = y_tile(p->prec, n);
-  Layout lay = layout_host(p, p->nbins, x_lo, x_hi);
+  OocSplit split;
+  UR_TRY(ooc_split(p, p->nbins, x_lo, x_hi, split));
+  const Layout lay = split.lay;
   UR_TRY(ensure_ws(p, lay.total, s));
   const size_t plane_bytes = (size_t)n * n * p->rs;
   const size_t slab_bytes = (size_t)tx * plane_bytes;
@@ -860,55 +896,69 @@ ur_status ur_simulate_host(ur_plan* p, const void* rho_host, int32_t x_lo, int32
     UR_HIP(hipEventRecord(p->ev_copied[b], p->copy_stream[b]));   // after any earlier copy on that stream
   }
   const int ntl = ntiles(p);
+  const int nxb = x_blocks(p);
   int zb = 0;
-  for (long long xt = xt0; xt <= xt1; ++xt) {
-    const int buf = (int)((xt - xt0) % K);
-    hipStream_t cs = p->copy_stream[buf];
-    char* st = (char*)p->stage + buf * slab_bytes;
-    const long long sx0 = xt * tx;
-    const long long lo = std::max<long long>(sx0, x_lo), hi = std::min<long long>(sx0 + tx - 1, x_hi);
-    const char* src = (const char*)rho_host + (size_t)(lo - x_lo) * plane_bytes;
-    const size_t len = (size_t)(hi - lo + 1) * plane_bytes;
-    if (!pinned) {
-      // pageable input: once the previous copy out of this bounce slab has
-      // finished, the host copies the planes into it (the copies of the
-      // slabs before it and the z / y passes keep running meanwhile)
-      char* bb = (char*)p->bounce + buf * slab_bytes;
-      UR_HIP(hipEventSynchronize(p->ev_copied[buf]));
-      parallel_copy(bb, src, len);
-      src = bb;
+  long long slab = 0;                                     // slabs streamed so far (staging buffer = slab mod K)
+  // each pass streams every slab and keeps rows kz0 .. kz0 + nk - 1 of the
+  // spectrum; a single pass when the whole x range fits the budget
+  for (int chunk = 0; chunk < split.nchunks; ++chunk) {
+    const int kz0 = chunk * split.kzc, nk = std::min(split.kzc, p->nkz - kz0);
+    for (long long xt = xt0; xt <= xt1; ++xt, ++slab) {
+      const int buf = (int)(slab % K);
+      hipStream_t cs = p->copy_stream[buf];
+      char* st = (char*)p->stage + buf * slab_bytes;
+      const long long sx0 = xt * tx;
+      const long long lo = std::max<long long>(sx0, x_lo), hi = std::min<long long>(sx0 + tx - 1, x_hi);
+      const char* src = (const char*)rho_host + (size_t)(lo - x_lo) * plane_bytes;
+      const size_t len = (size_t)(hi - lo + 1) * plane_bytes;
+      if (!pinned) {
+        // pageable input: once the previous copy out of this bounce slab has
+        // finished, the host copies the planes into it (the copies of the
+        // slabs before it and the z / y passes keep running meanwhile)
+        char* bb = (char*)p->bounce + buf * slab_bytes;
+        UR_HIP(hipEventSynchronize(p->ev_copied[buf]));
+        parallel_copy(bb, src, len);
+        src = bb;
+      }
+      // wait until the previous user of this staging buffer is done, then copy
+      UR_HIP(hipStreamWaitEvent(cs, p->ev_free[buf], 0));
+      UR_HIP(hipMemcpyAsync(st + (lo - sx0) * plane_bytes, src, len, hipMemcpyHostToDevice, cs));
+      copied += len;
+      UR_HIP(hipEventRecord(p->ev_copied[buf], cs));
+      UR_HIP(hipStreamWaitEvent(s, p->ev_copied[buf], 0));
+      // z pass over the planes of this slab (its rho^2 sums taken in the
+      // first pass only), then y pass of this x tile for the pass's kz rows
+      ZArgs za{};
+      za.A = A; za.ax0 = sx0; za.rho = st; za.rho_x0 = sx0; za.tw = p->tw;
+      za.mom = chunk == 0 ? (double*)(p->ws + lay.mom) + 2 * (size_t)zb : nullptr;
+      za.L = g.L; za.nkz = p->nkz; za.x0 = (int)lo; za.ntiles = ntl;
+      const int nb = (int)((hi - lo + 1) * ntl);
+      UR_HIP(launch_pass_z(p->prec, n, Z_LOAD_R2C, za, nb, s));
+      if (chunk == 0) zb += nb;
+      UR_HIP(hipEventRecord(p->ev_free[buf], s));
+      YArgs ya{};
+      ya.A = A; ya.ax0 = sx0; ya.B = B; ya.bx0 = bx0; ya.bs = bs; ya.tw = p->tw; ya.L = g.L; ya.gen = 0;
+      ya.nkz = p->nkz; ya.xlo = (int)lo; ya.xhi = (int)hi; ya.xt0 = (int)xt; ya.nxt = 1; ya.ty = zt(p);
+      ya.kz0 = kz0; ya.nkzc = nk;
+      UR_HIP(launch_pass_y(p->prec, n, ya, s));
     }
-    // wait until the previous user of this staging buffer is done, then copy
-    UR_HIP(hipStreamWaitEvent(cs, p->ev_free[buf], 0));
-    UR_HIP(hipMemcpyAsync(st + (lo - sx0) * plane_bytes, src, len, hipMemcpyHostToDevice, cs));
-    copied += (size_t)(hi - lo + 1) * plane_bytes;
-    UR_HIP(hipEventRecord(p->ev_copied[buf], cs));
-    UR_HIP(hipStreamWaitEvent(s, p->ev_copied[buf], 0));
-    // z pass over the planes of this slab, then y pass of this x tile
-    ZArgs za{};
-    za.A = A; za.ax0 = sx0; za.rho = st; za.rho_x0 = sx0; za.tw = p->tw;
-    za.mom = (double*)(p->ws + lay.mom) + 2 * (size_t)zb; za.L = g.L; za.nkz = p->nkz; za.x0 = (int)lo; za.ntiles = ntl;
-    const int nb = (int)((hi - lo + 1) * ntl);
-    UR_HIP(launch_pass_z(p->prec, n, Z_LOAD_R2C, za, nb, s));
-    zb += nb;
-    UR_HIP(hipEventRecord(p->ev_free[buf], s));
-    YArgs ya{};
-    ya.A = A; ya.ax0 = sx0; ya.B = B; ya.bx0 = bx0; ya.bs = bs; ya.tw = p->tw; ya.L = g.L; ya.gen = 0;
-    ya.nkz = p->nkz; ya.xlo = (int)lo; ya.xhi = (int)hi; ya.xt0 = (int)xt; ya.nxt = 1; ya.ty = zt(p);
-    UR_HIP(launch_pass_y(p->prec, n, ya, s));
+    // x pass over this pass's rows of the spectrum, added to the block partials
+    // of the earlier passes (a fixed order: chunk after chunk)
+    XArgs xa{};
+    xa.B = B; xa.bx0 = bx0; xa.bs = bs; xa.tw = p->tw; xa.nkz = p->nkz; xa.r2c = 1;
+    xa.xa = (int)bx0; xa.xb = (int)(bx0 + bs - 1);
+    xa.iscale = 1.0 / ((double)n * n * n) / ((double)n * n * n);
+    xa.nbins = p->nbins; xa.U = p->dU; xa.lut = p->dLut; xa.nlut = p->nlut;
+    xa.part = (double*)(p->ws + lay.part); xa.f0 = (double*)(p->ws + lay.f0);
+    xa.ncols = nk * n; xa.kz0 = kz0; xa.accum = chunk > 0;
+    UR_HIP(launch_pass_x(p->prec, n, X_FFT_BIN, -1, xa, nxb, s));
   }
   if (h2d_bytes) *h2d_bytes = copied;
-  // x pass over the whole spectrum + finalize
-  XArgs xa{};
-  xa.B = B; xa.bx0 = bx0; xa.bs = bs; xa.tw = p->tw; xa.nkz = p->nkz; xa.r2c = 1;
-  xa.xa = (int)bx0; xa.xb = (int)(bx0 + bs - 1);
-  xa.iscale = 1.0 / ((double)n * n * n) / ((double)n * n * n);
-  xa.nbins = p->nbins; xa.U = p->dU; xa.lut = p->dLut; xa.nlut = p->nlut; xa.part = (double*)(p->ws + lay.part); xa.f0 = (double*)(p->ws + lay.f0);
-  xa.ncols = p->nkz * n;
-  UR_HIP(launch_pass_x(p->prec, n, X_FFT_BIN, -1, xa, x_blocks(p), s));
   FinArgs fa{};
-  fa.part = xa.part; fa.nblk = x_blocks(p); fa.nbins = p->nbins; fa.mom = (const double*)(p->ws + lay.mom); fa.nzb = zb;
-  fa.mpart = (double*)(p->ws + lay.f0 + 64); fa.f0 = xa.f0; fa.cnt = p->dCount; fa.sum = h->sum; fa.sumsq = h->sumsq; fa.count = h->count; fa.totals = h->totals; fa.mean = h->mean; fa.sem = h->sem;
+  fa.part = (const double*)(p->ws + lay.part); fa.nblk = nxb; fa.nbins = p->nbins;
+  fa.mom = (const double*)(p->ws + lay.mom); fa.nzb = zb;
+  fa.mpart = (double*)(p->ws + lay.f0 + 64); fa.f0 = (const double*)(p->ws + lay.f0); fa.cnt = p->dCount;
+  fa.sum = h->sum; fa.sumsq = h->sumsq; fa.count = h->count; fa.totals = h->totals; fa.mean = h->mean; fa.sem = h->sem;
   UR_HIP(launch_finalize(fa, s));
   return UR_OK;
 }

@@ -653,7 +653,7 @@ k_pass_y(YArgs a) {
   // x tile fastest: the blocks resident at one time cover whole B rows
   // (one kz, all x tiles), so their 128-byte row segments are contiguous
   const int xt = a.xt0 + blockIdx.x % a.nxt;
-  const int kz = blockIdx.x / a.nxt;
+  const int kz = a.kz0 + blockIdx.x / a.nxt;
   const int xbase = xt * TX;
   // G >= 64: every wavefront lies in one group, the plane index is
   // wave-uniform and the row range of the plane is computed on the scalar unit
@@ -681,7 +681,7 @@ k_pass_y(YArgs a) {
     fft_column<T, N, -1>(s, g, tw, v);
   }
   __syncthreads();
-  cx<T>* Bp = (cx<T>*)a.B + ((size_t)kz * N) * a.bs + (xbase - a.bx0);
+  cx<T>* Bp = (cx<T>*)a.B + ((size_t)(kz - a.kz0) * N) * a.bs + (xbase - a.bx0);
   constexpr int RS = C::threads / TX;                      // rows per pass of the block
   if constexpr (G % 16 == 0 && RS % 16 == 0 && (G * TX) % C::threads == 0) {
     // thread = (plane j, row r0 + k RS of the chunk): one LDS base and one
@@ -803,7 +803,7 @@ k_pass_x(XArgs a) {
   cx<T> v[E];
   if (MODE != X_BIN_ONLY && col < a.ncols) x_load_column<T, N>(a, col, g, v);
   for (; col < a.ncols; col += stride) {
-    const int kz = (int)(col / N), ky = (int)(col % N);
+    const int kz = a.kz0 + (int)(col / N), ky = (int)(col % N);
     if (MODE == X_BIN_ONLY) {
       const cx<T>* src = (const cx<T>*)a.B + (size_t)col * a.bs - a.bx0;
       for (int i = g; i < N; i += G) s[pad(i)] = (i >= a.xa && i <= a.xb) ? src[i] : mk((T)0, (T)0);
@@ -883,7 +883,7 @@ k_pass_x(XArgs a) {
     atomicAdd(&hist[2 * cb + 0], (double)cs * ws);
     atomicAdd(&hist[2 * cb + 1], cs2 * ws2);
     tot += (double)(ct + cs) * ws;
-    if (col == 0 && g == 0 && a.f0) {
+    if (kz == 0 && ky == 0 && g == 0 && a.f0) {
       const cx<T> f = s[pad(0)];
       a.f0[0] = (double)f.x * sqrt(a.iscale);
       a.f0[1] = (double)f.y * sqrt(a.iscale);
@@ -895,7 +895,10 @@ k_pass_x(XArgs a) {
   if ((threadIdx.x & 63) == 0) atomicAdd(tot_s, tot);
   __syncthreads();
   double* out = a.part + (size_t)blockIdx.x * (2 * (size_t)a.nbins + 1);
-  for (int i = threadIdx.x; i < 2 * a.nbins + 1; i += C::threads) out[i] = i < 2 * a.nbins ? hist[i] : *tot_s;
+  for (int i = threadIdx.x; i < 2 * a.nbins + 1; i += C::threads) {
+    const double v = i < 2 * a.nbins ? hist[i] : *tot_s;
+    out[i] = a.accum ? out[i] + v : v;
+  }
 }
 
 // voxel count per bin (geometry only): one thread per (ky, kz) column walks
@@ -1609,7 +1612,7 @@ hipError_t launch_pass_z(int prec, int n, int mode, const ZArgs& a, int nblocks,
 
 template <typename T, int N>
 static hipError_t pass_y_t(const YArgs& a, hipStream_t s) {
-  long long nb = (long long)a.nkz * a.nxt;
+  long long nb = (long long)(a.nkzc > 0 ? a.nkzc : a.nkz) * a.nxt;
   if (nb <= 0) return hipSuccess;
   hipLaunchKernelGGL((k_pass_y<T, N>), dim3((unsigned)nb), dim3(YCfg<T, N>::threads), 0, s, a);
   return hipGetLastError();

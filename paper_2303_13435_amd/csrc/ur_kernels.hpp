@@ -52,6 +52,7 @@ struct YArgs {
   int xt0;                  // first x tile of the launch
   int nxt;                  // number of x tiles
   int ty;                   // y tile height of the z pass
+  int kz0, nkzc;            // rows kz0 .. kz0 + nkzc - 1 of A go to B rows 0 .. nkzc - 1 (nkzc 0: all)
 };
 
 // entries of the start-of-walk bin table of an n^3 box: s = 0 .. isqrt(3 (n/2)^2) + 1
@@ -80,6 +81,8 @@ struct XArgs {
   double* part;             // per block: 2*nbins (sum, sumsq) + 1 total
   double* f0;               // F(0) (2 doubles), written by the block holding it
   int ncols;
+  int kz0;                  // kz of column 0 (B holds rows kz0 .. kz0 + ncols / n - 1)
+  int accum;                // add to the block partials instead of writing them (later kz chunks)
 };
 
 struct FinArgs {

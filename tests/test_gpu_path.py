@@ -208,6 +208,70 @@ def test_out_of_core_matches_oracle(ur, orc, n, prec, pinned):
     assert abs(got["totals"][3] - ref["rho_sumsq"]) <= 1e-6 * ref["rho_sumsq"]
 
 
+@pytest.mark.parametrize("n,prec,pinned", [(64, 1, True), (128, 0, False)])
+def test_out_of_core_hbm_budget(ur, orc, n, prec, pinned):
+    """HBM budgets below the out-of-core workspace: the second stage of eq. 2
+    runs in kz chunks, each streaming the planes again.  At the smallest
+    budget that holds a kz row (one row per pass) and at one between it and
+    the full size: against the whole oracle and against the single pass
+    (counts equal, sums 1e-12), host-to-device bytes a whole multiple of
+    one pass; a budget below one kz row is refused."""
+    import torch
+    wl = W.small(n, c=8, n_atoms=7, seed=83, mask=W.trunc_oct(0.4 * n), nbins=60, prec=prec)
+    ref = orc.simulate(wl, return_fields=True)
+    rho = ref["rho"]
+    nz = np.flatnonzero(np.any(rho != 0.0, axis=(1, 2)))
+    x_lo, x_hi = int(nz.min()), int(nz.max())
+    dt = torch.float32 if prec == 0 else torch.float64
+    host = torch.empty((x_hi - x_lo + 1, n, n), dtype=dt, pin_memory=pinned)
+    host.copy_(torch.as_tensor(rho[x_lo:x_hi + 1]))
+    one = ur.Plan(n, 1.0, prec)
+    one.set_bins(wl.edges)
+    full = one.workspace_size_host(x_lo, x_hi)
+    h1 = ur.Hist(wl.nbins)
+    b1 = one.simulate_host(host, x_lo, x_hi, h1)
+    torch.cuda.synchronize()
+    b = h1.numpy()
+    plan = ur.Plan(n, 1.0, prec)
+    plan.set_bins(wl.edges)
+
+    def fits(budget):
+        plan.set_hbm_budget(budget)
+        try:
+            plan.workspace_size_host(x_lo, x_hi)
+            return True
+        except ur.UltimaError:
+            return False
+
+    lo_b, hi_b = 1, full                               # smallest budget that holds a kz row
+    while lo_b < hi_b:
+        mid = (lo_b + hi_b) // 2
+        lo_b, hi_b = (lo_b, mid) if fits(mid) else (mid + 1, hi_b)
+    for budget in (lo_b, (lo_b + full) // 2):
+        plan.set_hbm_budget(budget)
+        assert plan.workspace_size_host(x_lo, x_hi) <= budget
+        h2 = ur.Hist(wl.nbins)
+        b2 = plan.simulate_host(host, x_lo, x_hi, h2)
+        torch.cuda.synchronize()
+        passes = b2 // b1
+        _say(f"  budget {budget} of {full} bytes: {passes} passes")
+        assert b2 == passes * b1 and passes >= 2
+        a = h2.numpy()
+        assert np.array_equal(a["count"], ref["count"]) and np.array_equal(a["count"], b["count"])
+        pop = ref["count"] > 0
+        assert np.allclose(a["sum"][pop], b["sum"][pop], rtol=1e-12, atol=0.0)
+        assert np.allclose(a["totals"], b["totals"], rtol=1e-12, atol=0.0)
+        ibar = ref["totals"][0] / n ** 3
+        floor = (8 * (6e-8 if prec == 0 else 1.2e-16)) ** 2 * ibar
+        rel = np.abs(a["mean"][pop] - ref["mean"][pop]) / np.maximum(np.abs(ref["mean"][pop]), floor)
+        assert rel.max() <= (1e-5 if prec == 0 else 1e-12)
+    assert passes < n // 2 + 1                          # the second budget needs fewer passes
+    plan.set_hbm_budget(lo_b - 1)
+    with pytest.raises(ur.UltimaError, match="status 3"):
+        plan.simulate_host(host, x_lo, x_hi, ur.Hist(wl.nbins))
+    torch.cuda.synchronize()
+
+
 def test_out_of_core_2048_c5_recipe(ur, orc):
     """The out-of-core recipe at 2048^3 (truncated octahedron R = 950, a
     128-voxel cell of 200 atoms, 2048 log bins) with the density in pinned
