@@ -170,23 +170,27 @@ ur_status ur_simulate(ur_plan* plan, const ur_cell* cell, const ur_mask* mask,
  * precision, [x][y][z]). */
 ur_status ur_simulate_rho(ur_plan* plan, const void* rho, const ur_hist* hist, void* stream);
 
-/* Out-of-core forward path (the 2D + 1D separation of eq. 2): `rho_host` is
- * HOST memory holding planes x_lo..x_hi of the density, [x - x_lo][y][z],
- * (x_hi - x_lo + 1) n^2 reals.  Page-locked memory (ur_host_alloc, or any
- * hipHostMalloc buffer) is copied to the device directly; ordinary pageable
- * memory goes through four pinned bounce slabs of the plan, filled by up to
- * 16 host threads while earlier slabs are in flight (the call then returns
- * once the last slab has been handed to the copy engine).  Planes outside
- * [x_lo, x_hi] are taken as zero and never copied (the slices without
- * density need no 2D transform); slabs of planes
- * are copied to the device into four staging buffers, each on its own copy
- * stream (several copies in flight), while earlier slabs go through the z
- * and y passes on `stream`; the x pass with binning runs once every slab is
- * in.  Only the staging slabs, one slab of the first intermediate and the
- * x-range of the final spectrum live in HBM (the staging buffers are
- * allocated by the plan on first use).  The host
- * buffer must stay valid until the stream is synchronised.  *h2d_bytes (when
- * non-null) receives the bytes copied host to device. */
+/* Out-of-core forward path (the 2D + 1D separation of eq. 2).
+ *
+ * rho_host: HOST memory holding planes x_lo..x_hi of the density,
+ * [x - x_lo][y][z], (x_hi - x_lo + 1) n^2 reals of the plan precision.
+ * Planes outside [x_lo, x_hi] are taken as zero and never copied (the
+ * slices without density need no 2D transform).
+ *   - Page-locked memory (ur_host_alloc, or any hipHostMalloc buffer) is
+ *     copied to the device directly.
+ *   - Ordinary pageable memory goes through four pinned bounce slabs of the
+ *     plan, refilled by up to 16 host threads while the slabs ahead are in
+ *     flight; the call then returns once the last slab has been handed to
+ *     the copy engine.
+ *   - Device memory is refused with UR_ERR_INVALID (use ur_simulate_rho).
+ * Slabs of planes go to four device staging buffers, each filled on its own
+ * copy stream, while earlier slabs run through the z and y passes on
+ * `stream`; the x pass with binning follows.  HBM holds the staging slabs,
+ * one slab of the first intermediate and the x range of the spectrum (or,
+ * under an HBM budget, a kz chunk of it per pass: ur_plan_set_hbm_budget).
+ * The staging and bounce buffers are allocated by the plan on first use.
+ * The host buffer must stay valid until the stream is synchronised.
+ * *h2d_bytes (when non-null) receives the bytes copied host to device. */
 ur_status ur_simulate_host(ur_plan* plan, const void* rho_host, int32_t x_lo, int32_t x_hi,
                            const ur_hist* hist, void* stream, size_t* h2d_bytes);
 /* Device workspace of the out-of-core path for planes [x_lo, x_hi] under

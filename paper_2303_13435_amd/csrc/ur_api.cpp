@@ -300,15 +300,19 @@ static void thresholds(int n, double voxel, int nbins, const double* edges, std:
 }
 #pragma clang fp contract(on)
 
-// True when `ptr` is page-locked host memory known to HIP (the device can
-// read it directly); false for ordinary pageable memory.
-static bool host_pinned(const void* ptr) {
+// Kind of a host-side input pointer: page-locked host memory known to HIP
+// (the device reads it directly), ordinary pageable (or managed) memory, or
+// device memory, which the host cannot read.
+enum HostKind { HOST_PAGEABLE, HOST_PINNED, HOST_DEVICE };
+static HostKind host_kind(const void* ptr) {
   hipPointerAttribute_t a;
   if (hipPointerGetAttributes(&a, ptr) != hipSuccess) {
     (void)hipGetLastError();
-    return false;
+    return HOST_PAGEABLE;
   }
-  return a.type == hipMemoryTypeHost;
+  if (a.type == hipMemoryTypeHost) return HOST_PINNED;
+  if (a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeArray) return HOST_DEVICE;
+  return HOST_PAGEABLE;
 }
 
 // Host copy of `bytes` split over up to 16 threads (memory bandwidth, not
@@ -851,6 +855,8 @@ ur_status ur_simulate_host(ur_plan* p, const void* rho_host, int32_t x_lo, int32
   hipStreamCaptureStatus cst = hipStreamCaptureStatusNone;
   if (s) (void)hipStreamIsCapturing(s, &cst);
   if (cst != hipStreamCaptureStatusNone) return fail(UR_ERR_STATE, "the out-of-core path is a host-driven pipeline and cannot be captured");
+  const HostKind hk = host_kind(rho_host);
+  if (hk == HOST_DEVICE) return fail(UR_ERR_INVALID, "rho_host is device memory (ur_simulate_rho takes device densities)");
   const int n = p->n, tx = y_tile(p->prec, n);
   OocSplit split;
   UR_TRY(ooc_split(p, p->nbins, x_lo, x_hi, split));
@@ -866,7 +872,7 @@ ur_status ur_simulate_host(ur_plan* p, const void* rho_host, int32_t x_lo, int32
     if (hipMalloc(&p->stage, K * slab_bytes) != hipSuccess) { (void)hipGetLastError(); return fail(UR_ERR_OOM, "staging allocation failed"); }
     p->stage_bytes = K * slab_bytes;
   }
-  const bool pinned = host_pinned(rho_host);
+  const bool pinned = hk == HOST_PINNED;
   if (!pinned && (!p->bounce || p->bounce_bytes < K * slab_bytes)) {
     UR_HIP(hipDeviceSynchronize());
     if (p->bounce) UR_HIP(hipHostFree(p->bounce));

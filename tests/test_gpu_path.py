@@ -206,6 +206,14 @@ def test_out_of_core_matches_oracle(ur, orc, n, prec, pinned):
     rel = np.abs(got["mean"][pop] - ref["mean"][pop]) / np.maximum(np.abs(ref["mean"][pop]), floor)
     assert rel.max() <= (1e-5 if prec == 0 else 1e-12)
     assert abs(got["totals"][3] - ref["rho_sumsq"]) <= 1e-6 * ref["rho_sumsq"]
+    # a device pointer is refused through the C ABI (the host cannot read it)
+    dev = host.cuda()
+    hs = h.struct()
+    nb = ur._c.c_size_t()
+    st = ur.lib().ur_simulate_host(plan.h, ur._c.c_void_p(dev.data_ptr()), x_lo, x_hi, ur._c.byref(hs), None,
+                                   ur._c.byref(nb))
+    assert st == 1 and b"device memory" in ur.lib().ur_last_error()
+    torch.cuda.synchronize()
 
 
 @pytest.mark.parametrize("n,prec,pinned", [(64, 1, True), (128, 0, False)])
