@@ -26,10 +26,12 @@
  *     the stream is synchronised.  A plan must not run on two streams at once.
  *   - Pointers documented as DEVICE point to memory of the current HIP
  *     device, owned by the caller; HOST pointers are read during the call
- *     only.  The library never frees caller memory.
+ *     only (the out-of-core density: until the stream is synchronised).
+ *     The library never frees caller memory.
  *   - Box layout: real densities are [x][y][z] row-major, z fastest, edge n
- *     (a power of two, 16 <= n <= 2048; complex transforms, inverse
- *     transforms and the adjoint: n <= 1024).  The particle and the lattice are
+ *     (a power of two, 16 <= n <= 2048; FP32 real boxes of n = 4096 through
+ *     the out-of-core path only; complex transforms, inverse transforms and
+ *     the adjoint: n <= 1024).  The particle and the lattice are
  *     centred on voxel (n1/2, n1/2, n1/2) of the ED-1 grid.
  *   - Spectra exchanged through ur_fft3d_exec / ur_intensity_bin use the
  *     transposed layout [kz][ky][kx] (kx fastest, complex interleaved), with
