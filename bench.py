@@ -211,6 +211,25 @@ def mask_planes(W, wl):
     return wl.n // 2 - r, wl.n // 2 + r
 
 
+def other_configs(ur, W, torch, steps):
+    """The forward path on the other single-box configurations: C1 (64^3
+    FP64, full complex transform), C2 (512^3 FP32), C4 (256^3, FP32 and
+    FP64); ms per box and voxels/s, inputs resident."""
+    from dataclasses import replace
+    out = {}
+    for wl in (W.c1(), W.c2(), W.c4(), replace(W.c4(), name="C4_f64", prec=ur.UR_F64)):
+        plan = ur.Plan(wl.n, wl.voxel, wl.prec, c2c=wl.transform == "c2c")
+        plan.set_bins(wl.edges)
+        cell = ur.DeviceCell.from_host(wl.cell)
+        h = ur.Hist(wl.nbins)
+        ms, _ = time_steps(lambda: plan.simulate(cell, wl.mask, wl.zoom, h), steps, 3, torch)
+        out[wl.name] = {"ms_per_box": round(ms, 4), "voxels_per_s": wl.n ** 3 / (ms * 1e-3),
+                        "prec": "f64" if wl.prec == ur.UR_F64 else "f32", "transform": wl.transform}
+        del plan
+    torch.cuda.empty_cache()
+    return out
+
+
 def note(msg):
     """Progress on stderr (stdout carries only the JSON line)."""
     print(f"# {msg}", file=sys.stderr, flush=True)
@@ -384,6 +403,9 @@ def main():
         note("c3_batch done")
         # many particle sizes: 32 radii of 256^3 boxes in one graph
         extras["radii_batch"] = radii_batch(ur, W, torch, max(2, args.steps // 4))
+        # the other single-box configurations
+        extras["configs"] = other_configs(ur, W, torch, args.steps)
+        note("configs done")
         note("radii_batch done")
         # out-of-core: the same box streamed from pinned host memory
         extras["out_of_core"] = out_of_core(ur, W, torch, wl, max(2, args.steps // 4))
