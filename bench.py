@@ -211,6 +211,25 @@ def mask_planes(W, wl):
     return wl.n // 2 - r, wl.n // 2 + r
 
 
+def pass_timing(plan, step, steps, torch):
+    """Per-pass average duration (HIP events on the launch stream) and
+    algorithmic bytes / GB/s of `steps` calls of `step` on `plan`."""
+    plan.set_timing(True)
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    passes = plan.read_timing()
+    plan.set_timing(False)
+    kernels = {}
+    for name, d in passes.items():
+        if d["launches"] == 0:
+            continue
+        avg = d["ms"] / d["launches"]
+        kernels[name] = {"avg_ms": round(avg, 5), "alg_bytes": d["bytes"],
+                         "alg_GBps": round(d["bytes"] / (avg * 1e-3) / 1e9, 1) if avg > 0 else None}
+    return kernels
+
+
 def other_configs(ur, W, torch, steps):
     """The forward path on the other single-box configurations: C1 (64^3
     FP64, full complex transform), C2 (512^3 FP32), C4 (256^3, FP32 and
@@ -341,19 +360,7 @@ def main():
     value = wl.n ** 3 / (ms * 1e-3)
 
     # per-pass timing (HIP events on the launch stream) and algorithmic bytes
-    plan.set_timing(True)
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    passes = plan.read_timing()
-    plan.set_timing(False)
-    kernels = {}
-    for name, d in passes.items():
-        if d["launches"] == 0:
-            continue
-        avg = d["ms"] / d["launches"]
-        kernels[name] = {"avg_ms": round(avg, 5), "alg_bytes": d["bytes"],
-                         "alg_GBps": round(d["bytes"] / (avg * 1e-3) / 1e9, 1) if avg > 0 else None}
+    kernels = pass_timing(plan, step, args.steps, torch)
     dom = max((k for k in kernels if k.startswith("pass_")), key=lambda k: kernels[k]["avg_ms"])
     dk = kernels[dom]
     achieved = dk["alg_GBps"]
@@ -368,12 +375,12 @@ def main():
               "sum_kernel_ms": round(path_ms, 4)}
     if not args.no_extras:
         # FP64 path on the same box
-        wl64 = W.m1024(ur.UR_F64) if n == 1024 else wl
         p64 = ur.Plan(wl.n, wl.voxel, ur.UR_F64)
         p64.set_bins(wl.edges)
         h64 = ur.Hist(wl.nbins)
         ms64, _ = time_steps(lambda: p64.simulate(cell, wl.mask, wl.zoom, h64), max(3, args.steps // 2), 2, torch)
-        extras["fp64"] = {"ms_per_step": round(ms64, 4), "voxels_per_s": wl.n ** 3 / (ms64 * 1e-3)}
+        extras["fp64"] = {"ms_per_step": round(ms64, 4), "voxels_per_s": wl.n ** 3 / (ms64 * 1e-3),
+                          "kernels": pass_timing(p64, lambda: p64.simulate(cell, wl.mask, wl.zoom, h64), args.steps, torch)}
         note("fp64 done")
         del p64
         # forward + adjoint (chi^2 gradient w.r.t. the atom amplitudes), FP32
