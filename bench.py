@@ -148,19 +148,31 @@ def c3_batch(ur, W, torch, reps):
     return out
 
 
-def radii_batch(ur, W, torch, reps):
-    """32 particle radii (256^3 FP32 boxes, spheres R = 20..100) through one
-    plan, recorded in one HIP graph and replayed."""
-    levels = W.b_radii()
+def radii_batch(ur, W, torch, reps, count=32, ensemble=False):
+    """`count` particle radii (256^3 FP32 boxes, spheres R = 20..100) through
+    one plan, recorded in one HIP graph and replayed; with `ensemble`, the
+    polydisperse curve of the boxes (log-normal volume fractions) is formed
+    in the same graph."""
+    import math
+    import numpy as np
+    levels = W.b_radii(count=count)
     s = torch.cuda.Stream()
     plan = ur.Plan(levels[0].n, 1.0, ur.UR_F32)
     plan.set_bins(levels[0].edges)
     cell = ur.DeviceCell.from_host(levels[0].cell)
-    hists = [ur.Hist(w.nbins) for w in levels]
+    batch = ur.HistBatch(len(levels), levels[0].nbins)
+    hists = batch.hists
+    radii = [math.sqrt(float(wl.mask.p0)) for wl in levels]
+    phi = W.volume_fractions(radii, float(np.median(radii)), 0.4)
+    wt = torch.as_tensor(phi / np.array([(4.0 / 3.0) * math.pi * r ** 3 for r in radii]), device="cuda")
+    out = (torch.empty(batch.nbins, dtype=torch.float64, device="cuda"),
+           torch.empty(batch.nbins, dtype=torch.float64, device="cuda"))
 
     def run():
         for wl, h in zip(levels, hists):
             plan.simulate(cell, wl.mask, wl.zoom, h, stream=s)
+        if ensemble:
+            ur.ensemble(batch, wt, out=out, stream=s)
 
     with torch.cuda.stream(s):
         run()
@@ -181,8 +193,9 @@ def radii_batch(ur, W, torch, reps):
     ms = e0.elapsed_time(e1) / reps
     out = {"ms_per_batch": round(ms, 3), "boxes": len(levels), "box": levels[0].n,
            "radii": [round(float(w.mask.p0) ** 0.5, 1) for w in (levels[0], levels[-1])],
-           "voxels_per_s": len(levels) * levels[0].n ** 3 / (ms * 1e-3), "graph_launches": reps}
-    del g, plan, hists
+           "voxels_per_s": len(levels) * levels[0].n ** 3 / (ms * 1e-3), "graph_launches": reps,
+           "ensemble": ensemble}
+    del g, plan, hists, batch
     torch.cuda.empty_cache()
     return out
 
@@ -410,6 +423,8 @@ def main():
         note("c3_batch done")
         # many particle sizes: 32 radii of 256^3 boxes in one graph
         extras["radii_batch"] = radii_batch(ur, W, torch, max(2, args.steps // 4))
+        # the paper's polydispersity estimate: 200 radii and their ensemble curve, one graph
+        extras["ensemble_200"] = radii_batch(ur, W, torch, max(2, args.steps // 4), count=200, ensemble=True)
         # the other single-box configurations
         extras["configs"] = other_configs(ur, W, torch, args.steps)
         note("configs done")

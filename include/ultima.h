@@ -266,6 +266,21 @@ ur_status ur_merge_zooms(int32_t nlevels, const ur_hist* levels, const int32_t* 
                          const double* voxel, int32_t nbins, const double* edges, int32_t mode,
                          double n_min, double* mean, double* sem, int32_t* owner, void* stream);
 
+/* Polydisperse ensemble (Results and Discussion: polydispersity described by
+ * some 200 volume-weighted contributions, one simulation each).  For nboxes
+ * boxes that share one bin set (one particle each, summed incoherently),
+ * per bin:
+ *     out_mean[b] = sum_k w[k] mean[k][b],
+ *     out_sem[b]  = sqrt( sum_k (w[k] sem[k][b])^2 )   (independent boxes).
+ * mean, sem: DEVICE [nboxes][nbins] (the per-box outputs of ur_simulate);
+ * weights: DEVICE nboxes number weights (a volume fraction phi_k gives
+ * w_k = phi_k / V_k with V_k the particle volume); outputs DEVICE nbins.
+ * Empty bins give NaN means, one-voxel bins NaN SEMs.  No allocation: the
+ * call can sit in a captured graph after the boxes.  UR_ERR_INVALID for
+ * nboxes < 1, nbins outside [1, 4096] or a null pointer. */
+ur_status ur_ensemble(int32_t nboxes, int32_t nbins, const double* mean, const double* sem,
+                      const double* weights, double* out_mean, double* out_sem, void* stream);
+
 /* Record the work enqueued on `stream` between begin and end into a HIP
  * graph, instantiate it, and return the executable graph (as void*); replay
  * it with ur_graph_launch and release it with ur_graph_destroy.  Every entry

@@ -14,6 +14,7 @@ correct statement of the computation, written from the paper:
 * O11 low-frequency Fourier coefficients by direct summation (eq. 1/eq. 2)
 * O12 per-bin counts and two-voxel intensities of boxes too large for O4-O8
 * O13 per-bin intensities of a uniform cube at any box size (eq. 1 factorised)
+* O14 polydisperse ensemble of boxes (Results and Discussion; reading in ``ensemble``)
 
 The heavy loops live in ``ur_oracle.c`` (plain C, FP64, OpenMP over
 independent lines); this module marshals numpy arrays and holds the small
@@ -457,6 +458,26 @@ def merge(levels: Sequence[dict], edges: np.ndarray, mode: int = MERGE_FINEST, n
 # ---------------------------------------------------------------------------
 # O10  chi^2 misfit and gradients (derived from eq. 1)
 # ---------------------------------------------------------------------------
+
+# ---------------------------------------------------------------------------
+# O14  polydisperse ensemble
+# ---------------------------------------------------------------------------
+
+def ensemble(means: Sequence[np.ndarray], sems: Sequence[np.ndarray], weights: Sequence[float]):
+    """Curve of a dilute polydisperse population (Results and Discussion:
+    polydispersity as some 200 volume-weighted contributions, one
+    simulation each).  Reading: particles scatter incoherently, so with
+    number weights w_k the ensemble intensity of a bin is sum_k w_k I_k(b);
+    the boxes are independent, so its SEM is sqrt(sum_k (w_k SEM_k(b))^2).
+    Every box must share one bin set (same geometry, same counts)."""
+    nb = len(means[0])
+    mean = np.zeros(nb)
+    var = np.zeros(nb)
+    for m, e, w in zip(means, sems, weights):
+        mean += w * np.asarray(m, dtype=np.float64)
+        var += (w * np.asarray(e, dtype=np.float64)) ** 2
+    return mean, np.sqrt(var)
+
 
 def chi2(mean: np.ndarray, count: np.ndarray, target: np.ndarray, rel_sigma: float = 0.01) -> float:
     """chi^2 = sum over populated bins of ((I_b - T_b) / (rel_sigma T_b))^2."""

@@ -67,6 +67,7 @@ _SIGS = {
     "ur_adjoint_reuse": [_vp, _c.POINTER(UrCell), _c.POINTER(UrMask), _c.POINTER(UrHist), _vp, _vp, _vp],
     "ur_merge_zooms": [_c.c_int32, _c.POINTER(UrHist), _c.POINTER(_c.c_int32), _c.POINTER(_c.c_double),
                        _c.c_int32, _vp, _c.c_int32, _c.c_double, _vp, _vp, _vp, _vp],
+    "ur_ensemble": [_c.c_int32, _c.c_int32, _vp, _vp, _vp, _vp, _vp, _vp],
     "ur_graph_begin": [_vp],
     "ur_graph_end": [_vp, _c.POINTER(_vp)],
     "ur_graph_launch": [_vp, _vp],
@@ -180,7 +181,9 @@ class Hist:
 
     FIELDS = ("sum", "sumsq", "count", "totals", "mean", "sem")
 
-    def __init__(self, nbins: int):
+    def __init__(self, nbins: int, mean=None, sem=None):
+        """mean, sem: optional device views to write those two outputs into
+        (rows of a HistBatch)."""
         torch = _torch()
         dev = torch.device("cuda")
         self.nbins = nbins
@@ -188,14 +191,40 @@ class Hist:
         self.sumsq = torch.zeros(nbins, dtype=torch.float64, device=dev)
         self.count = torch.zeros(nbins, dtype=torch.float64, device=dev)
         self.totals = torch.zeros(4, dtype=torch.float64, device=dev)
-        self.mean = torch.zeros(nbins, dtype=torch.float64, device=dev)
-        self.sem = torch.zeros(nbins, dtype=torch.float64, device=dev)
+        self.mean = torch.zeros(nbins, dtype=torch.float64, device=dev) if mean is None else mean
+        self.sem = torch.zeros(nbins, dtype=torch.float64, device=dev) if sem is None else sem
 
     def struct(self) -> UrHist:
         return UrHist(*[_ptr(getattr(self, k)) for k in self.FIELDS])
 
     def numpy(self) -> dict:
         return {k: getattr(self, k).cpu().numpy() for k in self.FIELDS}
+
+
+class HistBatch:
+    """Histograms of several boxes sharing one bin set, whose means and SEMs
+    are the rows of two [nboxes, nbins] device tensors (the layout
+    ur_ensemble reads)."""
+
+    def __init__(self, nboxes: int, nbins: int):
+        torch = _torch()
+        self.mean = torch.zeros((nboxes, nbins), dtype=torch.float64, device="cuda")
+        self.sem = torch.zeros((nboxes, nbins), dtype=torch.float64, device="cuda")
+        self.hists = [Hist(nbins, mean=self.mean[k], sem=self.sem[k]) for k in range(nboxes)]
+        self.nboxes, self.nbins = nboxes, nbins
+
+
+def ensemble(batch: HistBatch, weights, out=None, stream=None):
+    """Weighted ensemble of the batch's curves (ur_ensemble): returns the
+    (mean, sem) device tensors; pass `out` under graph capture."""
+    torch = _torch()
+    _require(weights, torch.float64, batch.nboxes, "weights")
+    if out is None:
+        out = (torch.empty(batch.nbins, dtype=torch.float64, device="cuda"),
+               torch.empty(batch.nbins, dtype=torch.float64, device="cuda"))
+    _check(lib().ur_ensemble(batch.nboxes, batch.nbins, _ptr(batch.mean), _ptr(batch.sem), _ptr(weights),
+                             _ptr(out[0]), _ptr(out[1]), _stream(stream)), "ur_ensemble")
+    return out
 
 
 class Plan:

@@ -1122,6 +1122,15 @@ static ur_status adjoint_run(ur_plan* p, const void* rho, const ur_cell* cell, c
   return UR_OK;
 }
 
+ur_status ur_ensemble(int32_t nboxes, int32_t nbins, const double* mean, const double* sem, const double* weights,
+                      double* out_mean, double* out_sem, void* stream) {
+  if (nboxes < 1) return fail(UR_ERR_INVALID, "nboxes = %d must be >= 1", nboxes);
+  if (nbins < 1 || nbins > 4096) return fail(UR_ERR_INVALID, "nbins = %d outside [1, 4096]", nbins);
+  if (!mean || !sem || !weights || !out_mean || !out_sem) return fail(UR_ERR_INVALID, "null argument");
+  UR_HIP(launch_ensemble(nboxes, nbins, mean, sem, weights, out_mean, out_sem, (hipStream_t)stream));
+  return UR_OK;
+}
+
 ur_status ur_merge_zooms(int32_t nlevels, const ur_hist* levels, const int32_t* n, const double* voxel, int32_t nbins,
                          const double* edges, int32_t mode, double n_min, double* mean, double* sem, int32_t* owner,
                          void* stream) {

@@ -1101,6 +1101,26 @@ __global__ void k_merge(MergeArgs a) {
   a.owner[b] = owner;
 }
 
+// Ensemble of boxes that share a bin set (one particle each, incoherent sum
+// with number weights w): per bin, mean = sum_k w_k mean_k and
+// sem = sqrt(sum_k (w_k sem_k)^2), compensated sums in box order.  One
+// thread per bin; mean and sem are [box][bin].
+__global__ void __launch_bounds__(256) k_ensemble(int nboxes, int nbins, const double* __restrict__ mean,
+                                                   const double* __restrict__ sem, const double* __restrict__ w,
+                                                   double* __restrict__ out_mean, double* __restrict__ out_sem) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nbins) return;
+  Kahan m, v;
+  for (int k = 0; k < nboxes; ++k) {
+    const double wk = w[k];
+    m.add(wk * mean[(size_t)k * nbins + b]);
+    const double e = wk * sem[(size_t)k * nbins + b];
+    v.add(e * e);
+  }
+  out_mean[b] = m.val();                   // NaN where the bin is empty (every box)
+  out_sem[b] = sqrt(v.val());              // NaN for one-voxel bins
+}
+
 // ---------------------------------------------------------------------------
 // adjoint column pass along x: FFT_x, multiply by G(|q|) * gscale, IFFT_x
 // ---------------------------------------------------------------------------
@@ -1707,6 +1727,12 @@ hipError_t launch_finalize(const FinArgs& a, hipStream_t s) {
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(k_finalize, dim3(nvb + 1), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_ensemble(int nboxes, int nbins, const double* mean, const double* sem, const double* w,
+                           double* out_mean, double* out_sem, hipStream_t s) {
+  hipLaunchKernelGGL(k_ensemble, dim3(nblk_of(nbins, 256)), dim3(256), 0, s, nboxes, nbins, mean, sem, w, out_mean, out_sem);
   return hipGetLastError();
 }
 

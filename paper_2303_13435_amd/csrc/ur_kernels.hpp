@@ -194,6 +194,8 @@ hipError_t launch_pass_y(int prec, int n, const YArgs& a, hipStream_t s);
 hipError_t launch_pass_x(int prec, int n, int mode, int dir, const XArgs& a, int nblocks, hipStream_t s);
 hipError_t launch_finalize(const FinArgs& a, hipStream_t s);
 hipError_t launch_merge(const MergeArgs& a, hipStream_t s);
+hipError_t launch_ensemble(int nboxes, int nbins, const double* mean, const double* sem, const double* w,
+                           double* out_mean, double* out_sem, hipStream_t s);
 hipError_t launch_pass_x_adj(int prec, int n, const XAdjArgs& a, int nblocks, hipStream_t s);
 hipError_t launch_pass_y_inv(int prec, int n, const YInvArgs& a, hipStream_t s);
 hipError_t launch_pass_z_inv(int prec, int n, int c2c, const ZInvArgs& a, hipStream_t s);

@@ -378,6 +378,82 @@ def test_radii_batch_in_one_graph(ur, orc, n, count, r_lo, r_hi, check):
         assert rel.max() <= 1e-5
 
 
+def _ensemble_weights(levels):
+    """Number weights of a log-normal volume-fraction distribution over the
+    radii: phi_k / V_k with V_k the sphere volume."""
+    radii = [math.sqrt(float(wl.mask.p0)) for wl in levels]
+    phi = W.volume_fractions(radii, float(np.median(radii)), 0.4)
+    return phi / np.array([(4.0 / 3.0) * math.pi * r ** 3 for r in radii])
+
+
+@pytest.mark.parametrize("n,count,r_lo,r_hi,check", [(64, 5, 6.0, 28.0, "oracle"), (256, 200, 20.0, 100.0, "sum")])
+def test_polydisperse_ensemble_in_one_graph(ur, orc, n, count, r_lo, r_hi, check):
+    """A polydisperse population (ur_ensemble over the boxes of many radii,
+    log-normal volume fractions), boxes and ensemble recorded in one HIP
+    graph: replays equal the eager calls.  5 radii at 64^3: against O14
+    over the oracle's per-box curves.  200 radii at 256^3 (the paper's
+    count of contributions): against the weighted sum of the per-box curves
+    the kernels wrote."""
+    import torch
+    levels = W.b_radii(n, count, r_lo, r_hi, nbins=64 if n <= 64 else 256)
+    nb = levels[0].nbins
+    _say(f"ensemble {count} x {n}^3")
+    w = _ensemble_weights(levels)
+    plan = ur.Plan(n, 1.0, 0)
+    plan.set_bins(levels[0].edges)
+    cell = ur.DeviceCell.from_host(levels[0].cell)
+    batch = ur.HistBatch(count, nb)
+    wt = torch.as_tensor(w, device="cuda")
+    out = (torch.empty(nb, dtype=torch.float64, device="cuda"), torch.empty(nb, dtype=torch.float64, device="cuda"))
+    s = torch.cuda.Stream()
+
+    def run():
+        for wl, h in zip(levels, batch.hists):
+            plan.simulate(cell, wl.mask, wl.zoom, h, stream=s)
+        ur.ensemble(batch, wt, out=out, stream=s)
+
+    with torch.cuda.stream(s):
+        run()
+    torch.cuda.synchronize()
+    m_e, s_e = out[0].cpu().numpy(), out[1].cpu().numpy()
+    count_b = batch.hists[0].count.cpu().numpy()
+    g = ur.Graph(s)
+    with torch.cuda.stream(s):
+        with g:
+            run()
+    for rep in range(2):
+        out[0].fill_(0.0)
+        batch.mean.fill_(0.0)
+        torch.cuda.synchronize()
+        g.launch()
+        torch.cuda.synchronize()
+        # pass X sums with LDS atomics, whose order may change between runs:
+        # replays agree to rounding (the SEM's sum-of-squares difference
+        # magnifies it where a bin's spread is small)
+        m_g, s_g = out[0].cpu().numpy(), out[1].cpu().numpy()
+        assert np.array_equal(np.isnan(m_g), np.isnan(m_e)) and np.array_equal(np.isnan(s_g), np.isnan(s_e))
+        ok_m, ok_s = ~np.isnan(m_e), ~np.isnan(s_e)
+        dm = np.max(np.abs(m_g[ok_m] - m_e[ok_m]) / np.abs(m_e[ok_m]))
+        ds = np.max(np.abs(s_g[ok_s] - s_e[ok_s]) / np.abs(s_e[ok_s]))
+        _say(f"  replay {rep}: mean rel diff {dm:.2e}, sem rel diff {ds:.2e}")
+        assert dm <= 1e-12 and ds <= 1e-10
+    pop = count_b > 0
+    assert np.all(np.isnan(m_e[~pop]))
+    if check == "oracle":
+        refs = [orc.simulate(wl) for wl in levels]
+        assert all(np.array_equal(r["count"], count_b) for r in refs)
+        m_r, s_r = orc.ensemble([r["mean"] for r in refs], [r["sem"] for r in refs], w)
+    else:
+        m_r, s_r = orc.ensemble(list(batch.mean.cpu().numpy()), list(batch.sem.cpu().numpy()), w)
+    rel = np.abs(m_e[pop] - m_r[pop]) / np.abs(m_r[pop])
+    _say(f"  ensemble mean: max rel err {rel.max():.3e}")
+    assert rel.max() <= (1e-5 if check == "oracle" else 1e-13)
+    multi = count_b > 1
+    bound = (1e-5 * s_r[multi] + 1e-5 * np.abs(m_r[multi]) / np.sqrt(count_b[multi])) if check == "oracle" \
+        else 1e-13 * s_r[multi]
+    assert np.all(np.abs(s_e[multi] - s_r[multi]) <= bound)
+
+
 @pytest.mark.parametrize("prec", [0, 1])
 def test_adjoint_reuse_matches_recompute(ur, orc, prec):
     """ur_adjoint_reuse (held forward output) gives the recomputing adjoint's

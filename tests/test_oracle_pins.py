@@ -573,3 +573,27 @@ def test_cube_bin_sums_per_bin_at_128(oracle_lib):
     mean = s[pop] / cnt[pop]
     bound = np.maximum(1e-13, 8 * 2.0 ** -53 * math.sqrt(21.0) * np.sqrt(ibar / mean))
     assert np.all(np.abs(mean - ref["mean"][pop]) / mean <= bound)
+
+
+def test_ensemble_is_the_binned_sum_of_intensities(oracle_lib):
+    """O14 against the binning of the summed intensity: for incoherent
+    particles the ensemble curve is the bin mean of sum_k w_k |F_k|^2, a
+    different route through the oracle (one binning of the summed field
+    instead of a weighted sum of per-box means)."""
+    import oracle
+    levels = W.b_radii(32, 4, 5.0, 13.0, nbins=30)
+    w = W.volume_fractions([math.isqrt(int(wl.mask.p0)) for wl in levels], 9.0, 0.4)
+    w = w / np.array([(4.0 / 3.0) * math.pi * float(wl.mask.p0) ** 1.5 for wl in levels])
+    outs = [oracle.simulate(wl, return_fields=True) for wl in levels]
+    mean, sem = oracle.ensemble([o["mean"] for o in outs], [o["sem"] for o in outs], w)
+    I = sum(wk * np.abs(o["F"]) ** 2 for wk, o in zip(w, outs))
+    ref = oracle_lib.bin_spectrum(np.sqrt(I), levels[0].voxel, levels[0].edges)
+    pop = ref["count"] > 0
+    assert np.array_equal(np.isnan(mean), ~pop)
+    assert np.allclose(mean[pop], ref["mean"][pop], rtol=1e-12, atol=0.0)
+    # one box with weight 1 is that box; the SEM of two equal boxes is sqrt(2) w SEM
+    m1, s1 = oracle.ensemble([outs[0]["mean"]], [outs[0]["sem"]], [1.0])
+    assert np.array_equal(m1[pop], outs[0]["mean"][pop])
+    m2, s2 = oracle.ensemble([outs[1]["mean"]] * 2, [outs[1]["sem"]] * 2, [0.5, 0.5])
+    multi = ref["count"] > 1
+    assert np.allclose(s2[multi], math.sqrt(0.5) * outs[1]["sem"][multi], rtol=1e-15)

@@ -20,7 +20,7 @@ from __future__ import annotations
 
 import math
 from dataclasses import dataclass, field, replace
-from typing import List, Optional
+from typing import List, Optional, Sequence
 
 import numpy as np
 
@@ -299,6 +299,15 @@ def b_radii(n: int = 256, count: int = 32, r_lo: float = 20.0, r_hi: float = 100
         r = r_lo * (r_hi / r_lo) ** (i / max(count - 1, 1))
         out.append(Workload(f"B{n}_R{r:.1f}", n, 1.0, prec, "r2c", cell, sphere(r), Zoom(n, 1), edges))
     return out
+
+
+def volume_fractions(radii: Sequence[float], r0: float, width: float) -> np.ndarray:
+    """A log-normal volume-fraction distribution over the given radii
+    (median r0, log-width `width`), normalised to sum 1: input data for a
+    polydisperse ensemble."""
+    r = np.asarray(radii, dtype=np.float64)
+    phi = np.exp(-0.5 * (np.log(r / r0) / width) ** 2)
+    return phi / phi.sum()
 
 
 def c5(n: int = 4096) -> Workload:
