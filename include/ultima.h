@@ -83,7 +83,15 @@ typedef struct { int32_t kind; int64_t p0; int64_t p1; } ur_mask;
  * dividing n1/2); n_atoms Gaussian atoms.  DEVICE arrays, FP64:
  * xyz[3*n_atoms] centres in cell-voxel units, amp[n_atoms] electrons per atom,
  * sigma[n_atoms] widths in voxels.  Each voxel holds the Gaussian integrated
- * over it, with periodic images, plus `background`. */
+ * over it, with periodic images, plus `background`.
+ * rot: NULL for the lattice aligned with the box, or HOST 9 doubles R
+ * (row-major, finite) orienting it ("Electron density generation": the
+ * cell interpolated over a rotated grid, repeated outside its bounds): the
+ * ED-1 voxel at offset d = (x, y, z) - n1/2 from the particle centre takes
+ * the cell's value at u = R d, trilinearly interpolated between the cell
+ * voxels with periodic wrap (R = identity gives the aligned lattice
+ * exactly).  Rotated lattices run the forward paths at zoom factor 1 on
+ * real (UR_R2C) plans; the adjoint refuses them (UR_ERR_UNSUPPORTED). */
 typedef struct {
   int32_t c;
   int32_t n_atoms;
@@ -91,6 +99,7 @@ typedef struct {
   const double* amp;
   const double* sigma;
   double background;
+  const double* rot;
 } ur_cell;
 
 /* Zoom level (workflow step 3): the ED-1 grid of edge n1 is block-summed by

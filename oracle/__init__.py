@@ -5,7 +5,7 @@ CPU-baseline leg may import this package.  It is the plain, slow, obviously
 correct statement of the computation, written from the paper:
 
 * O1  unit-cell density (workflow step 1; "Electron density generation")
-* O2  ED-1 = tiled cell x particle mask (workflow step 2)
+* O2  ED-1 = tiled cell x particle mask (workflow step 2); O2r with a rotated lattice
 * O3  zoomed-out ED-2/ED-3 by block integration and zero padding (step 3)
 * O4  3D transform, eq. 1 (axis by axis, as eq. 2 separates it)
 * O5-O8  |Q| map, integer-threshold bins, per-bin mean and SEM (step 5)
@@ -65,6 +65,8 @@ def lib():
         L.or_mask_inside.restype = ctypes.c_int
         L.or_ed1.argtypes = [ctypes.c_int, ctypes.c_int, _D, ctypes.c_int, ctypes.c_longlong,
                              ctypes.c_longlong, _D]
+        L.or_ed1_rot.argtypes = [ctypes.c_int, ctypes.c_int, _D, ctypes.c_int, ctypes.c_longlong,
+                                 ctypes.c_longlong, _D, _D]
         L.or_zoom.argtypes = [ctypes.c_int, ctypes.c_int, _D, ctypes.c_int, ctypes.c_longlong,
                               ctypes.c_longlong, ctypes.c_int, ctypes.c_int, _D]
         L.or_fft3d.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_int]
@@ -157,6 +159,17 @@ def ed1(n: int, cell_grid: np.ndarray, mask) -> np.ndarray:
     return out
 
 
+def ed1_rot(n: int, cell_grid: np.ndarray, mask, rot: np.ndarray) -> np.ndarray:
+    """O2r: ED-1 of a lattice oriented by the 3x3 matrix rot (cell sampled at
+    u = rot d, trilinear with periodic wrap)."""
+    c = cell_grid.shape[0]
+    cg = np.ascontiguousarray(cell_grid, dtype=np.float64)
+    R = np.ascontiguousarray(rot, dtype=np.float64).reshape(9)
+    out = np.empty((n, n, n))
+    lib().or_ed1_rot(int(n), int(c), _dp(cg), int(mask.kind), int(mask.p0), int(mask.p1), _dp(R), _dp(out))
+    return out
+
+
 def zoomed(n1: int, cell_grid: np.ndarray, mask, f: int, nk: int) -> np.ndarray:
     c = cell_grid.shape[0]
     cg = np.ascontiguousarray(cell_grid, dtype=np.float64)
@@ -170,6 +183,10 @@ def density(wl, cell_grid: Optional[np.ndarray] = None) -> np.ndarray:
     """Real-space box of a workload: ED-1 (factor 1) or a zoomed level."""
     if cell_grid is None:
         cell_grid = cell_synth(wl.cell)
+    rot = getattr(wl.cell, "rot", None)
+    if rot is not None:
+        assert wl.zoom.factor == 1 and wl.zoom.n1 == wl.n, "rotated lattices are defined for ED-1"
+        return ed1_rot(wl.n, cell_grid, wl.mask, rot)
     if wl.zoom.factor == 1 and wl.zoom.n1 == wl.n:
         return ed1(wl.n, cell_grid, wl.mask)
     return zoomed(wl.zoom.n1, cell_grid, wl.mask, wl.zoom.factor, wl.n)

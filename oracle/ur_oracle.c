@@ -147,6 +147,49 @@ void or_ed1(int n, int c, const double* cell, int kind, long long p0, long long 
 }
 
 /* ------------------------------------------------------------------------ */
+/* O2r ED-1 of a rotated lattice ("Electron density generation": the cell is
+ *     interpolated over a rotated grid and repeated beyond its bounds).  The
+ *     voxel at offset d = (x, y, z) - n/2 from the particle centre takes the
+ *     cell's value at u = R d, linearly interpolated between the cell voxels
+ *     along each axis with periodic wrap (cell voxel i at coordinate i), the
+ *     third axis first; zero outside the mask.  u_i = (R_i0 dx + R_i1 dy)
+ *     + R_i2 dz, each operation rounded on its own.                          */
+/* ------------------------------------------------------------------------ */
+static double lerp(double a, double b, double t) { return a + t * (b - a); }
+
+void or_ed1_rot(int n, int c, const double* cell, int kind, long long p0, long long p1, const double* R,
+                double* rho)
+{
+    const long long h = n / 2;
+#pragma omp parallel for schedule(static)
+    for (long long x = 0; x < n; ++x)
+        for (long long y = 0; y < n; ++y)
+            for (long long z = 0; z < n; ++z) {
+                double* out = &rho[((size_t)x * n + y) * n + z];
+                const long long dx = x - h, dy = y - h, dz = z - h;
+                if (!or_mask_inside(kind, p0, p1, dx, dy, dz)) { *out = 0.0; continue; }
+                double u[3];
+                for (int i = 0; i < 3; ++i)
+                    u[i] = (R[3 * i] * (double)dx + R[3 * i + 1] * (double)dy) + R[3 * i + 2] * (double)dz;
+                long long i0[3];
+                double t[3];
+                for (int i = 0; i < 3; ++i) {
+                    const double f = floor(u[i]);
+                    i0[i] = (long long)f;
+                    t[i] = u[i] - f;
+                }
+                double a[2][2];
+                for (int di = 0; di < 2; ++di)
+                    for (int dj = 0; dj < 2; ++dj) {
+                        const long long ci = pmod(i0[0] + di, c), cj = pmod(i0[1] + dj, c);
+                        const double* row = cell + ((size_t)ci * c + cj) * c;
+                        a[di][dj] = lerp(row[pmod(i0[2], c)], row[pmod(i0[2] + 1, c)], t[2]);
+                    }
+                *out = lerp(lerp(a[0][0], a[0][1], t[1]), lerp(a[1][0], a[1][1], t[1]), t[0]);
+            }
+}
+
+/* ------------------------------------------------------------------------ */
 /* O3  zoomed-out levels ED-2/ED-3 (Methodology, workflow step 3 and
  *     "Electron density generation": block integration of ED-1 by a linear
  *     factor, with the result zero-padded into a smaller box).  Block

@@ -33,7 +33,7 @@ class UrMask(_c.Structure):
 
 class UrCell(_c.Structure):
     _fields_ = [("c", _c.c_int32), ("n_atoms", _c.c_int32), ("xyz", _vp), ("amp", _vp),
-                ("sigma", _vp), ("background", _c.c_double)]
+                ("sigma", _vp), ("background", _c.c_double), ("rot", _c.POINTER(_c.c_double))]
 
 
 class UrZoom(_c.Structure):
@@ -144,12 +144,14 @@ def _require(t, dtype, numel: Optional[int] = None, what: str = "tensor"):
 
 @dataclass
 class DeviceCell:
-    """Unit cell with its atom arrays in device memory (FP64)."""
+    """Unit cell with its atom arrays in device memory (FP64); `rot` the
+    optional 3x3 lattice orientation (host, row-major)."""
     c: int
     xyz: "object"
     amp: "object"
     sigma: "object"
     background: float
+    rot: Optional[np.ndarray] = None
 
     @staticmethod
     def from_host(cell) -> "DeviceCell":
@@ -163,12 +165,15 @@ class DeviceCell:
             xyz = torch.zeros(3, dtype=torch.float64, device=dev)
             amp = torch.zeros(1, dtype=torch.float64, device=dev)
             sig = torch.ones(1, dtype=torch.float64, device=dev)
-        return DeviceCell(int(cell.c), xyz, amp, sig, float(cell.background))
+        rot = getattr(cell, "rot", None)
+        rot = None if rot is None else np.ascontiguousarray(rot, dtype=np.float64).reshape(9)
+        return DeviceCell(int(cell.c), xyz, amp, sig, float(cell.background), rot)
 
     def struct(self, amp=None) -> UrCell:
         a = self.amp if amp is None else amp
         n = int(a.numel()) if self.xyz.numel() == 3 * a.numel() else 0
-        return UrCell(self.c, n, _ptr(self.xyz), _ptr(a), _ptr(self.sigma), self.background)
+        rot = None if self.rot is None else self.rot.ctypes.data_as(_c.POINTER(_c.c_double))
+        return UrCell(self.c, n, _ptr(self.xyz), _ptr(a), _ptr(self.sigma), self.background, rot)
 
 
 def mask_struct(mask) -> UrMask:

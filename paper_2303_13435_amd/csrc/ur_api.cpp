@@ -542,6 +542,20 @@ static ur_status check_cell(const ur_cell* c) {
   if (c->n_atoms < 0 || c->n_atoms > (1 << 20)) return fail(UR_ERR_INVALID, "n_atoms = %d out of range", c->n_atoms);
   if (c->n_atoms > 0 && (!c->xyz || !c->amp || !c->sigma)) return fail(UR_ERR_INVALID, "atom arrays must be non-null");
   if (!isfinite(c->background)) return fail(UR_ERR_INVALID, "background must be finite");
+  if (c->rot)
+    for (int i = 0; i < 9; ++i)
+      if (!isfinite(c->rot[i])) return fail(UR_ERR_INVALID, "lattice rotation entry %d is not finite", i);
+  return UR_OK;
+}
+
+// A rotated lattice runs the ED-1 generator of real plans only; copies its
+// matrix into the z-pass arguments.
+static ur_status set_rotation(const ur_plan* p, const ur_cell* cell, const ur_zoom* zoom, ZArgs& za) {
+  if (!cell->rot) return UR_OK;
+  if (zoom->factor != 1) return fail(UR_ERR_UNSUPPORTED, "rotated lattices run at zoom factor 1");
+  if (p->flags & UR_C2C) return fail(UR_ERR_UNSUPPORTED, "rotated lattices run on real (UR_R2C) plans");
+  za.rotated = 1;
+  for (int i = 0; i < 9; ++i) za.rot[i] = cell->rot[i];
   return UR_OK;
 }
 
@@ -700,6 +714,7 @@ ur_status ur_rho_generate(ur_plan* p, const ur_cell* cell, const ur_mask* mask, 
   UR_TRY(prepare_cell(p, cell, zoom->factor, t, s));
   ZArgs za{};
   za.cellT = t.cellT; za.cb = t.cb; za.pre = t.pre; za.L = L; za.m = m; za.cbn = t.cbn;
+  UR_TRY(set_rotation(p, cell, zoom, za));
   UR_HIP(launch_rho_generate(p->prec, p->n, x_lo, x_hi, za, rho, s));
   return UR_OK;
 }
@@ -713,6 +728,8 @@ ur_status ur_simulate(ur_plan* p, const ur_cell* cell, const ur_mask* mask, cons
   UR_TRY(check_cell(cell));
   FwdGeom g;
   UR_TRY(check_level(p, cell, mask, zoom, g.L, g.m));
+  ZArgs rot_args{};
+  UR_TRY(set_rotation(p, cell, zoom, rot_args));
   hipStream_t s = (hipStream_t)stream;
   Layout lay = layout_incore(p, p->nbins);
   UR_TRY(ensure_ws(p, lay.total, s));
@@ -733,18 +750,19 @@ ur_status ur_simulate(ur_plan* p, const ur_cell* cell, const ur_mask* mask, cons
   g.xlo = (int)xlo; g.xhi = (int)xhi; g.ax0 = xlo; g.gen = 1;
   int nzb = 0;
   if (xlo <= xhi) {
-    ZArgs za{};
+    ZArgs za = rot_args;
     za.A = p->ws + lay.A; za.ax0 = xlo; za.cellT = t.cellT; za.cb = t.cb; za.pre = t.pre; za.tw = p->tw;
     za.mom = (double*)(p->ws + lay.mom); za.L = g.L; za.m = g.m; za.nkz = p->nkz; za.x0 = (int)xlo;
     za.ntiles = ntiles(p); za.cbn = t.cbn;
     nzb = (int)((xhi - xlo + 1) * za.ntiles);
     PassTimer tm(p, P_Z, s);
-    const int zm = zoom->factor > 1 ? ((p->flags & UR_C2C) ? Z_ZOOM_C2C : Z_ZOOM_R2C) : ((p->flags & UR_C2C) ? Z_GEN_C2C : Z_GEN_R2C);
+    const int zm = za.rotated ? Z_ROT_R2C
+                 : zoom->factor > 1 ? ((p->flags & UR_C2C) ? Z_ZOOM_C2C : Z_ZOOM_R2C) : ((p->flags & UR_C2C) ? Z_GEN_C2C : Z_GEN_R2C);
     UR_HIP(launch_pass_z(p->prec, p->n, zm, za, nzb, s));
   }
   p->pass_bytes[P_Z] = live_rows(p, g) * p->nkz * p->cs + 16.0 * nzb;
   const ur_status st = run_y_x(p, g, p->ws + lay.A, p->ws + lay.B, lay, h, nzb, s);
-  if (st == UR_OK && zoom->factor == 1 && zoom->n1 == p->n && !(p->flags & UR_C2C)) {
+  if (st == UR_OK && zoom->factor == 1 && zoom->n1 == p->n && !(p->flags & UR_C2C) && !cell->rot) {
     p->keep_valid = true;
     p->keep_m = g.m;
     p->keep_c = cell->c;
@@ -1018,6 +1036,7 @@ static ur_status adjoint_run(ur_plan* p, const void* rho, const ur_cell* cell, c
   if (p->nbins < 1) return fail(UR_ERR_STATE, "no bins set on the plan");
   if ((rho != nullptr) == (cell != nullptr)) return fail(UR_ERR_INVALID, "give exactly one of rho and cell");
   if (grad_amp && !cell) return fail(UR_ERR_INVALID, "grad_amp needs the cell description");
+  if (cell && cell->rot) return fail(UR_ERR_UNSUPPORTED, "the adjoint runs for lattices aligned with the box (rot = NULL)");
   if (!grad_rho && !grad_amp) return UR_OK;
   if (p->n > 1024) return fail(UR_ERR_UNSUPPORTED, "the adjoint runs up to 1024^3");
   hipStream_t s = (hipStream_t)stream;

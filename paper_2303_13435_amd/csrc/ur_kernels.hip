@@ -185,6 +185,8 @@ struct Pencil {
   int I, J;                 // block-table indices of this pencil
   long long fx0, fy0;       // first fine x, y of the pencil's block column
   int zin_lo, zin_hi;       // coarse z of the blocks wholly inside the mask
+  // rotated lattice (f == 1): u = rot (dx, dy, dz), dz = z + zoff; (ux, uy, uz) = rot (dx, dy, 0)
+  double ux, uy, uz;
 
   __device__ __forceinline__ void init(const ZArgs& a, long long X, long long Y) {
     const Level& L = a.L;
@@ -198,6 +200,14 @@ struct Pencil {
       const int i = (int)(X - L.o - L.h) & cmask, j = (int)(Y - L.o - L.h) & cmask;
       row = (const T*)a.cellT + ((size_t)i * L.c + j) * L.c;
       zoff = -(L.o + L.h);
+      if (a.rotated) {
+        // each product and sum rounded on its own (no contraction), in the
+        // order the reference evaluation uses
+        const double dx = (double)(X - L.o - L.h), dy = (double)(Y - L.o - L.h);
+        ux = __dadd_rn(__dmul_rn(a.rot[0], dx), __dmul_rn(a.rot[1], dy));
+        uy = __dadd_rn(__dmul_rn(a.rot[3], dx), __dmul_rn(a.rot[4], dy));
+        uz = __dadd_rn(__dmul_rn(a.rot[6], dx), __dmul_rn(a.rot[7], dy));
+      }
     } else {
       long long ax, bx, ay, by;
       block_dist(L, X, ax, bx);
@@ -238,6 +248,35 @@ struct Pencil {
     }
     bnd = true;
     return (T)0;
+  }
+
+  // ED-1 voxel of a rotated lattice: the cell at u = rot d, trilinear
+  // between its voxels with periodic wrap (interpolated along the cell's
+  // third index, then the second, then the first); zero outside the mask
+  __device__ __forceinline__ T value_rot(const ZArgs& a, int z) const {
+    if (z < zlo || z > zhi) return (T)0;
+    const double dz = (double)(z + zoff);
+    const double u = __dadd_rn(ux, __dmul_rn(a.rot[2], dz));
+    const double v = __dadd_rn(uy, __dmul_rn(a.rot[5], dz));
+    const double w = __dadd_rn(uz, __dmul_rn(a.rot[8], dz));
+    const double fu = floor(u), fv = floor(v), fw = floor(w);
+    const T tu = (T)(u - fu), tv = (T)(v - fv), tw = (T)(w - fw);
+    const int c = cmask + 1;
+    const int i0 = (int)(long long)fu & cmask, i1 = (i0 + 1) & cmask;
+    const int j0 = (int)(long long)fv & cmask, j1 = (j0 + 1) & cmask;
+    const int k0 = (int)(long long)fw & cmask, k1 = (k0 + 1) & cmask;
+    const T* C = (const T*)a.cellT;
+    const T* r00 = C + ((size_t)i0 * c + j0) * c;
+    const T* r01 = C + ((size_t)i0 * c + j1) * c;
+    const T* r10 = C + ((size_t)i1 * c + j0) * c;
+    const T* r11 = C + ((size_t)i1 * c + j1) * c;
+    const T a00 = r00[k0] + tw * (r00[k1] - r00[k0]);
+    const T a01 = r01[k0] + tw * (r01[k1] - r01[k0]);
+    const T a10 = r10[k0] + tw * (r10[k1] - r10[k0]);
+    const T a11 = r11[k0] + tw * (r11[k1] - r11[k0]);
+    const T b0 = a00 + tv * (a01 - a00);
+    const T b1 = a10 + tv * (a11 - a10);
+    return b0 + tu * (b1 - b0);
   }
 
   // ED-1 voxel (factor 1): tiled cell inside the mask, exact integer test
@@ -330,7 +369,8 @@ __global__ void __launch_bounds__((ZCfg<T, N, (MODE == Z_GEN_C2C || MODE == Z_LO
 k_pass_z(ZArgs a) {
   constexpr bool C2C = MODE == Z_GEN_C2C || MODE == Z_LOAD_C2C || MODE == Z_ZOOM_C2C;
   constexpr bool ZOOM = MODE == Z_ZOOM_R2C || MODE == Z_ZOOM_C2C;
-  constexpr bool GEN = MODE == Z_GEN_R2C || MODE == Z_GEN_C2C || ZOOM;
+  constexpr bool ROT = MODE == Z_ROT_R2C;
+  constexpr bool GEN = MODE == Z_GEN_R2C || MODE == Z_GEN_C2C || ZOOM || ROT;
   using C = ZCfg<T, N, C2C>;
   constexpr int G = C::G, NG = C::NG, TY = C::TY, E = Geo<N>::E;
   constexpr int R0 = Radix<N, 1>::r, NB0 = E / R0, PS = CS<N>::v;
@@ -365,7 +405,15 @@ k_pass_z(ZArgs a) {
       Pencil<T> pa, pb;
       pa.init(a, X, yA);
       pb.init(a, X, yB);
-      if (!ZOOM) {
+      if constexpr (ROT) {
+#pragma unroll
+        for (int i = 0; i < NB0; ++i)
+#pragma unroll
+          for (int r = 0; r < R0; ++r) {
+            const int z = first_index<N>(g, i, r);
+            v[i * R0 + r] = mk(pa.value_rot(a, z), pb.value_rot(a, z));
+          }
+      } else if (!ZOOM) {
         // the cell residue of z = b + r N/R0 does not depend on r when the
         // cell edge divides N/R0: one cell load per pencil and butterfly
         const bool one_load = ((N / R0) & pa.cmask) == 0;
@@ -564,7 +612,7 @@ __global__ void __launch_bounds__(256) k_rho_generate(ZArgs a, int n, int x0, T*
   Pencil<T> p;
   p.init(a, X, Y);
   T* row = rho + t * n;
-  for (int z = threadIdx.x; z < n; z += 256) row[z] = p.value(a, z);
+  for (int z = threadIdx.x; z < n; z += 256) row[z] = a.rotated ? p.value_rot(a, z) : p.value(a, z);
 }
 
 // ---------------------------------------------------------------------------
@@ -1595,6 +1643,7 @@ static hipError_t pass_z_t(int mode, const ZArgs& a, int nblocks, hipStream_t s)
     if (mode == Z_GEN_C2C || mode == Z_LOAD_C2C || mode == Z_ZOOM_C2C) return hipErrorNotSupported;
     switch (mode) {
       case Z_GEN_R2C: hipLaunchKernelGGL((k_pass_z<T, N, Z_GEN_R2C>), dim3(nblocks), dim3(ZCfg<T, N, false>::threads), 0, s, a); break;
+      case Z_ROT_R2C: hipLaunchKernelGGL((k_pass_z<T, N, Z_ROT_R2C>), dim3(nblocks), dim3(ZCfg<T, N, false>::threads), 0, s, a); break;
       case Z_LOAD_R2C: hipLaunchKernelGGL((k_pass_z<T, N, Z_LOAD_R2C>), dim3(nblocks), dim3(ZCfg<T, N, false>::threads), 0, s, a); break;
       case Z_ZOOM_R2C: hipLaunchKernelGGL((k_pass_z<T, N, Z_ZOOM_R2C>), dim3(nblocks), dim3(ZCfg<T, N, false>::threads), 0, s, a); break;
       default: return hipErrorInvalidValue;
@@ -1603,6 +1652,7 @@ static hipError_t pass_z_t(int mode, const ZArgs& a, int nblocks, hipStream_t s)
   } else
   switch (mode) {
     case Z_GEN_R2C: hipLaunchKernelGGL((k_pass_z<T, N, Z_GEN_R2C>), dim3(nblocks), dim3(ZCfg<T, N, false>::threads), 0, s, a); break;
+    case Z_ROT_R2C: hipLaunchKernelGGL((k_pass_z<T, N, Z_ROT_R2C>), dim3(nblocks), dim3(ZCfg<T, N, false>::threads), 0, s, a); break;
     case Z_LOAD_R2C: hipLaunchKernelGGL((k_pass_z<T, N, Z_LOAD_R2C>), dim3(nblocks), dim3(ZCfg<T, N, false>::threads), 0, s, a); break;
     case Z_GEN_C2C: hipLaunchKernelGGL((k_pass_z<T, N, Z_GEN_C2C>), dim3(nblocks), dim3(ZCfg<T, N, true>::threads), 0, s, a); break;
     case Z_LOAD_C2C: hipLaunchKernelGGL((k_pass_z<T, N, Z_LOAD_C2C>), dim3(nblocks), dim3(ZCfg<T, N, true>::threads), 0, s, a); break;

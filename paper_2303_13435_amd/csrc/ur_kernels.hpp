@@ -15,7 +15,9 @@ constexpr int kMaxOutOfCore = 4096;
 
 // Density source of the first (z) pass.
 // GEN: ED-1 voxels (block factor 1); ZOOM: block-summed zoom levels.
-enum ZMode { Z_GEN_R2C = 0, Z_LOAD_R2C = 1, Z_GEN_C2C = 2, Z_LOAD_C2C = 3, Z_ZOOM_R2C = 4, Z_ZOOM_C2C = 5 };
+// ROT: ED-1 of a rotated lattice (trilinear periodic interpolation of the cell).
+enum ZMode { Z_GEN_R2C = 0, Z_LOAD_R2C = 1, Z_GEN_C2C = 2, Z_LOAD_C2C = 3, Z_ZOOM_R2C = 4, Z_ZOOM_C2C = 5,
+             Z_ROT_R2C = 6 };
 // What the last (x) pass does with each transformed column.
 enum XMode { X_FFT_BIN = 0, X_BIN_ONLY = 1, X_FFT_STORE = 2, X_ADJ = 3 };   // X_ADJ: the adjoint column pass
 
@@ -35,6 +37,8 @@ struct ZArgs {
   int x0;                   // first plane of this launch
   int ntiles;               // y tiles per plane
   int cbn;                  // edge of the block table
+  int rotated;              // ROT generation: the cell is sampled at u = rot d
+  double rot[9];            // row-major
 };
 
 struct YArgs {

@@ -597,3 +597,53 @@ def test_ensemble_is_the_binned_sum_of_intensities(oracle_lib):
     m2, s2 = oracle.ensemble([outs[1]["mean"]] * 2, [outs[1]["sem"]] * 2, [0.5, 0.5])
     multi = ref["count"] > 1
     assert np.allclose(s2[multi], math.sqrt(0.5) * outs[1]["sem"][multi], rtol=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# O2r: ED-1 of a rotated lattice
+# ---------------------------------------------------------------------------
+
+def _rot_case():
+    cell = W.draw_atoms(17, 5, 8)
+    mask = W.sphere(11.0)
+    return cell, mask
+
+
+def test_rotated_lattice_identity_and_quarter_turn(oracle_lib):
+    """R = identity samples the cell at integer points: the aligned tiling
+    exactly.  A quarter turn about z, u = (-dy, dx, dz), is the tiling with
+    the cell's first two axes exchanged (modular indexing)."""
+    import oracle
+    n = 32
+    cell, mask = _rot_case()
+    cg = oracle.cell_synth(cell)
+    assert np.array_equal(oracle.ed1_rot(n, cg, mask, np.eye(3)), oracle.ed1(n, cg, mask))
+    R = np.array([[0.0, -1.0, 0.0], [1.0, 0.0, 0.0], [0.0, 0.0, 1.0]])
+    got = oracle.ed1_rot(n, cg, mask, R)
+    d = np.arange(n) - n // 2
+    dx, dy, dz = np.meshgrid(d, d, d, indexing="ij")
+    inside = dx * dx + dy * dy + dz * dz <= int(mask.p0)
+    c = cg.shape[0]
+    want = np.where(inside, cg[(-dy) % c, dx % c, dz % c], 0.0)
+    assert np.array_equal(got, want)
+
+
+def test_rotated_lattice_matches_scipy_map_coordinates(oracle_lib):
+    """A general orientation against scipy.ndimage.map_coordinates (order 1,
+    periodic 'grid-wrap'), a library routine for the same interpolation, at
+    every inside voxel of a 24^3 box."""
+    import oracle
+    from scipy.ndimage import map_coordinates
+    n = 24
+    cell, mask = _rot_case()
+    cg = oracle.cell_synth(cell)
+    R = W.rotation([1.0, 2.0, 3.0], 0.7)
+    got = oracle.ed1_rot(n, cg, mask, R)
+    d = np.arange(n) - n // 2
+    dx, dy, dz = np.meshgrid(d, d, d, indexing="ij")
+    inside = dx * dx + dy * dy + dz * dz <= int(mask.p0)
+    D = np.stack([dx[inside], dy[inside], dz[inside]]).astype(np.float64)
+    U = R @ D
+    ref = map_coordinates(cg, U, order=1, mode="grid-wrap")
+    assert np.max(np.abs(got[inside] - ref)) <= 1e-12 * np.max(np.abs(cg))
+    assert np.all(got[~inside] == 0.0)

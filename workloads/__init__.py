@@ -49,6 +49,7 @@ class Cell:
     amp: np.ndarray
     sigma: np.ndarray
     background: float = 0.0
+    rot: Optional[np.ndarray] = None   # 3x3 lattice orientation (None: aligned with the box)
 
     @property
     def n_atoms(self) -> int:
@@ -56,6 +57,9 @@ class Cell:
 
     def with_amp(self, amp: np.ndarray) -> "Cell":
         return replace(self, amp=np.ascontiguousarray(amp, dtype=np.float64))
+
+    def with_rot(self, rot: Optional[np.ndarray]) -> "Cell":
+        return replace(self, rot=None if rot is None else np.ascontiguousarray(rot, dtype=np.float64).reshape(3, 3))
 
 
 @dataclass(frozen=True)
@@ -299,6 +303,15 @@ def b_radii(n: int = 256, count: int = 32, r_lo: float = 20.0, r_hi: float = 100
         r = r_lo * (r_hi / r_lo) ** (i / max(count - 1, 1))
         out.append(Workload(f"B{n}_R{r:.1f}", n, 1.0, prec, "r2c", cell, sphere(r), Zoom(n, 1), edges))
     return out
+
+
+def rotation(axis: Sequence[float], angle: float) -> np.ndarray:
+    """3x3 rotation by `angle` (radians) about `axis` (Rodrigues' formula):
+    an orientation for a lattice, input data."""
+    k = np.asarray(axis, dtype=np.float64)
+    k = k / np.linalg.norm(k)
+    K = np.array([[0.0, -k[2], k[1]], [k[2], 0.0, -k[0]], [-k[1], k[0], 0.0]])
+    return np.eye(3) + math.sin(angle) * K + (1.0 - math.cos(angle)) * (K @ K)
 
 
 def volume_fractions(radii: Sequence[float], r0: float, width: float) -> np.ndarray:
