@@ -210,6 +210,18 @@ ur_status ur_simulate_host(ur_plan* plan, const void* rho_host, int32_t x_lo, in
 ur_status ur_plan_workspace_size_host(const ur_plan* plan, int32_t nbins, int32_t x_lo, int32_t x_hi,
                                       size_t* bytes);
 
+/* Voxel form factor (Q-calculation and spherical averaging: the earlier
+ * voxel-sized sinc step, left out for tiny voxels and suggested for
+ * precision near the upper Q limit).  With enable != 0 every binned
+ * intensity of this plan is that of the density taken as uniform over each
+ * voxel rather than sampled at its centre:
+ *     I'(h, k, l) = I(h, k, l) S(h) S(k) S(l),  S(m) = sinc^2(pi m / n),
+ * sinc(x) = sin(x)/x, for the fused forward paths and ur_intensity_bin
+ * (totals[0] then sums I').  A zoom level applies its own voxel.  Allocates
+ * a small table (call before capture); enable = 0 frees it.  The adjoint
+ * refuses plans with the factor on (UR_ERR_UNSUPPORTED). */
+ur_status ur_plan_set_voxel_form(ur_plan* plan, int32_t enable);
+
 /* Limit the out-of-core workspace to `bytes` (0: no limit).  When the x
  * range of the spectrum does not fit, ur_simulate_host runs the second stage
  * of eq. 2 kz chunk by kz chunk: every pass streams the host planes again

@@ -15,6 +15,7 @@ correct statement of the computation, written from the paper:
 * O12 per-bin counts and two-voxel intensities of boxes too large for O4-O8
 * O13 per-bin intensities of a uniform cube at any box size (eq. 1 factorised)
 * O14 polydisperse ensemble of boxes (Results and Discussion; reading in ``ensemble``)
+* O15 voxel form factor (the voxel-sized sinc; reading in ``voxel_form``)
 
 The heavy loops live in ``ur_oracle.c`` (plain C, FP64, OpenMP over
 independent lines); this module marshals numpy arrays and holds the small
@@ -88,7 +89,7 @@ def lib():
         L.or_axis_pair_bins.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_int, _D, ctypes.c_longlong,
                                         ctypes.c_double, ctypes.c_double, _D, _D]
         L.or_cube_bins.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_int, _D, ctypes.c_longlong,
-                                   ctypes.c_double, _D, _D]
+                                   ctypes.c_double, ctypes.c_int, _D, _D]
         _LIB = L
     return _LIB
 
@@ -253,13 +254,28 @@ def bin_counts(n: int, voxel: float, edges: np.ndarray) -> np.ndarray:
     return out
 
 
-def simulate(wl, return_fields: bool = False):
-    """Whole forward path of one box: density -> eq. 1 -> per-bin statistics.
+def voxel_form(n: int) -> np.ndarray:
+    """O15: amplitude factor of a density uniform over each voxel instead of
+    sampled at its centre (the voxel-sized sinc of Q-calculation and
+    spherical averaging): sinc(pi h/n) sinc(pi k/n) sinc(pi l/n) on the
+    [u][v][w] frequency grid, signed indices, sinc(x) = sin(x)/x."""
+    u = np.arange(n)
+    h = np.where(u < n // 2, u, u - n).astype(np.float64)
+    x = np.pi * h / n
+    s1 = np.ones(n)
+    nz = h != 0
+    s1[nz] = np.sin(x[nz]) / x[nz]
+    return s1[:, None, None] * s1[None, :, None] * s1[None, None, :]
+
+
+def simulate(wl, return_fields: bool = False, voxel_form_factor: bool = False):
+    """Whole forward path of one box: density -> eq. 1 -> per-bin statistics
+    (of the voxel-uniform density's intensities with voxel_form_factor).
     Also reports the density moments sum(rho) and sum(rho^2)."""
     cg = cell_synth(wl.cell)
     rho = density(wl, cg)
     F = forward(rho)
-    res = bin_spectrum(F, wl.voxel, wl.edges)
+    res = bin_spectrum(F * voxel_form(wl.n) if voxel_form_factor else F, wl.voxel, wl.edges)
     res["rho_sum"] = float(rho.sum(dtype=np.float64))
     res["rho_sumsq"] = float(np.sum(rho * rho))
     if return_fields:
@@ -311,13 +327,17 @@ def axis_pair_bins(n: int, voxel: float, edges: np.ndarray, d: int, rho1: float,
     return count, s
 
 
-def cube_bins(n: int, voxel: float, edges: np.ndarray, half_width: int, value: float = 1.0):
+def cube_bins(n: int, voxel: float, edges: np.ndarray, half_width: int, value: float = 1.0,
+              voxel_form_factor: bool = False):
     """O13: per-bin voxel count and sum of |F|^2 (eq. 1) over the n^3 box for
-    a uniform cube of the given value on max_i |x_i - n/2| <= half_width."""
+    a uniform cube of the given value on max_i |x_i - n/2| <= half_width;
+    with voxel_form_factor, each axis factor a(u) also carries sinc^2(pi u/n)
+    (O15), which keeps the product form."""
     e = np.ascontiguousarray(edges, dtype=np.float64)
     nb = e.size - 1
     count, s = np.zeros(nb), np.zeros(nb)
-    lib().or_cube_bins(int(n), float(voxel), int(nb), _dp(e), int(half_width), float(value), _dp(count), _dp(s))
+    lib().or_cube_bins(int(n), float(voxel), int(nb), _dp(e), int(half_width), float(value),
+                       int(bool(voxel_form_factor)), _dp(count), _dp(s))
     return count, s
 
 

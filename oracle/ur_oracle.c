@@ -484,7 +484,9 @@ void or_axis_pair_bins(int n, double voxel, int nbins, const double* edges, long
  *      a(u) = |S(u)|^2, the sum of |F|^2 over bin b is
  *      v^2 / n^6 * sum over (h, k) of a(h) a(k) * (sum of a(l) over the l with
  *      U_b <= h^2 + k^2 + l^2 < U_b+1); the inner sum is a difference of the
- *      running sums of a(l) over |l| <= r.  Outputs count[b] and sum[b].      */
+ *      running sums of a(l) over |l| <= r.  Outputs count[b] and sum[b].
+ *      voxel_form != 0 multiplies a(u) by sinc^2(pi u / n) (O15, the form
+ *      factor of a voxel-uniform density), which keeps the product form.     */
 /* ------------------------------------------------------------------------ */
 static long long isqrt_floor(long long v)
 {
@@ -496,7 +498,7 @@ static long long isqrt_floor(long long v)
 }
 
 void or_cube_bins(int n, double voxel, int nbins, const double* edges, long long hw, double v,
-                  double* count, double* sum)
+                  int voxel_form, double* count, double* sum)
 {
     long long* U = (long long*)malloc(sizeof(long long) * (nbins + 1));
     or_thresholds(n, voxel, nbins, edges, U);
@@ -511,6 +513,10 @@ void or_cube_bins(int n, double voxel, int nbins, const double* edges, long long
             s += cexp(-2.0 * M_PI * I * (double)e / (double)n);
         }
         a[u + h2] = creal(s) * creal(s) + cimag(s) * cimag(s);
+        if (voxel_form && u != 0) {             /* O15: times sinc^2(pi u / n) */
+            const double x = M_PI * (double)u / (double)n;
+            a[u + h2] *= (sin(x) / x) * (sin(x) / x);
+        }
     }
     /* P[r] = sum of a(l) over l in [-n/2, n/2) with |l| <= r, kept as an
      * unevaluated pair Ph + Pl (exact two-sum accumulation): a bin's range

@@ -98,6 +98,7 @@ struct ur_plan {
   void* bounce = nullptr;    // pinned host memory
   size_t bounce_bytes = 0;
   size_t hbm_budget = 0;     // out-of-core workspace bytes allowed (0: no limit)
+  void* dSinc = nullptr;     // voxel form factor table S(m), m in [0, n/2], or null when off
 
   // per-pass timing
   bool timing = false;
@@ -391,6 +392,7 @@ void ur_plan_destroy(ur_plan* p) {
   if (p->tw) (void)hipFree(p->tw);
   if (p->dU) (void)hipFree(p->dU);
   if (p->dLut) (void)hipFree(p->dLut);
+  if (p->dSinc) (void)hipFree(p->dSinc);
   if (p->dCount) (void)hipFree(p->dCount);
   if (p->dCountTmp) (void)hipFree(p->dCountTmp);
   if (p->ws && p->ws_owned) (void)hipFree(p->ws);
@@ -420,6 +422,37 @@ ur_status ur_plan_workspace_size_host(const ur_plan* p, int32_t nbins, int32_t x
   OocSplit o;
   UR_TRY(ooc_split(p, nbins, x_lo, x_hi, o));
   *bytes = o.lay.total;
+  return UR_OK;
+}
+
+ur_status ur_plan_set_voxel_form(ur_plan* p, int32_t enable) {
+  if (!p) return fail(UR_ERR_INVALID, "plan is null");
+  if (!enable) {
+    if (p->dSinc) { UR_HIP(hipDeviceSynchronize()); UR_HIP(hipFree(p->dSinc)); p->dSinc = nullptr; }
+    return UR_OK;
+  }
+  if (p->dSinc) return UR_OK;
+  // S(m) = (sin(pi m / n) / (pi m / n))^2, evaluated in long double and
+  // rounded once to the working precision
+  const long double PI = 3.14159265358979323846264338327950288L;
+  const int h = p->n / 2;
+  std::vector<double> v64;
+  std::vector<float> v32;
+  try {
+    v64.resize(h + 1);
+    for (int m = 0; m <= h; ++m) {
+      const long double x = PI * (long double)m / (long double)p->n;
+      const long double sc = m == 0 ? 1.0L : sinl(x) / x;
+      v64[m] = (double)(sc * sc);
+    }
+    if (p->prec == UR_F32) v32.assign(v64.begin(), v64.end());
+  } catch (...) {
+    return fail(UR_ERR_OOM, "host allocation failed for the voxel form factor table");
+  }
+  const size_t bytes = (size_t)(h + 1) * p->rs;
+  UR_HIP(hipMalloc(&p->dSinc, bytes));
+  UR_HIP(hipMemcpy(p->dSinc, p->prec == UR_F32 ? (const void*)v32.data() : (const void*)v64.data(), bytes,
+                   hipMemcpyHostToDevice));
   return UR_OK;
 }
 
@@ -667,7 +700,7 @@ static ur_status run_y_x(ur_plan* p, const FwdGeom& g, char* A, char* B, const L
   xa.nkz = p->nkz; xa.r2c = !(p->flags & UR_C2C);
   xa.xa = (int)bx0; xa.xb = g.xlo <= g.xhi ? (int)(bx0 + bs - 1) : -1;
   xa.iscale = 1.0 / ((double)n * n * n) / ((double)n * n * n);
-  xa.oscale = 1.0; xa.nbins = p->nbins; xa.U = p->dU; xa.lut = p->dLut; xa.nlut = p->nlut;
+  xa.oscale = 1.0; xa.nbins = p->nbins; xa.U = p->dU; xa.lut = p->dLut; xa.nlut = p->nlut; xa.sinc = p->dSinc;
   xa.part = (double*)(p->ws + lay.part); xa.f0 = (double*)(p->ws + lay.f0);
   xa.ncols = p->nkz * n;
   {
@@ -851,6 +884,7 @@ ur_status ur_intensity_bin(ur_plan* p, const void* spectrum, const ur_hist* h, v
   XArgs xa{};
   xa.B = spectrum; xa.bx0 = 0; xa.bs = n; xa.tw = p->tw; xa.nkz = p->nkz; xa.r2c = !(p->flags & UR_C2C);
   xa.xa = 0; xa.xb = n - 1; xa.iscale = 1.0; xa.nbins = p->nbins; xa.U = p->dU; xa.lut = p->dLut; xa.nlut = p->nlut;
+  xa.sinc = p->dSinc;
   xa.part = (double*)(p->ws + lay.part); xa.f0 = (double*)(p->ws + lay.f0); xa.ncols = p->nkz * n;
   const int nxb = x_blocks(p, X_BIN_ONLY);
   UR_HIP(launch_pass_x(p->prec, n, X_BIN_ONLY, -1, xa, nxb, s));
@@ -972,7 +1006,7 @@ ur_status ur_simulate_host(ur_plan* p, const void* rho_host, int32_t x_lo, int32
     xa.B = B; xa.bx0 = bx0; xa.bs = bs; xa.tw = p->tw; xa.nkz = p->nkz; xa.r2c = 1;
     xa.xa = (int)bx0; xa.xb = (int)(bx0 + bs - 1);
     xa.iscale = 1.0 / ((double)n * n * n) / ((double)n * n * n);
-    xa.nbins = p->nbins; xa.U = p->dU; xa.lut = p->dLut; xa.nlut = p->nlut;
+    xa.nbins = p->nbins; xa.U = p->dU; xa.lut = p->dLut; xa.nlut = p->nlut; xa.sinc = p->dSinc;
     xa.part = (double*)(p->ws + lay.part); xa.f0 = (double*)(p->ws + lay.f0);
     xa.ncols = nk * n; xa.kz0 = kz0; xa.accum = chunk > 0;
     UR_HIP(launch_pass_x(p->prec, n, X_FFT_BIN, -1, xa, nxb, s));
@@ -1037,6 +1071,7 @@ static ur_status adjoint_run(ur_plan* p, const void* rho, const ur_cell* cell, c
   if ((rho != nullptr) == (cell != nullptr)) return fail(UR_ERR_INVALID, "give exactly one of rho and cell");
   if (grad_amp && !cell) return fail(UR_ERR_INVALID, "grad_amp needs the cell description");
   if (cell && cell->rot) return fail(UR_ERR_UNSUPPORTED, "the adjoint runs for lattices aligned with the box (rot = NULL)");
+  if (p->dSinc) return fail(UR_ERR_UNSUPPORTED, "the adjoint runs without the voxel form factor");
   if (!grad_rho && !grad_amp) return UR_OK;
   if (p->n > 1024) return fail(UR_ERR_UNSUPPORTED, "the adjoint runs up to 1024^3");
   hipStream_t s = (hipStream_t)stream;

@@ -819,6 +819,8 @@ k_pass_x(XArgs a) {
   // is needed, the column stride is the padded length itself (this keeps
   // the FP64 block within the LDS of two blocks per CU)
   constexpr int G = C::G, NG = C::NG, E = Geo<N>::E, PS = Padded<N>::size;
+  constexpr bool SINC = MODE == X_FFT_BIN_SINC || MODE == X_BIN_ONLY_SINC;
+  constexpr bool BINONLY = MODE == X_BIN_ONLY || MODE == X_BIN_ONLY_SINC;
   __shared__ cx<T> sm[NG * PS];
   extern __shared__ double dyn[];
   // hist[2 b], hist[2 b + 1] for b in [-1, nbins]: the two outer slots take
@@ -827,6 +829,8 @@ k_pass_x(XArgs a) {
   double* tot_s = dyn + 2 * ((size_t)a.nbins + 2);
   int* U = (int*)(tot_s + 1);                          // nbins + 3 (last two: sentinels)
   short* Ls = (short*)(U + a.nbins + 3);               // nlut: bin of n2 = s^2
+  // SINC: voxel form factor S(|m|) for |m| in [0, N/2], 16-byte aligned after Ls
+  T* St = (T*)((char*)dyn + ((((char*)(Ls + a.nlut) - (char*)dyn) + 15) & ~(size_t)15));
 
   // G >= 64: every wavefront lies in one column, wave-uniform column index.
   // For G > 64 the column syncs are workgroup barriers: the launcher makes
@@ -842,6 +846,8 @@ k_pass_x(XArgs a) {
     for (int i = threadIdx.x; i < 2 * (a.nbins + 2) + 1; i += C::threads) dyn[i] = 0.0;
     for (int i = threadIdx.x; i <= a.nbins; i += C::threads) U[i] = a.U[i];
     for (int i = threadIdx.x; i < a.nlut; i += C::threads) Ls[i] = a.lut[i];
+    if constexpr (SINC)
+      for (int i = threadIdx.x; i <= N / 2; i += C::threads) St[i] = ((const T*)a.sinc)[i];
     if (threadIdx.x == 0) { U[a.nbins + 1] = 0x7fffffff; U[a.nbins + 2] = 0x7fffffff; }
     __syncthreads();
   }
@@ -849,10 +855,10 @@ k_pass_x(XArgs a) {
   const long long stride = (long long)gridDim.x * NG;
   long long col = (long long)blockIdx.x * NG + q;
   cx<T> v[E];
-  if (MODE != X_BIN_ONLY && col < a.ncols) x_load_column<T, N>(a, col, g, v);
+  if (!BINONLY && col < a.ncols) x_load_column<T, N>(a, col, g, v);
   for (; col < a.ncols; col += stride) {
     const int kz = a.kz0 + (int)(col / N), ky = (int)(col % N);
-    if (MODE == X_BIN_ONLY) {
+    if (BINONLY) {
       const cx<T>* src = (const cx<T>*)a.B + (size_t)col * a.bs - a.bx0;
       for (int i = g; i < N; i += G) s[pad(i)] = (i >= a.xa && i <= a.xb) ? src[i] : mk((T)0, (T)0);
       col_sync<G>();
@@ -892,9 +898,12 @@ k_pass_x(XArgs a) {
     int cb = b;
     T cs = (T)0, ct = (T)0;
     double cs2 = 0.0;
-    const double ws = w * a.iscale, ws2 = w * a.iscale * a.iscale;
+    // SINC: the column's factor S(|k|) S(|l|) joins the weight, S(|h|) each voxel
+    const double wcol = SINC ? (double)St[k < 0 ? -k : k] * (double)St[l < 0 ? -l : l] : 1.0;
+    const double ws = w * a.iscale * wcol, ws2 = w * a.iscale * a.iscale * wcol * wcol;
     const cx<T>* sp = s + pad(hlo);
     auto take = [&](int ha, T q1, T q2) {
+      if constexpr (SINC) { const T sh = St[ha]; q1 *= sh; q2 *= sh; }
       const int n2 = ha * ha + base;
       if (n2 >= nextU) {
         atomicAdd(&hist[2 * cb + 0], (double)cs * ws);
@@ -1695,7 +1704,9 @@ hipError_t launch_pass_y(int prec, int n, const YArgs& a, hipStream_t s) {
 #undef UR_Y
 }
 
-static size_t x_shm(int mode, int nbins, int n) {
+static size_t x_shm(int mode, int nbins, int n, size_t ts = 8) {
+  if (mode == X_FFT_BIN_SINC || mode == X_BIN_ONLY_SINC)
+    return x_shm(mode == X_FFT_BIN_SINC ? X_FFT_BIN : X_BIN_ONLY, nbins, n) + 16 + ((size_t)n / 2 + 1) * ts;
   if (mode == X_ADJ)
     return ((size_t)nbins + 2) * sizeof(double) + ((size_t)nbins + 2) * sizeof(int) + (size_t)lut_len(n) * sizeof(short);
   return mode == X_FFT_STORE ? 0 : (2 * (size_t)nbins + 5) * sizeof(double) + ((size_t)nbins + 3) * sizeof(int)
@@ -1708,6 +1719,7 @@ static int x_resident_t(int mode, int dir, int nbins) {
   hipError_t e;
   size_t shm = x_shm(mode, nbins, N);
   if (mode == X_FFT_BIN) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pass_x<T, N, X_FFT_BIN, -1>, XCfg<N>::threads, shm);
+  else if (mode == X_FFT_BIN_SINC || mode == X_BIN_ONLY_SINC) return x_resident_t<T, N>(mode == X_FFT_BIN_SINC ? X_FFT_BIN : X_BIN_ONLY, dir, nbins);
   else if constexpr (N == kBig) return 1;
   else if (mode == X_ADJ) {
     if constexpr (inv_fits<T, N>()) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pass_x_adj<T, N>, XCfg<N>::threads, shm);
@@ -1745,13 +1757,17 @@ hipError_t launch_bin_counts(int n, int nkz, int r2c, int nbins, const int* U, u
 
 template <typename T, int N>
 static hipError_t pass_x_t(int mode, int dir, const XArgs& a, int nblocks, hipStream_t s) {
-  size_t shm = x_shm(mode, a.nbins, N);
+  if (a.sinc && mode == X_FFT_BIN) mode = X_FFT_BIN_SINC;        // voxel form factor requested
+  if (a.sinc && mode == X_BIN_ONLY) mode = X_BIN_ONLY_SINC;
+  size_t shm = x_shm(mode, a.nbins, N, sizeof(T));
   // columns spanning several wavefronts sync with workgroup barriers: every
   // group of a block must run the same number of iterations
   if (XCfg<N>::G > 64 && a.ncols % XCfg<N>::NG != 0) return hipErrorInvalidValue;
   dim3 grid(nblocks), blk(XCfg<N>::threads);
   if (mode == X_FFT_BIN) hipLaunchKernelGGL((k_pass_x<T, N, X_FFT_BIN, -1>), grid, blk, shm, s, a);
+  else if (mode == X_FFT_BIN_SINC) hipLaunchKernelGGL((k_pass_x<T, N, X_FFT_BIN_SINC, -1>), grid, blk, shm, s, a);
   else if constexpr (N == kBig) return hipErrorNotSupported;
+  else if (mode == X_BIN_ONLY_SINC) hipLaunchKernelGGL((k_pass_x<T, N, X_BIN_ONLY_SINC, -1>), grid, blk, shm, s, a);
   else if (mode == X_BIN_ONLY) hipLaunchKernelGGL((k_pass_x<T, N, X_BIN_ONLY, -1>), grid, blk, shm, s, a);
   else if (dir < 0) hipLaunchKernelGGL((k_pass_x<T, N, X_FFT_STORE, -1>), grid, blk, shm, s, a);
   else hipLaunchKernelGGL((k_pass_x<T, N, X_FFT_STORE, +1>), grid, blk, shm, s, a);

@@ -19,7 +19,9 @@ constexpr int kMaxOutOfCore = 4096;
 enum ZMode { Z_GEN_R2C = 0, Z_LOAD_R2C = 1, Z_GEN_C2C = 2, Z_LOAD_C2C = 3, Z_ZOOM_R2C = 4, Z_ZOOM_C2C = 5,
              Z_ROT_R2C = 6 };
 // What the last (x) pass does with each transformed column.
-enum XMode { X_FFT_BIN = 0, X_BIN_ONLY = 1, X_FFT_STORE = 2, X_ADJ = 3 };   // X_ADJ: the adjoint column pass
+// X_ADJ: the adjoint column pass; the _SINC variants (chosen by the launcher
+// when XArgs::sinc is set) weight every intensity by the voxel form factor.
+enum XMode { X_FFT_BIN = 0, X_BIN_ONLY = 1, X_FFT_STORE = 2, X_ADJ = 3, X_FFT_BIN_SINC = 4, X_BIN_ONLY_SINC = 5 };
 
 struct ZArgs {
   void* A;                  // out: [x - ax0][kz][y] complex
@@ -87,6 +89,7 @@ struct XArgs {
   int ncols;
   int kz0;                  // kz of column 0 (B holds rows kz0 .. kz0 + ncols / n - 1)
   int accum;                // add to the block partials instead of writing them (later kz chunks)
+  const void* sinc;         // null, or S(m) = sinc^2(pi m / n) for m in [0, n/2] (working precision)
 };
 
 struct FinArgs {

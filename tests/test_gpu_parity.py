@@ -306,3 +306,47 @@ def test_rotated_lattice(ur, orc, n, prec):
     with pytest.raises(ur.UltimaError, match="status 2"):
         plan.simulate(cell, wl.mask, W.Zoom(2 * n, 2), h)
     torch.cuda.synchronize()
+
+
+# ---------------------------------------------------------------------------
+# voxel form factor (intensities of the voxel-uniform density)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_voxel_form_factor(ur, orc, prec):
+    """With the voxel form factor on: the fused path, ur_simulate_rho and
+    ur_intensity_bin against the oracle with O15 applied; off again gives the
+    plain curve; the adjoint refuses the plan."""
+    import torch
+    wl = W.small(64, c=8, n_atoms=9, seed=33, radius=22.0, nbins=50, prec=prec)
+    _say(f"voxel form factor prec={prec}")
+    ref_v = orc.simulate(wl, return_fields=True, voxel_form_factor=True)
+    plan = ur.Plan(wl.n, wl.voxel, prec)
+    plan.set_bins(wl.edges)
+    plan.set_voxel_form(True)
+    cell = ur.DeviceCell.from_host(wl.cell)
+    tol = F32_BIN if prec == 0 else F64_BIN
+    h = ur.Hist(wl.nbins)
+    plan.simulate(cell, wl.mask, wl.zoom, h)
+    torch.cuda.synchronize()
+    compare_bins(h.numpy(), ref_v, tol, "simulate + voxel form", n=wl.n)
+    rho = torch.as_tensor(ref_v["rho"], dtype=plan.real_dtype, device="cuda").contiguous()
+    h1 = ur.Hist(wl.nbins)
+    plan.simulate_rho(rho, h1)
+    torch.cuda.synchronize()
+    compare_bins(h1.numpy(), ref_v, tol, "simulate_rho + voxel form", n=wl.n)
+    spec = torch.as_tensor(np.ascontiguousarray(ref_v["F"][:, :, : wl.n // 2 + 1].transpose(2, 1, 0)),
+                           dtype=plan.complex_dtype, device="cuda")
+    h2 = ur.Hist(wl.nbins)
+    plan.intensity_bin(spec, h2)
+    torch.cuda.synchronize()
+    compare_bins(h2.numpy(), ref_v, tol, "intensity_bin + voxel form", n=wl.n)
+    g = torch.zeros(wl.nbins, dtype=torch.float64, device="cuda")
+    ga = torch.zeros(wl.cell.n_atoms, dtype=torch.float64, device="cuda")
+    with pytest.raises(ur.UltimaError, match="status 2"):
+        plan.adjoint(h, g, cell=cell, mask=wl.mask, grad_amp=ga)
+    plan.set_voxel_form(False)
+    h3 = ur.Hist(wl.nbins)
+    plan.simulate(cell, wl.mask, wl.zoom, h3)
+    torch.cuda.synchronize()
+    compare_bins(h3.numpy(), orc.simulate(wl), tol, "voxel form off", n=wl.n)

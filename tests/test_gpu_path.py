@@ -594,11 +594,11 @@ def bin_bound(n, mean, ibar, prec):
     return np.maximum(tol, 8.0 * eps * math.sqrt(3 * math.log2(n)) * np.sqrt(ibar / mean))
 
 
-@pytest.mark.parametrize("prec", [1, 0])
-def test_uniform_cube_every_bin_2048(ur, orc, prec):
+@pytest.mark.parametrize("prec,vform", [(1, False), (0, False), (1, True)])
+def test_uniform_cube_every_bin_2048(ur, orc, prec, vform):
     """2048^3 in HBM (the in-HBM path's largest box): a uniform cube of
     half-width 700, every one of 1024 bins against the factorised closed form
-    of eq. 1 (O13): counts bit-exact; means within 1e-5 (FP32) / 1e-12
+    of eq. 1 (O13; with the voxel form factor, the continuous cube): counts bit-exact; means within 1e-5 (FP32) / 1e-12
     (FP64), or the transform's error bound (bin_bound) where a bin's mean
     lies far below the box mean."""
     import torch
@@ -606,13 +606,14 @@ def test_uniform_cube_every_bin_2048(ur, orc, prec):
     _say(f"uniform cube 2048^3 prec={prec}")
     plan = ur.Plan(wl.n, wl.voxel, prec)
     plan.set_bins(wl.edges)
+    plan.set_voxel_form(vform)
     h = ur.Hist(wl.nbins)
     plan.simulate(ur.DeviceCell.from_host(wl.cell), wl.mask, wl.zoom, h)
     torch.cuda.synchronize()
     got = h.numpy()
     del plan
     torch.cuda.empty_cache()
-    cnt, s = orc.cube_bins(wl.n, 1.0, wl.edges, 700, 1.0)
+    cnt, s = orc.cube_bins(wl.n, 1.0, wl.edges, 700, 1.0, voxel_form_factor=vform)
     assert np.array_equal(got["count"], cnt)
     pop = cnt > 0
     ref = s[pop] / cnt[pop]
@@ -628,7 +629,8 @@ def test_uniform_cube_every_bin_2048(ur, orc, prec):
         _say(f"    bin {np.flatnonzero(pop)[i]}: count {cnt[pop][i]:.0f}, I/Ibar {ref[i] / ibar:.3e}, "
              f"rel err {rel[i]:.3e}, bound {bound[i]:.3e}")
     assert np.all(rel <= bound)
-    assert abs(got["totals"][0] - w3 / n3) <= 1e-6 * w3 / n3                 # Parseval
+    if not vform:
+        assert abs(got["totals"][0] - w3 / n3) <= 1e-6 * w3 / n3             # Parseval
     assert abs(got["totals"][1] - w3 / n3) <= 1e-6 * w3 / n3                 # F(0)
 
 

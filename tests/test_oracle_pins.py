@@ -647,3 +647,35 @@ def test_rotated_lattice_matches_scipy_map_coordinates(oracle_lib):
     ref = map_coordinates(cg, U, order=1, mode="grid-wrap")
     assert np.max(np.abs(got[inside] - ref)) <= 1e-12 * np.max(np.abs(cg))
     assert np.all(got[~inside] == 0.0)
+
+
+# ---------------------------------------------------------------------------
+# O15: voxel form factor (a density uniform over each voxel)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,hw", [(32, 5), (32, 10), (16, 7)])
+def test_voxel_form_of_a_cube_is_the_continuous_cube(oracle_lib, n, hw):
+    """A cube of W = 2 hw + 1 voxels, each voxel uniform, is the continuous
+    cube of edge W: per axis sin(pi h W/n)/sin(pi h/n) * sinc(pi h/n) =
+    sin(pi h W/n)/(pi h/n).  O13 with the factor against that closed form
+    binned voxel by voxel, and O15 applied to the transform of the voxel
+    cube (oracle.simulate) against both."""
+    import oracle
+    W_ = 2 * hw + 1
+    edges = W.default_log_edges(n, 1.0, 30)
+    u = np.arange(n)
+    h = np.where(u < n // 2, u, u - n).astype(np.float64)
+    g = np.full(n, float(W_))
+    nz = h != 0
+    g[nz] = np.sin(np.pi * h[nz] * W_ / n) / (np.pi * h[nz] / n)
+    Fc = g[:, None, None] * g[None, :, None] * g[None, None, :] / float(n) ** 3
+    ref = oracle_lib.bin_spectrum(Fc.astype(np.complex128), 1.0, edges)
+    cnt, s = oracle.cube_bins(n, 1.0, edges, hw, 1.0, voxel_form_factor=True)
+    assert np.array_equal(cnt, ref["count"])
+    assert np.max(np.abs(s - ref["sum"])) <= 1e-12 * np.max(ref["sum"])
+    wl = W.uniform_cube(n, hw, 30, prec=1)
+    sim = oracle.simulate(wl, voxel_form_factor=True)
+    pop = cnt > 0
+    assert np.allclose(sim["mean"][pop], ref["mean"][pop], rtol=1e-11, atol=1e-14 * np.nanmax(ref["mean"]))
+    f = oracle.voxel_form(n)
+    assert f[0, 0, 0] == 1.0 and abs(f[n // 2, 0, 0] - 2.0 / np.pi) <= 1e-15
