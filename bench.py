@@ -423,6 +423,18 @@ def main():
         note("fwd_adjoint_keep_ms done")
         torch.cuda.synchronize()
         del fwd_adj
+        # Ewald-sphere image of the same box: 1024 x 1024 pixels, 16
+        # wavelength nodes (2 % spread), from the transform held in HBM
+        spec = plan.fft3d(plan.rho_generate(cell, wl.mask, wl.zoom))
+        geo = W.detector(W.rotation([0.0, 1.0, 0.0], 0.3), rel_spread=0.02, n_lambda=16, distance=1000.0,
+                         pixel=0.05, nu=1024, nv=1024)
+        img = torch.empty((geo.nv, geo.nu), dtype=torch.float64, device="cuda")
+        ms_ew, _ = time_steps(lambda: plan.ewald_image(spec, geo, out=img), max(3, args.steps), 2, torch)
+        extras["ewald_image"] = {"pixels": geo.nu * geo.nv, "n_lambda": geo.n_lambda, "ms": round(ms_ew, 4),
+                                 "samples_per_s": geo.nu * geo.nv * geo.n_lambda / (ms_ew * 1e-3)}
+        del spec, img
+        torch.cuda.empty_cache()
+        note("ewald_image done")
         # multi-zoom batch: ED-1 2048^3 + ED-2 1024^3 (f 4) + ED-3 512^3 (f 16)
         # and the merge, recorded in one HIP graph and replayed
         extras["c3_batch"] = c3_batch(ur, W, torch, max(2, args.steps // 4))

@@ -287,6 +287,36 @@ ur_status ur_merge_zooms(int32_t nlevels, const ur_hist* levels, const int32_t* 
                          const double* voxel, int32_t nbins, const double* edges, int32_t mode,
                          double n_min, double* mean, double* sem, int32_t* owner, void* stream);
 
+/* Ewald-sphere detector image (Q-calculation and spherical averaging: 2D
+ * data of an anisotropic sample taken on a spherical shell whose thickness
+ * follows the wavelength distribution).  Flat detector normal to the beam:
+ * pixel (iu, iv) sits at distance * beam + (iu - cu) pixel du
+ * + (iv - cv) pixel dv from the sample (box axes x, y, z; beam, du, dv
+ * orthonormal); s is its unit direction.  For each wavelength node
+ * lambda_j = wavelength (1 + rel_spread t_j), t_j evenly spaced on [-3, 3]
+ * with weights exp(-t_j^2/2) normalised (one node at t = 0 when
+ * rel_spread = 0), q = (2 pi / lambda_j)(s - beam) (nm^-1) is located on
+ * the reciprocal grid (step 2 pi / (n voxel)) and I = |F|^2 is
+ * interpolated trilinearly between the grid points (the DFT taken as
+ * periodic; a real transform's missing half from F(-q) = F(q)*).
+ * image[iv][iu] (DEVICE, nv x nu doubles) receives the node-weighted mean.
+ * spectrum: DEVICE, this plan's [kz][ky][kx] layout (ur_fft3d_exec).
+ * UR_ERR_INVALID for non-positive lengths, rel_spread outside [0, 0.3),
+ * n_lambda outside [1, 64], or axes that are not orthonormal. */
+typedef struct {
+  double wavelength;   /* nm */
+  double rel_spread;   /* Gaussian sigma of the wavelength, relative */
+  int32_t n_lambda;    /* wavelength nodes when rel_spread > 0 */
+  double beam[3];      /* unit vector of the incident beam */
+  double du[3];        /* unit vector along detector rows (iu) */
+  double dv[3];        /* unit vector along detector columns (iv) */
+  double distance;     /* sample to detector, along the beam */
+  double pixel;        /* pixel pitch, same unit as distance */
+  double cu, cv;       /* beam centre on the detector, pixels */
+  int32_t nu, nv;      /* pixels per row, rows */
+} ur_ewald;
+ur_status ur_ewald_image(ur_plan* plan, const void* spectrum, const ur_ewald* geom, double* image, void* stream);
+
 /* Polydisperse ensemble (Results and Discussion: polydispersity described by
  * some 200 volume-weighted contributions, one simulation each).  For nboxes
  * boxes that share one bin set (one particle each, summed incoherently),

@@ -16,6 +16,8 @@ correct statement of the computation, written from the paper:
 * O13 per-bin intensities of a uniform cube at any box size (eq. 1 factorised)
 * O14 polydisperse ensemble of boxes (Results and Discussion; reading in ``ensemble``)
 * O15 voxel form factor (the voxel-sized sinc; reading in ``voxel_form``)
+* O16 Ewald-sphere detector image (Q-calculation and spherical averaging;
+  reading in ``ewald_image``)
 
 The heavy loops live in ``ur_oracle.c`` (plain C, FP64, OpenMP over
 independent lines); this module marshals numpy arrays and holds the small
@@ -514,6 +516,66 @@ def ensemble(means: Sequence[np.ndarray], sems: Sequence[np.ndarray], weights: S
         mean += w * np.asarray(m, dtype=np.float64)
         var += (w * np.asarray(e, dtype=np.float64)) ** 2
     return mean, np.sqrt(var)
+
+
+# ---------------------------------------------------------------------------
+# O16  Ewald-sphere image
+# ---------------------------------------------------------------------------
+
+def wavelength_nodes(rel_spread: float, n_lambda: int):
+    """Reading of the shell thickness set by the wavelength distribution: a
+    Gaussian of relative width rel_spread, truncated at three widths and
+    taken at n_lambda evenly spaced points t_j of [-3, 3] with weights
+    proportional to exp(-t_j^2 / 2), normalised to sum 1 (lambda_j =
+    lambda (1 + rel_spread t_j)).  No spread, or one node: the single point
+    t = 0."""
+    if rel_spread == 0.0 or n_lambda == 1:
+        return np.zeros(1), np.ones(1)
+    t = np.linspace(-3.0, 3.0, n_lambda)
+    w = np.exp(-0.5 * t * t)
+    return t, w / w.sum()
+
+
+def ewald_image(F: np.ndarray, voxel: float, geo) -> np.ndarray:
+    """2D detector image of an anisotropic sample (Q-calculation and
+    spherical averaging: intensity taken on the Ewald sphere, a shell whose
+    thickness follows the wavelength distribution).
+
+    F is the full n^3 spectrum of eq. 1, F[u][v][w] at the frequency
+    (u, v, w) along the box axes (x, y, z).  The pixel (iu, iv) sits at
+    P = distance e + (iu - cu) pixel du + (iv - cv) pixel dv from the
+    sample and scatters along s = P / |P|; at the wavelength lambda_j the
+    elastic momentum transfer is q = (2 pi / lambda_j)(s - e), at grid
+    coordinate g = q / dq with dq = 2 pi / (n voxel) (the spacing of eq. 1's
+    frequencies).  I = |F|^2 is taken between the grid points by trilinear
+    interpolation, the grid periodic (the DFT is), and the image is the
+    node-weighted sum over the wavelengths (``wavelength_nodes``).
+    Returns image[iv][iu]."""
+    n = F.shape[0]
+    I = np.abs(np.asarray(F, dtype=np.complex128)) ** 2
+    e, du, dv = (np.asarray(v, dtype=np.float64) for v in (geo.beam, geo.du, geo.dv))
+    iv, iu = np.meshgrid(np.arange(geo.nv, dtype=np.float64), np.arange(geo.nu, dtype=np.float64), indexing="ij")
+    P = (geo.distance * e[None, None, :] + ((iu - geo.cu) * geo.pixel)[..., None] * du[None, None, :]
+         + ((iv - geo.cv) * geo.pixel)[..., None] * dv[None, None, :])
+    s = P / np.linalg.norm(P, axis=-1, keepdims=True)
+    dq = 2.0 * math.pi / (n * voxel)
+    t, w = wavelength_nodes(geo.rel_spread, geo.n_lambda)
+    image = np.zeros((geo.nv, geo.nu))
+    for tj, wj in zip(t, w):
+        k = 2.0 * math.pi / (geo.wavelength * (1.0 + geo.rel_spread * tj))
+        g = k * (s - e[None, None, :]) / dq
+        g0 = np.floor(g)
+        f = g - g0
+        g0 = g0.astype(np.int64)
+        val = np.zeros((geo.nv, geo.nu))
+        for a in (0, 1):
+            for b in (0, 1):
+                for c in (0, 1):
+                    wt = ((f[..., 0] if a else 1.0 - f[..., 0]) * (f[..., 1] if b else 1.0 - f[..., 1])
+                          * (f[..., 2] if c else 1.0 - f[..., 2]))
+                    val += wt * I[(g0[..., 0] + a) % n, (g0[..., 1] + b) % n, (g0[..., 2] + c) % n]
+        image += wj * val
+    return image
 
 
 def chi2(mean: np.ndarray, count: np.ndarray, target: np.ndarray, rel_sigma: float = 0.01) -> float:

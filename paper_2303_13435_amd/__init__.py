@@ -44,6 +44,19 @@ class UrHist(_c.Structure):
     _fields_ = [("sum", _vp), ("sumsq", _vp), ("count", _vp), ("totals", _vp), ("mean", _vp), ("sem", _vp)]
 
 
+class UrEwald(_c.Structure):
+    _fields_ = [("wavelength", _c.c_double), ("rel_spread", _c.c_double), ("n_lambda", _c.c_int32),
+                ("beam", _c.c_double * 3), ("du", _c.c_double * 3), ("dv", _c.c_double * 3),
+                ("distance", _c.c_double), ("pixel", _c.c_double), ("cu", _c.c_double), ("cv", _c.c_double),
+                ("nu", _c.c_int32), ("nv", _c.c_int32)]
+
+    @classmethod
+    def from_geometry(cls, g) -> "UrEwald":
+        return cls(float(g.wavelength), float(g.rel_spread), int(g.n_lambda), (_c.c_double * 3)(*g.beam),
+                   (_c.c_double * 3)(*g.du), (_c.c_double * 3)(*g.dv), float(g.distance), float(g.pixel),
+                   float(g.cu), float(g.cv), int(g.nu), int(g.nv))
+
+
 _LIB = None
 
 # (name, argtypes)
@@ -68,6 +81,7 @@ _SIGS = {
     "ur_adjoint_reuse": [_vp, _c.POINTER(UrCell), _c.POINTER(UrMask), _c.POINTER(UrHist), _vp, _vp, _vp],
     "ur_merge_zooms": [_c.c_int32, _c.POINTER(UrHist), _c.POINTER(_c.c_int32), _c.POINTER(_c.c_double),
                        _c.c_int32, _vp, _c.c_int32, _c.c_double, _vp, _vp, _vp, _vp],
+    "ur_ewald_image": [_vp, _vp, _c.POINTER(UrEwald), _vp, _vp],
     "ur_ensemble": [_c.c_int32, _c.c_int32, _vp, _vp, _vp, _vp, _vp, _vp],
     "ur_graph_begin": [_vp],
     "ur_graph_end": [_vp, _c.POINTER(_vp)],
@@ -410,6 +424,19 @@ class Plan:
             self._attach(self.workspace_size(1))
         self.calls += 1
         _check(lib().ur_fft3d_exec(self.h, _ptr(x), _ptr(out), int(direction), _stream(stream)), "ur_fft3d_exec")
+        return out
+
+    def ewald_image(self, spectrum, geometry, out=None, stream=None):
+        """Detector image (nv, nu) in FP64 of the spectrum of ``fft3d`` on the
+        Ewald sphere of a flat detector (``workloads.Ewald`` fields)."""
+        torch = _torch()
+        _require(spectrum, self.complex_dtype, self.nkz() * self.n * self.n, "spectrum")
+        if out is None:
+            out = torch.empty((int(geometry.nv), int(geometry.nu)), dtype=torch.float64, device="cuda")
+        _require(out, torch.float64, int(geometry.nv) * int(geometry.nu), "image")
+        g = UrEwald.from_geometry(geometry)
+        _check(lib().ur_ewald_image(self.h, _ptr(spectrum), _c.byref(g), _ptr(out), _stream(stream)),
+               "ur_ewald_image")
         return out
 
     def intensity_bin(self, spectrum, hist: Hist, stream=None) -> Hist:

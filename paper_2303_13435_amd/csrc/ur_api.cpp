@@ -1176,6 +1176,45 @@ static ur_status adjoint_run(ur_plan* p, const void* rho, const ur_cell* cell, c
   return UR_OK;
 }
 
+ur_status ur_ewald_image(ur_plan* p, const void* spectrum, const ur_ewald* geo, double* image, void* stream) {
+  if (!p || !spectrum || !geo || !image) return fail(UR_ERR_INVALID, "null argument");
+  UR_TRY(need_in_core(p));
+  if (!(geo->wavelength > 0.0) || !isfinite(geo->wavelength)) return fail(UR_ERR_INVALID, "wavelength must be positive");
+  if (!(geo->rel_spread >= 0.0) || !isfinite(geo->rel_spread) || geo->rel_spread >= 0.3)
+    return fail(UR_ERR_INVALID, "rel_spread must be in [0, 0.3)");
+  if (geo->n_lambda < 1 || geo->n_lambda > 64) return fail(UR_ERR_INVALID, "n_lambda = %d outside [1, 64]", geo->n_lambda);
+  if (!(geo->distance > 0.0) || !(geo->pixel > 0.0) || !isfinite(geo->distance) || !isfinite(geo->pixel))
+    return fail(UR_ERR_INVALID, "distance and pixel must be positive");
+  if (geo->nu < 1 || geo->nv < 1 || (long long)geo->nu * geo->nv > (1ll << 28))
+    return fail(UR_ERR_INVALID, "detector of %d x %d pixels", geo->nu, geo->nv);
+  if (!isfinite(geo->cu) || !isfinite(geo->cv)) return fail(UR_ERR_INVALID, "beam centre must be finite");
+  auto dot = [](const double* a, const double* b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; };
+  const double* vs[3] = {geo->beam, geo->du, geo->dv};
+  for (int i = 0; i < 3; ++i)
+    for (int j = i; j < 3; ++j)
+      if (fabs(dot(vs[i], vs[j]) - (i == j ? 1.0 : 0.0)) > 1e-9)
+        return fail(UR_ERR_INVALID, "beam, du and dv must be orthonormal");
+  EwaldArgs a{};
+  a.spec = spectrum; a.n = p->n; a.nkz = p->nkz; a.c2c = (p->flags & UR_C2C) ? 1 : 0;
+  a.dq = 2.0 * M_PI / ((double)p->n * p->voxel);
+  for (int i = 0; i < 3; ++i) { a.e[i] = geo->beam[i]; a.du[i] = geo->du[i]; a.dv[i] = geo->dv[i]; }
+  a.dist = geo->distance; a.pixel = geo->pixel; a.cu = geo->cu; a.cv = geo->cv;
+  a.nu = geo->nu; a.nv = geo->nv; a.nl = geo->rel_spread > 0.0 ? geo->n_lambda : 1;
+  // wavelength nodes lambda (1 + sigma t_j), t_j evenly spaced on [-3, 3],
+  // weights exp(-t_j^2 / 2) normalised
+  double wsum = 0.0;
+  for (int j = 0; j < a.nl; ++j) {
+    const double t = a.nl == 1 ? 0.0 : -3.0 + 6.0 * j / (a.nl - 1);
+    a.k[j] = 2.0 * M_PI / (geo->wavelength * (1.0 + geo->rel_spread * t));
+    a.w[j] = exp(-0.5 * t * t);
+    wsum += a.w[j];
+  }
+  for (int j = 0; j < a.nl; ++j) a.w[j] /= wsum;
+  a.image = image;
+  UR_HIP(launch_ewald(p->prec, a, (hipStream_t)stream));
+  return UR_OK;
+}
+
 ur_status ur_ensemble(int32_t nboxes, int32_t nbins, const double* mean, const double* sem, const double* weights,
                       double* out_mean, double* out_sem, void* stream) {
   if (nboxes < 1) return fail(UR_ERR_INVALID, "nboxes = %d must be >= 1", nboxes);

@@ -1796,6 +1796,63 @@ hipError_t launch_finalize(const FinArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+// |F|^2 at the integer frequency (h, k, l) (signed, any range: the DFT is
+// periodic); a real transform keeps kz in [0, n/2], the rest by F(-q) = F(q)*
+template <typename T>
+__device__ __forceinline__ double ewald_intensity(const EwaldArgs& a, long long h, long long k, long long l) {
+  const long long n = a.n;
+  long long lz = ((l % n) + n) % n;
+  if (!a.c2c && lz > n / 2) { h = -h; k = -k; lz = (((-l) % n) + n) % n; }
+  const long long kx = ((h % n) + n) % n, ky = ((k % n) + n) % n;
+  const cx<T> f = ((const cx<T>*)a.spec)[((size_t)lz * n + ky) * n + kx];
+  return (double)f.x * (double)f.x + (double)f.y * (double)f.y;
+}
+
+// One thread per pixel: flat detector normal to the beam e at distance
+// dist, pixel (iu, iv) at dist e + (iu - cu) pixel du + (iv - cv) pixel dv;
+// scattered direction s; for each wavelength node q = k_j (s - e), grid
+// coordinates q / dq, trilinear interpolation of |F|^2 (the third axis
+// first), weighted sum over the nodes.
+template <typename T>
+__global__ void __launch_bounds__(256) k_ewald(EwaldArgs a) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)a.nu * a.nv) return;
+  const int iu = (int)(t % a.nu), iv = (int)(t / a.nu);
+  double P[3];
+  for (int i = 0; i < 3; ++i)
+    P[i] = a.dist * a.e[i] + ((double)iu - a.cu) * a.pixel * a.du[i] + ((double)iv - a.cv) * a.pixel * a.dv[i];
+  const double r = sqrt(P[0] * P[0] + P[1] * P[1] + P[2] * P[2]);
+  double acc = 0.0;
+  for (int j = 0; j < a.nl; ++j) {
+    double g[3], tt[3];
+    long long f[3];
+    for (int i = 0; i < 3; ++i) {
+      g[i] = a.k[j] * (P[i] / r - a.e[i]) / a.dq;
+      const double fl = floor(g[i]);
+      f[i] = (long long)fl;
+      tt[i] = g[i] - fl;
+    }
+    double cz[2][2];
+    for (int di = 0; di < 2; ++di)
+      for (int dj = 0; dj < 2; ++dj) {
+        const double i0 = ewald_intensity<T>(a, f[0] + di, f[1] + dj, f[2]);
+        const double i1 = ewald_intensity<T>(a, f[0] + di, f[1] + dj, f[2] + 1);
+        cz[di][dj] = i0 + tt[2] * (i1 - i0);
+      }
+    const double c0 = cz[0][0] + tt[1] * (cz[0][1] - cz[0][0]);
+    const double c1 = cz[1][0] + tt[1] * (cz[1][1] - cz[1][0]);
+    acc += a.w[j] * (c0 + tt[0] * (c1 - c0));
+  }
+  a.image[t] = acc;
+}
+
+hipError_t launch_ewald(int prec, const EwaldArgs& a, hipStream_t s) {
+  const long long np = (long long)a.nu * a.nv;
+  if (prec == 0) hipLaunchKernelGGL(k_ewald<float>, dim3(nblk_of(np, 256)), dim3(256), 0, s, a);
+  else hipLaunchKernelGGL(k_ewald<double>, dim3(nblk_of(np, 256)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
 hipError_t launch_ensemble(int nboxes, int nbins, const double* mean, const double* sem, const double* w,
                            double* out_mean, double* out_sem, hipStream_t s) {
   hipLaunchKernelGGL(k_ensemble, dim3(nblk_of(nbins, 256)), dim3(256), 0, s, nboxes, nbins, mean, sem, w, out_mean, out_sem);

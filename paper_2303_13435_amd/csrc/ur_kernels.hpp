@@ -201,6 +201,20 @@ hipError_t launch_pass_y(int prec, int n, const YArgs& a, hipStream_t s);
 hipError_t launch_pass_x(int prec, int n, int mode, int dir, const XArgs& a, int nblocks, hipStream_t s);
 hipError_t launch_finalize(const FinArgs& a, hipStream_t s);
 hipError_t launch_merge(const MergeArgs& a, hipStream_t s);
+// Ewald-sphere image: per detector pixel, |F|^2 trilinear on the reciprocal
+// grid at q = k_j (s - e), averaged over wavelength nodes j
+struct EwaldArgs {
+  const void* spec;         // [kz][ky][kx], kz in [0, nkz)
+  int n, nkz, c2c;
+  double dq;                // 2 pi / (n voxel)
+  double e[3], du[3], dv[3];
+  double dist, pixel, cu, cv;
+  int nu, nv, nl;
+  double k[64], w[64];      // 2 pi / lambda_j and the node weights
+  double* image;            // [nv][nu]
+};
+hipError_t launch_ewald(int prec, const EwaldArgs& a, hipStream_t s);
+
 hipError_t launch_ensemble(int nboxes, int nbins, const double* mean, const double* sem, const double* w,
                            double* out_mean, double* out_sem, hipStream_t s);
 hipError_t launch_pass_x_adj(int prec, int n, const XAdjArgs& a, int nblocks, hipStream_t s);

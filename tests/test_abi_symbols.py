@@ -60,3 +60,32 @@ def test_version_and_errors_without_gpu(built_lib):
     assert built_lib.ur_plan_create(4096, 1.0, 0, 1, ctypes.byref(h)) == 2      # complex
     assert built_lib.ur_plan_create(2048, 1.0, 0, 1, ctypes.byref(h)) == 2      # complex above 1024
     assert not h.value
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """Every struct the binding passes by pointer has the header's size and
+    field offsets (a C program built with gcc from include/ultima.h prints
+    them)."""
+    import shutil
+    import subprocess
+    import paper_2303_13435_amd as ur
+    if shutil.which("gcc") is None:
+        pytest.skip("no gcc")
+    pairs = {"ur_cell": ur.UrCell, "ur_mask": ur.UrMask, "ur_zoom": ur.UrZoom, "ur_hist": ur.UrHist,
+             "ur_ewald": ur.UrEwald}
+    lines = ['#include <stdio.h>', '#include "ultima.h"', "int main(void) {"]
+    for cname, py in pairs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'  printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l}
+    for cname, py in pairs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)

@@ -350,3 +350,74 @@ def test_voxel_form_factor(ur, orc, prec):
     plan.simulate(cell, wl.mask, wl.zoom, h3)
     torch.cuda.synchronize()
     compare_bins(h3.numpy(), orc.simulate(wl), tol, "voxel form off", n=wl.n)
+
+
+# ---------------------------------------------------------------------------
+# Ewald-sphere detector image
+# ---------------------------------------------------------------------------
+
+EWALD_GEOS = {
+    "beam_z": W.detector(np.eye(3), pixel=5.0, nu=41, nv=33, cu=20, cv=16),
+    "tilted_spread": W.detector(W.rotation([0.3, -0.5, 0.8], 1.1), rel_spread=0.05, n_lambda=16,
+                                pixel=5.0, nu=37, nv=29, cu=11.0, cv=20.0),
+    "wide_offcentre": W.detector(W.rotation([1.0, 1.0, 0.0], 2.0), rel_spread=0.02, n_lambda=5,
+                                 distance=300.0, pixel=4.0, nu=64, nv=48, cu=-10.5, cv=60.25),
+}
+
+
+@pytest.mark.parametrize("geo_name", sorted(EWALD_GEOS))
+@pytest.mark.parametrize("prec,c2c,n", [(0, False, 64), (1, False, 64), (1, True, 32), (0, True, 32)])
+def test_ewald_image(ur, orc, geo_name, prec, c2c, n):
+    """ur_ewald_image on the transform of ur_fft3d_exec against the oracle's
+    image of the full FP64 spectrum: real boxes read the missing half of the
+    spectrum through F(-q) = F(q)*; the detectors reach several times past
+    the Nyquist frequency (periodic grid).  Bound per pixel: each spectrum
+    value is off by at most eps_F max|F| (2e-6 in FP32, 1e-13 in FP64, as
+    for the transform alone), so an interpolated intensity (weights summing
+    to 1) is off by at most 2 eps_F max|F| sqrt(I) + (eps_F max|F|)^2, plus
+    FP64 rounding of the interpolation (1e-14 max|F|^2)."""
+    import torch
+    geo = EWALD_GEOS[geo_name]
+    _say(f"ewald {geo_name} n={n} prec={prec} c2c={c2c}")
+    if c2c:
+        rng = np.random.default_rng(700 + n)
+        rho = rng.standard_normal((n, n, n)) + 1j * rng.standard_normal((n, n, n))
+        dt = torch.complex64 if prec == 0 else torch.complex128
+    else:
+        rho = W.random_density(700 + n, n)
+        dt = torch.float32 if prec == 0 else torch.float64
+    voxel = 1.0
+    F = orc.forward(rho)
+    ref = orc.ewald_image(F, voxel, geo)
+    plan = ur.Plan(n, voxel, prec, c2c=c2c)
+    spec = plan.fft3d(torch.as_tensor(rho, dtype=dt, device="cuda").contiguous())
+    img = plan.ewald_image(spec, geo)
+    torch.cuda.synchronize()
+    got = img.cpu().numpy()
+    fmax = float(np.max(np.abs(F)))
+    eps_f = 2e-6 if prec == 0 else 1e-13
+    bound = 2.0 * eps_f * fmax * np.sqrt(ref) + (eps_f * fmax) ** 2 + 1e-14 * fmax ** 2
+    ratio = np.abs(got - ref) / bound
+    _say(f"  max rel err {np.max(np.abs(got - ref) / ref):.3e}, max err/bound {ratio.max():.3f}")
+    assert np.all(ratio <= 1.0)
+
+
+def test_ewald_image_refusals(ur):
+    """Axes that are not orthonormal, a non-positive wavelength or pixel,
+    an out-of-range node count and a spectrum of the wrong size are refused
+    before any launch."""
+    import dataclasses
+    import torch
+    n = 16
+    plan = ur.Plan(n, 1.0, 1)
+    spec = torch.zeros((n // 2 + 1, n, n), dtype=torch.complex128, device="cuda")
+    good = W.detector(np.eye(3), nu=8, nv=8)
+    plan.ewald_image(spec, good)
+    for bad in (dataclasses.replace(good, du=(1.0, 0.1, 0.0)), dataclasses.replace(good, wavelength=0.0),
+                dataclasses.replace(good, pixel=-1.0), dataclasses.replace(good, rel_spread=0.1, n_lambda=65),
+                dataclasses.replace(good, rel_spread=0.5)):
+        with pytest.raises(ur.UltimaError, match="status 1"):
+            plan.ewald_image(spec, bad)
+    with pytest.raises(ur.UltimaError, match="elements"):
+        plan.ewald_image(spec[:4], good)
+    torch.cuda.synchronize()

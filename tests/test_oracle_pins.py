@@ -4,6 +4,7 @@ Each pin is chosen so that a plausible slip in the oracle (a dropped term, a
 wrong sign or index, a transposed operand, an off-by-one in a threshold)
 breaks at least one of them.  None of them re-types the oracle's own code.
 """
+import dataclasses
 import math
 import os
 
@@ -679,3 +680,113 @@ def test_voxel_form_of_a_cube_is_the_continuous_cube(oracle_lib, n, hw):
     assert np.allclose(sim["mean"][pop], ref["mean"][pop], rtol=1e-11, atol=1e-14 * np.nanmax(ref["mean"]))
     f = oracle.voxel_form(n)
     assert f[0, 0, 0] == 1.0 and abs(f[n // 2, 0, 0] - 2.0 / np.pi) <= 1e-15
+
+
+# ---------------------------------------------------------------------------
+# O16: Ewald-sphere detector image
+# ---------------------------------------------------------------------------
+
+def _affine_spectra(n, c0=None):
+    """Three spectra with |F|^2 = c0 + g_axis on the signed frequencies
+    (|g| < n/2): trilinear interpolation reproduces an affine field exactly
+    away from the wrap, so an image of each returns the grid coordinate of
+    every pixel along one axis."""
+    c0 = float(n) if c0 is None else c0
+    u = np.arange(n)
+    h = np.where(u < n // 2, u, u - n).astype(np.float64)
+    out = []
+    for ax in range(3):
+        shape = [1, 1, 1]
+        shape[ax] = n
+        I = c0 + np.broadcast_to(h.reshape(shape), (n, n, n))
+        out.append(np.sqrt(I).astype(np.complex128))
+    return c0, out
+
+
+def _grid_coords(n, voxel, geo):
+    import oracle
+    c0, Fs = _affine_spectra(n)
+    return np.stack([oracle.ewald_image(F, voxel, geo) - c0 for F in Fs], axis=-1)
+
+
+GEOS = [
+    ("identity", W.detector(np.eye(3), pixel=5.0, nu=41, nv=33, cu=20, cv=16)),
+    ("tilted", W.detector(W.rotation([0.3, -0.5, 0.8], 1.1), pixel=5.0, nu=37, nv=29, cu=11.0, cv=20.0)),
+]
+
+
+@pytest.mark.parametrize("name,geo", GEOS)
+def test_ewald_coordinates_lie_on_the_sphere(oracle_lib, name, geo):
+    """The grid coordinates the image samples (read back through affine
+    spectra) against the geometry of elastic scattering: q + k e has length
+    k (the Ewald sphere), |q| = (4 pi / lambda) sin(theta) with
+    tan(2 theta) = r / distance (Bragg), the component of q across the beam
+    points along the pixel's offset on the detector, and the beam centre
+    pixel samples q = 0."""
+    n, voxel = 128, 0.25
+    g = _grid_coords(n, voxel, geo)
+    assert np.max(np.abs(g)) < n // 2 - 1
+    dq = 2.0 * math.pi / (n * voxel)
+    q = g * dq
+    k = 2.0 * math.pi / geo.wavelength
+    e, du, dv = (np.asarray(v) for v in (geo.beam, geo.du, geo.dv))
+    assert np.max(np.abs(np.linalg.norm(q + k * e, axis=-1) - k)) <= 1e-9 * k
+    iv, iu = np.meshgrid(np.arange(geo.nv), np.arange(geo.nu), indexing="ij")
+    a, b = (iu - geo.cu) * geo.pixel, (iv - geo.cv) * geo.pixel
+    r = np.hypot(a, b)
+    theta = 0.5 * np.arctan2(r, geo.distance)
+    qn = np.linalg.norm(q, axis=-1)
+    assert np.max(np.abs(qn - 4.0 * math.pi * np.sin(theta) / geo.wavelength)) <= 1e-9 * qn.max()
+    qa, qb = q @ du, q @ dv
+    assert np.max(np.abs(qa * b - qb * a)) <= 1e-9 * qn.max() * r.max()
+    assert np.all(qa * a + qb * b >= -1e-12)
+    assert np.max(np.abs(q[int(geo.cv), int(geo.cu)])) <= 1e-12
+    assert qn.max() > 5 * dq
+
+
+@pytest.mark.parametrize("name,geo", GEOS)
+def test_ewald_interpolation_is_scipy_map_coordinates(oracle_lib, name, geo):
+    """The image of a random spectrum against scipy's order-1 spline (the
+    trilinear interpolant) of |F|^2 with periodic wrap, sampled at the
+    coordinates read back on a finer grid of the same frequency step: on the
+    32-point grid they run past the Nyquist frequency, so the wrap is
+    exercised in both directions."""
+    import oracle
+    from scipy.ndimage import map_coordinates
+    g = _grid_coords(128, 0.25, geo)
+    n = 32
+    assert np.max(np.abs(g)) > n / 2 + 1
+    rng = np.random.default_rng(16)
+    F = rng.standard_normal((n, n, n)) + 1j * rng.standard_normal((n, n, n))
+    img = oracle.ewald_image(F, 1.0, geo)
+    ref = map_coordinates(np.abs(F) ** 2, g.reshape(-1, 3).T, order=1, mode="grid-wrap").reshape(img.shape)
+    assert np.max(np.abs(img - ref)) <= 1e-12 * np.max(np.abs(F) ** 2)
+
+
+def test_ewald_wavelength_spread_is_the_gaussian_average(oracle_lib):
+    """With an affine |F|^2 the image is c0 + (g at lambda) E[lambda / lambda_j];
+    the 64-node rule against the truncated Gaussian integral of that
+    expectation (quadrature), which differs from 1 by about rel_spread^2.
+    No spread, or one node, reproduce the single wavelength, and the beam
+    centre gives |F(0)|^2 for any spread."""
+    import oracle
+    from scipy import integrate
+    geo0 = GEOS[1][1]
+    n, voxel, s = 128, 0.25, 0.05
+    c0, Fs = _affine_spectra(n)
+    geo = dataclasses.replace(geo0, rel_spread=s, n_lambda=64)
+    phi = lambda t: math.exp(-0.5 * t * t)
+    ek = (integrate.quad(lambda t: phi(t) / (1.0 + s * t), -3.0, 3.0, epsabs=0, epsrel=1e-12)[0]
+          / integrate.quad(phi, -3.0, 3.0, epsabs=0, epsrel=1e-12)[0])
+    assert ek - 1.0 > 2e-3
+    for F in Fs:
+        one = oracle.ewald_image(F, voxel, geo0) - c0
+        spread = oracle.ewald_image(F, voxel, geo) - c0
+        assert np.max(np.abs(spread - ek * one)) <= 3e-5 * np.max(np.abs(one))
+        for g2 in (dataclasses.replace(geo0, n_lambda=16), dataclasses.replace(geo, n_lambda=1)):
+            assert np.max(np.abs(oracle.ewald_image(F, voxel, g2) - c0 - one)) <= 1e-12 * np.max(np.abs(one))
+    rng = np.random.default_rng(3)
+    F = rng.standard_normal((16, 16, 16)) + 1j * rng.standard_normal((16, 16, 16))
+    geo = W.detector(np.eye(3), rel_spread=0.1, n_lambda=9, nu=9, nv=7, cu=4, cv=3)
+    img = oracle.ewald_image(F, 1.0, geo)
+    assert abs(img[3, 4] - abs(F[0, 0, 0]) ** 2) <= 1e-14 * abs(F[0, 0, 0]) ** 2

@@ -323,6 +323,41 @@ def volume_fractions(radii: Sequence[float], r0: float, width: float) -> np.ndar
     return phi / phi.sum()
 
 
+@dataclass(frozen=True)
+class Ewald:
+    """Geometry of a flat detector for an Ewald-sphere image: incident beam
+    direction and the detector's row/column directions (orthonormal, box
+    axes x, y, z), sample-detector distance and pixel pitch (same unit),
+    beam centre in pixels, pixel counts, and the wavelength (nm) with the
+    relative Gaussian spread of its distribution and the number of
+    wavelength nodes used for it."""
+    wavelength: float
+    rel_spread: float
+    n_lambda: int
+    beam: tuple
+    du: tuple
+    dv: tuple
+    distance: float
+    pixel: float
+    cu: float
+    cv: float
+    nu: int
+    nv: int
+
+
+def detector(R: np.ndarray, wavelength: float = 0.1, rel_spread: float = 0.0, n_lambda: int = 1,
+             distance: float = 1000.0, pixel: float = 0.5, nu: int = 200, nv: int = 160,
+             cu: Optional[float] = None, cv: Optional[float] = None) -> Ewald:
+    """A detector whose frame (beam, du, dv) is the columns (z, x, y) of the
+    rotation R: R = identity puts the beam along z, rows along x and columns
+    along y.  Beam centre in the middle unless given."""
+    R = np.asarray(R, dtype=np.float64)
+    col = lambda i: tuple(float(v) for v in R[:, i])
+    return Ewald(float(wavelength), float(rel_spread), int(n_lambda), col(2), col(0), col(1),
+                 float(distance), float(pixel), (nu - 1) / 2.0 if cu is None else float(cu),
+                 (nv - 1) / 2.0 if cv is None else float(cv), int(nu), int(nv))
+
+
 def c5(n: int = 4096) -> Workload:
     """Out-of-core box: 128-voxel cell with 200 atoms (seed 5), truncated
     octahedron inscribed in R = 1900 (scaled with n), 2048 log bins."""
