@@ -262,6 +262,28 @@ def other_configs(ur, W, torch, steps):
     return out
 
 
+def mixed_radix(ur, W, torch, steps):
+    """Boxes whose edge is not a power of two (the paper's 1000 / 2000 family):
+    the mixed-radix forward path (complex, one axis at a time) on the M1024
+    recipe scaled to the edge; ms per box, voxels/s and per-pass timing."""
+    out = {}
+    for n, prec in ((1000, ur.UR_F32), (1000, ur.UR_F64), (2000, ur.UR_F32)):
+        wl = W.mixed(n, prec, nbins=512)
+        plan = ur.Plan(wl.n, wl.voxel, prec, c2c=True)
+        plan.set_bins(wl.edges)
+        cell = ur.DeviceCell.from_host(wl.cell)
+        h = ur.Hist(wl.nbins)
+        step = lambda: plan.simulate(cell, wl.mask, wl.zoom, h)
+        ms, _ = time_steps(step, steps, 2, torch)
+        out[wl.name] = {"ms_per_box": round(ms, 4), "voxels_per_s": wl.n ** 3 / (ms * 1e-3),
+                        "prec": "f64" if prec == ur.UR_F64 else "f32", "transform": "c2c",
+                        "kernels": pass_timing(plan, step, steps, torch)}
+        del plan, step
+        torch.cuda.empty_cache()
+        note(f"mixed radix {wl.name} done")
+    return out
+
+
 def note(msg):
     """Progress on stderr (stdout carries only the JSON line)."""
     print(f"# {msg}", file=sys.stderr, flush=True)
@@ -445,6 +467,7 @@ def main():
         extras["ensemble_200"] = radii_batch(ur, W, torch, max(2, args.steps // 4), count=200, ensemble=True)
         # the other single-box configurations
         extras["configs"] = other_configs(ur, W, torch, args.steps)
+        extras["mixed_radix"] = mixed_radix(ur, W, torch, max(2, args.steps // 4))
         note("configs done")
         note("radii_batch done")
         # out-of-core: the same box streamed from pinned host memory

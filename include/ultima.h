@@ -126,12 +126,23 @@ typedef struct ur_plan ur_plan;
  * `prec`.  flags: UR_R2C or UR_C2C.  Allocates the plan's device tables
  * (twiddles) with hipMalloc; the large work buffers are either attached with
  * ur_plan_set_workspace or allocated lazily on first use.  Errors:
- * UR_ERR_INVALID for n not a power of two, a voxel that is not positive and
+ * UR_ERR_INVALID for n neither a power of two nor a mixed-radix edge (below), a voxel that is not positive and
  * finite, or an unknown precision; UR_ERR_UNSUPPORTED for n above 4096, for
  * n = 4096 in FP64 or complex, or for a complex (UR_C2C) plan above 1024.
  * A 4096^3 plan runs only ur_plan_set_bins, ur_rho_generate, ur_cell_synth
  * and the out-of-core path (ur_simulate_host and its workspace query); its
- * other calls fail with UR_ERR_UNSUPPORTED. */
+ * other calls fail with UR_ERR_UNSUPPORTED.
+ * Mixed-radix edges (boxes of the paper's 4000/16 = 250 family, Methodology,
+ * "Electron density generation"): n = 40, 80, 100, 160, 200, 250, 400, 500,
+ * 1000, 2000, 48, 96, 384, 768 or 1536 make a complex plan (UR_C2C required,
+ * else UR_ERR_UNSUPPORTED) whose transform runs one axis at a time through
+ * radix 2/4/8, 3 and 5 stages; its spectrum (ur_fft3d_exec, and the input of
+ * ur_intensity_bin and ur_ewald_image) is in natural order [kx][ky][kz].
+ * Such plans run ED-1 levels (zoom n1 = n, factor 1) through ur_simulate,
+ * ur_simulate_rho (complex density), ur_rho_generate, ur_fft3d_exec,
+ * ur_intensity_bin and ur_ewald_image; the adjoint, zoom levels and the
+ * voxel form factor fail with UR_ERR_UNSUPPORTED.  Other edges that are not
+ * powers of two fail with UR_ERR_INVALID. */
 ur_status ur_plan_create(int32_t n, double voxel, int32_t prec, uint32_t flags, ur_plan** out);
 void ur_plan_destroy(ur_plan* plan);
 

@@ -229,6 +229,19 @@ void or_zoom(int n1, int c, const double* cell, int kind, long long p0, long lon
 static void fft_rec(const cdouble* in, int len, int stride, cdouble* out, int sign)
 {
     if (len == 1) { out[0] = in[0]; return; }
+    if (len % 2) {
+        /* odd length (the 3^b 5^c part of a mixed-radix edge): the DFT sum
+         * itself, X_k = sum_j x_j w^(j k), with w^m = exp(sign 2 pi i m / len) */
+        cdouble* w = (cdouble*)malloc(sizeof(cdouble) * len);
+        for (int m = 0; m < len; ++m) w[m] = cexp(sign * 2.0 * M_PI * I * (double)m / (double)len);
+        for (int k = 0; k < len; ++k) {
+            cdouble acc = 0.0;
+            for (int j = 0; j < len; ++j) acc += in[(size_t)j * stride] * w[(long long)j * k % len];
+            out[k] = acc;
+        }
+        free(w);
+        return;
+    }
     int h = len / 2;
     fft_rec(in, h, 2 * stride, out, sign);               /* even samples -> out[0, h)   */
     fft_rec(in + stride, h, 2 * stride, out + h, sign);  /* odd samples  -> out[h, len) */

@@ -259,6 +259,7 @@ class Plan:
         self.h = h
         self.calls = 0          # library calls that touch this plan's workspace
         self.n, self.voxel, self.prec, self.c2c = int(n), float(voxel), int(prec), bool(c2c)
+        self.mixed = self.n & (self.n - 1) != 0      # mixed-radix edge: natural-order [kx][ky][kz] spectrum
         self.nbins = 0
         self._ws = None
         self._use_torch_ws = workspace
@@ -407,7 +408,8 @@ class Plan:
         return self.n if self.c2c else self.n // 2 + 1
 
     def fft3d(self, x, out=None, direction: int = -1, stream=None):
-        """eq. 1 forward (1/n^3) into the [kz][ky][kx] layout, or its inverse."""
+        """eq. 1 forward (1/n^3) into the [kz][ky][kx] layout ([kx][ky][kz] on a
+        mixed-radix plan, which needs no workspace), or its inverse."""
         torch = _torch()
         n = self.n
         if direction < 0:
@@ -420,7 +422,7 @@ class Plan:
             if out is None:
                 out = torch.empty((n, n, n), dtype=self.complex_dtype if self.c2c else self.real_dtype, device="cuda")
             _require(out, self.complex_dtype if self.c2c else self.real_dtype, n ** 3, "output")
-        if self.nbins == 0:
+        if self.nbins == 0 and not self.mixed:
             self._attach(self.workspace_size(1))
         self.calls += 1
         _check(lib().ur_fft3d_exec(self.h, _ptr(x), _ptr(out), int(direction), _stream(stream)), "ur_fft3d_exec")

@@ -58,6 +58,7 @@ struct ur_plan {
   int prec = 0;
   unsigned flags = 0;
   int nkz = 0;
+  bool mixed = false;        // edge 2^a 3^b 5^c, not a power of two (complex, natural-order spectrum)
   size_t cs = 0;             // bytes per complex element
   size_t rs = 0;             // bytes per real element
   int device = 0;
@@ -171,6 +172,20 @@ static Layout layout_incore(const ur_plan* p, int nbins) {
   L.part = align256(L.B + (size_t)p->nkz * n * n * p->cs);
   L.mom = align256(L.part + (size_t)x_blocks_for(nbins) * (2 * (size_t)std::max(nbins, 1) + 1) * 8);
   L.f0 = align256(L.mom + n * (size_t)ntiles(p) * 16);
+  L.total = align256(L.f0 + 64 + 256 * 8);
+  return L;
+}
+
+// mixed-radix layout: the complex box (transformed in place), block
+// partials, F(0) and the per-pencil moments
+static Layout layout_mixed(const ur_plan* p, int nbins) {
+  Layout L;
+  const size_t n = p->n;
+  L.A = 0;
+  L.B = 0;
+  L.part = align256(n * n * n * p->cs);
+  L.mom = align256(L.part + (size_t)kMaxXBlocks * (2 * (size_t)std::max(nbins, 1) + 1) * 8);
+  L.f0 = align256(L.mom + n * n * 16);
   L.total = align256(L.f0 + 64 + 256 * 8);
   return L;
 }
@@ -356,11 +371,15 @@ const char* ur_version(void) { return "ultima-gfx950 0.1"; }
 ur_status ur_plan_create(int32_t n, double voxel, int32_t prec, uint32_t flags, ur_plan** out) {
   if (!out) return fail(UR_ERR_INVALID, "out is null");
   *out = nullptr;
-  if (!is_pow2(n) || n < 16) return fail(UR_ERR_INVALID, "n = %d must be a power of two >= 16", n);
+  const bool mixed = !is_pow2(n) && mr_size(n);
+  if (!mixed && (!is_pow2(n) || n < 16))
+    return fail(UR_ERR_INVALID, "n = %d must be a power of two >= 16 or one of the mixed-radix edges", n);
+  if (mixed && !(flags & UR_C2C))
+    return fail(UR_ERR_UNSUPPORTED, "n = %d: mixed-radix boxes run complex transforms (UR_C2C)", n);
   if (n > kMaxOutOfCore) return fail(UR_ERR_UNSUPPORTED, "n = %d: boxes run up to %d^3", n, kMaxOutOfCore);
   if (n > kMaxInCore && (prec != UR_F32 || (flags & UR_C2C)))
     return fail(UR_ERR_UNSUPPORTED, "n = %d: boxes above %d^3 are FP32 real (UR_F32, no UR_C2C)", n, kMaxInCore);
-  if (n > 1024 && (flags & UR_C2C)) return fail(UR_ERR_UNSUPPORTED, "complex transforms run up to 1024^3");
+  if (n > 1024 && (flags & UR_C2C) && !mixed) return fail(UR_ERR_UNSUPPORTED, "complex transforms run up to 1024^3");
   if (!(voxel > 0.0) || !isfinite(voxel)) return fail(UR_ERR_INVALID, "voxel must be positive");
   if (prec != UR_F32 && prec != UR_F64) return fail(UR_ERR_INVALID, "prec must be UR_F32 or UR_F64");
   if (flags & ~1u) return fail(UR_ERR_INVALID, "unknown flags 0x%x", flags);
@@ -371,6 +390,7 @@ ur_status ur_plan_create(int32_t n, double voxel, int32_t prec, uint32_t flags, 
   p->prec = prec;
   p->flags = flags;
   p->nkz = (flags & UR_C2C) ? n : n / 2 + 1;
+  p->mixed = mixed;
   p->rs = prec == UR_F32 ? 4 : 8;
   p->cs = 2 * p->rs;
   if (hipGetDevice(&p->device) != hipSuccess) { delete p; return fail(UR_ERR_HIP, "hipGetDevice failed"); }
@@ -411,7 +431,7 @@ ur_status ur_plan_workspace_size(const ur_plan* p, int32_t nbins, size_t* bytes)
   if (!p || !bytes) return fail(UR_ERR_INVALID, "null argument");
   if (nbins < 1) return fail(UR_ERR_INVALID, "nbins must be >= 1");
   UR_TRY(need_in_core(p));
-  *bytes = layout_incore(p, nbins).total;
+  *bytes = p->mixed ? layout_mixed(p, nbins).total : layout_incore(p, nbins).total;
   return UR_OK;
 }
 
@@ -596,7 +616,11 @@ static ur_status check_level(const ur_plan* p, const ur_cell* cell, const ur_mas
   if (!m || !z) return fail(UR_ERR_INVALID, "mask and zoom must be non-null");
   if (m->kind < 0 || m->kind > 3) return fail(UR_ERR_INVALID, "mask kind %d unknown", m->kind);
   if (m->p0 > (1ll << 40) || m->p1 > (1ll << 40)) return fail(UR_ERR_INVALID, "mask parameters too large");
-  if (!is_pow2(z->n1) || !is_pow2(z->factor)) return fail(UR_ERR_INVALID, "zoom n1 and factor must be powers of two");
+  if (p->mixed) {
+    if (z->n1 != p->n || z->factor != 1) return fail(UR_ERR_UNSUPPORTED, "mixed-radix boxes run ED-1 only (zoom n1 = n, factor 1)");
+  } else if (!is_pow2(z->n1) || !is_pow2(z->factor)) {
+    return fail(UR_ERR_INVALID, "zoom n1 and factor must be powers of two");
+  }
   if (z->factor > 1 && z->factor > z->n1 / 2) return fail(UR_ERR_INVALID, "zoom factor %d too large for n1 = %d", z->factor, z->n1);
   if (z->n1 / z->factor > p->n) return fail(UR_ERR_INVALID, "reduced particle region %d exceeds the box %d", z->n1 / z->factor, p->n);
   if (z->factor > 1 && cell->c > z->n1) return fail(UR_ERR_INVALID, "cell larger than the ED-1 grid");
@@ -718,6 +742,53 @@ static ur_status run_y_x(ur_plan* p, const FwdGeom& g, char* A, char* B, const L
   return UR_OK;
 }
 
+// mixed-radix forward: the three axis passes in place on S (z from `src`,
+// with moments when asked), |F|^2 binning and the finalize
+static ur_status mr_transform(ur_plan* p, const void* src, void* S, int dir, double* mom, hipStream_t s) {
+  const int n = p->n;
+  MrArgs a{};
+  a.tw = p->tw; a.dst = S; a.mom = mom;
+  a.src = src; a.scale = 1.0;
+  {
+    PassTimer tm(p, P_Z, s);
+    UR_HIP(launch_mr_axis(p->prec, n, 2, dir, a, s));
+  }
+  a.src = S; a.mom = nullptr;
+  {
+    PassTimer tm(p, P_Y, s);
+    UR_HIP(launch_mr_axis(p->prec, n, 1, dir, a, s));
+  }
+  a.scale = dir < 0 ? 1.0 / ((double)n * n * n) : 1.0;
+  {
+    PassTimer tm(p, P_X, s);
+    UR_HIP(launch_mr_axis(p->prec, n, 0, dir, a, s));
+  }
+  const double box = (double)n * n * n * p->cs;
+  p->pass_bytes[P_Z] = 2.0 * box;
+  p->pass_bytes[P_Y] = 2.0 * box;
+  p->pass_bytes[P_X] = 2.0 * box;
+  return UR_OK;
+}
+
+static ur_status mr_bin(ur_plan* p, const void* S, const Layout& lay, const ur_hist* h, int nzb, hipStream_t s) {
+  MrBinArgs b{};
+  b.S = S; b.n = p->n; b.nbins = p->nbins; b.U = p->dU; b.lut = p->dLut; b.nlut = p->nlut; b.iscale = 1.0;
+  b.part = (double*)(p->ws + lay.part); b.f0 = (double*)(p->ws + lay.f0);
+  const int nblk = (int)std::min<long long>((long long)p->n * p->n, kMaxXBlocks);
+  {
+    PassTimer tm(p, P_FIN, s);
+    UR_HIP(launch_mr_bin(p->prec, b, nblk, s));
+    FinArgs fa{};
+    fa.part = b.part; fa.nblk = nblk; fa.nbins = p->nbins;
+    fa.mom = nzb > 0 ? (const double*)(p->ws + lay.mom) : nullptr; fa.nzb = nzb;
+    fa.mpart = (double*)(p->ws + lay.f0 + 64); fa.f0 = b.f0; fa.cnt = p->dCount; fa.sum = h->sum; fa.sumsq = h->sumsq;
+    fa.count = h->count; fa.totals = h->totals; fa.mean = h->mean; fa.sem = h->sem;
+    UR_HIP(launch_finalize(fa, s));
+  }
+  p->pass_bytes[P_FIN] = (double)p->n * p->n * p->n * p->cs + (double)nblk * (2.0 * p->nbins + 1.0) * 16.0;
+  return UR_OK;
+}
+
 extern "C" {
 
 ur_status ur_cell_synth(ur_plan* p, const ur_cell* cell, double* cell_out, void* stream) {
@@ -764,6 +835,22 @@ ur_status ur_simulate(ur_plan* p, const ur_cell* cell, const ur_mask* mask, cons
   ZArgs rot_args{};
   UR_TRY(set_rotation(p, cell, zoom, rot_args));
   hipStream_t s = (hipStream_t)stream;
+  if (p->mixed) {
+    if (p->dSinc) return fail(UR_ERR_UNSUPPORTED, "mixed-radix boxes run without the voxel form factor");
+    Layout lay = layout_mixed(p, p->nbins);
+    UR_TRY(ensure_ws(p, lay.total, s));
+    CellTables t;
+    {
+      PassTimer tm(p, P_CELL, s);                    // cell synthesis and the density of the box
+      UR_TRY(prepare_cell(p, cell, 1, t, s));
+      ZArgs za = rot_args;
+      za.cellT = t.cellT; za.cb = t.cb; za.pre = t.pre; za.L = g.L; za.m = g.m; za.cbn = t.cbn;
+      UR_HIP(launch_mr_gen(p->prec, p->n, za, p->ws + lay.A, (double*)(p->ws + lay.mom), s));
+    }
+    p->pass_bytes[P_CELL] = (double)p->n * p->n * p->n * p->cs + 16.0 * p->n * p->n;
+    UR_TRY(mr_transform(p, p->ws + lay.A, p->ws + lay.A, -1, nullptr, s));
+    return mr_bin(p, p->ws + lay.A, lay, h, p->n * p->n, s);
+  }
   Layout lay = layout_incore(p, p->nbins);
   UR_TRY(ensure_ws(p, lay.total, s));
   CellTables t;
@@ -810,6 +897,13 @@ ur_status ur_simulate_rho(ur_plan* p, const void* rho, const ur_hist* h, void* s
   if (p->nbins < 1) return fail(UR_ERR_STATE, "no bins set on the plan");
   UR_TRY(check_hist(h));
   hipStream_t s = (hipStream_t)stream;
+  if (p->mixed) {
+    if (p->dSinc) return fail(UR_ERR_UNSUPPORTED, "mixed-radix boxes run without the voxel form factor");
+    Layout lay = layout_mixed(p, p->nbins);
+    UR_TRY(ensure_ws(p, lay.total, s));
+    UR_TRY(mr_transform(p, rho, p->ws + lay.A, -1, (double*)(p->ws + lay.mom), s));
+    return mr_bin(p, p->ws + lay.A, lay, h, mr_axis_blocks(p->prec, p->n, 2), s);
+  }
   Layout lay = layout_incore(p, p->nbins);
   UR_TRY(ensure_ws(p, lay.total, s));
   FwdGeom g{};
@@ -837,6 +931,7 @@ ur_status ur_fft3d_exec(ur_plan* p, const void* in, void* out, int32_t dir, void
   if (dir > 0 && p->n > 1024) return fail(UR_ERR_UNSUPPORTED, "inverse transforms run up to 1024^3");
   if (in == out) return fail(UR_ERR_INVALID, "in and out must differ");
   hipStream_t s = (hipStream_t)stream;
+  if (p->mixed) return mr_transform(p, in, out, dir, nullptr, s);
   Layout lay = layout_incore(p, std::max(p->nbins, 1));
   UR_TRY(ensure_ws(p, lay.total, s));
   const int n = p->n, c2c = (p->flags & UR_C2C) ? 1 : 0;
@@ -878,6 +973,12 @@ ur_status ur_intensity_bin(ur_plan* p, const void* spectrum, const ur_hist* h, v
   if (p->nbins < 1) return fail(UR_ERR_STATE, "no bins set on the plan");
   UR_TRY(check_hist(h));
   hipStream_t s = (hipStream_t)stream;
+  if (p->mixed) {
+    if (p->dSinc) return fail(UR_ERR_UNSUPPORTED, "mixed-radix boxes run without the voxel form factor");
+    Layout lay = layout_mixed(p, p->nbins);
+    UR_TRY(ensure_ws(p, lay.total, s));
+    return mr_bin(p, spectrum, lay, h, 0, s);
+  }
   Layout lay = layout_incore(p, p->nbins);
   UR_TRY(ensure_ws(p, lay.total, s));
   const int n = p->n;
@@ -1072,6 +1173,7 @@ static ur_status adjoint_run(ur_plan* p, const void* rho, const ur_cell* cell, c
   if (grad_amp && !cell) return fail(UR_ERR_INVALID, "grad_amp needs the cell description");
   if (cell && cell->rot) return fail(UR_ERR_UNSUPPORTED, "the adjoint runs for lattices aligned with the box (rot = NULL)");
   if (p->dSinc) return fail(UR_ERR_UNSUPPORTED, "the adjoint runs without the voxel form factor");
+  if (p->mixed) return fail(UR_ERR_UNSUPPORTED, "the adjoint runs on power-of-two boxes");
   if (!grad_rho && !grad_amp) return UR_OK;
   if (p->n > 1024) return fail(UR_ERR_UNSUPPORTED, "the adjoint runs up to 1024^3");
   hipStream_t s = (hipStream_t)stream;
@@ -1195,7 +1297,7 @@ ur_status ur_ewald_image(ur_plan* p, const void* spectrum, const ur_ewald* geo, 
       if (fabs(dot(vs[i], vs[j]) - (i == j ? 1.0 : 0.0)) > 1e-9)
         return fail(UR_ERR_INVALID, "beam, du and dv must be orthonormal");
   EwaldArgs a{};
-  a.spec = spectrum; a.n = p->n; a.nkz = p->nkz; a.c2c = (p->flags & UR_C2C) ? 1 : 0;
+  a.spec = spectrum; a.n = p->n; a.nkz = p->nkz; a.c2c = (p->flags & UR_C2C) ? 1 : 0; a.natural = p->mixed ? 1 : 0;
   a.dq = 2.0 * M_PI / ((double)p->n * p->voxel);
   for (int i = 0; i < 3; ++i) { a.e[i] = geo->beam[i]; a.du[i] = geo->du[i]; a.dv[i] = geo->dv[i]; }
   a.dist = geo->distance; a.pixel = geo->pixel; a.cu = geo->cu; a.cv = geo->cv;

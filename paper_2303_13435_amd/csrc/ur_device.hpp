@@ -105,6 +105,44 @@ template <typename T, int DIR> struct DFT<T, 1, DIR> {
   static __device__ __forceinline__ void run(cx<T>*) {}
 };
 
+// i * a
+template <typename T> __device__ __forceinline__ cx<T> mul_i(cx<T> a) { return mk(-a.y, a.x); }
+
+// DFT of size 3 from its definition: with w = exp(DIR 2 pi i / 3),
+// X_1,2 = v0 - (v1 + v2)/2 +- DIR i sin(2 pi/3) (v1 - v2).
+template <typename T, int DIR> struct DFT<T, 3, DIR> {
+  static __device__ __forceinline__ void run(cx<T>* v) {
+    const T s = (T)0.86602540378443864676 * (T)DIR;      // DIR sin(2 pi / 3)
+    const cx<T> a = v[1] + v[2], b = v[1] - v[2];
+    const cx<T> m = v[0] - scale(a, (T)0.5);
+    const cx<T> t = mul_i(scale(b, s));
+    v[0] = v[0] + a;
+    v[1] = m + t;
+    v[2] = m - t;
+  }
+};
+
+// DFT of size 5 from its definition, pairing r with 5 - r: with
+// a_j = v_j + v_{5-j}, b_j = v_j - v_{5-j} and theta = 2 pi / 5,
+// X_1,4 = v0 + cos(theta) a1 + cos(2 theta) a2 +- DIR i (sin(theta) b1 + sin(2 theta) b2),
+// X_2,3 = v0 + cos(2 theta) a1 + cos(theta) a2 +- DIR i (sin(2 theta) b1 - sin(theta) b2).
+template <typename T, int DIR> struct DFT<T, 5, DIR> {
+  static __device__ __forceinline__ void run(cx<T>* v) {
+    const T c1 = (T)0.30901699437494742410, c2 = (T)-0.80901699437494742410;
+    const T s1 = (T)0.95105651629515357212 * (T)DIR, s2 = (T)0.58778525229247312917 * (T)DIR;
+    const cx<T> a1 = v[1] + v[4], b1 = v[1] - v[4], a2 = v[2] + v[3], b2 = v[2] - v[3];
+    const cx<T> m1 = v[0] + scale(a1, c1) + scale(a2, c2);
+    const cx<T> m2 = v[0] + scale(a1, c2) + scale(a2, c1);
+    const cx<T> t1 = mul_i(scale(b1, s1) + scale(b2, s2));
+    const cx<T> t2 = mul_i(scale(b1, s2) - scale(b2, s1));
+    v[0] = v[0] + a1 + a2;
+    v[1] = m1 + t1;
+    v[4] = m1 - t1;
+    v[2] = m2 + t2;
+    v[3] = m2 - t2;
+  }
+};
+
 // Padded LDS index: one spare element every 16 breaks the power-of-two
 // strides of the Stockham write pattern across LDS banks.
 __device__ __forceinline__ int pad(int i) { return i + (i >> 4); }
@@ -114,10 +152,21 @@ template <int N> struct Padded { static constexpr int size = N + N / 16; };
 // N = 1024 a column sits in one wavefront (G <= 64); N = 2048 and 4096 take
 // two and four whole wavefronts (G = 128, 256), with 16 elements per lane as
 // at 1024.
+//
+// Lengths N = 2^a 3^b 5^c that are not powers of two (mixed radix) take
+// power-of-two radices of at most P = min(2^a, 8), then radix 3, then radix
+// 5; E = P (x 3 if b > 0) (x 5 if c > 0) so that every radix divides it, and
+// the column lies in one wavefront (G <= 64, not necessarily a power of two).
+template <int N> struct Pow2 { static constexpr bool v = (N & (N - 1)) == 0; };
+constexpr int pow2_part(int n) { return n & -n; }
+template <int N> struct Mixed {
+  static constexpr int P = pow2_part(N) < 8 ? pow2_part(N) : 8;
+  static constexpr int E = P * (N % 3 == 0 ? 3 : 1) * (N % 5 == 0 ? 5 : 1);
+};
 template <int N> struct Geo {
-  static constexpr int E = N <= 16 ? N : (N == 512 ? 8 : 16);
+  static constexpr int E = Pow2<N>::v ? (N <= 16 ? N : (N == 512 ? 8 : 16)) : Mixed<N>::E;
   static constexpr int G = N / E;
-  static_assert(G >= 1 && (G <= 64 || G == 128 || G == 256), "column group: part of one wavefront or whole ones");
+  static_assert(G * E == N && G >= 1 && (G <= 64 || G == 128 || G == 256), "column group: part of one wavefront or whole ones");
 };
 
 // Ordering of the LDS accesses of the lanes that share a column: the
@@ -132,8 +181,14 @@ __device__ __forceinline__ void col_sync() {
 // radix of the stage with sub-transform length L: at most 16 and at most the
 // per-lane element count, so each lane runs whole butterflies
 template <int N> constexpr int radix_at(int L) {
-  constexpr int cap = Geo<N>::E < 16 ? Geo<N>::E : 16;
-  return (N / L) < cap ? (N / L) : cap;
+  if constexpr (Pow2<N>::v) {
+    constexpr int cap = Geo<N>::E < 16 ? Geo<N>::E : 16;
+    return (N / L) < cap ? (N / L) : cap;
+  } else {
+    const int m = N / L, p2 = pow2_part(m);
+    if (p2 > 1) return p2 < Mixed<N>::P ? p2 : Mixed<N>::P;
+    return m % 3 == 0 ? 3 : 5;
+  }
 }
 template <int N, int L> struct Radix { static constexpr int r = radix_at<N>(L); };
 
@@ -188,9 +243,15 @@ __device__ __forceinline__ void stage_lds(cx<T>* s, int g, const cx<T>* __restri
       }
     }
     DFT<T, R, DIR>::run(v[i]);
-    cx<T>* out = s + pad((b / L) * L * R + j);
+    if constexpr (Pow2<N>::v) {
+      cx<T>* out = s + pad((b / L) * L * R + j);
 #pragma unroll
-    for (int r = 0; r < R; ++r) out[(r * L) + ((r * L) >> 4)] = v[i][r];
+      for (int r = 0; r < R; ++r) out[(r * L) + ((r * L) >> 4)] = v[i][r];
+    } else {                                       // offsets r L may carry into the next 16-block
+      const int o = (b / L) * L * R + j;
+#pragma unroll
+      for (int r = 0; r < R; ++r) s[pad(o + r * L)] = v[i][r];
+    }
   }
   col_sync<G>();
 }
@@ -214,9 +275,14 @@ __device__ __forceinline__ void fft_column(cx<T>* s, int g, const cx<T>* __restr
   for (int i = 0; i < NB; ++i) {
     const int b = g + G * i;
     DFT<T, R, DIR>::run(v + i * R);
-    cx<T>* out = s + pad(b * R);                       // R | 16: the R outputs share one 16-block
+    if constexpr (Pow2<N>::v) {
+      cx<T>* out = s + pad(b * R);                     // R | 16: the R outputs share one 16-block
 #pragma unroll
-    for (int r = 0; r < R; ++r) out[r] = v[i * R + r];
+      for (int r = 0; r < R; ++r) out[r] = v[i * R + r];
+    } else {
+#pragma unroll
+      for (int r = 0; r < R; ++r) s[pad(b * R + r)] = v[i * R + r];
+    }
   }
   col_sync<G>();
   stages_from<T, N, R, DIR>(s, g, tw);

@@ -1796,6 +1796,234 @@ hipError_t launch_finalize(const FinArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// mixed-radix boxes (n = 2^a 3^b 5^c, not a power of two)
+// A block holds TL whole lines of one axis in LDS (padded columns), every
+// line transformed by G lanes in a slot of GP = 2^ceil(log2 G) lanes (so a
+// line never straddles two wavefronts), then written back in place.  Lines
+// along z are contiguous, so a tile is TL n consecutive elements; lines
+// along y and x are taken TL consecutive z at a time, so every load and
+// store is a TL-element contiguous segment.
+// ---------------------------------------------------------------------------
+constexpr int floor_pow2(int v) { int p = 1; while (2 * p <= v) p *= 2; return p; }
+constexpr int ceil_pow2(int v) { int p = 1; while (p < v) p *= 2; return p; }
+
+template <typename T, int N> struct MrCfg {
+  static constexpr int G = Geo<N>::G, GP = ceil_pow2(G);
+  static constexpr int PS = Padded<N>::size;
+  static constexpr int by_lds = (144 * 1024) / (PS * (int)sizeof(cx<T>));
+  static constexpr int TL0 = 64 < 1024 / GP ? 64 : 1024 / GP;
+  static constexpr int TL = floor_pow2(TL0 < by_lds ? TL0 : (by_lds > 0 ? by_lds : 1));
+  static constexpr int threads = TL * GP < 64 ? 64 : TL * GP;
+  static_assert(G <= 64, "mixed-radix lines lie in one wavefront");
+  static_assert(threads % 64 == 0 && TL * PS * (int)sizeof(cx<T>) <= 144 * 1024, "tile exceeds the LDS");
+};
+
+template <typename T, int N, int DIR, int AXIS>
+__global__ void __launch_bounds__((MrCfg<T, N>::threads)) k_mr_axis(MrArgs a) {
+  using C = MrCfg<T, N>;
+  constexpr int G = C::G, GP = C::GP, TL = C::TL, PS = C::PS, NT = C::threads;
+  constexpr int E = Geo<N>::E, R0 = Radix<N, 1>::r, NB0 = E / R0;
+  __shared__ cx<T> lds[TL * PS];
+  const cx<T>* __restrict__ src = (const cx<T>*)a.src;
+  cx<T>* __restrict__ dst = (cx<T>*)a.dst;
+  const int t = threadIdx.x;
+  size_t base;
+  size_t es;
+  int nl;
+  if constexpr (AXIS == 2) {
+    const long long l0 = (long long)blockIdx.x * TL;
+    const long long left = (long long)N * N - l0;
+    nl = left < TL ? (int)left : TL;
+    base = (size_t)l0 * N;
+    es = 1;
+  } else {
+    constexpr int nzt = (N + TL - 1) / TL;
+    const int o = blockIdx.x / nzt, z0 = (blockIdx.x % nzt) * TL;
+    nl = N - z0 < TL ? N - z0 : TL;
+    base = AXIS == 1 ? (size_t)o * N * N + z0 : (size_t)o * N + z0;
+    es = AXIS == 1 ? (size_t)N : (size_t)N * N;
+  }
+  double s1 = 0.0, s2 = 0.0;
+  if constexpr (AXIS == 2) {
+    for (int i = t; i < nl * N; i += NT) {
+      const cx<T> v = src[base + i];
+      lds[(i / N) * PS + pad(i % N)] = v;
+      if (a.mom) { s1 += (double)v.x; s2 += (double)v.x * v.x + (double)v.y * v.y; }
+    }
+  } else {
+    for (int i = t; i < N * TL; i += NT) {
+      const int e = i / TL, l = i % TL;
+      if (l < nl) {
+        const cx<T> v = src[base + e * es + l];
+        lds[l * PS + pad(e)] = v;
+        if (a.mom) { s1 += (double)v.x; s2 += (double)v.x * v.x + (double)v.y * v.y; }
+      }
+    }
+  }
+  if (a.mom) {                                       // fixed-order block sum of the loaded values
+    __shared__ double w1[NT / 64], w2[NT / 64];
+    for (int o = 32; o > 0; o >>= 1) { s1 += __shfl_down(s1, o, 64); s2 += __shfl_down(s2, o, 64); }
+    if (t % 64 == 0) { w1[t / 64] = s1; w2[t / 64] = s2; }
+    __syncthreads();
+    if (t == 0) {
+      double u1 = 0.0, u2 = 0.0;
+      for (int i = 0; i < NT / 64; ++i) { u1 += w1[i]; u2 += w2[i]; }
+      a.mom[2 * (size_t)blockIdx.x] = u1;
+      a.mom[2 * (size_t)blockIdx.x + 1] = u2;
+    }
+  }
+  __syncthreads();
+  const int l = t / GP, g = t % GP;
+  if (l < nl && g < G) {
+    cx<T>* col = lds + l * PS;
+    cx<T> v[E];
+#pragma unroll
+    for (int i = 0; i < NB0; ++i)
+#pragma unroll
+      for (int r = 0; r < R0; ++r) v[i * R0 + r] = col[pad(first_index<N>(g, i, r))];
+    wave_sync();
+    fft_column<T, N, DIR>(col, g, (const cx<T>*)a.tw, v);
+  }
+  __syncthreads();
+  const T sc = (T)a.scale;
+  if constexpr (AXIS == 2) {
+    for (int i = t; i < nl * N; i += NT) dst[base + i] = scale(lds[(i / N) * PS + pad(i % N)], sc);
+  } else {
+    for (int i = t; i < N * TL; i += NT) {
+      const int e = i / TL, l2 = i % TL;
+      if (l2 < nl) dst[base + e * es + l2] = scale(lds[l2 * PS + pad(e)], sc);
+    }
+  }
+}
+
+template <int N> static constexpr int mr_blocks_t(int prec, int axis) {
+  const int tl = prec == 0 ? MrCfg<float, N>::TL : MrCfg<double, N>::TL;
+  return axis == 2 ? (int)(((long long)N * N + tl - 1) / tl) : N * ((N + tl - 1) / tl);
+}
+
+template <typename T, int N>
+static hipError_t mr_axis_t(int axis, int dir, const MrArgs& a, hipStream_t s) {
+  const dim3 grid(mr_blocks_t<N>(sizeof(T) == 4 ? 0 : 1, axis)), blk(MrCfg<T, N>::threads);
+  if (dir < 0) {
+    if (axis == 0) hipLaunchKernelGGL((k_mr_axis<T, N, -1, 0>), grid, blk, 0, s, a);
+    else if (axis == 1) hipLaunchKernelGGL((k_mr_axis<T, N, -1, 1>), grid, blk, 0, s, a);
+    else hipLaunchKernelGGL((k_mr_axis<T, N, -1, 2>), grid, blk, 0, s, a);
+  } else {
+    if (axis == 0) hipLaunchKernelGGL((k_mr_axis<T, N, 1, 0>), grid, blk, 0, s, a);
+    else if (axis == 1) hipLaunchKernelGGL((k_mr_axis<T, N, 1, 1>), grid, blk, 0, s, a);
+    else hipLaunchKernelGGL((k_mr_axis<T, N, 1, 2>), grid, blk, 0, s, a);
+  }
+  return hipGetLastError();
+}
+
+// the compiled mixed-radix edges: the 2^a 5^3 family of the paper's boxes and
+// zoom levels (250 ... 2000) with smaller members for tests, and 2^a 3
+#define UR_MR_SIZES(X) X(40) X(80) X(100) X(160) X(200) X(250) X(400) X(500) X(1000) X(2000) \
+                       X(48) X(96) X(384) X(768) X(1536)
+
+bool mr_size(int n) {
+  switch (n) {
+#define UR_MR_CASE(NN) case NN:
+    UR_MR_SIZES(UR_MR_CASE) return true;
+#undef UR_MR_CASE
+    default: return false;
+  }
+}
+
+int mr_axis_blocks(int prec, int n, int axis) {
+  switch (n) {
+#define UR_MR_CASE(NN) case NN: return mr_blocks_t<NN>(prec, axis);
+    UR_MR_SIZES(UR_MR_CASE)
+#undef UR_MR_CASE
+    default: return 0;
+  }
+}
+
+hipError_t launch_mr_axis(int prec, int n, int axis, int dir, const MrArgs& a, hipStream_t s) {
+  switch (n) {
+#define UR_MR_CASE(NN) case NN: return prec == 0 ? mr_axis_t<float, NN>(axis, dir, a, s) : mr_axis_t<double, NN>(axis, dir, a, s);
+    UR_MR_SIZES(UR_MR_CASE)
+#undef UR_MR_CASE
+    default: return hipErrorNotSupported;
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_mr_gen(ZArgs a, int n, cx<T>* __restrict__ S, double* __restrict__ mom) {
+  __shared__ double r1[256], r2[256];
+  const long long t = blockIdx.x;                 // one block per pencil
+  const long long X = t / n, Y = t % n;
+  Pencil<T> p;
+  p.init(a, X, Y);
+  cx<T>* row = S + t * n;
+  double s1 = 0.0, s2 = 0.0;
+  for (int z = threadIdx.x; z < n; z += 256) {
+    const T v = a.rotated ? p.value_rot(a, z) : p.value(a, z);
+    row[z] = mk(v, (T)0);
+    s1 += (double)v;
+    s2 += (double)v * (double)v;
+  }
+  r1[threadIdx.x] = s1;
+  r2[threadIdx.x] = s2;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double u1 = 0.0, u2 = 0.0;
+    for (int i = 0; i < 256; ++i) { u1 += r1[i]; u2 += r2[i]; }
+    mom[2 * t] = u1;
+    mom[2 * t + 1] = u2;
+  }
+}
+
+hipError_t launch_mr_gen(int prec, int n, const ZArgs& za, void* S, double* mom, hipStream_t s) {
+  const unsigned nn = (unsigned)((long long)n * n);
+  if (prec == 0) hipLaunchKernelGGL(k_mr_gen<float>, dim3(nn), dim3(256), 0, s, za, n, (cx<float>*)S, mom);
+  else hipLaunchKernelGGL(k_mr_gen<double>, dim3(nn), dim3(256), 0, s, za, n, (cx<double>*)S, mom);
+  return hipGetLastError();
+}
+
+// |F|^2 of a full complex spectrum into integer-threshold |Q| bins: blocks
+// stride over (kx, ky) rows, threads over kz; per-block partials of the
+// sums and sums of squares (LDS FP64 atomics) and of the total intensity.
+template <typename T>
+__global__ void __launch_bounds__(256) k_mr_bin(MrBinArgs a) {
+  extern __shared__ double hist[];                 // 2 nbins + 1
+  const int nv = 2 * a.nbins + 1;
+  for (int i = threadIdx.x; i < nv; i += 256) hist[i] = 0.0;
+  __syncthreads();
+  const cx<T>* __restrict__ S = (const cx<T>*)a.S;
+  const int n = a.n;
+  double tot = 0.0;
+  for (long long r = blockIdx.x; r < (long long)n * n; r += gridDim.x) {
+    const int h = sidx((int)(r / n), n), k = sidx((int)(r % n), n);
+    const int base = h * h + k * k;
+    for (int z = threadIdx.x; z < n; z += 256) {
+      const cx<T> f = S[r * n + z];
+      if (r == 0 && z == 0) { a.f0[0] = (double)f.x; a.f0[1] = (double)f.y; }
+      const int l = sidx(z, n);
+      const int n2 = base + l * l;
+      const double I = ((double)f.x * f.x + (double)f.y * f.y) * a.iscale;
+      tot += I;
+      int b = a.lut[isqrt_ll(n2)];
+      while (b < a.nbins && n2 >= a.U[b + 1]) ++b;
+      if (b >= 0 && b < a.nbins) {
+        atomicAdd(&hist[2 * b], I);
+        atomicAdd(&hist[2 * b + 1], I * I);
+      }
+    }
+  }
+  atomicAdd(&hist[nv - 1], tot);
+  __syncthreads();
+  for (int i = threadIdx.x; i < nv; i += 256) a.part[(size_t)blockIdx.x * nv + i] = hist[i];
+}
+
+hipError_t launch_mr_bin(int prec, const MrBinArgs& a, int nblocks, hipStream_t s) {
+  const size_t shm = (2 * (size_t)a.nbins + 1) * sizeof(double);
+  if (prec == 0) hipLaunchKernelGGL(k_mr_bin<float>, dim3(nblocks), dim3(256), shm, s, a);
+  else hipLaunchKernelGGL(k_mr_bin<double>, dim3(nblocks), dim3(256), shm, s, a);
+  return hipGetLastError();
+}
+
 // |F|^2 at the integer frequency (h, k, l) (signed, any range: the DFT is
 // periodic); a real transform keeps kz in [0, n/2], the rest by F(-q) = F(q)*
 template <typename T>
@@ -1804,7 +2032,8 @@ __device__ __forceinline__ double ewald_intensity(const EwaldArgs& a, long long 
   long long lz = ((l % n) + n) % n;
   if (!a.c2c && lz > n / 2) { h = -h; k = -k; lz = (((-l) % n) + n) % n; }
   const long long kx = ((h % n) + n) % n, ky = ((k % n) + n) % n;
-  const cx<T> f = ((const cx<T>*)a.spec)[((size_t)lz * n + ky) * n + kx];
+  const size_t at = a.natural ? ((size_t)kx * n + ky) * n + lz : ((size_t)lz * n + ky) * n + kx;
+  const cx<T> f = ((const cx<T>*)a.spec)[at];
   return (double)f.x * (double)f.x + (double)f.y * (double)f.y;
 }
 
@@ -1998,6 +2227,9 @@ int fft_stages(int n, int* Ls, int* Rs) {
     case 256: return stages_t<256>(Ls, Rs); case 512: return stages_t<512>(Ls, Rs);
     case 1024: return stages_t<1024>(Ls, Rs); case 2048: return stages_t<2048>(Ls, Rs);
     case kBig: return stages_t<kBig>(Ls, Rs);
+#define UR_MR_CASE(NN) case NN: return stages_t<NN>(Ls, Rs);
+    UR_MR_SIZES(UR_MR_CASE)
+#undef UR_MR_CASE
     default: return 0;
   }
 }

@@ -201,11 +201,41 @@ hipError_t launch_pass_y(int prec, int n, const YArgs& a, hipStream_t s);
 hipError_t launch_pass_x(int prec, int n, int mode, int dir, const XArgs& a, int nblocks, hipStream_t s);
 hipError_t launch_finalize(const FinArgs& a, hipStream_t s);
 hipError_t launch_merge(const MergeArgs& a, hipStream_t s);
+// Mixed-radix boxes: edges n = 2^a 3^b 5^c that are not powers of two, complex
+// [x][y][z] arrays transformed in place one axis at a time; the spectrum
+// stays in natural order [kx][ky][kz].
+bool mr_size(int n);
+struct MrArgs {
+  const void* src;          // this pass's input (may equal dst)
+  void* dst;
+  const void* tw;
+  double scale;             // applied to the outputs
+  double* mom;              // per-block [sum rho, sum |rho|^2] of the input (may be null)
+};
+// axis 0 = x (stride n^2), 1 = y (stride n), 2 = z (contiguous)
+hipError_t launch_mr_axis(int prec, int n, int axis, int dir, const MrArgs& a, hipStream_t s);
+int mr_axis_blocks(int prec, int n, int axis);
+// density of a level written as complex (rho, 0), one block per (x, y)
+// pencil, with per-pencil [sum rho, sum rho^2] in mom
+hipError_t launch_mr_gen(int prec, int n, const ZArgs& za, void* S, double* mom, hipStream_t s);
+struct MrBinArgs {
+  const void* S;            // complex [kx][ky][kz]
+  int n, nbins;
+  const int* U;
+  const short* lut;
+  int nlut;
+  double iscale;
+  double* part;             // nblk x (2 nbins + 1)
+  double* f0;
+};
+hipError_t launch_mr_bin(int prec, const MrBinArgs& a, int nblocks, hipStream_t s);
+
 // Ewald-sphere image: per detector pixel, |F|^2 trilinear on the reciprocal
 // grid at q = k_j (s - e), averaged over wavelength nodes j
 struct EwaldArgs {
   const void* spec;         // [kz][ky][kx], kz in [0, nkz)
   int n, nkz, c2c;
+  int natural;              // spectrum in [kx][ky][kz] order (mixed-radix plans)
   double dq;                // 2 pi / (n voxel)
   double e[3], du[3], dv[3];
   double dist, pixel, cu, cv;

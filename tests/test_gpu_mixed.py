@@ -1,0 +1,201 @@
+"""Boxes whose edge is not a power of two (n = 2^a 3^b 5^c: the paper's 250 ...
+2000 family of ED-1 and zoom boxes, and 2^a 3): the mixed-radix path
+(radix 2/4/8 then 3 then 5 Stockham stages, one axis at a time, in place,
+natural-order spectrum) through the C ABI against the FP64 oracle, whose
+transform takes odd lengths by the DFT sum itself (pinned against brute force
+and numpy.fft in test_oracle_pins.py).
+
+Tolerances as for the power-of-two transforms: spectra within 2e-6 (FP32)
+or 1e-13 (FP64) of max|F|; bin counts bit-exact and means within 1e-5 /
+1e-12 relative (compare_bins).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from test_gpu_parity import F32_BIN, F64_BIN, compare_bins
+
+pytestmark = pytest.mark.gpu
+
+_SPECTRA = {}
+
+
+@pytest.fixture(scope="module")
+def ur():
+    import torch
+    import paper_2303_13435_amd as ur
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return ur
+
+
+@pytest.fixture(scope="module")
+def orc():
+    import oracle
+    oracle.lib()
+    return oracle
+
+
+def _say(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def _spectrum(orc, n):
+    if n not in _SPECTRA:
+        rng = np.random.default_rng(900 + n)
+        z = rng.standard_normal((n, n, n)) + 1j * rng.standard_normal((n, n, n))
+        _SPECTRA[n] = (z, orc.fft3d(z, -1) / float(n) ** 3)
+    return _SPECTRA[n]
+
+
+@pytest.mark.parametrize("n", [40, 48, 96, 100, 160, 200, 250])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_mixed_fft3d_forward_and_inverse(ur, orc, n, prec):
+    """Every coefficient of a random complex box (radix sequences 8,5 /
+    8,2,3 / 8,4,3 / 4,5,5 / 8,4,5 / 8,5,5 / 2,5,5,5), and the inverse
+    transform back to the input."""
+    import torch
+    _say(f"mixed fft3d n={n} prec={prec}")
+    z, F = _spectrum(orc, n)
+    plan = ur.Plan(n, 1.0, prec, c2c=True)
+    dt = torch.complex64 if prec == 0 else torch.complex128
+    out = plan.fft3d(torch.as_tensor(z, dtype=dt, device="cuda").contiguous())
+    torch.cuda.synchronize()
+    err = np.max(np.abs(out.cpu().numpy() - F)) / np.max(np.abs(F))
+    _say(f"  spectrum rel err {err:.3e}")
+    assert err <= (2e-6 if prec == 0 else 1e-13)
+    back = plan.fft3d(out, direction=+1)
+    torch.cuda.synchronize()
+    err2 = np.max(np.abs(back.cpu().numpy() - z)) / np.max(np.abs(z))
+    assert err2 <= (2e-6 if prec == 0 else 1e-13)
+
+
+@pytest.mark.parametrize("n,prec", [(400, 0), (500, 0), (384, 1), (768, 0), (1000, 0), (1000, 1), (1536, 0), (2000, 0)])
+def test_mixed_fft3d_sampled(ur, orc, n, prec):
+    """Large mixed-radix boxes (up to 2000^3 FP32, 64 GB each way): zero
+    except at 64 random voxels, 516 coefficients over the whole spectrum
+    against eq. 1 by direct summation."""
+    import torch
+    _say(f"mixed fft3d sampled n={n} prec={prec}")
+    xyz, val = W.sparse_voxels(3000 + n, n, 64, dtype=np.float32 if prec == 0 else np.float64)
+    dt = torch.complex64 if prec == 0 else torch.complex128
+    x = torch.zeros((n, n, n), dtype=dt, device="cuda")
+    idx = [torch.as_tensor(xyz[:, i], device="cuda") for i in range(3)]
+    x[idx[0], idx[1], idx[2]] = torch.as_tensor(val, device="cuda").to(dt)
+    plan = ur.Plan(n, 1.0, prec, c2c=True)
+    out = plan.fft3d(x)
+    del x
+    uvw = W.random_frequencies(3001 + n, n, 512, half_z=False)
+    q = torch.as_tensor(uvw, device="cuda")
+    got = out[q[:, 0], q[:, 1], q[:, 2]].cpu().numpy().astype(np.complex128)
+    del out, plan
+    torch.cuda.empty_cache()
+    ref = orc.dft_points(n, xyz, val.astype(np.float64), uvw)
+    err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+    _say(f"  sampled rel err {err:.3e}")
+    assert err <= (2e-6 if prec == 0 else 1e-13)
+
+
+@pytest.mark.parametrize("n,prec", [(40, 0), (40, 1), (100, 0), (100, 1), (200, 1), (250, 0)])
+def test_mixed_simulate(ur, orc, n, prec):
+    """The whole forward path on a mixed-radix box (lattice of Gaussian atoms
+    in a sphere): ur_simulate, ur_simulate_rho and ur_intensity_bin against
+    the oracle; ur_rho_generate voxel by voxel."""
+    import torch
+    wl = W.mixed(n, prec, nbins=64)
+    _say(f"mixed simulate n={n} prec={prec}")
+    ref = orc.simulate(wl, return_fields=True)
+    plan = ur.Plan(n, wl.voxel, prec, c2c=True)
+    plan.set_bins(wl.edges)
+    cell = ur.DeviceCell.from_host(wl.cell)
+    tol = F32_BIN if prec == 0 else F64_BIN
+    h = ur.Hist(wl.nbins)
+    plan.simulate(cell, wl.mask, wl.zoom, h)
+    torch.cuda.synchronize()
+    got = h.numpy()
+    compare_bins(got, ref, tol, "mixed simulate", n=n)
+    rt = 1e-6 if prec == 0 else 1e-12
+    assert abs(got["totals"][3] - np.sum(ref["rho"] ** 2)) <= rt * np.sum(ref["rho"] ** 2)
+    assert abs(got["totals"][1] - ref["totals"][1]) <= rt * abs(ref["totals"][1])
+    rho = plan.rho_generate(cell, wl.mask, wl.zoom)
+    torch.cuda.synchronize()
+    assert np.max(np.abs(rho.cpu().numpy() - ref["rho"])) <= (1e-6 if prec == 0 else 1e-14) * np.max(np.abs(ref["rho"]))
+    z = torch.as_tensor(ref["rho"], dtype=plan.complex_dtype, device="cuda").contiguous()
+    h1 = ur.Hist(wl.nbins)
+    plan.simulate_rho(z, h1)
+    torch.cuda.synchronize()
+    got1 = h1.numpy()
+    compare_bins(got1, ref, tol, "mixed simulate_rho", n=n)
+    assert abs(got1["totals"][3] - np.sum(ref["rho"] ** 2)) <= rt * np.sum(ref["rho"] ** 2)
+    spec = torch.as_tensor(ref["F"], dtype=plan.complex_dtype, device="cuda").contiguous()
+    h2 = ur.Hist(wl.nbins)
+    plan.intensity_bin(spec, h2)
+    torch.cuda.synchronize()
+    compare_bins(h2.numpy(), ref, tol, "mixed intensity_bin", n=n)
+
+
+def test_mixed_2000_counts_and_moments(ur, orc):
+    """The 2000^3 FP32 box of the family (64 GB complex box in HBM): counts of
+    all 256 bins bit-exact (O12 counts, axis by axis), Parseval, F(0) and the
+    sum of rho^2 against the oracle's voxel-by-voxel density moments, and the
+    curve finite and positive."""
+    import torch
+    wl = W.mixed(2000, 0, nbins=256)
+    _say("mixed simulate n=2000")
+    plan = ur.Plan(wl.n, wl.voxel, 0, c2c=True)
+    plan.set_bins(wl.edges)
+    cell = ur.DeviceCell.from_host(wl.cell)
+    h = ur.Hist(wl.nbins)
+    plan.simulate(cell, wl.mask, wl.zoom, h)
+    torch.cuda.synchronize()
+    got = h.numpy()
+    del plan
+    torch.cuda.empty_cache()
+    cnt, _ = orc.axis_pair_bins(wl.n, wl.voxel, wl.edges, 1, 1.0, 0.0)
+    assert np.array_equal(got["count"], cnt)
+    s1, s2 = orc.density_moments(wl, orc.cell_synth(wl.cell))
+    n3 = float(wl.n) ** 3
+    assert abs(got["totals"][0] - s2 / n3) <= 1e-6 * s2 / n3
+    assert abs(got["totals"][1] - s1 / n3) <= 1e-6 * s1 / n3
+    assert abs(got["totals"][2]) <= 1e-6 * s1 / n3
+    assert abs(got["totals"][3] - s2) <= 1e-6 * s2
+    pop = cnt > 0
+    assert np.all(np.isfinite(got["mean"][pop])) and np.all(got["mean"][pop] > 0)
+
+
+def test_mixed_ewald_and_refusals(ur, orc):
+    """The Ewald image reads the natural-order spectrum of a mixed-radix plan;
+    real transforms, zoom levels, the adjoint and the voxel form factor are
+    refused on such plans, and edges outside the compiled set at creation."""
+    import torch
+    n = 40
+    z, F = _spectrum(orc, n)
+    geo = W.detector(W.rotation([0.3, -0.5, 0.8], 1.1), rel_spread=0.05, n_lambda=16, pixel=5.0,
+                     nu=37, nv=29, cu=11.0, cv=20.0)
+    ref = orc.ewald_image(F, 1.0, geo)
+    plan = ur.Plan(n, 1.0, 1, c2c=True)
+    img = plan.ewald_image(plan.fft3d(torch.as_tensor(z, device="cuda").contiguous()), geo)
+    torch.cuda.synchronize()
+    fmax = float(np.max(np.abs(F)))
+    assert np.max(np.abs(img.cpu().numpy() - ref)) <= 1e-12 * fmax ** 2
+    with pytest.raises(ur.UltimaError, match="status 2"):
+        ur.Plan(n, 1.0, 0, c2c=False)
+    with pytest.raises(ur.UltimaError, match="status 1"):
+        ur.Plan(120, 1.0, 0, c2c=True)
+    wl = W.mixed(n, 1, nbins=16)
+    plan.set_bins(wl.edges)
+    cell = ur.DeviceCell.from_host(wl.cell)
+    h = ur.Hist(wl.nbins)
+    with pytest.raises(ur.UltimaError, match="status 2"):
+        plan.simulate(cell, wl.mask, W.Zoom(2 * n, 2), h)
+    plan.simulate(cell, wl.mask, wl.zoom, h)
+    g = torch.zeros(wl.nbins, dtype=torch.float64, device="cuda")
+    ga = torch.zeros(wl.cell.n_atoms, dtype=torch.float64, device="cuda")
+    with pytest.raises(ur.UltimaError, match="status 2"):
+        plan.adjoint(h, g, cell=cell, mask=wl.mask, grad_amp=ga)
+    plan.set_voxel_form(True)
+    with pytest.raises(ur.UltimaError, match="status 2"):
+        plan.simulate(cell, wl.mask, wl.zoom, h)
+    torch.cuda.synchronize()

@@ -39,7 +39,7 @@ def r3_table():
 # O4  transform
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("n", [8, 16])
+@pytest.mark.parametrize("n", [6, 8, 10, 12, 15, 16])
 def test_fft3d_matches_brute_force_dft(oracle_lib, n):
     rng = np.random.default_rng(n)
     rho = rng.standard_normal((n, n, n))
@@ -48,7 +48,7 @@ def test_fft3d_matches_brute_force_dft(oracle_lib, n):
     assert np.max(np.abs(F - ref)) <= 1e-14 * np.max(np.abs(ref)) * n
 
 
-@pytest.mark.parametrize("n", [2, 4, 8, 32, 256, 4096])
+@pytest.mark.parametrize("n", [2, 4, 8, 32, 256, 4096, 3, 5, 40, 48, 250, 1000, 1536, 2000])
 def test_fft1d_matches_library_routine(oracle_lib, n):
     rng = np.random.default_rng(n)
     a = rng.standard_normal((3, n)) + 1j * rng.standard_normal((3, n))
@@ -59,7 +59,7 @@ def test_fft1d_matches_library_routine(oracle_lib, n):
     assert np.max(np.abs(back - a)) <= 1e-14 * np.max(np.abs(a)) * math.log2(max(n, 2))
 
 
-@pytest.mark.parametrize("n", [32, 64])
+@pytest.mark.parametrize("n", [32, 64, 40, 48, 100])
 def test_fft3d_matches_library_fftn(oracle_lib, n):
     rng = np.random.default_rng(100 + n)
     rho = rng.standard_normal((n, n, n))
@@ -215,9 +215,9 @@ def test_linear_bin_thresholds_closed_form(oracle_lib):
     assert U2[0] == 1 and U2[-1] == 3 * 32 * 32 + 1
 
 
-def test_bin_counts_are_shell_counts(oracle_lib):
-    n = 32
-    edges = W.lin_edges(0.0, math.pi, 64)     # U_b = ceil(b^2/4) as above
+@pytest.mark.parametrize("n", [32, 40, 48])
+def test_bin_counts_are_shell_counts(oracle_lib, n):
+    edges = W.lin_edges(0.0, 16 * 2.0 * math.pi / n, 64)     # U_b = ceil(b^2/4) as above
     cnt = oracle_lib.bin_counts(n, 1.0, edges)
     U = oracle_lib.thresholds(n, 1.0, edges)
     r3 = r3_table()
