@@ -742,51 +742,66 @@ static ur_status run_y_x(ur_plan* p, const FwdGeom& g, char* A, char* B, const L
   return UR_OK;
 }
 
-// mixed-radix forward: the three axis passes in place on S (z from `src`,
-// with moments when asked), |F|^2 binning and the finalize
-static ur_status mr_transform(ur_plan* p, const void* src, void* S, int dir, double* mom, hipStream_t s) {
+// mixed-radix passes in place on S: z (from `src`, or generated from `gen`,
+// with per-block moments into `mom` when given), y, then x (scaled by 1/n^3
+// forward); with `lay` the forward x pass bins |F|^2 instead of storing it
+// (block partials and F(0) at their places in the workspace).
+static ur_status mr_transform(ur_plan* p, const void* src, void* S, int dir, double* mom, const ZArgs* gen,
+                              const Layout* lay, hipStream_t s) {
   const int n = p->n;
   MrArgs a{};
-  a.tw = p->tw; a.dst = S; a.mom = mom;
-  a.src = src; a.scale = 1.0;
+  a.tw = p->tw; a.dst = S; a.mom = mom; a.src = src; a.scale = 1.0;
+  if (gen) a.z = *gen;
   {
     PassTimer tm(p, P_Z, s);
-    UR_HIP(launch_mr_axis(p->prec, n, 2, dir, a, s));
+    UR_HIP(launch_mr_axis(p->prec, n, 2, dir, gen ? MR_GEN : MR_LOAD, a, s));
   }
   a.src = S; a.mom = nullptr;
   {
     PassTimer tm(p, P_Y, s);
-    UR_HIP(launch_mr_axis(p->prec, n, 1, dir, a, s));
+    UR_HIP(launch_mr_axis(p->prec, n, 1, dir, MR_LOAD, a, s));
   }
   a.scale = dir < 0 ? 1.0 / ((double)n * n * n) : 1.0;
+  if (lay) {
+    a.nbins = p->nbins; a.U = p->dU; a.lut = p->dLut; a.iscale = 1.0;
+    a.part = (double*)(p->ws + lay->part); a.f0 = (double*)(p->ws + lay->f0);
+  }
   {
     PassTimer tm(p, P_X, s);
-    UR_HIP(launch_mr_axis(p->prec, n, 0, dir, a, s));
+    UR_HIP(launch_mr_axis(p->prec, n, 0, dir, lay ? MR_BIN : MR_LOAD, a, s));
   }
   const double box = (double)n * n * n * p->cs;
-  p->pass_bytes[P_Z] = 2.0 * box;
+  p->pass_bytes[P_Z] = (gen ? 1.0 : 2.0) * box;
   p->pass_bytes[P_Y] = 2.0 * box;
-  p->pass_bytes[P_X] = 2.0 * box;
+  p->pass_bytes[P_X] = (lay ? 1.0 : 2.0) * box;
   return UR_OK;
 }
 
-static ur_status mr_bin(ur_plan* p, const void* S, const Layout& lay, const ur_hist* h, int nzb, hipStream_t s) {
+// finalize of the block partials written by the binning x pass (or k_mr_bin)
+static ur_status mr_finalize(ur_plan* p, const Layout& lay, int nblk, const ur_hist* h, int nzb, hipStream_t s) {
+  FinArgs fa{};
+  fa.part = (const double*)(p->ws + lay.part); fa.nblk = nblk; fa.nbins = p->nbins;
+  fa.mom = nzb > 0 ? (const double*)(p->ws + lay.mom) : nullptr; fa.nzb = nzb;
+  fa.mpart = (double*)(p->ws + lay.f0 + 64); fa.f0 = (const double*)(p->ws + lay.f0); fa.cnt = p->dCount;
+  fa.sum = h->sum; fa.sumsq = h->sumsq; fa.count = h->count; fa.totals = h->totals; fa.mean = h->mean; fa.sem = h->sem;
+  PassTimer tm(p, P_FIN, s);
+  UR_HIP(launch_finalize(fa, s));
+  p->pass_bytes[P_FIN] = (double)nblk * (2.0 * p->nbins + 1.0) * 8.0 + 16.0 * nzb;
+  return UR_OK;
+}
+
+// |F|^2 binning of a given spectrum and the finalize
+static ur_status mr_bin(ur_plan* p, const void* S, const Layout& lay, const ur_hist* h, hipStream_t s) {
   MrBinArgs b{};
   b.S = S; b.n = p->n; b.nbins = p->nbins; b.U = p->dU; b.lut = p->dLut; b.nlut = p->nlut; b.iscale = 1.0;
   b.part = (double*)(p->ws + lay.part); b.f0 = (double*)(p->ws + lay.f0);
   const int nblk = (int)std::min<long long>((long long)p->n * p->n, kMaxXBlocks);
   {
-    PassTimer tm(p, P_FIN, s);
+    PassTimer tm(p, P_X, s);
     UR_HIP(launch_mr_bin(p->prec, b, nblk, s));
-    FinArgs fa{};
-    fa.part = b.part; fa.nblk = nblk; fa.nbins = p->nbins;
-    fa.mom = nzb > 0 ? (const double*)(p->ws + lay.mom) : nullptr; fa.nzb = nzb;
-    fa.mpart = (double*)(p->ws + lay.f0 + 64); fa.f0 = b.f0; fa.cnt = p->dCount; fa.sum = h->sum; fa.sumsq = h->sumsq;
-    fa.count = h->count; fa.totals = h->totals; fa.mean = h->mean; fa.sem = h->sem;
-    UR_HIP(launch_finalize(fa, s));
   }
-  p->pass_bytes[P_FIN] = (double)p->n * p->n * p->n * p->cs + (double)nblk * (2.0 * p->nbins + 1.0) * 16.0;
-  return UR_OK;
+  p->pass_bytes[P_X] = (double)p->n * p->n * p->n * p->cs;
+  return mr_finalize(p, lay, nblk, h, 0, s);
 }
 
 extern "C" {
@@ -841,15 +856,17 @@ ur_status ur_simulate(ur_plan* p, const ur_cell* cell, const ur_mask* mask, cons
     UR_TRY(ensure_ws(p, lay.total, s));
     CellTables t;
     {
-      PassTimer tm(p, P_CELL, s);                    // cell synthesis and the density of the box
+      PassTimer tm(p, P_CELL, s);
       UR_TRY(prepare_cell(p, cell, 1, t, s));
-      ZArgs za = rot_args;
-      za.cellT = t.cellT; za.cb = t.cb; za.pre = t.pre; za.L = g.L; za.m = g.m; za.cbn = t.cbn;
-      UR_HIP(launch_mr_gen(p->prec, p->n, za, p->ws + lay.A, (double*)(p->ws + lay.mom), s));
     }
-    p->pass_bytes[P_CELL] = (double)p->n * p->n * p->n * p->cs + 16.0 * p->n * p->n;
-    UR_TRY(mr_transform(p, p->ws + lay.A, p->ws + lay.A, -1, nullptr, s));
-    return mr_bin(p, p->ws + lay.A, lay, h, p->n * p->n, s);
+    {
+      const double c = cell->c;
+      p->pass_bytes[P_CELL] = 8.0 * (3.0 * c * cell->n_atoms) * 2.0 + c * c * c * (16.0 + p->rs);
+    }
+    ZArgs za = rot_args;
+    za.cellT = t.cellT; za.cb = t.cb; za.pre = t.pre; za.L = g.L; za.m = g.m; za.cbn = t.cbn;
+    UR_TRY(mr_transform(p, nullptr, p->ws + lay.A, -1, (double*)(p->ws + lay.mom), &za, &lay, s));
+    return mr_finalize(p, lay, mr_axis_blocks(p->prec, p->n, 0, MR_BIN), h, mr_axis_blocks(p->prec, p->n, 2, MR_GEN), s);
   }
   Layout lay = layout_incore(p, p->nbins);
   UR_TRY(ensure_ws(p, lay.total, s));
@@ -901,8 +918,8 @@ ur_status ur_simulate_rho(ur_plan* p, const void* rho, const ur_hist* h, void* s
     if (p->dSinc) return fail(UR_ERR_UNSUPPORTED, "mixed-radix boxes run without the voxel form factor");
     Layout lay = layout_mixed(p, p->nbins);
     UR_TRY(ensure_ws(p, lay.total, s));
-    UR_TRY(mr_transform(p, rho, p->ws + lay.A, -1, (double*)(p->ws + lay.mom), s));
-    return mr_bin(p, p->ws + lay.A, lay, h, mr_axis_blocks(p->prec, p->n, 2), s);
+    UR_TRY(mr_transform(p, rho, p->ws + lay.A, -1, (double*)(p->ws + lay.mom), nullptr, &lay, s));
+    return mr_finalize(p, lay, mr_axis_blocks(p->prec, p->n, 0, MR_BIN), h, mr_axis_blocks(p->prec, p->n, 2, MR_LOAD), s);
   }
   Layout lay = layout_incore(p, p->nbins);
   UR_TRY(ensure_ws(p, lay.total, s));
@@ -931,7 +948,7 @@ ur_status ur_fft3d_exec(ur_plan* p, const void* in, void* out, int32_t dir, void
   if (dir > 0 && p->n > 1024) return fail(UR_ERR_UNSUPPORTED, "inverse transforms run up to 1024^3");
   if (in == out) return fail(UR_ERR_INVALID, "in and out must differ");
   hipStream_t s = (hipStream_t)stream;
-  if (p->mixed) return mr_transform(p, in, out, dir, nullptr, s);
+  if (p->mixed) return mr_transform(p, in, out, dir, nullptr, nullptr, nullptr, s);
   Layout lay = layout_incore(p, std::max(p->nbins, 1));
   UR_TRY(ensure_ws(p, lay.total, s));
   const int n = p->n, c2c = (p->flags & UR_C2C) ? 1 : 0;
@@ -977,7 +994,7 @@ ur_status ur_intensity_bin(ur_plan* p, const void* spectrum, const ur_hist* h, v
     if (p->dSinc) return fail(UR_ERR_UNSUPPORTED, "mixed-radix boxes run without the voxel form factor");
     Layout lay = layout_mixed(p, p->nbins);
     UR_TRY(ensure_ws(p, lay.total, s));
-    return mr_bin(p, spectrum, lay, h, 0, s);
+    return mr_bin(p, spectrum, lay, h, s);
   }
   Layout lay = layout_incore(p, p->nbins);
   UR_TRY(ensure_ws(p, lay.total, s));

@@ -211,13 +211,20 @@ struct MrArgs {
   const void* tw;
   double scale;             // applied to the outputs
   double* mom;              // per-block [sum rho, sum |rho|^2] of the input (may be null)
+  ZArgs z;                  // MR_GEN: the density generator of the level
+  int nbins;                // MR_BIN: |F|^2 * iscale into the bins, no store
+  const int* U;
+  const short* lut;
+  double iscale;
+  double* part;             // nblk x (2 nbins + 1)
+  double* f0;
 };
-// axis 0 = x (stride n^2), 1 = y (stride n), 2 = z (contiguous)
-hipError_t launch_mr_axis(int prec, int n, int axis, int dir, const MrArgs& a, hipStream_t s);
-int mr_axis_blocks(int prec, int n, int axis);
-// density of a level written as complex (rho, 0), one block per (x, y)
-// pencil, with per-pencil [sum rho, sum rho^2] in mom
-hipError_t launch_mr_gen(int prec, int n, const ZArgs& za, void* S, double* mom, hipStream_t s);
+// axis 0 = x (stride n^2), 1 = y (stride n), 2 = z (contiguous);
+// mode MR_LOAD: src -> dst, MR_GEN (axis 2): generated density -> dst,
+// MR_BIN (axis 0, forward): src -> bins
+enum MrMode { MR_LOAD = 0, MR_GEN = 1, MR_BIN = 2 };
+hipError_t launch_mr_axis(int prec, int n, int axis, int dir, int mode, const MrArgs& a, hipStream_t s);
+int mr_axis_blocks(int prec, int n, int axis, int mode);
 struct MrBinArgs {
   const void* S;            // complex [kx][ky][kz]
   int n, nbins;
