@@ -420,6 +420,12 @@ def main():
         extras["rotated_lattice"] = {"ms_per_step": round(msr, 4), "voxels_per_s": wl.n ** 3 / (msr * 1e-3),
                                      "pass_z_ms": pass_timing(plan, lambda: plan.simulate(rcell, wl.mask, wl.zoom, hist),
                                                               5, torch)["pass_z"]["avg_ms"]}
+        # the same with the cell sampled by the cubic B-spline (64 coefficients per voxel)
+        ccell = ur.DeviceCell.from_host(wl.cell.with_rot(W.rotation([1.0, 2.0, 3.0], 0.7), 3))
+        msc, _ = time_steps(lambda: plan.simulate(ccell, wl.mask, wl.zoom, hist), max(3, args.steps // 2), 2, torch)
+        extras["rotated_lattice_cubic"] = {"ms_per_step": round(msc, 4), "voxels_per_s": wl.n ** 3 / (msc * 1e-3),
+                                           "pass_z_ms": pass_timing(plan, lambda: plan.simulate(ccell, wl.mask, wl.zoom, hist),
+                                                                    5, torch)["pass_z"]["avg_ms"]}
         extras["fp64"] = {"ms_per_step": round(ms64, 4), "voxels_per_s": wl.n ** 3 / (ms64 * 1e-3),
                           "kernels": pass_timing(p64, lambda: p64.simulate(cell, wl.mask, wl.zoom, h64), args.steps, torch)}
         note("fp64 done")

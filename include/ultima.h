@@ -88,9 +88,14 @@ typedef struct { int32_t kind; int64_t p0; int64_t p1; } ur_mask;
  * (row-major, finite) orienting it ("Electron density generation": the
  * cell interpolated over a rotated grid, repeated outside its bounds): the
  * ED-1 voxel at offset d = (x, y, z) - n1/2 from the particle centre takes
- * the cell's value at u = R d, trilinearly interpolated between the cell
- * voxels with periodic wrap (R = identity gives the aligned lattice
- * exactly).  Rotated lattices run the forward paths at zoom factor 1 on
+ * the cell's value at u = R d, interpolated between the cell voxels with
+ * periodic wrap (R = identity gives the aligned lattice exactly).
+ * interp selects the interpolation: 0 or 1 trilinear; 3 the cubic B-spline
+ * through the cell values (periodic spline coefficients, then the sum over
+ * the 4 x 4 x 4 neighbouring coefficients with the cubic B-spline weights
+ * of the fractional offsets: the order-3 spline of the interpolation
+ * routine the paper names); other values fail with UR_ERR_INVALID.
+ * Rotated lattices run the forward paths at zoom factor 1 on
  * real (UR_R2C) plans; the adjoint refuses them (UR_ERR_UNSUPPORTED). */
 typedef struct {
   int32_t c;
@@ -100,6 +105,7 @@ typedef struct {
   const double* sigma;
   double background;
   const double* rot;
+  int32_t interp;
 } ur_cell;
 
 /* Zoom level (workflow step 3): the ED-1 grid of edge n1 is block-summed by

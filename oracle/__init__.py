@@ -6,6 +6,7 @@ correct statement of the computation, written from the paper:
 
 * O1  unit-cell density (workflow step 1; "Electron density generation")
 * O2  ED-1 = tiled cell x particle mask (workflow step 2); O2r with a rotated lattice
+  (trilinear or cubic B-spline sampling of the cell)
 * O3  zoomed-out ED-2/ED-3 by block integration and zero padding (step 3)
 * O4  3D transform, eq. 1 (axis by axis, as eq. 2 separates it)
 * O5-O8  |Q| map, integer-threshold bins, per-bin mean and SEM (step 5)
@@ -69,7 +70,7 @@ def lib():
         L.or_ed1.argtypes = [ctypes.c_int, ctypes.c_int, _D, ctypes.c_int, ctypes.c_longlong,
                              ctypes.c_longlong, _D]
         L.or_ed1_rot.argtypes = [ctypes.c_int, ctypes.c_int, _D, ctypes.c_int, ctypes.c_longlong,
-                                 ctypes.c_longlong, _D, _D]
+                                 ctypes.c_longlong, _D, ctypes.c_int, _D]
         L.or_zoom.argtypes = [ctypes.c_int, ctypes.c_int, _D, ctypes.c_int, ctypes.c_longlong,
                               ctypes.c_longlong, ctypes.c_int, ctypes.c_int, _D]
         L.or_fft3d.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_int]
@@ -162,14 +163,29 @@ def ed1(n: int, cell_grid: np.ndarray, mask) -> np.ndarray:
     return out
 
 
-def ed1_rot(n: int, cell_grid: np.ndarray, mask, rot: np.ndarray) -> np.ndarray:
-    """O2r: ED-1 of a lattice oriented by the 3x3 matrix rot (cell sampled at
-    u = rot d, trilinear with periodic wrap)."""
+def bspline_coefficients(cell_grid: np.ndarray) -> np.ndarray:
+    """Periodic cubic B-spline coefficients C of the cell (the spline through
+    its values): sampled at the integers the spline is C filtered by
+    (1, 4, 1)/6 along each axis, so in the DFT domain C = S / (b b b) with
+    b(k) = (4 + 2 cos(2 pi k / c)) / 6."""
     c = cell_grid.shape[0]
-    cg = np.ascontiguousarray(cell_grid, dtype=np.float64)
+    b = (4.0 + 2.0 * np.cos(2.0 * np.pi * np.arange(c) / c)) / 6.0
+    B = b[:, None, None] * b[None, :, None] * b[None, None, :]
+    return np.real(np.fft.ifftn(np.fft.fftn(np.asarray(cell_grid, dtype=np.float64)) / B))
+
+
+def ed1_rot(n: int, cell_grid: np.ndarray, mask, rot: np.ndarray, interp: int = 1) -> np.ndarray:
+    """O2r: ED-1 of a lattice oriented by the 3x3 matrix rot (cell sampled at
+    u = rot d with periodic wrap): trilinear (interp 1) or the cubic
+    B-spline through the cell values (interp 3, the order-3 spline of the
+    interpolation routine the paper names)."""
+    assert interp in (1, 3)
+    c = cell_grid.shape[0]
+    cg = np.ascontiguousarray(cell_grid if interp == 1 else bspline_coefficients(cell_grid), dtype=np.float64)
     R = np.ascontiguousarray(rot, dtype=np.float64).reshape(9)
     out = np.empty((n, n, n))
-    lib().or_ed1_rot(int(n), int(c), _dp(cg), int(mask.kind), int(mask.p0), int(mask.p1), _dp(R), _dp(out))
+    lib().or_ed1_rot(int(n), int(c), _dp(cg), int(mask.kind), int(mask.p0), int(mask.p1), _dp(R), int(interp),
+                     _dp(out))
     return out
 
 
@@ -189,7 +205,7 @@ def density(wl, cell_grid: Optional[np.ndarray] = None) -> np.ndarray:
     rot = getattr(wl.cell, "rot", None)
     if rot is not None:
         assert wl.zoom.factor == 1 and wl.zoom.n1 == wl.n, "rotated lattices are defined for ED-1"
-        return ed1_rot(wl.n, cell_grid, wl.mask, rot)
+        return ed1_rot(wl.n, cell_grid, wl.mask, rot, int(getattr(wl.cell, "interp", 1)))
     if wl.zoom.factor == 1 and wl.zoom.n1 == wl.n:
         return ed1(wl.n, cell_grid, wl.mask)
     return zoomed(wl.zoom.n1, cell_grid, wl.mask, wl.zoom.factor, wl.n)

@@ -157,8 +157,21 @@ void or_ed1(int n, int c, const double* cell, int kind, long long p0, long long 
 /* ------------------------------------------------------------------------ */
 static double lerp(double a, double b, double t) { return a + t * (b - a); }
 
+/* cubic B-spline B3(x): (2 - |x|)^3 / 6 for 1 <= |x| < 2, (4 - 6 x^2 + 3 |x|^3) / 6
+ * for |x| < 1, zero beyond */
+static double bspline3(double x)
+{
+    const double a = fabs(x);
+    if (a >= 2.0) return 0.0;
+    if (a >= 1.0) return (2.0 - a) * (2.0 - a) * (2.0 - a) / 6.0;
+    return (4.0 - 6.0 * a * a + 3.0 * a * a * a) / 6.0;
+}
+
+/* order 1: `cell` holds the cell values, trilinear; order 3: `cell` holds the
+ * periodic cubic B-spline coefficients C, value = sum over the 4^3 nearest
+ * coefficients of C[i] B3(u0 - i0) B3(u1 - i1) B3(u2 - i2) */
 void or_ed1_rot(int n, int c, const double* cell, int kind, long long p0, long long p1, const double* R,
-                double* rho)
+                int order, double* rho)
 {
     const long long h = n / 2;
 #pragma omp parallel for schedule(static)
@@ -177,6 +190,17 @@ void or_ed1_rot(int n, int c, const double* cell, int kind, long long p0, long l
                     const double f = floor(u[i]);
                     i0[i] = (long long)f;
                     t[i] = u[i] - f;
+                }
+                if (order == 3) {
+                    double s = 0.0;
+                    for (int a0 = -1; a0 <= 2; ++a0)
+                        for (int a1 = -1; a1 <= 2; ++a1)
+                            for (int a2 = -1; a2 <= 2; ++a2) {
+                                const double w = bspline3(t[0] - a0) * bspline3(t[1] - a1) * bspline3(t[2] - a2);
+                                s += w * cell[((size_t)pmod(i0[0] + a0, c) * c + pmod(i0[1] + a1, c)) * c + pmod(i0[2] + a2, c)];
+                            }
+                    *out = s;
+                    continue;
                 }
                 double a[2][2];
                 for (int di = 0; di < 2; ++di)

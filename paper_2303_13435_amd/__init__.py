@@ -33,7 +33,8 @@ class UrMask(_c.Structure):
 
 class UrCell(_c.Structure):
     _fields_ = [("c", _c.c_int32), ("n_atoms", _c.c_int32), ("xyz", _vp), ("amp", _vp),
-                ("sigma", _vp), ("background", _c.c_double), ("rot", _c.POINTER(_c.c_double))]
+                ("sigma", _vp), ("background", _c.c_double), ("rot", _c.POINTER(_c.c_double)),
+                ("interp", _c.c_int32)]
 
 
 class UrZoom(_c.Structure):
@@ -167,6 +168,7 @@ class DeviceCell:
     sigma: "object"
     background: float
     rot: Optional[np.ndarray] = None
+    interp: int = 1
 
     @staticmethod
     def from_host(cell) -> "DeviceCell":
@@ -182,13 +184,13 @@ class DeviceCell:
             sig = torch.ones(1, dtype=torch.float64, device=dev)
         rot = getattr(cell, "rot", None)
         rot = None if rot is None else np.ascontiguousarray(rot, dtype=np.float64).reshape(9)
-        return DeviceCell(int(cell.c), xyz, amp, sig, float(cell.background), rot)
+        return DeviceCell(int(cell.c), xyz, amp, sig, float(cell.background), rot, int(getattr(cell, "interp", 1)))
 
     def struct(self, amp=None) -> UrCell:
         a = self.amp if amp is None else amp
         n = int(a.numel()) if self.xyz.numel() == 3 * a.numel() else 0
         rot = None if self.rot is None else self.rot.ctypes.data_as(_c.POINTER(_c.c_double))
-        return UrCell(self.c, n, _ptr(self.xyz), _ptr(a), _ptr(self.sigma), self.background, rot)
+        return UrCell(self.c, n, _ptr(self.xyz), _ptr(a), _ptr(self.sigma), self.background, rot, self.interp)
 
 
 def mask_struct(mask) -> UrMask:

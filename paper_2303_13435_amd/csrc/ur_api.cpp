@@ -598,6 +598,8 @@ static ur_status check_cell(const ur_cell* c) {
   if (c->rot)
     for (int i = 0; i < 9; ++i)
       if (!isfinite(c->rot[i])) return fail(UR_ERR_INVALID, "lattice rotation entry %d is not finite", i);
+  if (c->interp != 0 && c->interp != 1 && c->interp != 3)
+    return fail(UR_ERR_INVALID, "interp = %d: 1 (trilinear) or 3 (cubic B-spline)", c->interp);
   return UR_OK;
 }
 
@@ -608,6 +610,7 @@ static ur_status set_rotation(const ur_plan* p, const ur_cell* cell, const ur_zo
   if (zoom->factor != 1) return fail(UR_ERR_UNSUPPORTED, "rotated lattices run at zoom factor 1");
   if (p->flags & UR_C2C) return fail(UR_ERR_UNSUPPORTED, "rotated lattices run on real (UR_R2C) plans");
   za.rotated = 1;
+  za.cubic = cell->interp == 3 ? 1 : 0;
   for (int i = 0; i < 9; ++i) za.rot[i] = cell->rot[i];
   return UR_OK;
 }
@@ -669,6 +672,7 @@ static ur_status prepare_cell(ur_plan* p, const ur_cell* cell, int f, CellTables
   t.fold_part = (double*)(b + o_fp);
   UR_HIP(launch_cell_profiles(cell->c, cell->n_atoms, cell->xyz, cell->sigma, t.prof, s));
   UR_HIP(launch_cell_sum(cell->c, cell->n_atoms, cell->amp, t.prof, cell->background, t.cell64, s));
+  if (cell->rot && cell->interp == 3) UR_HIP(launch_bspline_cell(cell->c, t.cell64, s));   // spline coefficients
   UR_HIP(launch_cell_tables(p->prec, cell->c, f, t.cell64, t.cellT, t.pre, t.cb, t.cbn, s));
   return UR_OK;
 }

@@ -174,6 +174,18 @@ __global__ void __launch_bounds__(256) k_cell_blocks(int c, int f, const double*
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int pmodi(long long a, int m) { long long r = a % m; return (int)(r < 0 ? r + m : r); }
 
+// cubic B-spline weights of the four coefficients around a point at
+// fractional offset t in [0, 1): B3(t + 1), B3(t), B3(t - 1), B3(t - 2)
+template <typename T>
+__device__ __forceinline__ void bspline_weights(T t, T* w) {
+  const T t2 = t * t, t3 = t2 * t, s = (T)1 - t;
+  const T k = (T)1 / (T)6;
+  w[0] = k * s * s * s;
+  w[1] = k * ((T)3 * t3 - (T)6 * t2 + (T)4);
+  w[2] = k * ((T)-3 * t3 + (T)3 * t2 + (T)3 * t + (T)1);
+  w[3] = k * t3;
+}
+
 template <typename T>
 struct Pencil {
   int zlo, zhi;             // coarse z range that can hold density (zlo > zhi: empty)
@@ -277,6 +289,45 @@ struct Pencil {
     const T b0 = a00 + tv * (a01 - a00);
     const T b1 = a10 + tv * (a11 - a10);
     return b0 + tu * (b1 - b0);
+  }
+
+  // ED-1 voxel of a rotated lattice, cubic B-spline: cellT holds the
+  // periodic spline coefficients C; the value at u is the sum over the
+  // 4 x 4 x 4 coefficients around floor(u) with the cubic B-spline weights
+  // of the fractional offsets (third index innermost)
+  __device__ __forceinline__ T value_rot3(const ZArgs& a, int z) const {
+    if (z < zlo || z > zhi) return (T)0;
+    const double dz = (double)(z + zoff);
+    const double u = __dadd_rn(ux, __dmul_rn(a.rot[2], dz));
+    const double v = __dadd_rn(uy, __dmul_rn(a.rot[5], dz));
+    const double w = __dadd_rn(uz, __dmul_rn(a.rot[8], dz));
+    const double fu = floor(u), fv = floor(v), fw = floor(w);
+    T wu[4], wv[4], ww[4];
+    bspline_weights<T>((T)(u - fu), wu);
+    bspline_weights<T>((T)(v - fv), wv);
+    bspline_weights<T>((T)(w - fw), ww);
+    const int c = cmask + 1;
+    const int i0 = (int)(long long)fu - 1, j0 = (int)(long long)fv - 1, k0 = (int)(long long)fw - 1;
+    const T* C = (const T*)a.cellT;
+    T acc = (T)0;
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      T sp = (T)0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const T* r = C + ((size_t)((i0 + p) & cmask) * c + ((j0 + q) & cmask)) * c;
+        T sq = (T)0;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) sq += ww[m] * r[(k0 + m) & cmask];
+        sp += wv[q] * sq;
+      }
+      acc += wu[p] * sp;
+    }
+    return acc;
+  }
+
+  __device__ __forceinline__ T value_rotated(const ZArgs& a, int z) const {
+    return a.cubic ? value_rot3(a, z) : value_rot(a, z);
   }
 
   // ED-1 voxel (factor 1): tiled cell inside the mask, exact integer test
@@ -411,7 +462,7 @@ k_pass_z(ZArgs a) {
 #pragma unroll
           for (int r = 0; r < R0; ++r) {
             const int z = first_index<N>(g, i, r);
-            v[i * R0 + r] = mk(pa.value_rot(a, z), pb.value_rot(a, z));
+            v[i * R0 + r] = mk(pa.value_rotated(a, z), pb.value_rotated(a, z));
           }
       } else if (!ZOOM) {
         // the cell residue of z = b + r N/R0 does not depend on r when the
@@ -612,7 +663,7 @@ __global__ void __launch_bounds__(256) k_rho_generate(ZArgs a, int n, int x0, T*
   Pencil<T> p;
   p.init(a, X, Y);
   T* row = rho + t * n;
-  for (int z = threadIdx.x; z < n; z += 256) row[z] = a.rotated ? p.value_rot(a, z) : p.value(a, z);
+  for (int z = threadIdx.x; z < n; z += 256) row[z] = a.rotated ? p.value_rotated(a, z) : p.value(a, z);
 }
 
 // ---------------------------------------------------------------------------
@@ -1876,7 +1927,7 @@ __global__ void __launch_bounds__((MrCfg<T, N, MODE == MR_BIN>::threads)) k_mr_a
         p.init(a.z, line / N, line % N);
         cx<T>* col = lds + l * PS;
         for (int e = g; e < N; e += GP) {
-          const T v = a.z.rotated ? p.value_rot(a.z, e) : p.value(a.z, e);
+          const T v = a.z.rotated ? p.value_rotated(a.z, e) : p.value(a.z, e);
           col[pad(e)] = mk(v, (T)0);
           s1 += (double)v;
           s2 += (double)v * (double)v;
@@ -2279,6 +2330,50 @@ hipError_t launch_grad_amp(int c, int n_atoms, const double* prof, const double*
   if (n_atoms <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_grad_amp, dim3(n_atoms), dim3(256), 0, s, c, prof, gcell, grad_amp);
   return hipGetLastError();
+}
+
+// Periodic cubic B-spline coefficients along one axis of the c^3 cell, in
+// place, one thread per line.  The cell values s and coefficients C satisfy
+// (C[k-1] + 4 C[k] + C[k+1]) / 6 = s[k] (indices mod c).  With z = sqrt(3) - 2
+// (z + 1/z = -4) the operator factors as -(1/z)(1 - z E^-1)(1 - z E), so
+// C = -6 z w with y[k] = s[k] + z y[k-1] (causal) and w[k] = y[k] + z w[k+1]
+// (anticausal); the periodic starts are the geometric sums
+// y[0] = sum_m z^m s[-m] / (1 - z^c) and w[c-1] = sum_m z^m y[c-1+m] / (1 - z^c).
+__global__ void __launch_bounds__(256) k_bspline_axis(double* __restrict__ cell, int c, int axis) {
+  const int line = blockIdx.x * blockDim.x + threadIdx.x;
+  if (line >= c * c) return;
+  const size_t st = axis == 2 ? 1 : (axis == 1 ? (size_t)c : (size_t)c * c);
+  const size_t base = axis == 2 ? (size_t)line * c
+                    : (axis == 1 ? (size_t)(line / c) * c * c + line % c : (size_t)line);
+  double* x = cell + base;
+  const double z = 1.7320508075688772935 - 2.0;
+  double zc = 1.0, y0 = 0.0;
+  for (int m = 0; m < c; ++m) {
+    y0 += zc * x[(size_t)((c - m) % c) * st];
+    zc *= z;
+  }
+  y0 /= 1.0 - zc;
+  x[0] = y0;
+  for (int k = 1; k < c; ++k) x[(size_t)k * st] += z * x[(size_t)(k - 1) * st];
+  double zm = 1.0, wl = 0.0;
+  for (int m = 0; m < c; ++m) {
+    wl += zm * x[(size_t)((c - 1 + m) % c) * st];
+    zm *= z;
+  }
+  wl /= 1.0 - zc;
+  x[(size_t)(c - 1) * st] = wl;
+  for (int k = c - 2; k >= 0; --k) x[(size_t)k * st] += z * x[(size_t)(k + 1) * st];
+  for (int k = 0; k < c; ++k) x[(size_t)k * st] *= -6.0 * z;
+}
+
+hipError_t launch_bspline_cell(int c, double* cell, hipStream_t s) {
+  const int lines = c * c;
+  for (int axis = 0; axis < 3; ++axis) {
+    hipLaunchKernelGGL(k_bspline_axis, dim3((lines + 255) / 256), dim3(256), 0, s, cell, c, axis);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_rho_generate(int prec, int n, int x_lo, int x_hi, const ZArgs& a, void* rho, hipStream_t s) {

@@ -41,6 +41,7 @@ struct ZArgs {
   int cbn;                  // edge of the block table
   int rotated;              // ROT generation: the cell is sampled at u = rot d
   double rot[9];            // row-major
+  int cubic;                // ROT: cellT holds cubic B-spline coefficients (64-tap sampling)
 };
 
 struct YArgs {
@@ -262,6 +263,8 @@ hipError_t launch_pass_z_fold(int prec, int n, const ZFoldArgs& a, int nblocks, 
 hipError_t launch_fold_reduce_classes(int c, const double* part, int nblk, double* gcell, hipStream_t s);
 hipError_t launch_fold_reduce(int c3, const double* part, int nblk, double* gcell, hipStream_t s);
 hipError_t launch_grad_amp(int c, int n_atoms, const double* prof, const double* gcell, double* grad_amp, hipStream_t s);
+// periodic cubic B-spline coefficients of a c^3 FP64 cell, in place
+hipError_t launch_bspline_cell(int c, double* cell, hipStream_t s);
 hipError_t launch_rho_generate(int prec, int n, int x_lo, int x_hi, const ZArgs& a, void* rho, hipStream_t s);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 hipError_t launch_bin_counts(int n, int nkz, int r2c, int nbins, const int* U, unsigned long long* tmp, double* out, hipStream_t s);

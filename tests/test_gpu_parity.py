@@ -274,16 +274,19 @@ def test_c4_size_256(ur, orc, prec):
 # rotated lattice (cell sampled at u = R d, trilinear, periodic)
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("n,prec", [(64, 0), (64, 1), (128, 0)])
-def test_rotated_lattice(ur, orc, n, prec):
-    """A lattice oriented by a general rotation: the fused forward path
-    against the whole oracle (O2r, then O4-O8), the generated density voxel
-    by voxel; the adjoint and zoomed levels refuse rotated lattices."""
+@pytest.mark.parametrize("n,prec,interp", [(64, 0, 1), (64, 1, 1), (128, 0, 1), (64, 0, 3), (64, 1, 3), (128, 0, 3)])
+def test_rotated_lattice(ur, orc, n, prec, interp):
+    """A lattice oriented by a general rotation, the cell sampled trilinearly
+    or by the cubic B-spline: the fused forward path against the whole
+    oracle (O2r, then O4-O8), the generated density voxel by voxel (the
+    cubic case's spline coefficients, stored in the working precision, are
+    up to 2.4 times the cell's largest value here: same bounds); the adjoint
+    and zoomed levels refuse rotated lattices."""
     import torch
     from dataclasses import replace
     base = W.small(n, c=8, n_atoms=9, seed=71, radius=0.4 * n, nbins=60, prec=prec)
-    wl = replace(base, cell=base.cell.with_rot(W.rotation([1.0, 2.0, 3.0], 0.7)))
-    _say(f"rotated lattice {n}^3 prec={prec}")
+    wl = replace(base, cell=base.cell.with_rot(W.rotation([1.0, 2.0, 3.0], 0.7), interp))
+    _say(f"rotated lattice {n}^3 prec={prec} interp={interp}")
     ref = orc.simulate(wl)
     got = run_simulate(ur, wl)
     compare_bins(got, ref, F32_BIN if prec == 0 else F64_BIN, "rotated", n=n)

@@ -650,6 +650,50 @@ def test_rotated_lattice_matches_scipy_map_coordinates(oracle_lib):
     assert np.all(got[~inside] == 0.0)
 
 
+def test_cubic_spline_coefficients_match_scipy_spline_filter(oracle_lib):
+    """The periodic cubic B-spline coefficients of a cell against
+    scipy.ndimage.spline_filter (order 3, 'grid-wrap'), and the defining
+    property: filtered by (1, 4, 1)/6 along each axis they give the cell."""
+    import oracle
+    from scipy.ndimage import spline_filter
+    cell, _ = _rot_case()
+    cg = oracle.cell_synth(cell)
+    C = oracle.bspline_coefficients(cg)
+    assert np.max(np.abs(C - spline_filter(cg, order=3, mode="grid-wrap"))) <= 1e-12 * np.max(np.abs(cg))
+    back = C
+    for ax in range(3):
+        back = (np.roll(back, 1, axis=ax) + 4.0 * back + np.roll(back, -1, axis=ax)) / 6.0
+    assert np.max(np.abs(back - cg)) <= 1e-12 * np.max(np.abs(cg))
+
+
+def test_cubic_rotated_lattice(oracle_lib):
+    """Cubic B-spline sampling: through the cell values at integer points
+    (identity: the aligned tiling; quarter turn: the trilinear result, both
+    exact up to rounding), and a general orientation against
+    scipy.ndimage.map_coordinates (order 3, 'grid-wrap') at every inside voxel
+    of a 24^3 box."""
+    import oracle
+    from scipy.ndimage import map_coordinates
+    cell, mask = _rot_case()
+    cg = oracle.cell_synth(cell)
+    scale = np.max(np.abs(cg))
+    n = 32
+    assert np.max(np.abs(oracle.ed1_rot(n, cg, mask, np.eye(3), 3) - oracle.ed1(n, cg, mask))) <= 1e-12 * scale
+    Rq = np.array([[0.0, -1.0, 0.0], [1.0, 0.0, 0.0], [0.0, 0.0, 1.0]])
+    assert np.max(np.abs(oracle.ed1_rot(n, cg, mask, Rq, 3) - oracle.ed1_rot(n, cg, mask, Rq, 1))) <= 1e-12 * scale
+    n = 24
+    R = W.rotation([1.0, 2.0, 3.0], 0.7)
+    got = oracle.ed1_rot(n, cg, mask, R, 3)
+    d = np.arange(n) - n // 2
+    dx, dy, dz = np.meshgrid(d, d, d, indexing="ij")
+    inside = dx * dx + dy * dy + dz * dz <= int(mask.p0)
+    U = R @ np.stack([dx[inside], dy[inside], dz[inside]]).astype(np.float64)
+    ref = map_coordinates(cg, U, order=3, mode="grid-wrap")
+    assert np.max(np.abs(got[inside] - ref)) <= 1e-12 * scale
+    assert np.all(got[~inside] == 0.0)
+    assert np.max(np.abs(got - oracle.ed1_rot(n, cg, mask, R, 1))) > 1e-3 * scale   # not the trilinear sampling
+
+
 # ---------------------------------------------------------------------------
 # O15: voxel form factor (a density uniform over each voxel)
 # ---------------------------------------------------------------------------

@@ -50,6 +50,7 @@ class Cell:
     sigma: np.ndarray
     background: float = 0.0
     rot: Optional[np.ndarray] = None   # 3x3 lattice orientation (None: aligned with the box)
+    interp: int = 1                    # sampling of a rotated cell: 1 trilinear, 3 cubic B-spline
 
     @property
     def n_atoms(self) -> int:
@@ -58,8 +59,9 @@ class Cell:
     def with_amp(self, amp: np.ndarray) -> "Cell":
         return replace(self, amp=np.ascontiguousarray(amp, dtype=np.float64))
 
-    def with_rot(self, rot: Optional[np.ndarray]) -> "Cell":
-        return replace(self, rot=None if rot is None else np.ascontiguousarray(rot, dtype=np.float64).reshape(3, 3))
+    def with_rot(self, rot: Optional[np.ndarray], interp: int = 1) -> "Cell":
+        return replace(self, rot=None if rot is None else np.ascontiguousarray(rot, dtype=np.float64).reshape(3, 3),
+                       interp=int(interp))
 
 
 @dataclass(frozen=True)
