@@ -420,6 +420,11 @@ def main():
         extras["rotated_lattice"] = {"ms_per_step": round(msr, 4), "voxels_per_s": wl.n ** 3 / (msr * 1e-3),
                                      "pass_z_ms": pass_timing(plan, lambda: plan.simulate(rcell, wl.mask, wl.zoom, hist),
                                                               5, torch)["pass_z"]["avg_ms"]}
+        # a polycrystalline particle: 16 grains of random orientation (trilinear)
+        gs, gr = W.random_grains(16, 16, 0.35 * wl.n)
+        gcell = ur.DeviceCell.from_host(wl.cell.with_grains(gs, gr, 1))
+        msg, _ = time_steps(lambda: plan.simulate(gcell, wl.mask, wl.zoom, hist), max(3, args.steps // 2), 2, torch)
+        extras["polycrystal_16_grains"] = {"ms_per_step": round(msg, 4), "voxels_per_s": wl.n ** 3 / (msg * 1e-3)}
         # the same with the cell sampled by the cubic B-spline (64 coefficients per voxel)
         ccell = ur.DeviceCell.from_host(wl.cell.with_rot(W.rotation([1.0, 2.0, 3.0], 0.7), 3))
         msc, _ = time_steps(lambda: plan.simulate(ccell, wl.mask, wl.zoom, hist), max(3, args.steps // 2), 2, torch)

@@ -95,7 +95,16 @@ typedef struct { int32_t kind; int64_t p0; int64_t p1; } ur_mask;
  * the 4 x 4 x 4 neighbouring coefficients with the cubic B-spline weights
  * of the fractional offsets: the order-3 spline of the interpolation
  * routine the paper names); other values fail with UR_ERR_INVALID.
- * Rotated lattices run the forward paths at zoom factor 1 on
+ * n_grains (0 .. 16) > 0 makes a polycrystalline particle (the rotated
+ * grid serves to build crystallites of random orientations; the outlook
+ * names polycrystalline grains): HOST grain_seed[3*n_grains] integer voxel
+ * offsets from the particle centre and grain_rot[9*n_grains] orientations
+ * (row-major, finite); the inside voxel at offset d belongs to the grain
+ * whose seed is nearest (squared integer distance, ties to the lower grain
+ * index) and takes the cell at u = R_g d, sampled as chosen by interp; rot
+ * must then be NULL.  Seeds that are not integers or exceed 2^20 in
+ * magnitude fail with UR_ERR_INVALID.
+ * Rotated lattices and grains run the forward paths at zoom factor 1 on
  * real (UR_R2C) plans; the adjoint refuses them (UR_ERR_UNSUPPORTED). */
 typedef struct {
   int32_t c;
@@ -106,6 +115,9 @@ typedef struct {
   double background;
   const double* rot;
   int32_t interp;
+  int32_t n_grains;
+  const double* grain_seed;
+  const double* grain_rot;
 } ur_cell;
 
 /* Zoom level (workflow step 3): the ED-1 grid of edge n1 is block-summed by

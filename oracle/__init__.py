@@ -6,7 +6,7 @@ correct statement of the computation, written from the paper:
 
 * O1  unit-cell density (workflow step 1; "Electron density generation")
 * O2  ED-1 = tiled cell x particle mask (workflow step 2); O2r with a rotated lattice
-  (trilinear or cubic B-spline sampling of the cell)
+  (trilinear or cubic B-spline sampling of the cell); O2g polycrystalline grains
 * O3  zoomed-out ED-2/ED-3 by block integration and zero padding (step 3)
 * O4  3D transform, eq. 1 (axis by axis, as eq. 2 separates it)
 * O5-O8  |Q| map, integer-threshold bins, per-bin mean and SEM (step 5)
@@ -71,6 +71,8 @@ def lib():
                              ctypes.c_longlong, _D]
         L.or_ed1_rot.argtypes = [ctypes.c_int, ctypes.c_int, _D, ctypes.c_int, ctypes.c_longlong,
                                  ctypes.c_longlong, _D, ctypes.c_int, _D]
+        L.or_ed1_grains.argtypes = [ctypes.c_int, ctypes.c_int, _D, ctypes.c_int, ctypes.c_longlong,
+                                    ctypes.c_longlong, ctypes.c_int, _LL, _D, ctypes.c_int, _D]
         L.or_zoom.argtypes = [ctypes.c_int, ctypes.c_int, _D, ctypes.c_int, ctypes.c_longlong,
                               ctypes.c_longlong, ctypes.c_int, ctypes.c_int, _D]
         L.or_fft3d.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_int]
@@ -189,6 +191,24 @@ def ed1_rot(n: int, cell_grid: np.ndarray, mask, rot: np.ndarray, interp: int = 
     return out
 
 
+def ed1_grains(n: int, cell_grid: np.ndarray, mask, seeds: np.ndarray, rots: np.ndarray, interp: int = 1) -> np.ndarray:
+    """O2g: polycrystalline ED-1 (the rotated grid builds crystallites of
+    random orientation; the outlook names polycrystalline grains): each
+    inside voxel belongs to the grain of the nearest integer seed (ties to
+    the lower index) and samples the cell at u = R_g d as ``ed1_rot``."""
+    assert interp in (1, 3)
+    c = cell_grid.shape[0]
+    cg = np.ascontiguousarray(cell_grid if interp == 1 else bspline_coefficients(cell_grid), dtype=np.float64)
+    S = np.ascontiguousarray(np.rint(seeds), dtype=np.int64).reshape(-1)
+    R = np.ascontiguousarray(rots, dtype=np.float64).reshape(-1)
+    g = S.size // 3
+    assert R.size == 9 * g and g >= 1
+    out = np.empty((n, n, n))
+    lib().or_ed1_grains(int(n), int(c), _dp(cg), int(mask.kind), int(mask.p0), int(mask.p1), int(g),
+                        S.ctypes.data_as(_LL), _dp(R), int(interp), _dp(out))
+    return out
+
+
 def zoomed(n1: int, cell_grid: np.ndarray, mask, f: int, nk: int) -> np.ndarray:
     c = cell_grid.shape[0]
     cg = np.ascontiguousarray(cell_grid, dtype=np.float64)
@@ -202,6 +222,10 @@ def density(wl, cell_grid: Optional[np.ndarray] = None) -> np.ndarray:
     """Real-space box of a workload: ED-1 (factor 1) or a zoomed level."""
     if cell_grid is None:
         cell_grid = cell_synth(wl.cell)
+    seeds = getattr(wl.cell, "grain_seed", None)
+    if seeds is not None:
+        assert wl.zoom.factor == 1 and wl.zoom.n1 == wl.n, "grains are defined for ED-1"
+        return ed1_grains(wl.n, cell_grid, wl.mask, seeds, wl.cell.grain_rot, int(getattr(wl.cell, "interp", 1)))
     rot = getattr(wl.cell, "rot", None)
     if rot is not None:
         assert wl.zoom.factor == 1 and wl.zoom.n1 == wl.n, "rotated lattices are defined for ED-1"

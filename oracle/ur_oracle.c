@@ -167,11 +167,15 @@ static double bspline3(double x)
     return (4.0 - 6.0 * a * a + 3.0 * a * a * a) / 6.0;
 }
 
-/* order 1: `cell` holds the cell values, trilinear; order 3: `cell` holds the
+/* Polycrystalline ED-1: the inside voxel at offset d belongs to the grain g
+ * whose integer seed s_g is nearest (squared distance, ties to the lower
+ * index) and takes the cell at u = R_g d (R_g row-major, 9 per grain).
+ * order 1: `cell` holds the cell values, trilinear; order 3: `cell` holds the
  * periodic cubic B-spline coefficients C, value = sum over the 4^3 nearest
- * coefficients of C[i] B3(u0 - i0) B3(u1 - i1) B3(u2 - i2) */
-void or_ed1_rot(int n, int c, const double* cell, int kind, long long p0, long long p1, const double* R,
-                int order, double* rho)
+ * coefficients of C[i] B3(u0 - i0) B3(u1 - i1) B3(u2 - i2).  One grain with
+ * any seed is a single rotated lattice. */
+void or_ed1_grains(int n, int c, const double* cell, int kind, long long p0, long long p1, int ngrain,
+                   const long long* seed, const double* Rg, int order, double* rho)
 {
     const long long h = n / 2;
 #pragma omp parallel for schedule(static)
@@ -181,6 +185,14 @@ void or_ed1_rot(int n, int c, const double* cell, int kind, long long p0, long l
                 double* out = &rho[((size_t)x * n + y) * n + z];
                 const long long dx = x - h, dy = y - h, dz = z - h;
                 if (!or_mask_inside(kind, p0, p1, dx, dy, dz)) { *out = 0.0; continue; }
+                int g = 0;
+                long long best = -1;
+                for (int k = 0; k < ngrain; ++k) {
+                    const long long ex = dx - seed[3 * k], ey = dy - seed[3 * k + 1], ez = dz - seed[3 * k + 2];
+                    const long long d2 = ex * ex + ey * ey + ez * ez;
+                    if (best < 0 || d2 < best) { best = d2; g = k; }
+                }
+                const double* R = Rg + 9 * g;
                 double u[3];
                 for (int i = 0; i < 3; ++i)
                     u[i] = (R[3 * i] * (double)dx + R[3 * i + 1] * (double)dy) + R[3 * i + 2] * (double)dz;
@@ -211,6 +223,13 @@ void or_ed1_rot(int n, int c, const double* cell, int kind, long long p0, long l
                     }
                 *out = lerp(lerp(a[0][0], a[0][1], t[1]), lerp(a[1][0], a[1][1], t[1]), t[0]);
             }
+}
+
+void or_ed1_rot(int n, int c, const double* cell, int kind, long long p0, long long p1, const double* R,
+                int order, double* rho)
+{
+    const long long origin[3] = {0, 0, 0};
+    or_ed1_grains(n, c, cell, kind, p0, p1, 1, origin, R, order, rho);
 }
 
 /* ------------------------------------------------------------------------ */

@@ -34,7 +34,8 @@ class UrMask(_c.Structure):
 class UrCell(_c.Structure):
     _fields_ = [("c", _c.c_int32), ("n_atoms", _c.c_int32), ("xyz", _vp), ("amp", _vp),
                 ("sigma", _vp), ("background", _c.c_double), ("rot", _c.POINTER(_c.c_double)),
-                ("interp", _c.c_int32)]
+                ("interp", _c.c_int32), ("n_grains", _c.c_int32), ("grain_seed", _c.POINTER(_c.c_double)),
+                ("grain_rot", _c.POINTER(_c.c_double))]
 
 
 class UrZoom(_c.Structure):
@@ -169,6 +170,8 @@ class DeviceCell:
     background: float
     rot: Optional[np.ndarray] = None
     interp: int = 1
+    grain_seed: Optional[np.ndarray] = None     # host [G*3], integer voxel offsets
+    grain_rot: Optional[np.ndarray] = None      # host [G*9]
 
     @staticmethod
     def from_host(cell) -> "DeviceCell":
@@ -184,13 +187,21 @@ class DeviceCell:
             sig = torch.ones(1, dtype=torch.float64, device=dev)
         rot = getattr(cell, "rot", None)
         rot = None if rot is None else np.ascontiguousarray(rot, dtype=np.float64).reshape(9)
-        return DeviceCell(int(cell.c), xyz, amp, sig, float(cell.background), rot, int(getattr(cell, "interp", 1)))
+        gs = getattr(cell, "grain_seed", None)
+        gr = getattr(cell, "grain_rot", None)
+        gs = None if gs is None else np.ascontiguousarray(gs, dtype=np.float64).reshape(-1)
+        gr = None if gr is None else np.ascontiguousarray(gr, dtype=np.float64).reshape(-1)
+        return DeviceCell(int(cell.c), xyz, amp, sig, float(cell.background), rot, int(getattr(cell, "interp", 1)),
+                          gs, gr)
 
     def struct(self, amp=None) -> UrCell:
         a = self.amp if amp is None else amp
         n = int(a.numel()) if self.xyz.numel() == 3 * a.numel() else 0
         rot = None if self.rot is None else self.rot.ctypes.data_as(_c.POINTER(_c.c_double))
-        return UrCell(self.c, n, _ptr(self.xyz), _ptr(a), _ptr(self.sigma), self.background, rot, self.interp)
+        dp = lambda v: None if v is None else v.ctypes.data_as(_c.POINTER(_c.c_double))
+        ng = 0 if self.grain_seed is None else int(self.grain_seed.size // 3)
+        return UrCell(self.c, n, _ptr(self.xyz), _ptr(a), _ptr(self.sigma), self.background, rot, self.interp,
+                      ng, dp(self.grain_seed), dp(self.grain_rot))
 
 
 def mask_struct(mask) -> UrMask:

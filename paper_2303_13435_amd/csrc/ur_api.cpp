@@ -600,18 +600,40 @@ static ur_status check_cell(const ur_cell* c) {
       if (!isfinite(c->rot[i])) return fail(UR_ERR_INVALID, "lattice rotation entry %d is not finite", i);
   if (c->interp != 0 && c->interp != 1 && c->interp != 3)
     return fail(UR_ERR_INVALID, "interp = %d: 1 (trilinear) or 3 (cubic B-spline)", c->interp);
+  if (c->n_grains < 0 || c->n_grains > kMaxGrains)
+    return fail(UR_ERR_INVALID, "n_grains = %d outside [0, %d]", c->n_grains, kMaxGrains);
+  if (c->n_grains > 0) {
+    if (c->rot) return fail(UR_ERR_INVALID, "give either rot or grains, not both");
+    if (!c->grain_seed || !c->grain_rot) return fail(UR_ERR_INVALID, "grain arrays must be non-null");
+    for (int i = 0; i < 3 * c->n_grains; ++i) {
+      const double v = c->grain_seed[i];
+      if (!isfinite(v) || v != floor(v) || fabs(v) > 1048576.0)
+        return fail(UR_ERR_INVALID, "grain seed entry %d must be an integer of magnitude <= 2^20", i);
+    }
+    for (int i = 0; i < 9 * c->n_grains; ++i)
+      if (!isfinite(c->grain_rot[i])) return fail(UR_ERR_INVALID, "grain orientation entry %d is not finite", i);
+  }
   return UR_OK;
 }
+
+// a lattice that is not aligned with the box: one orientation or grains
+static bool oriented(const ur_cell* c) { return c->rot || c->n_grains > 0; }
 
 // A rotated lattice runs the ED-1 generator of real plans only; copies its
 // matrix into the z-pass arguments.
 static ur_status set_rotation(const ur_plan* p, const ur_cell* cell, const ur_zoom* zoom, ZArgs& za) {
-  if (!cell->rot) return UR_OK;
+  if (!oriented(cell)) return UR_OK;
   if (zoom->factor != 1) return fail(UR_ERR_UNSUPPORTED, "rotated lattices run at zoom factor 1");
   if (p->flags & UR_C2C) return fail(UR_ERR_UNSUPPORTED, "rotated lattices run on real (UR_R2C) plans");
   za.rotated = 1;
   za.cubic = cell->interp == 3 ? 1 : 0;
-  for (int i = 0; i < 9; ++i) za.rot[i] = cell->rot[i];
+  za.ngrain = cell->n_grains;
+  if (cell->rot)
+    for (int i = 0; i < 9; ++i) za.rot[i] = cell->rot[i];
+  for (int g = 0; g < cell->n_grains; ++g) {
+    for (int i = 0; i < 3; ++i) za.gseed[g][i] = (int)cell->grain_seed[3 * g + i];
+    for (int i = 0; i < 9; ++i) za.grot[g][i] = cell->grain_rot[9 * g + i];
+  }
   return UR_OK;
 }
 
@@ -672,7 +694,7 @@ static ur_status prepare_cell(ur_plan* p, const ur_cell* cell, int f, CellTables
   t.fold_part = (double*)(b + o_fp);
   UR_HIP(launch_cell_profiles(cell->c, cell->n_atoms, cell->xyz, cell->sigma, t.prof, s));
   UR_HIP(launch_cell_sum(cell->c, cell->n_atoms, cell->amp, t.prof, cell->background, t.cell64, s));
-  if (cell->rot && cell->interp == 3) UR_HIP(launch_bspline_cell(cell->c, t.cell64, s));   // spline coefficients
+  if (oriented(cell) && cell->interp == 3) UR_HIP(launch_bspline_cell(cell->c, t.cell64, s));   // spline coefficients
   UR_HIP(launch_cell_tables(p->prec, cell->c, f, t.cell64, t.cellT, t.pre, t.cb, t.cbn, s));
   return UR_OK;
 }
@@ -903,7 +925,7 @@ ur_status ur_simulate(ur_plan* p, const ur_cell* cell, const ur_mask* mask, cons
   }
   p->pass_bytes[P_Z] = live_rows(p, g) * p->nkz * p->cs + 16.0 * nzb;
   const ur_status st = run_y_x(p, g, p->ws + lay.A, p->ws + lay.B, lay, h, nzb, s);
-  if (st == UR_OK && zoom->factor == 1 && zoom->n1 == p->n && !(p->flags & UR_C2C) && !cell->rot) {
+  if (st == UR_OK && zoom->factor == 1 && zoom->n1 == p->n && !(p->flags & UR_C2C) && !oriented(cell)) {
     p->keep_valid = true;
     p->keep_m = g.m;
     p->keep_c = cell->c;
@@ -1192,7 +1214,7 @@ static ur_status adjoint_run(ur_plan* p, const void* rho, const ur_cell* cell, c
   if (p->nbins < 1) return fail(UR_ERR_STATE, "no bins set on the plan");
   if ((rho != nullptr) == (cell != nullptr)) return fail(UR_ERR_INVALID, "give exactly one of rho and cell");
   if (grad_amp && !cell) return fail(UR_ERR_INVALID, "grad_amp needs the cell description");
-  if (cell && cell->rot) return fail(UR_ERR_UNSUPPORTED, "the adjoint runs for lattices aligned with the box (rot = NULL)");
+  if (cell && oriented(cell)) return fail(UR_ERR_UNSUPPORTED, "the adjoint runs for lattices aligned with the box (rot = NULL, no grains)");
   if (p->dSinc) return fail(UR_ERR_UNSUPPORTED, "the adjoint runs without the voxel form factor");
   if (p->mixed) return fail(UR_ERR_UNSUPPORTED, "the adjoint runs on power-of-two boxes");
   if (!grad_rho && !grad_amp) return UR_OK;

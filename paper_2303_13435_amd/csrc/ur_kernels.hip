@@ -199,6 +199,7 @@ struct Pencil {
   int zin_lo, zin_hi;       // coarse z of the blocks wholly inside the mask
   // rotated lattice (f == 1): u = rot (dx, dy, dz), dz = z + zoff; (ux, uy, uz) = rot (dx, dy, 0)
   double ux, uy, uz;
+  int pdx, pdy;             // pencil offset from the particle centre (grains)
 
   __device__ __forceinline__ void init(const ZArgs& a, long long X, long long Y) {
     const Level& L = a.L;
@@ -219,6 +220,8 @@ struct Pencil {
         ux = __dadd_rn(__dmul_rn(a.rot[0], dx), __dmul_rn(a.rot[1], dy));
         uy = __dadd_rn(__dmul_rn(a.rot[3], dx), __dmul_rn(a.rot[4], dy));
         uz = __dadd_rn(__dmul_rn(a.rot[6], dx), __dmul_rn(a.rot[7], dy));
+        pdx = (int)(X - L.o - L.h);
+        pdy = (int)(Y - L.o - L.h);
       }
     } else {
       long long ax, bx, ay, by;
@@ -265,12 +268,36 @@ struct Pencil {
   // ED-1 voxel of a rotated lattice: the cell at u = rot d, trilinear
   // between its voxels with periodic wrap (interpolated along the cell's
   // third index, then the second, then the first); zero outside the mask
+  // cell coordinate u = R d of inside voxel z: R the lattice's orientation,
+  // or with grains that of the seed nearest to d (squared integer distance,
+  // ties to the lower index); products and sums rounded one by one
+  __device__ __forceinline__ void coords(const ZArgs& a, int z, double& u, double& v, double& w) const {
+    const double dz = (double)(z + zoff);
+    if (a.ngrain == 0) {
+      u = __dadd_rn(ux, __dmul_rn(a.rot[2], dz));
+      v = __dadd_rn(uy, __dmul_rn(a.rot[5], dz));
+      w = __dadd_rn(uz, __dmul_rn(a.rot[8], dz));
+      return;
+    }
+    const long long iz = z + zoff;
+    int best = 0;
+    long long bd = 0;
+    for (int g = 0; g < a.ngrain; ++g) {
+      const long long ex = pdx - a.gseed[g][0], ey = pdy - a.gseed[g][1], ez = iz - a.gseed[g][2];
+      const long long d2 = ex * ex + ey * ey + ez * ez;
+      if (g == 0 || d2 < bd) { bd = d2; best = g; }
+    }
+    const double* R = a.grot[best];
+    const double dx = (double)pdx, dy = (double)pdy;
+    u = __dadd_rn(__dadd_rn(__dmul_rn(R[0], dx), __dmul_rn(R[1], dy)), __dmul_rn(R[2], dz));
+    v = __dadd_rn(__dadd_rn(__dmul_rn(R[3], dx), __dmul_rn(R[4], dy)), __dmul_rn(R[5], dz));
+    w = __dadd_rn(__dadd_rn(__dmul_rn(R[6], dx), __dmul_rn(R[7], dy)), __dmul_rn(R[8], dz));
+  }
+
   __device__ __forceinline__ T value_rot(const ZArgs& a, int z) const {
     if (z < zlo || z > zhi) return (T)0;
-    const double dz = (double)(z + zoff);
-    const double u = __dadd_rn(ux, __dmul_rn(a.rot[2], dz));
-    const double v = __dadd_rn(uy, __dmul_rn(a.rot[5], dz));
-    const double w = __dadd_rn(uz, __dmul_rn(a.rot[8], dz));
+    double u, v, w;
+    coords(a, z, u, v, w);
     const double fu = floor(u), fv = floor(v), fw = floor(w);
     const T tu = (T)(u - fu), tv = (T)(v - fv), tw = (T)(w - fw);
     const int c = cmask + 1;
@@ -297,10 +324,8 @@ struct Pencil {
   // of the fractional offsets (third index innermost)
   __device__ __forceinline__ T value_rot3(const ZArgs& a, int z) const {
     if (z < zlo || z > zhi) return (T)0;
-    const double dz = (double)(z + zoff);
-    const double u = __dadd_rn(ux, __dmul_rn(a.rot[2], dz));
-    const double v = __dadd_rn(uy, __dmul_rn(a.rot[5], dz));
-    const double w = __dadd_rn(uz, __dmul_rn(a.rot[8], dz));
+    double u, v, w;
+    coords(a, z, u, v, w);
     const double fu = floor(u), fv = floor(v), fw = floor(w);
     T wu[4], wv[4], ww[4];
     bspline_weights<T>((T)(u - fu), wu);

@@ -23,6 +23,8 @@ enum ZMode { Z_GEN_R2C = 0, Z_LOAD_R2C = 1, Z_GEN_C2C = 2, Z_LOAD_C2C = 3, Z_ZOO
 // when XArgs::sinc is set) weight every intensity by the voxel form factor.
 enum XMode { X_FFT_BIN = 0, X_BIN_ONLY = 1, X_FFT_STORE = 2, X_ADJ = 3, X_FFT_BIN_SINC = 4, X_BIN_ONLY_SINC = 5 };
 
+constexpr int kMaxGrains = 16;
+
 struct ZArgs {
   void* A;                  // out: [x - ax0][kz][y] complex
   long long ax0;            // first plane held by A
@@ -42,6 +44,9 @@ struct ZArgs {
   int rotated;              // ROT generation: the cell is sampled at u = rot d
   double rot[9];            // row-major
   int cubic;                // ROT: cellT holds cubic B-spline coefficients (64-tap sampling)
+  int ngrain;               // ROT with grains: voxel d takes the orientation of its nearest seed
+  int gseed[kMaxGrains][3]; // seed offsets from the particle centre (voxels)
+  double grot[kMaxGrains][9];
 };
 
 struct YArgs {

@@ -694,6 +694,39 @@ def test_cubic_rotated_lattice(oracle_lib):
     assert np.max(np.abs(got - oracle.ed1_rot(n, cg, mask, R, 1))) > 1e-3 * scale   # not the trilinear sampling
 
 
+@pytest.mark.parametrize("interp", [1, 3])
+def test_grains_are_voronoi_pieces_of_rotated_lattices(oracle_lib, interp):
+    """O2g: the grain of every inside voxel against a brute-force nearest
+    seed (numpy argmin over squared distances, ties to the lower index, with
+    two seeds placed so that the plane between them is tied), and each
+    grain's voxels equal to the single rotated lattice of its orientation;
+    all grains aligned give the aligned tiling."""
+    import oracle
+    n = 32
+    cell, mask = _rot_case()
+    cg = oracle.cell_synth(cell)
+    seeds = np.array([[-4, 0, 0], [4, 0, 0], [0, 7, -3], [2, -6, 5]], dtype=np.float64)
+    rots = np.stack([W.rotation([1.0, 2.0, 3.0], 0.7), W.rotation([0.0, 1.0, 0.0], 1.3),
+                     W.rotation([1.0, -1.0, 0.5], 2.1), W.rotation([0.3, 0.2, -1.0], 0.4)])
+    got = oracle.ed1_grains(n, cg, mask, seeds, rots, interp)
+    d = np.arange(n) - n // 2
+    dx, dy, dz = np.meshgrid(d, d, d, indexing="ij")
+    inside = dx * dx + dy * dy + dz * dz <= int(mask.p0)
+    D2 = np.stack([(dx - s[0]) ** 2 + (dy - s[1]) ** 2 + (dz - s[2]) ** 2 for s in seeds.astype(np.int64)])
+    owner = np.argmin(D2, axis=0)
+    tied = (D2[0] == D2[1]) & (D2[0] <= D2.min(axis=0)) & inside
+    assert tied.sum() > 50 and np.all(owner[tied] == 0)
+    assert np.all(got[~inside] == 0.0)
+    for g in range(len(seeds)):
+        sel = inside & (owner == g)
+        assert sel.sum() > 100
+        single = oracle.ed1_rot(n, cg, mask, rots[g], interp)
+        assert np.array_equal(got[sel], single[sel]), g
+    eye = np.stack([np.eye(3)] * len(seeds))
+    aligned = oracle.ed1_grains(n, cg, mask, seeds, eye, interp)
+    assert np.max(np.abs(aligned - oracle.ed1(n, cg, mask))) <= 1e-12 * np.max(np.abs(cg))
+
+
 # ---------------------------------------------------------------------------
 # O15: voxel form factor (a density uniform over each voxel)
 # ---------------------------------------------------------------------------

@@ -51,6 +51,8 @@ class Cell:
     background: float = 0.0
     rot: Optional[np.ndarray] = None   # 3x3 lattice orientation (None: aligned with the box)
     interp: int = 1                    # sampling of a rotated cell: 1 trilinear, 3 cubic B-spline
+    grain_seed: Optional[np.ndarray] = None   # [G, 3] integer offsets of grain seeds from the particle centre
+    grain_rot: Optional[np.ndarray] = None    # [G, 3, 3] grain orientations
 
     @property
     def n_atoms(self) -> int:
@@ -58,6 +60,11 @@ class Cell:
 
     def with_amp(self, amp: np.ndarray) -> "Cell":
         return replace(self, amp=np.ascontiguousarray(amp, dtype=np.float64))
+
+    def with_grains(self, seeds: np.ndarray, rots: np.ndarray, interp: int = 1) -> "Cell":
+        return replace(self, rot=None, interp=int(interp),
+                       grain_seed=np.ascontiguousarray(seeds, dtype=np.float64).reshape(-1, 3),
+                       grain_rot=np.ascontiguousarray(rots, dtype=np.float64).reshape(-1, 3, 3))
 
     def with_rot(self, rot: Optional[np.ndarray], interp: int = 1) -> "Cell":
         return replace(self, rot=None if rot is None else np.ascontiguousarray(rot, dtype=np.float64).reshape(3, 3),
@@ -323,6 +330,28 @@ def rotation(axis: Sequence[float], angle: float) -> np.ndarray:
     k = k / np.linalg.norm(k)
     K = np.array([[0.0, -k[2], k[1]], [k[2], 0.0, -k[0]], [-k[1], k[0], 0.0]])
     return np.eye(3) + math.sin(angle) * K + (1.0 - math.cos(angle)) * (K @ K)
+
+
+def random_grains(seed: int, count: int, radius: float):
+    """count grain seeds (distinct integer points within `radius` of the
+    particle centre) and orientations uniform over the rotations (unit
+    quaternions from four normal deviates): input data for a polycrystalline
+    particle."""
+    rng = np.random.default_rng(seed)
+    r = int(math.floor(radius))
+    pts = []
+    while len(pts) < count:
+        p = tuple(int(v) for v in rng.integers(-r, r + 1, 3))
+        if p[0] * p[0] + p[1] * p[1] + p[2] * p[2] <= radius * radius and p not in pts:
+            pts.append(p)
+    rots = []
+    for _ in range(count):
+        q = rng.standard_normal(4)
+        w, x, y, z = q / np.linalg.norm(q)
+        rots.append(np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - z * w), 2 * (x * z + y * w)],
+                              [2 * (x * y + z * w), 1 - 2 * (x * x + z * z), 2 * (y * z - x * w)],
+                              [2 * (x * z - y * w), 2 * (y * z + x * w), 1 - 2 * (x * x + y * y)]]))
+    return np.array(pts, dtype=np.float64), np.array(rots)
 
 
 def volume_fractions(radii: Sequence[float], r0: float, width: float) -> np.ndarray:
