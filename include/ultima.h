@@ -346,6 +346,26 @@ typedef struct {
 } ur_ewald;
 ur_status ur_ewald_image(ur_plan* plan, const void* spectrum, const ur_ewald* geom, double* image, void* stream);
 
+/* Peak integrals for the degree of crystallinity (Results and Discussion: the
+ * simulation assumes perfect crystallinity, so the integral intensity under
+ * a simulated diffraction peak stands for 100 % crystallinity, in absolute
+ * units or relative to the small-angle signal; a measured peak integral
+ * divided by it gives the degree of crystallinity).  For each window
+ * w = [q_lo, q_hi] (HOST windows[2*nwin], nm^-1, q_lo < q_hi) the bins of
+ * the curve whose centres (e_b + e_b+1)/2 lie in the window and whose mean
+ * is not NaN (empty bins are skipped) give, with widths d_b = e_b+1 - e_b:
+ *   out[3w+0] peak  = sum_b (mean_b - base(q_b)) d_b, base the straight line
+ *             through the (centre, mean) of the window's first and last bins,
+ *   out[3w+1] total = sum_b mean_b d_b,
+ *   out[3w+2] the number of bins used;
+ * fewer than two bins give NaN peak and total.  edges: DEVICE nbins+1
+ * (strictly increasing), mean: DEVICE nbins, out: DEVICE 3*nwin doubles.
+ * No allocation (capturable).  UR_ERR_INVALID for nbins outside [1, 4096],
+ * nwin outside [1, 64], a window with q_lo >= q_hi or non-finite ends, or a
+ * null pointer. */
+ur_status ur_peak_integrals(int32_t nbins, const double* edges, const double* mean, int32_t nwin,
+                            const double* windows, double* out, void* stream);
+
 /* Polydisperse ensemble (Results and Discussion: polydispersity described by
  * some 200 volume-weighted contributions, one simulation each).  For nboxes
  * boxes that share one bin set (one particle each, summed incoherently),

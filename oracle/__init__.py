@@ -19,6 +19,8 @@ correct statement of the computation, written from the paper:
 * O15 voxel form factor (the voxel-sized sinc; reading in ``voxel_form``)
 * O16 Ewald-sphere detector image (Q-calculation and spherical averaging;
   reading in ``ewald_image``)
+* O17 peak integrals for the degree of crystallinity (Results and
+  Discussion; reading in ``peak_integrals``)
 
 The heavy loops live in ``ur_oracle.c`` (plain C, FP64, OpenMP over
 independent lines); this module marshals numpy arrays and holds the small
@@ -616,6 +618,36 @@ def ewald_image(F: np.ndarray, voxel: float, geo) -> np.ndarray:
                     val += wt * I[(g0[..., 0] + a) % n, (g0[..., 1] + b) % n, (g0[..., 2] + c) % n]
         image += wj * val
     return image
+
+
+# ---------------------------------------------------------------------------
+# O17  peak integrals (degree of crystallinity)
+# ---------------------------------------------------------------------------
+
+def peak_integrals(edges: np.ndarray, mean: np.ndarray, windows) -> np.ndarray:
+    """Integral intensity under a diffraction peak (Results and Discussion:
+    the simulated, perfectly crystalline peak integral stands for 100 %
+    crystallinity).  Reading: per window [q_lo, q_hi], the populated bins
+    whose centres lie in it; the background is the straight line through
+    the (centre, mean) of the first and last of them; peak = sum over them
+    of (mean - background) * width, total = sum of mean * width.  Rows
+    (peak, total, bins used); NaN below two bins."""
+    e = np.asarray(edges, dtype=np.float64)
+    m = np.asarray(mean, dtype=np.float64)
+    q = 0.5 * (e[:-1] + e[1:])
+    width = e[1:] - e[:-1]
+    out = []
+    for lo, hi in np.asarray(windows, dtype=np.float64).reshape(-1, 2):
+        idx = [b for b in range(len(m)) if lo <= q[b] <= hi and not np.isnan(m[b])]
+        if len(idx) < 2:
+            out.append((np.nan, np.nan, float(len(idx))))
+            continue
+        f, l = idx[0], idx[-1]
+        base = lambda x: m[f] + (m[l] - m[f]) * (x - q[f]) / (q[l] - q[f])
+        peak = sum((m[b] - base(q[b])) * width[b] for b in idx)
+        total = sum(m[b] * width[b] for b in idx)
+        out.append((peak, total, float(len(idx))))
+    return np.array(out)
 
 
 def chi2(mean: np.ndarray, count: np.ndarray, target: np.ndarray, rel_sigma: float = 0.01) -> float:

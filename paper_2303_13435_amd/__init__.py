@@ -84,6 +84,7 @@ _SIGS = {
     "ur_merge_zooms": [_c.c_int32, _c.POINTER(UrHist), _c.POINTER(_c.c_int32), _c.POINTER(_c.c_double),
                        _c.c_int32, _vp, _c.c_int32, _c.c_double, _vp, _vp, _vp, _vp],
     "ur_ewald_image": [_vp, _vp, _c.POINTER(UrEwald), _vp, _vp],
+    "ur_peak_integrals": [_c.c_int32, _vp, _vp, _c.c_int32, _c.POINTER(_c.c_double), _vp, _vp],
     "ur_ensemble": [_c.c_int32, _c.c_int32, _vp, _vp, _vp, _vp, _vp, _vp],
     "ur_graph_begin": [_vp],
     "ur_graph_end": [_vp, _c.POINTER(_vp)],
@@ -245,6 +246,23 @@ class HistBatch:
         self.sem = torch.zeros((nboxes, nbins), dtype=torch.float64, device="cuda")
         self.hists = [Hist(nbins, mean=self.mean[k], sem=self.sem[k]) for k in range(nboxes)]
         self.nboxes, self.nbins = nboxes, nbins
+
+
+def peak_integrals(edges, mean, windows, out=None, stream=None):
+    """Per q window [(q_lo, q_hi), ...]: (peak integral above the straight
+    baseline through the window's end bins, total integral, bins used) of a
+    binned curve; `edges` and `mean` device FP64 tensors, result (nwin, 3)."""
+    torch = _torch()
+    w = np.ascontiguousarray(windows, dtype=np.float64).reshape(-1, 2)
+    nb = int(mean.numel())
+    _require(edges, torch.float64, nb + 1, "edges")
+    _require(mean, torch.float64, nb, "mean")
+    if out is None:
+        out = torch.empty((len(w), 3), dtype=torch.float64, device="cuda")
+    _require(out, torch.float64, 3 * len(w), "out")
+    _check(lib().ur_peak_integrals(nb, _ptr(edges), _ptr(mean), len(w), w.ctypes.data_as(_c.POINTER(_c.c_double)),
+                                   _ptr(out), _stream(stream)), "ur_peak_integrals")
+    return out
 
 
 def ensemble(batch: HistBatch, weights, out=None, stream=None):

@@ -1360,6 +1360,23 @@ ur_status ur_ewald_image(ur_plan* p, const void* spectrum, const ur_ewald* geo, 
   return UR_OK;
 }
 
+ur_status ur_peak_integrals(int32_t nbins, const double* edges, const double* mean, int32_t nwin,
+                            const double* windows, double* out, void* stream) {
+  if (!edges || !mean || !windows || !out) return fail(UR_ERR_INVALID, "null argument");
+  if (nbins < 1 || nbins > 4096) return fail(UR_ERR_INVALID, "nbins = %d outside [1, 4096]", nbins);
+  if (nwin < 1 || nwin > kMaxWindows) return fail(UR_ERR_INVALID, "nwin = %d outside [1, %d]", nwin, kMaxWindows);
+  PeakArgs a{};
+  a.nbins = nbins; a.nwin = nwin; a.edges = edges; a.mean = mean; a.out = out;
+  for (int w = 0; w < nwin; ++w) {
+    const double lo = windows[2 * w], hi = windows[2 * w + 1];
+    if (!isfinite(lo) || !isfinite(hi) || !(lo < hi)) return fail(UR_ERR_INVALID, "window %d must have finite q_lo < q_hi", w);
+    a.lo[w] = lo;
+    a.hi[w] = hi;
+  }
+  UR_HIP(launch_peaks(a, (hipStream_t)stream));
+  return UR_OK;
+}
+
 ur_status ur_ensemble(int32_t nboxes, int32_t nbins, const double* mean, const double* sem, const double* weights,
                       double* out_mean, double* out_sem, void* stream) {
   if (nboxes < 1) return fail(UR_ERR_INVALID, "nboxes = %d must be >= 1", nboxes);

@@ -2240,6 +2240,44 @@ hipError_t launch_ewald(int prec, const EwaldArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Window w: the populated bins whose centres lie in [lo, hi]; a first scan
+// finds the first and last of them (the baseline's ends), a second adds
+// (mean - baseline) * width and mean * width in bin order.
+__global__ void k_peaks(PeakArgs a) {
+  const int w = blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= a.nwin) return;
+  const double lo = a.lo[w], hi = a.hi[w];
+  int first = -1, last = -1, cnt = 0;
+  for (int b = 0; b < a.nbins; ++b) {
+    const double q = 0.5 * (a.edges[b] + a.edges[b + 1]);
+    if (q < lo || q > hi || isnan(a.mean[b])) continue;
+    if (first < 0) first = b;
+    last = b;
+    ++cnt;
+  }
+  double peak = NAN, total = NAN;
+  if (cnt >= 2) {
+    const double q0 = 0.5 * (a.edges[first] + a.edges[first + 1]), q1 = 0.5 * (a.edges[last] + a.edges[last + 1]);
+    const double m0 = a.mean[first], slope = (a.mean[last] - m0) / (q1 - q0);
+    peak = 0.0;
+    total = 0.0;
+    for (int b = first; b <= last; ++b) {
+      if (isnan(a.mean[b])) continue;
+      const double q = 0.5 * (a.edges[b] + a.edges[b + 1]), d = a.edges[b + 1] - a.edges[b];
+      peak += (a.mean[b] - (m0 + slope * (q - q0))) * d;
+      total += a.mean[b] * d;
+    }
+  }
+  a.out[3 * w] = peak;
+  a.out[3 * w + 1] = total;
+  a.out[3 * w + 2] = (double)cnt;
+}
+
+hipError_t launch_peaks(const PeakArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_peaks, dim3(1), dim3(64), 0, s, a);
+  return hipGetLastError();
+}
+
 hipError_t launch_ensemble(int nboxes, int nbins, const double* mean, const double* sem, const double* w,
                            double* out_mean, double* out_sem, hipStream_t s) {
   hipLaunchKernelGGL(k_ensemble, dim3(nblk_of(nbins, 256)), dim3(256), 0, s, nboxes, nbins, mean, sem, w, out_mean, out_sem);

@@ -258,6 +258,17 @@ struct EwaldArgs {
 };
 hipError_t launch_ewald(int prec, const EwaldArgs& a, hipStream_t s);
 
+// peak integrals over q windows of a binned curve, one thread per window
+constexpr int kMaxWindows = 64;
+struct PeakArgs {
+  int nbins, nwin;
+  const double* edges;
+  const double* mean;
+  double lo[kMaxWindows], hi[kMaxWindows];
+  double* out;              // [nwin][3]: peak, total, bins
+};
+hipError_t launch_peaks(const PeakArgs& a, hipStream_t s);
+
 hipError_t launch_ensemble(int nboxes, int nbins, const double* mean, const double* sem, const double* w,
                            double* out_mean, double* out_sem, hipStream_t s);
 hipError_t launch_pass_x_adj(int prec, int n, const XAdjArgs& a, int nblocks, hipStream_t s);

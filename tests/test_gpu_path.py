@@ -806,3 +806,35 @@ def test_autograd_voxel_density_fd(ur):
             return float(chi2(BinnedIntensityRho.apply(r2, plan), T, count).item())
         fd = (L(h) - L(-h)) / (2 * h)
         assert abs(fd - float(g[x, y, z])) <= 1e-5 * max(1.0, abs(fd)), (x, y, z, fd, float(g[x, y, z]))
+
+
+def test_peak_integrals_of_a_lattice_curve(ur, orc):
+    """ur_peak_integrals on the curve of a 128^3 FP64 lattice box (Bragg
+    peaks on the particle's small-angle scattering): against the oracle's
+    peak integrals of the same device curve (1e-12 relative) and of the
+    oracle's own curve (1e-10); a window of one bin gives NaN on both
+    sides; bad windows are refused."""
+    import torch
+    wl = W.small(128, c=8, n_atoms=10, seed=31, radius=45.0, nbins=400, prec=1)
+    ref = orc.simulate(wl)
+    plan = ur.Plan(wl.n, wl.voxel, 1)
+    plan.set_bins(wl.edges)
+    cell = ur.DeviceCell.from_host(wl.cell)
+    h = ur.Hist(wl.nbins)
+    plan.simulate(cell, wl.mask, wl.zoom, h)
+    q = 0.5 * (wl.edges[:-1] + wl.edges[1:])
+    windows = [(q[40], q[90]), (q[150], q[260]), (q[300], q[399]), (q[200] - 1e-9, q[200] + 1e-9)]
+    edges = torch.as_tensor(wl.edges, device="cuda")
+    got = ur.peak_integrals(edges, h.mean, windows).cpu().numpy()
+    same = orc.peak_integrals(wl.edges, h.mean.cpu().numpy(), windows)
+    own = orc.peak_integrals(wl.edges, ref["mean"], windows)
+    fin = np.isfinite(same[:, 0])
+    assert list(fin) == [True, True, True, False] and np.all(np.isnan(got[~fin, :2]))
+    assert np.array_equal(got[:, 2], same[:, 2]) and np.array_equal(got[:, 2], own[:, 2])
+    scale = np.abs(same[fin, 1])
+    assert np.all(np.abs(got[fin, :2] - same[fin, :2]) <= 1e-12 * scale[:, None])
+    assert np.all(np.abs(got[fin, :2] - own[fin, :2]) <= 1e-10 * scale[:, None])
+    for bad in ([(1.0, 1.0)], [(np.nan, 2.0)], [(0.0, 1.0)] * 65):
+        with pytest.raises(ur.UltimaError, match="status 1"):
+            ur.peak_integrals(edges, h.mean, bad)
+    torch.cuda.synchronize()

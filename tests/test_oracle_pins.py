@@ -728,6 +728,40 @@ def test_grains_are_voronoi_pieces_of_rotated_lattices(oracle_lib, interp):
 
 
 # ---------------------------------------------------------------------------
+# O17: peak integrals (degree of crystallinity)
+# ---------------------------------------------------------------------------
+
+def test_peak_integrals_closed_forms(oracle_lib):
+    """A Gaussian peak of area A on a sloping straight background, sampled at
+    the centres of fine bins: the peak integral is A (the midpoint rule of a
+    Gaussian over +-6 widths, and the baseline through the window's ends is
+    the background to exp(-18)); the background alone integrates to zero
+    above its own baseline, and its total is the trapezoid of a line; a
+    window of fewer than two populated bins gives NaN; an empty bin inside a
+    window is skipped."""
+    import oracle
+    e = W.lin_edges(0.0, 10.0, 2000)
+    q = 0.5 * (e[:-1] + e[1:])
+    A, q0, s = 3.0, 4.0, 0.07
+    bg = 2.0 - 0.1 * q
+    m = bg + A / (s * math.sqrt(2.0 * math.pi)) * np.exp(-0.5 * ((q - q0) / s) ** 2)
+    lo, hi = q0 - 6 * s, q0 + 6 * s
+    r = oracle.peak_integrals(e, m, [(lo, hi), (1.0, 2.0), (5.0001, 5.0049)])
+    assert abs(r[0, 0] - A) <= 1e-6 * A
+    line = oracle.peak_integrals(e, bg, [(lo, hi), (1.0, 2.0)])
+    assert np.all(np.abs(line[:, 0]) <= 1e-12 * line[:, 1])
+    sel = (q >= 1.0) & (q <= 2.0)
+    qa, qb = q[sel][0] - 0.0025, q[sel][-1] + 0.0025
+    trap = (2.0 - 0.05 * (qa + qb)) * (qb - qa)
+    assert abs(line[1, 1] - trap) <= 1e-12 * trap and line[1, 2] == sel.sum()
+    assert np.isnan(r[2, 0]) and np.isnan(r[2, 1]) and r[2, 2] < 2
+    m2 = m.copy()
+    m2[np.argmin(np.abs(q - 1.5))] = np.nan
+    r2 = oracle.peak_integrals(e, m2, [(1.0, 2.0)])
+    assert r2[0, 2] == r[1, 2] - 1 and np.isfinite(r2[0, 0])
+
+
+# ---------------------------------------------------------------------------
 # O15: voxel form factor (a density uniform over each voxel)
 # ---------------------------------------------------------------------------
 
