@@ -351,6 +351,8 @@ def main():
     ap.add_argument("--n", type=int, default=1024, help="box edge (1024 = the headline workload)")
     ap.add_argument("--no-ooc4096", action="store_true",
                     help="skip the 4096^3 out-of-core box (212 GiB of host memory, about 90 s, in a child process)")
+    ap.add_argument("--mixed-radix-only", action="store_true",
+                    help="time only the mixed-radix boxes (1000^3, 2000^3) and print their JSON")
     ap.add_argument("--ooc4096-only", action="store_true",
                     help="only stream the 4096^3 out-of-core box and print its result (the child of the full run)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -382,6 +384,10 @@ def main():
         # than a process may page-lock here: pageable memory through the
         # bounce slabs), 229 GB of spectrum in HBM
         print(json.dumps(out_of_core(ur, W, torch, W.c5(4096), 2, pinned=False)))
+        return
+    if args.mixed_radix_only:
+        # the mixed-radix boxes alone (M1000 FP32/FP64, M2000 FP32)
+        print(json.dumps(mixed_radix(ur, W, torch, max(2, args.steps // 4))))
         return
 
     n = args.n

@@ -919,7 +919,7 @@ ur_status ur_simulate(ur_plan* p, const ur_cell* cell, const ur_mask* mask, cons
     za.ntiles = ntiles(p); za.cbn = t.cbn;
     nzb = (int)((xhi - xlo + 1) * za.ntiles);
     PassTimer tm(p, P_Z, s);
-    const int zm = za.rotated ? Z_ROT_R2C
+    const int zm = za.rotated ? (za.cubic ? (za.ngrain ? Z_ROT3G_R2C : Z_ROT3_R2C) : (za.ngrain ? Z_ROTG_R2C : Z_ROT_R2C))
                  : zoom->factor > 1 ? ((p->flags & UR_C2C) ? Z_ZOOM_C2C : Z_ZOOM_R2C) : ((p->flags & UR_C2C) ? Z_GEN_C2C : Z_GEN_R2C);
     UR_HIP(launch_pass_z(p->prec, p->n, zm, za, nzb, s));
   }

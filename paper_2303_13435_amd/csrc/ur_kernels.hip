@@ -271,9 +271,10 @@ struct Pencil {
   // cell coordinate u = R d of inside voxel z: R the lattice's orientation,
   // or with grains that of the seed nearest to d (squared integer distance,
   // ties to the lower index); products and sums rounded one by one
+  template <bool GRAINS>
   __device__ __forceinline__ void coords(const ZArgs& a, int z, double& u, double& v, double& w) const {
     const double dz = (double)(z + zoff);
-    if (a.ngrain == 0) {
+    if constexpr (!GRAINS) {
       u = __dadd_rn(ux, __dmul_rn(a.rot[2], dz));
       v = __dadd_rn(uy, __dmul_rn(a.rot[5], dz));
       w = __dadd_rn(uz, __dmul_rn(a.rot[8], dz));
@@ -294,10 +295,11 @@ struct Pencil {
     w = __dadd_rn(__dadd_rn(__dmul_rn(R[6], dx), __dmul_rn(R[7], dy)), __dmul_rn(R[8], dz));
   }
 
+  template <bool GRAINS>
   __device__ __forceinline__ T value_rot(const ZArgs& a, int z) const {
     if (z < zlo || z > zhi) return (T)0;
     double u, v, w;
-    coords(a, z, u, v, w);
+    coords<GRAINS>(a, z, u, v, w);
     const double fu = floor(u), fv = floor(v), fw = floor(w);
     const T tu = (T)(u - fu), tv = (T)(v - fv), tw = (T)(w - fw);
     const int c = cmask + 1;
@@ -322,10 +324,11 @@ struct Pencil {
   // periodic spline coefficients C; the value at u is the sum over the
   // 4 x 4 x 4 coefficients around floor(u) with the cubic B-spline weights
   // of the fractional offsets (third index innermost)
+  template <bool GRAINS>
   __device__ __forceinline__ T value_rot3(const ZArgs& a, int z) const {
     if (z < zlo || z > zhi) return (T)0;
     double u, v, w;
-    coords(a, z, u, v, w);
+    coords<GRAINS>(a, z, u, v, w);
     const double fu = floor(u), fv = floor(v), fw = floor(w);
     T wu[4], wv[4], ww[4];
     bspline_weights<T>((T)(u - fu), wu);
@@ -351,8 +354,16 @@ struct Pencil {
     return acc;
   }
 
+  // the sampler chosen at compile time (pass Z modes), or at run time from
+  // the arguments (density generation)
+  template <int INTERP, bool GRAINS>
   __device__ __forceinline__ T value_rotated(const ZArgs& a, int z) const {
-    return a.cubic ? value_rot3(a, z) : value_rot(a, z);
+    if constexpr (INTERP == 3) return value_rot3<GRAINS>(a, z);
+    else return value_rot<GRAINS>(a, z);
+  }
+  __device__ __forceinline__ T value_rotated_rt(const ZArgs& a, int z) const {
+    if (a.cubic) return a.ngrain ? value_rot3<true>(a, z) : value_rot3<false>(a, z);
+    return a.ngrain ? value_rot<true>(a, z) : value_rot<false>(a, z);
   }
 
   // ED-1 voxel (factor 1): tiled cell inside the mask, exact integer test
@@ -445,7 +456,9 @@ __global__ void __launch_bounds__((ZCfg<T, N, (MODE == Z_GEN_C2C || MODE == Z_LO
 k_pass_z(ZArgs a) {
   constexpr bool C2C = MODE == Z_GEN_C2C || MODE == Z_LOAD_C2C || MODE == Z_ZOOM_C2C;
   constexpr bool ZOOM = MODE == Z_ZOOM_R2C || MODE == Z_ZOOM_C2C;
-  constexpr bool ROT = MODE == Z_ROT_R2C;
+  constexpr bool ROT = MODE == Z_ROT_R2C || MODE == Z_ROT3_R2C || MODE == Z_ROTG_R2C || MODE == Z_ROT3G_R2C;
+  constexpr int RI = (MODE == Z_ROT3_R2C || MODE == Z_ROT3G_R2C) ? 3 : 1;     // sampler of a rotated cell
+  constexpr bool RG = MODE == Z_ROTG_R2C || MODE == Z_ROT3G_R2C;              // grains
   constexpr bool GEN = MODE == Z_GEN_R2C || MODE == Z_GEN_C2C || ZOOM || ROT;
   using C = ZCfg<T, N, C2C>;
   constexpr int G = C::G, NG = C::NG, TY = C::TY, E = Geo<N>::E;
@@ -487,7 +500,7 @@ k_pass_z(ZArgs a) {
 #pragma unroll
           for (int r = 0; r < R0; ++r) {
             const int z = first_index<N>(g, i, r);
-            v[i * R0 + r] = mk(pa.value_rotated(a, z), pb.value_rotated(a, z));
+            v[i * R0 + r] = mk(pa.template value_rotated<RI, RG>(a, z), pb.template value_rotated<RI, RG>(a, z));
           }
       } else if (!ZOOM) {
         // the cell residue of z = b + r N/R0 does not depend on r when the
@@ -688,7 +701,7 @@ __global__ void __launch_bounds__(256) k_rho_generate(ZArgs a, int n, int x0, T*
   Pencil<T> p;
   p.init(a, X, Y);
   T* row = rho + t * n;
-  for (int z = threadIdx.x; z < n; z += 256) row[z] = a.rotated ? p.value_rotated(a, z) : p.value(a, z);
+  for (int z = threadIdx.x; z < n; z += 256) row[z] = a.rotated ? p.value_rotated_rt(a, z) : p.value(a, z);
 }
 
 // ---------------------------------------------------------------------------
@@ -1729,6 +1742,9 @@ static hipError_t pass_z_t(int mode, const ZArgs& a, int nblocks, hipStream_t s)
     switch (mode) {
       case Z_GEN_R2C: hipLaunchKernelGGL((k_pass_z<T, N, Z_GEN_R2C>), dim3(nblocks), dim3(ZCfg<T, N, false>::threads), 0, s, a); break;
       case Z_ROT_R2C: hipLaunchKernelGGL((k_pass_z<T, N, Z_ROT_R2C>), dim3(nblocks), dim3(ZCfg<T, N, false>::threads), 0, s, a); break;
+      case Z_ROT3_R2C: hipLaunchKernelGGL((k_pass_z<T, N, Z_ROT3_R2C>), dim3(nblocks), dim3(ZCfg<T, N, false>::threads), 0, s, a); break;
+      case Z_ROTG_R2C: hipLaunchKernelGGL((k_pass_z<T, N, Z_ROTG_R2C>), dim3(nblocks), dim3(ZCfg<T, N, false>::threads), 0, s, a); break;
+      case Z_ROT3G_R2C: hipLaunchKernelGGL((k_pass_z<T, N, Z_ROT3G_R2C>), dim3(nblocks), dim3(ZCfg<T, N, false>::threads), 0, s, a); break;
       case Z_LOAD_R2C: hipLaunchKernelGGL((k_pass_z<T, N, Z_LOAD_R2C>), dim3(nblocks), dim3(ZCfg<T, N, false>::threads), 0, s, a); break;
       case Z_ZOOM_R2C: hipLaunchKernelGGL((k_pass_z<T, N, Z_ZOOM_R2C>), dim3(nblocks), dim3(ZCfg<T, N, false>::threads), 0, s, a); break;
       default: return hipErrorInvalidValue;
@@ -1738,6 +1754,9 @@ static hipError_t pass_z_t(int mode, const ZArgs& a, int nblocks, hipStream_t s)
   switch (mode) {
     case Z_GEN_R2C: hipLaunchKernelGGL((k_pass_z<T, N, Z_GEN_R2C>), dim3(nblocks), dim3(ZCfg<T, N, false>::threads), 0, s, a); break;
     case Z_ROT_R2C: hipLaunchKernelGGL((k_pass_z<T, N, Z_ROT_R2C>), dim3(nblocks), dim3(ZCfg<T, N, false>::threads), 0, s, a); break;
+    case Z_ROT3_R2C: hipLaunchKernelGGL((k_pass_z<T, N, Z_ROT3_R2C>), dim3(nblocks), dim3(ZCfg<T, N, false>::threads), 0, s, a); break;
+    case Z_ROTG_R2C: hipLaunchKernelGGL((k_pass_z<T, N, Z_ROTG_R2C>), dim3(nblocks), dim3(ZCfg<T, N, false>::threads), 0, s, a); break;
+    case Z_ROT3G_R2C: hipLaunchKernelGGL((k_pass_z<T, N, Z_ROT3G_R2C>), dim3(nblocks), dim3(ZCfg<T, N, false>::threads), 0, s, a); break;
     case Z_LOAD_R2C: hipLaunchKernelGGL((k_pass_z<T, N, Z_LOAD_R2C>), dim3(nblocks), dim3(ZCfg<T, N, false>::threads), 0, s, a); break;
     case Z_GEN_C2C: hipLaunchKernelGGL((k_pass_z<T, N, Z_GEN_C2C>), dim3(nblocks), dim3(ZCfg<T, N, true>::threads), 0, s, a); break;
     case Z_LOAD_C2C: hipLaunchKernelGGL((k_pass_z<T, N, Z_LOAD_C2C>), dim3(nblocks), dim3(ZCfg<T, N, true>::threads), 0, s, a); break;
@@ -1952,7 +1971,7 @@ __global__ void __launch_bounds__((MrCfg<T, N, MODE == MR_BIN>::threads)) k_mr_a
         p.init(a.z, line / N, line % N);
         cx<T>* col = lds + l * PS;
         for (int e = g; e < N; e += GP) {
-          const T v = a.z.rotated ? p.value_rotated(a.z, e) : p.value(a.z, e);
+          const T v = a.z.rotated ? p.value_rotated_rt(a.z, e) : p.value(a.z, e);
           col[pad(e)] = mk(v, (T)0);
           s1 += (double)v;
           s2 += (double)v * (double)v;

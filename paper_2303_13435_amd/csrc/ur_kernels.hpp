@@ -15,9 +15,10 @@ constexpr int kMaxOutOfCore = 4096;
 
 // Density source of the first (z) pass.
 // GEN: ED-1 voxels (block factor 1); ZOOM: block-summed zoom levels.
-// ROT: ED-1 of a rotated lattice (trilinear periodic interpolation of the cell).
+// ROT: ED-1 of a rotated lattice (periodic interpolation of the cell):
+// trilinear or cubic B-spline (ROT3), one orientation or grains (G).
 enum ZMode { Z_GEN_R2C = 0, Z_LOAD_R2C = 1, Z_GEN_C2C = 2, Z_LOAD_C2C = 3, Z_ZOOM_R2C = 4, Z_ZOOM_C2C = 5,
-             Z_ROT_R2C = 6 };
+             Z_ROT_R2C = 6, Z_ROT3_R2C = 7, Z_ROTG_R2C = 8, Z_ROT3G_R2C = 9 };
 // What the last (x) pass does with each transformed column.
 // X_ADJ: the adjoint column pass; the _SINC variants (chosen by the launcher
 // when XArgs::sinc is set) weight every intensity by the voxel form factor.
