@@ -578,46 +578,65 @@ def wavelength_nodes(rel_spread: float, n_lambda: int):
     return t, w / w.sum()
 
 
-def ewald_image(F: np.ndarray, voxel: float, geo) -> np.ndarray:
-    """2D detector image of an anisotropic sample (Q-calculation and
-    spherical averaging: intensity taken on the Ewald sphere, a shell whose
-    thickness follows the wavelength distribution).
+def ewald_pixels(n: int, voxel: float, geo, iv: np.ndarray, iu: np.ndarray, intensity) -> np.ndarray:
+    """Ewald-sphere intensities at detector pixels (iv[p], iu[p]) (Q-calculation
+    and spherical averaging: intensity taken on the Ewald sphere, a shell
+    whose thickness follows the wavelength distribution).
 
-    F is the full n^3 spectrum of eq. 1, F[u][v][w] at the frequency
-    (u, v, w) along the box axes (x, y, z).  The pixel (iu, iv) sits at
-    P = distance e + (iu - cu) pixel du + (iv - cv) pixel dv from the
-    sample and scatters along s = P / |P|; at the wavelength lambda_j the
-    elastic momentum transfer is q = (2 pi / lambda_j)(s - e), at grid
-    coordinate g = q / dq with dq = 2 pi / (n voxel) (the spacing of eq. 1's
-    frequencies).  I = |F|^2 is taken between the grid points by trilinear
-    interpolation, the grid periodic (the DFT is), and the image is the
+    The pixel (iu, iv) sits at P = distance e + (iu - cu) pixel du +
+    (iv - cv) pixel dv from the sample and scatters along s = P / |P|; at
+    the wavelength lambda_j the elastic momentum transfer is
+    q = (2 pi / lambda_j)(s - e), at grid coordinate g = q / dq with
+    dq = 2 pi / (n voxel) (the spacing of eq. 1's frequencies, u along the
+    box's x axis).  I = |F|^2 is taken between the grid points by trilinear
+    interpolation, the grid periodic (the DFT is), and the result is the
     node-weighted sum over the wavelengths (``wavelength_nodes``).
-    Returns image[iv][iu]."""
-    n = F.shape[0]
-    I = np.abs(np.asarray(F, dtype=np.complex128)) ** 2
+    ``intensity`` maps an (M, 3) array of frequencies in [0, n) to |F|^2."""
     e, du, dv = (np.asarray(v, dtype=np.float64) for v in (geo.beam, geo.du, geo.dv))
-    iv, iu = np.meshgrid(np.arange(geo.nv, dtype=np.float64), np.arange(geo.nu, dtype=np.float64), indexing="ij")
-    P = (geo.distance * e[None, None, :] + ((iu - geo.cu) * geo.pixel)[..., None] * du[None, None, :]
-         + ((iv - geo.cv) * geo.pixel)[..., None] * dv[None, None, :])
+    iv = np.asarray(iv, dtype=np.float64)
+    iu = np.asarray(iu, dtype=np.float64)
+    P = (geo.distance * e[None, :] + ((iu - geo.cu) * geo.pixel)[:, None] * du[None, :]
+         + ((iv - geo.cv) * geo.pixel)[:, None] * dv[None, :])
     s = P / np.linalg.norm(P, axis=-1, keepdims=True)
     dq = 2.0 * math.pi / (n * voxel)
     t, w = wavelength_nodes(geo.rel_spread, geo.n_lambda)
-    image = np.zeros((geo.nv, geo.nu))
+    out = np.zeros(len(iu))
     for tj, wj in zip(t, w):
         k = 2.0 * math.pi / (geo.wavelength * (1.0 + geo.rel_spread * tj))
-        g = k * (s - e[None, None, :]) / dq
+        g = k * (s - e[None, :]) / dq
         g0 = np.floor(g)
         f = g - g0
         g0 = g0.astype(np.int64)
-        val = np.zeros((geo.nv, geo.nu))
+        val = np.zeros(len(iu))
         for a in (0, 1):
             for b in (0, 1):
                 for c in (0, 1):
-                    wt = ((f[..., 0] if a else 1.0 - f[..., 0]) * (f[..., 1] if b else 1.0 - f[..., 1])
-                          * (f[..., 2] if c else 1.0 - f[..., 2]))
-                    val += wt * I[(g0[..., 0] + a) % n, (g0[..., 1] + b) % n, (g0[..., 2] + c) % n]
-        image += wj * val
-    return image
+                    wt = ((f[:, 0] if a else 1.0 - f[:, 0]) * (f[:, 1] if b else 1.0 - f[:, 1])
+                          * (f[:, 2] if c else 1.0 - f[:, 2]))
+                    val += wt * intensity(np.mod(g0 + np.array([a, b, c]), n))
+        out += wj * val
+    return out
+
+
+def ewald_image(F: np.ndarray, voxel: float, geo) -> np.ndarray:
+    """O16 over the whole detector from the full n^3 spectrum F[u][v][w] of
+    eq. 1; returns image[iv][iu]."""
+    n = F.shape[0]
+    I = np.abs(np.asarray(F, dtype=np.complex128)) ** 2
+    iv, iu = np.meshgrid(np.arange(geo.nv), np.arange(geo.nu), indexing="ij")
+    img = ewald_pixels(n, voxel, geo, iv.reshape(-1), iu.reshape(-1), lambda q: I[q[:, 0], q[:, 1], q[:, 2]])
+    return img.reshape(geo.nv, geo.nu)
+
+
+def ewald_pixels_sparse(n: int, voxel: float, geo, iv, iu, xyz: np.ndarray, values: np.ndarray) -> np.ndarray:
+    """O16 at chosen pixels of a box that is zero but at the voxels xyz, with
+    every needed coefficient of eq. 1 summed directly (``dft_points``): for
+    boxes whose transform the oracle cannot hold."""
+    def intensity(q):
+        uq, inv = np.unique(q, axis=0, return_inverse=True)
+        F = dft_points(n, xyz, values, uq)
+        return (np.abs(F) ** 2)[inv.reshape(-1)]
+    return ewald_pixels(n, voxel, geo, iv, iu, intensity)
 
 
 # ---------------------------------------------------------------------------

@@ -462,3 +462,37 @@ def test_ewald_image_refusals(ur):
     with pytest.raises(ur.UltimaError, match="elements"):
         plan.ewald_image(spec[:4], good)
     torch.cuda.synchronize()
+
+
+def test_ewald_image_1024_sampled(ur, orc):
+    """The Ewald image at the headline box size: a 1024^3 FP32 box that is
+    zero but at 64 voxels, its r2c spectrum from ur_fft3d_exec, a tilted
+    256 x 192 detector with a 2 % wavelength spread (8 nodes) reaching past
+    the Nyquist frequency; 60 random pixels against the oracle with every
+    corner coefficient summed directly over the 64 voxels.  Bound as for the
+    small boxes, with max|F| <= sum(rho)/n^3."""
+    import torch
+    n = 1024
+    _say("ewald 1024 sampled")
+    xyz, val = W.sparse_voxels(4096, n, 64, dtype=np.float32)
+    x = torch.zeros((n, n, n), dtype=torch.float32, device="cuda")
+    x[torch.as_tensor(xyz[:, 0], device="cuda"), torch.as_tensor(xyz[:, 1], device="cuda"),
+      torch.as_tensor(xyz[:, 2], device="cuda")] = torch.as_tensor(val, device="cuda")
+    plan = ur.Plan(n, 1.0, 0)
+    spec = plan.fft3d(x)
+    del x
+    geo = W.detector(W.rotation([0.3, -0.5, 0.8], 1.1), rel_spread=0.02, n_lambda=8, distance=300.0,
+                     pixel=0.5, nu=256, nv=192, cu=100.0, cv=60.0)
+    img = plan.ewald_image(spec, geo)
+    torch.cuda.synchronize()
+    del spec, plan
+    torch.cuda.empty_cache()
+    rng = np.random.default_rng(61)
+    iv, iu = rng.integers(0, geo.nv, 60), rng.integers(0, geo.nu, 60)
+    got = img.cpu().numpy()[iv, iu]
+    ref = orc.ewald_pixels_sparse(n, 1.0, geo, iv, iu, xyz, val.astype(np.float64))
+    fmax = float(np.sum(val.astype(np.float64))) / float(n) ** 3
+    bound = 2.0 * 2e-6 * fmax * np.sqrt(ref) + (2e-6 * fmax) ** 2 + 1e-14 * fmax ** 2
+    ratio = np.abs(got - ref) / bound
+    _say(f"  max rel err {np.max(np.abs(got - ref) / ref):.3e}, max err/bound {ratio.max():.3f}")
+    assert np.all(ratio <= 1.0)

@@ -901,3 +901,20 @@ def test_ewald_wavelength_spread_is_the_gaussian_average(oracle_lib):
     geo = W.detector(np.eye(3), rel_spread=0.1, n_lambda=9, nu=9, nv=7, cu=4, cv=3)
     img = oracle.ewald_image(F, 1.0, geo)
     assert abs(img[3, 4] - abs(F[0, 0, 0]) ** 2) <= 1e-14 * abs(F[0, 0, 0]) ** 2
+
+
+def test_ewald_sparse_route_matches_full_spectrum(oracle_lib):
+    """O16 at chosen pixels with every needed coefficient summed directly over
+    the nonzero voxels (the route for boxes too large to transform) against
+    the image of the full transform, on a 32^3 box of 20 voxels."""
+    import oracle
+    n = 32
+    xyz, val = W.sparse_voxels(5, n, 20, dtype=np.float64)
+    rho = np.zeros((n, n, n))
+    rho[xyz[:, 0], xyz[:, 1], xyz[:, 2]] = val
+    geo = W.detector(W.rotation([0.3, -0.5, 0.8], 1.1), rel_spread=0.05, n_lambda=5, pixel=5.0,
+                     nu=21, nv=17, cu=7.0, cv=9.0)
+    full = oracle.ewald_image(oracle.forward(rho), 1.0, geo)
+    iv, iu = np.array([0, 5, 16, 8, 9]), np.array([0, 20, 3, 11, 7])
+    sp = oracle.ewald_pixels_sparse(n, 1.0, geo, iv, iu, xyz, val)
+    assert np.max(np.abs(sp - full[iv, iu])) <= 1e-13 * np.max(full)
