@@ -102,7 +102,7 @@ typedef struct { int32_t kind; int64_t p0; int64_t p1; } ur_mask;
  * (row-major, finite); the inside voxel at offset d belongs to the grain
  * whose seed is nearest (squared integer distance, ties to the lower grain
  * index) and takes the cell at u = R_g d, sampled as chosen by interp; rot
- * must then be NULL.  Seeds that are not integers or exceed 2^20 in
+ * must then be NULL.  Seeds that are not integers or exceed 8192 in
  * magnitude fail with UR_ERR_INVALID.
  * Rotated lattices and grains run the forward paths at zoom factor 1 on
  * real (UR_R2C) plans; the adjoint refuses them (UR_ERR_UNSUPPORTED). */

@@ -607,8 +607,8 @@ static ur_status check_cell(const ur_cell* c) {
     if (!c->grain_seed || !c->grain_rot) return fail(UR_ERR_INVALID, "grain arrays must be non-null");
     for (int i = 0; i < 3 * c->n_grains; ++i) {
       const double v = c->grain_seed[i];
-      if (!isfinite(v) || v != floor(v) || fabs(v) > 1048576.0)
-        return fail(UR_ERR_INVALID, "grain seed entry %d must be an integer of magnitude <= 2^20", i);
+      if (!isfinite(v) || v != floor(v) || fabs(v) > 8192.0)
+        return fail(UR_ERR_INVALID, "grain seed entry %d must be an integer of magnitude <= 8192", i);
     }
     for (int i = 0; i < 9 * c->n_grains; ++i)
       if (!isfinite(c->grain_rot[i])) return fail(UR_ERR_INVALID, "grain orientation entry %d is not finite", i);

@@ -200,6 +200,19 @@ struct Pencil {
   // rotated lattice (f == 1): u = rot (dx, dy, dz), dz = z + zoff; (ux, uy, uz) = rot (dx, dy, 0)
   double ux, uy, uz;
   int pdx, pdy;             // pencil offset from the particle centre (grains)
+  const double* GR;         // grain orientations [g][9] (the arguments, or a copy in LDS)
+  int A[kMaxGrains];        // grains: squared in-plane distance of the pencil to each seed
+
+  // grains: |(dx, dy) - seed_g (x, y)|^2 for every grain (int32: offsets
+  // stay below 4096 and seeds below 8192 in magnitude, so squared distances
+  // stay below 2^30)
+  __device__ __forceinline__ void init_grains(const ZArgs& a) {
+#pragma unroll
+    for (int g = 0; g < kMaxGrains; ++g) {
+      const int ex = pdx - a.gseed[g][0], ey = pdy - a.gseed[g][1];
+      A[g] = g < a.ngrain ? ex * ex + ey * ey : 0x7fffffff;
+    }
+  }
 
   __device__ __forceinline__ void init(const ZArgs& a, long long X, long long Y) {
     const Level& L = a.L;
@@ -222,6 +235,7 @@ struct Pencil {
         uz = __dadd_rn(__dmul_rn(a.rot[6], dx), __dmul_rn(a.rot[7], dy));
         pdx = (int)(X - L.o - L.h);
         pdy = (int)(Y - L.o - L.h);
+        GR = &a.grot[0][0];
       }
     } else {
       long long ax, bx, ay, by;
@@ -280,15 +294,15 @@ struct Pencil {
       w = __dadd_rn(uz, __dmul_rn(a.rot[8], dz));
       return;
     }
-    const long long iz = z + zoff;
-    int best = 0;
-    long long bd = 0;
-    for (int g = 0; g < a.ngrain; ++g) {
-      const long long ex = pdx - a.gseed[g][0], ey = pdy - a.gseed[g][1], ez = iz - a.gseed[g][2];
-      const long long d2 = ex * ex + ey * ey + ez * ez;
-      if (g == 0 || d2 < bd) { bd = d2; best = g; }
+    const int iz = z + zoff;
+    int best = 0, bd = 0x7fffffff;
+#pragma unroll
+    for (int g = 0; g < kMaxGrains; ++g) {               // A[g] is 2^31 - 1 beyond the grains
+      const int ez = iz - a.gseed[g][2];
+      const int d2 = A[g] == 0x7fffffff ? 0x7fffffff : A[g] + ez * ez;
+      if (d2 < bd) { bd = d2; best = g; }
     }
-    const double* R = a.grot[best];
+    const double* R = GR + 9 * best;
     const double dx = (double)pdx, dy = (double)pdy;
     u = __dadd_rn(__dadd_rn(__dmul_rn(R[0], dx), __dmul_rn(R[1], dy)), __dmul_rn(R[2], dz));
     v = __dadd_rn(__dadd_rn(__dmul_rn(R[3], dx), __dmul_rn(R[4], dy)), __dmul_rn(R[5], dz));
@@ -296,7 +310,7 @@ struct Pencil {
   }
 
   template <bool GRAINS>
-  __device__ __forceinline__ T value_rot(const ZArgs& a, int z) const {
+  __device__ __forceinline__ T value_rot(const ZArgs& a, int z, const T* C) const {
     if (z < zlo || z > zhi) return (T)0;
     double u, v, w;
     coords<GRAINS>(a, z, u, v, w);
@@ -306,7 +320,6 @@ struct Pencil {
     const int i0 = (int)(long long)fu & cmask, i1 = (i0 + 1) & cmask;
     const int j0 = (int)(long long)fv & cmask, j1 = (j0 + 1) & cmask;
     const int k0 = (int)(long long)fw & cmask, k1 = (k0 + 1) & cmask;
-    const T* C = (const T*)a.cellT;
     const T* r00 = C + ((size_t)i0 * c + j0) * c;
     const T* r01 = C + ((size_t)i0 * c + j1) * c;
     const T* r10 = C + ((size_t)i1 * c + j0) * c;
@@ -325,7 +338,7 @@ struct Pencil {
   // 4 x 4 x 4 coefficients around floor(u) with the cubic B-spline weights
   // of the fractional offsets (third index innermost)
   template <bool GRAINS>
-  __device__ __forceinline__ T value_rot3(const ZArgs& a, int z) const {
+  __device__ __forceinline__ T value_rot3(const ZArgs& a, int z, const T* C) const {
     if (z < zlo || z > zhi) return (T)0;
     double u, v, w;
     coords<GRAINS>(a, z, u, v, w);
@@ -336,7 +349,6 @@ struct Pencil {
     bspline_weights<T>((T)(w - fw), ww);
     const int c = cmask + 1;
     const int i0 = (int)(long long)fu - 1, j0 = (int)(long long)fv - 1, k0 = (int)(long long)fw - 1;
-    const T* C = (const T*)a.cellT;
     T acc = (T)0;
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
@@ -357,13 +369,14 @@ struct Pencil {
   // the sampler chosen at compile time (pass Z modes), or at run time from
   // the arguments (density generation)
   template <int INTERP, bool GRAINS>
-  __device__ __forceinline__ T value_rotated(const ZArgs& a, int z) const {
-    if constexpr (INTERP == 3) return value_rot3<GRAINS>(a, z);
-    else return value_rot<GRAINS>(a, z);
+  __device__ __forceinline__ T value_rotated(const ZArgs& a, int z, const T* C) const {
+    if constexpr (INTERP == 3) return value_rot3<GRAINS>(a, z, C);
+    else return value_rot<GRAINS>(a, z, C);
   }
   __device__ __forceinline__ T value_rotated_rt(const ZArgs& a, int z) const {
-    if (a.cubic) return a.ngrain ? value_rot3<true>(a, z) : value_rot3<false>(a, z);
-    return a.ngrain ? value_rot<true>(a, z) : value_rot<false>(a, z);
+    const T* C = (const T*)a.cellT;
+    if (a.cubic) return a.ngrain ? value_rot3<true>(a, z, C) : value_rot3<false>(a, z, C);
+    return a.ngrain ? value_rot<true>(a, z, C) : value_rot<false>(a, z, C);   // init_grains first
   }
 
   // ED-1 voxel (factor 1): tiled cell inside the mask, exact integer test
@@ -465,6 +478,9 @@ k_pass_z(ZArgs a) {
   constexpr int R0 = Radix<N, 1>::r, NB0 = E / R0, PS = CS<N>::v;
   __shared__ cx<T> sm[NG * PS];
   __shared__ double red[C::threads];                   // per-lane sums of rho^2
+  constexpr int CL = ROT ? 4096 : 1;                   // rotated: cells up to 16^3 staged in LDS
+  __shared__ T cl[CL];
+  __shared__ double grl[RG ? kMaxGrains * 9 : 1];      // grain orientations (per-voxel choice)
 
   const int tile = blockIdx.x % a.ntiles;
   const long long X = a.x0 + blockIdx.x / a.ntiles;
@@ -495,13 +511,37 @@ k_pass_z(ZArgs a) {
       pa.init(a, X, yA);
       pb.init(a, X, yB);
       if constexpr (ROT) {
+        // the cell's samples are gathers at arbitrary positions: from LDS
+        // when the cell fits (block-uniform test), else through the caches
+        const int c3 = a.L.c * a.L.c * a.L.c;
+        if constexpr (RG) {
+          for (int i = threadIdx.x; i < 9 * a.ngrain; i += C::threads) grl[i] = (&a.grot[0][0])[i];
+          pa.GR = grl;
+          pb.GR = grl;
+          pa.init_grains(a);
+          pb.init_grains(a);
+        }
+        if (c3 <= CL) {
+          for (int i = threadIdx.x; i < c3; i += C::threads) cl[i] = ((const T*)a.cellT)[i];
+          __syncthreads();
 #pragma unroll
-        for (int i = 0; i < NB0; ++i)
+          for (int i = 0; i < NB0; ++i)
 #pragma unroll
-          for (int r = 0; r < R0; ++r) {
-            const int z = first_index<N>(g, i, r);
-            v[i * R0 + r] = mk(pa.template value_rotated<RI, RG>(a, z), pb.template value_rotated<RI, RG>(a, z));
-          }
+            for (int r = 0; r < R0; ++r) {
+              const int z = first_index<N>(g, i, r);
+              v[i * R0 + r] = mk(pa.template value_rotated<RI, RG>(a, z, cl), pb.template value_rotated<RI, RG>(a, z, cl));
+            }
+        } else {
+          if constexpr (RG) __syncthreads();             // the grain table
+          const T* cg = (const T*)a.cellT;
+#pragma unroll
+          for (int i = 0; i < NB0; ++i)
+#pragma unroll
+            for (int r = 0; r < R0; ++r) {
+              const int z = first_index<N>(g, i, r);
+              v[i * R0 + r] = mk(pa.template value_rotated<RI, RG>(a, z, cg), pb.template value_rotated<RI, RG>(a, z, cg));
+            }
+        }
       } else if (!ZOOM) {
         // the cell residue of z = b + r N/R0 does not depend on r when the
         // cell edge divides N/R0: one cell load per pencil and butterfly
@@ -700,6 +740,7 @@ __global__ void __launch_bounds__(256) k_rho_generate(ZArgs a, int n, int x0, T*
   const long long X = x0 + t / n, Y = t % n;
   Pencil<T> p;
   p.init(a, X, Y);
+  if (a.ngrain) p.init_grains(a);
   T* row = rho + t * n;
   for (int z = threadIdx.x; z < n; z += 256) row[z] = a.rotated ? p.value_rotated_rt(a, z) : p.value(a, z);
 }
@@ -1969,6 +2010,7 @@ __global__ void __launch_bounds__((MrCfg<T, N, MODE == MR_BIN>::threads)) k_mr_a
         const long long line = tile * TL + l;
         Pencil<T> p;
         p.init(a.z, line / N, line % N);
+        if (a.z.ngrain) p.init_grains(a.z);
         cx<T>* col = lds + l * PS;
         for (int e = g; e < N; e += GP) {
           const T v = a.z.rotated ? p.value_rotated_rt(a.z, e) : p.value(a.z, e);

@@ -274,19 +274,21 @@ def test_c4_size_256(ur, orc, prec):
 # rotated lattice (cell sampled at u = R d, trilinear, periodic)
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("n,prec,interp", [(64, 0, 1), (64, 1, 1), (128, 0, 1), (64, 0, 3), (64, 1, 3), (128, 0, 3)])
-def test_rotated_lattice(ur, orc, n, prec, interp):
+@pytest.mark.parametrize("n,prec,interp,c", [(64, 0, 1, 8), (64, 1, 1, 8), (128, 0, 1, 8), (64, 0, 3, 8), (64, 1, 3, 8),
+                                              (128, 0, 3, 8), (64, 1, 1, 32), (64, 0, 3, 32)])
+def test_rotated_lattice(ur, orc, n, prec, interp, c):
     """A lattice oriented by a general rotation, the cell sampled trilinearly
-    or by the cubic B-spline: the fused forward path against the whole
+    or by the cubic B-spline (cells of 8^3, read from LDS, and of 32^3, read
+    through the caches): the fused forward path against the whole
     oracle (O2r, then O4-O8), the generated density voxel by voxel (the
     cubic case's spline coefficients, stored in the working precision, are
     up to 2.4 times the cell's largest value here: same bounds); the adjoint
     and zoomed levels refuse rotated lattices."""
     import torch
     from dataclasses import replace
-    base = W.small(n, c=8, n_atoms=9, seed=71, radius=0.4 * n, nbins=60, prec=prec)
+    base = W.small(n, c=c, n_atoms=9, seed=71, radius=0.4 * n, nbins=60, prec=prec)
     wl = replace(base, cell=base.cell.with_rot(W.rotation([1.0, 2.0, 3.0], 0.7), interp))
-    _say(f"rotated lattice {n}^3 prec={prec} interp={interp}")
+    _say(f"rotated lattice {n}^3 prec={prec} interp={interp} cell {c}^3")
     ref = orc.simulate(wl)
     got = run_simulate(ur, wl)
     compare_bins(got, ref, F32_BIN if prec == 0 else F64_BIN, "rotated", n=n)
@@ -311,8 +313,9 @@ def test_rotated_lattice(ur, orc, n, prec, interp):
     torch.cuda.synchronize()
 
 
-@pytest.mark.parametrize("n,prec,interp", [(64, 0, 1), (64, 1, 1), (64, 0, 3), (64, 1, 3), (128, 0, 3)])
-def test_polycrystalline_grains(ur, orc, n, prec, interp):
+@pytest.mark.parametrize("n,prec,interp,c", [(64, 0, 1, 8), (64, 1, 1, 8), (64, 0, 3, 8), (64, 1, 3, 8), (128, 0, 3, 8),
+                                              (64, 1, 3, 32), (64, 0, 1, 32)])
+def test_polycrystalline_grains(ur, orc, n, prec, interp, c):
     """A polycrystalline particle: 7 grains (random integer seeds inside the
     sphere, random orientations), every inside voxel sampling the cell in
     its nearest seed's orientation; the fused forward path against the
@@ -322,10 +325,10 @@ def test_polycrystalline_grains(ur, orc, n, prec, interp):
     import ctypes
     import torch
     from dataclasses import replace
-    base = W.small(n, c=8, n_atoms=9, seed=72, radius=0.4 * n, nbins=60, prec=prec)
+    base = W.small(n, c=c, n_atoms=9, seed=72, radius=0.4 * n, nbins=60, prec=prec)
     seeds, rots = W.random_grains(73, 7, 0.35 * n)
     wl = replace(base, cell=base.cell.with_grains(seeds, rots, interp))
-    _say(f"grains {n}^3 prec={prec} interp={interp}")
+    _say(f"grains {n}^3 prec={prec} interp={interp} cell {c}^3")
     ref = orc.simulate(wl)
     got = run_simulate(ur, wl)
     compare_bins(got, ref, F32_BIN if prec == 0 else F64_BIN, "grains", n=n)
