@@ -154,14 +154,24 @@ template <int N> struct Padded { static constexpr int size = N + N / 16; };
 // at 1024.
 //
 // Lengths N = 2^a 3^b 5^c that are not powers of two (mixed radix) take
-// power-of-two radices of at most P = min(2^a, 8), then radix 3, then radix
-// 5; E = P (x 3 if b > 0) (x 5 if c > 0) so that every radix divides it, and
-// the column lies in one wavefront (G <= 64, not necessarily a power of two).
+// power-of-two radices of at most P, then radix 3, then radix 5;
+// E = P (x 3 if b > 0) (x 5 if c > 0) so that every radix divides it; P is
+// the smallest power of two (at most 8 and 2^a) that puts the column in one
+// wavefront (G = N / E <= 64, not necessarily a power of two).
 template <int N> struct Pow2 { static constexpr bool v = (N & (N - 1)) == 0; };
 constexpr int pow2_part(int n) { return n & -n; }
 template <int N> struct Mixed {
-  static constexpr int P = pow2_part(N) < 8 ? pow2_part(N) : 8;
-  static constexpr int E = P * (N % 3 == 0 ? 3 : 1) * (N % 5 == 0 ? 5 : 1);
+  static_assert(N % 2 == 0, "mixed-radix edges are even");
+  static constexpr int odd = (N % 3 == 0 ? 3 : 1) * (N % 5 == 0 ? 5 : 1);
+  // the smallest power-of-two cap (at most 8) that keeps a line in one
+  // wavefront: fewer elements per lane, fewer registers
+  static constexpr int pick() {
+    int p = 2;                                     // every compiled edge is even
+    while (p < 8 && p < pow2_part(N) && N / (p * odd) > 64) p *= 2;
+    return p < pow2_part(N) ? p : pow2_part(N);
+  }
+  static constexpr int P = pick();
+  static constexpr int E = P * odd;
 };
 template <int N> struct Geo {
   static constexpr int E = Pow2<N>::v ? (N <= 16 ? N : (N == 512 ? 8 : 16)) : Mixed<N>::E;

@@ -1972,7 +1972,7 @@ __global__ void __launch_bounds__((MrCfg<T, N, MODE == MR_BIN>::threads)) k_mr_a
   using C = MrCfg<T, N, MODE == MR_BIN>;
   constexpr int G = C::G, GP = C::GP, TL = C::TL, PS = C::PS, NT = C::threads;
   constexpr int E = Geo<N>::E, R0 = Radix<N, 1>::r, NB0 = E / R0;
-  constexpr int U = cmin(32, (TL * N + NT - 1) / NT);  // loads in flight per thread (the whole tile)
+  constexpr int U = cmin(8, (TL * N + NT - 1) / NT);   // loads in flight per thread
   constexpr long long NTILE = mr_tiles<T, N, AXIS, MODE>();
   static_assert(MODE != MR_GEN || AXIS == 2, "generation feeds the z pass");
   static_assert(MODE != MR_BIN || (AXIS == 0 && DIR < 0), "binning follows the forward x pass");
@@ -2007,13 +2007,20 @@ __global__ void __launch_bounds__((MrCfg<T, N, MODE == MR_BIN>::threads)) k_mr_a
       // every lane of a line's slot generates elements g, g + GP, ... of it
       const int l = t / GP, g = t % GP;
       if (l < nl) {
+        // aligned lattice (complex plans refuse rotation), level factor 1:
+        // the cell row of the pencil, inside the mask's z range
         const long long line = tile * TL + l;
-        Pencil<T> p;
-        p.init(a.z, line / N, line % N);
-        if (a.z.ngrain) p.init_grains(a.z);
+        const long long X = line / N, Y = line % N;
+        const Level& L = a.z.L;
+        long long lo, hi;
+        col_range(L, a.z.m, X, Y, lo, hi);
+        const int cm = L.c - 1;
+        const T* row = (const T*)a.z.cellT +
+                       ((size_t)((int)(X - L.o - L.h) & cm) * L.c + ((int)(Y - L.o - L.h) & cm)) * L.c;
+        const int zoff = -(int)(L.o + L.h);
         cx<T>* col = lds + l * PS;
         for (int e = g; e < N; e += GP) {
-          const T v = a.z.rotated ? p.value_rotated_rt(a.z, e) : p.value(a.z, e);
+          const T v = (e >= lo && e <= hi) ? row[(e + zoff) & cm] : (T)0;
           col[pad(e)] = mk(v, (T)0);
           s1 += (double)v;
           s2 += (double)v * (double)v;
