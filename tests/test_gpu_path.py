@@ -393,7 +393,9 @@ def test_polydisperse_ensemble_in_one_graph(ur, orc, n, count, r_lo, r_hi, check
     graph: replays equal the eager calls.  5 radii at 64^3: against O14
     over the oracle's per-box curves.  200 radii at 256^3 (the paper's
     count of contributions): against the weighted sum of the per-box curves
-    the kernels wrote."""
+    the kernels wrote.  The peak integrals of the ensemble curve
+    (ur_peak_integrals over four q windows) ride in the same graph and
+    match the oracle's integrals of the curve each replay wrote."""
     import torch
     levels = W.b_radii(n, count, r_lo, r_hi, nbins=64 if n <= 64 else 256)
     nb = levels[0].nbins
@@ -406,11 +408,16 @@ def test_polydisperse_ensemble_in_one_graph(ur, orc, n, count, r_lo, r_hi, check
     wt = torch.as_tensor(w, device="cuda")
     out = (torch.empty(nb, dtype=torch.float64, device="cuda"), torch.empty(nb, dtype=torch.float64, device="cuda"))
     s = torch.cuda.Stream()
+    edges = torch.as_tensor(levels[0].edges, device="cuda")
+    q = 0.5 * (levels[0].edges[:-1] + levels[0].edges[1:])
+    windows = [(q[nb // 8], q[nb // 4]), (q[nb // 4], q[nb // 2]), (q[nb // 2], q[3 * nb // 4]), (q[3 * nb // 4], q[-1])]
+    pk = torch.empty((len(windows), 3), dtype=torch.float64, device="cuda")
 
     def run():
         for wl, h in zip(levels, batch.hists):
             plan.simulate(cell, wl.mask, wl.zoom, h, stream=s)
         ur.ensemble(batch, wt, out=out, stream=s)
+        ur.peak_integrals(edges, out[0], windows, out=pk, stream=s)
 
     with torch.cuda.stream(s):
         run()
@@ -424,6 +431,7 @@ def test_polydisperse_ensemble_in_one_graph(ur, orc, n, count, r_lo, r_hi, check
     for rep in range(2):
         out[0].fill_(0.0)
         batch.mean.fill_(0.0)
+        pk.fill_(0.0)
         torch.cuda.synchronize()
         g.launch()
         torch.cuda.synchronize()
@@ -437,6 +445,10 @@ def test_polydisperse_ensemble_in_one_graph(ur, orc, n, count, r_lo, r_hi, check
         ds = np.max(np.abs(s_g[ok_s] - s_e[ok_s]) / np.abs(s_e[ok_s]))
         _say(f"  replay {rep}: mean rel diff {dm:.2e}, sem rel diff {ds:.2e}")
         assert dm <= 1e-12 and ds <= 1e-10
+        pr = orc.peak_integrals(levels[0].edges, m_g, windows)
+        pg = pk.cpu().numpy()
+        assert np.array_equal(pg[:, 2], pr[:, 2]) and np.all(np.isfinite(pr[:, :2]))
+        assert np.all(np.abs(pg[:, :2] - pr[:, :2]) <= 1e-12 * np.abs(pr[:, 1:2]))
     pop = count_b > 0
     assert np.all(np.isnan(m_e[~pop]))
     if check == "oracle":
