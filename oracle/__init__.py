@@ -75,6 +75,9 @@ def lib():
                                  ctypes.c_longlong, _D, ctypes.c_int, _D]
         L.or_ed1_grains.argtypes = [ctypes.c_int, ctypes.c_int, _D, ctypes.c_int, ctypes.c_longlong,
                                     ctypes.c_longlong, ctypes.c_int, _LL, _D, ctypes.c_int, _D]
+        L.or_ed1_grains_points.argtypes = [ctypes.c_int, ctypes.c_int, _D, ctypes.c_int, ctypes.c_longlong,
+                                           ctypes.c_longlong, ctypes.c_int, _LL, _D, ctypes.c_int, ctypes.c_longlong,
+                                           _LL, _D]
         L.or_zoom.argtypes = [ctypes.c_int, ctypes.c_int, _D, ctypes.c_int, ctypes.c_longlong,
                               ctypes.c_longlong, ctypes.c_int, ctypes.c_int, _D]
         L.or_fft3d.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_int]
@@ -208,6 +211,23 @@ def ed1_grains(n: int, cell_grid: np.ndarray, mask, seeds: np.ndarray, rots: np.
     out = np.empty((n, n, n))
     lib().or_ed1_grains(int(n), int(c), _dp(cg), int(mask.kind), int(mask.p0), int(mask.p1), int(g),
                         S.ctypes.data_as(_LL), _dp(R), int(interp), _dp(out))
+    return out
+
+
+def oriented_points(n: int, cell_grid: np.ndarray, mask, xyz: np.ndarray, seeds: np.ndarray, rots: np.ndarray,
+                    interp: int = 1) -> np.ndarray:
+    """O2r / O2g at the voxels xyz[p] = (x, y, z) only (one orientation is
+    one grain), for boxes too large to generate whole."""
+    assert interp in (1, 3)
+    c = cell_grid.shape[0]
+    cg = np.ascontiguousarray(cell_grid if interp == 1 else bspline_coefficients(cell_grid), dtype=np.float64)
+    S = np.ascontiguousarray(np.rint(seeds), dtype=np.int64).reshape(-1)
+    R = np.ascontiguousarray(rots, dtype=np.float64).reshape(-1)
+    P = np.ascontiguousarray(xyz, dtype=np.int64).reshape(-1)
+    out = np.empty(P.size // 3)
+    lib().or_ed1_grains_points(int(n), int(c), _dp(cg), int(mask.kind), int(mask.p0), int(mask.p1), int(S.size // 3),
+                               S.ctypes.data_as(_LL), _dp(R), int(interp), int(out.size), P.ctypes.data_as(_LL),
+                               _dp(out))
     return out
 
 

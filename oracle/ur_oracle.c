@@ -174,55 +174,70 @@ static double bspline3(double x)
  * periodic cubic B-spline coefficients C, value = sum over the 4^3 nearest
  * coefficients of C[i] B3(u0 - i0) B3(u1 - i1) B3(u2 - i2).  One grain with
  * any seed is a single rotated lattice. */
+/* one voxel of the polycrystalline ED-1 (see or_ed1_grains) */
+static double grains_voxel(int n, int c, const double* cell, int kind, long long p0, long long p1, int ngrain,
+                           const long long* seed, const double* Rg, int order, long long x, long long y, long long z)
+{
+    const long long h = n / 2;
+    const long long dx = x - h, dy = y - h, dz = z - h;
+    if (!or_mask_inside(kind, p0, p1, dx, dy, dz)) return 0.0;
+    int g = 0;
+    long long best = -1;
+    for (int k = 0; k < ngrain; ++k) {
+        const long long ex = dx - seed[3 * k], ey = dy - seed[3 * k + 1], ez = dz - seed[3 * k + 2];
+        const long long d2 = ex * ex + ey * ey + ez * ez;
+        if (best < 0 || d2 < best) { best = d2; g = k; }
+    }
+    const double* R = Rg + 9 * g;
+    double u[3];
+    for (int i = 0; i < 3; ++i)
+        u[i] = (R[3 * i] * (double)dx + R[3 * i + 1] * (double)dy) + R[3 * i + 2] * (double)dz;
+    long long i0[3];
+    double t[3];
+    for (int i = 0; i < 3; ++i) {
+        const double f = floor(u[i]);
+        i0[i] = (long long)f;
+        t[i] = u[i] - f;
+    }
+    if (order == 3) {
+        double s = 0.0;
+        for (int a0 = -1; a0 <= 2; ++a0)
+            for (int a1 = -1; a1 <= 2; ++a1)
+                for (int a2 = -1; a2 <= 2; ++a2) {
+                    const double w = bspline3(t[0] - a0) * bspline3(t[1] - a1) * bspline3(t[2] - a2);
+                    s += w * cell[((size_t)pmod(i0[0] + a0, c) * c + pmod(i0[1] + a1, c)) * c + pmod(i0[2] + a2, c)];
+                }
+        return s;
+    }
+    double a[2][2];
+    for (int di = 0; di < 2; ++di)
+        for (int dj = 0; dj < 2; ++dj) {
+            const long long ci = pmod(i0[0] + di, c), cj = pmod(i0[1] + dj, c);
+            const double* row = cell + ((size_t)ci * c + cj) * c;
+            a[di][dj] = lerp(row[pmod(i0[2], c)], row[pmod(i0[2] + 1, c)], t[2]);
+        }
+    return lerp(lerp(a[0][0], a[0][1], t[1]), lerp(a[1][0], a[1][1], t[1]), t[0]);
+}
+
 void or_ed1_grains(int n, int c, const double* cell, int kind, long long p0, long long p1, int ngrain,
                    const long long* seed, const double* Rg, int order, double* rho)
 {
-    const long long h = n / 2;
 #pragma omp parallel for schedule(static)
     for (long long x = 0; x < n; ++x)
         for (long long y = 0; y < n; ++y)
-            for (long long z = 0; z < n; ++z) {
-                double* out = &rho[((size_t)x * n + y) * n + z];
-                const long long dx = x - h, dy = y - h, dz = z - h;
-                if (!or_mask_inside(kind, p0, p1, dx, dy, dz)) { *out = 0.0; continue; }
-                int g = 0;
-                long long best = -1;
-                for (int k = 0; k < ngrain; ++k) {
-                    const long long ex = dx - seed[3 * k], ey = dy - seed[3 * k + 1], ez = dz - seed[3 * k + 2];
-                    const long long d2 = ex * ex + ey * ey + ez * ez;
-                    if (best < 0 || d2 < best) { best = d2; g = k; }
-                }
-                const double* R = Rg + 9 * g;
-                double u[3];
-                for (int i = 0; i < 3; ++i)
-                    u[i] = (R[3 * i] * (double)dx + R[3 * i + 1] * (double)dy) + R[3 * i + 2] * (double)dz;
-                long long i0[3];
-                double t[3];
-                for (int i = 0; i < 3; ++i) {
-                    const double f = floor(u[i]);
-                    i0[i] = (long long)f;
-                    t[i] = u[i] - f;
-                }
-                if (order == 3) {
-                    double s = 0.0;
-                    for (int a0 = -1; a0 <= 2; ++a0)
-                        for (int a1 = -1; a1 <= 2; ++a1)
-                            for (int a2 = -1; a2 <= 2; ++a2) {
-                                const double w = bspline3(t[0] - a0) * bspline3(t[1] - a1) * bspline3(t[2] - a2);
-                                s += w * cell[((size_t)pmod(i0[0] + a0, c) * c + pmod(i0[1] + a1, c)) * c + pmod(i0[2] + a2, c)];
-                            }
-                    *out = s;
-                    continue;
-                }
-                double a[2][2];
-                for (int di = 0; di < 2; ++di)
-                    for (int dj = 0; dj < 2; ++dj) {
-                        const long long ci = pmod(i0[0] + di, c), cj = pmod(i0[1] + dj, c);
-                        const double* row = cell + ((size_t)ci * c + cj) * c;
-                        a[di][dj] = lerp(row[pmod(i0[2], c)], row[pmod(i0[2] + 1, c)], t[2]);
-                    }
-                *out = lerp(lerp(a[0][0], a[0][1], t[1]), lerp(a[1][0], a[1][1], t[1]), t[0]);
-            }
+            for (long long z = 0; z < n; ++z)
+                rho[((size_t)x * n + y) * n + z] = grains_voxel(n, c, cell, kind, p0, p1, ngrain, seed, Rg, order, x, y, z);
+}
+
+/* the same at npts voxels xyz[3p .. 3p+2] of the box (for boxes too large to
+ * generate whole) */
+void or_ed1_grains_points(int n, int c, const double* cell, int kind, long long p0, long long p1, int ngrain,
+                          const long long* seed, const double* Rg, int order, long long npts, const long long* xyz,
+                          double* out)
+{
+#pragma omp parallel for schedule(static)
+    for (long long p = 0; p < npts; ++p)
+        out[p] = grains_voxel(n, c, cell, kind, p0, p1, ngrain, seed, Rg, order, xyz[3 * p], xyz[3 * p + 1], xyz[3 * p + 2]);
 }
 
 void or_ed1_rot(int n, int c, const double* cell, int kind, long long p0, long long p1, const double* R,

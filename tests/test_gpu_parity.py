@@ -499,3 +499,40 @@ def test_ewald_image_1024_sampled(ur, orc):
     ratio = np.abs(got - ref) / bound
     _say(f"  max rel err {np.max(np.abs(got - ref) / ref):.3e}, max err/bound {ratio.max():.3f}")
     assert np.all(ratio <= 1.0)
+
+
+@pytest.mark.parametrize("kind", ["trilinear", "cubic", "grains16"])
+def test_oriented_density_1024_sampled(ur, orc, kind):
+    """The rotated samplers at the size the benchmark times them: the 1024^3
+    FP32 headline particle with its lattice rotated (trilinear or cubic) or
+    split into 16 grains; ur_rho_generate over the 8 central planes, 4000
+    random voxels of them against the oracle evaluated voxel by voxel.
+    Bound: 16 eps32 times the largest cell value or spline coefficient (the
+    weights are nonnegative and sum to 1; they and the cell table are
+    rounded to FP32)."""
+    import torch
+    wl = W.m1024()
+    R = W.rotation([1.0, 2.0, 3.0], 0.7)
+    if kind == "grains16":
+        seeds, rots = W.random_grains(16, 16, 0.35 * wl.n)
+        cellh = wl.cell.with_grains(seeds, rots, 1)
+        interp = 1
+    else:
+        interp = 3 if kind == "cubic" else 1
+        cellh = wl.cell.with_rot(R, interp)
+        seeds, rots = np.zeros((1, 3)), R[None]
+    _say(f"oriented density 1024 {kind}")
+    plan = ur.Plan(wl.n, wl.voxel, 0)
+    x_lo, x_hi = wl.n // 2 - 4, wl.n // 2 + 3
+    rho = plan.rho_generate(ur.DeviceCell.from_host(cellh), wl.mask, wl.zoom, x_lo=x_lo, x_hi=x_hi)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(1024)
+    pts = np.stack([rng.integers(x_lo, x_hi + 1, 4000), rng.integers(0, wl.n, 4000), rng.integers(0, wl.n, 4000)], axis=1)
+    got = rho.cpu().numpy()[pts[:, 0] - x_lo, pts[:, 1], pts[:, 2]].astype(np.float64)
+    cg = orc.cell_synth(wl.cell)
+    ref = orc.oriented_points(wl.n, cg, wl.mask, pts, seeds, rots, interp)
+    big = np.max(np.abs(orc.bspline_coefficients(cg) if interp == 3 else cg))
+    err = np.max(np.abs(got - ref))
+    _say(f"  {np.count_nonzero(ref)} inside, max abs err {err:.3e} = {err / (2.0 ** -24 * big):.2f} eps32 x max")
+    assert np.count_nonzero(ref) > 1000
+    assert err <= 16 * 2.0 ** -24 * big

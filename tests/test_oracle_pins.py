@@ -918,3 +918,24 @@ def test_ewald_sparse_route_matches_full_spectrum(oracle_lib):
     iv, iu = np.array([0, 5, 16, 8, 9]), np.array([0, 20, 3, 11, 7])
     sp = oracle.ewald_pixels_sparse(n, 1.0, geo, iv, iu, xyz, val)
     assert np.max(np.abs(sp - full[iv, iu])) <= 1e-13 * np.max(full)
+
+
+@pytest.mark.parametrize("interp", [1, 3])
+def test_oriented_points_match_the_whole_box(oracle_lib, interp):
+    """O2r / O2g evaluated at chosen voxels (the route for boxes too large to
+    generate) against the same voxels of the whole-box evaluation, for one
+    orientation and for grains."""
+    import oracle
+    n = 32
+    cell, mask = _rot_case()
+    cg = oracle.cell_synth(cell)
+    rng = np.random.default_rng(9)
+    xyz = rng.integers(0, n, (300, 3))
+    R = W.rotation([1.0, 2.0, 3.0], 0.7)
+    whole = oracle.ed1_rot(n, cg, mask, R, interp)
+    pts = oracle.oriented_points(n, cg, mask, xyz, np.zeros((1, 3)), R[None], interp)
+    assert np.array_equal(pts, whole[xyz[:, 0], xyz[:, 1], xyz[:, 2]])
+    seeds, rots = W.random_grains(4, 5, 12.0)
+    whole = oracle.ed1_grains(n, cg, mask, seeds, rots, interp)
+    pts = oracle.oriented_points(n, cg, mask, xyz, seeds, rots, interp)
+    assert np.array_equal(pts, whole[xyz[:, 0], xyz[:, 1], xyz[:, 2]])
