@@ -2091,16 +2091,23 @@ __global__ void __launch_bounds__((MrCfg<T, N, MODE == MR_BIN>::threads)) k_mr_a
         const cx<T>* col = lds + l * PS;
         int cur = -2;
         double rs = 0.0, rs2 = 0.0;
-        const int e1 = (g + 1) * CH < N ? (g + 1) * CH : N;
-        for (int e = g * CH; e < e1; ++e) {
+        const int e0 = g * CH, e1 = (g + 1) * CH < N ? (g + 1) * CH : N;
+        // bin of the first element from the start-of-walk table; after that
+        // n2 moves by small steps, so the bin is walked from the previous one
+        int b = -1;
+        if (e0 < e1) {
+          const int h0 = sidx(e0, N), n20 = h0 * h0 + base2;
+          b = a.lut[isqrt_ll(n20)];
+        }
+        for (int e = e0; e < e1; ++e) {
           const cx<T> f = scale(col[pad(e)], sc);
           if (e == 0 && base2 == 0 && o == 0 && z0 + l == 0) { a.f0[0] = (double)f.x; a.f0[1] = (double)f.y; }
           const int h = sidx(e, N);
           const int n2 = h * h + base2;
           const double I = ((double)f.x * f.x + (double)f.y * f.y) * a.iscale;
           tot += I;
-          int b = a.lut[isqrt_ll(n2)];
           while (b < a.nbins && n2 >= a.U[b + 1]) ++b;
+          while (b >= 0 && n2 < a.U[b]) --b;
           if (b != cur) {
             if (cur >= 0 && cur < a.nbins) { atomicAdd(&hist[2 * cur], rs); atomicAdd(&hist[2 * cur + 1], rs2); }
             cur = b;
