@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libultima.so")
-SOURCES = ["ur_kernels.hip", "ur_api.cpp"]
+SOURCES = ["ur_kernels.hip", "ur_mixed.hip", "ur_api.cpp"]
 HEADERS = ["ur_device.hpp", "ur_geom.hpp", "ur_kernels.hpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

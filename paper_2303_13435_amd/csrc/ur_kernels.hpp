@@ -211,6 +211,11 @@ hipError_t launch_merge(const MergeArgs& a, hipStream_t s);
 // Mixed-radix boxes: edges n = 2^a 3^b 5^c that are not powers of two, complex
 // [x][y][z] arrays transformed in place one axis at a time; the spectrum
 // stays in natural order [kx][ky][kz].
+// the compiled mixed-radix edges: the 2^a 5^3 family of the paper's boxes and
+// zoom levels (250 ... 2000) with smaller members for tests, and 2^a 3
+#define UR_MR_SIZES(X) X(40) X(80) X(100) X(160) X(200) X(250) X(400) X(500) X(1000) X(2000) \
+                       X(48) X(96) X(384) X(768) X(1536)
+
 bool mr_size(int n);
 struct MrArgs {
   const void* src;          // this pass's input (may equal dst)

@@ -1,0 +1,332 @@
+// Mixed-radix boxes (edges 2^a 3^b 5^c that are not powers of two): the
+// in-place axis passes with the density generated in the first and |F|^2
+// binned in the last, and the binning of a given spectrum.
+#include <hip/hip_runtime.h>
+
+#include "ur_device.hpp"
+#include "ur_geom.hpp"
+#include "ur_kernels.hpp"
+
+namespace ur {
+
+// ---------------------------------------------------------------------------
+// mixed-radix boxes (n = 2^a 3^b 5^c, not a power of two)
+// A block holds TL whole lines of one axis in LDS (padded columns), every
+// line transformed by G lanes in a slot of GP = 2^ceil(log2 G) lanes (so a
+// line never straddles two wavefronts), then written back in place.  Lines
+// along z are contiguous, so a tile is TL n consecutive elements; lines
+// along y and x are taken TL consecutive z at a time, so every load and
+// store is a TL-element contiguous segment.
+// ---------------------------------------------------------------------------
+constexpr int floor_pow2(int v) { int p = 1; while (2 * p <= v) p *= 2; return p; }
+constexpr int ceil_pow2(int v) { int p = 1; while (p < v) p *= 2; return p; }
+constexpr int cmin(int a, int b) { return a < b ? a : b; }
+
+// Lines per tile: at most 64 (and 1024 threads), within 72 KB of LDS so that
+// two blocks share a CU, but at least 8 (64-byte segments along y and x)
+// when 144 KB allow it; the binning x pass keeps 94 KB for the tile so the
+// histogram (up to 4096 bins) fits beside it.
+template <typename T, int N, bool BIN> struct MrCfg {
+  static constexpr int G = Geo<N>::G, GP = ceil_pow2(G);
+  static constexpr int PS = Padded<N>::size, LB = PS * (int)sizeof(cx<T>);
+  static constexpr int TL0 = cmin(64, 1024 / GP);
+  static constexpr int TLa = floor_pow2(cmin(TL0, (BIN ? 94 * 1024 : 72 * 1024) / LB > 0 ? (BIN ? 94 * 1024 : 72 * 1024) / LB : 1));
+  static constexpr int TLb = floor_pow2(cmin(cmin(TL0, 8), (144 * 1024) / LB > 0 ? (144 * 1024) / LB : 1));
+  static constexpr int TL = (BIN || TLa >= 8) ? TLa : (TLb > TLa ? TLb : TLa);
+  static constexpr int threads = TL * GP < 64 ? 64 : TL * GP;
+  static_assert(G <= 64, "mixed-radix lines lie in one wavefront");
+  static_assert(threads % 64 == 0 && TL * LB <= 144 * 1024, "tile exceeds the LDS");
+};
+
+template <typename T, int N, int AXIS, int MODE>
+__host__ __device__ constexpr long long mr_tiles() {
+  constexpr int TL = MrCfg<T, N, MODE == MR_BIN>::TL;
+  return AXIS == 2 ? ((long long)N * N + TL - 1) / TL : (long long)N * ((N + TL - 1) / TL);
+}
+
+template <typename T, int N, int DIR, int AXIS, int MODE>
+__global__ void __launch_bounds__((MrCfg<T, N, MODE == MR_BIN>::threads)) k_mr_axis(MrArgs a) {
+  using C = MrCfg<T, N, MODE == MR_BIN>;
+  constexpr int G = C::G, GP = C::GP, TL = C::TL, PS = C::PS, NT = C::threads;
+  constexpr int E = Geo<N>::E, R0 = Radix<N, 1>::r, NB0 = E / R0;
+  constexpr int U = cmin(8, (TL * N + NT - 1) / NT);   // loads in flight per thread
+  constexpr long long NTILE = mr_tiles<T, N, AXIS, MODE>();
+  static_assert(MODE != MR_GEN || AXIS == 2, "generation feeds the z pass");
+  static_assert(MODE != MR_BIN || (AXIS == 0 && DIR < 0), "binning follows the forward x pass");
+  __shared__ cx<T> lds[TL * PS];
+  extern __shared__ double hist[];                   // MR_BIN: 2 nbins + 1
+  const cx<T>* __restrict__ src = (const cx<T>*)a.src;
+  cx<T>* __restrict__ dst = (cx<T>*)a.dst;
+  const int t = threadIdx.x;
+  const int nv = 2 * a.nbins + 1;
+  if constexpr (MODE == MR_BIN) {
+    for (int i = t; i < nv; i += NT) hist[i] = 0.0;
+  }
+  double s1 = 0.0, s2 = 0.0, tot = 0.0;
+  for (long long tile = blockIdx.x; tile < NTILE; tile += gridDim.x) {
+    size_t base, es;
+    int nl, o = 0, z0 = 0;
+    if constexpr (AXIS == 2) {
+      const long long l0 = tile * TL;
+      const long long left = (long long)N * N - l0;
+      nl = left < TL ? (int)left : TL;
+      base = (size_t)l0 * N;
+      es = 1;
+    } else {
+      constexpr int nzt = (N + TL - 1) / TL;
+      o = (int)(tile / nzt);
+      z0 = (int)(tile % nzt) * TL;
+      nl = N - z0 < TL ? N - z0 : TL;
+      base = AXIS == 1 ? (size_t)o * N * N + z0 : (size_t)o * N + z0;
+      es = AXIS == 1 ? (size_t)N : (size_t)N * N;
+    }
+    if constexpr (MODE == MR_GEN) {
+      // every lane of a line's slot generates elements g, g + GP, ... of it
+      const int l = t / GP, g = t % GP;
+      if (l < nl) {
+        // aligned lattice (complex plans refuse rotation), level factor 1:
+        // the cell row of the pencil, inside the mask's z range
+        const long long line = tile * TL + l;
+        const long long X = line / N, Y = line % N;
+        const Level& L = a.z.L;
+        long long lo, hi;
+        col_range(L, a.z.m, X, Y, lo, hi);
+        const int cm = L.c - 1;
+        const T* row = (const T*)a.z.cellT +
+                       ((size_t)((int)(X - L.o - L.h) & cm) * L.c + ((int)(Y - L.o - L.h) & cm)) * L.c;
+        const int zoff = -(int)(L.o + L.h);
+        cx<T>* col = lds + l * PS;
+        for (int e = g; e < N; e += GP) {
+          const T v = (e >= lo && e <= hi) ? row[(e + zoff) & cm] : (T)0;
+          col[pad(e)] = mk(v, (T)0);
+          s1 += (double)v;
+          s2 += (double)v * (double)v;
+        }
+      }
+    } else if constexpr (AXIS == 2) {
+      constexpr int TOT = TL * N;
+      for (int i0 = 0; i0 < TOT; i0 += NT * U) {
+        cx<T> v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int i = i0 + u * NT + t;
+          if (i < nl * N) v[u] = src[base + i];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int i = i0 + u * NT + t;
+          if (i < nl * N) {
+            lds[(i / N) * PS + pad(i % N)] = v[u];
+            if (a.mom) { s1 += (double)v[u].x; s2 += (double)v[u].x * v[u].x + (double)v[u].y * v[u].y; }
+          }
+        }
+      }
+    } else {
+      constexpr int TOT = TL * N;
+      for (int i0 = 0; i0 < TOT; i0 += NT * U) {
+        cx<T> v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int i = i0 + u * NT + t;
+          if (i < TOT && i % TL < nl) v[u] = src[base + (size_t)(i / TL) * es + i % TL];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int i = i0 + u * NT + t;
+          if (i < TOT && i % TL < nl) {
+            lds[(i % TL) * PS + pad(i / TL)] = v[u];
+            if (a.mom) { s1 += (double)v[u].x; s2 += (double)v[u].x * v[u].x + (double)v[u].y * v[u].y; }
+          }
+        }
+      }
+    }
+    __syncthreads();
+    {
+      const int l = t / GP, g = t % GP;
+      if (l < nl && g < G) {
+        cx<T>* col = lds + l * PS;
+        cx<T> v[E];
+#pragma unroll
+        for (int i = 0; i < NB0; ++i)
+#pragma unroll
+          for (int r = 0; r < R0; ++r) v[i * R0 + r] = col[pad(first_index<N>(g, i, r))];
+        wave_sync();
+        fft_column<T, N, DIR>(col, g, (const cx<T>*)a.tw, v);
+      }
+    }
+    __syncthreads();
+    if constexpr (MODE == MR_BIN) {
+      // element (kx = e, ky = o, kz = z0 + l) of the spectrum, scaled by
+      // 1/n^3; lane g of line l's slot takes kx in [g CH, (g + 1) CH) and
+      // adds runs of equal bin in registers, one LDS atomic pair per run
+      constexpr int CH = (N + GP - 1) / GP;
+      const int l = t / GP, g = t % GP;
+      if (l < nl) {
+        const int k = sidx(o, N), lz = sidx(z0 + l, N);
+        const int base2 = k * k + lz * lz;
+        const T sc = (T)a.scale;
+        const cx<T>* col = lds + l * PS;
+        int cur = -2;
+        double rs = 0.0, rs2 = 0.0;
+        const int e0 = g * CH, e1 = (g + 1) * CH < N ? (g + 1) * CH : N;
+        // bin of the first element from the start-of-walk table; after that
+        // n2 moves by small steps, so the bin is walked from the previous one
+        int b = -1;
+        if (e0 < e1) {
+          const int h0 = sidx(e0, N), n20 = h0 * h0 + base2;
+          b = a.lut[isqrt_ll(n20)];
+        }
+        for (int e = e0; e < e1; ++e) {
+          const cx<T> f = scale(col[pad(e)], sc);
+          if (e == 0 && base2 == 0 && o == 0 && z0 + l == 0) { a.f0[0] = (double)f.x; a.f0[1] = (double)f.y; }
+          const int h = sidx(e, N);
+          const int n2 = h * h + base2;
+          const double I = ((double)f.x * f.x + (double)f.y * f.y) * a.iscale;
+          tot += I;
+          while (b < a.nbins && n2 >= a.U[b + 1]) ++b;
+          while (b >= 0 && n2 < a.U[b]) --b;
+          if (b != cur) {
+            if (cur >= 0 && cur < a.nbins) { atomicAdd(&hist[2 * cur], rs); atomicAdd(&hist[2 * cur + 1], rs2); }
+            cur = b;
+            rs = 0.0;
+            rs2 = 0.0;
+          }
+          rs += I;
+          rs2 += I * I;
+        }
+        if (cur >= 0 && cur < a.nbins) { atomicAdd(&hist[2 * cur], rs); atomicAdd(&hist[2 * cur + 1], rs2); }
+      }
+    } else {
+      const T sc = (T)a.scale;
+      if constexpr (AXIS == 2) {
+        for (int i = t; i < nl * N; i += NT) dst[base + i] = scale(lds[(i / N) * PS + pad(i % N)], sc);
+      } else {
+        for (int i = t; i < N * TL; i += NT) {
+          const int e = i / TL, l2 = i % TL;
+          if (l2 < nl) dst[base + e * es + l2] = scale(lds[l2 * PS + pad(e)], sc);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (a.mom) {                                       // fixed-order block sum of the input values
+    __shared__ double w1[NT / 64], w2[NT / 64];
+    for (int o = 32; o > 0; o >>= 1) { s1 += __shfl_down(s1, o, 64); s2 += __shfl_down(s2, o, 64); }
+    if (t % 64 == 0) { w1[t / 64] = s1; w2[t / 64] = s2; }
+    __syncthreads();
+    if (t == 0) {
+      double u1 = 0.0, u2 = 0.0;
+      for (int i = 0; i < NT / 64; ++i) { u1 += w1[i]; u2 += w2[i]; }
+      a.mom[2 * (size_t)blockIdx.x] = u1;
+      a.mom[2 * (size_t)blockIdx.x + 1] = u2;
+    }
+  }
+  if constexpr (MODE == MR_BIN) {
+    atomicAdd(&hist[nv - 1], tot);
+    __syncthreads();
+    for (int i = t; i < nv; i += NT) a.part[(size_t)blockIdx.x * nv + i] = hist[i];
+  }
+}
+
+// blocks of a pass: one tile per block, except the binning pass, whose
+// persistent blocks (at most kMrBinBlocks) each own one set of partials
+constexpr int kMrBinBlocks = 1024;
+template <int N> static int mr_blocks_t(int prec, int axis, int mode) {
+  long long nt;
+  if (prec == 0) nt = axis == 2 ? mr_tiles<float, N, 2, 0>() : (mode == MR_BIN ? mr_tiles<float, N, 0, MR_BIN>() : mr_tiles<float, N, 1, 0>());
+  else nt = axis == 2 ? mr_tiles<double, N, 2, 0>() : (mode == MR_BIN ? mr_tiles<double, N, 0, MR_BIN>() : mr_tiles<double, N, 1, 0>());
+  return (int)(mode == MR_BIN ? (nt < kMrBinBlocks ? nt : kMrBinBlocks) : nt);
+}
+
+template <typename T, int N, int DIR, int AXIS, int MODE>
+static hipError_t mr_launch(const MrArgs& a, int nblk, hipStream_t s) {
+  const size_t shm = MODE == MR_BIN ? (2 * (size_t)a.nbins + 1) * sizeof(double) : 0;
+  hipLaunchKernelGGL((k_mr_axis<T, N, DIR, AXIS, MODE>), dim3(nblk), dim3(MrCfg<T, N, MODE == MR_BIN>::threads), shm, s, a);
+  return hipGetLastError();
+}
+
+template <typename T, int N>
+static hipError_t mr_axis_t(int axis, int dir, int mode, const MrArgs& a, hipStream_t s) {
+  const int nblk = mr_blocks_t<N>(sizeof(T) == 4 ? 0 : 1, axis, mode);
+  if (mode == MR_GEN) return axis == 2 && dir < 0 ? mr_launch<T, N, -1, 2, MR_GEN>(a, nblk, s) : hipErrorInvalidValue;
+  if (mode == MR_BIN) return axis == 0 && dir < 0 ? mr_launch<T, N, -1, 0, MR_BIN>(a, nblk, s) : hipErrorInvalidValue;
+  if (dir < 0) {
+    if (axis == 0) return mr_launch<T, N, -1, 0, MR_LOAD>(a, nblk, s);
+    if (axis == 1) return mr_launch<T, N, -1, 1, MR_LOAD>(a, nblk, s);
+    return mr_launch<T, N, -1, 2, MR_LOAD>(a, nblk, s);
+  }
+  if (axis == 0) return mr_launch<T, N, 1, 0, MR_LOAD>(a, nblk, s);
+  if (axis == 1) return mr_launch<T, N, 1, 1, MR_LOAD>(a, nblk, s);
+  return mr_launch<T, N, 1, 2, MR_LOAD>(a, nblk, s);
+}
+
+bool mr_size(int n) {
+  switch (n) {
+#define UR_MR_CASE(NN) case NN:
+    UR_MR_SIZES(UR_MR_CASE) return true;
+#undef UR_MR_CASE
+    default: return false;
+  }
+}
+
+int mr_axis_blocks(int prec, int n, int axis, int mode) {
+  switch (n) {
+#define UR_MR_CASE(NN) case NN: return mr_blocks_t<NN>(prec, axis, mode);
+    UR_MR_SIZES(UR_MR_CASE)
+#undef UR_MR_CASE
+    default: return 0;
+  }
+}
+
+hipError_t launch_mr_axis(int prec, int n, int axis, int dir, int mode, const MrArgs& a, hipStream_t s) {
+  switch (n) {
+#define UR_MR_CASE(NN) case NN: return prec == 0 ? mr_axis_t<float, NN>(axis, dir, mode, a, s) : mr_axis_t<double, NN>(axis, dir, mode, a, s);
+    UR_MR_SIZES(UR_MR_CASE)
+#undef UR_MR_CASE
+    default: return hipErrorNotSupported;
+  }
+}
+
+// |F|^2 of a full complex spectrum into integer-threshold |Q| bins: blocks
+// stride over (kx, ky) rows, threads over kz; per-block partials of the
+// sums and sums of squares (LDS FP64 atomics) and of the total intensity.
+template <typename T>
+__global__ void __launch_bounds__(256) k_mr_bin(MrBinArgs a) {
+  extern __shared__ double hist[];                 // 2 nbins + 1
+  const int nv = 2 * a.nbins + 1;
+  for (int i = threadIdx.x; i < nv; i += 256) hist[i] = 0.0;
+  __syncthreads();
+  const cx<T>* __restrict__ S = (const cx<T>*)a.S;
+  const int n = a.n;
+  double tot = 0.0;
+  for (long long r = blockIdx.x; r < (long long)n * n; r += gridDim.x) {
+    const int h = sidx((int)(r / n), n), k = sidx((int)(r % n), n);
+    const int base = h * h + k * k;
+    for (int z = threadIdx.x; z < n; z += 256) {
+      const cx<T> f = S[r * n + z];
+      if (r == 0 && z == 0) { a.f0[0] = (double)f.x; a.f0[1] = (double)f.y; }
+      const int l = sidx(z, n);
+      const int n2 = base + l * l;
+      const double I = ((double)f.x * f.x + (double)f.y * f.y) * a.iscale;
+      tot += I;
+      int b = a.lut[isqrt_ll(n2)];
+      while (b < a.nbins && n2 >= a.U[b + 1]) ++b;
+      if (b >= 0 && b < a.nbins) {
+        atomicAdd(&hist[2 * b], I);
+        atomicAdd(&hist[2 * b + 1], I * I);
+      }
+    }
+  }
+  atomicAdd(&hist[nv - 1], tot);
+  __syncthreads();
+  for (int i = threadIdx.x; i < nv; i += 256) a.part[(size_t)blockIdx.x * nv + i] = hist[i];
+}
+
+hipError_t launch_mr_bin(int prec, const MrBinArgs& a, int nblocks, hipStream_t s) {
+  const size_t shm = (2 * (size_t)a.nbins + 1) * sizeof(double);
+  if (prec == 0) hipLaunchKernelGGL(k_mr_bin<float>, dim3(nblocks), dim3(256), shm, s, a);
+  else hipLaunchKernelGGL(k_mr_bin<double>, dim3(nblocks), dim3(256), shm, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace ur
