@@ -53,9 +53,9 @@ def _spectrum(orc, n):
 @pytest.mark.parametrize("n", [40, 48, 96, 100, 160, 200, 250])
 @pytest.mark.parametrize("prec", [0, 1])
 def test_mixed_fft3d_forward_and_inverse(ur, orc, n, prec):
-    """Every coefficient of a random complex box (radix sequences 8,5 /
-    8,2,3 / 8,4,3 / 4,5,5 / 8,4,5 / 8,5,5 / 2,5,5,5), and the inverse
-    transform back to the input."""
+    """Every coefficient of a random complex box (radix sequences 2,2,2,5 /
+    2,2,2,2,3 / 2,2,2,2,2,3 / 2,2,5,5 / 2,2,2,2,2,5 / 2,2,2,5,5 / 2,5,5,5),
+    and the inverse transform back to the input."""
     import torch
     _say(f"mixed fft3d n={n} prec={prec}")
     z, F = _spectrum(orc, n)
@@ -199,3 +199,51 @@ def test_mixed_ewald_and_refusals(ur, orc):
     with pytest.raises(ur.UltimaError, match="status 2"):
         plan.simulate(cell, wl.mask, wl.zoom, h)
     torch.cuda.synchronize()
+
+
+def test_mixed_simulate_and_ewald_in_one_graph(ur, orc):
+    """A mixed-radix box (200^3 FP32: density generated in the z pass, |F|^2
+    binned in the x pass, the finalize) and an Ewald image of a power-of-two
+    box's spectrum, recorded in one HIP graph; three replays, with eager work
+    and synchronisation between them, each against the eager results (curve
+    to rounding, the image exactly)."""
+    import torch
+    wl = W.mixed(200, 0, nbins=64)
+    plan = ur.Plan(wl.n, wl.voxel, 0, c2c=True)
+    plan.set_bins(wl.edges)
+    cell = ur.DeviceCell.from_host(wl.cell)
+    h = ur.Hist(wl.nbins)
+    p2 = ur.Plan(64, 1.0, 0)
+    rho = torch.as_tensor(W.random_density(5, 64), dtype=torch.float32, device="cuda").contiguous()
+    spec = p2.fft3d(rho)
+    geo = W.detector(W.rotation([0.3, -0.5, 0.8], 1.1), rel_spread=0.05, n_lambda=8, pixel=5.0, nu=48, nv=40)
+    img = torch.empty((geo.nv, geo.nu), dtype=torch.float64, device="cuda")
+    s = torch.cuda.Stream()
+
+    def run():
+        plan.simulate(cell, wl.mask, wl.zoom, h, stream=s)
+        p2.ewald_image(spec, geo, out=img, stream=s)
+
+    with torch.cuda.stream(s):
+        run()
+    torch.cuda.synchronize()
+    m_e, i_e = h.mean.cpu().numpy(), img.cpu().numpy()
+    g = ur.Graph(s)
+    with torch.cuda.stream(s):
+        with g:
+            run()
+    for rep in range(3):
+        h.mean.fill_(0.0)
+        img.fill_(0.0)
+        junk = torch.randn(1 << 20, device="cuda").sum()      # eager work between replays
+        torch.cuda.synchronize()
+        g.launch()
+        torch.cuda.synchronize()
+        m_g = h.mean.cpu().numpy()
+        ok = ~np.isnan(m_e)
+        assert np.array_equal(np.isnan(m_g), np.isnan(m_e))
+        assert np.max(np.abs(m_g[ok] - m_e[ok]) / np.abs(m_e[ok])) <= 1e-12
+        assert np.array_equal(img.cpu().numpy(), i_e)
+        del junk
+    ref = orc.simulate(wl)
+    compare_bins(h.numpy(), ref, F32_BIN, "mixed in a graph", n=wl.n)
