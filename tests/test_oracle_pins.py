@@ -939,3 +939,25 @@ def test_oriented_points_match_the_whole_box(oracle_lib, interp):
     whole = oracle.ed1_grains(n, cg, mask, seeds, rots, interp)
     pts = oracle.oriented_points(n, cg, mask, xyz, seeds, rots, interp)
     assert np.array_equal(pts, whole[xyz[:, 0], xyz[:, 1], xyz[:, 2]])
+
+
+def test_constant_solvent_is_a_background_shift(oracle_lib):
+    """A particle in a solvent of constant density rho_s (the outlook's
+    surrounding matrix, without fluctuations) against the particle with its
+    cell background lowered by rho_s: the two boxes differ by a uniform box,
+    whose eq. 1 transform is zero away from q = 0, so every bin that holds
+    no q = 0 voxel agrees (the first bin's lower edge is above zero here)."""
+    import dataclasses
+    import oracle
+    wl = W.small(32, c=8, n_atoms=6, seed=11, radius=10.0, nbins=40, prec=1)
+    rho_s = 0.7
+    cg = oracle.cell_synth(wl.cell)
+    inside = oracle.density(wl, cg) != 0.0
+    solvent = np.where(inside, oracle.density(wl, cg), rho_s)
+    shifted = dataclasses.replace(wl, cell=dataclasses.replace(wl.cell, background=wl.cell.background - rho_s))
+    a = oracle.bin_spectrum(oracle.forward(solvent), wl.voxel, wl.edges)
+    b = oracle.simulate(shifted)
+    assert wl.edges[0] > 0.0
+    pop = a["count"] > 0
+    assert np.array_equal(a["count"], b["count"])
+    assert np.max(np.abs(a["mean"][pop] - b["mean"][pop])) <= 1e-12 * np.max(a["mean"][pop])
