@@ -80,7 +80,9 @@ typedef enum { UR_F32 = 0, UR_F64 = 1 } ur_prec;
 typedef struct { int32_t kind; int64_t p0; int64_t p1; } ur_mask;
 
 /* Unit cell ("ED-Unit", workflow step 1).  Edge c voxels (power of two
- * dividing n1/2); n_atoms Gaussian atoms.  DEVICE arrays, FP64:
+ * dividing n1/2; any edge up to 256, such as the paper's reduced 105^3
+ * cell, for ur_cell_synth and for ur_simulate on mixed-radix plans, whose
+ * generator wraps the cell index by a modulo); n_atoms Gaussian atoms.  DEVICE arrays, FP64:
  * xyz[3*n_atoms] centres in cell-voxel units, amp[n_atoms] electrons per atom,
  * sigma[n_atoms] widths in voxels.  Each voxel holds the Gaussian integrated
  * over it, with periodic images, plus `background`.

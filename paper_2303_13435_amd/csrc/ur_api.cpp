@@ -589,9 +589,13 @@ static ur_status check_hist(const ur_hist* h) {
   return UR_OK;
 }
 
-static ur_status check_cell(const ur_cell* c) {
+// any_edge: the call takes cell edges that are not powers of two (cell
+// synthesis, and aligned ED-1 of mixed-radix plans, whose generator wraps by a
+// modulo); every other generator wraps with a bit mask
+static ur_status check_cell(const ur_cell* c, bool any_edge = false) {
   if (!c) return fail(UR_ERR_INVALID, "cell is null");
-  if (!is_pow2(c->c) || c->c > 256) return fail(UR_ERR_INVALID, "cell edge %d must be a power of two <= 256", c->c);
+  if (c->c < 1 || c->c > 256 || (!any_edge && !is_pow2(c->c)))
+    return fail(UR_ERR_INVALID, "cell edge %d must be a power of two <= 256 (any edge <= 256 on mixed-radix plans)", c->c);
   if (c->n_atoms < 0 || c->n_atoms > (1 << 20)) return fail(UR_ERR_INVALID, "n_atoms = %d out of range", c->n_atoms);
   if (c->n_atoms > 0 && (!c->xyz || !c->amp || !c->sigma)) return fail(UR_ERR_INVALID, "atom arrays must be non-null");
   if (!isfinite(c->background)) return fail(UR_ERR_INVALID, "background must be finite");
@@ -835,7 +839,7 @@ extern "C" {
 ur_status ur_cell_synth(ur_plan* p, const ur_cell* cell, double* cell_out, void* stream) {
   if (p) p->keep_valid = false;
   if (!p || !cell_out) return fail(UR_ERR_INVALID, "null argument");
-  UR_TRY(check_cell(cell));
+  UR_TRY(check_cell(cell, true));
   hipStream_t s = (hipStream_t)stream;
   size_t need = align256(std::max<size_t>(1, (size_t)cell->n_atoms * 3 * cell->c) * 8);
   UR_TRY(ensure_cell_scratch(p, std::max(need, p->cs_bytes), s));
@@ -870,7 +874,7 @@ ur_status ur_simulate(ur_plan* p, const ur_cell* cell, const ur_mask* mask, cons
   UR_TRY(need_in_core(p));
   if (p->nbins < 1) return fail(UR_ERR_STATE, "no bins set on the plan");
   UR_TRY(check_hist(h));
-  UR_TRY(check_cell(cell));
+  UR_TRY(check_cell(cell, p->mixed));
   FwdGeom g;
   UR_TRY(check_level(p, cell, mask, zoom, g.L, g.m));
   ZArgs rot_args{};

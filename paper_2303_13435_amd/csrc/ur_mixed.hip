@@ -91,13 +91,14 @@ __global__ void __launch_bounds__((MrCfg<T, N, MODE == MR_BIN>::threads)) k_mr_a
         const Level& L = a.z.L;
         long long lo, hi;
         col_range(L, a.z.m, X, Y, lo, hi);
-        const int cm = L.c - 1;
-        const T* row = (const T*)a.z.cellT +
-                       ((size_t)((int)(X - L.o - L.h) & cm) * L.c + ((int)(Y - L.o - L.h) & cm)) * L.c;
+        // periodic cell index by a true modulo: any cell edge
+        const int c = L.c;
+        auto wrap = [c](long long v) { const long long r = v % c; return (int)(r < 0 ? r + c : r); };
+        const T* row = (const T*)a.z.cellT + ((size_t)wrap(X - L.o - L.h) * c + wrap(Y - L.o - L.h)) * c;
         const int zoff = -(int)(L.o + L.h);
         cx<T>* col = lds + l * PS;
         for (int e = g; e < N; e += GP) {
-          const T v = (e >= lo && e <= hi) ? row[(e + zoff) & cm] : (T)0;
+          const T v = (e >= lo && e <= hi) ? row[wrap(e + zoff)] : (T)0;
           col[pad(e)] = mk(v, (T)0);
           s1 += (double)v;
           s2 += (double)v * (double)v;

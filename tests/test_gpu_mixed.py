@@ -247,3 +247,32 @@ def test_mixed_simulate_and_ewald_in_one_graph(ur, orc):
         del junk
     ref = orc.simulate(wl)
     compare_bins(h.numpy(), ref, F32_BIN, "mixed in a graph", n=wl.n)
+
+
+@pytest.mark.parametrize("n,prec,c", [(200, 1, 21), (250, 0, 105), (100, 0, 7)])
+def test_mixed_any_cell_edge(ur, orc, n, prec, c):
+    """Cells whose edge is not a power of two (the paper's block-reduced cell
+    is 105^3) on mixed-radix boxes, whose generator wraps the cell index by
+    a modulo: the whole forward path against the oracle.  The generators of
+    the other paths wrap with a bit mask and refuse such cells."""
+    import torch
+    wl = W.mixed(n, prec, nbins=64, c=c)
+    _say(f"mixed simulate n={n} prec={prec} cell {c}^3")
+    ref = orc.simulate(wl)
+    plan = ur.Plan(n, wl.voxel, prec, c2c=True)
+    plan.set_bins(wl.edges)
+    cell = ur.DeviceCell.from_host(wl.cell)
+    h = ur.Hist(wl.nbins)
+    plan.simulate(cell, wl.mask, wl.zoom, h)
+    torch.cuda.synchronize()
+    got = h.numpy()
+    compare_bins(got, ref, F32_BIN if prec == 0 else F64_BIN, f"mixed, cell {c}^3", n=n)
+    rt = 1e-6 if prec == 0 else 1e-12
+    assert abs(got["totals"][3] - ref["rho_sumsq"]) <= rt * ref["rho_sumsq"]
+    with pytest.raises(ur.UltimaError, match="status 1"):
+        plan.rho_generate(cell, wl.mask, wl.zoom)
+    p2 = ur.Plan(128, 1.0, prec)
+    p2.set_bins(W.default_log_edges(128, 1.0, 16))
+    with pytest.raises(ur.UltimaError, match="status 1"):
+        p2.simulate(cell, W.sphere(40.0), W.Zoom(128, 1), ur.Hist(16))
+    torch.cuda.synchronize()

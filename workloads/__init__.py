@@ -254,11 +254,13 @@ def lattice_sphere(name: str, n: int, c: int, n_atoms: int, seed: int, radius: f
                     default_log_edges(n, voxel, nbins))
 
 
-def mixed(n: int, prec: int = PREC_F32, nbins: int = 256) -> Workload:
+def mixed(n: int, prec: int = PREC_F32, nbins: int = 256, c: int = 16) -> Workload:
     """A box whose edge is not a power of two (2^a 3^b 5^c: the paper's 250,
-    500, 1000, 2000 family): the M1024 recipe (16-voxel cell, 40 atoms,
-    seed 2) in a sphere of radius 0.39 n, complex transform, log bins."""
-    cell = draw_atoms(2, 40, 16)
+    500, 1000, 2000 family): the M1024 recipe (cell of c voxels, 16 as
+    there, 40 atoms, seed 2) in a sphere of radius 0.39 n, complex
+    transform, log bins.  c may be any edge (the paper's reduced cell is
+    105^3)."""
+    cell = draw_atoms(2, 40, c)
     return Workload(f"M{n}" + ("_f64" if prec == PREC_F64 else ""), n, 1.0, prec, "c2c", cell,
                     sphere(0.39 * n), Zoom(n, 1), default_log_edges(n, 1.0, nbins))
 
