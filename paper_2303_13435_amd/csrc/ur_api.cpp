@@ -646,7 +646,11 @@ static ur_status check_level(const ur_plan* p, const ur_cell* cell, const ur_mas
   if (m->kind < 0 || m->kind > 3) return fail(UR_ERR_INVALID, "mask kind %d unknown", m->kind);
   if (m->p0 > (1ll << 40) || m->p1 > (1ll << 40)) return fail(UR_ERR_INVALID, "mask parameters too large");
   if (p->mixed) {
-    if (z->n1 != p->n || z->factor != 1) return fail(UR_ERR_UNSUPPORTED, "mixed-radix boxes run ED-1 only (zoom n1 = n, factor 1)");
+    // ED-1 (n1 = n, factor 1) or a zoom level of any even ED-1 edge by a
+    // power-of-two factor (the zoom tables need power-of-two cells)
+    if (z->factor == 1 && z->n1 != p->n) return fail(UR_ERR_UNSUPPORTED, "mixed-radix ED-1 levels have n1 = n");
+    if (z->factor > 1 && (!is_pow2(z->factor) || !is_pow2(cell->c) || z->n1 % z->factor || z->n1 % 2 || z->n1 < 2))
+      return fail(UR_ERR_UNSUPPORTED, "mixed-radix zoom levels take power-of-two factors and cells, and an even n1 divisible by the factor");
   } else if (!is_pow2(z->n1) || !is_pow2(z->factor)) {
     return fail(UR_ERR_INVALID, "zoom n1 and factor must be powers of two");
   }
@@ -887,7 +891,7 @@ ur_status ur_simulate(ur_plan* p, const ur_cell* cell, const ur_mask* mask, cons
     CellTables t;
     {
       PassTimer tm(p, P_CELL, s);
-      UR_TRY(prepare_cell(p, cell, 1, t, s));
+      UR_TRY(prepare_cell(p, cell, zoom->factor, t, s));
     }
     {
       const double c = cell->c;
@@ -895,7 +899,15 @@ ur_status ur_simulate(ur_plan* p, const ur_cell* cell, const ur_mask* mask, cons
     }
     ZArgs za = rot_args;
     za.cellT = t.cellT; za.cb = t.cb; za.pre = t.pre; za.L = g.L; za.m = g.m; za.cbn = t.cbn;
-    UR_TRY(mr_transform(p, nullptr, p->ws + lay.A, -1, (double*)(p->ws + lay.mom), &za, &lay, s));
+    double* mom = (double*)(p->ws + lay.mom);
+    if (zoom->factor > 1) {
+      // zoom level: block sums of ED-1 written as a complex box first, then
+      // the three passes from it (the generating z pass serves ED-1 only)
+      UR_HIP(launch_level_complex(p->prec, p->n, za, p->ws + lay.A, mom, s));
+      UR_TRY(mr_transform(p, p->ws + lay.A, p->ws + lay.A, -1, nullptr, nullptr, &lay, s));
+      return mr_finalize(p, lay, mr_axis_blocks(p->prec, p->n, 0, MR_BIN), h, p->n * p->n, s);
+    }
+    UR_TRY(mr_transform(p, nullptr, p->ws + lay.A, -1, mom, &za, &lay, s));
     return mr_finalize(p, lay, mr_axis_blocks(p->prec, p->n, 0, MR_BIN), h, mr_axis_blocks(p->prec, p->n, 2, MR_GEN), s);
   }
   Layout lay = layout_incore(p, p->nbins);

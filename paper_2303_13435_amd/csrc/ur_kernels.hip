@@ -2189,6 +2189,41 @@ hipError_t launch_bspline_cell(int c, double* cell, hipStream_t s) {
   return hipSuccess;
 }
 
+// A level's density as complex values (rho, 0) for the mixed-radix passes
+// (zoom levels there: block sums of ED-1), one block per (x, y) pencil, with
+// the pencil's [sum rho, sum rho^2] (fixed-order block sum) in mom.
+template <typename T>
+__global__ void __launch_bounds__(256) k_level_complex(ZArgs a, int n, cx<T>* __restrict__ S, double* __restrict__ mom) {
+  __shared__ double r1[256], r2[256];
+  const long long t = blockIdx.x;
+  Pencil<T> p;
+  p.init(a, t / n, t % n);
+  cx<T>* row = S + t * n;
+  double s1 = 0.0, s2 = 0.0;
+  for (int z = threadIdx.x; z < n; z += 256) {
+    const T v = p.value(a, z);
+    row[z] = mk(v, (T)0);
+    s1 += (double)v;
+    s2 += (double)v * (double)v;
+  }
+  r1[threadIdx.x] = s1;
+  r2[threadIdx.x] = s2;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double u1 = 0.0, u2 = 0.0;
+    for (int i = 0; i < 256; ++i) { u1 += r1[i]; u2 += r2[i]; }
+    mom[2 * t] = u1;
+    mom[2 * t + 1] = u2;
+  }
+}
+
+hipError_t launch_level_complex(int prec, int n, const ZArgs& a, void* S, double* mom, hipStream_t s) {
+  const unsigned nn = (unsigned)((long long)n * n);
+  if (prec == 0) hipLaunchKernelGGL(k_level_complex<float>, dim3(nn), dim3(256), 0, s, a, n, (cx<float>*)S, mom);
+  else hipLaunchKernelGGL(k_level_complex<double>, dim3(nn), dim3(256), 0, s, a, n, (cx<double>*)S, mom);
+  return hipGetLastError();
+}
+
 hipError_t launch_rho_generate(int prec, int n, int x_lo, int x_hi, const ZArgs& a, void* rho, hipStream_t s) {
   const unsigned nn = (unsigned)((long long)(x_hi - x_lo + 1) * n);
   if (prec == 0) hipLaunchKernelGGL(k_rho_generate<float>, dim3(nn), dim3(256), 0, s, a, n, x_lo, (float*)rho);

@@ -287,6 +287,8 @@ hipError_t launch_fold_reduce(int c3, const double* part, int nblk, double* gcel
 hipError_t launch_grad_amp(int c, int n_atoms, const double* prof, const double* gcell, double* grad_amp, hipStream_t s);
 // periodic cubic B-spline coefficients of a c^3 FP64 cell, in place
 hipError_t launch_bspline_cell(int c, double* cell, hipStream_t s);
+// a level's density as complex (rho, 0) with per-pencil moments (mixed-radix zoom levels)
+hipError_t launch_level_complex(int prec, int n, const ZArgs& a, void* S, double* mom, hipStream_t s);
 hipError_t launch_rho_generate(int prec, int n, int x_lo, int x_hi, const ZArgs& a, void* rho, hipStream_t s);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 hipError_t launch_bin_counts(int n, int nkz, int r2c, int nbins, const int* U, unsigned long long* tmp, double* out, hipStream_t s);

@@ -167,8 +167,9 @@ def test_mixed_2000_counts_and_moments(ur, orc):
 
 def test_mixed_ewald_and_refusals(ur, orc):
     """The Ewald image reads the natural-order spectrum of a mixed-radix plan;
-    real transforms, zoom levels, the adjoint and the voxel form factor are
-    refused on such plans, and edges outside the compiled set at creation."""
+    real transforms, zoom factors that are not powers of two, the adjoint and
+    the voxel form factor are refused on such plans, and edges outside the
+    compiled set at creation."""
     import torch
     n = 40
     z, F = _spectrum(orc, n)
@@ -189,7 +190,7 @@ def test_mixed_ewald_and_refusals(ur, orc):
     cell = ur.DeviceCell.from_host(wl.cell)
     h = ur.Hist(wl.nbins)
     with pytest.raises(ur.UltimaError, match="status 2"):
-        plan.simulate(cell, wl.mask, W.Zoom(2 * n, 2), h)
+        plan.simulate(cell, wl.mask, W.Zoom(3 * n, 3), h)              # factor not a power of two
     plan.simulate(cell, wl.mask, wl.zoom, h)
     g = torch.zeros(wl.nbins, dtype=torch.float64, device="cuda")
     ga = torch.zeros(wl.cell.n_atoms, dtype=torch.float64, device="cuda")
@@ -276,3 +277,28 @@ def test_mixed_any_cell_edge(ur, orc, n, prec, c):
     with pytest.raises(ur.UltimaError, match="status 1"):
         p2.simulate(cell, W.sphere(40.0), W.Zoom(128, 1), ur.Hist(16))
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("n,n1,f,prec", [(40, 160, 4, 1), (100, 800, 8, 0), (250, 1000, 4, 0)])
+def test_mixed_zoom_level(ur, orc, n, n1, f, prec):
+    """Zoom levels on mixed-radix boxes (the paper's ED-2: its ED-1 block-summed
+    by 16 into a 250^3 box): the level's density (block sums of ED-1 over
+    f^3 voxels, centred) and its curve against the oracle (O3 then O4-O8)."""
+    import torch
+    wl = W.mixed_zoom(n, n1, f, prec)
+    _say(f"mixed zoom level {n}^3 from {n1}^3 / {f} prec={prec}")
+    ref = orc.simulate(wl, return_fields=True)
+    plan = ur.Plan(n, wl.voxel, prec, c2c=True)
+    plan.set_bins(wl.edges)
+    cell = ur.DeviceCell.from_host(wl.cell)
+    h = ur.Hist(wl.nbins)
+    plan.simulate(cell, wl.mask, wl.zoom, h)
+    torch.cuda.synchronize()
+    got = h.numpy()
+    compare_bins(got, ref, F32_BIN if prec == 0 else F64_BIN, "mixed zoom level", n=n)
+    rt = 1e-6 if prec == 0 else 1e-12
+    assert abs(got["totals"][3] - ref["rho_sumsq"]) <= rt * ref["rho_sumsq"]
+    rho = plan.rho_generate(cell, wl.mask, wl.zoom)
+    torch.cuda.synchronize()
+    err = np.max(np.abs(rho.cpu().numpy().astype(np.float64) - ref["rho"])) / np.max(np.abs(ref["rho"]))
+    assert err <= (1e-6 if prec == 0 else 1e-14)

@@ -265,6 +265,16 @@ def mixed(n: int, prec: int = PREC_F32, nbins: int = 256, c: int = 16) -> Worklo
                     sphere(0.39 * n), Zoom(n, 1), default_log_edges(n, 1.0, nbins))
 
 
+def mixed_zoom(n: int, n1: int, f: int, prec: int = PREC_F32, nbins: int = 64) -> Workload:
+    """A zoom level on a box whose edge is not a power of two (the paper's
+    ED-2 is its 4000^3 ED-1 block-summed by 16 into 250^3): the mixed()
+    particle on an ED-1 grid of edge n1 (sphere of radius 0.39 n1), block
+    factor f, voxel f, complex transform."""
+    cell = draw_atoms(2, 40, 16)
+    return Workload(f"M{n}_from{n1}f{f}", n, float(f), prec, "c2c", cell, sphere(0.39 * n1), Zoom(n1, f),
+                    default_log_edges(n, float(f), nbins))
+
+
 def c2() -> Workload:
     """512^3 FP32: 16-voxel cell with 40 atoms (seed 2), sphere R = 200,
     512 log bins."""
