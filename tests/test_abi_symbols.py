@@ -90,3 +90,21 @@ def test_struct_layouts_match_the_header(tmp_path):
         assert got[(cname, "size")] == ctypes.sizeof(py), cname
         for f, _ in py._fields_:
             assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
+
+
+def test_peak_integrals_argument_checks_without_gpu(built_lib):
+    """ur_peak_integrals validates before any device call: null pointers, a
+    bin or window count out of range and windows that are empty or not
+    finite are refused (UR_ERR_INVALID) on a host without a GPU."""
+    f = built_lib.ur_peak_integrals
+    f.argtypes = [ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                  ctypes.POINTER(ctypes.c_double), ctypes.c_void_p, ctypes.c_void_p]
+    buf = (ctypes.c_double * 16)()
+    p = ctypes.cast(buf, ctypes.c_void_p)
+    win = (ctypes.c_double * 4)(1.0, 2.0, 3.0, 4.0)
+    assert f(8, None, p, 1, win, p, None) == 1
+    assert f(0, p, p, 1, win, p, None) == 1
+    assert f(8, p, p, 0, win, p, None) == 1
+    assert f(8, p, p, 65, win, p, None) == 1
+    assert f(8, p, p, 1, (ctypes.c_double * 2)(2.0, 2.0), p, None) == 1
+    assert f(8, p, p, 2, (ctypes.c_double * 4)(1.0, 2.0, float("nan"), 4.0), p, None) == 1
