@@ -158,11 +158,11 @@ typedef struct ur_plan ur_plan;
  * else UR_ERR_UNSUPPORTED) whose transform runs one axis at a time through
  * radix 2/4/8, 3 and 5 stages; its spectrum (ur_fft3d_exec, and the input of
  * ur_intensity_bin and ur_ewald_image) is in natural order [kx][ky][kz].
- * Such plans run ED-1 levels (zoom n1 = n, factor 1) and zoom levels (a
- * power-of-two factor and cell edge, n1 even and divisible by the factor)
+ * Such plans run ED-1 levels (zoom n1 = n, factor 1) and zoom levels (any
+ * factor dividing an even n1, such as the paper's 125; power-of-two cells)
  * through ur_simulate, ur_simulate_rho (complex density), ur_rho_generate,
- * ur_fft3d_exec, ur_intensity_bin and ur_ewald_image; the adjoint, other
- * zoom factors and the voxel form factor fail with UR_ERR_UNSUPPORTED.  Other edges that are not
+ * ur_fft3d_exec, ur_intensity_bin and ur_ewald_image; the adjoint and the
+ * voxel form factor fail with UR_ERR_UNSUPPORTED.  Other edges that are not
  * powers of two fail with UR_ERR_INVALID. */
 ur_status ur_plan_create(int32_t n, double voxel, int32_t prec, uint32_t flags, ur_plan** out);
 void ur_plan_destroy(ur_plan* plan);

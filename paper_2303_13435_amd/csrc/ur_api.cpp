@@ -645,12 +645,13 @@ static ur_status check_level(const ur_plan* p, const ur_cell* cell, const ur_mas
   if (!m || !z) return fail(UR_ERR_INVALID, "mask and zoom must be non-null");
   if (m->kind < 0 || m->kind > 3) return fail(UR_ERR_INVALID, "mask kind %d unknown", m->kind);
   if (m->p0 > (1ll << 40) || m->p1 > (1ll << 40)) return fail(UR_ERR_INVALID, "mask parameters too large");
+  if (z->factor < 1 || z->n1 < 1) return fail(UR_ERR_INVALID, "zoom factor %d and n1 %d must be positive", z->factor, z->n1);
   if (p->mixed) {
-    // ED-1 (n1 = n, factor 1) or a zoom level of any even ED-1 edge by a
-    // power-of-two factor (the zoom tables need power-of-two cells)
+    // ED-1 (n1 = n, factor 1) or a zoom level of any even ED-1 edge by any
+    // factor dividing it (the prefix-sum tables need power-of-two cells)
     if (z->factor == 1 && z->n1 != p->n) return fail(UR_ERR_UNSUPPORTED, "mixed-radix ED-1 levels have n1 = n");
-    if (z->factor > 1 && (!is_pow2(z->factor) || !is_pow2(cell->c) || z->n1 % z->factor || z->n1 % 2 || z->n1 < 2))
-      return fail(UR_ERR_UNSUPPORTED, "mixed-radix zoom levels take power-of-two factors and cells, and an even n1 divisible by the factor");
+    if (z->factor > 1 && (!is_pow2(cell->c) || z->n1 % z->factor || z->n1 % 2 || z->n1 < 2))
+      return fail(UR_ERR_UNSUPPORTED, "mixed-radix zoom levels take power-of-two cells and an even n1 divisible by the factor");
   } else if (!is_pow2(z->n1) || !is_pow2(z->factor)) {
     return fail(UR_ERR_INVALID, "zoom n1 and factor must be powers of two");
   }

@@ -241,7 +241,10 @@ struct Pencil {
       long long ax, bx, ay, by;
       block_dist(L, X, ax, bx);
       block_dist(L, Y, ay, by);
-      rin = mask_reach(a.m, bx, by);
+      // a factor that is not a power of two (mixed-radix levels) has blocks
+      // that are not aligned to cell periods: no whole-block table, every
+      // block summed pencil by pencil (value_zoom's exact route)
+      rin = (L.f & (L.f - 1)) ? -1 : mask_reach(a.m, bx, by);
       fx0 = (long long)L.f * (X - L.o);
       fy0 = (long long)L.f * (Y - L.o);
       if (L.f <= L.c) {

@@ -167,9 +167,9 @@ def test_mixed_2000_counts_and_moments(ur, orc):
 
 def test_mixed_ewald_and_refusals(ur, orc):
     """The Ewald image reads the natural-order spectrum of a mixed-radix plan;
-    real transforms, zoom factors that are not powers of two, the adjoint and
-    the voxel form factor are refused on such plans, and edges outside the
-    compiled set at creation."""
+    real transforms, zoom levels whose n1 the factor does not divide (or a
+    factor that is not positive), the adjoint and the voxel form factor are
+    refused on such plans, and edges outside the compiled set at creation."""
     import torch
     n = 40
     z, F = _spectrum(orc, n)
@@ -190,7 +190,9 @@ def test_mixed_ewald_and_refusals(ur, orc):
     cell = ur.DeviceCell.from_host(wl.cell)
     h = ur.Hist(wl.nbins)
     with pytest.raises(ur.UltimaError, match="status 2"):
-        plan.simulate(cell, wl.mask, W.Zoom(3 * n, 3), h)              # factor not a power of two
+        plan.simulate(cell, wl.mask, W.Zoom(3 * n + 1, 3), h)          # n1 not divisible by the factor
+    with pytest.raises(ur.UltimaError, match="status 1"):
+        plan.simulate(cell, wl.mask, W.Zoom(3 * n, 0), h)              # factor not positive
     plan.simulate(cell, wl.mask, wl.zoom, h)
     g = torch.zeros(wl.nbins, dtype=torch.float64, device="cuda")
     ga = torch.zeros(wl.cell.n_atoms, dtype=torch.float64, device="cuda")
@@ -279,11 +281,14 @@ def test_mixed_any_cell_edge(ur, orc, n, prec, c):
     torch.cuda.synchronize()
 
 
-@pytest.mark.parametrize("n,n1,f,prec", [(40, 160, 4, 1), (100, 800, 8, 0), (250, 1000, 4, 0)])
+@pytest.mark.parametrize("n,n1,f,prec", [(40, 160, 4, 1), (100, 800, 8, 0), (250, 1000, 4, 0),
+                                         (40, 200, 5, 1), (100, 300, 3, 0), (40, 1000, 25, 0)])
 def test_mixed_zoom_level(ur, orc, n, n1, f, prec):
     """Zoom levels on mixed-radix boxes (the paper's ED-2: its ED-1 block-summed
-    by 16 into a 250^3 box): the level's density (block sums of ED-1 over
-    f^3 voxels, centred) and its curve against the oracle (O3 then O4-O8)."""
+    by 16 into a 250^3 box; its ED-3 factor 125 = 5^3 is not a power of two,
+    here 5, 3 and 25, whose blocks are summed pencil by pencil): the level's
+    density (block sums of ED-1 over f^3 voxels, centred) and its curve
+    against the oracle (O3 then O4-O8)."""
     import torch
     wl = W.mixed_zoom(n, n1, f, prec)
     _say(f"mixed zoom level {n}^3 from {n1}^3 / {f} prec={prec}")
