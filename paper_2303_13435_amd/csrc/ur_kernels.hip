@@ -16,6 +16,15 @@
 #include "ur_geom.hpp"
 #include "ur_kernels.hpp"
 
+// The file is compiled once per part (-DUR_PART=k, k in [0, UR_NPARTS)) so
+// that the large template instantiations build in parallel: part 0 holds the
+// small kernels and the dispatchers, the others one group of transform passes
+// each.  Without UR_PART it is a single translation unit holding everything.
+#ifndef UR_PART
+#define UR_PART -1
+#endif
+#define UR_IN(k) (UR_PART < 0 || UR_PART == (k))
+
 namespace ur {
 
 // ---------------------------------------------------------------------------
@@ -86,6 +95,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double phi_cdf(double t) { return 0.5 * erfc(-t * 0.70710678118654752440); }
 
+#if UR_IN(0)
 __global__ void k_cell_profiles(int c, int n_atoms, const double* __restrict__ xyz,
                                 const double* __restrict__ sigma, double* __restrict__ prof) {
   long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -122,6 +132,7 @@ __global__ void k_cell_sum(int c, int n_atoms, const double* __restrict__ amp,
   cell[v] = acc;
 }
 
+#endif
 template <typename T>
 __global__ void k_cell_tables(int c, int f, const double* __restrict__ cell, T* __restrict__ cellT,
                               double* __restrict__ pre, T* __restrict__ cb, int cbn) {
@@ -1091,6 +1102,7 @@ k_pass_x(XArgs a) {
   }
 }
 
+#if UR_IN(0)
 // voxel count per bin (geometry only): one thread per (ky, kz) column walks
 // |h| upward; integer LDS histogram, integer global totals
 __global__ void __launch_bounds__(256) k_bin_counts(int n, int nkz, int r2c, int nbins, const int* __restrict__ Ug,
@@ -1131,6 +1143,7 @@ __global__ void k_counts_to_double(int nbins, const unsigned long long* __restri
   if (i < nbins) out[i] = (double)c[i];
 }
 
+#endif
 // ---------------------------------------------------------------------------
 // finalize: fixed-order compensated sums over the block partials
 // ---------------------------------------------------------------------------
@@ -1144,6 +1157,7 @@ struct Kahan {
   __device__ __forceinline__ double val() const { return s + c; }
 };
 
+#if UR_IN(0)
 // block b < nvb: 8 values x 32 phases; the last block reduces the z-pass
 // moments and copies the (geometric) bin counts
 __global__ void __launch_bounds__(256) k_finalize(FinArgs a) {
@@ -1230,6 +1244,7 @@ __global__ void __launch_bounds__(256) k_moments(const double* __restrict__ mom,
   }
 }
 
+#endif
 // ---------------------------------------------------------------------------
 // merge of zoom levels, one thread per bin
 // ---------------------------------------------------------------------------
@@ -1240,6 +1255,7 @@ __device__ __forceinline__ double sem_from_sums(double cnt, double s, double s2)
   return sqrt(var / cnt);
 }
 
+#if UR_IN(0)
 __global__ void k_merge(MergeArgs a) {
   int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= a.nbins) return;
@@ -1311,6 +1327,7 @@ __global__ void __launch_bounds__(256) k_ensemble(int nboxes, int nbins, const d
   out_sem[b] = sqrt(v.val());              // NaN for one-voxel bins
 }
 
+#endif
 // ---------------------------------------------------------------------------
 // adjoint column pass along x: FFT_x, multiply by G(|q|) * gscale, IFFT_x
 // ---------------------------------------------------------------------------
@@ -1689,6 +1706,7 @@ __global__ void __launch_bounds__(256) k_fold(FoldArgs a, int n) {
   }
 }
 
+#if UR_IN(0)
 __global__ void k_fold_reduce(int c3, const double* __restrict__ part, int nblk, double* __restrict__ gcell) {
   int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= c3) return;
@@ -1720,6 +1738,7 @@ __global__ void k_zero(double* p, size_t n) {
   if (i < n) p[i] = 0.0;
 }
 
+#endif
 // ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
@@ -1749,6 +1768,7 @@ template <typename T, int N> constexpr bool inv_fits() {      // inverse y / z p
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 static unsigned nblk_of(long long total, int threads) { return (unsigned)((total + threads - 1) / threads); }
 
+#if UR_IN(0)
 hipError_t launch_cell_profiles(int c, int n_atoms, const double* xyz, const double* sigma, double* prof, hipStream_t s) {
   long long total = (long long)n_atoms * 3 * c;
   if (total == 0) return hipSuccess;
@@ -1777,37 +1797,46 @@ hipError_t launch_cell_tables(int prec, int c, int f, const double* cell, void* 
   }
   return hipGetLastError();
 }
+#endif
 
-template <typename T, int N>
+// SAMP: the rotated-lattice modes of one sampler (1 trilinear, 3 cubic;
+// instantiated in their own parts), or 0 for the aligned modes
+template <typename T, int N, int SAMP>
 static hipError_t pass_z_t(int mode, const ZArgs& a, int nblocks, hipStream_t s) {
   if (nblocks <= 0) return hipSuccess;
-  if constexpr (!z_fits<T, N, true>()) {
-    if (mode == Z_GEN_C2C || mode == Z_LOAD_C2C || mode == Z_ZOOM_C2C) return hipErrorNotSupported;
+  const dim3 grid(nblocks), real_blk(ZCfg<T, N, false>::threads);
+#define UR_ZK(M) hipLaunchKernelGGL((k_pass_z<T, N, M>), grid, real_blk, 0, s, a)
+  if constexpr (SAMP == 1) {
     switch (mode) {
-      case Z_GEN_R2C: hipLaunchKernelGGL((k_pass_z<T, N, Z_GEN_R2C>), dim3(nblocks), dim3(ZCfg<T, N, false>::threads), 0, s, a); break;
-      case Z_ROT_R2C: hipLaunchKernelGGL((k_pass_z<T, N, Z_ROT_R2C>), dim3(nblocks), dim3(ZCfg<T, N, false>::threads), 0, s, a); break;
-      case Z_ROT3_R2C: hipLaunchKernelGGL((k_pass_z<T, N, Z_ROT3_R2C>), dim3(nblocks), dim3(ZCfg<T, N, false>::threads), 0, s, a); break;
-      case Z_ROTG_R2C: hipLaunchKernelGGL((k_pass_z<T, N, Z_ROTG_R2C>), dim3(nblocks), dim3(ZCfg<T, N, false>::threads), 0, s, a); break;
-      case Z_ROT3G_R2C: hipLaunchKernelGGL((k_pass_z<T, N, Z_ROT3G_R2C>), dim3(nblocks), dim3(ZCfg<T, N, false>::threads), 0, s, a); break;
-      case Z_LOAD_R2C: hipLaunchKernelGGL((k_pass_z<T, N, Z_LOAD_R2C>), dim3(nblocks), dim3(ZCfg<T, N, false>::threads), 0, s, a); break;
-      case Z_ZOOM_R2C: hipLaunchKernelGGL((k_pass_z<T, N, Z_ZOOM_R2C>), dim3(nblocks), dim3(ZCfg<T, N, false>::threads), 0, s, a); break;
+      case Z_ROT_R2C: UR_ZK(Z_ROT_R2C); break;
+      case Z_ROTG_R2C: UR_ZK(Z_ROTG_R2C); break;
       default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
-  } else
-  switch (mode) {
-    case Z_GEN_R2C: hipLaunchKernelGGL((k_pass_z<T, N, Z_GEN_R2C>), dim3(nblocks), dim3(ZCfg<T, N, false>::threads), 0, s, a); break;
-    case Z_ROT_R2C: hipLaunchKernelGGL((k_pass_z<T, N, Z_ROT_R2C>), dim3(nblocks), dim3(ZCfg<T, N, false>::threads), 0, s, a); break;
-    case Z_ROT3_R2C: hipLaunchKernelGGL((k_pass_z<T, N, Z_ROT3_R2C>), dim3(nblocks), dim3(ZCfg<T, N, false>::threads), 0, s, a); break;
-    case Z_ROTG_R2C: hipLaunchKernelGGL((k_pass_z<T, N, Z_ROTG_R2C>), dim3(nblocks), dim3(ZCfg<T, N, false>::threads), 0, s, a); break;
-    case Z_ROT3G_R2C: hipLaunchKernelGGL((k_pass_z<T, N, Z_ROT3G_R2C>), dim3(nblocks), dim3(ZCfg<T, N, false>::threads), 0, s, a); break;
-    case Z_LOAD_R2C: hipLaunchKernelGGL((k_pass_z<T, N, Z_LOAD_R2C>), dim3(nblocks), dim3(ZCfg<T, N, false>::threads), 0, s, a); break;
-    case Z_GEN_C2C: hipLaunchKernelGGL((k_pass_z<T, N, Z_GEN_C2C>), dim3(nblocks), dim3(ZCfg<T, N, true>::threads), 0, s, a); break;
-    case Z_LOAD_C2C: hipLaunchKernelGGL((k_pass_z<T, N, Z_LOAD_C2C>), dim3(nblocks), dim3(ZCfg<T, N, true>::threads), 0, s, a); break;
-    case Z_ZOOM_R2C: hipLaunchKernelGGL((k_pass_z<T, N, Z_ZOOM_R2C>), dim3(nblocks), dim3(ZCfg<T, N, false>::threads), 0, s, a); break;
-    case Z_ZOOM_C2C: hipLaunchKernelGGL((k_pass_z<T, N, Z_ZOOM_C2C>), dim3(nblocks), dim3(ZCfg<T, N, true>::threads), 0, s, a); break;
-    default: return hipErrorInvalidValue;
+  } else if constexpr (SAMP == 3) {
+    switch (mode) {
+      case Z_ROT3_R2C: UR_ZK(Z_ROT3_R2C); break;
+      case Z_ROT3G_R2C: UR_ZK(Z_ROT3G_R2C); break;
+      default: return hipErrorInvalidValue;
+    }
+  } else {
+    switch (mode) {
+      case Z_GEN_R2C: UR_ZK(Z_GEN_R2C); break;
+      case Z_LOAD_R2C: UR_ZK(Z_LOAD_R2C); break;
+      case Z_ZOOM_R2C: UR_ZK(Z_ZOOM_R2C); break;
+      case Z_GEN_C2C: case Z_LOAD_C2C: case Z_ZOOM_C2C:
+        if constexpr (!z_fits<T, N, true>()) {
+          return hipErrorNotSupported;
+        } else {
+          const dim3 cblk(ZCfg<T, N, true>::threads);
+          if (mode == Z_GEN_C2C) hipLaunchKernelGGL((k_pass_z<T, N, Z_GEN_C2C>), grid, cblk, 0, s, a);
+          else if (mode == Z_LOAD_C2C) hipLaunchKernelGGL((k_pass_z<T, N, Z_LOAD_C2C>), grid, cblk, 0, s, a);
+          else hipLaunchKernelGGL((k_pass_z<T, N, Z_ZOOM_C2C>), grid, cblk, 0, s, a);
+        }
+        break;
+      default: return hipErrorInvalidValue;
+    }
   }
+#undef UR_ZK
   return hipGetLastError();
 }
 
@@ -1816,17 +1845,62 @@ static hipError_t pass_z_t(int mode, const ZArgs& a, int nblocks, hipStream_t s)
 constexpr int kBig = kMaxOutOfCore;
 static_assert(kMaxInCore == 2048, "the in-HBM dispatch below instantiates sizes up to 2048");
 
-hipError_t launch_pass_z(int prec, int n, int mode, const ZArgs& a, int nblocks, hipStream_t s) {
+template <typename T, int SAMP>
+static hipError_t pass_z_any(int n, int mode, const ZArgs& a, int nblocks, hipStream_t s) {
   if (n == kBig) {
-    if (prec != 0 || mode != Z_LOAD_R2C) return hipErrorNotSupported;
-    if (nblocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_pass_z<float, kBig, Z_LOAD_R2C>), dim3(nblocks), dim3(ZCfg<float, kBig, false>::threads), 0, s, a);
-    return hipGetLastError();
+    if constexpr (sizeof(T) != 4 || SAMP != 0) {
+      return hipErrorNotSupported;
+    } else {
+      if (mode != Z_LOAD_R2C) return hipErrorNotSupported;
+      if (nblocks <= 0) return hipSuccess;
+      hipLaunchKernelGGL((k_pass_z<float, kBig, Z_LOAD_R2C>), dim3(nblocks), dim3(ZCfg<float, kBig, false>::threads), 0, s, a);
+      return hipGetLastError();
+    }
   }
-#define UR_Z(NN) return prec == 0 ? pass_z_t<float, NN>(mode, a, nblocks, s) : pass_z_t<double, NN>(mode, a, nblocks, s)
+#define UR_Z(NN) return pass_z_t<T, NN, SAMP>(mode, a, nblocks, s)
   UR_DISPATCH_N(n, UR_Z);
 #undef UR_Z
 }
+
+// per-precision and per-sampler entry points, each in its own part
+hipError_t launch_pass_z_f32(int n, int mode, const ZArgs& a, int nblocks, hipStream_t s);
+hipError_t launch_pass_z_f64(int n, int mode, const ZArgs& a, int nblocks, hipStream_t s);
+hipError_t launch_pass_z_rot_f32(int n, int mode, const ZArgs& a, int nblocks, hipStream_t s);
+hipError_t launch_pass_z_rot_f64(int n, int mode, const ZArgs& a, int nblocks, hipStream_t s);
+hipError_t launch_pass_z_rot3_f32(int n, int mode, const ZArgs& a, int nblocks, hipStream_t s);
+hipError_t launch_pass_z_rot3_f64(int n, int mode, const ZArgs& a, int nblocks, hipStream_t s);
+#define UR_ZENTRY(PART, NAME, T, SAMP)                                                   \
+  hipError_t NAME(int n, int mode, const ZArgs& a, int nblocks, hipStream_t s) { \
+    return pass_z_any<T, SAMP>(n, mode, a, nblocks, s);                          \
+  }
+#if UR_IN(1)
+UR_ZENTRY(1, launch_pass_z_f32, float, 0)
+#endif
+#if UR_IN(2)
+UR_ZENTRY(2, launch_pass_z_f64, double, 0)
+#endif
+#if UR_IN(7)
+UR_ZENTRY(7, launch_pass_z_rot_f32, float, 1)
+#endif
+#if UR_IN(8)
+UR_ZENTRY(8, launch_pass_z_rot_f64, double, 1)
+#endif
+#if UR_IN(9)
+UR_ZENTRY(9, launch_pass_z_rot3_f32, float, 3)
+#endif
+#if UR_IN(10)
+UR_ZENTRY(10, launch_pass_z_rot3_f64, double, 3)
+#endif
+#undef UR_ZENTRY
+#if UR_IN(0)
+hipError_t launch_pass_z(int prec, int n, int mode, const ZArgs& a, int nblocks, hipStream_t s) {
+  if (mode == Z_ROT_R2C || mode == Z_ROTG_R2C)
+    return prec == 0 ? launch_pass_z_rot_f32(n, mode, a, nblocks, s) : launch_pass_z_rot_f64(n, mode, a, nblocks, s);
+  if (mode == Z_ROT3_R2C || mode == Z_ROT3G_R2C)
+    return prec == 0 ? launch_pass_z_rot3_f32(n, mode, a, nblocks, s) : launch_pass_z_rot3_f64(n, mode, a, nblocks, s);
+  return prec == 0 ? launch_pass_z_f32(n, mode, a, nblocks, s) : launch_pass_z_f64(n, mode, a, nblocks, s);
+}
+#endif
 
 template <typename T, int N>
 static hipError_t pass_y_t(const YArgs& a, hipStream_t s) {
@@ -1836,12 +1910,14 @@ static hipError_t pass_y_t(const YArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+#if UR_IN(5)
 hipError_t launch_pass_y(int prec, int n, const YArgs& a, hipStream_t s) {
   if (n == kBig) return prec == 0 ? pass_y_t<float, kBig>(a, s) : hipErrorNotSupported;
 #define UR_Y(NN) return prec == 0 ? pass_y_t<float, NN>(a, s) : pass_y_t<double, NN>(a, s)
   UR_DISPATCH_N(n, UR_Y);
 #undef UR_Y
 }
+#endif
 
 static size_t x_shm(int mode, int nbins, int n, size_t ts = 8) {
   if (mode == X_FFT_BIN_SINC || mode == X_BIN_ONLY_SINC)
@@ -1860,10 +1936,7 @@ static int x_resident_t(int mode, int dir, int nbins) {
   if (mode == X_FFT_BIN) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pass_x<T, N, X_FFT_BIN, -1>, XCfg<N>::threads, shm);
   else if (mode == X_FFT_BIN_SINC || mode == X_BIN_ONLY_SINC) return x_resident_t<T, N>(mode == X_FFT_BIN_SINC ? X_FFT_BIN : X_BIN_ONLY, dir, nbins);
   else if constexpr (N == kBig) return 1;
-  else if (mode == X_ADJ) {
-    if constexpr (inv_fits<T, N>()) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pass_x_adj<T, N>, XCfg<N>::threads, shm);
-    else return 1;
-  }
+  else if (mode == X_ADJ) return 1;                  // x_resident_adj_t
   else if (mode == X_BIN_ONLY) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pass_x<T, N, X_BIN_ONLY, -1>, XCfg<N>::threads, shm);
   else if (dir < 0) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pass_x<T, N, X_FFT_STORE, -1>, XCfg<N>::threads, shm);
   else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pass_x<T, N, X_FFT_STORE, +1>, XCfg<N>::threads, shm);
@@ -1871,9 +1944,28 @@ static int x_resident_t(int mode, int dir, int nbins) {
   return nb > 0 ? nb : 1;
 }
 
-int x_resident(int prec, int n, int mode, int dir, int nbins) {
-  if (n == kBig) return prec == 0 && mode == X_FFT_BIN ? x_resident_t<float, kBig>(mode, dir, nbins) : 1;
-#define UR_XR(NN) return prec == 0 ? x_resident_t<float, NN>(mode, dir, nbins) : x_resident_t<double, NN>(mode, dir, nbins)
+template <typename T, int N>
+static int x_resident_adj_t(int nbins) {
+  if constexpr (!inv_fits<T, N>()) {
+    return 1;
+  } else {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pass_x_adj<T, N>, XCfg<N>::threads, x_shm(X_ADJ, nbins, N)) !=
+        hipSuccess) {
+      (void)hipGetLastError();
+      return 1;
+    }
+    return nb > 0 ? nb : 1;
+  }
+}
+
+template <typename T>
+static int x_resident_any(int n, int mode, int dir, int nbins) {
+  if (n == kBig) {
+    if constexpr (sizeof(T) == 4) return mode == X_FFT_BIN ? x_resident_t<float, kBig>(mode, dir, nbins) : 1;
+    else return 1;
+  }
+#define UR_XR(NN) return x_resident_t<T, NN>(mode, dir, nbins)
   switch (n) {
     case 16: UR_XR(16); case 32: UR_XR(32); case 64: UR_XR(64); case 128: UR_XR(128);
     case 256: UR_XR(256); case 512: UR_XR(512); case 1024: UR_XR(1024); case 2048: UR_XR(2048);
@@ -1882,6 +1974,39 @@ int x_resident(int prec, int n, int mode, int dir, int nbins) {
 #undef UR_XR
 }
 
+template <typename T>
+static int x_resident_adj_any(int n, int nbins) {
+#define UR_XR(NN) return x_resident_adj_t<T, NN>(nbins)
+  switch (n) {
+    case 16: UR_XR(16); case 32: UR_XR(32); case 64: UR_XR(64); case 128: UR_XR(128);
+    case 256: UR_XR(256); case 512: UR_XR(512); case 1024: UR_XR(1024); case 2048: UR_XR(2048);
+    default: return 1;
+  }
+#undef UR_XR
+}
+
+int x_resident_f32(int n, int mode, int dir, int nbins);
+int x_resident_f64(int n, int mode, int dir, int nbins);
+int x_resident_adj(int prec, int n, int nbins);
+#if UR_IN(3)
+int x_resident_f32(int n, int mode, int dir, int nbins) { return x_resident_any<float>(n, mode, dir, nbins); }
+#endif
+#if UR_IN(4)
+int x_resident_f64(int n, int mode, int dir, int nbins) { return x_resident_any<double>(n, mode, dir, nbins); }
+#endif
+#if UR_IN(6)
+int x_resident_adj(int prec, int n, int nbins) {
+  return prec == 0 ? x_resident_adj_any<float>(n, nbins) : x_resident_adj_any<double>(n, nbins);
+}
+#endif
+#if UR_IN(0)
+int x_resident(int prec, int n, int mode, int dir, int nbins) {
+  if (mode == X_ADJ) return x_resident_adj(prec, n, nbins);
+  return prec == 0 ? x_resident_f32(n, mode, dir, nbins) : x_resident_f64(n, mode, dir, nbins);
+}
+#endif
+
+#if UR_IN(0)
 hipError_t launch_bin_counts(int n, int nkz, int r2c, int nbins, const int* U, unsigned long long* tmp, double* out, hipStream_t s) {
   long long ncols = (long long)nkz * n;
   size_t shm = (size_t)nbins * sizeof(unsigned long long) + ((size_t)nbins + 2) * sizeof(int);
@@ -1893,6 +2018,7 @@ hipError_t launch_bin_counts(int n, int nkz, int r2c, int nbins, const int* U, u
   hipLaunchKernelGGL(k_counts_to_double, dim3((nbins + 255) / 256), dim3(256), 0, s, nbins, tmp, out);
   return hipGetLastError();
 }
+#endif
 
 template <typename T, int N>
 static hipError_t pass_x_t(int mode, int dir, const XArgs& a, int nblocks, hipStream_t s) {
@@ -1913,16 +2039,40 @@ static hipError_t pass_x_t(int mode, int dir, const XArgs& a, int nblocks, hipSt
   return hipGetLastError();
 }
 
-hipError_t launch_pass_x(int prec, int n, int mode, int dir, const XArgs& a, int nblocks, hipStream_t s) {
+template <typename T>
+static hipError_t pass_x_any(int n, int mode, int dir, const XArgs& a, int nblocks, hipStream_t s) {
   if (n == kBig) {
-    if (prec != 0 || mode != X_FFT_BIN) return hipErrorNotSupported;
-    return pass_x_t<float, kBig>(mode, dir, a, nblocks, s);
+    if constexpr (sizeof(T) != 4) {
+      return hipErrorNotSupported;
+    } else {
+      if (mode != X_FFT_BIN) return hipErrorNotSupported;
+      return pass_x_t<float, kBig>(mode, dir, a, nblocks, s);
+    }
   }
-#define UR_X(NN) return prec == 0 ? pass_x_t<float, NN>(mode, dir, a, nblocks, s) : pass_x_t<double, NN>(mode, dir, a, nblocks, s)
+#define UR_X(NN) return pass_x_t<T, NN>(mode, dir, a, nblocks, s)
   UR_DISPATCH_N(n, UR_X);
 #undef UR_X
 }
 
+hipError_t launch_pass_x_f32(int n, int mode, int dir, const XArgs& a, int nblocks, hipStream_t s);
+hipError_t launch_pass_x_f64(int n, int mode, int dir, const XArgs& a, int nblocks, hipStream_t s);
+#if UR_IN(3)
+hipError_t launch_pass_x_f32(int n, int mode, int dir, const XArgs& a, int nblocks, hipStream_t s) {
+  return pass_x_any<float>(n, mode, dir, a, nblocks, s);
+}
+#endif
+#if UR_IN(4)
+hipError_t launch_pass_x_f64(int n, int mode, int dir, const XArgs& a, int nblocks, hipStream_t s) {
+  return pass_x_any<double>(n, mode, dir, a, nblocks, s);
+}
+#endif
+#if UR_IN(0)
+hipError_t launch_pass_x(int prec, int n, int mode, int dir, const XArgs& a, int nblocks, hipStream_t s) {
+  return prec == 0 ? launch_pass_x_f32(n, mode, dir, a, nblocks, s) : launch_pass_x_f64(n, mode, dir, a, nblocks, s);
+}
+#endif
+
+#if UR_IN(0)
 hipError_t launch_finalize(const FinArgs& a, hipStream_t s) {
   int nv = 2 * a.nbins + 1;
   int nvb = (nv + 7) / 8;
@@ -1992,10 +2142,12 @@ hipError_t launch_ewald(int prec, const EwaldArgs& a, hipStream_t s) {
   else hipLaunchKernelGGL(k_ewald<double>, dim3(nblk_of(np, 256)), dim3(256), 0, s, a);
   return hipGetLastError();
 }
+#endif
 
 // Window w: the populated bins whose centres lie in [lo, hi]; a first scan
 // finds the first and last of them (the baseline's ends), a second adds
 // (mean - baseline) * width and mean * width in bin order.
+#if UR_IN(0)
 __global__ void k_peaks(PeakArgs a) {
   const int w = blockIdx.x * blockDim.x + threadIdx.x;
   if (w >= a.nwin) return;
@@ -2042,6 +2194,7 @@ hipError_t launch_merge(const MergeArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+#endif
 template <typename T, int N>
 static hipError_t pass_x_adj_t(const XAdjArgs& a, int nblocks, hipStream_t s) {
   if (nblocks <= 0) return hipSuccess;
@@ -2052,11 +2205,13 @@ static hipError_t pass_x_adj_t(const XAdjArgs& a, int nblocks, hipStream_t s) {
   }
 }
 
+#if UR_IN(6)
 hipError_t launch_pass_x_adj(int prec, int n, const XAdjArgs& a, int nblocks, hipStream_t s) {
 #define UR_XA(NN) return prec == 0 ? pass_x_adj_t<float, NN>(a, nblocks, s) : pass_x_adj_t<double, NN>(a, nblocks, s)
   UR_DISPATCH_N(n, UR_XA);
 #undef UR_XA
 }
+#endif
 
 template <typename T, int N>
 static hipError_t pass_y_inv_t(const YInvArgs& a, hipStream_t s) {
@@ -2068,11 +2223,13 @@ static hipError_t pass_y_inv_t(const YInvArgs& a, hipStream_t s) {
   }
 }
 
+#if UR_IN(5)
 hipError_t launch_pass_y_inv(int prec, int n, const YInvArgs& a, hipStream_t s) {
 #define UR_YI(NN) return prec == 0 ? pass_y_inv_t<float, NN>(a, s) : pass_y_inv_t<double, NN>(a, s)
   UR_DISPATCH_N(n, UR_YI);
 #undef UR_YI
 }
+#endif
 
 template <typename T, int N>
 static hipError_t pass_z_inv_t(int c2c, const ZInvArgs& a, hipStream_t s) {
@@ -2084,12 +2241,15 @@ static hipError_t pass_z_inv_t(int c2c, const ZInvArgs& a, hipStream_t s) {
   }
 }
 
+#if UR_IN(5)
 hipError_t launch_pass_z_inv(int prec, int n, int c2c, const ZInvArgs& a, hipStream_t s) {
 #define UR_ZI(NN) return prec == 0 ? pass_z_inv_t<float, NN>(c2c, a, s) : pass_z_inv_t<double, NN>(c2c, a, s)
   UR_DISPATCH_N(n, UR_ZI);
 #undef UR_ZI
 }
+#endif
 
+#if UR_IN(0)
 hipError_t launch_fold(int prec, int n, const FoldArgs& a, int nblocks, hipStream_t s) {
   const int c3 = a.L.c * a.L.c * a.L.c;
   const bool lds = a.L.c <= 16;
@@ -2103,6 +2263,7 @@ hipError_t launch_fold(int prec, int n, const FoldArgs& a, int nblocks, hipStrea
   }
   return hipGetLastError();
 }
+#endif
 
 template <typename T, int N>
 static hipError_t pass_z_fold_t(const ZFoldArgs& a, int nblocks, hipStream_t s) {
@@ -2114,12 +2275,15 @@ static hipError_t pass_z_fold_t(const ZFoldArgs& a, int nblocks, hipStream_t s) 
   }
 }
 
+#if UR_IN(6)
 hipError_t launch_pass_z_fold(int prec, int n, const ZFoldArgs& a, int nblocks, hipStream_t s) {
 #define UR_ZF(NN) return prec == 0 ? pass_z_fold_t<float, NN>(a, nblocks, s) : pass_z_fold_t<double, NN>(a, nblocks, s)
   UR_DISPATCH_N(n, UR_ZF);
 #undef UR_ZF
 }
+#endif
 
+#if UR_IN(0)
 // gcell[(ci c + cj) c + k] = sum over the blocks of class ci (b = r c + ci)
 // of their slice partial [cj][k], in a fixed order
 __global__ void k_fold_reduce_classes(int c, const double* __restrict__ part, int nblk, double* __restrict__ gcell) {
@@ -2192,6 +2356,7 @@ hipError_t launch_bspline_cell(int c, double* cell, hipStream_t s) {
   return hipSuccess;
 }
 
+#endif
 // A level's density as complex values (rho, 0) for the mixed-radix passes
 // (zoom levels there: block sums of ED-1), one block per (x, y) pencil, with
 // the pencil's [sum rho, sum rho^2] (fixed-order block sum) in mom.
@@ -2220,6 +2385,7 @@ __global__ void __launch_bounds__(256) k_level_complex(ZArgs a, int n, cx<T>* __
   }
 }
 
+#if UR_IN(0)
 hipError_t launch_level_complex(int prec, int n, const ZArgs& a, void* S, double* mom, hipStream_t s) {
   const unsigned nn = (unsigned)((long long)n * n);
   if (prec == 0) hipLaunchKernelGGL(k_level_complex<float>, dim3(nn), dim3(256), 0, s, a, n, (cx<float>*)S, mom);
@@ -2297,5 +2463,7 @@ int x_groups(int n) {
   }
 }
 #undef UR_XG
+
+#endif
 
 }  // namespace ur

@@ -163,6 +163,40 @@ def test_mask_voxel_counts_are_lattice_point_counts(oracle_lib):
     assert oracle_lib.ed1(n, ones, W.Mask(W.MASK_SPHERE, -1)).sum() == 0
 
 
+@pytest.mark.parametrize("R", [3.0, 5.3, 9.999999, 11.3, 12.0, 17.9, 25.0, 28.62])
+def test_integer_mask_parameters_match_real_shapes(oracle_lib, R):
+    """The masks cross the boundary as integers (inside test on the integer
+    offset d of a voxel centre); the workload constructors derive them from
+    a real radius R.  The integer masks must contain exactly the voxel
+    centres of the real shapes: the ball |d| <= R, and the truncated
+    octahedron inscribed in it, built here independently as the convex hull
+    of its 24 vertices (permutations of (0, +-1, +-2) R / sqrt 5, all at
+    distance R from the centre; square faces normal to the axes)."""
+    from itertools import permutations
+    from scipy.spatial import ConvexHull
+    n = 64
+    ones = np.ones((4, 4, 4))
+    r = int(math.ceil(R)) + 1
+    g = np.arange(-r, r + 1, dtype=np.float64)
+    d = np.stack(np.meshgrid(g, g, g, indexing="ij"), axis=-1).reshape(-1, 3)
+    # ball: voxel centres within distance R (real arithmetic, tie within 1e-9)
+    ball = int(np.count_nonzero(np.sqrt(np.sum(d * d, axis=1)) <= R + 1e-9))
+    assert oracle_lib.ed1(n, ones, W.sphere(R)).sum() == ball
+    # truncated octahedron as a hull of vertices, not of the face planes
+    base = set()
+    for p in permutations((0.0, 1.0, 2.0)):
+        for sx in (-1, 1):
+            for sy in (-1, 1):
+                for sz in (-1, 1):
+                    base.add((sx * p[0], sy * p[1], sz * p[2]))
+    verts = np.array(sorted(base)) * (R / math.sqrt(5.0))
+    assert len(verts) == 24 and np.allclose(np.linalg.norm(verts, axis=1), R)
+    hull = ConvexHull(verts)
+    side = d @ hull.equations[:, :3].T + hull.equations[:, 3]
+    inside = int(np.count_nonzero(np.all(side <= 1e-9, axis=1)))
+    assert oracle_lib.ed1(n, ones, W.trunc_oct(R)).sum() == inside
+
+
 def test_cube_mask_dirichlet_closed_form(oracle_lib):
     """Uniform cube of half-width h: |F|^2 = prod_axes D(u)^2 with the Dirichlet
     kernel D(u) = sin(pi u (2h+1)/n) / (n sin(pi u / n)), D(0) = (2h+1)/n."""
@@ -248,14 +282,31 @@ def test_bin_statistics_of_constructed_spectra(oracle_lib):
     r = oracle_lib.bin_spectrum(np.sqrt(n2).astype(complex), 1.0, edges)
     U = oracle_lib.thresholds(n, 1.0, edges)
     r3 = r3_table()
+    checked = 0
     for b in range(16):
         if U[b + 1] > len(r3):
             break
         m = np.arange(U[b], U[b + 1])
         w = r3[m]
-        if w.sum() > 0:
-            assert abs(r["mean"][b] - (m * w).sum() / w.sum()) < 1e-12
-            assert r["count"][b] == w.sum()
+        c = w.sum()
+        if c > 0:
+            mean = (m * w).sum() / c
+            assert abs(r["mean"][b] - mean) < 1e-12
+            assert r["count"][b] == c
+            if c == 1:
+                assert np.isnan(r["sem"][b])              # one voxel: no spread estimate
+                continue
+            # SEM from the shell table: the population variance of n2 over the
+            # bin, sum m^2 r3 / sum r3 - mean^2, turned into the sample
+            # variance (x c/(c-1)) and divided by the count
+            var_pop = (m * m * w).sum() / c - mean * mean
+            sem = math.sqrt(max(var_pop, 0.0) * c / (c - 1.0) / c)
+            if np.count_nonzero(w) == 1:                  # one shell: every value equal
+                assert r["sem"][b] <= 1e-12 * mean, (b, r["sem"][b])
+                continue
+            assert abs(r["sem"][b] - sem) <= 1e-12 * sem, (b, r["sem"][b], sem)
+            checked += 1
+    assert checked >= 8 and r["count"][0] == 1
 
 
 def test_circular_shift_leaves_bins_unchanged(oracle_lib):
