@@ -67,19 +67,49 @@ def time_steps(fn, steps, warmup, torch):
     return e0.elapsed_time(e1) / steps, wall
 
 
-def cpu_baseline(budget_s: float = 30.0):
-    """FP64 oracle, as it stands, on C2 (the headline recipe at half scale,
-    512^3): full path density -> eq. 1 -> binning.  Reported as voxels/s."""
+def cpu_baseline(wl, got32=None, got64=None):
+    """The FP64 oracle, as it stands, on the benchmarked box itself (density
+    -> eq. 1 -> binning of the whole 1024^3 box; FFT lines on every OpenMP
+    thread, binning on one), reported as voxels/s; the same path on C4
+    (256^3) with one thread; and, from the oracle's result, the accuracy of
+    the GPU curves of the same box (FP32 and FP64): max relative error over
+    the populated bins, Parseval and F(0) errors."""
+    import numpy as np
     import oracle
     import workloads as W
     oracle.lib()
-    wl = W.c2()
+    nthr = oracle.num_threads()
     t0 = time.perf_counter()
-    oracle.simulate(wl)
+    ref = oracle.simulate(wl)
     dt = time.perf_counter() - t0
-    return {"value": wl.n ** 3 / dt, "unit": "voxels/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"C2 box 512^3 (same cell recipe, sphere R=200, 512 log bins), whole oracle path "
-                      f"in {dt:.1f} s; FFT lines on {oracle.num_threads()} OpenMP threads, binning on 1",
+    note(f"oracle {wl.name}: {dt:.1f} s on {nthr} threads")
+    c4 = W.c4()
+    oracle.set_num_threads(1)
+    try:
+        t1 = time.perf_counter()
+        oracle.simulate(c4)
+        dt1 = time.perf_counter() - t1
+    finally:
+        oracle.set_num_threads(nthr)
+    note(f"oracle C4 on 1 thread: {dt1:.1f} s")
+    n3 = float(wl.n) ** 3
+    acc = {}
+    for tag, got in (("f32", got32), ("f64", got64)):
+        if got is None:
+            continue
+        pop = ref["count"] > 0
+        rel = np.abs(got["mean"][pop] - ref["mean"][pop]) / np.abs(ref["mean"][pop])
+        acc[tag] = {"counts_equal": bool(np.array_equal(got["count"], ref["count"])),
+                    "max_rel_err": float(rel.max()), "median_rel_err": float(np.median(rel)),
+                    "bins_above_1e-5": int(np.sum(rel > 1e-5)), "bins": int(pop.sum()),
+                    "parseval_rel_err": float(abs(got["totals"][0] - ref["rho_sumsq"] / n3) / (ref["rho_sumsq"] / n3)),
+                    "f0_rel_err": float(abs(got["totals"][1] - ref["rho_sum"] / n3) / abs(ref["rho_sum"] / n3))}
+    return {"value": wl.n ** 3 / dt, "unit": "voxels/s", "cores": nthr, "kind": "oracle",
+            "sample": f"the whole {wl.name} box ({wl.n}^3, 512 log bins): density, eq. 1 by recursive radix-2 "
+                      f"lines on {nthr} OpenMP threads, binning on one thread; {dt:.1f} s",
+            "one_thread": {"workload": "C4 256^3 whole path", "s": round(dt1, 2),
+                           "voxels_per_s": c4.n ** 3 / dt1},
+            "gpu_accuracy_vs_oracle": acc,
             "host": host_info()}
 
 
@@ -284,6 +314,41 @@ def mixed_radix(ur, W, torch, steps):
     return out
 
 
+def c4_fwd_adjoint(ur, W, torch, steps):
+    """C4 (256^3 FP32, 40 atoms, sphere R = 100, 256 log bins): one forward
+    call plus the adjoint to both the voxel density and the 40 amplitudes
+    (recomputing the forward passes), and forward plus the amplitude
+    adjoint from the held y-pass output; ms per step."""
+    import numpy as np
+    wl = W.c4()
+    plan = ur.Plan(wl.n, wl.voxel, ur.UR_F32)
+    plan.set_bins(wl.edges)
+    cell = ur.DeviceCell.from_host(wl.cell)
+    h = ur.Hist(wl.nbins)
+    plan.simulate(cell, wl.mask, wl.zoom, h)
+    torch.cuda.synchronize()
+    d = h.numpy()
+    g_bin = torch.as_tensor(np.where(d["count"] > 0, 1.0, 0.0), device="cuda")
+    grho = torch.empty((wl.n,) * 3, dtype=torch.float32, device="cuda")
+    gamp = torch.empty(wl.cell.n_atoms, dtype=torch.float64, device="cuda")
+
+    def both():
+        plan.simulate(cell, wl.mask, wl.zoom, h)
+        plan.adjoint(h, g_bin, cell=cell, mask=wl.mask, grad_rho=grho, grad_amp=gamp)
+
+    def keep():
+        plan.simulate(cell, wl.mask, wl.zoom, h)
+        plan.adjoint_reuse(h, g_bin, cell, wl.mask, gamp)
+
+    ms_fwd, _ = time_steps(lambda: plan.simulate(cell, wl.mask, wl.zoom, h), steps, 3, torch)
+    ms_both, _ = time_steps(both, steps, 3, torch)
+    ms_keep, _ = time_steps(keep, steps, 3, torch)
+    del plan, grho
+    torch.cuda.empty_cache()
+    return {"forward_ms": round(ms_fwd, 4), "fwd_adjoint_rho_and_amp_ms": round(ms_both, 4),
+            "fwd_adjoint_amp_from_held_output_ms": round(ms_keep, 4)}
+
+
 def note(msg):
     """Progress on stderr (stdout carries only the JSON line)."""
     print(f"# {msg}", file=sys.stderr, flush=True)
@@ -399,6 +464,7 @@ def main():
     step = lambda: plan.simulate(cell, wl.mask, wl.zoom, hist)
     ms, wall = time_steps(step, args.steps, args.warmup, torch)
     value = wl.n ** 3 / (ms * 1e-3)
+    got32, got64 = hist.numpy(), None
 
     # per-pass timing (HIP events on the launch stream) and algorithmic bytes
     kernels = pass_timing(plan, step, args.steps, torch)
@@ -410,6 +476,18 @@ def main():
                 "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic}
     path_bytes = sum(kernels[k]["alg_bytes"] for k in kernels)
     path_ms = sum(kernels[k]["avg_ms"] for k in kernels)
+    # the whole path: bytes summed over the passes / kernel time summed over
+    # the passes (counter-measured bytes when every transform pass has a
+    # summary taken from the current kernel sources)
+    counted = {k: measured_traffic(k, wl.name) for k in ("pass_z", "pass_y", "pass_x")}
+    roofline_path = {"kernel_ms": round(path_ms, 4), "step_ms": round(ms, 4),
+                     "alg_bytes": path_bytes, "alg_GBps": round(path_bytes / (path_ms * 1e-3) / 1e9, 1),
+                     "alg_frac": round(path_bytes / (path_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+                     "counter_bytes": None, "counter_frac": None, "peak": PEAK_HBM_GBS, "unit": "GB/s"}
+    if all(v is not None for v in counted.values()):
+        cb = sum(counted.values()) + sum(kernels[k]["alg_bytes"] for k in kernels if k not in counted)
+        roofline_path["counter_bytes"] = cb
+        roofline_path["counter_frac"] = round(cb / (path_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)
 
     extras = {"kernels": kernels, "path_alg_bytes": path_bytes,
               "path_alg_GBps": round(path_bytes / (ms * 1e-3) / 1e9, 1),
@@ -420,6 +498,7 @@ def main():
         p64.set_bins(wl.edges)
         h64 = ur.Hist(wl.nbins)
         ms64, _ = time_steps(lambda: p64.simulate(cell, wl.mask, wl.zoom, h64), max(3, args.steps // 2), 2, torch)
+        got64 = h64.numpy()
         # the same box with its lattice rotated (trilinear periodic sampling of the cell)
         rcell = ur.DeviceCell.from_host(wl.cell.with_rot(W.rotation([1.0, 2.0, 3.0], 0.7)))
         msr, _ = time_steps(lambda: plan.simulate(rcell, wl.mask, wl.zoom, hist), max(3, args.steps // 2), 2, torch)
@@ -460,6 +539,8 @@ def main():
         ms_fk, _ = time_steps(fwd_adj_keep, max(3, args.steps // 2), 2, torch)
         extras["fwd_adjoint_keep_ms"] = round(ms_fk, 4)       # adjoint from the held y-pass output
         note("fwd_adjoint_keep_ms done")
+        extras["c4_fwd_adjoint"] = c4_fwd_adjoint(ur, W, torch, args.steps)
+        note("c4 forward + adjoint done")
         torch.cuda.synchronize()
         del fwd_adj
         # Ewald-sphere image of the same box: 1024 x 1024 pixels, 16
@@ -504,7 +585,10 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline()
+        if n != 1024:
+            note("the CPU baseline runs the 1024^3 box only")
+        else:
+            cpu = cpu_baseline(W.m1024(), got32, got64)
 
     line = {
         "metric": "voxels/s, FFT->|F|^2->Q-bin at 1024^3 FP32 (FP64 and fwd+adjoint ms in extras)",
@@ -523,6 +607,7 @@ def main():
                                f"sphere R={int(round(400 * n / 1024))}, {wl.nbins} log |Q| bins",
                    "box": wl.n, "nbins": wl.nbins, "parallelism": "single GPU"},
         "roofline": roofline,
+        "roofline_path": roofline_path,
         "cpu_baseline": cpu,
         "extras": extras,
         "wall_s": round(wall, 3),

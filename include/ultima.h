@@ -194,23 +194,35 @@ ur_status ur_rho_generate(ur_plan* plan, const ur_cell* cell, const ur_mask* mas
 
 /* 3D transform of eq. 1.  dir = -1: forward, scaled by 1/n^3; input `in`
  * real [x][y][z] (UR_R2C) or complex [x][y][z] (UR_C2C); output `out`
- * spectrum [kz][ky][kx].  dir = +1: inverse, unscaled; input spectrum, output
+ * spectrum [kz][ky][kx] (mixed-radix plans: natural order [kx][ky][kz], see
+ * ur_plan_create).  dir = +1: inverse, unscaled; input spectrum, output
  * real (UR_R2C, the half spectrum is taken as Hermitian) or complex box.
  * in and out must not overlap. */
 ur_status ur_fft3d_exec(ur_plan* plan, const void* in, void* out, int32_t dir, void* stream);
 
-/* Bin I = |F|^2 of a spectrum already in the [kz][ky][kx] layout (DEVICE). */
+/* Spherical averaging of a given spectrum (workflow step 5; section
+ * "Q-calculation and spherical averaging"): bin I = |F|^2 of a spectrum
+ * already in this plan's layout (DEVICE: [kz][ky][kx] on power-of-two plans,
+ * the natural order [kx][ky][kz] on mixed-radix plans, as ur_fft3d_exec
+ * writes it) into the plan's |Q| bins; outputs as for ur_hist. */
 ur_status ur_intensity_bin(ur_plan* plan, const void* spectrum, const ur_hist* hist, void* stream);
 
-/* Fused forward path from the unit cell: generate ED (tile + mask + zoom)
- * inside the first transform pass, transform, and bin |F|^2 inside the last
- * pass; planes, pencils and rows that lie outside the particle are skipped.
- * The cell is synthesised on the device from its atoms in the same call. */
+/* Fused forward path from the unit cell (workflow steps 1-5): generate the
+ * ED (tile + mask + zoom; section "Electron density generation") inside the
+ * first transform pass, transform it (eq. 1, axis by axis as eq. 2
+ * separates it), and bin |F|^2 into the plan's |Q| bins inside the last pass
+ * (section "Q-calculation and spherical averaging"); planes, pencils and
+ * rows that lie outside the particle are skipped (the paper's skipping of
+ * slices without density, extended to rows and pencils).  The cell is
+ * synthesised on the device from its atoms in the same call.  Outputs as for
+ * ur_hist. */
 ur_status ur_simulate(ur_plan* plan, const ur_cell* cell, const ur_mask* mask,
                       const ur_zoom* zoom, const ur_hist* hist, void* stream);
 
-/* Fused forward path from a given density (DEVICE, n^3 reals of the plan
- * precision, [x][y][z]). */
+/* Fused forward path from a given density (workflow steps 4-5: eq. 1 axis by
+ * axis as eq. 2 separates it, then the spherical averaging of section
+ * "Q-calculation and spherical averaging"): rho DEVICE, n^3 reals of the plan
+ * precision [x][y][z] (complex values on mixed-radix plans). */
 ur_status ur_simulate_rho(ur_plan* plan, const void* rho, const ur_hist* hist, void* stream);
 
 /* Out-of-core forward path (the 2D + 1D separation of eq. 2).
@@ -369,6 +381,22 @@ ur_status ur_ewald_image(ur_plan* plan, const void* spectrum, const ur_ewald* ge
 ur_status ur_peak_integrals(int32_t nbins, const double* edges, const double* mean, int32_t nwin,
                             const double* windows, double* out, void* stream);
 
+/* chi^2 misfit of a simulated curve against a target curve, and its
+ * gradient per bin, the g_bin that ur_adjoint takes (Results and Discussion:
+ * the polydispersity estimate from some 200 volume-weighted simulations is a
+ * fit of simulated to measured curves; the relative uncertainty
+ * sigma_b = rel_sigma target_b is this library's reading, the paper gives
+ * none):
+ *     chi2     = sum over bins with count_b > 0 of ((mean_b - target_b) / sigma_b)^2,
+ *     g_bin[b] = d chi2 / d mean_b = 2 (mean_b - target_b) / sigma_b^2  (0 for empty bins).
+ * mean, count (the ur_hist fields of the simulated curve), target: DEVICE,
+ * nbins doubles; out_chi2: DEVICE, 1 double; g_bin: DEVICE nbins doubles, or
+ * NULL.  The sum is compensated and taken in a fixed order (the same bits on
+ * every call).  No allocation (capturable).  UR_ERR_INVALID for nbins outside
+ * [1, 4096], rel_sigma not positive and finite, or a null pointer. */
+ur_status ur_chi2(int32_t nbins, const double* mean, const double* count, const double* target, double rel_sigma,
+                  double* out_chi2, double* g_bin, void* stream);
+
 /* Polydisperse ensemble (Results and Discussion: polydispersity described by
  * some 200 volume-weighted contributions, one simulation each).  For nboxes
  * boxes that share one bin set (one particle each, summed incoherently),
@@ -387,8 +415,21 @@ ur_status ur_ensemble(int32_t nboxes, int32_t nbins, const double* mean, const d
 /* Record the work enqueued on `stream` between begin and end into a HIP
  * graph, instantiate it, and return the executable graph (as void*); replay
  * it with ur_graph_launch and release it with ur_graph_destroy.  Every entry
- * point above except ur_plan_create / set_bins / set_workspace may be
- * recorded. */
+ * point above except ur_plan_create / set_bins / set_workspace and the
+ * out-of-core ur_simulate_host may be recorded; the plans' workspaces must
+ * already be large enough (make the same calls once eagerly first), since
+ * nothing is allocated under capture.
+ * Lifetime: a graph holds raw device pointers into the workspaces and tables
+ * of the plans whose calls it recorded.  From ur_graph_end until
+ * ur_graph_destroy of every such graph, a plan refuses (UR_ERR_STATE, before
+ * anything is freed) every call that would reallocate or rewrite them:
+ * ur_plan_set_bins, ur_plan_set_workspace with another pointer, switching
+ * ur_plan_set_voxel_form, and calls needing a larger workspace or cell
+ * scratch (more bins, larger cells or more atoms, a larger out-of-core
+ * range).  A plan recorded under a capture that ur_graph_begin did not start
+ * stays bound for its whole life.  Destroying a plan invalidates the graphs
+ * recorded from it (replaying them is undefined).  One open capture per
+ * thread. */
 ur_status ur_graph_begin(void* stream);
 ur_status ur_graph_end(void* stream, void** graph_exec);
 ur_status ur_graph_launch(void* graph_exec, void* stream);

@@ -86,6 +86,7 @@ _SIGS = {
     "ur_ewald_image": [_vp, _vp, _c.POINTER(UrEwald), _vp, _vp],
     "ur_peak_integrals": [_c.c_int32, _vp, _vp, _c.c_int32, _c.POINTER(_c.c_double), _vp, _vp],
     "ur_ensemble": [_c.c_int32, _c.c_int32, _vp, _vp, _vp, _vp, _vp, _vp],
+    "ur_chi2": [_c.c_int32, _vp, _vp, _vp, _c.c_double, _vp, _vp, _vp],
     "ur_graph_begin": [_vp],
     "ur_graph_end": [_vp, _c.POINTER(_vp)],
     "ur_graph_launch": [_vp, _vp],
@@ -275,6 +276,25 @@ def ensemble(batch: HistBatch, weights, out=None, stream=None):
                torch.empty(batch.nbins, dtype=torch.float64, device="cuda"))
     _check(lib().ur_ensemble(batch.nboxes, batch.nbins, _ptr(batch.mean), _ptr(batch.sem), _ptr(weights),
                              _ptr(out[0]), _ptr(out[1]), _stream(stream)), "ur_ensemble")
+    return out
+
+
+def chi2(mean, count, target, rel_sigma: float = 0.01, out=None, g_bin=None, stream=None):
+    """chi^2 of a binned curve against a target (ur_chi2) and, into `g_bin`
+    when given, its gradient per bin; device FP64 tensors.  Returns the
+    1-element device tensor holding chi^2."""
+    torch = _torch()
+    nb = int(mean.numel())
+    _require(mean, torch.float64, nb, "mean")
+    _require(count, torch.float64, nb, "count")
+    _require(target, torch.float64, nb, "target")
+    if out is None:
+        out = torch.empty(1, dtype=torch.float64, device="cuda")
+    _require(out, torch.float64, 1, "out")
+    if g_bin is not None:
+        _require(g_bin, torch.float64, nb, "g_bin")
+    _check(lib().ur_chi2(nb, _ptr(mean), _ptr(count), _ptr(target), float(rel_sigma), _ptr(out), _ptr(g_bin),
+                         _stream(stream)), "ur_chi2")
     return out
 
 

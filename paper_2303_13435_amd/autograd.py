@@ -7,14 +7,16 @@ which gives dL/d amp from dL/dI_b (the gradient of eq. 1's |F|^2 averaged per
 bin, folded back through tiling and masking); when nothing else ran on the
 plan since the forward call it starts from the plan's held y-pass output
 (``ur_adjoint_reuse``) instead of recomputing it.  ``BinnedIntensityRho`` does
-the same for a given voxel density.  Both run entirely in the HIP kernels;
-the Python here only moves pointers.
+the same for a given voxel density, and ``chi2`` is the misfit of a curve
+against a target with its per-bin gradient (``ur_chi2``).  All of it runs in
+the HIP kernels; the Python here only moves pointers.
 """
 from __future__ import annotations
 
 import torch
 
 from . import DeviceCell, Hist, Plan
+from . import chi2 as _chi2
 
 
 def _means(h: Hist) -> torch.Tensor:
@@ -63,8 +65,25 @@ class BinnedIntensityRho(torch.autograd.Function):
         return grad, None
 
 
+class Chi2(torch.autograd.Function):
+    """chi^2 of a binned curve against a target and its gradient per bin,
+    both computed by ``ur_chi2`` on the device (fixed-order compensated sum)."""
+
+    @staticmethod
+    def forward(ctx, mean: torch.Tensor, target: torch.Tensor, count: torch.Tensor, rel_sigma: float = 0.01):
+        m = mean.detach().to(torch.float64).contiguous()
+        g = torch.empty_like(m)
+        out = _chi2(m, count.detach().to(torch.float64).contiguous(), target.detach().to(torch.float64).contiguous(),
+                    rel_sigma, g_bin=g)
+        ctx.save_for_backward(g)
+        return out[0].clone()
+
+    @staticmethod
+    def backward(ctx, g_out: torch.Tensor):
+        (g,) = ctx.saved_tensors
+        return g * g_out, None, None, None
+
+
 def chi2(mean: torch.Tensor, target: torch.Tensor, count: torch.Tensor, rel_sigma: float = 0.01) -> torch.Tensor:
-    """sum over populated bins of ((I_b - T_b) / (rel_sigma T_b))^2."""
-    m = count > 0
-    r = (mean[m] - target[m]) / (rel_sigma * target[m])
-    return torch.sum(r * r)
+    """sum over populated bins of ((I_b - T_b) / (rel_sigma T_b))^2 (ur_chi2)."""
+    return Chi2.apply(mean, target, count, rel_sigma)

@@ -8,6 +8,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
 #include <mutex>
 #include <string>
 #include <thread>
@@ -100,6 +101,14 @@ struct ur_plan {
   size_t bounce_bytes = 0;
   size_t hbm_budget = 0;     // out-of-core workspace bytes allowed (0: no limit)
   void* dSinc = nullptr;     // voxel form factor table S(m), m in [0, n/2], or null when off
+
+  // live HIP graphs recorded from this plan's calls (ur_graph_begin/end):
+  // they hold raw pointers into the workspace and tables, so nothing may be
+  // reallocated or rewritten while any exists; graph_external marks a call
+  // recorded under a capture this library did not start (its graph's
+  // lifetime is unknown, so the plan stays bound)
+  int graphs = 0;
+  bool graph_external = false;
 
   // per-pass timing
   bool timing = false;
@@ -232,8 +241,40 @@ static ur_status ooc_split(const ur_plan* p, int nbins, int xlo, int xhi, OocSpl
   return fail(UR_ERR_OOM, "HBM budget of %zu bytes is below the out-of-core workspace of one kz row", p->hbm_budget);
 }
 
+// ---------------------------------------------------------------------------
+// graphs: which plans a live graph was recorded from
+// ---------------------------------------------------------------------------
+static std::mutex g_graph_mu;
+static std::map<void*, std::vector<ur_plan*>> g_graph_plans;   // graph exec -> plans it uses
+static thread_local bool tl_capturing = false;                // between ur_graph_begin and ur_graph_end
+static thread_local std::vector<ur_plan*> tl_captured;
+
+static bool graph_bound(const ur_plan* p) { return p->graphs > 0 || p->graph_external; }
+
+// Entry of every call that enqueues work of the plan on `s`: under capture,
+// note the plan as used by the graph being recorded.
+static void note_stream(ur_plan* p, hipStream_t s) {
+  hipStreamCaptureStatus cst = hipStreamCaptureStatusNone;
+  if (!s || hipStreamIsCapturing(s, &cst) != hipSuccess) { (void)hipGetLastError(); return; }
+  if (cst == hipStreamCaptureStatusNone) return;
+  if (!tl_capturing) { p->graph_external = true; return; }
+  if (std::find(tl_captured.begin(), tl_captured.end(), p) == tl_captured.end()) {
+    try {
+      tl_captured.push_back(p);
+    } catch (...) {
+      p->graph_external = true;                 // cannot track it: keep the plan bound
+    }
+  }
+}
+
+static ur_status refuse_bound(const ur_plan* p, const char* what) {
+  return fail(UR_ERR_STATE, "%s: the plan is recorded in a live graph (destroy the graph with ur_graph_destroy first)%s",
+              what, p->graph_external ? "; it was recorded under a capture not started by ur_graph_begin" : "");
+}
+
 static ur_status ensure_ws(ur_plan* p, size_t need, hipStream_t s) {
   if (p->ws && p->ws_bytes >= need) return UR_OK;
+  if (graph_bound(p)) return refuse_bound(p, "workspace reallocation");
   if (p->ws && !p->ws_owned)
     return fail(UR_ERR_STATE, "attached workspace holds %zu bytes, this call needs %zu", p->ws_bytes, need);
   hipStreamCaptureStatus cst = hipStreamCaptureStatusNone;
@@ -251,6 +292,7 @@ static ur_status ensure_ws(ur_plan* p, size_t need, hipStream_t s) {
 
 static ur_status ensure_cell_scratch(ur_plan* p, size_t need, hipStream_t s) {
   if (p->cs_buf && p->cs_bytes >= need) return UR_OK;
+  if (graph_bound(p)) return refuse_bound(p, "cell scratch reallocation");
   hipStreamCaptureStatus cst = hipStreamCaptureStatusNone;
   if (s) (void)hipStreamIsCapturing(s, &cst);
   if (cst != hipStreamCaptureStatusNone)
@@ -408,6 +450,10 @@ ur_status ur_plan_create(int32_t n, double voxel, int32_t prec, uint32_t flags, 
 
 void ur_plan_destroy(ur_plan* p) {
   if (!p) return;
+  if (p->graphs > 0) {                   // graphs that still name it forget it (replaying them is invalid)
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    for (auto& e : g_graph_plans) e.second.erase(std::remove(e.second.begin(), e.second.end(), p), e.second.end());
+  }
   (void)hipDeviceSynchronize();
   if (p->tw) (void)hipFree(p->tw);
   if (p->dU) (void)hipFree(p->dU);
@@ -447,6 +493,7 @@ ur_status ur_plan_workspace_size_host(const ur_plan* p, int32_t nbins, int32_t x
 
 ur_status ur_plan_set_voxel_form(ur_plan* p, int32_t enable) {
   if (!p) return fail(UR_ERR_INVALID, "plan is null");
+  if (graph_bound(p) && ((enable != 0) != (p->dSinc != nullptr))) return refuse_bound(p, "ur_plan_set_voxel_form");
   if (!enable) {
     if (p->dSinc) { UR_HIP(hipDeviceSynchronize()); UR_HIP(hipFree(p->dSinc)); p->dSinc = nullptr; }
     return UR_OK;
@@ -486,6 +533,7 @@ ur_status ur_plan_set_workspace(ur_plan* p, void* dev_ptr, size_t bytes) {
   if (p) p->keep_valid = false;
   if (!p || !dev_ptr) return fail(UR_ERR_INVALID, "null argument");
   if (((uintptr_t)dev_ptr) & 255) return fail(UR_ERR_INVALID, "workspace must be 256-byte aligned");
+  if (graph_bound(p) && dev_ptr != (void*)p->ws) return refuse_bound(p, "ur_plan_set_workspace");
   if (p->ws && p->ws_owned) { UR_HIP(hipDeviceSynchronize()); UR_HIP(hipFree(p->ws)); }
   p->ws = (char*)dev_ptr;
   p->ws_bytes = bytes;
@@ -536,6 +584,7 @@ static ur_status set_bins_impl(ur_plan* p, int32_t nbins, const double* edges) {
   if (p) p->keep_valid = false;
   if (!p || !edges) return fail(UR_ERR_INVALID, "null argument");
   if (nbins < 1 || nbins > 4096) return fail(UR_ERR_INVALID, "nbins = %d outside [1, 4096]", nbins);
+  if (graph_bound(p)) return refuse_bound(p, "ur_plan_set_bins");
   for (int b = 0; b <= nbins; ++b)
     if (!isfinite(edges[b]) || (b > 0 && !(edges[b] > edges[b - 1])))
       return fail(UR_ERR_INVALID, "bin edges must be finite and strictly increasing (edge %d)", b);
@@ -678,29 +727,45 @@ struct CellTables {
 
 static const int kFoldBlocks = 512;
 
-// cell synthesis + tables for the generator (a1 of the path)
-static ur_status prepare_cell(ur_plan* p, const ur_cell* cell, int f, CellTables& t, hipStream_t s) {
+// Byte offsets of the cell tables; `fold` adds the adjoint's fold buffers.
+struct CellLayout {
+  size_t prof, cell, cellT, pre, cb, g, fp, total;
+};
+static CellLayout cell_layout(const ur_plan* p, const ur_cell* cell, int f, bool fold) {
   const size_t c = cell->c, c3 = c * c * c;
-  t.cbn = f <= (int)c ? (int)c / f : 1;
-  const size_t nb = (size_t)t.cbn * t.cbn * t.cbn;
+  const int cbn = f <= (int)c ? (int)c / f : 1;
+  const size_t nb = (size_t)cbn * cbn * cbn;
+  CellLayout L{};
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
-  size_t o_prof = take(std::max<size_t>(1, (size_t)cell->n_atoms * 3 * c) * 8);
-  size_t o_cell = take(c3 * 8);
-  size_t o_cellT = take(c3 * p->rs);
-  size_t o_pre = take(c * c * (c + 1) * 8);
-  size_t o_cb = take(nb * p->rs);
-  size_t o_g = take(c3 * 8);
-  size_t o_fp = take((c <= 16 ? (size_t)kFoldBlocks * c3 : 1) * 8);
-  UR_TRY(ensure_cell_scratch(p, off, s));
-  char* b = p->cs_buf;
+  L.prof = take(std::max<size_t>(1, (size_t)cell->n_atoms * 3 * c) * 8);
+  L.cell = take(c3 * 8);
+  L.cellT = take(c3 * p->rs);
+  L.pre = take(c * c * (c + 1) * 8);
+  L.cb = take(nb * p->rs);
+  L.g = fold ? take(c3 * 8) : 0;
+  L.fp = fold ? take((c <= 16 ? (size_t)kFoldBlocks * c3 : 1) * 8) : 0;
+  L.total = off;
+  return L;
+}
+
+// cell synthesis + tables for the generator (a1 of the path), in the plan's
+// cell scratch, or at `base` (the static scratch of the allocation-free entry)
+static ur_status prepare_cell(ur_plan* p, const ur_cell* cell, int f, CellTables& t, hipStream_t s,
+                              char* base = nullptr) {
+  const CellLayout CL = cell_layout(p, cell, f, base == nullptr);
+  t.cbn = f <= (int)cell->c ? (int)cell->c / f : 1;
+  const size_t o_prof = CL.prof, o_cell = CL.cell, o_cellT = CL.cellT, o_pre = CL.pre, o_cb = CL.cb, o_g = CL.g,
+               o_fp = CL.fp;
+  if (!base) UR_TRY(ensure_cell_scratch(p, CL.total, s));
+  char* b = base ? base : p->cs_buf;
   t.prof = (double*)(b + o_prof);
   t.cell64 = (double*)(b + o_cell);
   t.cellT = b + o_cellT;
   t.pre = (double*)(b + o_pre);
   t.cb = b + o_cb;
-  t.gcell = (double*)(b + o_g);
-  t.fold_part = (double*)(b + o_fp);
+  t.gcell = base ? nullptr : (double*)(b + o_g);
+  t.fold_part = base ? nullptr : (double*)(b + o_fp);
   UR_HIP(launch_cell_profiles(cell->c, cell->n_atoms, cell->xyz, cell->sigma, t.prof, s));
   UR_HIP(launch_cell_sum(cell->c, cell->n_atoms, cell->amp, t.prof, cell->background, t.cell64, s));
   if (oriented(cell) && cell->interp == 3) UR_HIP(launch_bspline_cell(cell->c, t.cell64, s));   // spline coefficients
@@ -732,7 +797,7 @@ static double live_rows(const ur_plan* p, const FwdGeom& g) {
 }
 
 static ur_status run_y_x(ur_plan* p, const FwdGeom& g, char* A, char* B, const Layout& lay,
-                         const ur_hist* h, int nzb, hipStream_t s) {
+                         const ur_hist* h, int nzb, hipStream_t s, char* ws) {
   const int n = p->n, tx = y_tile(p->prec, n);
   const double rows = live_rows(p, g);
   long long xt0 = 0, xt1 = -1, bx0 = 0, bs = tx;
@@ -760,7 +825,7 @@ static ur_status run_y_x(ur_plan* p, const FwdGeom& g, char* A, char* B, const L
   xa.xa = (int)bx0; xa.xb = g.xlo <= g.xhi ? (int)(bx0 + bs - 1) : -1;
   xa.iscale = 1.0 / ((double)n * n * n) / ((double)n * n * n);
   xa.oscale = 1.0; xa.nbins = p->nbins; xa.U = p->dU; xa.lut = p->dLut; xa.nlut = p->nlut; xa.sinc = p->dSinc;
-  xa.part = (double*)(p->ws + lay.part); xa.f0 = (double*)(p->ws + lay.f0);
+  xa.part = (double*)(ws + lay.part); xa.f0 = (double*)(ws + lay.f0);
   xa.ncols = p->nkz * n;
   {
     PassTimer tm(p, P_X, s);
@@ -768,8 +833,8 @@ static ur_status run_y_x(ur_plan* p, const FwdGeom& g, char* A, char* B, const L
   }
   FinArgs fa{};
   fa.part = xa.part; fa.nblk = nxb; fa.nbins = p->nbins;
-  fa.mom = nzb > 0 ? (const double*)(p->ws + lay.mom) : nullptr; fa.nzb = nzb;
-  fa.mpart = (double*)(p->ws + lay.f0 + 64); fa.f0 = xa.f0; fa.cnt = p->dCount; fa.sum = h->sum; fa.sumsq = h->sumsq; fa.count = h->count; fa.totals = h->totals; fa.mean = h->mean; fa.sem = h->sem;
+  fa.mom = nzb > 0 ? (const double*)(ws + lay.mom) : nullptr; fa.nzb = nzb;
+  fa.mpart = (double*)(ws + lay.f0 + 64); fa.f0 = xa.f0; fa.cnt = p->dCount; fa.sum = h->sum; fa.sumsq = h->sumsq; fa.count = h->count; fa.totals = h->totals; fa.mean = h->mean; fa.sem = h->sem;
   {
     PassTimer tm(p, P_FIN, s);
     UR_HIP(launch_finalize(fa, s));
@@ -846,6 +911,7 @@ ur_status ur_cell_synth(ur_plan* p, const ur_cell* cell, double* cell_out, void*
   if (!p || !cell_out) return fail(UR_ERR_INVALID, "null argument");
   UR_TRY(check_cell(cell, true));
   hipStream_t s = (hipStream_t)stream;
+  note_stream(p, s);
   size_t need = align256(std::max<size_t>(1, (size_t)cell->n_atoms * 3 * cell->c) * 8);
   UR_TRY(ensure_cell_scratch(p, std::max(need, p->cs_bytes), s));
   double* prof = (double*)p->cs_buf;
@@ -864,6 +930,7 @@ ur_status ur_rho_generate(ur_plan* p, const ur_cell* cell, const ur_mask* mask, 
   MaskP m;
   UR_TRY(check_level(p, cell, mask, zoom, L, m));
   hipStream_t s = (hipStream_t)stream;
+  note_stream(p, s);
   CellTables t;
   UR_TRY(prepare_cell(p, cell, zoom->factor, t, s));
   ZArgs za{};
@@ -872,6 +939,11 @@ ur_status ur_rho_generate(ur_plan* p, const ur_cell* cell, const ur_mask* mask, 
   UR_HIP(launch_rho_generate(p->prec, p->n, x_lo, x_hi, za, rho, s));
   return UR_OK;
 }
+
+}  // extern "C"
+static ur_status simulate_pow2(ur_plan* p, const ur_cell* cell, const ur_zoom* zoom, const ur_hist* h, hipStream_t s,
+                               FwdGeom g, const ZArgs& rot_args, const CellTables& t, const Layout& lay, char* ws);
+extern "C" {
 
 ur_status ur_simulate(ur_plan* p, const ur_cell* cell, const ur_mask* mask, const ur_zoom* zoom, const ur_hist* h, void* stream) {
   if (p) p->keep_valid = false;
@@ -885,6 +957,7 @@ ur_status ur_simulate(ur_plan* p, const ur_cell* cell, const ur_mask* mask, cons
   ZArgs rot_args{};
   UR_TRY(set_rotation(p, cell, zoom, rot_args));
   hipStream_t s = (hipStream_t)stream;
+  note_stream(p, s);
   if (p->mixed) {
     if (p->dSinc) return fail(UR_ERR_UNSUPPORTED, "mixed-radix boxes run without the voxel form factor");
     Layout lay = layout_mixed(p, p->nbins);
@@ -918,6 +991,15 @@ ur_status ur_simulate(ur_plan* p, const ur_cell* cell, const ur_mask* mask, cons
     PassTimer tm(p, P_CELL, s);
     UR_TRY(prepare_cell(p, cell, zoom->factor, t, s));
   }
+  return simulate_pow2(p, cell, zoom, h, s, g, rot_args, t, lay, p->ws);
+}
+
+}  // extern "C"
+
+// passes Z, Y, X and the finalize of a power-of-two box, with the transform
+// intermediates and partials at `ws` (layout `lay`) and the cell tables `t`
+static ur_status simulate_pow2(ur_plan* p, const ur_cell* cell, const ur_zoom* zoom, const ur_hist* h, hipStream_t s,
+                               FwdGeom g, const ZArgs& rot_args, const CellTables& t, const Layout& lay, char* ws) {
   {
     const double c = cell->c;
     p->pass_bytes[P_CELL] = 8.0 * (3.0 * c * cell->n_atoms) * 2.0 + c * c * c * (16.0 + p->rs);
@@ -931,8 +1013,8 @@ ur_status ur_simulate(ur_plan* p, const ur_cell* cell, const ur_mask* mask, cons
   int nzb = 0;
   if (xlo <= xhi) {
     ZArgs za = rot_args;
-    za.A = p->ws + lay.A; za.ax0 = xlo; za.cellT = t.cellT; za.cb = t.cb; za.pre = t.pre; za.tw = p->tw;
-    za.mom = (double*)(p->ws + lay.mom); za.L = g.L; za.m = g.m; za.nkz = p->nkz; za.x0 = (int)xlo;
+    za.A = ws + lay.A; za.ax0 = xlo; za.cellT = t.cellT; za.cb = t.cb; za.pre = t.pre; za.tw = p->tw;
+    za.mom = (double*)(ws + lay.mom); za.L = g.L; za.m = g.m; za.nkz = p->nkz; za.x0 = (int)xlo;
     za.ntiles = ntiles(p); za.cbn = t.cbn;
     nzb = (int)((xhi - xlo + 1) * za.ntiles);
     PassTimer tm(p, P_Z, s);
@@ -941,14 +1023,16 @@ ur_status ur_simulate(ur_plan* p, const ur_cell* cell, const ur_mask* mask, cons
     UR_HIP(launch_pass_z(p->prec, p->n, zm, za, nzb, s));
   }
   p->pass_bytes[P_Z] = live_rows(p, g) * p->nkz * p->cs + 16.0 * nzb;
-  const ur_status st = run_y_x(p, g, p->ws + lay.A, p->ws + lay.B, lay, h, nzb, s);
-  if (st == UR_OK && zoom->factor == 1 && zoom->n1 == p->n && !(p->flags & UR_C2C) && !oriented(cell)) {
+  const ur_status st = run_y_x(p, g, ws + lay.A, ws + lay.B, lay, h, nzb, s, ws);
+  if (st == UR_OK && ws == p->ws && zoom->factor == 1 && zoom->n1 == p->n && !(p->flags & UR_C2C) && !oriented(cell)) {
     p->keep_valid = true;
     p->keep_m = g.m;
     p->keep_c = cell->c;
   }
   return st;
 }
+
+extern "C" {
 
 ur_status ur_simulate_rho(ur_plan* p, const void* rho, const ur_hist* h, void* stream) {
   if (p) p->keep_valid = false;
@@ -957,6 +1041,7 @@ ur_status ur_simulate_rho(ur_plan* p, const void* rho, const ur_hist* h, void* s
   if (p->nbins < 1) return fail(UR_ERR_STATE, "no bins set on the plan");
   UR_TRY(check_hist(h));
   hipStream_t s = (hipStream_t)stream;
+  note_stream(p, s);
   if (p->mixed) {
     if (p->dSinc) return fail(UR_ERR_UNSUPPORTED, "mixed-radix boxes run without the voxel form factor");
     Layout lay = layout_mixed(p, p->nbins);
@@ -980,7 +1065,7 @@ ur_status ur_simulate_rho(ur_plan* p, const void* rho, const ur_hist* h, void* s
   p->pass_bytes[P_CELL] = 0.0;
   p->pass_bytes[P_Z] = (double)p->n * p->n * p->n * ((p->flags & UR_C2C) ? p->cs : p->rs) +
                        (double)p->n * p->nkz * p->n * p->cs + 16.0 * nzb;
-  return run_y_x(p, g, p->ws + lay.A, p->ws + lay.B, lay, h, nzb, s);
+  return run_y_x(p, g, p->ws + lay.A, p->ws + lay.B, lay, h, nzb, s, p->ws);
 }
 
 ur_status ur_fft3d_exec(ur_plan* p, const void* in, void* out, int32_t dir, void* stream) {
@@ -991,6 +1076,7 @@ ur_status ur_fft3d_exec(ur_plan* p, const void* in, void* out, int32_t dir, void
   if (dir > 0 && p->n > 1024) return fail(UR_ERR_UNSUPPORTED, "inverse transforms run up to 1024^3");
   if (in == out) return fail(UR_ERR_INVALID, "in and out must differ");
   hipStream_t s = (hipStream_t)stream;
+  note_stream(p, s);
   if (p->mixed) return mr_transform(p, in, out, dir, nullptr, nullptr, nullptr, s);
   Layout lay = layout_incore(p, std::max(p->nbins, 1));
   UR_TRY(ensure_ws(p, lay.total, s));
@@ -1033,6 +1119,7 @@ ur_status ur_intensity_bin(ur_plan* p, const void* spectrum, const ur_hist* h, v
   if (p->nbins < 1) return fail(UR_ERR_STATE, "no bins set on the plan");
   UR_TRY(check_hist(h));
   hipStream_t s = (hipStream_t)stream;
+  note_stream(p, s);
   if (p->mixed) {
     if (p->dSinc) return fail(UR_ERR_UNSUPPORTED, "mixed-radix boxes run without the voxel form factor");
     Layout lay = layout_mixed(p, p->nbins);
@@ -1065,6 +1152,7 @@ ur_status ur_simulate_host(ur_plan* p, const void* rho_host, int32_t x_lo, int32
   if (x_lo < 0 || x_hi >= p->n || x_lo > x_hi) return fail(UR_ERR_INVALID, "plane range [%d, %d] outside the box", x_lo, x_hi);
   UR_TRY(check_hist(h));
   hipStream_t s = (hipStream_t)stream;
+  note_stream(p, s);
   hipStreamCaptureStatus cst = hipStreamCaptureStatusNone;
   if (s) (void)hipStreamIsCapturing(s, &cst);
   if (cst != hipStreamCaptureStatusNone) return fail(UR_ERR_STATE, "the out-of-core path is a host-driven pipeline and cannot be captured");
@@ -1237,6 +1325,7 @@ static ur_status adjoint_run(ur_plan* p, const void* rho, const ur_cell* cell, c
   if (!grad_rho && !grad_amp) return UR_OK;
   if (p->n > 1024) return fail(UR_ERR_UNSUPPORTED, "the adjoint runs up to 1024^3");
   hipStream_t s = (hipStream_t)stream;
+  note_stream(p, s);
   Layout lay = layout_incore(p, p->nbins);
   UR_TRY(ensure_ws(p, lay.total, s));
   const int n = p->n, c2c = (p->flags & UR_C2C) ? 1 : 0, tx = y_tile(p->prec, n);
@@ -1394,6 +1483,15 @@ ur_status ur_peak_integrals(int32_t nbins, const double* edges, const double* me
   return UR_OK;
 }
 
+ur_status ur_chi2(int32_t nbins, const double* mean, const double* count, const double* target, double rel_sigma,
+                  double* out_chi2, double* g_bin, void* stream) {
+  if (nbins < 1 || nbins > 4096) return fail(UR_ERR_INVALID, "nbins = %d outside [1, 4096]", nbins);
+  if (!mean || !count || !target || !out_chi2) return fail(UR_ERR_INVALID, "null argument");
+  if (!(rel_sigma > 0.0) || !isfinite(rel_sigma)) return fail(UR_ERR_INVALID, "rel_sigma must be positive and finite");
+  UR_HIP(launch_chi2(nbins, mean, count, target, rel_sigma, out_chi2, g_bin, (hipStream_t)stream));
+  return UR_OK;
+}
+
 ur_status ur_ensemble(int32_t nboxes, int32_t nbins, const double* mean, const double* sem, const double* weights,
                       double* out_mean, double* out_sem, void* stream) {
   if (nboxes < 1) return fail(UR_ERR_INVALID, "nboxes = %d must be >= 1", nboxes);
@@ -1434,18 +1532,31 @@ ur_status ur_merge_zooms(int32_t nlevels, const ur_hist* levels, const int32_t* 
 
 ur_status ur_graph_begin(void* stream) {
   if (!stream) return fail(UR_ERR_INVALID, "capture needs a non-null stream");
+  if (tl_capturing) return fail(UR_ERR_STATE, "a capture started by ur_graph_begin is already open on this thread");
   UR_HIP(hipStreamBeginCapture((hipStream_t)stream, hipStreamCaptureModeThreadLocal));
+  tl_capturing = true;
+  tl_captured.clear();
   return UR_OK;
 }
 
 ur_status ur_graph_end(void* stream, void** graph_exec) {
   if (!stream || !graph_exec) return fail(UR_ERR_INVALID, "null argument");
+  std::vector<ur_plan*> used;
+  used.swap(tl_captured);
+  tl_capturing = false;
   hipGraph_t g = nullptr;
   UR_HIP(hipStreamEndCapture((hipStream_t)stream, &g));
   hipGraphExec_t ex = nullptr;
   hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
   (void)hipGraphDestroy(g);
   if (e != hipSuccess) return fail(UR_ERR_HIP, "hipGraphInstantiate failed: %s", hipGetErrorString(e));
+  try {
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    g_graph_plans[(void*)ex] = used;
+    for (ur_plan* p : used) p->graphs += 1;
+  } catch (...) {
+    for (ur_plan* p : used) p->graph_external = true;          // untracked: bound for good
+  }
   *graph_exec = (void*)ex;
   return UR_OK;
 }
@@ -1458,6 +1569,14 @@ ur_status ur_graph_launch(void* graph_exec, void* stream) {
 
 ur_status ur_graph_destroy(void* graph_exec) {
   if (!graph_exec) return UR_OK;
+  {
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    auto it = g_graph_plans.find(graph_exec);
+    if (it != g_graph_plans.end()) {
+      for (ur_plan* p : it->second) p->graphs -= 1;
+      g_graph_plans.erase(it);
+    }
+  }
   UR_HIP(hipGraphExecDestroy((hipGraphExec_t)graph_exec));
   return UR_OK;
 }

@@ -1024,9 +1024,12 @@ k_pass_x(XArgs a) {
     const int base = k * k + l * l;
     // lane g owns |h| in [hlo, hlo + NH) (both signs), the last lane also
     // |h| = N/2; NH consecutive |h| stay inside one 16-element LDS block.
-    // Within a run of equal bins, |X|^2 is summed in the working precision
-    // (at most 2 NH + 1 terms) and |X|^4 in FP64; the scale 1/n^6 of eq. 1
-    // and the conjugate weight w are applied once per run.
+    // Within a run of equal bins, |X|^2 and |X|^4 of the working-precision
+    // values are both summed in FP64, so that a bin's sum and sum of squares
+    // describe the same numbers (the one-pass variance of the finalize
+    // subtracts them; a bin whose intensities barely vary would lose its SEM
+    // to the rounding of a working-precision run sum); the scale 1/n^6 of
+    // eq. 1 and the conjugate weight w are applied once per run.
     constexpr int NH = G == 1 ? N / 2 : E / 2;
     const int hlo = G == 1 ? 0 : g * NH;
     // starting bin: the table entry of s = isqrt(n2) (the bin of s^2 <= n2),
@@ -1040,8 +1043,7 @@ k_pass_x(XArgs a) {
     while (n20 >= nextU) { ++b; nextU = U[b + 1]; }
     int nextU2 = U[b + 2];                               // one threshold ahead, off the critical path
     int cb = b;
-    T cs = (T)0, ct = (T)0;
-    double cs2 = 0.0;
+    double cs = 0.0, ct = 0.0, cs2 = 0.0;
     // SINC: the column's factor S(|k|) S(|l|) joins the weight, S(|h|) each voxel
     const double wcol = SINC ? (double)St[k < 0 ? -k : k] * (double)St[l < 0 ? -l : l] : 1.0;
     const double ws = w * a.iscale * wcol, ws2 = w * a.iscale * a.iscale * wcol * wcol;
@@ -1050,10 +1052,10 @@ k_pass_x(XArgs a) {
       if constexpr (SINC) { const T sh = St[ha]; q1 *= sh; q2 *= sh; }
       const int n2 = ha * ha + base;
       if (n2 >= nextU) {
-        atomicAdd(&hist[2 * cb + 0], (double)cs * ws);
+        atomicAdd(&hist[2 * cb + 0], cs * ws);
         atomicAdd(&hist[2 * cb + 1], cs2 * ws2);
         ct += cs;
-        cs = (T)0;
+        cs = 0.0;
         cs2 = 0.0;
         ++b;
         nextU = nextU2;
@@ -1062,7 +1064,7 @@ k_pass_x(XArgs a) {
         cb = b;
       }
       const double d1 = (double)q1, d2 = (double)q2;
-      cs += q1 + q2;
+      cs += d1 + d2;
       cs2 += d1 * d1 + d2 * d2;
     };
 #pragma unroll
@@ -1081,9 +1083,9 @@ k_pass_x(XArgs a) {
       const cx<T> f1 = s[pad(N / 2)];
       take(N / 2, f1.x * f1.x + f1.y * f1.y, (T)0);
     }
-    atomicAdd(&hist[2 * cb + 0], (double)cs * ws);
+    atomicAdd(&hist[2 * cb + 0], cs * ws);
     atomicAdd(&hist[2 * cb + 1], cs2 * ws2);
-    tot += (double)(ct + cs) * ws;
+    tot += (ct + cs) * ws;
     if (kz == 0 && ky == 0 && g == 0 && a.f0) {
       const cx<T> f = s[pad(0)];
       a.f0[0] = (double)f.x * sqrt(a.iscale);
@@ -1325,6 +1327,43 @@ __global__ void __launch_bounds__(256) k_ensemble(int nboxes, int nbins, const d
   }
   out_mean[b] = m.val();                   // NaN where the bin is empty (every box)
   out_sem[b] = sqrt(v.val());              // NaN for one-voxel bins
+}
+
+// chi^2 of a binned curve against a target and its gradient per bin, one
+// block: thread t takes bins t, t + 256, ... in order (compensated), then a
+// fixed-order tree over the 256 partials, so the sum does not depend on
+// timing.  Empty bins (count 0) take no part and get a zero gradient.
+__global__ void __launch_bounds__(256) k_chi2(int nbins, const double* __restrict__ mean,
+                                              const double* __restrict__ count, const double* __restrict__ target,
+                                              double rel_sigma, double* __restrict__ out, double* __restrict__ g) {
+  __shared__ double ps[256], pc[256];
+  Kahan k;
+  for (int b = threadIdx.x; b < nbins; b += 256) {
+    double gb = 0.0;
+    if (count[b] > 0.0) {
+      const double sg = rel_sigma * target[b];
+      const double r = (mean[b] - target[b]) / sg;
+      k.add(r * r);
+      gb = 2.0 * r / sg;                     // d (r^2) / d mean_b
+    }
+    if (g) g[b] = gb;
+  }
+  ps[threadIdx.x] = k.s;
+  pc[threadIdx.x] = k.c;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      Kahan m;
+      m.s = ps[threadIdx.x];
+      m.c = pc[threadIdx.x];
+      m.add(ps[threadIdx.x + w]);
+      m.c += pc[threadIdx.x + w];
+      ps[threadIdx.x] = m.s;
+      pc[threadIdx.x] = m.c;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = ps[0] + pc[0];
 }
 
 #endif
@@ -2191,6 +2230,12 @@ hipError_t launch_ensemble(int nboxes, int nbins, const double* mean, const doub
 
 hipError_t launch_merge(const MergeArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_merge, dim3(nblk_of(a.nbins, 256)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_chi2(int nbins, const double* mean, const double* count, const double* target, double rel_sigma,
+                       double* out, double* g, hipStream_t s) {
+  hipLaunchKernelGGL(k_chi2, dim3(1), dim3(256), 0, s, nbins, mean, count, target, rel_sigma, out, g);
   return hipGetLastError();
 }
 

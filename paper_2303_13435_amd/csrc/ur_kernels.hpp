@@ -275,6 +275,8 @@ struct PeakArgs {
 };
 hipError_t launch_peaks(const PeakArgs& a, hipStream_t s);
 
+hipError_t launch_chi2(int nbins, const double* mean, const double* count, const double* target, double rel_sigma,
+                       double* out, double* g, hipStream_t s);
 hipError_t launch_ensemble(int nboxes, int nbins, const double* mean, const double* sem, const double* w,
                            double* out_mean, double* out_sem, hipStream_t s);
 hipError_t launch_pass_x_adj(int prec, int n, const XAdjArgs& a, int nblocks, hipStream_t s);

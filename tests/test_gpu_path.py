@@ -364,8 +364,10 @@ def test_radii_batch_in_one_graph(ur, orc, n, count, r_lo, r_hi, check):
             d = h.numpy()
             assert np.array_equal(d["count"], e["count"])
             pop = e["count"] > 0
-            assert np.array_equal(d["sum"][pop], e["sum"][pop])
-            assert np.array_equal(d["mean"][pop], e["mean"][pop])
+            # the in-block bin sums are FP64 LDS atomics, whose order between
+            # wavefronts varies from run to run: equal to rounding, not bit for bit
+            assert np.allclose(d["sum"][pop], e["sum"][pop], rtol=1e-12, atol=0)
+            assert np.allclose(d["mean"][pop], e["mean"][pop], rtol=1e-12, atol=0)
     sel = range(count) if check == "all" else (0, count - 1)
     for i in sel:
         wl = levels[i]
@@ -507,6 +509,80 @@ def test_adjoint_reuse_matches_recompute(ur, orc, prec):
     with pytest.raises(ur.UltimaError, match="status 6"):
         plan.adjoint_reuse(fwd, g, cell, W.sphere(20.0), gb)
     torch.cuda.synchronize()
+
+
+def test_graph_bound_plan_refuses_reallocation(ur):
+    """While a graph recorded from a plan's calls is alive, the plan refuses
+    every call that would free or rewrite what the graph points into (bins,
+    workspace, a larger cell scratch), with UR_ERR_STATE and before anything
+    is freed; the graph still replays correctly afterwards, and once it is
+    destroyed the same calls succeed."""
+    import torch
+    wl = W.small(64, c=8, n_atoms=10, seed=7, radius=25.0, nbins=64)
+    plan = ur.Plan(64, 1.0, 0)
+    plan.set_bins(wl.edges)
+    cell = ur.DeviceCell.from_host(wl.cell)
+    eager = ur.Hist(wl.nbins)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        plan.simulate(cell, wl.mask, wl.zoom, eager, stream=s)
+    torch.cuda.synchronize()
+    ref = eager.numpy()
+    h = ur.Hist(wl.nbins)
+    g = ur.Graph(s)
+    with torch.cuda.stream(s):
+        with g:
+            plan.simulate(cell, wl.mask, wl.zoom, h, stream=s)
+    more = W.small(64, c=8, n_atoms=10, seed=7, radius=25.0, nbins=400).edges
+    with pytest.raises(ur.UltimaError, match="status 6"):
+        plan.set_bins(more)                                  # would reallocate the threshold tables
+    with pytest.raises(ur.UltimaError, match="status 6"):
+        plan.set_bins(wl.edges)                              # would rewrite them
+    big = ur.DeviceCell.from_host(W.draw_atoms(3, 400, 16))  # larger cell scratch (more atoms, larger cell)
+    with pytest.raises(ur.UltimaError, match="status 6"):
+        plan.simulate(big, W.sphere(20.0), W.Zoom(64, 1), ur.Hist(wl.nbins))
+    with pytest.raises(ur.UltimaError, match="status 6"):
+        plan.set_voxel_form(True)
+    g.launch()
+    torch.cuda.synchronize()
+    got = h.numpy()
+    assert np.array_equal(got["count"], ref["count"])
+    pop = ref["count"] > 0
+    assert np.allclose(got["sum"][pop], ref["sum"][pop], rtol=1e-12, atol=0)
+    ur.lib().ur_graph_destroy(g.h)
+    g.h = None
+    plan.set_bins(more)                                      # free again
+    hb = ur.Hist(400)
+    plan.simulate(big, W.sphere(20.0), W.Zoom(64, 1), hb)
+    torch.cuda.synchronize()
+    assert hb.numpy()["count"].sum() > 0
+
+
+def test_chi2_matches_oracle(ur, orc):
+    """ur_chi2: chi^2 of a curve against a target and d chi^2 / d I_b
+    against the oracle's (O10) on the bins of a 64^3 box (empty bins
+    included), 1e-13 relative; the same bits on a second call."""
+    import torch
+    wl = W.small(64, c=8, n_atoms=10, seed=9, radius=25.0, nbins=80, prec=1)
+    ref = orc.simulate(wl)
+    T = np.where(ref["count"] > 0, ref["mean"] * (1.0 + 0.05 * np.sin(np.arange(wl.nbins))), 1.0)
+    mean = torch.as_tensor(np.nan_to_num(ref["mean"], nan=0.0), device="cuda")
+    cnt = torch.as_tensor(ref["count"], device="cuda")
+    tgt = torch.as_tensor(T, device="cuda")
+    g = torch.empty_like(mean)
+    out = ur.chi2(mean, cnt, tgt, 0.01, g_bin=g)
+    out2 = ur.chi2(mean, cnt, tgt, 0.01)
+    torch.cuda.synchronize()
+    c_ref = orc.chi2(ref["mean"], ref["count"], T)
+    g_ref = orc.chi2_bin_grad(ref["mean"], ref["count"], T)
+    assert abs(out.item() - c_ref) <= 1e-13 * c_ref
+    assert out.item() == out2.item()
+    gg = g.cpu().numpy()
+    assert np.all(gg[ref["count"] == 0] == 0.0)
+    assert np.max(np.abs(gg - g_ref)) <= 1e-13 * np.max(np.abs(g_ref))
+    for bad in (0.0, -1.0, float("nan")):
+        with pytest.raises(ur.UltimaError, match="status 1"):
+            ur.chi2(mean, cnt, tgt, bad)
 
 
 def test_graph_replay_matches_eager(ur):
