@@ -225,6 +225,29 @@ ur_status ur_simulate(ur_plan* plan, const ur_cell* cell, const ur_mask* mask,
  * precision [x][y][z] (complex values on mixed-radix plans). */
 ur_status ur_simulate_rho(ur_plan* plan, const void* rho, const ur_hist* hist, void* stream);
 
+/* Allocation-free variant of ur_simulate, for callers that cannot allocate
+ * device memory: code under HIP graph capture (no eager call is needed
+ * first), tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, computation and outputs as ur_simulate, but the transform
+ * intermediates, block partials and cell tables live in one static device
+ * array of the library (160 MiB, held by every device the library runs on
+ * until the process ends) instead of the plan's workspace and cell scratch;
+ * the call makes no hipMalloc / hipFree and no allocating library call.  The
+ * plan's own small tables (twiddles, bin thresholds) come from
+ * ur_plan_create and ur_plan_set_bins as before.
+ * Limit: power-of-two plans whose workspace plus cell tables fit the array,
+ * at most a 256^3 FP32 real box (with up to about 2000 bins); larger boxes
+ * fail with UR_ERR_UNSUPPORTED before anything is enqueued.
+ * Every call on one device shares the array, which keeps the last call's
+ * contents: calls that overlap on one device (on different streams, or from
+ * different threads) race and give wrong results; serialise them.  No scratch
+ * word is read before the same call has written it, so nothing needs
+ * clearing between calls.  Per-pass timing is not recorded for this call,
+ * and ur_adjoint_reuse cannot start from it (the held forward output is that
+ * of the plan's workspace). */
+ur_status ur_simulate_noalloc(ur_plan* plan, const ur_cell* cell, const ur_mask* mask, const ur_zoom* zoom,
+                              const ur_hist* hist, void* stream);
+
 /* Out-of-core forward path (the 2D + 1D separation of eq. 2).
  *
  * rho_host: HOST memory holding planes x_lo..x_hi of the density,

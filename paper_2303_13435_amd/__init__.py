@@ -78,6 +78,7 @@ _SIGS = {
     "ur_intensity_bin": [_vp, _vp, _c.POINTER(UrHist), _vp],
     "ur_simulate": [_vp, _c.POINTER(UrCell), _c.POINTER(UrMask), _c.POINTER(UrZoom), _c.POINTER(UrHist), _vp],
     "ur_simulate_rho": [_vp, _vp, _c.POINTER(UrHist), _vp],
+    "ur_simulate_noalloc": [_vp, _c.POINTER(UrCell), _c.POINTER(UrMask), _c.POINTER(UrZoom), _c.POINTER(UrHist), _vp],
     "ur_simulate_host": [_vp, _vp, _c.c_int32, _c.c_int32, _c.POINTER(UrHist), _vp, _c.POINTER(_c.c_size_t)],
     "ur_adjoint": [_vp, _vp, _c.POINTER(UrCell), _c.POINTER(UrMask), _c.POINTER(UrHist), _vp, _vp, _vp, _vp],
     "ur_adjoint_reuse": [_vp, _c.POINTER(UrCell), _c.POINTER(UrMask), _c.POINTER(UrHist), _vp, _vp, _vp],
@@ -405,6 +406,18 @@ class Plan:
         self.calls += 1
         _check(lib().ur_simulate(self.h, _c.byref(cs), _c.byref(ms), _c.byref(zs), _c.byref(hs), _stream(stream)),
                "ur_simulate")
+        return hist
+
+    def simulate_noalloc(self, cell: DeviceCell, mask, zoom, hist: Hist, stream=None, amp=None) -> Hist:
+        """ur_simulate_noalloc: the fused forward path with its scratch in the
+        library's static device array (nothing allocated by the call; boxes
+        up to 256^3 FP32)."""
+        cs = cell.struct(amp)
+        ms = mask_struct(mask)
+        zs = UrZoom(int(zoom.n1), int(zoom.factor))
+        hs = hist.struct()
+        _check(lib().ur_simulate_noalloc(self.h, _c.byref(cs), _c.byref(ms), _c.byref(zs), _c.byref(hs),
+                                         _stream(stream)), "ur_simulate_noalloc")
         return hist
 
     def simulate_rho(self, rho, hist: Hist, stream=None) -> Hist:

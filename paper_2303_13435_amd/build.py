@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libultima.so")
-SOURCES = ["ur_kernels.hip", "ur_mixed.hip", "ur_api.cpp"]
+SOURCES = ["ur_kernels.hip", "ur_mixed.hip", "ur_noalloc.hip", "ur_api.cpp"]
 # ur_kernels.hip is compiled once per part (-DUR_PART=k): each part
 # instantiates one group of transform passes, so the parts build in parallel
 KERNEL_PARTS = 11

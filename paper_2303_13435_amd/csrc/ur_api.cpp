@@ -1034,6 +1034,41 @@ static ur_status simulate_pow2(ur_plan* p, const ur_cell* cell, const ur_zoom* z
 
 extern "C" {
 
+ur_status ur_simulate_noalloc(ur_plan* p, const ur_cell* cell, const ur_mask* mask, const ur_zoom* zoom,
+                              const ur_hist* h, void* stream) {
+  if (p) p->keep_valid = false;
+  if (!p) return fail(UR_ERR_INVALID, "plan is null");
+  UR_TRY(need_in_core(p));
+  if (p->mixed) return fail(UR_ERR_UNSUPPORTED, "the allocation-free entry runs power-of-two boxes");
+  if (p->nbins < 1) return fail(UR_ERR_STATE, "no bins set on the plan");
+  UR_TRY(check_hist(h));
+  UR_TRY(check_cell(cell));
+  FwdGeom g;
+  UR_TRY(check_level(p, cell, mask, zoom, g.L, g.m));
+  ZArgs rot_args{};
+  UR_TRY(set_rotation(p, cell, zoom, rot_args));
+  const Layout lay = layout_incore(p, p->nbins);
+  const size_t cell_off = align256(lay.total);
+  const size_t need = cell_off + cell_layout(p, cell, zoom->factor, false).total;
+  if (need > kNoAllocScratchBytes)
+    return fail(UR_ERR_UNSUPPORTED,
+                "this box needs %zu bytes of scratch; the allocation-free entry holds %zu (a %d^3 %s box with %d bins "
+                "does not fit; at most a 256^3 FP32 real box)",
+                need, kNoAllocScratchBytes, p->n, p->prec == UR_F32 ? "FP32" : "FP64", p->nbins);
+  void* base = nullptr;
+  UR_HIP(noalloc_scratch(&base));
+  hipStream_t s = (hipStream_t)stream;
+  note_stream(p, s);
+  char* ws = (char*)base;
+  const bool timing = p->timing;
+  p->timing = false;                  // per-pass timing would create event objects
+  CellTables t;
+  ur_status st = prepare_cell(p, cell, zoom->factor, t, s, ws + cell_off);
+  if (st == UR_OK) st = simulate_pow2(p, cell, zoom, h, s, g, rot_args, t, lay, ws);
+  p->timing = timing;
+  return st;
+}
+
 ur_status ur_simulate_rho(ur_plan* p, const void* rho, const ur_hist* h, void* stream) {
   if (p) p->keep_valid = false;
   if (!p || !rho) return fail(UR_ERR_INVALID, "null argument");

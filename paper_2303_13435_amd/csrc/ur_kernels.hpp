@@ -296,6 +296,12 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 hipError_t launch_bin_counts(int n, int nkz, int r2c, int nbins, const int* U, unsigned long long* tmp, double* out, hipStream_t s);
 int x_resident(int prec, int n, int mode, int dir, int nbins);   // resident x-pass blocks per CU
 
+// Allocation-free forward entry: bytes of its static device scratch (a
+// 256^3 FP32 real box with its block partials and cell tables fits), and the
+// scratch's address on the current device (resolved once per device).
+constexpr size_t kNoAllocScratchBytes = (size_t)160 << 20;
+hipError_t noalloc_scratch(void** ptr);
+
 // Stockham stages (L, R) the kernels run for a length-n column; returns the
 // count (the twiddle table of stage (L, R) holds exp(-2 pi i r j/(L R)) for
 // j < L, 1 <= r < R, laid out [j][r-1], stages back to back)
