@@ -32,7 +32,7 @@ PROFILES = os.path.join(ROOT, "profiles")
 
 def kernel_hash() -> str:
     h = hashlib.sha256()
-    for f in ("ur_kernels.hip", "ur_device.hpp", "ur_geom.hpp", "ur_kernels.hpp"):
+    for f in ("ur_kernels.hip", "ur_device.hpp", "ur_geom.hpp", "ur_kernels.hpp", "ur_tuned.hpp"):
         with open(os.path.join(ROOT, "paper_2303_13435_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

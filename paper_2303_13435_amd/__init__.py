@@ -16,7 +16,9 @@ from typing import Optional, Sequence
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIBPATH = os.path.join(HERE, "libultima.so")
+# the in-tree library; UR_LIBPATH names another build of it (the tuner's
+# candidate libraries, each timed in a process of its own)
+LIBPATH = os.environ.get("UR_LIBPATH") or os.path.join(HERE, "libultima.so")
 
 UR_F32, UR_F64 = 0, 1
 UR_R2C, UR_C2C = 0, 1

@@ -13,7 +13,7 @@ SOURCES = ["ur_kernels.hip", "ur_mixed.hip", "ur_noalloc.hip", "ur_api.cpp"]
 # ur_kernels.hip is compiled once per part (-DUR_PART=k): each part
 # instantiates one group of transform passes, so the parts build in parallel
 KERNEL_PARTS = 11
-HEADERS = ["ur_device.hpp", "ur_geom.hpp", "ur_kernels.hpp"]
+HEADERS = ["ur_device.hpp", "ur_geom.hpp", "ur_kernels.hpp", "ur_tuned.hpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("UR_OFFLOAD_ARCH", "gfx950")

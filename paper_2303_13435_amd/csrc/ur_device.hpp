@@ -227,6 +227,17 @@ __device__ __forceinline__ void stage_lds(cx<T>* s, int g, const cx<T>* __restri
   constexpr int E = Geo<N>::E, G = Geo<N>::G, R = Radix<N, L>::r, NB = E / R;
   constexpr int NR = N / R;
   static_assert(NB * R == E, "radix must divide the per-lane count");
+  // twiddles first: their loads do not depend on the column, and issued
+  // ahead of the LDS reads and the fence their latency overlaps both
+  cx<T> w[NB][R > 1 ? R - 1 : 1];
+  if (L > 1) {
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const cx<T>* wp = tw + (tw_off<N>(L) + ((g + G * i) % L) * (R - 1));
+#pragma unroll
+      for (int r = 1; r < R; ++r) w[i][r - 1] = wp[r - 1];     // exp(-2 pi i r j / (L R))
+    }
+  }
   cx<T> v[NB][R];
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
@@ -245,12 +256,8 @@ __device__ __forceinline__ void stage_lds(cx<T>* s, int g, const cx<T>* __restri
     const int b = g + G * i;
     const int j = b % L;
     if (L > 1) {
-      const cx<T>* wp = tw + (tw_off<N>(L) + j * (R - 1));
 #pragma unroll
-      for (int r = 1; r < R; ++r) {
-        const cx<T> w = wp[r - 1];                 // exp(-2 pi i r j / (L R))
-        v[i][r] = DIR < 0 ? cmul(v[i][r], w) : cmulc(v[i][r], w);
-      }
+      for (int r = 1; r < R; ++r) v[i][r] = DIR < 0 ? cmul(v[i][r], w[i][r - 1]) : cmulc(v[i][r], w[i][r - 1]);
     }
     DFT<T, R, DIR>::run(v[i]);
     if constexpr (Pow2<N>::v) {

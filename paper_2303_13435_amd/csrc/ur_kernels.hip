@@ -25,11 +25,22 @@
 #endif
 #define UR_IN(k) (UR_PART < 0 || UR_PART == (k))
 
+// compile-time choices picked by the tuner (paper_2303_13435_amd/tune.py)
+#include "ur_tuned.hpp"
+
 namespace ur {
 
 // ---------------------------------------------------------------------------
 // block configuration
 // ---------------------------------------------------------------------------
+// Stores of the first intermediate (pass Z) and of the second (pass Y): with
+// the streaming policy or plain (tuned)
+template <typename T> __device__ __forceinline__ void st_a2(cx2<T>* p, cx2<T> v) {
+  if constexpr (UR_ST_NT_A) st_nt2(p, v); else *p = v;
+}
+template <typename T> __device__ __forceinline__ void st_b(cx<T>* p, cx<T> v) {
+  if constexpr (UR_ST_NT_B) st_nt(p, v); else *p = v;
+}
 template <typename T> struct Seg { static constexpr int cols = 128 / (int)sizeof(cx<T>); };  // 16 f32, 8 f64
 
 // z pass: groups per block (each group = one complex FFT = two real pencils in r2c)
@@ -39,9 +50,11 @@ template <typename T, int N, bool C2C> struct ZCfg {
   // barrier: half-width tiles keep two blocks per CU (measured faster than
   // one block of full 128-byte rows); 4096-point columns (four wavefronts)
   // take quarter-width tiles for the same LDS budget
+  // (real FP32 columns up to 1024 points: UR_Z_PAIRS_F32 pencil pairs, tuned)
   static constexpr int want = N >= 4096 ? (C2C ? Seg<T>::cols / 4 : Seg<T>::cols / 8)
                             : N == 2048 ? (C2C ? Seg<T>::cols / 2 : Seg<T>::cols / 4)
-                                        : (C2C ? Seg<T>::cols : Seg<T>::cols / 2);
+                            : C2C       ? Seg<T>::cols
+                                        : (sizeof(T) == 4 ? UR_Z_PAIRS_F32 : Seg<T>::cols / 2);
   static constexpr int fill = 256 / G > 0 ? 256 / G : 1;
   static constexpr int ng0 = want > fill ? want : fill;
   static constexpr int cap = C2C ? N : N / 2;
@@ -66,10 +79,17 @@ template <typename T, int N> struct YICfg {
 // x pass: columns per block
 template <int N> struct XCfg {
   static constexpr int G = Geo<N>::G;
-  // 4096-point columns: two per block, so that a CU holds eight wavefronts
-  static constexpr int NG = G > 128 ? 2 : (256 / G < 64 ? 256 / G : 64);
+  // 4096-point columns: two per block, so that a CU holds eight wavefronts;
+  // one-wavefront columns (1024 points): UR_X_THREADS threads' worth (tuned);
+  // shorter columns: 256 threads' worth
+  static constexpr int T0 = G == 64 ? UR_X_THREADS : 256;
+  static constexpr int want = T0 / G > 0 ? T0 / G : 1;
+  static constexpr int NG = G > 128 ? 2 : (want < 64 ? want : 64);
   static constexpr int threads = NG * G;
 };
+// minimum resident waves per SIMD the binning x pass is compiled for (a VGPR
+// cap; 1 = none), per precision (tuned)
+template <typename T> struct XMinW { static constexpr int v = sizeof(T) == 4 ? UR_X_MINW_F32 : UR_X_MINW_F64; };
 // LDS column stride: a multiple of 32 elements plus 4, so that reading the
 // same few consecutive rows from 8 neighbouring columns (the transposed
 // write-outs) touches 32 distinct 8-byte bank pairs
@@ -729,15 +749,15 @@ k_pass_z(ZArgs a) {
       for (int m = 0; m < M; ++m, dst += (size_t)KP * N / 2) {
         const cx<T> zk = zkb[m * DK];
         const cx<T> zm = (m == 0 && kz0 == 0) ? col[0] : zmb[-m * DK];
-        st_nt2(dst, unpack(zk, zm));
+        st_a2(dst, unpack(zk, zm));
       }
       if (kz0 == 0) {                                      // kz = N/2 (self-conjugate)
         const cx<T> zh = col[pad(N / 2)];
-        st_nt2(dst, unpack(zh, zh));
+        st_a2(dst, unpack(zh, zh));
       }
     } else {
       for (int kz = kz0; kz <= N / 2; kz += KP, dst += (size_t)KP * N / 2)
-        st_nt2(dst, unpack(col[pad(kz)], col[pad((N - kz) & (N - 1))]));
+        st_a2(dst, unpack(col[pad(kz)], col[pad((N - kz) & (N - 1))]));
     }
   } else {
     const cx<T>* col = sm + j * PS;
@@ -781,8 +801,9 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t column_rsrc(const void* base, 
 // The columns are read once per pass: non-temporal cache policy (aux bit 1).
 template <typename T>
 __device__ __forceinline__ cx<T> column_ld(__amdgpu_buffer_rsrc_t rs, unsigned off) {
-  if constexpr (sizeof(T) == 4) return __builtin_bit_cast(cx<T>, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)off, 0, 2));
-  else return __builtin_bit_cast(cx<T>, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off, 0, 2));
+  constexpr int aux = UR_LD_NT ? 2 : 0;                 // non-temporal policy (tuned)
+  if constexpr (sizeof(T) == 4) return __builtin_bit_cast(cx<T>, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)off, 0, aux));
+  else return __builtin_bit_cast(cx<T>, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off, 0, aux));
 }
 
 // v[i R0 + r] = col[p] for p = g + G i + r N/R0 inside [lo, hi], zero elsewhere
@@ -892,7 +913,7 @@ k_pass_y(YArgs a) {
 #pragma unroll
       for (int k = 0; k < G / RS; ++k, dst += rstep) {
         const int off = from_stg ? k * RS * SS : t * (G + G / 16) + k * (RS + RS / 16);
-        st_nt(dst, src[off]);
+        st_b(dst, src[off]);
       }
       __syncthreads();
     });
@@ -956,7 +977,7 @@ __device__ __forceinline__ void x_load_column(const XArgs& a, long long col, int
 }
 
 template <typename T, int N, int MODE, int DIR>
-__global__ void __launch_bounds__((XCfg<N>::threads))
+__global__ void __launch_bounds__((XCfg<N>::threads), XMinW<T>::v)
 k_pass_x(XArgs a) {
   using C = XCfg<N>;
   // every wavefront reads only its own column: no bank skew between columns
@@ -1048,6 +1069,18 @@ k_pass_x(XArgs a) {
     const double wcol = SINC ? (double)St[k < 0 ? -k : k] * (double)St[l < 0 ? -l : l] : 1.0;
     const double ws = w * a.iscale * wcol, ws2 = w * a.iscale * a.iscale * wcol * wcol;
     const cx<T>* sp = s + pad(hlo);
+    // the lane's intensities first, in one batch of LDS reads: |F|^2 at +|h|
+    // and -|h| for its NH values of |h| (nothing at -0), so the walk below
+    // runs on registers
+    T qp[NH], qm[NH];
+#pragma unroll
+    for (int t = 0; t < NH; ++t) {
+      const int ha = hlo + t;
+      const cx<T> f1 = (NH <= 16 || G == 1) ? sp[t + (G == 1 ? (t >> 4) : 0)] : s[pad(ha)];
+      const cx<T> f2 = s[pad((N - ha) & (N - 1))];       // ha = 0 reads F(0) again; weighted out below
+      qp[t] = f1.x * f1.x + f1.y * f1.y;
+      qm[t] = ha != 0 ? f2.x * f2.x + f2.y * f2.y : (T)0;
+    }
     auto take = [&](int ha, T q1, T q2) {
       if constexpr (SINC) { const T sh = St[ha]; q1 *= sh; q2 *= sh; }
       const int n2 = ha * ha + base;
@@ -1068,17 +1101,7 @@ k_pass_x(XArgs a) {
       cs2 += d1 * d1 + d2 * d2;
     };
 #pragma unroll
-    for (int t = 0; t < NH; ++t) {
-      const int ha = hlo + t;
-      const cx<T> f1 = (NH <= 16 || G == 1) ? sp[t + (G == 1 ? (t >> 4) : 0)] : s[pad(ha)];
-      const T q1 = f1.x * f1.x + f1.y * f1.y;
-      T q2 = (T)0;
-      if (ha != 0) {
-        const cx<T> f2 = s[pad(N - ha)];
-        q2 = f2.x * f2.x + f2.y * f2.y;
-      }
-      take(ha, q1, q2);
-    }
+    for (int t = 0; t < NH; ++t) take(hlo + t, qp[t], qm[t]);
     if (g == G - 1) {                                      // |h| = N/2 (kx = N/2 only)
       const cx<T> f1 = s[pad(N / 2)];
       take(N / 2, f1.x * f1.x + f1.y * f1.y, (T)0);
