@@ -43,8 +43,10 @@ template <typename T> __device__ __forceinline__ void st_b(cx<T>* p, cx<T> v) {
 }
 template <typename T> struct Seg { static constexpr int cols = 128 / (int)sizeof(cx<T>); };  // 16 f32, 8 f64
 
-// z pass: groups per block (each group = one complex FFT = two real pencils in r2c)
-template <typename T, int N, bool C2C> struct ZCfg {
+// z pass: groups per block (each group = one complex FFT = two real pencils
+// in r2c); PAIRS is the pencil-pair count of real FP32 columns up to 1024
+// points (the forward pass and the inverse passes are tuned apart)
+template <typename T, int N, bool C2C, int PAIRS = UR_Z_PAIRS_F32> struct ZCfg {
   static constexpr int G = Geo<N>::G;
   // 2048-point columns span two wavefronts and sync with the workgroup
   // barrier: half-width tiles keep two blocks per CU (measured faster than
@@ -54,7 +56,7 @@ template <typename T, int N, bool C2C> struct ZCfg {
   static constexpr int want = N >= 4096 ? (C2C ? Seg<T>::cols / 4 : Seg<T>::cols / 8)
                             : N == 2048 ? (C2C ? Seg<T>::cols / 2 : Seg<T>::cols / 4)
                             : C2C       ? Seg<T>::cols
-                                        : (sizeof(T) == 4 ? UR_Z_PAIRS_F32 : Seg<T>::cols / 2);
+                                        : (sizeof(T) == 4 ? PAIRS : Seg<T>::cols / 2);
   static constexpr int fill = 256 / G > 0 ? 256 / G : 1;
   static constexpr int ng0 = want > fill ? want : fill;
   static constexpr int cap = C2C ? N : N / 2;
@@ -1544,8 +1546,8 @@ k_pass_y_inv(YInvArgs a) {
 template <typename T, int N, bool C2C>
 struct ZICfg {
   static constexpr int G = Geo<N>::G;
-  static constexpr int TY = ZCfg<T, N, C2C>::TY;
-  static constexpr int NG = ZCfg<T, N, C2C>::NG;
+  static constexpr int TY = ZCfg<T, N, C2C, UR_ZI_PAIRS_F32>::TY;
+  static constexpr int NG = ZCfg<T, N, C2C, UR_ZI_PAIRS_F32>::NG;
   static constexpr int threads = NG * G;
   static constexpr int HS = C2C ? N : N / 2 + 1;       // staged rows per pencil
 };
@@ -2508,7 +2510,16 @@ int z_tile(int prec, int n, int c2c) {
   }
 }
 #undef UR_TILE
-int zinv_tile(int prec, int n, int c2c) { return z_tile(prec, n, c2c); }
+#define UR_ZITILE(NN) { if (prec == 0) return c2c ? ZICfg<float, NN, true>::TY : ZICfg<float, NN, false>::TY; \
+                        return c2c ? ZICfg<double, NN, true>::TY : ZICfg<double, NN, false>::TY; }
+int zinv_tile(int prec, int n, int c2c) {
+  switch (n) {
+    case 16: UR_ZITILE(16) case 32: UR_ZITILE(32) case 64: UR_ZITILE(64) case 128: UR_ZITILE(128)
+    case 256: UR_ZITILE(256) case 512: UR_ZITILE(512) case 1024: UR_ZITILE(1024) case 2048: UR_ZITILE(2048)
+    default: return 0;
+  }
+}
+#undef UR_ZITILE
 
 #define UR_YT(NN) return prec == 0 ? YCfg<float, NN>::TX : YCfg<double, NN>::TX
 int y_tile(int prec, int n) {

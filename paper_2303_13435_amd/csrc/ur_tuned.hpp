@@ -23,6 +23,12 @@
 #define UR_Z_PAIRS_F32 4
 #endif
 
+// the inverse z passes of the adjoint (inverse transform, fold onto the
+// cell): pencil pairs per block of real FP32 columns up to 1024 points
+#ifndef UR_ZI_PAIRS_F32
+#define UR_ZI_PAIRS_F32 8
+#endif
+
 // streaming (non-temporal) policy: stores of the first intermediate (pass
 // Z), stores of the second (pass Y), column loads of passes Y and X
 #ifndef UR_ST_NT_A

@@ -39,7 +39,8 @@ CHOICES = {
     "UR_X_THREADS": ((256, 128, 512), (0, 3, 4, 6), ("pass_x",), ("f32",)),
     "UR_X_MINW_F32": ((1, 3, 4), (3,), ("pass_x",), ("f32",)),
     "UR_X_MINW_F64": ((1, 2), (4,), ("pass_x",), ("f64",)),
-    "UR_Z_PAIRS_F32": ((8, 4), (0, 1, 5, 6, 7, 9), ("pass_z", "pass_y"), ("f32",)),
+    "UR_Z_PAIRS_F32": ((8, 4, 2), (0, 1, 5, 6, 7, 9), ("pass_z", "pass_y"), ("f32",)),
+    "UR_ZI_PAIRS_F32": ((8, 4), (0, 5, 6), ("fwd_adjoint",), ("f32",)),
     "UR_ST_NT_A": ((1, 0), (1, 2), ("pass_z", "pass_y"), ("f32", "f64")),
     "UR_ST_NT_B": ((1, 0), (5,), ("pass_y", "pass_x"), ("f32", "f64")),
     "UR_LD_NT": ((1, 0), (3, 4, 5), ("pass_y", "pass_x"), ("f32", "f64")),
@@ -146,6 +147,24 @@ def measure(steps: int = 20) -> dict:
         out[tag] = {"step_ms": e0.elapsed_time(e1) / steps,
                     "passes": {k: v["ms"] / v["launches"] for k, v in t.items() if v["launches"]},
                     "mean": [float(x) for x in np.nan_to_num(mean, nan=-1.0)]}
+        # forward + adjoint to the 40 amplitudes (recomputing the forward
+        # passes): the inverse passes' choices are judged on it
+        g_bin = torch.where(h.count > 0, torch.ones_like(h.count), torch.zeros_like(h.count))
+        gamp = torch.empty(wl.cell.n_atoms, dtype=torch.float64, device="cuda")
+
+        def fa():
+            plan.simulate(cell, wl.mask, wl.zoom, h)
+            plan.adjoint(h, g_bin, cell=cell, mask=wl.mask, grad_amp=gamp)
+        for _ in range(2):
+            fa()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(steps // 2):
+            fa()
+        e1.record()
+        torch.cuda.synchronize()
+        out[tag]["passes"]["fwd_adjoint"] = e0.elapsed_time(e1) / (steps // 2)
+        out[tag]["grad_amp"] = [float(x) for x in gamp.cpu().numpy()]
         del plan
         torch.cuda.empty_cache()
     return out
@@ -201,6 +220,9 @@ def pick(results_path: str) -> None:
                 pos = b > 0
                 if not np.array_equal(a < 0, b < 0) or np.max(np.abs(a[pos] - b[pos]) / b[pos]) > 1e-6:
                     ok = False
+                ga, gb = np.array(res[tg].get("grad_amp", [])), np.array(ref[tg].get("grad_amp", []))
+                if ga.size and (ga.size != gb.size or np.max(np.abs(ga - gb)) > 1e-5 * np.max(np.abs(gb))):
+                    ok = False
             t = sum(res[tg]["passes"].get(ps, 0.0) for tg in precs for ps in passes)
             rows.append((m, v, res, "" if ok else "curve differs: rejected"))
             if ok and (best_t is None or t < best_t * 0.99 or (v == base[m] and t <= best_t * 1.01)):
@@ -226,17 +248,18 @@ def write_table(rows, chosen, ref) -> None:
              "a process of its own (20 steps after 3 warm-up steps, per-pass HIP events).  A value is chosen on the",
              "passes it affects; a candidate whose curve differs from the default's by more than 1e-6 is rejected;",
              "a change must win by more than 1 %.", "",
-             "| macro | value | FP32 step ms | FP32 pass Z / Y / X ms | FP64 step ms | FP64 pass Z / Y / X ms | note |",
-             "|---|---|---|---|---|---|---|"]
+             "| macro | value | FP32 step ms | FP32 pass Z / Y / X ms | FP32 fwd+adjoint ms | FP64 step ms | FP64 pass Z / Y / X ms | FP64 fwd+adjoint ms | note |",
+             "|---|---|---|---|---|---|---|---|---|"]
     for m, v, res, note in rows:
         if res is None:
-            lines.append(f"| {m} | {v} | | | | | {note} |")
+            lines.append(f"| {m} | {v} | | | | | | | {note} |")
             continue
         cells = []
         for tg in ("f32", "f64"):
             ps = res[tg]["passes"]
             cells.append(f"{res[tg]['step_ms']:.4f}")
             cells.append(" / ".join(f"{ps.get(k, 0.0):.4f}" for k in ("pass_z", "pass_y", "pass_x")))
+            cells.append(f"{ps['fwd_adjoint']:.4f}" if "fwd_adjoint" in ps else "")
         mark = "**chosen**" if chosen[m] == v else ""
         lines.append(f"| {m} | {v} | {' | '.join(cells)} | {(mark + ' ' + note).strip()} |")
     lines += ["", "Chosen: " + ", ".join(f"`{m} = {v}`" for m, v in chosen.items())]
