@@ -349,6 +349,35 @@ def c4_fwd_adjoint(ur, W, torch, steps):
             "fwd_adjoint_amp_from_held_output_ms": round(ms_keep, 4)}
 
 
+def fwd_adjoint(ur, W, torch, plan, cell, wl, hist, steps):
+    """Forward + adjoint (chi^2 gradient w.r.t. the atom amplitudes), FP32, at
+    the headline box (recomputing passes Z and Y, and from the held y-pass
+    output), then the 256^3 differentiable configuration."""
+    import numpy as np
+    out = {}
+    plan.simulate(cell, wl.mask, wl.zoom, hist)
+    d = hist.numpy()
+    g_bin = torch.as_tensor(np.where(d["count"] > 0, 1.0, 0.0), device="cuda")
+    gamp = torch.empty(wl.cell.n_atoms, dtype=torch.float64, device="cuda")
+
+    def fwd_adj():
+        plan.simulate(cell, wl.mask, wl.zoom, hist)
+        plan.adjoint(hist, g_bin, cell=cell, mask=wl.mask, grad_amp=gamp)
+
+    ms_fa, _ = time_steps(fwd_adj, max(3, steps // 2), 2, torch)
+    out["fwd_adjoint_ms"] = round(ms_fa, 4)
+
+    def fwd_adj_keep():
+        plan.simulate(cell, wl.mask, wl.zoom, hist)
+        plan.adjoint_reuse(hist, g_bin, cell, wl.mask, gamp)
+
+    ms_fk, _ = time_steps(fwd_adj_keep, max(3, steps // 2), 2, torch)
+    out["fwd_adjoint_keep_ms"] = round(ms_fk, 4)       # adjoint from the held y-pass output
+    note("fwd_adjoint_keep_ms done")
+    out["c4_fwd_adjoint"] = c4_fwd_adjoint(ur, W, torch, steps)
+    return out
+
+
 def note(msg):
     """Progress on stderr (stdout carries only the JSON line)."""
     print(f"# {msg}", file=sys.stderr, flush=True)
@@ -420,6 +449,9 @@ def main():
                     help="time only the mixed-radix boxes (1000^3, 2000^3) and print their JSON")
     ap.add_argument("--ooc4096-only", action="store_true",
                     help="only stream the 4096^3 out-of-core box and print its result (the child of the full run)")
+    ap.add_argument("--only", choices=("adjoint", "c3"),
+                    help="time only one part and print its JSON: the forward + adjoint measurements "
+                         "(1024^3 and 256^3) or the multi-zoom batch (2048^3 + 1024^3 f4 + 512^3 f16)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (reference kernel for HBM byte counters)")
     args = ap.parse_args()
@@ -455,6 +487,10 @@ def main():
         print(json.dumps(mixed_radix(ur, W, torch, max(2, args.steps // 4))))
         return
 
+    if args.only == "c3":
+        print(json.dumps(c3_batch(ur, W, torch, max(2, args.steps // 4))))
+        return
+
     n = args.n
     wl = W.m1024() if n == 1024 else W.lattice_sphere(f"S{n}", n, 16, 40, 2, 400.0 * n / 1024, 512)
     plan = ur.Plan(wl.n, wl.voxel, ur.UR_F32)
@@ -462,6 +498,9 @@ def main():
     cell = ur.DeviceCell.from_host(wl.cell)
     hist = ur.Hist(wl.nbins)
     step = lambda: plan.simulate(cell, wl.mask, wl.zoom, hist)
+    if args.only == "adjoint":
+        print(json.dumps(fwd_adjoint(ur, W, torch, plan, cell, wl, hist, args.steps)))
+        return
     ms, wall = time_steps(step, args.steps, args.warmup, torch)
     value = wl.n ** 3 / (ms * 1e-3)
     got32, got64 = hist.numpy(), None
@@ -520,29 +559,9 @@ def main():
                           "kernels": pass_timing(p64, lambda: p64.simulate(cell, wl.mask, wl.zoom, h64), args.steps, torch)}
         note("fp64 done")
         del p64
-        # forward + adjoint (chi^2 gradient w.r.t. the atom amplitudes), FP32
-        d = hist.numpy()
-        g_bin = torch.as_tensor(np.where(d["count"] > 0, 1.0, 0.0), device="cuda")
-        gamp = torch.empty(wl.cell.n_atoms, dtype=torch.float64, device="cuda")
-
-        def fwd_adj():
-            plan.simulate(cell, wl.mask, wl.zoom, hist)
-            plan.adjoint(hist, g_bin, cell=cell, mask=wl.mask, grad_amp=gamp)
-
-        ms_fa, _ = time_steps(fwd_adj, max(3, args.steps // 2), 2, torch)
-        extras["fwd_adjoint_ms"] = round(ms_fa, 4)
-
-        def fwd_adj_keep():
-            plan.simulate(cell, wl.mask, wl.zoom, hist)
-            plan.adjoint_reuse(hist, g_bin, cell, wl.mask, gamp)
-
-        ms_fk, _ = time_steps(fwd_adj_keep, max(3, args.steps // 2), 2, torch)
-        extras["fwd_adjoint_keep_ms"] = round(ms_fk, 4)       # adjoint from the held y-pass output
-        note("fwd_adjoint_keep_ms done")
-        extras["c4_fwd_adjoint"] = c4_fwd_adjoint(ur, W, torch, args.steps)
+        extras.update(fwd_adjoint(ur, W, torch, plan, cell, wl, hist, args.steps))
         note("c4 forward + adjoint done")
         torch.cuda.synchronize()
-        del fwd_adj
         # Ewald-sphere image of the same box: 1024 x 1024 pixels, 16
         # wavelength nodes (2 % spread), from the transform held in HBM
         spec = plan.fft3d(plan.rho_generate(cell, wl.mask, wl.zoom))
