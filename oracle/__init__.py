@@ -21,6 +21,8 @@ correct statement of the computation, written from the paper:
   reading in ``ewald_image``)
 * O17 peak integrals for the degree of crystallinity (Results and
   Discussion; reading in ``peak_integrals``)
+* O18 block transfer of a zoom level and its removal from the level's
+  intensities (high-Q correction of coarse levels; reading in ``block_transfer``)
 
 The heavy loops live in ``ur_oracle.c`` (plain C, FP64, OpenMP over
 independent lines); this module marshals numpy arrays and holds the small
@@ -332,14 +334,43 @@ def voxel_form(n: int) -> np.ndarray:
     return s1[:, None, None] * s1[None, :, None] * s1[None, None, :]
 
 
-def simulate(wl, return_fields: bool = False, voxel_form_factor: bool = False):
+def block_transfer(n: int, f: int) -> np.ndarray:
+    """O18: amplitude transfer of the block sum that makes a zoom level.
+
+    A level's voxel X holds the sum of the f^3 fine voxels f X + j (j in
+    [0, f)^3, step 3 of the workflow), so along one axis its absolute
+    amplitude at coarse index m is sum_s T(m - s n) A1(m - s n) over the f
+    aliases s, with A1 the fine box's amplitude on the f n grid and
+        T(m) = (1/f) sum_{j<f} exp(+2 pi i m j / (f n)),
+    written here as that sum (the identity is pinned against transforms of
+    a box and of its block sums).  Returns T(h) T(k) T(l) on the level's
+    [u][v][w] grid, signed indices.  Dividing a level's amplitudes by it
+    undoes the attenuation of the block sum (|T|^2 = 0.81 per axis at half
+    the level's Nyquist index, for large f); aliased fine frequencies are
+    not removed.  Reading: the paper names the correction of coarse levels
+    near their cut-off without a formula; this is the exact transfer of its
+    own block integration, applied to the intensities before binning."""
+    u = np.arange(n)
+    h = np.where(u < n // 2, u, u - n).astype(np.float64)
+    j = np.arange(f, dtype=np.float64)
+    t1 = np.exp(2j * np.pi * np.outer(h, j) / (f * n)).sum(axis=1) / f
+    return t1[:, None, None] * t1[None, :, None] * t1[None, None, :]
+
+
+def simulate(wl, return_fields: bool = False, voxel_form_factor: bool = False,
+             block_transfer_removed: bool = False):
     """Whole forward path of one box: density -> eq. 1 -> per-bin statistics
-    (of the voxel-uniform density's intensities with voxel_form_factor).
-    Also reports the density moments sum(rho) and sum(rho^2)."""
+    (of the voxel-uniform density's intensities with voxel_form_factor; of
+    intensities divided by the level's block transfer |T|^2 (O18) with
+    block_transfer_removed, for a zoom level).  Also reports the density
+    moments sum(rho) and sum(rho^2)."""
     cg = cell_synth(wl.cell)
     rho = density(wl, cg)
     F = forward(rho)
-    res = bin_spectrum(F * voxel_form(wl.n) if voxel_form_factor else F, wl.voxel, wl.edges)
+    G = F * voxel_form(wl.n) if voxel_form_factor else F
+    if block_transfer_removed and wl.zoom.factor > 1:
+        G = G / block_transfer(wl.n, wl.zoom.factor)
+    res = bin_spectrum(G, wl.voxel, wl.edges)
     res["rho_sum"] = float(rho.sum(dtype=np.float64))
     res["rho_sumsq"] = float(np.sum(rho * rho))
     if return_fields:

@@ -816,6 +816,53 @@ def test_peak_integrals_closed_forms(oracle_lib):
 # O15: voxel form factor (a density uniform over each voxel)
 # ---------------------------------------------------------------------------
 
+@pytest.mark.parametrize("f", [2, 4])
+def test_block_transfer_is_the_ratio_of_level_to_fine_amplitudes(oracle_lib, f):
+    """O18 pinned by transforms: for a fine density whose spectrum lies
+    inside the level's band (|u| < n_k/2 on every axis, so no alias reaches
+    the level's grid), the level made of block sums has amplitude
+    T(m) A1(m) at every shared frequency and zero at the level's Nyquist
+    index. A1 and the level's amplitude are numpy transforms of the box and
+    of its block sums; T is the oracle's sum."""
+    n1 = 32
+    nk = n1 // f
+    rng = np.random.default_rng(18 + f)
+    A = np.zeros((n1, n1, n1), dtype=complex)
+    band = [u % n1 for u in range(-(nk // 2) + 1, nk // 2)]
+    for u in band:
+        for v in band:
+            for w in band:
+                A[u, v, w] = rng.normal() + 1j * rng.normal()
+    rho1 = np.real(np.fft.ifftn(A))
+    a1 = np.fft.fftn(rho1)
+    level = rho1.reshape(nk, f, nk, f, nk, f).sum(axis=(1, 3, 5))
+    ak = np.fft.fftn(level)
+    T = oracle_lib.block_transfer(nk, f)
+    scale = np.abs(a1).max()
+    idx = [m % nk for m in range(-(nk // 2) + 1, nk // 2)]
+    for u in idx:
+        for v in idx:
+            for w in idx:
+                uf, vf, wf = [(m if m < nk // 2 else m - nk) % n1 for m in (u, v, w)]
+                assert abs(ak[u, v, w] - T[u, v, w] * a1[uf, vf, wf]) <= 1e-12 * scale
+    assert np.abs(ak[nk // 2, :, :]).max() <= 1e-12 * scale
+    # the level keeps the electrons: T(0) = 1
+    assert abs(T[0, 0, 0] - 1.0) < 1e-15 and abs(ak[0, 0, 0] - a1[0, 0, 0]) <= 1e-12 * scale
+
+
+@pytest.mark.parametrize("n, f", [(16, 2), (16, 4), (64, 16), (250, 5)])
+def test_block_transfer_power_is_the_dirichlet_kernel(oracle_lib, n, f):
+    """|T(m)|^2 per axis against the closed form of a sum of f unit phasors,
+    sin^2(pi m / n) / (f sin(pi m / (f n)))^2, and 0.81 at half the Nyquist
+    index for large f."""
+    T = oracle_lib.block_transfer(n, f)
+    for m in range(1, n // 2 + 1):
+        ref = (math.sin(math.pi * m / n) / (f * math.sin(math.pi * m / (f * n)))) ** 2
+        assert abs(abs(T[m, 0, 0]) ** 2 - ref) <= 1e-13
+    big = oracle_lib.block_transfer(64, 125)
+    assert abs(abs(big[16, 0, 0]) ** 2 - 8.0 / math.pi ** 2) < 1e-4      # (sin(pi/4) / (pi/4))^2
+
+
 @pytest.mark.parametrize("n,hw", [(32, 5), (32, 10), (16, 7)])
 def test_voxel_form_of_a_cube_is_the_continuous_cube(oracle_lib, n, hw):
     """A cube of W = 2 hw + 1 voxels, each voxel uniform, is the continuous
