@@ -7,7 +7,8 @@ correct statement of the computation, written from the paper:
 * O1  unit-cell density (workflow step 1; "Electron density generation")
 * O2  ED-1 = tiled cell x particle mask (workflow step 2); O2r with a rotated lattice
   (trilinear or cubic B-spline sampling of the cell); O2g polycrystalline grains
-* O3  zoomed-out ED-2/ED-3 by block integration and zero padding (step 3)
+* O3  zoomed-out ED-2/ED-3 by block integration and zero padding (step 3),
+  also of rotated and polycrystalline ED-1 boxes
 * O4  3D transform, eq. 1 (axis by axis, as eq. 2 separates it)
 * O5-O8  |Q| map, integer-threshold bins, per-bin mean and SEM (step 5)
 * O9  merge of zoom levels into one curve (step 6; reading in ``merge``)
@@ -242,18 +243,34 @@ def zoomed(n1: int, cell_grid: np.ndarray, mask, f: int, nk: int) -> np.ndarray:
     return out
 
 
+def block_level(rho1: np.ndarray, f: int, nk: int) -> np.ndarray:
+    """O3 from a given ED-1 box (workflow step 3): block sums of f^3 fine
+    voxels, the reduced region centred in an nk^3 box at offset
+    o = (nk - n1/f)/2, zero elsewhere."""
+    n1 = rho1.shape[0]
+    m = n1 // f
+    assert m * f == n1 and m <= nk
+    red = rho1.reshape(m, f, m, f, m, f).sum(axis=(1, 3, 5))
+    out = np.zeros((nk, nk, nk))
+    o = (nk - m) // 2
+    out[o:o + m, o:o + m, o:o + m] = red
+    return out
+
+
 def density(wl, cell_grid: Optional[np.ndarray] = None) -> np.ndarray:
-    """Real-space box of a workload: ED-1 (factor 1) or a zoomed level."""
+    """Real-space box of a workload: ED-1 (factor 1) or a zoomed level; a
+    zoom level of a rotated or polycrystalline lattice is the block sum of
+    that lattice's ED-1 (O2r / O2g, then O3)."""
     if cell_grid is None:
         cell_grid = cell_synth(wl.cell)
     seeds = getattr(wl.cell, "grain_seed", None)
     if seeds is not None:
-        assert wl.zoom.factor == 1 and wl.zoom.n1 == wl.n, "grains are defined for ED-1"
-        return ed1_grains(wl.n, cell_grid, wl.mask, seeds, wl.cell.grain_rot, int(getattr(wl.cell, "interp", 1)))
+        rho1 = ed1_grains(wl.zoom.n1, cell_grid, wl.mask, seeds, wl.cell.grain_rot, int(getattr(wl.cell, "interp", 1)))
+        return rho1 if wl.zoom.factor == 1 and wl.zoom.n1 == wl.n else block_level(rho1, wl.zoom.factor, wl.n)
     rot = getattr(wl.cell, "rot", None)
     if rot is not None:
-        assert wl.zoom.factor == 1 and wl.zoom.n1 == wl.n, "rotated lattices are defined for ED-1"
-        return ed1_rot(wl.n, cell_grid, wl.mask, rot, int(getattr(wl.cell, "interp", 1)))
+        rho1 = ed1_rot(wl.zoom.n1, cell_grid, wl.mask, rot, int(getattr(wl.cell, "interp", 1)))
+        return rho1 if wl.zoom.factor == 1 and wl.zoom.n1 == wl.n else block_level(rho1, wl.zoom.factor, wl.n)
     if wl.zoom.factor == 1 and wl.zoom.n1 == wl.n:
         return ed1(wl.n, cell_grid, wl.mask)
     return zoomed(wl.zoom.n1, cell_grid, wl.mask, wl.zoom.factor, wl.n)

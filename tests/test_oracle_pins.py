@@ -231,6 +231,32 @@ def test_zoom_block_sum(oracle_lib):
     assert abs(rk.sum() - rho1.sum()) < 1e-10 * abs(rho1.sum())
 
 
+@pytest.mark.parametrize("f", [2, 4])
+def test_zoom_levels_of_rotated_lattices(oracle_lib, f):
+    """O3 of an oriented ED-1: with the identity orientation the level equals
+    the aligned level of the C route (block sums evaluated per level voxel);
+    for a general orientation, cubic sampling and grains the level keeps the
+    electrons of its ED-1 and is zero outside the reduced region."""
+    from dataclasses import replace
+    n1, nk, c = 32, 16, 8
+    base = W.zoom_levels(n1, c, 6, 9, 11.0, [(nk, f)], 16)[0]
+    g = oracle_lib.cell_synth(base.cell)
+    ident = replace(base, cell=base.cell.with_rot(np.eye(3), 1))
+    assert np.max(np.abs(oracle_lib.density(ident, g) - oracle_lib.zoomed(n1, g, base.mask, f, nk))) < 1e-12
+    m, o = n1 // f, (nk - n1 // f) // 2
+    R = W.rotation([1.0, 2.0, 3.0], 0.7)
+    seeds, rots = W.random_grains(5, 4, 0.3 * n1)
+    for cell, rho1 in ((base.cell.with_rot(R, 1), oracle_lib.ed1_rot(n1, g, base.mask, R, 1)),
+                       (base.cell.with_rot(R, 3), oracle_lib.ed1_rot(n1, g, base.mask, R, 3)),
+                       (base.cell.with_grains(seeds, rots, 1), oracle_lib.ed1_grains(n1, g, base.mask, seeds, rots, 1))):
+        lvl = oracle_lib.density(replace(base, cell=cell), g)
+        assert abs(lvl.sum() - rho1.sum()) <= 1e-10 * abs(rho1.sum())
+        inner = np.zeros_like(lvl, dtype=bool)
+        inner[o:o + m, o:o + m, o:o + m] = True
+        assert np.all(lvl[~inner] == 0.0)
+        assert abs(lvl[o, o, o] - rho1[:f, :f, :f].sum()) <= 1e-12 * max(1.0, abs(rho1).max())
+
+
 # ---------------------------------------------------------------------------
 # O5-O8  binning
 # ---------------------------------------------------------------------------
