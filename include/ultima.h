@@ -187,8 +187,9 @@ ur_status ur_cell_synth(ur_plan* plan, const ur_cell* cell, double* cell_out, vo
 /* Materialise planes x_lo..x_hi of the ED of this plan's box (tiled cell x
  * mask, optionally zoomed; section "Electron density generation") as
  * (x_hi - x_lo + 1) n^2 reals of the plan precision at `rho` (DEVICE,
- * [x - x_lo][y][z]); [0, n - 1] gives the whole box.  UR_ERR_INVALID for a
- * range outside [0, n - 1]. */
+ * [x - x_lo][y][z]); [0, n - 1] gives the whole box; zoom levels of oriented
+ * lattices as block sums of the oriented ED-1 (boxes up to 2048^3).
+ * UR_ERR_INVALID for a range outside [0, n - 1]. */
 ur_status ur_rho_generate(ur_plan* plan, const ur_cell* cell, const ur_mask* mask,
                           const ur_zoom* zoom, int32_t x_lo, int32_t x_hi, void* rho, void* stream);
 
@@ -214,8 +215,12 @@ ur_status ur_intensity_bin(ur_plan* plan, const void* spectrum, const ur_hist* h
  * (section "Q-calculation and spherical averaging"); planes, pencils and
  * rows that lie outside the particle are skipped (the paper's skipping of
  * slices without density, extended to rows and pencils).  The cell is
- * synthesised on the device from its atoms in the same call.  Outputs as for
- * ur_hist. */
+ * synthesised on the device from its atoms in the same call.  A zoom level
+ * (factor > 1) of an oriented lattice (rot or grains) is the block sum of the
+ * oriented ED-1 (workflow step 3 on the rotated-plane density): its density
+ * is generated first into an n^3 buffer the plan allocates at the first such
+ * call (outside any attached workspace; boxes up to 2048^3), then
+ * transformed and binned.  Outputs as for ur_hist. */
 ur_status ur_simulate(ur_plan* plan, const ur_cell* cell, const ur_mask* mask,
                       const ur_zoom* zoom, const ur_hist* hist, void* stream);
 
@@ -288,6 +293,24 @@ ur_status ur_plan_workspace_size_host(const ur_plan* plan, int32_t nbins, int32_
  * a small table (call before capture); enable = 0 frees it.  The adjoint
  * refuses plans with the factor on (UR_ERR_UNSUPPORTED). */
 ur_status ur_plan_set_voxel_form(ur_plan* plan, int32_t enable);
+
+/* Block-transfer correction of a zoom level (Q-calculation and spherical
+ * averaging: corrections of the coarse levels near their cut-off before the
+ * merge; workflow step 3 makes a level by block integration).  A level
+ * voxel sums f^3 fine voxels, which multiplies the amplitude at level index
+ * m by T(m) = (1/f) sum_{j<f} exp(2 pi i m j / (f n)) per axis (fine
+ * frequencies beyond the level's band alias onto it as well).  With
+ * factor f >= 2 every binned intensity of this plan is divided by it:
+ *     I'(h, k, l) = I(h, k, l) W(h) W(k) W(l),
+ *     W(m) = (f sin(pi m / (f n)) / sin(pi m / n))^2,  W(0) = 1,
+ * for the fused forward paths and ur_intensity_bin (totals[0] then sums
+ * I'), times the voxel form factor when that is on too.  ur_simulate and
+ * ur_simulate_noalloc then take only levels whose zoom factor is f
+ * (UR_ERR_INVALID otherwise).  factor 0 or 1 turns it off.  Allocates a
+ * small table (call before capture; UR_ERR_STATE while the plan is bound to
+ * a live graph).  Mixed-radix plans and the adjoint refuse it
+ * (UR_ERR_UNSUPPORTED). */
+ur_status ur_plan_set_block_transfer(ur_plan* plan, int32_t factor);
 
 /* Limit the out-of-core workspace to `bytes` (0: no limit).  When the x
  * range of the spectrum does not fit, ur_simulate_host runs the second stage

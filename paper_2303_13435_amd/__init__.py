@@ -72,6 +72,7 @@ _SIGS = {
     "ur_plan_set_workspace": [_vp, _vp, _c.c_size_t],
     "ur_plan_set_hbm_budget": [_vp, _c.c_size_t],
     "ur_plan_set_voxel_form": [_vp, _c.c_int32],
+    "ur_plan_set_block_transfer": [_vp, _c.c_int32],
     "ur_plan_set_bins": [_vp, _c.c_int32, _c.POINTER(_c.c_double)],
     "ur_cell_synth": [_vp, _c.POINTER(UrCell), _vp, _vp],
     "ur_rho_generate": [_vp, _c.POINTER(UrCell), _c.POINTER(UrMask), _c.POINTER(UrZoom), _c.c_int32, _c.c_int32,
@@ -358,6 +359,12 @@ class Plan:
         """Weight binned intensities by the voxel form factor
         S(h) S(k) S(l), S(m) = sinc^2(pi m / n) (ur_plan_set_voxel_form)."""
         _check(lib().ur_plan_set_voxel_form(self.h, int(bool(enable))), "ur_plan_set_voxel_form")
+
+    def set_block_transfer(self, factor: int) -> None:
+        """Divide every binned intensity by the block transfer of a zoom
+        level made by block sums of `factor` (0 or 1: off)
+        (ur_plan_set_block_transfer)."""
+        _check(lib().ur_plan_set_block_transfer(self.h, int(factor)), "ur_plan_set_block_transfer")
 
     def set_hbm_budget(self, nbytes: int) -> None:
         """Out-of-core workspace limit in bytes (0: none); above it the path

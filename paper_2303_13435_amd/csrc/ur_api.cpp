@@ -88,6 +88,8 @@ struct ur_plan {
   // cell scratch (library owned, grown on demand)
   char* cs_buf = nullptr;
   size_t cs_bytes = 0;
+  char* lvl_buf = nullptr;   // density of a zoom level of an oriented lattice (n^3 reals), owned
+  size_t lvl_bytes = 0;
 
   // out-of-core staging: kStage slab buffers on the device, each filled on
   // its own copy stream (several host-to-device copies in flight keep PCIe
@@ -100,7 +102,10 @@ struct ur_plan {
   void* bounce = nullptr;    // pinned host memory
   size_t bounce_bytes = 0;
   size_t hbm_budget = 0;     // out-of-core workspace bytes allowed (0: no limit)
-  void* dSinc = nullptr;     // voxel form factor table S(m), m in [0, n/2], or null when off
+  void* dSinc = nullptr;     // per-axis intensity weight W(m), m in [0, n/2], or null when off:
+                             // the voxel form factor S(m) and/or the removed block transfer 1/|T(m)|^2
+  bool vox = false;          // voxel form factor on
+  int bt_f = 0;              // block-sum factor whose transfer is removed (0: none)
 
   // live HIP graphs recorded from this plan's calls (ur_graph_begin/end):
   // they hold raw pointers into the workspace and tables, so nothing may be
@@ -305,6 +310,23 @@ static ur_status ensure_cell_scratch(ur_plan* p, size_t need, hipStream_t s) {
   return UR_OK;
 }
 
+// the density buffer of oriented zoom levels: the library's own, not the
+// attached workspace (whose size query covers the transform passes only)
+static ur_status ensure_level_buf(ur_plan* p, size_t need, hipStream_t s) {
+  if (p->lvl_buf && p->lvl_bytes >= need) return UR_OK;
+  if (graph_bound(p)) return refuse_bound(p, "level density reallocation");
+  hipStreamCaptureStatus cst = hipStreamCaptureStatusNone;
+  if (s) (void)hipStreamIsCapturing(s, &cst);
+  if (cst != hipStreamCaptureStatusNone)
+    return fail(UR_ERR_STATE, "the level density buffer must be allocated (first call) before graph capture");
+  if (p->lvl_buf) { UR_HIP(hipDeviceSynchronize()); UR_HIP(hipFree(p->lvl_buf)); p->lvl_buf = nullptr; p->lvl_bytes = 0; }
+  void* ptr = nullptr;
+  if (hipMalloc(&ptr, need) != hipSuccess) { (void)hipGetLastError(); return fail(UR_ERR_OOM, "hipMalloc(%zu) failed", need); }
+  p->lvl_buf = (char*)ptr;
+  p->lvl_bytes = need;
+  return UR_OK;
+}
+
 // per-stage twiddle tables exp(-2 pi i r j / (L R)), evaluated in long double
 // and rounded once to the working precision
 static ur_status make_twiddles(ur_plan* p) {
@@ -463,6 +485,7 @@ void ur_plan_destroy(ur_plan* p) {
   if (p->dCountTmp) (void)hipFree(p->dCountTmp);
   if (p->ws && p->ws_owned) (void)hipFree(p->ws);
   if (p->cs_buf) (void)hipFree(p->cs_buf);
+  if (p->lvl_buf) (void)hipFree(p->lvl_buf);
   if (p->stage) (void)hipFree(p->stage);
   if (p->bounce) (void)hipHostFree(p->bounce);
   for (auto& e : p->ev_copied) if (e) (void)hipEventDestroy(e);
@@ -491,35 +514,70 @@ ur_status ur_plan_workspace_size_host(const ur_plan* p, int32_t nbins, int32_t x
   return UR_OK;
 }
 
-ur_status ur_plan_set_voxel_form(ur_plan* p, int32_t enable) {
-  if (!p) return fail(UR_ERR_INVALID, "plan is null");
-  if (graph_bound(p) && ((enable != 0) != (p->dSinc != nullptr))) return refuse_bound(p, "ur_plan_set_voxel_form");
-  if (!enable) {
-    if (p->dSinc) { UR_HIP(hipDeviceSynchronize()); UR_HIP(hipFree(p->dSinc)); p->dSinc = nullptr; }
-    return UR_OK;
-  }
-  if (p->dSinc) return UR_OK;
-  // S(m) = (sin(pi m / n) / (pi m / n))^2, evaluated in long double and
-  // rounded once to the working precision
-  const long double PI = 3.14159265358979323846264338327950288L;
-  const int h = p->n / 2;
+// Per-axis weight table of the binned intensities, W(m) for m in [0, n/2]
+// (signed index |m|), the product of the factors that are on:
+//  * voxel form factor: S(m) = (sin(pi m / n) / (pi m / n))^2;
+//  * removed block transfer of a zoom level made by block sums of f:
+//    1/|T(m)|^2 = (f sin(pi m / (f n)) / sin(pi m / n))^2, the inverse of the
+//    power of (1/f) sum_{j<f} exp(2 pi i m j / (f n)) (a sum of f phasors).
+// Evaluated in long double and rounded once to the working precision.
+static ur_status rebuild_weights(ur_plan* p, bool vox, int bt_f) {
+  const bool on = vox || bt_f > 1;
+  const bool same = on == (p->dSinc != nullptr) && (!on || (vox == p->vox && bt_f == p->bt_f));
+  if (same) return UR_OK;
+  if (graph_bound(p)) return refuse_bound(p, "a change of the intensity weights (voxel form factor, block transfer)");
   std::vector<double> v64;
   std::vector<float> v32;
-  try {
-    v64.resize(h + 1);
-    for (int m = 0; m <= h; ++m) {
-      const long double x = PI * (long double)m / (long double)p->n;
-      const long double sc = m == 0 ? 1.0L : sinl(x) / x;
-      v64[m] = (double)(sc * sc);
+  const int h = p->n / 2;
+  if (on) {
+    const long double PI = 3.14159265358979323846264338327950288L;
+    try {
+      v64.resize(h + 1);
+      for (int m = 0; m <= h; ++m) {
+        long double w = 1.0L;
+        if (m > 0) {
+          const long double x = PI * (long double)m / (long double)p->n;
+          if (vox) { const long double sc = sinl(x) / x; w *= sc * sc; }
+          if (bt_f > 1) {
+            const long double r = (long double)bt_f * sinl(x / (long double)bt_f) / sinl(x);
+            w *= r * r;
+          }
+        }
+        v64[m] = (double)w;
+      }
+      if (p->prec == UR_F32) v32.assign(v64.begin(), v64.end());
+    } catch (...) {
+      return fail(UR_ERR_OOM, "host allocation failed for the intensity weight table");
     }
-    if (p->prec == UR_F32) v32.assign(v64.begin(), v64.end());
-  } catch (...) {
-    return fail(UR_ERR_OOM, "host allocation failed for the voxel form factor table");
   }
+  if (p->dSinc) { UR_HIP(hipDeviceSynchronize()); UR_HIP(hipFree(p->dSinc)); p->dSinc = nullptr; }
+  p->vox = vox;
+  p->bt_f = bt_f > 1 ? bt_f : 0;
+  if (!on) return UR_OK;
   const size_t bytes = (size_t)(h + 1) * p->rs;
   UR_HIP(hipMalloc(&p->dSinc, bytes));
   UR_HIP(hipMemcpy(p->dSinc, p->prec == UR_F32 ? (const void*)v32.data() : (const void*)v64.data(), bytes,
                    hipMemcpyHostToDevice));
+  return UR_OK;
+}
+
+ur_status ur_plan_set_voxel_form(ur_plan* p, int32_t enable) {
+  if (!p) return fail(UR_ERR_INVALID, "plan is null");
+  return rebuild_weights(p, enable != 0, p->bt_f);
+}
+
+ur_status ur_plan_set_block_transfer(ur_plan* p, int32_t factor) {
+  if (!p) return fail(UR_ERR_INVALID, "plan is null");
+  if (factor < 0) return fail(UR_ERR_INVALID, "block factor %d is negative", factor);
+  if (p->mixed && factor > 1) return fail(UR_ERR_UNSUPPORTED, "mixed-radix boxes run without the block-transfer correction");
+  return rebuild_weights(p, p->vox, factor);
+}
+
+// a plan that removes the block transfer of factor f bins only levels made
+// with that factor
+static ur_status check_block_transfer(const ur_plan* p, const ur_zoom* z) {
+  if (p->bt_f > 1 && z->factor != p->bt_f)
+    return fail(UR_ERR_INVALID, "the plan removes the block transfer of factor %d, the level has factor %d", p->bt_f, z->factor);
   return UR_OK;
 }
 
@@ -674,9 +732,13 @@ static bool oriented(const ur_cell* c) { return c->rot || c->n_grains > 0; }
 
 // A rotated lattice runs the ED-1 generator of real plans only; copies its
 // matrix into the z-pass arguments.
-static ur_status set_rotation(const ur_plan* p, const ur_cell* cell, const ur_zoom* zoom, ZArgs& za) {
+// zoom levels of oriented lattices are generated as a density first
+// (ur_simulate, ur_rho_generate: allow_zoom), the other entries take ED-1
+static ur_status set_rotation(const ur_plan* p, const ur_cell* cell, const ur_zoom* zoom, ZArgs& za,
+                              bool allow_zoom = false) {
   if (!oriented(cell)) return UR_OK;
-  if (zoom->factor != 1) return fail(UR_ERR_UNSUPPORTED, "rotated lattices run at zoom factor 1");
+  if (zoom->factor != 1 && !allow_zoom)
+    return fail(UR_ERR_UNSUPPORTED, "this entry runs rotated lattices at zoom factor 1");
   if (p->flags & UR_C2C) return fail(UR_ERR_UNSUPPORTED, "rotated lattices run on real (UR_R2C) plans");
   za.rotated = 1;
   za.cubic = cell->interp == 3 ? 1 : 0;
@@ -935,7 +997,9 @@ ur_status ur_rho_generate(ur_plan* p, const ur_cell* cell, const ur_mask* mask, 
   UR_TRY(prepare_cell(p, cell, zoom->factor, t, s));
   ZArgs za{};
   za.cellT = t.cellT; za.cb = t.cb; za.pre = t.pre; za.L = L; za.m = m; za.cbn = t.cbn;
-  UR_TRY(set_rotation(p, cell, zoom, za));
+  UR_TRY(set_rotation(p, cell, zoom, za, true));
+  if (za.rotated && zoom->factor > 1 && p->n > kZoomRotMaxBox)
+    return fail(UR_ERR_UNSUPPORTED, "zoom levels of rotated lattices run in boxes up to %d", kZoomRotMaxBox);
   UR_HIP(launch_rho_generate(p->prec, p->n, x_lo, x_hi, za, rho, s));
   return UR_OK;
 }
@@ -943,6 +1007,7 @@ ur_status ur_rho_generate(ur_plan* p, const ur_cell* cell, const ur_mask* mask, 
 }  // extern "C"
 static ur_status simulate_pow2(ur_plan* p, const ur_cell* cell, const ur_zoom* zoom, const ur_hist* h, hipStream_t s,
                                FwdGeom g, const ZArgs& rot_args, const CellTables& t, const Layout& lay, char* ws);
+static ur_status simulate_rho_pow2(ur_plan* p, const void* rho, const ur_hist* h, const Layout& lay, hipStream_t s);
 extern "C" {
 
 ur_status ur_simulate(ur_plan* p, const ur_cell* cell, const ur_mask* mask, const ur_zoom* zoom, const ur_hist* h, void* stream) {
@@ -954,12 +1019,13 @@ ur_status ur_simulate(ur_plan* p, const ur_cell* cell, const ur_mask* mask, cons
   UR_TRY(check_cell(cell, p->mixed));
   FwdGeom g;
   UR_TRY(check_level(p, cell, mask, zoom, g.L, g.m));
+  UR_TRY(check_block_transfer(p, zoom));
   ZArgs rot_args{};
-  UR_TRY(set_rotation(p, cell, zoom, rot_args));
+  UR_TRY(set_rotation(p, cell, zoom, rot_args, !p->mixed));
   hipStream_t s = (hipStream_t)stream;
   note_stream(p, s);
   if (p->mixed) {
-    if (p->dSinc) return fail(UR_ERR_UNSUPPORTED, "mixed-radix boxes run without the voxel form factor");
+    if (p->dSinc) return fail(UR_ERR_UNSUPPORTED, "mixed-radix boxes run without the voxel form factor and block-transfer correction");
     Layout lay = layout_mixed(p, p->nbins);
     UR_TRY(ensure_ws(p, lay.total, s));
     CellTables t;
@@ -985,6 +1051,29 @@ ur_status ur_simulate(ur_plan* p, const ur_cell* cell, const ur_mask* mask, cons
     return mr_finalize(p, lay, mr_axis_blocks(p->prec, p->n, 0, MR_BIN), h, mr_axis_blocks(p->prec, p->n, 2, MR_GEN), s);
   }
   Layout lay = layout_incore(p, p->nbins);
+  if (rot_args.rotated && zoom->factor > 1) {
+    // zoom level of an oriented lattice: the level's density (block sums of
+    // the oriented ED-1) is generated into the plan's level buffer first,
+    // then transformed and binned as a given density
+    if (p->n > kZoomRotMaxBox)
+      return fail(UR_ERR_UNSUPPORTED, "zoom levels of rotated lattices run in boxes up to %d", kZoomRotMaxBox);
+    UR_TRY(ensure_ws(p, lay.total, s));
+    UR_TRY(ensure_level_buf(p, (size_t)p->n * p->n * p->n * p->rs, s));
+    CellTables t;
+    ZArgs za = rot_args;
+    {
+      PassTimer tm(p, P_CELL, s);
+      UR_TRY(prepare_cell(p, cell, 1, t, s));
+      za.cellT = t.cellT; za.cb = t.cb; za.pre = t.pre; za.L = g.L; za.m = g.m; za.cbn = t.cbn;
+      UR_HIP(launch_rho_generate(p->prec, p->n, 0, p->n - 1, za, p->lvl_buf, s));
+    }
+    {
+      const double c = cell->c;
+      p->pass_bytes[P_CELL] = 8.0 * (3.0 * c * cell->n_atoms) * 2.0 + c * c * c * (16.0 + p->rs) +
+                              (double)p->n * p->n * p->n * p->rs;
+    }
+    return simulate_rho_pow2(p, p->lvl_buf, h, lay, s);
+  }
   UR_TRY(ensure_ws(p, lay.total, s));
   CellTables t;
   {
@@ -1045,6 +1134,7 @@ ur_status ur_simulate_noalloc(ur_plan* p, const ur_cell* cell, const ur_mask* ma
   UR_TRY(check_cell(cell));
   FwdGeom g;
   UR_TRY(check_level(p, cell, mask, zoom, g.L, g.m));
+  UR_TRY(check_block_transfer(p, zoom));
   ZArgs rot_args{};
   UR_TRY(set_rotation(p, cell, zoom, rot_args));
   const Layout lay = layout_incore(p, p->nbins);
@@ -1078,7 +1168,7 @@ ur_status ur_simulate_rho(ur_plan* p, const void* rho, const ur_hist* h, void* s
   hipStream_t s = (hipStream_t)stream;
   note_stream(p, s);
   if (p->mixed) {
-    if (p->dSinc) return fail(UR_ERR_UNSUPPORTED, "mixed-radix boxes run without the voxel form factor");
+    if (p->dSinc) return fail(UR_ERR_UNSUPPORTED, "mixed-radix boxes run without the voxel form factor and block-transfer correction");
     Layout lay = layout_mixed(p, p->nbins);
     UR_TRY(ensure_ws(p, lay.total, s));
     UR_TRY(mr_transform(p, rho, p->ws + lay.A, -1, (double*)(p->ws + lay.mom), nullptr, &lay, s));
@@ -1086,6 +1176,15 @@ ur_status ur_simulate_rho(ur_plan* p, const void* rho, const ur_hist* h, void* s
   }
   Layout lay = layout_incore(p, p->nbins);
   UR_TRY(ensure_ws(p, lay.total, s));
+  p->pass_bytes[P_CELL] = 0.0;
+  return simulate_rho_pow2(p, rho, h, lay, s);
+}
+
+}  // extern "C"
+
+// passes Z (from a given real or complex density), Y, X and the finalize of
+// a power-of-two box; the workspace holds at least `lay`
+static ur_status simulate_rho_pow2(ur_plan* p, const void* rho, const ur_hist* h, const Layout& lay, hipStream_t s) {
   FwdGeom g{};
   g.xlo = 0; g.xhi = p->n - 1; g.ax0 = 0; g.gen = 0;
   g.L = make_level(p->n, p->n, 1, 1);
@@ -1097,11 +1196,12 @@ ur_status ur_simulate_rho(ur_plan* p, const void* rho, const ur_hist* h, void* s
     PassTimer tm(p, P_Z, s);
     UR_HIP(launch_pass_z(p->prec, p->n, (p->flags & UR_C2C) ? Z_LOAD_C2C : Z_LOAD_R2C, za, nzb, s));
   }
-  p->pass_bytes[P_CELL] = 0.0;
   p->pass_bytes[P_Z] = (double)p->n * p->n * p->n * ((p->flags & UR_C2C) ? p->cs : p->rs) +
                        (double)p->n * p->nkz * p->n * p->cs + 16.0 * nzb;
   return run_y_x(p, g, p->ws + lay.A, p->ws + lay.B, lay, h, nzb, s, p->ws);
 }
+
+extern "C" {
 
 ur_status ur_fft3d_exec(ur_plan* p, const void* in, void* out, int32_t dir, void* stream) {
   if (p) p->keep_valid = false;
@@ -1156,7 +1256,7 @@ ur_status ur_intensity_bin(ur_plan* p, const void* spectrum, const ur_hist* h, v
   hipStream_t s = (hipStream_t)stream;
   note_stream(p, s);
   if (p->mixed) {
-    if (p->dSinc) return fail(UR_ERR_UNSUPPORTED, "mixed-radix boxes run without the voxel form factor");
+    if (p->dSinc) return fail(UR_ERR_UNSUPPORTED, "mixed-radix boxes run without the voxel form factor and block-transfer correction");
     Layout lay = layout_mixed(p, p->nbins);
     UR_TRY(ensure_ws(p, lay.total, s));
     return mr_bin(p, spectrum, lay, h, s);
@@ -1355,7 +1455,7 @@ static ur_status adjoint_run(ur_plan* p, const void* rho, const ur_cell* cell, c
   if ((rho != nullptr) == (cell != nullptr)) return fail(UR_ERR_INVALID, "give exactly one of rho and cell");
   if (grad_amp && !cell) return fail(UR_ERR_INVALID, "grad_amp needs the cell description");
   if (cell && oriented(cell)) return fail(UR_ERR_UNSUPPORTED, "the adjoint runs for lattices aligned with the box (rot = NULL, no grains)");
-  if (p->dSinc) return fail(UR_ERR_UNSUPPORTED, "the adjoint runs without the voxel form factor");
+  if (p->dSinc) return fail(UR_ERR_UNSUPPORTED, "the adjoint runs without the voxel form factor and block-transfer correction");
   if (p->mixed) return fail(UR_ERR_UNSUPPORTED, "the adjoint runs on power-of-two boxes");
   if (!grad_rho && !grad_amp) return UR_OK;
   if (p->n > 1024) return fail(UR_ERR_UNSUPPORTED, "the adjoint runs up to 1024^3");

@@ -67,8 +67,12 @@ template <typename T, int N, bool C2C, int PAIRS = UR_Z_PAIRS_F32> struct ZCfg {
 // y pass: x planes per block (two per group)
 template <typename T, int N> struct YCfg {
   static constexpr int G = Geo<N>::G;
-  // 4096-point columns: half-width tiles (1024 threads, 150 KB of LDS)
-  static constexpr int TX = N >= 4096 ? Seg<T>::cols / 2 : (Seg<T>::cols < N ? Seg<T>::cols : N);
+  // 4096-point columns: half-width tiles (1024 threads, 150 KB of LDS);
+  // 2048-point FP32 columns: half-width tiles when UR_Y_HALF_2K (two blocks of
+  // 75 KB per CU instead of one of 150 KB; 64-byte instead of 128-byte
+  // segments of B; tuned)
+  static constexpr bool HALF = N >= 4096 || (N == 2048 && UR_Y_HALF_2K && sizeof(T) == 4);
+  static constexpr int TX = HALF ? Seg<T>::cols / 2 : (Seg<T>::cols < N ? Seg<T>::cols : N);
   static constexpr int NS = TX / 2;
   static constexpr int threads = NS * G;
 };
@@ -82,9 +86,11 @@ template <typename T, int N> struct YICfg {
 template <int N> struct XCfg {
   static constexpr int G = Geo<N>::G;
   // 4096-point columns: two per block, so that a CU holds eight wavefronts;
-  // one-wavefront columns (1024 points): UR_X_THREADS threads' worth (tuned);
-  // shorter columns: 256 threads' worth
-  static constexpr int T0 = G == 64 ? UR_X_THREADS : 256;
+  // one-wavefront columns (1024 points): UR_X_THREADS threads' worth, and
+  // two-wavefront columns (2048 points) UR_X_THREADS_2K (tuned; a block of
+  // one such column syncs only its own two wavefronts); shorter columns:
+  // 256 threads' worth
+  static constexpr int T0 = G == 64 ? UR_X_THREADS : (G == 128 ? UR_X_THREADS_2K : 256);
   static constexpr int want = T0 / G > 0 ? T0 / G : 1;
   static constexpr int NG = G > 128 ? 2 : (want < 64 ? want : 64);
   static constexpr int threads = NG * G;
@@ -247,8 +253,11 @@ struct Pencil {
     }
   }
 
-  __device__ __forceinline__ void init(const ZArgs& a, long long X, long long Y) {
-    const Level& L = a.L;
+  __device__ __forceinline__ void init(const ZArgs& a, long long X, long long Y) { init_at(a, a.L, X, Y); }
+
+  // the pencil (X, Y) of level L (the arguments' own level, or the ED-1
+  // grid beneath a zoom level)
+  __device__ __forceinline__ void init_at(const ZArgs& a, const Level& L, long long X, long long Y) {
     long long lo, hi;
     col_range(L, a.m, X, Y, lo, hi);
     zlo = (int)lo;
@@ -518,8 +527,17 @@ k_pass_z(ZArgs a) {
   __shared__ T cl[CL];
   __shared__ double grl[RG ? kMaxGrains * 9 : 1];      // grain orientations (per-voxel choice)
 
-  const int tile = blockIdx.x % a.ntiles;
-  const long long X = a.x0 + blockIdx.x / a.ntiles;
+  // Tiles narrower than a 128-byte line of A (UR_Z_XCD): workgroups are
+  // dealt to the 8 XCDs in turn, so blocks b and b + 8 run on the same XCD
+  // at about the same time; within every 16 blocks the two tiles that share
+  // each line go to such a pair, and both halves of the line meet in one L2.
+  unsigned bid = blockIdx.x;
+  if constexpr (UR_Z_XCD && TY * sizeof(cx<T>) < 128) {
+    const unsigned j = bid & 15u;
+    if ((bid | 15u) < gridDim.x && a.ntiles % 16 == 0) bid = (bid & ~15u) + 2 * (j & 7u) + (j >> 3);
+  }
+  const int tile = bid % a.ntiles;
+  const long long X = a.x0 + bid / a.ntiles;
   const int y0 = tile * TY;
   const cx<T>* tw = (const cx<T>*)a.tw;
   cx<T>* A = (cx<T>*)a.A;
@@ -582,17 +600,21 @@ k_pass_z(ZArgs a) {
         // the cell residue of z = b + r N/R0 does not depend on r when the
         // cell edge divides N/R0: one cell load per pencil and butterfly
         const bool one_load = ((N / R0) & pa.cmask) == 0;
+        if (one_load) {
 #pragma unroll
-        for (int i = 0; i < NB0; ++i) {
-          const int b = g + Geo<N>::G * i;
-          if (one_load) {
+          for (int i = 0; i < NB0; ++i) {
+            const int b = g + Geo<N>::G * i;
             const T ca = pa.row[(b + pa.zoff) & pa.cmask], cb = pb.row[(b + pb.zoff) & pb.cmask];
 #pragma unroll
             for (int r = 0; r < R0; ++r) {
               const int z = b + r * (N / R0);
               v[i * R0 + r] = mk((z >= pa.zlo && z <= pa.zhi) ? ca : (T)0, (z >= pb.zlo && z <= pb.zhi) ? cb : (T)0);
             }
-          } else {
+          }
+        } else {
+#pragma unroll
+          for (int i = 0; i < NB0; ++i) {
+            const int b = g + Geo<N>::G * i;
 #pragma unroll
             for (int r = 0; r < R0; ++r) {
               const int z = b + r * (N / R0);
@@ -781,6 +803,69 @@ __global__ void __launch_bounds__(256) k_rho_generate(ZArgs a, int n, int x0, T*
   for (int z = threadIdx.x; z < n; z += 256) row[z] = a.rotated ? p.value_rotated_rt(a, z) : p.value(a, z);
 }
 
+// Zoom level of a rotated or polycrystalline lattice (real [x - x0][y][z]
+// planes): each level voxel is the sum of the f^3 ED-1 voxels of its block,
+// every one generated as the ED-1 generator does (the inside test of the
+// fine voxel, then the cell at u = R d with the chosen interpolation),
+// summed in FP64 and rounded once.  One block per level pencil (X, Y): the
+// f^2 fine pencils of its block column are the same for the whole block, so
+// their set-up (inside range, rotated base coordinates) is wave-uniform; the
+// threads take the level's z.  Level boxes up to kZoomRotMaxBox.
+
+template <typename T, int INTERP, bool GRAINS>
+__global__ void __launch_bounds__(256) k_zoom_rot(ZArgs a, int n, int x0, T* __restrict__ rho) {
+  constexpr int KZ = kZoomRotMaxBox / 256;
+  __shared__ T cl[4096];                               // the cell, when c^3 <= 4096
+  __shared__ double grl[GRAINS ? kMaxGrains * 9 : 1];
+  const long long t = blockIdx.x;
+  const long long X = x0 + t / n, Y = t % n;
+  const Level& Lk = a.L;
+  const int f = Lk.f;
+  T* row = rho + (size_t)t * n;
+  long long clo, chi;
+  col_range(Lk, a.m, X, Y, clo, chi);                 // level voxels whose block can hold density
+  if (clo > chi) {
+    for (int z = threadIdx.x; z < n; z += 256) row[z] = (T)0;
+    return;
+  }
+  const int c3 = Lk.c * Lk.c * Lk.c;
+  const bool in_lds = c3 <= 4096;
+  if (in_lds)
+    for (int i = threadIdx.x; i < c3; i += 256) cl[i] = ((const T*)a.cellT)[i];
+  if constexpr (GRAINS)
+    for (int i = threadIdx.x; i < 9 * a.ngrain; i += 256) grl[i] = (&a.grot[0][0])[i];
+  __syncthreads();
+  const T* C = in_lds ? cl : (const T*)a.cellT;
+  const Level L1 = make_level(Lk.n1, Lk.n1, 1, Lk.c);
+  const long long fx0 = (long long)f * (X - Lk.o), fy0 = (long long)f * (Y - Lk.o);
+  double acc[KZ];
+#pragma unroll
+  for (int k = 0; k < KZ; ++k) acc[k] = 0.0;
+  for (int u = 0; u < f; ++u)
+    for (int v = 0; v < f; ++v) {
+      Pencil<T> p;
+      p.init_at(a, L1, fx0 + u, fy0 + v);
+      if (p.zlo > p.zhi) continue;                     // block-uniform
+      if constexpr (GRAINS) { p.GR = grl; p.init_grains(a); }
+#pragma unroll
+      for (int k = 0; k < KZ; ++k) {
+        const int Z = (int)threadIdx.x + 256 * k;
+        if (Z >= n || Z < clo || Z > chi) continue;
+        const long long fz0 = (long long)f * (Z - Lk.o);
+        if (fz0 + f - 1 < p.zlo || fz0 > p.zhi) continue;
+        for (int w = 0; w < f; ++w) {
+          const int fz = (int)(fz0 + w);
+          if (fz >= p.zlo && fz <= p.zhi) acc[k] += (double)p.template value_rotated<INTERP, GRAINS>(a, fz, C);
+        }
+      }
+    }
+#pragma unroll
+  for (int k = 0; k < KZ; ++k) {
+    const int Z = (int)threadIdx.x + 256 * k;
+    if (Z < n) row[Z] = (T)acc[k];
+  }
+}
+
 // ---------------------------------------------------------------------------
 // pass Y: A[x][kz][y] columns -> transform along y -> B[kz][ky][x]
 // Each group transforms two x planes of the block's TX-plane tile one after
@@ -790,10 +875,20 @@ __global__ void __launch_bounds__(256) k_rho_generate(ZArgs a, int n, int x0, T*
 // ---------------------------------------------------------------------------
 // Zero-extended column loads when every wavefront lies in one column (G >= 64), where
 // the column address is wave-uniform: a raw buffer resource whose size ends
-// at the last valid element makes the hardware return zero beyond it, and
-// lanes below the first valid element use offset 2^31, which is always out
-// of range.  Offsets are never negative, so a constant part folded into the
-// instruction offset cannot wrap.  No branch, no masked load.
+// at the last valid element makes the hardware return zero beyond it.  No
+// branch per element, no masked load.  Two forms (SKIP; tuned per pass:
+// UR_LD_SKIP_Y for the y passes, UR_LD_SKIP_X for the x passes):
+//  1: the resource starts at element 0; lanes below the first valid element
+//     use offset 2^31, which is always out of range, and chunks of G
+//     elements wholly outside the range are skipped by a scalar branch (the
+//     registers zeroed instead).  Offsets are never negative, so a constant
+//     part folded into the instruction offset cannot wrap.
+//  0: the resource starts at the first valid element and every chunk is
+//     loaded: a lane below it has a negative offset, which as an unsigned
+//     number lies far beyond the resource's size; the whole offset is kept
+//     in the register (no constant folded into the instruction offset,
+//     where the 32-bit sum could wrap back into range).  One integer add per
+//     element, no select, no zeroing, no branch.
 constexpr unsigned kOutOfRange = 0x80000000u;
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t column_rsrc(const void* base, int bytes) {
@@ -809,26 +904,39 @@ __device__ __forceinline__ cx<T> column_ld(__amdgpu_buffer_rsrc_t rs, unsigned o
 }
 
 // v[i R0 + r] = col[p] for p = g + G i + r N/R0 inside [lo, hi], zero elsewhere
-// (col points at element 0; lo, hi and col are wave-uniform)
-template <typename T, int N>
+// (col points at element 0; lo, hi and col are wave-uniform; 0 <= lo)
+template <typename T, int N, bool SKIP>
 __device__ __forceinline__ void load_column_u(const cx<T>* col, int lo, int hi, int g, cx<T>* v) {
   constexpr int G = Geo<N>::G, E = Geo<N>::E, R0 = Radix<N, 1>::r, NB0 = E / R0;
   constexpr unsigned SZ = sizeof(cx<T>);
-  const __amdgpu_buffer_rsrc_t rs = column_rsrc(col, lo <= hi ? (hi + 1) * (int)SZ : 0);
-  const unsigned gb = (unsigned)g * SZ;
+  if constexpr (SKIP) {
+    const __amdgpu_buffer_rsrc_t rs = column_rsrc(col, lo <= hi ? (hi + 1) * (int)SZ : 0);
+    const unsigned gb = (unsigned)g * SZ;
 #pragma unroll
-  for (int i = 0; i < NB0; ++i)
+    for (int i = 0; i < NB0; ++i)
 #pragma unroll
-    for (int r = 0; r < R0; ++r) {
-      const int c = G * i + r * (N / R0);                // compile-time displacement
-      if (c + G - 1 < lo || c > hi) {                      // wave-uniform: no load at all
-        v[i * R0 + r] = mk((T)0, (T)0);
-      } else {
-        unsigned o = g >= lo - c ? gb : kOutOfRange;
-        asm("" : "+v"(o));   // keeps the constant out of the select: it becomes the instruction offset
-        v[i * R0 + r] = column_ld<T>(rs, o + (unsigned)c * SZ);
+      for (int r = 0; r < R0; ++r) {
+        const int c = G * i + r * (N / R0);              // compile-time displacement
+        if (c + G - 1 < lo || c > hi) {                    // wave-uniform: no load at all
+          v[i * R0 + r] = mk((T)0, (T)0);
+        } else {
+          unsigned o = g >= lo - c ? gb : kOutOfRange;
+          asm("" : "+v"(o));   // keeps the constant out of the select: it becomes the instruction offset
+          v[i * R0 + r] = column_ld<T>(rs, o + (unsigned)c * SZ);
+        }
       }
-    }
+  } else {
+    const __amdgpu_buffer_rsrc_t rs = column_rsrc(col + lo, lo <= hi ? (hi - lo + 1) * (int)SZ : 0);
+    const unsigned gb = (unsigned)(g - lo) * SZ;       // wraps below lo
+#pragma unroll
+    for (int i = 0; i < NB0; ++i)
+#pragma unroll
+      for (int r = 0; r < R0; ++r) {
+        unsigned o = gb + (unsigned)(G * i + r * (N / R0)) * SZ;
+        asm("" : "+v"(o));                                 // the whole offset stays in the register
+        v[i * R0 + r] = column_ld<T>(rs, o);
+      }
+  }
 }
 
 template <typename T, int N>
@@ -843,7 +951,7 @@ __device__ __forceinline__ void y_load_column(const YArgs& a, long long X, int k
   }
   const cx<T>* col = (const cx<T>*)a.A + ((size_t)(X - a.ax0) * a.nkz + kz) * N;
   if constexpr (G >= 64) {
-    load_column_u<T, N>(col, (int)ylo, (int)yhi, g, v);
+    load_column_u<T, N, UR_LD_SKIP_Y>(col, (int)ylo, (int)yhi, g, v);
   } else {
     const int lo = (int)ylo, hi = (int)yhi;
 #pragma unroll
@@ -966,7 +1074,7 @@ __device__ __forceinline__ void x_load_column(const XArgs& a, long long col, int
   constexpr int G = Geo<N>::G, E = Geo<N>::E, R0 = Radix<N, 1>::r, NB0 = E / R0;
   const cx<T>* src = (const cx<T>*)a.B + (size_t)col * a.bs - a.bx0;   // element x = 0
   if constexpr (G >= 64) {
-    load_column_u<T, N>(src, a.xa, a.xb, g, v);
+    load_column_u<T, N, UR_LD_SKIP_X>(src, a.xa, a.xb, g, v);
   } else {
 #pragma unroll
     for (int i = 0; i < NB0; ++i)
@@ -1018,7 +1126,6 @@ k_pass_x(XArgs a) {
     if (threadIdx.x == 0) { U[a.nbins + 1] = 0x7fffffff; U[a.nbins + 2] = 0x7fffffff; }
     __syncthreads();
   }
-  double tot = 0.0;
   const long long stride = (long long)gridDim.x * NG;
   long long col = (long long)blockIdx.x * NG + q;
   cx<T> v[E];
@@ -1043,7 +1150,6 @@ k_pass_x(XArgs a) {
     // order, so n2 and the bin index never decrease along the walk.
     const int k = sidx(ky, N);
     const int l = a.r2c ? kz : sidx(kz, N);
-    const double w = (a.r2c && kz != 0 && kz != N / 2) ? 2.0 : 1.0;
     const int base = k * k + l * l;
     // lane g owns |h| in [hlo, hlo + NH) (both signs), the last lane also
     // |h| = N/2; NH consecutive |h| stay inside one 16-element LDS block.
@@ -1051,8 +1157,11 @@ k_pass_x(XArgs a) {
     // values are both summed in FP64, so that a bin's sum and sum of squares
     // describe the same numbers (the one-pass variance of the finalize
     // subtracts them; a bin whose intensities barely vary would lose its SEM
-    // to the rounding of a working-precision run sum); the scale 1/n^6 of
-    // eq. 1 and the conjugate weight w are applied once per run.
+    // to the rounding of a working-precision run sum).  The LDS histogram
+    // holds the sums relative to the common column weight wref (2 for a real
+    // transform: the conjugate half counted twice), so most columns flush
+    // their runs unscaled; wref and the scale 1/n^6 of eq. 1 are applied once
+    // per block when the partials are written.
     constexpr int NH = G == 1 ? N / 2 : E / 2;
     const int hlo = G == 1 ? 0 : g * NH;
     // starting bin: the table entry of s = isqrt(n2) (the bin of s^2 <= n2),
@@ -1066,10 +1175,13 @@ k_pass_x(XArgs a) {
     while (n20 >= nextU) { ++b; nextU = U[b + 1]; }
     int nextU2 = U[b + 2];                               // one threshold ahead, off the critical path
     int cb = b;
-    double cs = 0.0, ct = 0.0, cs2 = 0.0;
-    // SINC: the column's factor S(|k|) S(|l|) joins the weight, S(|h|) each voxel
+    double cs = 0.0, cs2 = 0.0;
+    // this column's weight relative to wref: 1/2 at kz = 0 and N/2 of a real
+    // transform; SINC: times S(|k|) S(|l|) (S(|h|) is applied per voxel)
     const double wcol = SINC ? (double)St[k < 0 ? -k : k] * (double)St[l < 0 ? -l : l] : 1.0;
-    const double ws = w * a.iscale * wcol, ws2 = w * a.iscale * a.iscale * wcol * wcol;
+    const double wr = (a.r2c && (kz == 0 || kz == N / 2)) ? 0.5 : 1.0;
+    const double ws = wr * wcol, ws2 = wr * wcol * wcol;
+    const bool unit = !SINC && wr == 1.0;
     const cx<T>* sp = s + pad(hlo);
     // the lane's intensities first, in one batch of LDS reads: |F|^2 at +|h|
     // and -|h| for its NH values of |h| (nothing at -0), so the walk below
@@ -1083,13 +1195,20 @@ k_pass_x(XArgs a) {
       qp[t] = f1.x * f1.x + f1.y * f1.y;
       qm[t] = ha != 0 ? f2.x * f2.x + f2.y * f2.y : (T)0;
     }
+    auto flush = [&]() {
+      if (unit) {
+        atomicAdd(&hist[2 * cb + 0], cs);
+        atomicAdd(&hist[2 * cb + 1], cs2);
+      } else {
+        atomicAdd(&hist[2 * cb + 0], cs * ws);
+        atomicAdd(&hist[2 * cb + 1], cs2 * ws2);
+      }
+    };
     auto take = [&](int ha, T q1, T q2) {
       if constexpr (SINC) { const T sh = St[ha]; q1 *= sh; q2 *= sh; }
       const int n2 = ha * ha + base;
       if (n2 >= nextU) {
-        atomicAdd(&hist[2 * cb + 0], cs * ws);
-        atomicAdd(&hist[2 * cb + 1], cs2 * ws2);
-        ct += cs;
+        flush();
         cs = 0.0;
         cs2 = 0.0;
         ++b;
@@ -1098,9 +1217,11 @@ k_pass_x(XArgs a) {
         nextU2 = U[b + 2];
         cb = b;
       }
+      // the squares of working-precision values are exact in FP64
       const double d1 = (double)q1, d2 = (double)q2;
       cs += d1 + d2;
-      cs2 += d1 * d1 + d2 * d2;
+      cs2 = fma(d1, d1, cs2);
+      cs2 = fma(d2, d2, cs2);
     };
 #pragma unroll
     for (int t = 0; t < NH; ++t) take(hlo + t, qp[t], qm[t]);
@@ -1108,9 +1229,7 @@ k_pass_x(XArgs a) {
       const cx<T> f1 = s[pad(N / 2)];
       take(N / 2, f1.x * f1.x + f1.y * f1.y, (T)0);
     }
-    atomicAdd(&hist[2 * cb + 0], cs * ws);
-    atomicAdd(&hist[2 * cb + 1], cs2 * ws2);
-    tot += (ct + cs) * ws;
+    flush();
     if (kz == 0 && ky == 0 && g == 0 && a.f0) {
       const cx<T> f = s[pad(0)];
       a.f0[0] = (double)f.x * sqrt(a.iscale);
@@ -1119,12 +1238,20 @@ k_pass_x(XArgs a) {
     col_sync<G>();
   }
   if (!BIN) return;
-  tot = wave_sum(tot);
-  if ((threadIdx.x & 63) == 0) atomicAdd(tot_s, tot);
+  __syncthreads();
+  // every run went to one slot (the two outer slots included): the block's
+  // total is the sum of the slots, taken in a fixed order by one wavefront
+  const double wref = a.r2c ? 2.0 : 1.0, s1 = wref * a.iscale, s2 = wref * a.iscale * a.iscale;
+  if (threadIdx.x < 64) {
+    double t = 0.0;
+    for (int i = (int)threadIdx.x - 1; i <= a.nbins; i += 64) t += hist[2 * i];
+    t = wave_sum(t);
+    if (threadIdx.x == 0) *tot_s = t;
+  }
   __syncthreads();
   double* out = a.part + (size_t)blockIdx.x * (2 * (size_t)a.nbins + 1);
   for (int i = threadIdx.x; i < 2 * a.nbins + 1; i += C::threads) {
-    const double v = i < 2 * a.nbins ? hist[i] : *tot_s;
+    const double v = i < 2 * a.nbins ? hist[i] * ((i & 1) ? s2 : s1) : *tot_s * s1;
     out[i] = a.accum ? out[i] + v : v;
   }
 }
@@ -1427,7 +1554,7 @@ k_pass_x_adj(XAdjArgs a) {
   auto load = [&](long long c, cx<T>* v) {
     const cx<T>* src = (const cx<T>*)a.B + (size_t)c * a.bs - a.bx0;
     if constexpr (G >= 64) {
-      load_column_u<T, N>(src, a.xa, a.xb, g, v);
+      load_column_u<T, N, UR_LD_SKIP_X>(src, a.xa, a.xb, g, v);
     } else {
 #pragma unroll
       for (int i = 0; i < NB0; ++i)
@@ -2463,8 +2590,25 @@ hipError_t launch_level_complex(int prec, int n, const ZArgs& a, void* S, double
   return hipGetLastError();
 }
 
+template <typename T>
+static void zoom_rot_launch(unsigned nn, const ZArgs& a, int n, int x_lo, void* rho, hipStream_t s) {
+  if (a.cubic) {
+    if (a.ngrain) hipLaunchKernelGGL((k_zoom_rot<T, 3, true>), dim3(nn), dim3(256), 0, s, a, n, x_lo, (T*)rho);
+    else hipLaunchKernelGGL((k_zoom_rot<T, 3, false>), dim3(nn), dim3(256), 0, s, a, n, x_lo, (T*)rho);
+  } else {
+    if (a.ngrain) hipLaunchKernelGGL((k_zoom_rot<T, 1, true>), dim3(nn), dim3(256), 0, s, a, n, x_lo, (T*)rho);
+    else hipLaunchKernelGGL((k_zoom_rot<T, 1, false>), dim3(nn), dim3(256), 0, s, a, n, x_lo, (T*)rho);
+  }
+}
+
 hipError_t launch_rho_generate(int prec, int n, int x_lo, int x_hi, const ZArgs& a, void* rho, hipStream_t s) {
   const unsigned nn = (unsigned)((long long)(x_hi - x_lo + 1) * n);
+  if (a.rotated && a.L.f > 1) {                        // zoom level of an oriented lattice
+    if (n > kZoomRotMaxBox) return hipErrorNotSupported;
+    if (prec == 0) zoom_rot_launch<float>(nn, a, n, x_lo, rho, s);
+    else zoom_rot_launch<double>(nn, a, n, x_lo, rho, s);
+    return hipGetLastError();
+  }
   if (prec == 0) hipLaunchKernelGGL(k_rho_generate<float>, dim3(nn), dim3(256), 0, s, a, n, x_lo, (float*)rho);
   else hipLaunchKernelGGL(k_rho_generate<double>, dim3(nn), dim3(256), 0, s, a, n, x_lo, (double*)rho);
   return hipGetLastError();

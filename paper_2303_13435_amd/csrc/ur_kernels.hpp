@@ -25,6 +25,9 @@ enum ZMode { Z_GEN_R2C = 0, Z_LOAD_R2C = 1, Z_GEN_C2C = 2, Z_LOAD_C2C = 3, Z_ZOO
 enum XMode { X_FFT_BIN = 0, X_BIN_ONLY = 1, X_FFT_STORE = 2, X_ADJ = 3, X_FFT_BIN_SINC = 4, X_BIN_ONLY_SINC = 5 };
 
 constexpr int kMaxGrains = 16;
+// largest box of a zoom level of a rotated lattice (the generator keeps
+// kZoomRotMaxBox / 256 level voxels per thread)
+constexpr int kZoomRotMaxBox = 2048;
 
 struct ZArgs {
   void* A;                  // out: [x - ax0][kz][y] complex

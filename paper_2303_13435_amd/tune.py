@@ -10,8 +10,9 @@ csrc/ur_tuned.hpp with the table of candidates and timings in
 profiles/tuning_M1024.md.
 
     python -m paper_2303_13435_amd.tune build          # CPU: the candidate libraries
-    python -m paper_2303_13435_amd.tune run OUT.jsonl  # GPU: time them (one process per library)
-    python -m paper_2303_13435_amd.tune pick OUT.jsonl # CPU: write ur_tuned.hpp and the table
+    python -m paper_2303_13435_amd.tune run OUT.jsonl [MACRO ...]  # GPU: time them (one process per
+                                                                    # library; only those macros' candidates)
+    python -m paper_2303_13435_amd.tune pick OUT.jsonl [OUT2.jsonl ...]  # CPU: write ur_tuned.hpp and the table
 
 A choice is judged on the passes it affects; choices of different passes
 are picked independently (each candidate varies one macro from the default).
@@ -37,13 +38,18 @@ TABLE = os.path.join(ROOT, "profiles", "tuning_M1024.md")
 #           passes whose time decides it, precisions timed for it)
 CHOICES = {
     "UR_X_THREADS": ((256, 128, 512), (0, 3, 4, 6), ("pass_x",), ("f32",)),
+    "UR_X_THREADS_2K": ((256, 128), (3, 4), ("pass_x_2048",), ("f32",)),
+    "UR_Y_HALF_2K": ((0, 1), (0, 5, 6), ("pass_y_2048", "pass_x_2048"), ("f32",)),
     "UR_X_MINW_F32": ((1, 3, 4), (3,), ("pass_x",), ("f32",)),
     "UR_X_MINW_F64": ((1, 2), (4,), ("pass_x",), ("f64",)),
     "UR_Z_PAIRS_F32": ((8, 4, 2), (0, 1, 5, 6, 7, 9), ("pass_z", "pass_y"), ("f32",)),
     "UR_ZI_PAIRS_F32": ((8, 4), (0, 5, 6), ("fwd_adjoint",), ("f32",)),
+    "UR_Z_XCD": ((0, 1), (1, 7, 9), ("pass_z",), ("f32",)),
     "UR_ST_NT_A": ((1, 0), (1, 2), ("pass_z", "pass_y"), ("f32", "f64")),
     "UR_ST_NT_B": ((1, 0), (5,), ("pass_y", "pass_x"), ("f32", "f64")),
     "UR_LD_NT": ((1, 0), (3, 4, 5), ("pass_y", "pass_x"), ("f32", "f64")),
+    "UR_LD_SKIP_Y": ((1, 0), (5,), ("pass_y",), ("f32", "f64")),
+    "UR_LD_SKIP_X": ((0, 1), (3, 4, 6), ("pass_x",), ("f32", "f64")),
 }
 
 
@@ -167,10 +173,32 @@ def measure(steps: int = 20) -> dict:
         out[tag]["grad_amp"] = [float(x) for x in gamp.cpu().numpy()]
         del plan
         torch.cuda.empty_cache()
+    # the 2048^3 ED-1 level of the multi-zoom batch, FP32 (two-wavefront
+    # columns): per-pass times, and its curve joins the comparison
+    wl = W.c3_levels()[0]
+    plan = ur.Plan(wl.n, wl.voxel, ur.UR_F32)
+    plan.set_bins(wl.edges)
+    cell = ur.DeviceCell.from_host(wl.cell)
+    h = ur.Hist(wl.nbins)
+    plan.simulate(cell, wl.mask, wl.zoom, h)
+    plan.set_timing(True)
+    for _ in range(max(3, steps // 4)):
+        plan.simulate(cell, wl.mask, wl.zoom, h)
+    torch.cuda.synchronize()
+    t = plan.read_timing()
+    plan.set_timing(False)
+    for k, v in t.items():
+        if v["launches"]:
+            out["f32"]["passes"][k + "_2048"] = v["ms"] / v["launches"]
+    out["f32"]["mean_2048"] = [float(x) for x in np.nan_to_num(h.mean.cpu().numpy(), nan=-1.0)]
+    del plan
+    torch.cuda.empty_cache()
     return out
 
 
-def run_all(out_path: str) -> None:
+def run_all(out_path: str, macros=()) -> None:
+    """Times the built candidates (those of the named macros and the default
+    when `macros` is given) and writes one JSON line per candidate."""
     names = sorted(os.listdir(LIBDIR)) if os.path.isdir(LIBDIR) else []
     with open(out_path, "w") as fh:
         for d in names:
@@ -179,6 +207,8 @@ def run_all(out_path: str) -> None:
             if not (os.path.exists(lib) and os.path.exists(meta)):
                 continue
             cand = json.load(open(meta))
+            if macros and cand["overrides"] and not any(m in cand["overrides"] for m in macros):
+                continue
             env = dict(os.environ, UR_LIBPATH=lib)
             print(f"timing {cand['name']}", flush=True)
             r = subprocess.run([sys.executable, "-m", "paper_2303_13435_amd.tune", "measure"], cwd=ROOT, env=env,
@@ -194,9 +224,11 @@ def run_all(out_path: str) -> None:
             print(f"  {msg}", flush=True)
 
 
-def pick(results_path: str) -> None:
+def pick(results_paths) -> None:
     import numpy as np
-    recs = [json.loads(ln) for ln in open(results_path) if ln.strip()]
+    if isinstance(results_paths, str):
+        results_paths = [results_paths]
+    recs = [json.loads(ln) for path in results_paths for ln in open(path) if ln.strip()]
     by_name = {r["candidate"]["name"]: r for r in recs if "result" in r}
     if "default" not in by_name:
         raise SystemExit("no timing of the default candidate")
@@ -215,8 +247,10 @@ def pick(results_path: str) -> None:
             res = r["result"]
             # the curve must be the default's (same arithmetic up to rounding order)
             ok = True
-            for tg in ("f32", "f64"):
-                a, b = np.array(res[tg]["mean"]), np.array(ref[tg]["mean"])
+            for tg, key in (("f32", "mean"), ("f64", "mean"), ("f32", "mean_2048")):
+                if key not in ref[tg] or key not in res[tg]:
+                    continue
+                a, b = np.array(res[tg][key]), np.array(ref[tg][key])
                 pos = b > 0
                 if not np.array_equal(a < 0, b < 0) or np.max(np.abs(a[pos] - b[pos]) / b[pos]) > 1e-6:
                     ok = False
@@ -248,11 +282,12 @@ def write_table(rows, chosen, ref) -> None:
              "a process of its own (20 steps after 3 warm-up steps, per-pass HIP events).  A value is chosen on the",
              "passes it affects; a candidate whose curve differs from the default's by more than 1e-6 is rejected;",
              "a change must win by more than 1 %.", "",
-             "| macro | value | FP32 step ms | FP32 pass Z / Y / X ms | FP32 fwd+adjoint ms | FP64 step ms | FP64 pass Z / Y / X ms | FP64 fwd+adjoint ms | note |",
-             "|---|---|---|---|---|---|---|---|---|"]
+             "The 2048^3 column is the ED-1 level of the multi-zoom batch (FP32, per-pass HIP events).", "",
+             "| macro | value | FP32 step ms | FP32 pass Z / Y / X ms | FP32 fwd+adjoint ms | FP64 step ms | FP64 pass Z / Y / X ms | FP64 fwd+adjoint ms | 2048^3 FP32 pass Z / Y / X ms | note |",
+             "|---|---|---|---|---|---|---|---|---|---|"]
     for m, v, res, note in rows:
         if res is None:
-            lines.append(f"| {m} | {v} | | | | | | | {note} |")
+            lines.append(f"| {m} | {v} | | | | | | | | {note} |")
             continue
         cells = []
         for tg in ("f32", "f64"):
@@ -260,6 +295,8 @@ def write_table(rows, chosen, ref) -> None:
             cells.append(f"{res[tg]['step_ms']:.4f}")
             cells.append(" / ".join(f"{ps.get(k, 0.0):.4f}" for k in ("pass_z", "pass_y", "pass_x")))
             cells.append(f"{ps['fwd_adjoint']:.4f}" if "fwd_adjoint" in ps else "")
+        ps = res["f32"]["passes"]
+        cells.append(" / ".join(f"{ps.get(k + '_2048', 0.0):.3f}" for k in ("pass_z", "pass_y", "pass_x")))
         mark = "**chosen**" if chosen[m] == v else ""
         lines.append(f"| {m} | {v} | {' | '.join(cells)} | {(mark + ' ' + note).strip()} |")
     lines += ["", "Chosen: " + ", ".join(f"`{m} = {v}`" for m, v in chosen.items())]
@@ -274,11 +311,11 @@ def main(argv) -> None:
     if cmd == "build":
         build_all()
     elif cmd == "run":
-        run_all(argv[1] if len(argv) > 1 else os.path.join(ROOT, "gpurun_out", "tune.jsonl"))
+        run_all(argv[1] if len(argv) > 1 else os.path.join(ROOT, "gpurun_out", "tune.jsonl"), tuple(argv[2:]))
     elif cmd == "measure":
         print(json.dumps(measure()))
     elif cmd == "pick":
-        pick(argv[1])
+        pick(argv[1:])
     else:
         raise SystemExit(__doc__)
 

@@ -308,9 +308,43 @@ def test_rotated_lattice(ur, orc, n, prec, interp, c):
     ga = torch.zeros(wl.cell.n_atoms, dtype=torch.float64, device="cuda")
     with pytest.raises(ur.UltimaError, match="status 2"):
         plan.adjoint(h, g, cell=cell, mask=wl.mask, grad_amp=ga)
-    with pytest.raises(ur.UltimaError, match="status 2"):
-        plan.simulate(cell, wl.mask, W.Zoom(2 * n, 2), h)
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("prec,interp,grains", [(0, 1, False), (1, 1, False), (0, 3, False), (1, 3, True),
+                                                (0, 1, True)])
+def test_rotated_zoom_levels(ur, orc, prec, interp, grains):
+    """Zoom levels of an oriented lattice (64^3 by 2 and 32^3 by 4 from a
+    128^3 ED-1; one orientation, or 5 grains): the fused forward path against
+    the oracle (O2r/O2g, block sums O3, then O4-O8), the level's density from
+    ur_rho_generate voxel by voxel, and Sum rho^2; the allocation-free entry
+    refuses such levels."""
+    import torch
+    from dataclasses import replace
+    R = W.rotation([1.0, 2.0, 3.0], 0.7)
+    seeds, rots = W.random_grains(77, 5, 0.35 * 128)
+    for wl in W.zoom_levels(128, 8, 9, 73, 50.0, [(64, 2), (32, 4)], 40, decades=2.0):
+        cell_h = wl.cell.with_grains(seeds, rots, interp) if grains else wl.cell.with_rot(R, interp)
+        wl = replace(wl, prec=prec, cell=cell_h)
+        _say(f"rotated zoom level {wl.n}^3 f={wl.zoom.factor} prec={prec} interp={interp} grains={grains}")
+        ref = orc.simulate(wl, return_fields=True)
+        got = run_simulate(ur, wl)
+        compare_bins(got, ref, F32_BIN if prec == 0 else F64_BIN, "rotated zoom level", n=wl.n)
+        assert abs(got["totals"][3] - ref["rho_sumsq"]) <= (1e-6 if prec == 0 else 1e-12) * ref["rho_sumsq"]
+        plan = ur.Plan(wl.n, wl.voxel, prec)
+        plan.set_bins(wl.edges)
+        cell = ur.DeviceCell.from_host(wl.cell)
+        rho = plan.rho_generate(cell, wl.mask, wl.zoom)
+        torch.cuda.synchronize()
+        want = ref["rho"]
+        err = np.max(np.abs(rho.cpu().numpy().astype(np.float64) - want)) / np.max(np.abs(want))
+        _say(f"  level density max rel err {err:.3e}")
+        assert err <= (2e-6 if prec == 0 else 1e-13)
+        if prec == 0:
+            h = ur.Hist(wl.nbins)
+            with pytest.raises(ur.UltimaError, match="status 2"):
+                plan.simulate_noalloc(cell, wl.mask, wl.zoom, h)
+        torch.cuda.synchronize()
 
 
 @pytest.mark.parametrize("n,prec,interp,c", [(64, 0, 1, 8), (64, 1, 1, 8), (64, 0, 3, 8), (64, 1, 3, 8), (128, 0, 3, 8),
@@ -394,6 +428,70 @@ def test_voxel_form_factor(ur, orc, prec):
     plan.simulate(cell, wl.mask, wl.zoom, h3)
     torch.cuda.synchronize()
     compare_bins(h3.numpy(), orc.simulate(wl), tol, "voxel form off", n=wl.n)
+
+
+# ---------------------------------------------------------------------------
+# block-transfer correction of zoom levels (O18)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_block_transfer_correction(ur, orc, prec):
+    """Zoom levels 64^3 by 2 and by 4 of a 128^3 ED-1 with the block
+    transfer removed: the fused path and ur_intensity_bin against the
+    oracle with O18 applied, alone and with the voxel form factor; a level of
+    another factor, the adjoint and a mixed-radix plan are refused; factor 0
+    restores the plain curve."""
+    import torch
+    from dataclasses import replace
+    levels = W.zoom_levels(128, 8, 10, 41, 50.0, [(64, 2), (64, 4)], 48, decades=2.0)
+    tol = F32_BIN if prec == 0 else F64_BIN
+    for wl in levels:
+        wl = replace(wl, prec=prec)
+        f = wl.zoom.factor
+        _say(f"block transfer f={f} prec={prec}")
+        ref = orc.simulate(wl, return_fields=True, block_transfer_removed=True)
+        plan = ur.Plan(wl.n, wl.voxel, prec)
+        plan.set_bins(wl.edges)
+        plan.set_block_transfer(f)
+        cell = ur.DeviceCell.from_host(wl.cell)
+        h = ur.Hist(wl.nbins)
+        plan.simulate(cell, wl.mask, wl.zoom, h)
+        torch.cuda.synchronize()
+        compare_bins(h.numpy(), ref, tol, f"simulate, block transfer f={f}", n=wl.n)
+        spec = torch.as_tensor(np.ascontiguousarray(ref["F"][:, :, : wl.n // 2 + 1].transpose(2, 1, 0)),
+                               dtype=plan.complex_dtype, device="cuda")
+        h2 = ur.Hist(wl.nbins)
+        plan.intensity_bin(spec, h2)
+        torch.cuda.synchronize()
+        compare_bins(h2.numpy(), ref, tol, f"intensity_bin, block transfer f={f}", n=wl.n)
+        # with the voxel form factor as well: the weights multiply
+        plan.set_voxel_form(True)
+        h3 = ur.Hist(wl.nbins)
+        plan.simulate(cell, wl.mask, wl.zoom, h3)
+        torch.cuda.synchronize()
+        compare_bins(h3.numpy(), orc.simulate(wl, voxel_form_factor=True, block_transfer_removed=True), tol,
+                     f"simulate, block transfer f={f} + voxel form", n=wl.n)
+        plan.set_voxel_form(False)
+        # refusals: another factor, the adjoint
+        other = replace(wl, zoom=replace(wl.zoom, factor=2 if f != 2 else 4))
+        with pytest.raises(ur.UltimaError, match="status 1"):
+            plan.simulate(cell, other.mask, other.zoom, h)
+        g = torch.zeros(wl.nbins, dtype=torch.float64, device="cuda")
+        ga = torch.zeros(wl.cell.n_atoms, dtype=torch.float64, device="cuda")
+        with pytest.raises(ur.UltimaError, match="status 2"):
+            plan.adjoint(h, g, cell=cell, mask=wl.mask, grad_amp=ga)
+        # off again: the plain curve
+        plan.set_block_transfer(0)
+        h4 = ur.Hist(wl.nbins)
+        plan.simulate(cell, wl.mask, wl.zoom, h4)
+        torch.cuda.synchronize()
+        compare_bins(h4.numpy(), orc.simulate(wl), tol, f"block transfer off f={f}", n=wl.n)
+        # the correction raises every populated bin away from q = 0
+        pop = (ref["count"] > 0) & (h4.numpy()["count"] > 0)
+        assert np.all(h.numpy()["mean"][pop] >= h4.numpy()["mean"][pop] * (1 - 1e-6))
+    mplan = ur.Plan(40, 1.0, prec, c2c=True)
+    with pytest.raises(ur.UltimaError, match="status 2"):
+        mplan.set_block_transfer(2)
 
 
 # ---------------------------------------------------------------------------
