@@ -294,20 +294,24 @@ def other_configs(ur, W, torch, steps):
 
 def mixed_radix(ur, W, torch, steps):
     """Boxes whose edge is not a power of two (the paper's 1000 / 2000 family):
-    the mixed-radix forward path (complex, one axis at a time) on the M1024
-    recipe scaled to the edge; ms per box, voxels/s and per-pass timing."""
+    the mixed-radix forward path (one axis at a time; real plans pair two
+    real pencils per z line and keep the half spectrum, complex plans the
+    whole box) on the M1024 recipe scaled to the edge; ms per box, voxels/s
+    and per-pass timing."""
     out = {}
-    for n, prec in ((1000, ur.UR_F32), (1000, ur.UR_F64), (2000, ur.UR_F32)):
+    for n, prec, c2c in ((1000, ur.UR_F32, False), (1000, ur.UR_F64, False), (2000, ur.UR_F32, False),
+                         (1000, ur.UR_F32, True), (1000, ur.UR_F64, True), (2000, ur.UR_F32, True)):
         wl = W.mixed(n, prec, nbins=512)
-        plan = ur.Plan(wl.n, wl.voxel, prec, c2c=True)
+        plan = ur.Plan(wl.n, wl.voxel, prec, c2c=c2c)
         plan.set_bins(wl.edges)
         cell = ur.DeviceCell.from_host(wl.cell)
         h = ur.Hist(wl.nbins)
         step = lambda: plan.simulate(cell, wl.mask, wl.zoom, h)
         ms, _ = time_steps(step, steps, 2, torch)
-        out[wl.name] = {"ms_per_box": round(ms, 4), "voxels_per_s": wl.n ** 3 / (ms * 1e-3),
-                        "prec": "f64" if prec == ur.UR_F64 else "f32", "transform": "c2c",
-                        "kernels": pass_timing(plan, step, steps, torch)}
+        out[wl.name + ("_c2c" if c2c else "")] = {
+            "ms_per_box": round(ms, 4), "voxels_per_s": wl.n ** 3 / (ms * 1e-3),
+            "prec": "f64" if prec == ur.UR_F64 else "f32", "transform": "c2c" if c2c else "r2c",
+            "kernels": pass_timing(plan, step, steps, torch)}
         del plan, step
         torch.cuda.empty_cache()
         note(f"mixed radix {wl.name} done")

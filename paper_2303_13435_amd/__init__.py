@@ -482,13 +482,15 @@ class Plan:
 
     def fft3d(self, x, out=None, direction: int = -1, stream=None):
         """eq. 1 forward (1/n^3) into the [kz][ky][kx] layout ([kx][ky][kz] on a
-        mixed-radix plan, which needs no workspace), or its inverse."""
+        mixed-radix plan, which needs no workspace; kz in [0, n/2] for a real
+        plan), or its inverse (not on real mixed-radix plans)."""
         torch = _torch()
         n = self.n
         if direction < 0:
             _require(x, self.complex_dtype if self.c2c else self.real_dtype, n ** 3, "input")
             if out is None:
-                out = torch.empty((self.nkz(), n, n), dtype=self.complex_dtype, device="cuda")
+                shape = (n, n, self.nkz()) if self.mixed else (self.nkz(), n, n)
+                out = torch.empty(shape, dtype=self.complex_dtype, device="cuda")
             _require(out, self.complex_dtype, self.nkz() * n * n, "output")
         else:
             _require(x, self.complex_dtype, self.nkz() * n * n, "spectrum")

@@ -197,7 +197,7 @@ static Layout layout_mixed(const ur_plan* p, int nbins) {
   const size_t n = p->n;
   L.A = 0;
   L.B = 0;
-  L.part = align256(n * n * n * p->cs);
+  L.part = align256(n * n * (size_t)p->nkz * p->cs);  // the box (real plans: the half spectrum)
   L.mom = align256(L.part + (size_t)kMaxXBlocks * (2 * (size_t)std::max(nbins, 1) + 1) * 8);
   L.f0 = align256(L.mom + n * n * 16);
   L.total = align256(L.f0 + 64 + 256 * 8);
@@ -438,8 +438,6 @@ ur_status ur_plan_create(int32_t n, double voxel, int32_t prec, uint32_t flags, 
   const bool mixed = !is_pow2(n) && mr_size(n);
   if (!mixed && (!is_pow2(n) || n < 16))
     return fail(UR_ERR_INVALID, "n = %d must be a power of two >= 16 or one of the mixed-radix edges", n);
-  if (mixed && !(flags & UR_C2C))
-    return fail(UR_ERR_UNSUPPORTED, "n = %d: mixed-radix boxes run complex transforms (UR_C2C)", n);
   if (n > kMaxOutOfCore) return fail(UR_ERR_UNSUPPORTED, "n = %d: boxes run up to %d^3", n, kMaxOutOfCore);
   if (n > kMaxInCore && (prec != UR_F32 || (flags & UR_C2C)))
     return fail(UR_ERR_UNSUPPORTED, "n = %d: boxes above %d^3 are FP32 real (UR_F32, no UR_C2C)", n, kMaxInCore);
@@ -911,17 +909,19 @@ static ur_status run_y_x(ur_plan* p, const FwdGeom& g, char* A, char* B, const L
 static ur_status mr_transform(ur_plan* p, const void* src, void* S, int dir, double* mom, const ZArgs* gen,
                               const Layout* lay, hipStream_t s) {
   const int n = p->n;
+  const bool r2c = !(p->flags & UR_C2C);
+  if (r2c && dir > 0) return fail(UR_ERR_UNSUPPORTED, "real mixed-radix plans run the forward transform only");
   MrArgs a{};
   a.tw = p->tw; a.dst = S; a.mom = mom; a.src = src; a.scale = 1.0;
   if (gen) a.z = *gen;
   {
     PassTimer tm(p, P_Z, s);
-    UR_HIP(launch_mr_axis(p->prec, n, 2, dir, gen ? MR_GEN : MR_LOAD, a, s));
+    UR_HIP(launch_mr_axis(p->prec, n, 2, dir, gen ? MR_GEN : MR_LOAD, r2c, a, s));
   }
   a.src = S; a.mom = nullptr;
   {
     PassTimer tm(p, P_Y, s);
-    UR_HIP(launch_mr_axis(p->prec, n, 1, dir, MR_LOAD, a, s));
+    UR_HIP(launch_mr_axis(p->prec, n, 1, dir, MR_LOAD, r2c, a, s));
   }
   a.scale = dir < 0 ? 1.0 / ((double)n * n * n) : 1.0;
   if (lay) {
@@ -930,10 +930,13 @@ static ur_status mr_transform(ur_plan* p, const void* src, void* S, int dir, dou
   }
   {
     PassTimer tm(p, P_X, s);
-    UR_HIP(launch_mr_axis(p->prec, n, 0, dir, lay ? MR_BIN : MR_LOAD, a, s));
+    UR_HIP(launch_mr_axis(p->prec, n, 0, dir, lay ? MR_BIN : MR_LOAD, r2c, a, s));
   }
-  const double box = (double)n * n * n * p->cs;
-  p->pass_bytes[P_Z] = (gen ? 1.0 : 2.0) * box;
+  // algorithmic bytes: the box of nkz complex elements per (x, y) line; a
+  // real input of n reals per line
+  const double box = (double)n * n * p->nkz * p->cs;
+  const double in = r2c ? (double)n * n * n * p->rs : box;
+  p->pass_bytes[P_Z] = (gen ? 0.0 : in) + box;
   p->pass_bytes[P_Y] = 2.0 * box;
   p->pass_bytes[P_X] = (lay ? 1.0 : 2.0) * box;
   return UR_OK;
@@ -956,13 +959,14 @@ static ur_status mr_finalize(ur_plan* p, const Layout& lay, int nblk, const ur_h
 static ur_status mr_bin(ur_plan* p, const void* S, const Layout& lay, const ur_hist* h, hipStream_t s) {
   MrBinArgs b{};
   b.S = S; b.n = p->n; b.nbins = p->nbins; b.U = p->dU; b.lut = p->dLut; b.nlut = p->nlut; b.iscale = 1.0;
+  b.r2c = (p->flags & UR_C2C) ? 0 : 1;
   b.part = (double*)(p->ws + lay.part); b.f0 = (double*)(p->ws + lay.f0);
   const int nblk = (int)std::min<long long>((long long)p->n * p->n, kMaxXBlocks);
   {
     PassTimer tm(p, P_X, s);
     UR_HIP(launch_mr_bin(p->prec, b, nblk, s));
   }
-  p->pass_bytes[P_X] = (double)p->n * p->n * p->n * p->cs;
+  p->pass_bytes[P_X] = (double)p->n * p->n * p->nkz * p->cs;
   return mr_finalize(p, lay, nblk, h, 0, s);
 }
 
@@ -991,6 +995,7 @@ ur_status ur_rho_generate(ur_plan* p, const ur_cell* cell, const ur_mask* mask, 
   Level L;
   MaskP m;
   UR_TRY(check_level(p, cell, mask, zoom, L, m));
+  if (p->mixed && oriented(cell)) return fail(UR_ERR_UNSUPPORTED, "mixed-radix boxes run lattices aligned with the box");
   hipStream_t s = (hipStream_t)stream;
   note_stream(p, s);
   CellTables t;
@@ -1020,6 +1025,7 @@ ur_status ur_simulate(ur_plan* p, const ur_cell* cell, const ur_mask* mask, cons
   FwdGeom g;
   UR_TRY(check_level(p, cell, mask, zoom, g.L, g.m));
   UR_TRY(check_block_transfer(p, zoom));
+  if (p->mixed && oriented(cell)) return fail(UR_ERR_UNSUPPORTED, "mixed-radix boxes run lattices aligned with the box");
   ZArgs rot_args{};
   UR_TRY(set_rotation(p, cell, zoom, rot_args, !p->mixed));
   hipStream_t s = (hipStream_t)stream;
@@ -1041,14 +1047,23 @@ ur_status ur_simulate(ur_plan* p, const ur_cell* cell, const ur_mask* mask, cons
     za.cellT = t.cellT; za.cb = t.cb; za.pre = t.pre; za.L = g.L; za.m = g.m; za.cbn = t.cbn;
     double* mom = (double*)(p->ws + lay.mom);
     if (zoom->factor > 1) {
+      if (!(p->flags & UR_C2C)) {
+        // real box: the level's density into the plan's level buffer, then
+        // the three passes from it (the z pass pairs its real pencils)
+        UR_TRY(ensure_level_buf(p, (size_t)p->n * p->n * p->n * p->rs, s));
+        UR_HIP(launch_rho_generate(p->prec, p->n, 0, p->n - 1, za, p->lvl_buf, s));
+        UR_TRY(mr_transform(p, p->lvl_buf, p->ws + lay.A, -1, mom, nullptr, &lay, s));
+        return mr_finalize(p, lay, mr_axis_blocks(p->prec, p->n, 0, MR_BIN, true), h,
+                           mr_axis_blocks(p->prec, p->n, 2, MR_LOAD, true), s);
+      }
       // zoom level: block sums of ED-1 written as a complex box first, then
       // the three passes from it (the generating z pass serves ED-1 only)
       UR_HIP(launch_level_complex(p->prec, p->n, za, p->ws + lay.A, mom, s));
       UR_TRY(mr_transform(p, p->ws + lay.A, p->ws + lay.A, -1, nullptr, nullptr, &lay, s));
-      return mr_finalize(p, lay, mr_axis_blocks(p->prec, p->n, 0, MR_BIN), h, p->n * p->n, s);
+      return mr_finalize(p, lay, mr_axis_blocks(p->prec, p->n, 0, MR_BIN, false), h, p->n * p->n, s);
     }
     UR_TRY(mr_transform(p, nullptr, p->ws + lay.A, -1, mom, &za, &lay, s));
-    return mr_finalize(p, lay, mr_axis_blocks(p->prec, p->n, 0, MR_BIN), h, mr_axis_blocks(p->prec, p->n, 2, MR_GEN), s);
+    return mr_finalize(p, lay, mr_axis_blocks(p->prec, p->n, 0, MR_BIN, !(p->flags & UR_C2C)), h, mr_axis_blocks(p->prec, p->n, 2, MR_GEN, !(p->flags & UR_C2C)), s);
   }
   Layout lay = layout_incore(p, p->nbins);
   if (rot_args.rotated && zoom->factor > 1) {
@@ -1172,7 +1187,7 @@ ur_status ur_simulate_rho(ur_plan* p, const void* rho, const ur_hist* h, void* s
     Layout lay = layout_mixed(p, p->nbins);
     UR_TRY(ensure_ws(p, lay.total, s));
     UR_TRY(mr_transform(p, rho, p->ws + lay.A, -1, (double*)(p->ws + lay.mom), nullptr, &lay, s));
-    return mr_finalize(p, lay, mr_axis_blocks(p->prec, p->n, 0, MR_BIN), h, mr_axis_blocks(p->prec, p->n, 2, MR_LOAD), s);
+    return mr_finalize(p, lay, mr_axis_blocks(p->prec, p->n, 0, MR_BIN, !(p->flags & UR_C2C)), h, mr_axis_blocks(p->prec, p->n, 2, MR_LOAD, !(p->flags & UR_C2C)), s);
   }
   Layout lay = layout_incore(p, p->nbins);
   UR_TRY(ensure_ws(p, lay.total, s));
@@ -1284,6 +1299,7 @@ ur_status ur_simulate_host(ur_plan* p, const void* rho_host, int32_t x_lo, int32
   if (!p || !rho_host) return fail(UR_ERR_INVALID, "null argument");
   if (p->nbins < 1) return fail(UR_ERR_STATE, "no bins set on the plan");
   if (p->flags & UR_C2C) return fail(UR_ERR_UNSUPPORTED, "the out-of-core path takes real densities (UR_R2C plans)");
+  if (p->mixed) return fail(UR_ERR_UNSUPPORTED, "the out-of-core path runs power-of-two boxes");
   if (x_lo < 0 || x_hi >= p->n || x_lo > x_hi) return fail(UR_ERR_INVALID, "plane range [%d, %d] outside the box", x_lo, x_hi);
   UR_TRY(check_hist(h));
   hipStream_t s = (hipStream_t)stream;

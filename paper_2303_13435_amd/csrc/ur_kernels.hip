@@ -2284,7 +2284,7 @@ __device__ __forceinline__ double ewald_intensity(const EwaldArgs& a, long long 
   long long lz = ((l % n) + n) % n;
   if (!a.c2c && lz > n / 2) { h = -h; k = -k; lz = (((-l) % n) + n) % n; }
   const long long kx = ((h % n) + n) % n, ky = ((k % n) + n) % n;
-  const size_t at = a.natural ? ((size_t)kx * n + ky) * n + lz : ((size_t)lz * n + ky) * n + kx;
+  const size_t at = a.natural ? ((size_t)kx * n + ky) * a.nkz + lz : ((size_t)lz * n + ky) * n + kx;
   const cx<T> f = ((const cx<T>*)a.spec)[at];
   return (double)f.x * (double)f.x + (double)f.y * (double)f.y;
 }

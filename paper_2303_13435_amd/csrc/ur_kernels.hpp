@@ -238,11 +238,13 @@ struct MrArgs {
 // mode MR_LOAD: src -> dst, MR_GEN (axis 2): generated density -> dst,
 // MR_BIN (axis 0, forward): src -> bins
 enum MrMode { MR_LOAD = 0, MR_GEN = 1, MR_BIN = 2 };
-hipError_t launch_mr_axis(int prec, int n, int axis, int dir, int mode, const MrArgs& a, hipStream_t s);
-int mr_axis_blocks(int prec, int n, int axis, int mode);
+// r2c: a real box (two real pencils per z line, half spectrum [..][..][kz <= n/2]; forward only)
+hipError_t launch_mr_axis(int prec, int n, int axis, int dir, int mode, bool r2c, const MrArgs& a, hipStream_t s);
+int mr_axis_blocks(int prec, int n, int axis, int mode, bool r2c);
 struct MrBinArgs {
-  const void* S;            // complex [kx][ky][kz]
+  const void* S;            // complex [kx][ky][kz] (r2c: kz in [0, n/2])
   int n, nbins;
+  int r2c;                  // half spectrum of a real box: kz in (0, n/2) counted twice
   const int* U;
   const short* lut;
   int nlut;

@@ -17,6 +17,13 @@ namespace ur {
 // along z are contiguous, so a tile is TL n consecutive elements; lines
 // along y and x are taken TL consecutive z at a time, so every load and
 // store is a TL-element contiguous segment.
+// Real boxes (R2C): the z pass packs two real pencils into one complex line
+// (the first as real, the second as imaginary part), transforms it and
+// unpacks the two half spectra, A_k = (Z_k + conj Z_{N-k}) / 2 and
+// B_k = (Z_k - conj Z_{N-k}) / 2i for k in [0, N/2], into a box of
+// N x N x (N/2 + 1) elements ([x][y][kz], then [kx][ky][kz] after the x
+// pass); the y and x passes take lines of that box, and the binning counts
+// kz in (0, N/2) twice (the conjugate half).
 // ---------------------------------------------------------------------------
 constexpr int floor_pow2(int v) { int p = 1; while (2 * p <= v) p *= 2; return p; }
 constexpr int ceil_pow2(int v) { int p = 1; while (p < v) p *= 2; return p; }
@@ -38,21 +45,25 @@ template <typename T, int N, bool BIN> struct MrCfg {
   static_assert(threads % 64 == 0 && TL * LB <= 144 * 1024, "tile exceeds the LDS");
 };
 
-template <typename T, int N, int AXIS, int MODE>
+template <typename T, int N, int AXIS, int MODE, bool R2C>
 __host__ __device__ constexpr long long mr_tiles() {
   constexpr int TL = MrCfg<T, N, MODE == MR_BIN>::TL;
-  return AXIS == 2 ? ((long long)N * N + TL - 1) / TL : (long long)N * ((N + TL - 1) / TL);
+  constexpr long long LINES2 = R2C ? (long long)N * N / 2 : (long long)N * N;   // z lines (pencil pairs)
+  constexpr int NZ = R2C ? N / 2 + 1 : N;                                        // extent of the third index
+  return AXIS == 2 ? (LINES2 + TL - 1) / TL : (long long)N * ((NZ + TL - 1) / TL);
 }
 
-template <typename T, int N, int DIR, int AXIS, int MODE>
+template <typename T, int N, int DIR, int AXIS, int MODE, bool R2C>
 __global__ void __launch_bounds__((MrCfg<T, N, MODE == MR_BIN>::threads)) k_mr_axis(MrArgs a) {
   using C = MrCfg<T, N, MODE == MR_BIN>;
   constexpr int G = C::G, GP = C::GP, TL = C::TL, PS = C::PS, NT = C::threads;
   constexpr int E = Geo<N>::E, R0 = Radix<N, 1>::r, NB0 = E / R0;
   constexpr int U = cmin(8, (TL * N + NT - 1) / NT);   // loads in flight per thread
-  constexpr long long NTILE = mr_tiles<T, N, AXIS, MODE>();
+  constexpr long long NTILE = mr_tiles<T, N, AXIS, MODE, R2C>();
+  constexpr int NZ = R2C ? N / 2 + 1 : N;              // extent of the third index of the box
   static_assert(MODE != MR_GEN || AXIS == 2, "generation feeds the z pass");
   static_assert(MODE != MR_BIN || (AXIS == 0 && DIR < 0), "binning follows the forward x pass");
+  static_assert(!R2C || DIR < 0, "real boxes run the forward transform");
   __shared__ cx<T> lds[TL * PS];
   extern __shared__ double hist[];                   // MR_BIN: 2 nbins + 1
   const cx<T>* __restrict__ src = (const cx<T>*)a.src;
@@ -67,41 +78,81 @@ __global__ void __launch_bounds__((MrCfg<T, N, MODE == MR_BIN>::threads)) k_mr_a
     size_t base, es;
     int nl, o = 0, z0 = 0;
     if constexpr (AXIS == 2) {
+      // complex: lines l0 .. l0 + nl - 1; real: pencil pairs, line l holding
+      // pencils 2 (l0 + l) and 2 (l0 + l) + 1 (same x, adjacent y: N is even)
       const long long l0 = tile * TL;
-      const long long left = (long long)N * N - l0;
+      const long long left = (R2C ? (long long)N * N / 2 : (long long)N * N) - l0;
       nl = left < TL ? (int)left : TL;
-      base = (size_t)l0 * N;
+      base = (size_t)l0 * N * (R2C ? 2 : 1);
       es = 1;
     } else {
-      constexpr int nzt = (N + TL - 1) / TL;
+      constexpr int nzt = (NZ + TL - 1) / TL;
       o = (int)(tile / nzt);
       z0 = (int)(tile % nzt) * TL;
-      nl = N - z0 < TL ? N - z0 : TL;
-      base = AXIS == 1 ? (size_t)o * N * N + z0 : (size_t)o * N + z0;
-      es = AXIS == 1 ? (size_t)N : (size_t)N * N;
+      nl = NZ - z0 < TL ? NZ - z0 : TL;
+      base = AXIS == 1 ? (size_t)o * N * NZ + z0 : (size_t)o * NZ + z0;
+      es = AXIS == 1 ? (size_t)NZ : (size_t)N * NZ;
     }
     if constexpr (MODE == MR_GEN) {
       // every lane of a line's slot generates elements g, g + GP, ... of it
       const int l = t / GP, g = t % GP;
       if (l < nl) {
-        // aligned lattice (complex plans refuse rotation), level factor 1:
-        // the cell row of the pencil, inside the mask's z range
+        // aligned lattice (rotated lattices refused), level factor 1: the
+        // cell row of the pencil, inside the mask's z range
         const long long line = tile * TL + l;
-        const long long X = line / N, Y = line % N;
         const Level& L = a.z.L;
-        long long lo, hi;
-        col_range(L, a.z.m, X, Y, lo, hi);
         // periodic cell index by a true modulo: any cell edge
         const int c = L.c;
         auto wrap = [c](long long v) { const long long r = v % c; return (int)(r < 0 ? r + c : r); };
-        const T* row = (const T*)a.z.cellT + ((size_t)wrap(X - L.o - L.h) * c + wrap(Y - L.o - L.h)) * c;
         const int zoff = -(int)(L.o + L.h);
         cx<T>* col = lds + l * PS;
-        for (int e = g; e < N; e += GP) {
-          const T v = (e >= lo && e <= hi) ? row[wrap(e + zoff)] : (T)0;
-          col[pad(e)] = mk(v, (T)0);
-          s1 += (double)v;
-          s2 += (double)v * (double)v;
+        if constexpr (R2C) {
+          const long long X = (2 * line) / N, Y = (2 * line) % N;
+          long long lo, hi, lo1, hi1;
+          col_range(L, a.z.m, X, Y, lo, hi);
+          col_range(L, a.z.m, X, Y + 1, lo1, hi1);
+          const T* row = (const T*)a.z.cellT + ((size_t)wrap(X - L.o - L.h) * c + wrap(Y - L.o - L.h)) * c;
+          const T* row1 = (const T*)a.z.cellT + ((size_t)wrap(X - L.o - L.h) * c + wrap(Y + 1 - L.o - L.h)) * c;
+          for (int e = g; e < N; e += GP) {
+            const T v = (e >= lo && e <= hi) ? row[wrap(e + zoff)] : (T)0;
+            const T v1 = (e >= lo1 && e <= hi1) ? row1[wrap(e + zoff)] : (T)0;
+            col[pad(e)] = mk(v, v1);
+            s1 += (double)v + (double)v1;
+            s2 += (double)v * (double)v + (double)v1 * (double)v1;
+          }
+        } else {
+          const long long X = line / N, Y = line % N;
+          long long lo, hi;
+          col_range(L, a.z.m, X, Y, lo, hi);
+          const T* row = (const T*)a.z.cellT + ((size_t)wrap(X - L.o - L.h) * c + wrap(Y - L.o - L.h)) * c;
+          for (int e = g; e < N; e += GP) {
+            const T v = (e >= lo && e <= hi) ? row[wrap(e + zoff)] : (T)0;
+            col[pad(e)] = mk(v, (T)0);
+            s1 += (double)v;
+            s2 += (double)v * (double)v;
+          }
+        }
+      }
+    } else if constexpr (AXIS == 2 && R2C) {
+      // two real pencils per line: 2 nl N consecutive reals
+      const T* __restrict__ rs = (const T*)a.src;
+      constexpr int TOT = 2 * TL * N;
+      for (int i0 = 0; i0 < TOT; i0 += NT * U) {
+        T v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int i = i0 + u * NT + t;
+          if (i < 2 * nl * N) v[u] = rs[base + i];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int i = i0 + u * NT + t;
+          if (i < 2 * nl * N) {
+            const int j = i / N, e = i % N;
+            cx<T>& d = lds[(j >> 1) * PS + pad(e)];
+            if (j & 1) d.y = v[u]; else d.x = v[u];
+            if (a.mom) { s1 += (double)v[u]; s2 += (double)v[u] * v[u]; }
+          }
         }
       }
     } else if constexpr (AXIS == 2) {
@@ -165,6 +216,8 @@ __global__ void __launch_bounds__((MrCfg<T, N, MODE == MR_BIN>::threads)) k_mr_a
       if (l < nl) {
         const int k = sidx(o, N), lz = sidx(z0 + l, N);
         const int base2 = k * k + lz * lz;
+        // real boxes: kz in (0, N/2) stands for its conjugate too
+        const double wz = (R2C && z0 + l != 0 && 2 * (z0 + l) != N) ? 2.0 : 1.0;
         const T sc = (T)a.scale;
         const cx<T>* col = lds + l * PS;
         int cur = -2;
@@ -183,11 +236,11 @@ __global__ void __launch_bounds__((MrCfg<T, N, MODE == MR_BIN>::threads)) k_mr_a
           const int h = sidx(e, N);
           const int n2 = h * h + base2;
           const double I = ((double)f.x * f.x + (double)f.y * f.y) * a.iscale;
-          tot += I;
+          tot += wz * I;
           while (b < a.nbins && n2 >= a.U[b + 1]) ++b;
           while (b >= 0 && n2 < a.U[b]) --b;
           if (b != cur) {
-            if (cur >= 0 && cur < a.nbins) { atomicAdd(&hist[2 * cur], rs); atomicAdd(&hist[2 * cur + 1], rs2); }
+            if (cur >= 0 && cur < a.nbins) { atomicAdd(&hist[2 * cur], wz * rs); atomicAdd(&hist[2 * cur + 1], wz * rs2); }
             cur = b;
             rs = 0.0;
             rs2 = 0.0;
@@ -195,11 +248,23 @@ __global__ void __launch_bounds__((MrCfg<T, N, MODE == MR_BIN>::threads)) k_mr_a
           rs += I;
           rs2 += I * I;
         }
-        if (cur >= 0 && cur < a.nbins) { atomicAdd(&hist[2 * cur], rs); atomicAdd(&hist[2 * cur + 1], rs2); }
+        if (cur >= 0 && cur < a.nbins) { atomicAdd(&hist[2 * cur], wz * rs); atomicAdd(&hist[2 * cur + 1], wz * rs2); }
       }
     } else {
       const T sc = (T)a.scale;
-      if constexpr (AXIS == 2) {
+      if constexpr (AXIS == 2 && R2C) {
+        // unpack each line into its two pencils' half spectra: 2 nl rows of
+        // N/2 + 1 consecutive elements
+        const size_t ob = (size_t)(tile * TL) * 2 * NZ;
+        for (int i = t; i < 2 * nl * NZ; i += NT) {
+          const int j = i / NZ, k = i % NZ;
+          const cx<T>* col = lds + (j >> 1) * PS;
+          const cx<T> zk = col[pad(k)], zm = col[pad(k == 0 ? 0 : N - k)];
+          const cx<T> r = (j & 1) ? mk((zk.y + zm.y) * (T)0.5, (zm.x - zk.x) * (T)0.5)
+                                  : mk((zk.x + zm.x) * (T)0.5, (zk.y - zm.y) * (T)0.5);
+          dst[ob + i] = scale(r, sc);
+        }
+      } else if constexpr (AXIS == 2) {
         for (int i = t; i < nl * N; i += NT) dst[base + i] = scale(lds[(i / N) * PS + pad(i % N)], sc);
       } else {
         for (int i = t; i < N * TL; i += NT) {
@@ -232,33 +297,44 @@ __global__ void __launch_bounds__((MrCfg<T, N, MODE == MR_BIN>::threads)) k_mr_a
 // blocks of a pass: one tile per block, except the binning pass, whose
 // persistent blocks (at most kMrBinBlocks) each own one set of partials
 constexpr int kMrBinBlocks = 1024;
-template <int N> static int mr_blocks_t(int prec, int axis, int mode) {
+template <typename T, int N, bool R2C> static long long mr_tiles_rt(int axis, int mode) {
+  return axis == 2 ? mr_tiles<T, N, 2, 0, R2C>() : (mode == MR_BIN ? mr_tiles<T, N, 0, MR_BIN, R2C>() : mr_tiles<T, N, 1, 0, R2C>());
+}
+template <int N> static int mr_blocks_t(int prec, int axis, int mode, bool r2c) {
   long long nt;
-  if (prec == 0) nt = axis == 2 ? mr_tiles<float, N, 2, 0>() : (mode == MR_BIN ? mr_tiles<float, N, 0, MR_BIN>() : mr_tiles<float, N, 1, 0>());
-  else nt = axis == 2 ? mr_tiles<double, N, 2, 0>() : (mode == MR_BIN ? mr_tiles<double, N, 0, MR_BIN>() : mr_tiles<double, N, 1, 0>());
+  if (prec == 0) nt = r2c ? mr_tiles_rt<float, N, true>(axis, mode) : mr_tiles_rt<float, N, false>(axis, mode);
+  else nt = r2c ? mr_tiles_rt<double, N, true>(axis, mode) : mr_tiles_rt<double, N, false>(axis, mode);
   return (int)(mode == MR_BIN ? (nt < kMrBinBlocks ? nt : kMrBinBlocks) : nt);
 }
 
-template <typename T, int N, int DIR, int AXIS, int MODE>
+template <typename T, int N, int DIR, int AXIS, int MODE, bool R2C>
 static hipError_t mr_launch(const MrArgs& a, int nblk, hipStream_t s) {
   const size_t shm = MODE == MR_BIN ? (2 * (size_t)a.nbins + 1) * sizeof(double) : 0;
-  hipLaunchKernelGGL((k_mr_axis<T, N, DIR, AXIS, MODE>), dim3(nblk), dim3(MrCfg<T, N, MODE == MR_BIN>::threads), shm, s, a);
+  hipLaunchKernelGGL((k_mr_axis<T, N, DIR, AXIS, MODE, R2C>), dim3(nblk), dim3(MrCfg<T, N, MODE == MR_BIN>::threads), shm, s, a);
   return hipGetLastError();
 }
 
 template <typename T, int N>
-static hipError_t mr_axis_t(int axis, int dir, int mode, const MrArgs& a, hipStream_t s) {
-  const int nblk = mr_blocks_t<N>(sizeof(T) == 4 ? 0 : 1, axis, mode);
-  if (mode == MR_GEN) return axis == 2 && dir < 0 ? mr_launch<T, N, -1, 2, MR_GEN>(a, nblk, s) : hipErrorInvalidValue;
-  if (mode == MR_BIN) return axis == 0 && dir < 0 ? mr_launch<T, N, -1, 0, MR_BIN>(a, nblk, s) : hipErrorInvalidValue;
-  if (dir < 0) {
-    if (axis == 0) return mr_launch<T, N, -1, 0, MR_LOAD>(a, nblk, s);
-    if (axis == 1) return mr_launch<T, N, -1, 1, MR_LOAD>(a, nblk, s);
-    return mr_launch<T, N, -1, 2, MR_LOAD>(a, nblk, s);
+static hipError_t mr_axis_t(int axis, int dir, int mode, bool r2c, const MrArgs& a, hipStream_t s) {
+  const int nblk = mr_blocks_t<N>(sizeof(T) == 4 ? 0 : 1, axis, mode, r2c);
+  if (r2c) {                                         // real boxes: forward only
+    if (dir >= 0) return hipErrorInvalidValue;
+    if (mode == MR_GEN) return axis == 2 ? mr_launch<T, N, -1, 2, MR_GEN, true>(a, nblk, s) : hipErrorInvalidValue;
+    if (mode == MR_BIN) return axis == 0 ? mr_launch<T, N, -1, 0, MR_BIN, true>(a, nblk, s) : hipErrorInvalidValue;
+    if (axis == 0) return mr_launch<T, N, -1, 0, MR_LOAD, true>(a, nblk, s);
+    if (axis == 1) return mr_launch<T, N, -1, 1, MR_LOAD, true>(a, nblk, s);
+    return mr_launch<T, N, -1, 2, MR_LOAD, true>(a, nblk, s);
   }
-  if (axis == 0) return mr_launch<T, N, 1, 0, MR_LOAD>(a, nblk, s);
-  if (axis == 1) return mr_launch<T, N, 1, 1, MR_LOAD>(a, nblk, s);
-  return mr_launch<T, N, 1, 2, MR_LOAD>(a, nblk, s);
+  if (mode == MR_GEN) return axis == 2 && dir < 0 ? mr_launch<T, N, -1, 2, MR_GEN, false>(a, nblk, s) : hipErrorInvalidValue;
+  if (mode == MR_BIN) return axis == 0 && dir < 0 ? mr_launch<T, N, -1, 0, MR_BIN, false>(a, nblk, s) : hipErrorInvalidValue;
+  if (dir < 0) {
+    if (axis == 0) return mr_launch<T, N, -1, 0, MR_LOAD, false>(a, nblk, s);
+    if (axis == 1) return mr_launch<T, N, -1, 1, MR_LOAD, false>(a, nblk, s);
+    return mr_launch<T, N, -1, 2, MR_LOAD, false>(a, nblk, s);
+  }
+  if (axis == 0) return mr_launch<T, N, 1, 0, MR_LOAD, false>(a, nblk, s);
+  if (axis == 1) return mr_launch<T, N, 1, 1, MR_LOAD, false>(a, nblk, s);
+  return mr_launch<T, N, 1, 2, MR_LOAD, false>(a, nblk, s);
 }
 
 bool mr_size(int n) {
@@ -270,18 +346,18 @@ bool mr_size(int n) {
   }
 }
 
-int mr_axis_blocks(int prec, int n, int axis, int mode) {
+int mr_axis_blocks(int prec, int n, int axis, int mode, bool r2c) {
   switch (n) {
-#define UR_MR_CASE(NN) case NN: return mr_blocks_t<NN>(prec, axis, mode);
+#define UR_MR_CASE(NN) case NN: return mr_blocks_t<NN>(prec, axis, mode, r2c);
     UR_MR_SIZES(UR_MR_CASE)
 #undef UR_MR_CASE
     default: return 0;
   }
 }
 
-hipError_t launch_mr_axis(int prec, int n, int axis, int dir, int mode, const MrArgs& a, hipStream_t s) {
+hipError_t launch_mr_axis(int prec, int n, int axis, int dir, int mode, bool r2c, const MrArgs& a, hipStream_t s) {
   switch (n) {
-#define UR_MR_CASE(NN) case NN: return prec == 0 ? mr_axis_t<float, NN>(axis, dir, mode, a, s) : mr_axis_t<double, NN>(axis, dir, mode, a, s);
+#define UR_MR_CASE(NN) case NN: return prec == 0 ? mr_axis_t<float, NN>(axis, dir, mode, r2c, a, s) : mr_axis_t<double, NN>(axis, dir, mode, r2c, a, s);
     UR_MR_SIZES(UR_MR_CASE)
 #undef UR_MR_CASE
     default: return hipErrorNotSupported;
@@ -299,22 +375,24 @@ __global__ void __launch_bounds__(256) k_mr_bin(MrBinArgs a) {
   __syncthreads();
   const cx<T>* __restrict__ S = (const cx<T>*)a.S;
   const int n = a.n;
+  const int nz = a.r2c ? n / 2 + 1 : n;            // half spectrum: kz in [0, n/2], the rest conjugate
   double tot = 0.0;
   for (long long r = blockIdx.x; r < (long long)n * n; r += gridDim.x) {
     const int h = sidx((int)(r / n), n), k = sidx((int)(r % n), n);
     const int base = h * h + k * k;
-    for (int z = threadIdx.x; z < n; z += 256) {
-      const cx<T> f = S[r * n + z];
+    for (int z = threadIdx.x; z < nz; z += 256) {
+      const cx<T> f = S[r * nz + z];
       if (r == 0 && z == 0) { a.f0[0] = (double)f.x; a.f0[1] = (double)f.y; }
       const int l = sidx(z, n);
       const int n2 = base + l * l;
+      const double w = (a.r2c && z != 0 && 2 * z != n) ? 2.0 : 1.0;
       const double I = ((double)f.x * f.x + (double)f.y * f.y) * a.iscale;
-      tot += I;
+      tot += w * I;
       int b = a.lut[isqrt_ll(n2)];
       while (b < a.nbins && n2 >= a.U[b + 1]) ++b;
       if (b >= 0 && b < a.nbins) {
-        atomicAdd(&hist[2 * b], I);
-        atomicAdd(&hist[2 * b + 1], I * I);
+        atomicAdd(&hist[2 * b], w * I);
+        atomicAdd(&hist[2 * b + 1], w * I * I);
       }
     }
   }

@@ -25,7 +25,7 @@
 #define UR_X_MINW_F32 3
 #endif
 #ifndef UR_X_MINW_F64
-#define UR_X_MINW_F64 2
+#define UR_X_MINW_F64 1
 #endif
 
 // pass Z, real FP32 columns up to 1024 points: pencil pairs per block (a

@@ -45,7 +45,7 @@ CHOICES = {
     "UR_Z_PAIRS_F32": ((8, 4, 2), (0, 1, 5, 6, 7, 9), ("pass_z", "pass_y"), ("f32",)),
     "UR_ZI_PAIRS_F32": ((8, 4), (0, 5, 6), ("fwd_adjoint",), ("f32",)),
     "UR_Z_XCD": ((0, 1), (1, 7, 9), ("pass_z",), ("f32",)),
-    "UR_ST_NT_A": ((1, 0), (1, 2), ("pass_z", "pass_y"), ("f32", "f64")),
+    "UR_ST_NT_A": ((1, 0), (1, 2), ("pass_z", "pass_y"), ("f32",)),
     "UR_ST_NT_B": ((1, 0), (5,), ("pass_y", "pass_x"), ("f32", "f64")),
     "UR_LD_NT": ((1, 0), (3, 4, 5), ("pass_y", "pass_x"), ("f32", "f64")),
     "UR_LD_SKIP_Y": ((1, 0), (5,), ("pass_y",), ("f32", "f64")),
@@ -228,16 +228,22 @@ def pick(results_paths) -> None:
     import numpy as np
     if isinstance(results_paths, str):
         results_paths = [results_paths]
-    recs = [json.loads(ln) for path in results_paths for ln in open(path) if ln.strip()]
-    by_name = {r["candidate"]["name"]: r for r in recs if "result" in r}
-    if "default" not in by_name:
-        raise SystemExit("no timing of the default candidate")
-    ref = by_name["default"]["result"]
+    # one timing run per file, each with its own timing of the default: a
+    # macro's candidates are judged against the default of their own run
+    runs = []
+    for path in results_paths:
+        recs = [json.loads(ln) for ln in open(path) if ln.strip()]
+        runs.append({r["candidate"]["name"]: r for r in recs if "result" in r})
+    if not all("default" in run for run in runs):
+        raise SystemExit("every timing run needs its timing of the default candidate")
+    ref = runs[0]["default"]["result"]
     base = defaults()
     chosen = dict(base)
     rows = []
     for m, (vals, _, passes, precs) in CHOICES.items():
         best, best_t = base[m], None
+        by_name = next((run for run in runs if any(k.startswith(m + "=") for k in run)), runs[0])
+        ref = by_name["default"]["result"]
         for v in vals:
             name = "default" if v == base[m] else f"{m}={v}"
             r = by_name.get(name)
@@ -277,11 +283,13 @@ def write_tuned(chosen: dict) -> None:
 def write_table(rows, chosen, ref) -> None:
     lines = ["# Tuning of the compile-time choices: M1024 (1024^3, sphere R = 400, 512 log bins)", "",
              "Command: `python -m paper_2303_13435_amd.tune build` (CPU), then on the GPU",
-             "`python -m paper_2303_13435_amd.tune run <out>.jsonl`, then `python -m paper_2303_13435_amd.tune pick <out>.jsonl`.",
+             "`python -m paper_2303_13435_amd.tune run <out>.jsonl [MACRO ...]` (one or more runs, each timing the candidates of",
+             "the macros it names and the default), then `python -m paper_2303_13435_amd.tune pick <out>.jsonl [<out2>.jsonl ...]`.",
              "Each candidate changes one macro of `csrc/ur_tuned.hpp` from the values it held; its library is timed in",
              "a process of its own (20 steps after 3 warm-up steps, per-pass HIP events).  A value is chosen on the",
              "passes it affects; a candidate whose curve differs from the default's by more than 1e-6 is rejected;",
-             "a change must win by more than 1 %.", "",
+             "a change must win by more than 1 %.  When the candidates were timed in several runs, each macro is",
+             "judged against the default timed in its own run (its row of the current value shows that timing).", "",
              "The 2048^3 column is the ED-1 level of the multi-zoom batch (FP32, per-pass HIP events).", "",
              "| macro | value | FP32 step ms | FP32 pass Z / Y / X ms | FP32 fwd+adjoint ms | FP64 step ms | FP64 pass Z / Y / X ms | FP64 fwd+adjoint ms | 2048^3 FP32 pass Z / Y / X ms | note |",
              "|---|---|---|---|---|---|---|---|---|---|"]

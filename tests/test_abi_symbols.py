@@ -52,7 +52,7 @@ def test_version_and_errors_without_gpu(built_lib):
     assert built_lib.ur_plan_create(120, 1.0, 0, 0, ctypes.byref(h)) == 1       # neither 2^a nor a mixed-radix edge
     built_lib.ur_last_error.restype = ctypes.c_char_p
     assert b"power of two" in built_lib.ur_last_error()
-    assert built_lib.ur_plan_create(100, 1.0, 0, 0, ctypes.byref(h)) == 2       # mixed radix: complex only
+    assert built_lib.ur_plan_create(100, 1.0, 0, 2, ctypes.byref(h)) == 1       # unknown flag
     assert built_lib.ur_plan_create(64, -1.0, 0, 0, ctypes.byref(h)) == 1       # bad voxel
     assert built_lib.ur_plan_create(64, 1.0, 7, 0, ctypes.byref(h)) == 1        # bad precision
     # box limits: 4096^3 only in FP32 real, nothing above; complex only up to 1024^3
