@@ -56,6 +56,7 @@ typedef enum {
   UR_ERR_UNSUPPORTED = 2,  /* valid request the library does not implement  */
   UR_ERR_OOM = 3,          /* device allocation failed                        */
   UR_ERR_HIP = 4,          /* a HIP runtime call failed                       */
+  UR_ERR_HOST = 5,         /* host memory (pageable or page-locked) unavailable */
   UR_ERR_STATE = 6         /* call out of order (e.g. no bins set on the plan) */
 } ur_status;
 

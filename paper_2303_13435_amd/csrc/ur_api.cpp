@@ -446,7 +446,7 @@ ur_status ur_plan_create(int32_t n, double voxel, int32_t prec, uint32_t flags, 
   if (prec != UR_F32 && prec != UR_F64) return fail(UR_ERR_INVALID, "prec must be UR_F32 or UR_F64");
   if (flags & ~1u) return fail(UR_ERR_INVALID, "unknown flags 0x%x", flags);
   ur_plan* p = new (std::nothrow) ur_plan();
-  if (!p) return fail(UR_ERR_OOM, "plan allocation failed");
+  if (!p) return fail(UR_ERR_HOST, "plan allocation failed");
   p->n = n;
   p->voxel = voxel;
   p->prec = prec;
@@ -461,7 +461,7 @@ ur_status ur_plan_create(int32_t n, double voxel, int32_t prec, uint32_t flags, 
   try {
     st = make_twiddles(p);
   } catch (...) {
-    st = fail(UR_ERR_OOM, "host allocation failed while building the twiddle tables");
+    st = fail(UR_ERR_HOST, "host allocation failed while building the twiddle tables");
   }
   if (st != UR_OK) { ur_plan_destroy(p); return st; }
   *out = p;
@@ -545,7 +545,7 @@ static ur_status rebuild_weights(ur_plan* p, bool vox, int bt_f) {
       }
       if (p->prec == UR_F32) v32.assign(v64.begin(), v64.end());
     } catch (...) {
-      return fail(UR_ERR_OOM, "host allocation failed for the intensity weight table");
+      return fail(UR_ERR_HOST, "host allocation failed for the intensity weight table");
     }
   }
   if (p->dSinc) { UR_HIP(hipDeviceSynchronize()); UR_HIP(hipFree(p->dSinc)); p->dSinc = nullptr; }
@@ -632,7 +632,7 @@ ur_status ur_plan_set_bins(ur_plan* p, int32_t nbins, const double* edges) {
   try {
     return set_bins_impl(p, nbins, edges);
   } catch (...) {
-    return fail(UR_ERR_OOM, "host allocation failed while setting the bins");
+    return fail(UR_ERR_HOST, "host allocation failed while setting the bins");
   }
 }
 
@@ -1332,7 +1332,7 @@ ur_status ur_simulate_host(ur_plan* p, const void* rho_host, int32_t x_lo, int32
     if (hipHostMalloc(&p->bounce, K * slab_bytes, hipHostMallocDefault) != hipSuccess) {
       (void)hipGetLastError();
       p->bounce = nullptr;
-      return fail(UR_ERR_OOM, "pinned bounce allocation failed");
+      return fail(UR_ERR_HOST, "pinned bounce allocation failed");
     }
     p->bounce_bytes = K * slab_bytes;
   }
@@ -1434,7 +1434,7 @@ ur_status ur_host_alloc(size_t bytes, void** out) {
   if (hipHostMalloc(out, bytes, hipHostMallocDefault) != hipSuccess) {
     (void)hipGetLastError();
     *out = nullptr;
-    return fail(UR_ERR_OOM, "pinned host allocation of %zu bytes failed", bytes);
+    return fail(UR_ERR_HOST, "pinned host allocation of %zu bytes failed", bytes);
   }
   return UR_OK;
 }
