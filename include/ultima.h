@@ -273,6 +273,11 @@ ur_status ur_simulate_noalloc(ur_plan* plan, const ur_cell* cell, const ur_mask*
  * one slab of the first intermediate and the x range of the spectrum (or,
  * under an HBM budget, a kz chunk of it per pass: ur_plan_set_hbm_budget).
  * The staging and bounce buffers are allocated by the plan on first use.
+ * Real mixed-radix plans: slabs of 8 planes are transformed along z (two
+ * real pencils per complex line) and y as they arrive, into a half spectrum
+ * that holds only planes x_lo..x_hi; the x pass reads the other planes as
+ * zero (no HBM budget: the planes' half spectrum must fit).  Complex plans
+ * are refused (UR_ERR_UNSUPPORTED).
  * The host buffer must stay valid until the stream is synchronised.
  * *h2d_bytes (when non-null) receives the bytes copied host to device. */
 ur_status ur_simulate_host(ur_plan* plan, const void* rho_host, int32_t x_lo, int32_t x_hi,

@@ -192,6 +192,20 @@ static Layout layout_incore(const ur_plan* p, int nbins) {
 
 // mixed-radix layout: the complex box (transformed in place), block
 // partials, F(0) and the per-pencil moments
+// the out-of-core box of a real mixed-radix plan: only planes [x_lo, x_hi]
+// (nx of them) of the half spectrum
+static Layout layout_mixed_ooc(const ur_plan* p, int nbins, size_t nx) {
+  Layout L;
+  const size_t n = p->n;
+  L.A = 0;
+  L.B = 0;
+  L.part = align256(nx * n * (size_t)p->nkz * p->cs);
+  L.mom = align256(L.part + (size_t)kMaxXBlocks * (2 * (size_t)std::max(nbins, 1) + 1) * 8);
+  L.f0 = align256(L.mom + n * n * 16);
+  L.total = align256(L.f0 + 64 + 256 * 8);
+  return L;
+}
+
 static Layout layout_mixed(const ur_plan* p, int nbins) {
   Layout L;
   const size_t n = p->n;
@@ -506,6 +520,10 @@ ur_status ur_plan_workspace_size_host(const ur_plan* p, int32_t nbins, int32_t x
   if (!p || !bytes) return fail(UR_ERR_INVALID, "null argument");
   if (nbins < 1) return fail(UR_ERR_INVALID, "nbins must be >= 1");
   if (x_lo < 0 || x_hi >= p->n || x_lo > x_hi) return fail(UR_ERR_INVALID, "plane range [%d, %d] outside the box", x_lo, x_hi);
+  if (p->mixed) {
+    *bytes = layout_mixed_ooc(p, nbins, (size_t)(x_hi - x_lo + 1)).total;
+    return UR_OK;
+  }
   OocSplit o;
   UR_TRY(ooc_split(p, nbins, x_lo, x_hi, o));
   *bytes = o.lay.total;
@@ -1293,13 +1311,128 @@ ur_status ur_intensity_bin(ur_plan* p, const void* spectrum, const ur_hist* h, v
   return UR_OK;
 }
 
+}  // extern "C"
+
+// Staging of the out-of-core paths: K slabs of `slab_bytes` on the device
+// and, for pageable input, as many page-locked bounce slabs; the copy
+// streams and their events
+static ur_status ensure_staging(ur_plan* p, size_t slab_bytes, bool pinned) {
+  constexpr int K = ur_plan::kStage;
+  if (!p->stage || p->stage_bytes < K * slab_bytes) {
+    UR_HIP(hipDeviceSynchronize());
+    if (p->stage) UR_HIP(hipFree(p->stage));
+    p->stage = nullptr;
+    if (hipMalloc(&p->stage, K * slab_bytes) != hipSuccess) { (void)hipGetLastError(); return fail(UR_ERR_OOM, "staging allocation failed"); }
+    p->stage_bytes = K * slab_bytes;
+  }
+  if (!pinned && (!p->bounce || p->bounce_bytes < K * slab_bytes)) {
+    UR_HIP(hipDeviceSynchronize());
+    if (p->bounce) UR_HIP(hipHostFree(p->bounce));
+    p->bounce = nullptr;
+    if (hipHostMalloc(&p->bounce, K * slab_bytes, hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      p->bounce = nullptr;
+      return fail(UR_ERR_HOST, "pinned bounce allocation failed");
+    }
+    p->bounce_bytes = K * slab_bytes;
+  }
+  for (auto& c : p->copy_stream) if (!c) UR_HIP(hipStreamCreateWithFlags(&c, hipStreamNonBlocking));
+  for (auto& e : p->ev_copied) if (!e) UR_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  for (auto& e : p->ev_free) if (!e) UR_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  return UR_OK;
+}
+
+// Out-of-core forward path of a real mixed-radix box (eq. 2 with the second
+// stage in HBM): slabs of planes [x_lo, x_hi] stream from host memory into
+// the staging buffers; each slab is transformed along z (two real pencils
+// per complex line, half spectra) and along y right away, into a box that
+// holds only the planes of [x_lo, x_hi]; the x pass then takes every (ky,
+// kz) line of that box with the other planes read as zero, and bins.
+static ur_status simulate_host_mixed(ur_plan* p, const void* rho_host, int x_lo, int x_hi, const ur_hist* h,
+                                     hipStream_t s, size_t* h2d_bytes, bool pinned) {
+  const int n = p->n;
+  const size_t nx = (size_t)(x_hi - x_lo + 1);
+  const Layout lay = layout_mixed_ooc(p, p->nbins, nx);
+  UR_TRY(ensure_ws(p, lay.total, s));
+  const size_t plane_bytes = (size_t)n * n * p->rs;
+  const int ts = 8;                                       // planes per slab
+  const size_t slab_bytes = (size_t)ts * plane_bytes;
+  UR_TRY(ensure_staging(p, slab_bytes, pinned));
+  constexpr int K = ur_plan::kStage;
+  char* box = p->ws;
+  const size_t box_plane = (size_t)n * p->nkz * p->cs;    // bytes of one x plane of the box
+  double* mom = (double*)(p->ws + lay.mom);
+  const int tl = mr_tile_lines(p->prec, n);
+  for (int b = 0; b < K; ++b) {
+    UR_HIP(hipEventRecord(p->ev_free[b], s));
+    UR_HIP(hipEventRecord(p->ev_copied[b], p->copy_stream[b]));
+  }
+  size_t copied = 0;
+  long long zb = 0;
+  long long slab = 0;
+  for (long long lo = x_lo; lo <= x_hi; lo += ts, ++slab) {
+    const long long hi = std::min<long long>(lo + ts - 1, x_hi);
+    const int buf = (int)(slab % K);
+    hipStream_t cs = p->copy_stream[buf];
+    char* st = (char*)p->stage + buf * slab_bytes;
+    const char* src = (const char*)rho_host + (size_t)(lo - x_lo) * plane_bytes;
+    const size_t len = (size_t)(hi - lo + 1) * plane_bytes;
+    if (!pinned) {
+      char* bb = (char*)p->bounce + buf * slab_bytes;
+      UR_HIP(hipEventSynchronize(p->ev_copied[buf]));
+      parallel_copy(bb, src, len);
+      src = bb;
+    }
+    UR_HIP(hipStreamWaitEvent(cs, p->ev_free[buf], 0));
+    UR_HIP(hipMemcpyAsync(st, src, len, hipMemcpyHostToDevice, cs));
+    copied += len;
+    UR_HIP(hipEventRecord(p->ev_copied[buf], cs));
+    UR_HIP(hipStreamWaitEvent(s, p->ev_copied[buf], 0));
+    char* dst = box + (size_t)(lo - x_lo) * box_plane;
+    MrArgs a{};
+    a.tw = p->tw; a.src = st; a.dst = dst; a.scale = 1.0;
+    a.lines = (long long)(hi - lo + 1) * n / 2;           // pencil pairs of the slab
+    a.mom = mom + 2 * (size_t)zb;
+    {
+      PassTimer tm(p, P_Z, s);
+      UR_HIP(launch_mr_axis(p->prec, n, 2, -1, MR_LOAD, true, a, s));
+    }
+    zb += (a.lines + tl - 1) / tl;
+    UR_HIP(hipEventRecord(p->ev_free[buf], s));
+    MrArgs y{};
+    y.tw = p->tw; y.src = dst; y.dst = dst; y.scale = 1.0;
+    y.planes = (int)(hi - lo + 1);
+    {
+      PassTimer tm(p, P_Y, s);
+      UR_HIP(launch_mr_axis(p->prec, n, 1, -1, MR_LOAD, true, y, s));
+    }
+  }
+  MrArgs x{};
+  x.tw = p->tw; x.src = box; x.dst = box; x.xa = x_lo; x.xn = (int)nx;
+  x.scale = 1.0 / ((double)n * n * n);
+  x.nbins = p->nbins; x.U = p->dU; x.lut = p->dLut; x.iscale = 1.0;
+  x.part = (double*)(p->ws + lay.part); x.f0 = (double*)(p->ws + lay.f0);
+  {
+    PassTimer tm(p, P_X, s);
+    UR_HIP(launch_mr_axis(p->prec, n, 0, -1, MR_BIN, true, x, s));
+  }
+  const double boxb = (double)nx * n * p->nkz * p->cs;
+  p->pass_bytes[P_CELL] = 0.0;
+  p->pass_bytes[P_Z] = (double)nx * n * n * p->rs + boxb;
+  p->pass_bytes[P_Y] = 2.0 * boxb;
+  p->pass_bytes[P_X] = boxb;
+  if (h2d_bytes) *h2d_bytes = copied;
+  return mr_finalize(p, lay, mr_axis_blocks(p->prec, n, 0, MR_BIN, true), h, (int)zb, s);
+}
+
+extern "C" {
+
 ur_status ur_simulate_host(ur_plan* p, const void* rho_host, int32_t x_lo, int32_t x_hi, const ur_hist* h,
                            void* stream, size_t* h2d_bytes) {
   if (p) p->keep_valid = false;
   if (!p || !rho_host) return fail(UR_ERR_INVALID, "null argument");
   if (p->nbins < 1) return fail(UR_ERR_STATE, "no bins set on the plan");
   if (p->flags & UR_C2C) return fail(UR_ERR_UNSUPPORTED, "the out-of-core path takes real densities (UR_R2C plans)");
-  if (p->mixed) return fail(UR_ERR_UNSUPPORTED, "the out-of-core path runs power-of-two boxes");
   if (x_lo < 0 || x_hi >= p->n || x_lo > x_hi) return fail(UR_ERR_INVALID, "plane range [%d, %d] outside the box", x_lo, x_hi);
   UR_TRY(check_hist(h));
   hipStream_t s = (hipStream_t)stream;
@@ -1309,6 +1442,10 @@ ur_status ur_simulate_host(ur_plan* p, const void* rho_host, int32_t x_lo, int32
   if (cst != hipStreamCaptureStatusNone) return fail(UR_ERR_STATE, "the out-of-core path is a host-driven pipeline and cannot be captured");
   const HostKind hk = host_kind(rho_host);
   if (hk == HOST_DEVICE) return fail(UR_ERR_INVALID, "rho_host is device memory (ur_simulate_rho takes device densities)");
+  if (p->mixed) {
+    if (p->dSinc) return fail(UR_ERR_UNSUPPORTED, "mixed-radix boxes run without the voxel form factor and block-transfer correction");
+    return simulate_host_mixed(p, rho_host, x_lo, x_hi, h, s, h2d_bytes, hk == HOST_PINNED);
+  }
   const int n = p->n, tx = y_tile(p->prec, n);
   OocSplit split;
   UR_TRY(ooc_split(p, p->nbins, x_lo, x_hi, split));

@@ -233,6 +233,13 @@ struct MrArgs {
   double iscale;
   double* part;             // nblk x (2 nbins + 1)
   double* f0;
+  // part of a box (out-of-core): z pass over `lines` z lines (real boxes:
+  // pencil pairs) from src, y pass over `planes` x planes of dst, x pass
+  // over a box that stores only planes [xa, xa + xn) (the rest read as zero);
+  // 0: the whole box
+  long long lines;
+  int planes;
+  int xa, xn;
 };
 // axis 0 = x (stride n^2), 1 = y (stride n), 2 = z (contiguous);
 // mode MR_LOAD: src -> dst, MR_GEN (axis 2): generated density -> dst,
@@ -241,6 +248,7 @@ enum MrMode { MR_LOAD = 0, MR_GEN = 1, MR_BIN = 2 };
 // r2c: a real box (two real pencils per z line, half spectrum [..][..][kz <= n/2]; forward only)
 hipError_t launch_mr_axis(int prec, int n, int axis, int dir, int mode, bool r2c, const MrArgs& a, hipStream_t s);
 int mr_axis_blocks(int prec, int n, int axis, int mode, bool r2c);
+int mr_tile_lines(int prec, int n);
 struct MrBinArgs {
   const void* S;            // complex [kx][ky][kz] (r2c: kz in [0, n/2])
   int n, nbins;

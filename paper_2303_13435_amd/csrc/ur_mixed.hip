@@ -59,8 +59,14 @@ __global__ void __launch_bounds__((MrCfg<T, N, MODE == MR_BIN>::threads)) k_mr_a
   constexpr int G = C::G, GP = C::GP, TL = C::TL, PS = C::PS, NT = C::threads;
   constexpr int E = Geo<N>::E, R0 = Radix<N, 1>::r, NB0 = E / R0;
   constexpr int U = cmin(8, (TL * N + NT - 1) / NT);   // loads in flight per thread
-  constexpr long long NTILE = mr_tiles<T, N, AXIS, MODE, R2C>();
   constexpr int NZ = R2C ? N / 2 + 1 : N;              // extent of the third index of the box
+  constexpr int NZT = (NZ + TL - 1) / TL;
+  // tiles of this launch: the whole box, or the lines / planes given
+  const long long NTILE = AXIS == 2 ? (a.lines > 0 ? (a.lines + TL - 1) / TL : mr_tiles<T, N, AXIS, MODE, R2C>())
+                        : AXIS == 1 ? (long long)(a.planes > 0 ? a.planes : N) * NZT
+                                    : mr_tiles<T, N, AXIS, MODE, R2C>();
+  const long long LINES = a.lines > 0 ? a.lines : (R2C ? (long long)N * N / 2 : (long long)N * N);
+  const int XA = a.xn > 0 ? a.xa : 0, XN = a.xn > 0 ? a.xn : N;   // stored x planes (x pass)
   static_assert(MODE != MR_GEN || AXIS == 2, "generation feeds the z pass");
   static_assert(MODE != MR_BIN || (AXIS == 0 && DIR < 0), "binning follows the forward x pass");
   static_assert(!R2C || DIR < 0, "real boxes run the forward transform");
@@ -81,12 +87,12 @@ __global__ void __launch_bounds__((MrCfg<T, N, MODE == MR_BIN>::threads)) k_mr_a
       // complex: lines l0 .. l0 + nl - 1; real: pencil pairs, line l holding
       // pencils 2 (l0 + l) and 2 (l0 + l) + 1 (same x, adjacent y: N is even)
       const long long l0 = tile * TL;
-      const long long left = (R2C ? (long long)N * N / 2 : (long long)N * N) - l0;
+      const long long left = LINES - l0;
       nl = left < TL ? (int)left : TL;
       base = (size_t)l0 * N * (R2C ? 2 : 1);
       es = 1;
     } else {
-      constexpr int nzt = (NZ + TL - 1) / TL;
+      constexpr int nzt = NZT;
       o = (int)(tile / nzt);
       z0 = (int)(tile % nzt) * TL;
       nl = NZ - z0 < TL ? NZ - z0 : TL;
@@ -180,7 +186,15 @@ __global__ void __launch_bounds__((MrCfg<T, N, MODE == MR_BIN>::threads)) k_mr_a
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const int i = i0 + u * NT + t;
-          if (i < TOT && i % TL < nl) v[u] = src[base + (size_t)(i / TL) * es + i % TL];
+          if (i < TOT && i % TL < nl) {
+            if constexpr (AXIS == 0) {
+              // element e of the x line: stored planes [XA, XA + XN) only
+              const int e = i / TL;
+              v[u] = (e >= XA && e < XA + XN) ? src[base + (size_t)(e - XA) * es + i % TL] : mk((T)0, (T)0);
+            } else {
+              v[u] = src[base + (size_t)(i / TL) * es + i % TL];
+            }
+          }
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -316,7 +330,14 @@ static hipError_t mr_launch(const MrArgs& a, int nblk, hipStream_t s) {
 
 template <typename T, int N>
 static hipError_t mr_axis_t(int axis, int dir, int mode, bool r2c, const MrArgs& a, hipStream_t s) {
-  const int nblk = mr_blocks_t<N>(sizeof(T) == 4 ? 0 : 1, axis, mode, r2c);
+  int nblk = mr_blocks_t<N>(sizeof(T) == 4 ? 0 : 1, axis, mode, r2c);
+  {
+    // part of a box: one tile per block over the lines / planes given
+    constexpr int TL = MrCfg<T, N, false>::TL, NZ1 = N / 2 + 1;
+    if (axis == 2 && a.lines > 0 && mode != MR_BIN) nblk = (int)((a.lines + TL - 1) / TL);
+    if (axis == 1 && a.planes > 0) nblk = a.planes * (((r2c ? NZ1 : N) + TL - 1) / TL);
+  }
+  if (nblk <= 0) return hipSuccess;
   if (r2c) {                                         // real boxes: forward only
     if (dir >= 0) return hipErrorInvalidValue;
     if (mode == MR_GEN) return axis == 2 ? mr_launch<T, N, -1, 2, MR_GEN, true>(a, nblk, s) : hipErrorInvalidValue;
@@ -343,6 +364,17 @@ bool mr_size(int n) {
     UR_MR_SIZES(UR_MR_CASE) return true;
 #undef UR_MR_CASE
     default: return false;
+  }
+}
+
+// z lines per tile of the loading and generating passes (the block count of
+// a partial z pass is ceil(lines / that))
+int mr_tile_lines(int prec, int n) {
+  switch (n) {
+#define UR_MR_CASE(NN) case NN: return prec == 0 ? MrCfg<float, NN, false>::TL : MrCfg<double, NN, false>::TL;
+    UR_MR_SIZES(UR_MR_CASE)
+#undef UR_MR_CASE
+    default: return 0;
   }
 }
 

@@ -203,6 +203,52 @@ def test_mixed_real_boxes(ur, orc, n, prec):
     torch.cuda.synchronize()
 
 
+@pytest.mark.parametrize("n,prec,pinned", [(100, 1, True), (250, 0, False), (40, 0, True)])
+def test_mixed_out_of_core(ur, orc, n, prec, pinned):
+    """Real mixed-radix boxes streamed from host memory (page-locked, or
+    pageable through the bounce slabs): slabs of planes transformed along z
+    and y as they arrive into a box of only the particle's planes, then the
+    x pass with the other planes read as zero; against the whole oracle,
+    and against the in-HBM real plan; a truncated octahedron whose planes do
+    not start at a slab boundary."""
+    import torch
+    from dataclasses import replace
+    wl = replace(W.mixed(n, prec, nbins=60), mask=W.trunc_oct(0.37 * n), transform="r2c")
+    _say(f"mixed out-of-core n={n} prec={prec} pinned={pinned}")
+    ref = orc.simulate(wl, return_fields=True)
+    rho = ref["rho"]
+    nz = np.flatnonzero(np.any(rho != 0.0, axis=(1, 2)))
+    x_lo, x_hi = int(nz.min()), int(nz.max())
+    host = torch.empty((x_hi - x_lo + 1, n, n), dtype=torch.float32 if prec == 0 else torch.float64, pin_memory=pinned)
+    host.copy_(torch.as_tensor(rho[x_lo:x_hi + 1]))
+    plan = ur.Plan(n, wl.voxel, prec)
+    plan.set_bins(wl.edges)
+    h = ur.Hist(wl.nbins)
+    nbytes = plan.simulate_host(host, x_lo, x_hi, h)
+    torch.cuda.synchronize()
+    got = h.numpy()
+    assert nbytes == (x_hi - x_lo + 1) * n * n * host.element_size()
+    tol = F32_BIN if prec == 0 else F64_BIN
+    compare_bins(got, ref, tol, "mixed out-of-core", n=n)
+    rt = 1e-6 if prec == 0 else 1e-12
+    assert abs(got["totals"][3] - ref["rho_sumsq"]) <= rt * ref["rho_sumsq"]
+    assert abs(got["totals"][1] - ref["totals"][1]) <= rt * abs(ref["totals"][1])
+    p2 = ur.Plan(n, wl.voxel, prec)
+    p2.set_bins(wl.edges)
+    h2 = ur.Hist(wl.nbins)
+    p2.simulate(ur.DeviceCell.from_host(wl.cell), wl.mask, wl.zoom, h2)
+    torch.cuda.synchronize()
+    b = h2.numpy()
+    pop = ref["count"] > 0
+    assert np.array_equal(got["count"], b["count"])
+    assert np.allclose(got["mean"][pop], b["mean"][pop], rtol=1e-12 if prec == 1 else 1e-6, atol=0.0)
+    cplan = ur.Plan(n, wl.voxel, prec, c2c=True)
+    cplan.set_bins(wl.edges)
+    with pytest.raises(ur.UltimaError, match="status 2"):
+        cplan.simulate_host(host, x_lo, x_hi, h)
+    torch.cuda.synchronize()
+
+
 def test_mixed_2000_counts_and_moments(ur, orc):
     """The 2000^3 FP32 box of the family (64 GB complex box in HBM): counts of
     all 256 bins bit-exact (O12 counts, axis by axis), Parseval, F(0) and the
