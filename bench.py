@@ -447,13 +447,14 @@ def out_of_core(ur, W, torch, wl, reps, pinned=True):
     return out
 
 
-def ooc4096_child():
-    """Run `bench.py --ooc4096-only` as a child process (its progress notes go
-    to this process's stderr) and return its result, or an error record."""
+def ooc4096_child(flag="--ooc4096-only"):
+    """Run `bench.py --ooc4096-only` (or `--ooc4000-only`) as a child process
+    (its progress notes go to this process's stderr) and return its result,
+    or an error record."""
     import subprocess
-    note("out-of-core C5_4096 in a child process")
+    note(f"out-of-core {flag} in a child process")
     try:
-        r = subprocess.run([sys.executable, os.path.abspath(__file__), "--ooc4096-only"], stdout=subprocess.PIPE,
+        r = subprocess.run([sys.executable, os.path.abspath(__file__), flag], stdout=subprocess.PIPE,
                            text=True, timeout=900)
     except subprocess.TimeoutExpired:
         return {"error": "timed out after 900 s"}
@@ -473,6 +474,9 @@ def main():
     ap.add_argument("--n", type=int, default=1024, help="box edge (1024 = the headline workload)")
     ap.add_argument("--no-ooc4096", action="store_true",
                     help="skip the 4096^3 out-of-core box (212 GiB of host memory, about 90 s, in a child process)")
+    ap.add_argument("--ooc4000-only", action="store_true",
+                    help="only stream the out-of-core recipe at the paper's ED-1 edge 4000 (real mixed-radix plan) "
+                         "and print its result (the child of the full run)")
     ap.add_argument("--mixed-radix-only", action="store_true",
                     help="time only the mixed-radix boxes (1000^3, 2000^3) and print their JSON")
     ap.add_argument("--ooc4096-only", action="store_true",
@@ -509,6 +513,11 @@ def main():
         # than a process may page-lock here: pageable memory through the
         # bounce slabs), 229 GB of spectrum in HBM
         print(json.dumps(out_of_core(ur, W, torch, W.c5(4096), 2, pinned=False)))
+        return
+    if args.ooc4000_only:
+        # the out-of-core recipe at 4000^3 (2^5 5^3): truncated octahedron
+        # R = 1855, pageable host memory, half spectrum of its planes in HBM
+        print(json.dumps(out_of_core(ur, W, torch, W.c5(4000), 2, pinned=False)))
         return
     if args.mixed_radix_only:
         # the mixed-radix boxes alone (M1000 FP32/FP64, M2000 FP32)
@@ -629,6 +638,8 @@ def main():
             del plan
             torch.cuda.empty_cache()
             extras["out_of_core_c5_4096"] = ooc4096_child()
+            # the same recipe at the paper's ED-1 edge, 4000 (mixed radix)
+            extras["out_of_core_c5_4000_mixed"] = ooc4096_child("--ooc4000-only")
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -163,11 +163,11 @@ constexpr int pow2_part(int n) { return n & -n; }
 template <int N> struct Mixed {
   static_assert(N % 2 == 0, "mixed-radix edges are even");
   static constexpr int odd = (N % 3 == 0 ? 3 : 1) * (N % 5 == 0 ? 5 : 1);
-  // the smallest power-of-two cap (at most 8) that keeps a line in one
+  // the smallest power-of-two cap (at most 16) that keeps a line in one
   // wavefront: fewer elements per lane, fewer registers
   static constexpr int pick() {
     int p = 2;                                     // every compiled edge is even
-    while (p < 8 && p < pow2_part(N) && N / (p * odd) > 64) p *= 2;
+    while (p < 16 && p < pow2_part(N) && N / (p * odd) > 64) p *= 2;
     return p < pow2_part(N) ? p : pow2_part(N);
   }
   static constexpr int P = pick();

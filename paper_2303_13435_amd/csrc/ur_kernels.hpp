@@ -217,7 +217,7 @@ hipError_t launch_merge(const MergeArgs& a, hipStream_t s);
 // the compiled mixed-radix edges: the 2^a 5^3 family of the paper's boxes and
 // zoom levels (250 ... 2000) with smaller members for tests, and 2^a 3
 #define UR_MR_SIZES(X) X(40) X(80) X(100) X(160) X(200) X(250) X(400) X(500) X(1000) X(2000) \
-                       X(48) X(96) X(384) X(768) X(1536)
+                       X(48) X(96) X(384) X(768) X(1536) X(4000)
 
 bool mr_size(int n);
 struct MrArgs {

@@ -330,6 +330,9 @@ static hipError_t mr_launch(const MrArgs& a, int nblk, hipStream_t s) {
 
 template <typename T, int N>
 static hipError_t mr_axis_t(int axis, int dir, int mode, bool r2c, const MrArgs& a, hipStream_t s) {
+  if constexpr (N > 2048 && sizeof(T) != 4) {
+    return hipErrorNotSupported;                     // edges above 2048: FP32 real plans only
+  } else {
   int nblk = mr_blocks_t<N>(sizeof(T) == 4 ? 0 : 1, axis, mode, r2c);
   {
     // part of a box: one tile per block over the lines / planes given
@@ -346,16 +349,21 @@ static hipError_t mr_axis_t(int axis, int dir, int mode, bool r2c, const MrArgs&
     if (axis == 1) return mr_launch<T, N, -1, 1, MR_LOAD, true>(a, nblk, s);
     return mr_launch<T, N, -1, 2, MR_LOAD, true>(a, nblk, s);
   }
-  if (mode == MR_GEN) return axis == 2 && dir < 0 ? mr_launch<T, N, -1, 2, MR_GEN, false>(a, nblk, s) : hipErrorInvalidValue;
-  if (mode == MR_BIN) return axis == 0 && dir < 0 ? mr_launch<T, N, -1, 0, MR_BIN, false>(a, nblk, s) : hipErrorInvalidValue;
-  if (dir < 0) {
-    if (axis == 0) return mr_launch<T, N, -1, 0, MR_LOAD, false>(a, nblk, s);
-    if (axis == 1) return mr_launch<T, N, -1, 1, MR_LOAD, false>(a, nblk, s);
-    return mr_launch<T, N, -1, 2, MR_LOAD, false>(a, nblk, s);
+  if constexpr (N > 2048) {
+    return hipErrorNotSupported;                     // complex plans run edges up to 2048
+  } else {
+    if (mode == MR_GEN) return axis == 2 && dir < 0 ? mr_launch<T, N, -1, 2, MR_GEN, false>(a, nblk, s) : hipErrorInvalidValue;
+    if (mode == MR_BIN) return axis == 0 && dir < 0 ? mr_launch<T, N, -1, 0, MR_BIN, false>(a, nblk, s) : hipErrorInvalidValue;
+    if (dir < 0) {
+      if (axis == 0) return mr_launch<T, N, -1, 0, MR_LOAD, false>(a, nblk, s);
+      if (axis == 1) return mr_launch<T, N, -1, 1, MR_LOAD, false>(a, nblk, s);
+      return mr_launch<T, N, -1, 2, MR_LOAD, false>(a, nblk, s);
+    }
+    if (axis == 0) return mr_launch<T, N, 1, 0, MR_LOAD, false>(a, nblk, s);
+    if (axis == 1) return mr_launch<T, N, 1, 1, MR_LOAD, false>(a, nblk, s);
+    return mr_launch<T, N, 1, 2, MR_LOAD, false>(a, nblk, s);
   }
-  if (axis == 0) return mr_launch<T, N, 1, 0, MR_LOAD, false>(a, nblk, s);
-  if (axis == 1) return mr_launch<T, N, 1, 1, MR_LOAD, false>(a, nblk, s);
-  return mr_launch<T, N, 1, 2, MR_LOAD, false>(a, nblk, s);
+  }
 }
 
 bool mr_size(int n) {
