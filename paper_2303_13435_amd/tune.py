@@ -9,7 +9,8 @@ candidate's curve equals the default's, and writes the winners into
 csrc/ur_tuned.hpp with the table of candidates and timings in
 profiles/tuning_M1024.md.
 
-    python -m paper_2303_13435_amd.tune build          # CPU: the candidate libraries
+    python -m paper_2303_13435_amd.tune build [MACRO ...]  # CPU: the candidate libraries (of those
+                                                            # macros only, and the default)
     python -m paper_2303_13435_amd.tune run OUT.jsonl [MACRO ...]  # GPU: time them (one process per
                                                                     # library; only those macros' candidates)
     python -m paper_2303_13435_amd.tune pick OUT.jsonl [OUT2.jsonl ...]  # CPU: write ur_tuned.hpp and the table
@@ -63,11 +64,14 @@ def defaults() -> dict:
     return out
 
 
-def candidates():
-    """(name, overrides): the default, then one macro changed at a time."""
+def candidates(macros=()):
+    """(name, overrides): the default, then one macro changed at a time (of
+    the named macros only, when given)."""
     base = defaults()
     out = [("default", {})]
     for m, (vals, _, _, _) in CHOICES.items():
+        if macros and m not in macros:
+            continue
         for v in vals:
             if v != base[m]:
                 out.append((f"{m}={v}", {m: v}))
@@ -78,12 +82,12 @@ def _safe(name: str) -> str:
     return re.sub(r"[^A-Za-z0-9_.=-]", "_", name)
 
 
-def build_all() -> None:
+def build_all(macros=()) -> None:
     from . import build as B
     B.build()                                       # default objects of every source
     objdir = os.path.join(HERE, "_build")
     jobs = []
-    for name, over in candidates():
+    for name, over in candidates(macros):
         if not over:
             continue
         parts = sorted({p for m in over for p in CHOICES[m][1]})
@@ -91,11 +95,11 @@ def build_all() -> None:
         out = os.path.join(objdir, "tune", _safe(name))
         os.makedirs(out, exist_ok=True)
         for k in parts:
-            jobs.append((name, k, defs, os.path.join(out, f"ur_kernels.p{k}.o")))
+            jobs.append((name, "ur_kernels.hip", [f"-DUR_PART={k}"] + defs, os.path.join(out, f"ur_kernels.p{k}.o")))
     t0 = time.perf_counter()
     with cf.ThreadPoolExecutor(max_workers=os.cpu_count() or 4) as ex:
-        list(ex.map(lambda j: B._compile_one("ur_kernels.hip", j[3], [f"-DUR_PART={j[1]}"] + j[2]), jobs))
-    for name, over in candidates():
+        list(ex.map(lambda j: B._compile_one(j[1], j[3], j[2]), jobs))
+    for name, over in candidates(macros):
         lib_dir = os.path.join(LIBDIR, _safe(name))
         os.makedirs(lib_dir, exist_ok=True)
         parts = {p for m in over for p in CHOICES[m][1]}
@@ -116,7 +120,7 @@ def build_all() -> None:
             raise RuntimeError(f"link of {name} failed")
         with open(os.path.join(lib_dir, "candidate.json"), "w") as fh:
             json.dump({"name": name, "overrides": over}, fh)
-    print(f"built {len(candidates())} candidate libraries in {time.perf_counter() - t0:.0f} s under {LIBDIR}")
+    print(f"built {len(candidates(macros))} candidate libraries in {time.perf_counter() - t0:.0f} s under {LIBDIR}")
 
 
 def measure(steps: int = 20) -> dict:
@@ -151,7 +155,8 @@ def measure(steps: int = 20) -> dict:
         plan.set_timing(False)
         mean = h.mean.cpu().numpy()
         out[tag] = {"step_ms": e0.elapsed_time(e1) / steps,
-                    "passes": {k: v["ms"] / v["launches"] for k, v in t.items() if v["launches"]},
+                    "passes": dict({k: v["ms"] / v["launches"] for k, v in t.items() if v["launches"]},
+                                   step=e0.elapsed_time(e1) / steps),
                     "mean": [float(x) for x in np.nan_to_num(mean, nan=-1.0)]}
         # forward + adjoint to the 40 amplitudes (recomputing the forward
         # passes): the inverse passes' choices are judged on it
@@ -181,6 +186,13 @@ def measure(steps: int = 20) -> dict:
     cell = ur.DeviceCell.from_host(wl.cell)
     h = ur.Hist(wl.nbins)
     plan.simulate(cell, wl.mask, wl.zoom, h)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(max(3, steps // 4)):
+        plan.simulate(cell, wl.mask, wl.zoom, h)
+    e1.record()
+    torch.cuda.synchronize()
+    out["f32"]["passes"]["step_2048"] = e0.elapsed_time(e1) / max(3, steps // 4)
     plan.set_timing(True)
     for _ in range(max(3, steps // 4)):
         plan.simulate(cell, wl.mask, wl.zoom, h)
@@ -317,7 +329,7 @@ def main(argv) -> None:
         raise SystemExit(__doc__)
     cmd = argv[0]
     if cmd == "build":
-        build_all()
+        build_all(tuple(argv[1:]))
     elif cmd == "run":
         run_all(argv[1] if len(argv) > 1 else os.path.join(ROOT, "gpurun_out", "tune.jsonl"), tuple(argv[2:]))
     elif cmd == "measure":
