@@ -149,22 +149,27 @@ typedef struct ur_plan ur_plan;
  * ur_plan_set_workspace or allocated lazily on first use.  Errors:
  * UR_ERR_INVALID for n neither a power of two nor a mixed-radix edge (below), a voxel that is not positive and
  * finite, or an unknown precision; UR_ERR_UNSUPPORTED for n above 4096, for
- * n = 4096 in FP64 or complex, or for a complex (UR_C2C) plan above 1024.
- * A 4096^3 plan runs only ur_plan_set_bins, ur_rho_generate, ur_cell_synth
- * and the out-of-core path (ur_simulate_host and its workspace query); its
- * other calls fail with UR_ERR_UNSUPPORTED.
- * Mixed-radix edges (boxes of the paper's 4000/16 = 250 family, Methodology,
+ * n above 2048 in FP64 or complex, or for a complex (UR_C2C) power-of-two
+ * plan above 1024.  A plan above 2048 (4096, or the mixed-radix 4000) runs
+ * only ur_plan_set_bins, ur_rho_generate, ur_cell_synth and the out-of-core
+ * path (ur_simulate_host and its workspace query); its other calls fail
+ * with UR_ERR_UNSUPPORTED.
+ * Mixed-radix edges (boxes of the paper's 4000 family, Methodology,
  * "Electron density generation"): n = 40, 80, 100, 160, 200, 250, 400, 500,
- * 1000, 2000, 48, 96, 384, 768 or 1536 make a complex plan (UR_C2C required,
- * else UR_ERR_UNSUPPORTED) whose transform runs one axis at a time through
- * radix 2/4/8, 3 and 5 stages; its spectrum (ur_fft3d_exec, and the input of
- * ur_intensity_bin and ur_ewald_image) is in natural order [kx][ky][kz].
- * Such plans run ED-1 levels (zoom n1 = n, factor 1) and zoom levels (any
- * factor dividing an even n1, such as the paper's 125; power-of-two cells)
- * through ur_simulate, ur_simulate_rho (complex density), ur_rho_generate,
- * ur_fft3d_exec, ur_intensity_bin and ur_ewald_image; the adjoint and the
- * voxel form factor fail with UR_ERR_UNSUPPORTED.  Other edges that are not
- * powers of two fail with UR_ERR_INVALID. */
+ * 1000, 2000, 4000, 48, 96, 384, 768 or 1536 make a plan whose transform
+ * runs one axis at a time, in place, through radix 2/4/8/16, 3 and 5
+ * stages; its spectrum (ur_fft3d_exec, and the input of ur_intensity_bin
+ * and ur_ewald_image) is in natural order [kx][ky][kz], kz in [0, n/2] on a
+ * real plan (two real z pencils per complex line, unpacked into their half
+ * spectra; forward transform only) and in [0, n) on a complex one.  Such
+ * plans run ED-1 levels (zoom n1 = n, factor 1, any cell edge up to 256)
+ * and zoom levels (any factor dividing an even n1, such as the paper's 125;
+ * power-of-two cells) through ur_simulate, ur_simulate_rho (a real density
+ * on real plans, complex on complex ones), ur_simulate_host (real plans),
+ * ur_rho_generate, ur_fft3d_exec, ur_intensity_bin and ur_ewald_image; the
+ * adjoint, oriented lattices, the voxel form factor and the block-transfer
+ * correction fail with UR_ERR_UNSUPPORTED.  Other edges that are not powers
+ * of two fail with UR_ERR_INVALID. */
 ur_status ur_plan_create(int32_t n, double voxel, int32_t prec, uint32_t flags, ur_plan** out);
 void ur_plan_destroy(ur_plan* plan);
 
@@ -228,7 +233,7 @@ ur_status ur_simulate(ur_plan* plan, const ur_cell* cell, const ur_mask* mask,
 /* Fused forward path from a given density (workflow steps 4-5: eq. 1 axis by
  * axis as eq. 2 separates it, then the spherical averaging of section
  * "Q-calculation and spherical averaging"): rho DEVICE, n^3 reals of the plan
- * precision [x][y][z] (complex values on mixed-radix plans). */
+ * precision [x][y][z] (complex values on complex plans, UR_C2C). */
 ur_status ur_simulate_rho(ur_plan* plan, const void* rho, const ur_hist* hist, void* stream);
 
 /* Allocation-free variant of ur_simulate, for callers that cannot allocate

@@ -222,15 +222,16 @@ template <int K> struct PadOff { static constexpr int v = K + (K >> 4); };
 // x[b + r N/R], twiddles exp(DIR 2 pi i r j/(L R)) with j = b mod L, outputs
 // y[(b/L) L R + j + r L].  Every LDS address is one padded base per
 // butterfly plus a compile-time offset.
-template <typename T, int N, int L, int DIR>
+// TWH: the stage's twiddles are loaded ahead of its LDS reads (their
+// latency overlaps the reads and the fence; E R-1 values held at once) or
+// else at each butterfly (fewer live registers).
+template <typename T, int N, int L, int DIR, bool TWH = true>
 __device__ __forceinline__ void stage_lds(cx<T>* s, int g, const cx<T>* __restrict__ tw) {
   constexpr int E = Geo<N>::E, G = Geo<N>::G, R = Radix<N, L>::r, NB = E / R;
   constexpr int NR = N / R;
   static_assert(NB * R == E, "radix must divide the per-lane count");
-  // twiddles first: their loads do not depend on the column, and issued
-  // ahead of the LDS reads and the fence their latency overlaps both
   cx<T> w[NB][R > 1 ? R - 1 : 1];
-  if (L > 1) {
+  if (L > 1 && TWH) {
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
       const cx<T>* wp = tw + (tw_off<N>(L) + ((g + G * i) % L) * (R - 1));
@@ -256,6 +257,11 @@ __device__ __forceinline__ void stage_lds(cx<T>* s, int g, const cx<T>* __restri
     const int b = g + G * i;
     const int j = b % L;
     if (L > 1) {
+      if constexpr (!TWH) {
+        const cx<T>* wp = tw + (tw_off<N>(L) + j * (R - 1));
+#pragma unroll
+        for (int r = 1; r < R; ++r) w[i][r - 1] = wp[r - 1];
+      }
 #pragma unroll
       for (int r = 1; r < R; ++r) v[i][r] = DIR < 0 ? cmul(v[i][r], w[i][r - 1]) : cmulc(v[i][r], w[i][r - 1]);
     }
@@ -273,11 +279,11 @@ __device__ __forceinline__ void stage_lds(cx<T>* s, int g, const cx<T>* __restri
   col_sync<G>();
 }
 
-template <typename T, int N, int L, int DIR>
+template <typename T, int N, int L, int DIR, bool TWH = true>
 __device__ __forceinline__ void stages_from(cx<T>* s, int g, const cx<T>* __restrict__ tw) {
   if constexpr (L < N) {
-    stage_lds<T, N, L, DIR>(s, g, tw);
-    stages_from<T, N, L * Radix<N, L>::r, DIR>(s, g, tw);
+    stage_lds<T, N, L, DIR, TWH>(s, g, tw);
+    stages_from<T, N, L * Radix<N, L>::r, DIR, TWH>(s, g, tw);
   }
 }
 
@@ -285,7 +291,7 @@ __device__ __forceinline__ void stages_from(cx<T>* s, int g, const cx<T>* __rest
 // inputs in the order v[i*R0 + r] = x[b + r*(N/R0)], b = g + G*i, with R0 the
 // first radix. Results of the whole transform are left in natural order in
 // the LDS column s (padded indexing).
-template <typename T, int N, int DIR>
+template <typename T, int N, int DIR, bool TWH = true>
 __device__ __forceinline__ void fft_column(cx<T>* s, int g, const cx<T>* __restrict__ tw, cx<T>* v) {
   constexpr int E = Geo<N>::E, G = Geo<N>::G, R = Radix<N, 1>::r, NB = E / R;
 #pragma unroll
@@ -302,7 +308,7 @@ __device__ __forceinline__ void fft_column(cx<T>* s, int g, const cx<T>* __restr
     }
   }
   col_sync<G>();
-  stages_from<T, N, R, DIR>(s, g, tw);
+  stages_from<T, N, R, DIR, TWH>(s, g, tw);
 }
 
 // Index of the r-th input of lane g's i-th first-stage butterfly.

@@ -1112,7 +1112,7 @@ k_pass_x(XArgs a) {
   // the number of columns a multiple of NG, so every group of a block runs
   // the same iterations.
   const int q = G >= 64 ? __builtin_amdgcn_readfirstlane(threadIdx.x / G) : threadIdx.x / G;
-  const int g = threadIdx.x % G;
+  const int g0 = threadIdx.x % G;
   cx<T>* s = sm + q * PS;
   const cx<T>* tw = (const cx<T>*)a.tw;
   constexpr bool BIN = MODE != X_FFT_STORE;
@@ -1129,8 +1129,13 @@ k_pass_x(XArgs a) {
   const long long stride = (long long)gridDim.x * NG;
   long long col = (long long)blockIdx.x * NG + q;
   cx<T> v[E];
-  if (!BINONLY && col < a.ncols) x_load_column<T, N>(a, col, g, v);
+  if (!BINONLY && col < a.ncols) x_load_column<T, N>(a, col, g0, v);
   for (; col < a.ncols; col += stride) {
+    // UR_X_REFETCH: the lane index is opaque in every column, so that the
+    // lane's twiddles and LDS offsets are reloaded and recomputed per column
+    // instead of held in registers across the loop
+    int g = g0;
+    if constexpr (UR_X_REFETCH) asm volatile("" : "+v"(g));
     const int kz = a.kz0 + (int)(col / N), ky = (int)(col % N);
     if (BINONLY) {
       const cx<T>* src = (const cx<T>*)a.B + (size_t)col * a.bs - a.bx0;

@@ -25,22 +25,37 @@ namespace ur {
 // pass); the y and x passes take lines of that box, and the binning counts
 // kz in (0, N/2) twice (the conjugate half).
 // ---------------------------------------------------------------------------
+#ifndef UR_MR_CAP
+#define UR_MR_CAP 0
+#endif
 constexpr int floor_pow2(int v) { int p = 1; while (2 * p <= v) p *= 2; return p; }
 constexpr int ceil_pow2(int v) { int p = 1; while (p < v) p *= 2; return p; }
 constexpr int cmin(int a, int b) { return a < b ? a : b; }
 
 // Lines per tile: at most 64 (and 1024 threads), within 72 KB of LDS so that
 // two blocks share a CU, but at least 8 (64-byte segments along y and x)
-// when 144 KB allow it; the binning x pass keeps 94 KB for the tile so the
-// histogram (up to 4096 bins) fits beside it.
+// when 144 KB allow it; the binning x pass keeps 76 KB for the tile so the
+// histogram and its thresholds (up to 4096 bins: 82 KB) fit beside it.
 template <typename T, int N, bool BIN> struct MrCfg {
   static constexpr int G = Geo<N>::G, GP = ceil_pow2(G);
   static constexpr int PS = Padded<N>::size, LB = PS * (int)sizeof(cx<T>);
   static constexpr int TL0 = cmin(64, 1024 / GP);
-  static constexpr int TLa = floor_pow2(cmin(TL0, (BIN ? 94 * 1024 : 72 * 1024) / LB > 0 ? (BIN ? 94 * 1024 : 72 * 1024) / LB : 1));
+  static constexpr int TLa = floor_pow2(cmin(TL0, (BIN ? 76 * 1024 : 72 * 1024) / LB > 0 ? (BIN ? 76 * 1024 : 72 * 1024) / LB : 1));
   static constexpr int TLb = floor_pow2(cmin(cmin(TL0, 8), (144 * 1024) / LB > 0 ? (144 * 1024) / LB : 1));
   static constexpr int TL = (BIN || TLa >= 8) ? TLa : (TLb > TLa ? TLb : TLa);
   static constexpr int threads = TL * GP < 64 ? 64 : TL * GP;
+  // UR_MR_CAP: FP32 lines of up to 24 elements per lane get registers for
+  // two blocks per CU (the LDS holds two tiles; unbounded, the compiler
+  // takes up to 256 VGPRs and leaves one block per CU).  Off: at 1000
+  // points the cap spills 400-500 bytes per lane and the y pass of a
+  // 1000^3 box takes 9.1 ms instead of 5.0.
+  static constexpr int minw = (UR_MR_CAP && sizeof(T) == 4 && Geo<N>::E <= 24) ? cmin(4, threads / 128 > 0 ? threads / 128 : 1) : 1;
+  // twiddles of a stage loaded ahead of it (more registers, more overlap),
+  // except where two blocks per CU need 128 VGPRs or fewer: FP32 blocks of
+  // 512 threads or more whose tile leaves room for a second, which load them
+  // at each butterfly (1000^3: 11.0 ms per box against 14.4 with the hoist;
+  // 2000^3, one block of 8 waves or two of 4: 112 ms against 129 without it)
+  static constexpr bool twh = sizeof(T) != 4 || threads < 512 || TL * LB > 72 * 1024;
   static_assert(G <= 64, "mixed-radix lines lie in one wavefront");
   static_assert(threads % 64 == 0 && TL * LB <= 144 * 1024, "tile exceeds the LDS");
 };
@@ -54,11 +69,13 @@ __host__ __device__ constexpr long long mr_tiles() {
 }
 
 template <typename T, int N, int DIR, int AXIS, int MODE, bool R2C>
-__global__ void __launch_bounds__((MrCfg<T, N, MODE == MR_BIN>::threads)) k_mr_axis(MrArgs a) {
+__global__ void __launch_bounds__((MrCfg<T, N, MODE == MR_BIN>::threads), (MrCfg<T, N, MODE == MR_BIN>::minw)) k_mr_axis(MrArgs a) {
   using C = MrCfg<T, N, MODE == MR_BIN>;
   constexpr int G = C::G, GP = C::GP, TL = C::TL, PS = C::PS, NT = C::threads;
   constexpr int E = Geo<N>::E, R0 = Radix<N, 1>::r, NB0 = E / R0;
-  constexpr int U = cmin(8, (TL * N + NT - 1) / NT);   // loads in flight per thread
+  // loads in flight per thread: 16 FP32 elements outside the binning pass
+  // (32 VGPRs), else 8
+  constexpr int U = cmin(sizeof(T) == 4 && MODE != MR_BIN ? 16 : 8, (TL * N + NT - 1) / NT);
   constexpr int NZ = R2C ? N / 2 + 1 : N;              // extent of the third index of the box
   constexpr int NZT = (NZ + TL - 1) / TL;
   // tiles of this launch: the whole box, or the lines / planes given
@@ -71,16 +88,27 @@ __global__ void __launch_bounds__((MrCfg<T, N, MODE == MR_BIN>::threads)) k_mr_a
   static_assert(MODE != MR_BIN || (AXIS == 0 && DIR < 0), "binning follows the forward x pass");
   static_assert(!R2C || DIR < 0, "real boxes run the forward transform");
   __shared__ cx<T> lds[TL * PS];
-  extern __shared__ double hist[];                   // MR_BIN: 2 nbins + 1
+  // MR_BIN: 2 nbins + 1 sums, then the thresholds Us[b + 1] = U[b] for b in
+  // [0, nbins] between two sentinels (Us[0] below every n2, Us[nbins + 2]
+  // above), so the bin walk reads LDS and needs no range tests
+  extern __shared__ double hist[];
   const cx<T>* __restrict__ src = (const cx<T>*)a.src;
   cx<T>* __restrict__ dst = (cx<T>*)a.dst;
   const int t = threadIdx.x;
   const int nv = 2 * a.nbins + 1;
+  int* Us = (int*)(hist + nv);
   if constexpr (MODE == MR_BIN) {
     for (int i = t; i < nv; i += NT) hist[i] = 0.0;
+    for (int i = t; i <= a.nbins; i += NT) Us[i + 1] = a.U[i];
+    if (t == 0) { Us[0] = -1; Us[a.nbins + 2] = 0x7fffffff; }
   }
   double s1 = 0.0, s2 = 0.0, tot = 0.0;
   for (long long tile = blockIdx.x; tile < NTILE; tile += gridDim.x) {
+    // the thread index is made opaque in every tile, so that the index
+    // arithmetic of the loads, stores and transform stages (which depends on
+    // the lane only) is not hoisted out of the tile loop into live registers
+    int t = threadIdx.x;
+    asm volatile("" : "+v"(t));
     size_t base, es;
     int nl, o = 0, z0 = 0;
     if constexpr (AXIS == 2) {
@@ -112,6 +140,10 @@ __global__ void __launch_bounds__((MrCfg<T, N, MODE == MR_BIN>::threads)) k_mr_a
         auto wrap = [c](long long v) { const long long r = v % c; return (int)(r < 0 ? r + c : r); };
         const int zoff = -(int)(L.o + L.h);
         cx<T>* col = lds + l * PS;
+        // cell index of element e: wrap(e + zoff), advanced by GP mod c per
+        // step (32-bit adds instead of a 64-bit remainder per element)
+        const int cstep = GP % c;
+        int ci = wrap(g + zoff);
         if constexpr (R2C) {
           const long long X = (2 * line) / N, Y = (2 * line) % N;
           long long lo, hi, lo1, hi1;
@@ -119,23 +151,29 @@ __global__ void __launch_bounds__((MrCfg<T, N, MODE == MR_BIN>::threads)) k_mr_a
           col_range(L, a.z.m, X, Y + 1, lo1, hi1);
           const T* row = (const T*)a.z.cellT + ((size_t)wrap(X - L.o - L.h) * c + wrap(Y - L.o - L.h)) * c;
           const T* row1 = (const T*)a.z.cellT + ((size_t)wrap(X - L.o - L.h) * c + wrap(Y + 1 - L.o - L.h)) * c;
+          const int ilo = (int)lo, ihi = (int)hi, ilo1 = (int)lo1, ihi1 = (int)hi1;
           for (int e = g; e < N; e += GP) {
-            const T v = (e >= lo && e <= hi) ? row[wrap(e + zoff)] : (T)0;
-            const T v1 = (e >= lo1 && e <= hi1) ? row1[wrap(e + zoff)] : (T)0;
+            const T v = (e >= ilo && e <= ihi) ? row[ci] : (T)0;
+            const T v1 = (e >= ilo1 && e <= ihi1) ? row1[ci] : (T)0;
             col[pad(e)] = mk(v, v1);
             s1 += (double)v + (double)v1;
             s2 += (double)v * (double)v + (double)v1 * (double)v1;
+            ci += cstep;
+            if (ci >= c) ci -= c;
           }
         } else {
           const long long X = line / N, Y = line % N;
           long long lo, hi;
           col_range(L, a.z.m, X, Y, lo, hi);
           const T* row = (const T*)a.z.cellT + ((size_t)wrap(X - L.o - L.h) * c + wrap(Y - L.o - L.h)) * c;
+          const int ilo = (int)lo, ihi = (int)hi;
           for (int e = g; e < N; e += GP) {
-            const T v = (e >= lo && e <= hi) ? row[wrap(e + zoff)] : (T)0;
+            const T v = (e >= ilo && e <= ihi) ? row[ci] : (T)0;
             col[pad(e)] = mk(v, (T)0);
             s1 += (double)v;
             s2 += (double)v * (double)v;
+            ci += cstep;
+            if (ci >= c) ci -= c;
           }
         }
       }
@@ -217,7 +255,7 @@ __global__ void __launch_bounds__((MrCfg<T, N, MODE == MR_BIN>::threads)) k_mr_a
 #pragma unroll
           for (int r = 0; r < R0; ++r) v[i * R0 + r] = col[pad(first_index<N>(g, i, r))];
         wave_sync();
-        fft_column<T, N, DIR>(col, g, (const cx<T>*)a.tw, v);
+        fft_column<T, N, DIR, C::twh>(col, g, (const cx<T>*)a.tw, v);
       }
     }
     __syncthreads();
@@ -251,8 +289,8 @@ __global__ void __launch_bounds__((MrCfg<T, N, MODE == MR_BIN>::threads)) k_mr_a
           const int n2 = h * h + base2;
           const double I = ((double)f.x * f.x + (double)f.y * f.y) * a.iscale;
           tot += wz * I;
-          while (b < a.nbins && n2 >= a.U[b + 1]) ++b;
-          while (b >= 0 && n2 < a.U[b]) --b;
+          while (n2 >= Us[b + 2]) ++b;
+          while (n2 < Us[b + 1]) --b;
           if (b != cur) {
             if (cur >= 0 && cur < a.nbins) { atomicAdd(&hist[2 * cur], wz * rs); atomicAdd(&hist[2 * cur + 1], wz * rs2); }
             cur = b;
@@ -323,7 +361,7 @@ template <int N> static int mr_blocks_t(int prec, int axis, int mode, bool r2c) 
 
 template <typename T, int N, int DIR, int AXIS, int MODE, bool R2C>
 static hipError_t mr_launch(const MrArgs& a, int nblk, hipStream_t s) {
-  const size_t shm = MODE == MR_BIN ? (2 * (size_t)a.nbins + 1) * sizeof(double) : 0;
+  const size_t shm = MODE == MR_BIN ? (2 * (size_t)a.nbins + 1) * sizeof(double) + ((size_t)a.nbins + 3) * sizeof(int) : 0;
   hipLaunchKernelGGL((k_mr_axis<T, N, DIR, AXIS, MODE, R2C>), dim3(nblk), dim3(MrCfg<T, N, MODE == MR_BIN>::threads), shm, s, a);
   return hipGetLastError();
 }

@@ -67,3 +67,9 @@
 #ifndef UR_LD_NT
 #define UR_LD_NT 1
 #endif
+
+// pass X: twiddles and LDS offsets reloaded per column (1) or held in
+// registers across the column loop (0)
+#ifndef UR_X_REFETCH
+#define UR_X_REFETCH 0
+#endif

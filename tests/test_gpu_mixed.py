@@ -418,3 +418,32 @@ def test_mixed_zoom_level(ur, orc, n, n1, f, prec):
     torch.cuda.synchronize()
     err = np.max(np.abs(rho.cpu().numpy().astype(np.float64) - ref["rho"])) / np.max(np.abs(ref["rho"]))
     assert err <= (1e-6 if prec == 0 else 1e-14)
+
+
+@pytest.mark.parametrize("n,transform", [(40, "c2c"), (40, "r2c"), (32, "r2c"), (32, "c2c")])
+def test_maximum_bin_count(ur, orc, n, transform):
+    """4096 bins, the most a plan accepts: the binning x passes then keep
+    82 KB of histogram and thresholds in LDS (beside the mixed-radix tile,
+    beside the power-of-two columns), and most bins of a small box are
+    empty.  ur_simulate and ur_intensity_bin against the oracle."""
+    import torch
+    from dataclasses import replace
+    wl = replace(W.mixed(n, 0, nbins=4096), transform=transform)
+    _say(f"maximum bin count n={n} {transform}")
+    ref = orc.simulate(wl, return_fields=True)
+    plan = ur.Plan(n, wl.voxel, 0, c2c=transform == "c2c")
+    plan.set_bins(wl.edges)
+    h = ur.Hist(wl.nbins)
+    plan.simulate(ur.DeviceCell.from_host(wl.cell), wl.mask, wl.zoom, h)
+    torch.cuda.synchronize()
+    got = h.numpy()
+    assert np.count_nonzero(got["count"]) < wl.nbins
+    compare_bins(got, ref, F32_BIN, "4096 bins simulate", n=n)
+    F = ref["F"] if transform == "c2c" else ref["F"][:, :, :n // 2 + 1]
+    if n & (n - 1) == 0:                               # power-of-two plans: [kz][ky][kx]
+        F = np.transpose(F, (2, 1, 0))
+    F = np.ascontiguousarray(F)
+    h2 = ur.Hist(wl.nbins)
+    plan.intensity_bin(torch.as_tensor(F, dtype=plan.complex_dtype, device="cuda"), h2)
+    torch.cuda.synchronize()
+    compare_bins(h2.numpy(), ref, F32_BIN, "4096 bins intensity_bin", n=n)
