@@ -923,40 +923,70 @@ static ur_status run_y_x(ur_plan* p, const FwdGeom& g, char* A, char* B, const L
 // mixed-radix passes in place on S: z (from `src`, or generated from `gen`,
 // with per-block moments into `mom` when given), y, then x (scaled by 1/n^3
 // forward); with `lay` the forward x pass bins |F|^2 instead of storing it
-// (block partials and F(0) at their places in the workspace).
+// (block partials and F(0) at their places in the workspace).  With `region`
+// (the level whose density src holds or gen generates) the binning path is
+// pruned as the power-of-two passes are: the z pass leaves the lines of
+// pencils outside the region unwritten, the y pass runs the region's planes
+// only and reads rows outside each plane's row range as zero, and the x pass
+// reads those planes and takes the others as zero.
 static ur_status mr_transform(ur_plan* p, const void* src, void* S, int dir, double* mom, const ZArgs* gen,
-                              const Layout* lay, hipStream_t s) {
+                              const Layout* lay, hipStream_t s, const ZArgs* region = nullptr) {
   const int n = p->n;
   const bool r2c = !(p->flags & UR_C2C);
   if (r2c && dir > 0) return fail(UR_ERR_UNSUPPORTED, "real mixed-radix plans run the forward transform only");
   MrArgs a{};
   a.tw = p->tw; a.dst = S; a.mom = mom; a.src = src; a.scale = 1.0;
   if (gen) a.z = *gen;
+  long long xlo = 0, xhi = n - 1;
+  double rows = (double)n * n;                       // (x, y) lines that hold data
+  if (region && lay && dir < 0) {
+    plane_range(region->L, region->m, xlo, xhi);
+    if (xlo <= xhi) {
+      a.z.L = region->L;
+      a.z.m = region->m;
+      a.prune = 1;
+      rows = 0.0;
+      for (long long x = xlo; x <= xhi; ++x) {
+        long long lo, hi;
+        row_range(region->L, region->m, x, lo, hi);
+        if (lo <= hi) rows += (double)(hi - lo + 1);
+      }
+    } else {
+      xlo = 0;
+      xhi = n - 1;
+    }
+  }
+  const size_t plane = (size_t)n * p->nkz * p->cs;   // one x plane of the box
   {
     PassTimer tm(p, P_Z, s);
     UR_HIP(launch_mr_axis(p->prec, n, 2, dir, gen ? MR_GEN : MR_LOAD, r2c, a, s));
   }
   a.src = S; a.mom = nullptr;
+  if (a.prune) { a.px0 = (int)xlo; a.planes = (int)(xhi - xlo + 1); }
   {
     PassTimer tm(p, P_Y, s);
     UR_HIP(launch_mr_axis(p->prec, n, 1, dir, MR_LOAD, r2c, a, s));
   }
+  a.px0 = 0; a.planes = 0;
   a.scale = dir < 0 ? 1.0 / ((double)n * n * n) : 1.0;
   if (lay) {
     a.nbins = p->nbins; a.U = p->dU; a.lut = p->dLut; a.iscale = 1.0;
     a.part = (double*)(p->ws + lay->part); a.f0 = (double*)(p->ws + lay->f0);
   }
+  if (a.prune) { a.src = (const char*)S + (size_t)xlo * plane; a.xa = (int)xlo; a.xn = (int)(xhi - xlo + 1); }
   {
     PassTimer tm(p, P_X, s);
     UR_HIP(launch_mr_axis(p->prec, n, 0, dir, lay ? MR_BIN : MR_LOAD, r2c, a, s));
   }
-  // algorithmic bytes: the box of nkz complex elements per (x, y) line; a
-  // real input of n reals per line
-  const double box = (double)n * n * p->nkz * p->cs;
-  const double in = r2c ? (double)n * n * n * p->rs : box;
-  p->pass_bytes[P_Z] = (gen ? 0.0 : in) + box;
-  p->pass_bytes[P_Y] = 2.0 * box;
-  p->pass_bytes[P_X] = (lay ? 1.0 : 2.0) * box;
+  // algorithmic bytes: nkz complex elements per (x, y) line that holds data
+  // (z pass writes, y pass reads), per line of the planes run (y pass
+  // writes, x pass reads); a real input of n reals per line
+  const double nx = (double)(xhi - xlo + 1);
+  const double line = (double)p->nkz * p->cs;
+  const double in = r2c ? rows * n * p->rs : rows * line;
+  p->pass_bytes[P_Z] = (gen ? 0.0 : in) + rows * line;
+  p->pass_bytes[P_Y] = rows * line + nx * n * line;
+  p->pass_bytes[P_X] = (lay ? 1.0 : 2.0) * nx * n * line;
   return UR_OK;
 }
 
@@ -1070,17 +1100,17 @@ ur_status ur_simulate(ur_plan* p, const ur_cell* cell, const ur_mask* mask, cons
         // the three passes from it (the z pass pairs its real pencils)
         UR_TRY(ensure_level_buf(p, (size_t)p->n * p->n * p->n * p->rs, s));
         UR_HIP(launch_rho_generate(p->prec, p->n, 0, p->n - 1, za, p->lvl_buf, s));
-        UR_TRY(mr_transform(p, p->lvl_buf, p->ws + lay.A, -1, mom, nullptr, &lay, s));
+        UR_TRY(mr_transform(p, p->lvl_buf, p->ws + lay.A, -1, mom, nullptr, &lay, s, &za));
         return mr_finalize(p, lay, mr_axis_blocks(p->prec, p->n, 0, MR_BIN, true), h,
                            mr_axis_blocks(p->prec, p->n, 2, MR_LOAD, true), s);
       }
       // zoom level: block sums of ED-1 written as a complex box first, then
       // the three passes from it (the generating z pass serves ED-1 only)
       UR_HIP(launch_level_complex(p->prec, p->n, za, p->ws + lay.A, mom, s));
-      UR_TRY(mr_transform(p, p->ws + lay.A, p->ws + lay.A, -1, nullptr, nullptr, &lay, s));
+      UR_TRY(mr_transform(p, p->ws + lay.A, p->ws + lay.A, -1, nullptr, nullptr, &lay, s, &za));
       return mr_finalize(p, lay, mr_axis_blocks(p->prec, p->n, 0, MR_BIN, false), h, p->n * p->n, s);
     }
-    UR_TRY(mr_transform(p, nullptr, p->ws + lay.A, -1, mom, &za, &lay, s));
+    UR_TRY(mr_transform(p, nullptr, p->ws + lay.A, -1, mom, &za, &lay, s, &za));
     return mr_finalize(p, lay, mr_axis_blocks(p->prec, p->n, 0, MR_BIN, !(p->flags & UR_C2C)), h, mr_axis_blocks(p->prec, p->n, 2, MR_GEN, !(p->flags & UR_C2C)), s);
   }
   Layout lay = layout_incore(p, p->nbins);

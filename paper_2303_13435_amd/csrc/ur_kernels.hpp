@@ -240,6 +240,12 @@ struct MrArgs {
   long long lines;
   int planes;
   int xa, xn;
+  // pruning of an in-HBM box whose density lies in the region of the level
+  // in z (L and m): the z pass skips tiles of lines that hold no density
+  // (leaving them unwritten), the y pass runs planes [px0, px0 + planes) and
+  // reads the rows outside each plane's row range as zero
+  int prune;
+  int px0;
 };
 // axis 0 = x (stride n^2), 1 = y (stride n), 2 = z (contiguous);
 // mode MR_LOAD: src -> dst, MR_GEN (axis 2): generated density -> dst,

@@ -121,11 +121,34 @@ __global__ void __launch_bounds__((MrCfg<T, N, MODE == MR_BIN>::threads), (MrCfg
       es = 1;
     } else {
       constexpr int nzt = NZT;
-      o = (int)(tile / nzt);
+      o = (AXIS == 1 ? a.px0 : 0) + (int)(tile / nzt);
       z0 = (int)(tile % nzt) * TL;
       nl = NZ - z0 < TL ? NZ - z0 : TL;
       base = AXIS == 1 ? (size_t)o * N * NZ + z0 : (size_t)o * NZ + z0;
       es = AXIS == 1 ? (size_t)NZ : (size_t)N * NZ;
+    }
+    if constexpr (AXIS == 2) {
+      // pruned box: a tile none of whose pencils can hold density is skipped
+      // (block-uniform: the barrier's OR), its lines left unwritten
+      if (a.prune) {
+        bool has = false;
+        if (t < nl) {
+          const long long line = tile * TL + t;
+          const long long X = R2C ? (2 * line) / N : line / N, Y = R2C ? (2 * line) % N : line % N;
+          long long lo, hi;
+          row_range(a.z.L, a.z.m, X, lo, hi);
+          has = Y + (R2C ? 1 : 0) >= lo && Y <= hi;
+        }
+        if (!__syncthreads_or(has)) continue;
+      }
+    }
+    // pruned y pass: rows of plane o outside its row range read as zero
+    int ylo = 0, yhi = N - 1;
+    if (AXIS == 1 && a.prune) {
+      long long lo, hi;
+      row_range(a.z.L, a.z.m, o, lo, hi);
+      ylo = (int)lo;
+      yhi = (int)hi;
     }
     if constexpr (MODE == MR_GEN) {
       // every lane of a line's slot generates elements g, g + GP, ... of it
@@ -230,7 +253,8 @@ __global__ void __launch_bounds__((MrCfg<T, N, MODE == MR_BIN>::threads), (MrCfg
               const int e = i / TL;
               v[u] = (e >= XA && e < XA + XN) ? src[base + (size_t)(e - XA) * es + i % TL] : mk((T)0, (T)0);
             } else {
-              v[u] = src[base + (size_t)(i / TL) * es + i % TL];
+              const int e = i / TL;
+              v[u] = (e >= ylo && e <= yhi) ? src[base + (size_t)e * es + i % TL] : mk((T)0, (T)0);
             }
           }
         }
