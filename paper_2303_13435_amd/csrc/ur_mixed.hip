@@ -284,10 +284,12 @@ __global__ void __launch_bounds__((MrCfg<T, N, MODE == MR_BIN>::threads), (MrCfg
     }
     __syncthreads();
     if constexpr (MODE == MR_BIN) {
-      // element (kx = e, ky = o, kz = z0 + l) of the spectrum, scaled by
-      // 1/n^3; lane g of line l's slot takes kx in [g CH, (g + 1) CH) and
-      // adds runs of equal bin in registers, one LDS atomic pair per run
-      constexpr int CH = (N + GP - 1) / GP;
+      // element (kx, ky = o, kz = z0 + l) of the spectrum, scaled by 1/n^3.
+      // Lane g of line l's slot takes |h| in [g CH, (g + 1) CH), both signs
+      // (kx = |h| and n - |h|), walking |h| upward so that n2 and the bin
+      // index never decrease: runs of equal bin are summed in registers,
+      // one LDS atomic pair per run, the next threshold held in a register.
+      constexpr int CH = (N / 2 + GP) / GP;              // |h| in [0, N/2] over GP lanes
       const int l = t / GP, g = t % GP;
       if (l < nl) {
         const int k = sidx(o, N), lz = sidx(z0 + l, N);
@@ -296,35 +298,43 @@ __global__ void __launch_bounds__((MrCfg<T, N, MODE == MR_BIN>::threads), (MrCfg
         const double wz = (R2C && z0 + l != 0 && 2 * (z0 + l) != N) ? 2.0 : 1.0;
         const T sc = (T)a.scale;
         const cx<T>* col = lds + l * PS;
-        int cur = -2;
-        double rs = 0.0, rs2 = 0.0;
-        const int e0 = g * CH, e1 = (g + 1) * CH < N ? (g + 1) * CH : N;
-        // bin of the first element from the start-of-walk table; after that
-        // n2 moves by small steps, so the bin is walked from the previous one
-        int b = -1;
-        if (e0 < e1) {
-          const int h0 = sidx(e0, N), n20 = h0 * h0 + base2;
-          b = a.lut[isqrt_ll(n20)];
-        }
-        for (int e = e0; e < e1; ++e) {
-          const cx<T> f = scale(col[pad(e)], sc);
-          if (e == 0 && base2 == 0 && o == 0 && z0 + l == 0) { a.f0[0] = (double)f.x; a.f0[1] = (double)f.y; }
-          const int h = sidx(e, N);
-          const int n2 = h * h + base2;
-          const double I = ((double)f.x * f.x + (double)f.y * f.y) * a.iscale;
-          tot += wz * I;
-          while (n2 >= Us[b + 2]) ++b;
-          while (n2 < Us[b + 1]) --b;
-          if (b != cur) {
-            if (cur >= 0 && cur < a.nbins) { atomicAdd(&hist[2 * cur], wz * rs); atomicAdd(&hist[2 * cur + 1], wz * rs2); }
-            cur = b;
-            rs = 0.0;
-            rs2 = 0.0;
+        const int h0 = g * CH, h1 = h0 + CH < N / 2 + 1 ? h0 + CH : N / 2 + 1;
+        if (h0 < h1) {
+          // bin of the first |h| from the start-of-walk table, then forward
+          const int n20 = h0 * h0 + base2;
+          int b = a.lut[isqrt_ll(n20)];
+          while (n20 >= Us[b + 2]) ++b;
+          int nextU = Us[b + 2];
+          int cur = b;
+          double rs = 0.0, rs2 = 0.0;
+          for (int ha = h0; ha < h1; ++ha) {
+            const int n2 = ha * ha + base2;
+            if (n2 >= nextU) {
+              if (cur >= 0 && cur < a.nbins) { atomicAdd(&hist[2 * cur], wz * rs); atomicAdd(&hist[2 * cur + 1], wz * rs2); }
+              rs = 0.0;
+              rs2 = 0.0;
+              ++b;
+              while (n2 >= Us[b + 2]) ++b;
+              nextU = Us[b + 2];
+              cur = b;
+            }
+            const cx<T> f1 = scale(col[pad(ha)], sc);
+            const double i1 = ((double)f1.x * f1.x + (double)f1.y * f1.y) * a.iscale;
+            double i2 = 0.0;
+            if (ha != 0 && 2 * ha != N) {                 // kx = n - |h| (the same voxel at 0 and n/2)
+              const cx<T> f2 = scale(col[pad(N - ha)], sc);
+              i2 = ((double)f2.x * f2.x + (double)f2.y * f2.y) * a.iscale;
+            } else if (ha == 0 && base2 == 0 && o == 0 && z0 + l == 0) {
+              a.f0[0] = (double)f1.x;
+              a.f0[1] = (double)f1.y;
+            }
+            tot += wz * (i1 + i2);
+            rs += i1 + i2;
+            rs2 = fma(i1, i1, rs2);
+            rs2 = fma(i2, i2, rs2);
           }
-          rs += I;
-          rs2 += I * I;
+          if (cur >= 0 && cur < a.nbins) { atomicAdd(&hist[2 * cur], wz * rs); atomicAdd(&hist[2 * cur + 1], wz * rs2); }
         }
-        if (cur >= 0 && cur < a.nbins) { atomicAdd(&hist[2 * cur], wz * rs); atomicAdd(&hist[2 * cur + 1], wz * rs2); }
       }
     } else {
       const T sc = (T)a.scale;
