@@ -28,6 +28,12 @@ namespace ur {
 #ifndef UR_MR_CAP
 #define UR_MR_CAP 0
 #endif
+// LDS of a tile outside the binning pass (72 KB: two blocks per CU; 144 KB,
+// one block of 16 lines and 128-byte segments along y and x: 1000^3 8.8 ms
+// per box against 7.85)
+#ifndef UR_MR_TILE_KB
+#define UR_MR_TILE_KB 72
+#endif
 constexpr int floor_pow2(int v) { int p = 1; while (2 * p <= v) p *= 2; return p; }
 constexpr int ceil_pow2(int v) { int p = 1; while (p < v) p *= 2; return p; }
 constexpr int cmin(int a, int b) { return a < b ? a : b; }
@@ -40,7 +46,7 @@ template <typename T, int N, bool BIN> struct MrCfg {
   static constexpr int G = Geo<N>::G, GP = ceil_pow2(G);
   static constexpr int PS = Padded<N>::size, LB = PS * (int)sizeof(cx<T>);
   static constexpr int TL0 = cmin(64, 1024 / GP);
-  static constexpr int TLa = floor_pow2(cmin(TL0, (BIN ? 76 * 1024 : 72 * 1024) / LB > 0 ? (BIN ? 76 * 1024 : 72 * 1024) / LB : 1));
+  static constexpr int TLa = floor_pow2(cmin(TL0, (BIN ? 76 * 1024 : UR_MR_TILE_KB * 1024) / LB > 0 ? (BIN ? 76 * 1024 : UR_MR_TILE_KB * 1024) / LB : 1));
   static constexpr int TLb = floor_pow2(cmin(cmin(TL0, 8), (144 * 1024) / LB > 0 ? (144 * 1024) / LB : 1));
   static constexpr int TL = (BIN || TLa >= 8) ? TLa : (TLb > TLa ? TLb : TLa);
   static constexpr int threads = TL * GP < 64 ? 64 : TL * GP;
@@ -51,11 +57,12 @@ template <typename T, int N, bool BIN> struct MrCfg {
   // 1000^3 box takes 9.1 ms instead of 5.0.
   static constexpr int minw = (UR_MR_CAP && sizeof(T) == 4 && Geo<N>::E <= 24) ? cmin(4, threads / 128 > 0 ? threads / 128 : 1) : 1;
   // twiddles of a stage loaded ahead of it (more registers, more overlap),
-  // except where two blocks per CU need 128 VGPRs or fewer: FP32 blocks of
-  // 512 threads or more whose tile leaves room for a second, which load them
-  // at each butterfly (1000^3: 11.0 ms per box against 14.4 with the hoist;
-  // 2000^3, one block of 8 waves or two of 4: 112 ms against 129 without it)
-  static constexpr bool twh = sizeof(T) != 4 || threads < 512 || TL * LB > 72 * 1024;
+  // except where the blocks the LDS holds per CU need 128 VGPRs or fewer
+  // (16 waves): FP32 tiles load them at each butterfly there (1000^3: 11.0 ms
+  // per box against 14.4 with the hoist; 2000^3, one block of 8 waves or two
+  // of 4: 112 ms against 129 without it)
+  static constexpr int BPC = (160 * 1024) / (TL * LB) > 0 ? (160 * 1024) / (TL * LB) : 1;
+  static constexpr bool twh = sizeof(T) != 4 || BPC * threads < 1024;
   static_assert(G <= 64, "mixed-radix lines lie in one wavefront");
   static_assert(threads % 64 == 0 && TL * LB <= 144 * 1024, "tile exceeds the LDS");
 };
