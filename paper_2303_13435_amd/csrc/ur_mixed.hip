@@ -182,14 +182,27 @@ __global__ void __launch_bounds__((MrCfg<T, N, MODE == MR_BIN>::threads), (MrCfg
           const T* row = (const T*)a.z.cellT + ((size_t)wrap(X - L.o - L.h) * c + wrap(Y - L.o - L.h)) * c;
           const T* row1 = (const T*)a.z.cellT + ((size_t)wrap(X - L.o - L.h) * c + wrap(Y + 1 - L.o - L.h)) * c;
           const int ilo = (int)lo, ihi = (int)hi, ilo1 = (int)lo1, ihi1 = (int)hi1;
-          for (int e = g; e < N; e += GP) {
-            const T v = (e >= ilo && e <= ihi) ? row[ci] : (T)0;
-            const T v1 = (e >= ilo1 && e <= ihi1) ? row1[ci] : (T)0;
-            col[pad(e)] = mk(v, v1);
-            s1 += (double)v + (double)v1;
-            s2 += (double)v * (double)v + (double)v1 * (double)v1;
-            ci += cstep;
-            if (ci >= c) ci -= c;
+          if (cstep == 0) {
+            // the cell edge divides the slot width: every element of this lane
+            // takes the same cell value of each pencil
+            const T cv = row[ci], cv1 = row1[ci];
+            for (int e = g; e < N; e += GP) {
+              const T v = (e >= ilo && e <= ihi) ? cv : (T)0;
+              const T v1 = (e >= ilo1 && e <= ihi1) ? cv1 : (T)0;
+              col[pad(e)] = mk(v, v1);
+              s1 += (double)v + (double)v1;
+              s2 += (double)v * (double)v + (double)v1 * (double)v1;
+            }
+          } else {
+            for (int e = g; e < N; e += GP) {
+              const T v = (e >= ilo && e <= ihi) ? row[ci] : (T)0;
+              const T v1 = (e >= ilo1 && e <= ihi1) ? row1[ci] : (T)0;
+              col[pad(e)] = mk(v, v1);
+              s1 += (double)v + (double)v1;
+              s2 += (double)v * (double)v + (double)v1 * (double)v1;
+              ci += cstep;
+              if (ci >= c) ci -= c;
+            }
           }
         } else {
           const long long X = line / N, Y = line % N;
@@ -197,13 +210,23 @@ __global__ void __launch_bounds__((MrCfg<T, N, MODE == MR_BIN>::threads), (MrCfg
           col_range(L, a.z.m, X, Y, lo, hi);
           const T* row = (const T*)a.z.cellT + ((size_t)wrap(X - L.o - L.h) * c + wrap(Y - L.o - L.h)) * c;
           const int ilo = (int)lo, ihi = (int)hi;
-          for (int e = g; e < N; e += GP) {
-            const T v = (e >= ilo && e <= ihi) ? row[ci] : (T)0;
-            col[pad(e)] = mk(v, (T)0);
-            s1 += (double)v;
-            s2 += (double)v * (double)v;
-            ci += cstep;
-            if (ci >= c) ci -= c;
+          if (cstep == 0) {
+            const T cv = row[ci];
+            for (int e = g; e < N; e += GP) {
+              const T v = (e >= ilo && e <= ihi) ? cv : (T)0;
+              col[pad(e)] = mk(v, (T)0);
+              s1 += (double)v;
+              s2 += (double)v * (double)v;
+            }
+          } else {
+            for (int e = g; e < N; e += GP) {
+              const T v = (e >= ilo && e <= ihi) ? row[ci] : (T)0;
+              col[pad(e)] = mk(v, (T)0);
+              s1 += (double)v;
+              s2 += (double)v * (double)v;
+              ci += cstep;
+              if (ci >= c) ci -= c;
+            }
           }
         }
       }
