@@ -206,12 +206,21 @@ static Layout layout_mixed_ooc(const ur_plan* p, int nbins, size_t nx) {
   return L;
 }
 
+// row pitch of the kz index of a real mixed-radix box in the workspace: n/2 + 1
+// rounded up to whole 128-byte lines, so that the y and x passes' segments of
+// consecutive kz start on line boundaries (complex boxes: n)
+static int mixed_pitch(const ur_plan* p) {
+  if (p->flags & UR_C2C) return p->nkz;
+  const int q = (int)(128 / p->cs);
+  return (p->nkz + q - 1) / q * q;
+}
+
 static Layout layout_mixed(const ur_plan* p, int nbins) {
   Layout L;
   const size_t n = p->n;
   L.A = 0;
   L.B = 0;
-  L.part = align256(n * n * (size_t)p->nkz * p->cs);  // the box (real plans: the half spectrum)
+  L.part = align256(n * n * (size_t)mixed_pitch(p) * p->cs);  // the box (real plans: the half spectrum)
   L.mom = align256(L.part + (size_t)kMaxXBlocks * (2 * (size_t)std::max(nbins, 1) + 1) * 8);
   L.f0 = align256(L.mom + n * n * 16);
   L.total = align256(L.f0 + 64 + 256 * 8);
@@ -937,6 +946,9 @@ static ur_status mr_transform(ur_plan* p, const void* src, void* S, int dir, dou
   MrArgs a{};
   a.tw = p->tw; a.dst = S; a.mom = mom; a.src = src; a.scale = 1.0;
   if (gen) a.z = *gen;
+  // the binning path's box lives in the workspace: padded rows (a spectrum
+  // written for the caller keeps the natural layout)
+  if (lay && r2c) a.nzp = mixed_pitch(p);
   long long xlo = 0, xhi = n - 1;
   double rows = (double)n * n;                       // (x, y) lines that hold data
   if (region && lay && dir < 0) {
@@ -956,7 +968,7 @@ static ur_status mr_transform(ur_plan* p, const void* src, void* S, int dir, dou
       xhi = n - 1;
     }
   }
-  const size_t plane = (size_t)n * p->nkz * p->cs;   // one x plane of the box
+  const size_t plane = (size_t)n * (a.nzp > 0 ? a.nzp : p->nkz) * p->cs;   // one x plane of the box
   {
     PassTimer tm(p, P_Z, s);
     UR_HIP(launch_mr_axis(p->prec, n, 2, dir, gen ? MR_GEN : MR_LOAD, r2c, a, s));

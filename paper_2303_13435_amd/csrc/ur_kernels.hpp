@@ -246,6 +246,9 @@ struct MrArgs {
   // reads the rows outside each plane's row range as zero
   int prune;
   int px0;
+  // real boxes in the plan's workspace: row pitch of the kz index (0: the
+  // natural n/2 + 1), rounded up so that every row starts on a 128-byte line
+  int nzp;
 };
 // axis 0 = x (stride n^2), 1 = y (stride n), 2 = z (contiguous);
 // mode MR_LOAD: src -> dst, MR_GEN (axis 2): generated density -> dst,

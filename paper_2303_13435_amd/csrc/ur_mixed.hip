@@ -85,6 +85,7 @@ __global__ void __launch_bounds__((MrCfg<T, N, MODE == MR_BIN>::threads), (MrCfg
   constexpr int U = cmin(sizeof(T) == 4 && MODE != MR_BIN ? 16 : 8, (TL * N + NT - 1) / NT);
   constexpr int NZ = R2C ? N / 2 + 1 : N;              // extent of the third index of the box
   constexpr int NZT = (NZ + TL - 1) / TL;
+  const int NZP = R2C && a.nzp > 0 ? a.nzp : NZ;       // its row pitch
   // tiles of this launch: the whole box, or the lines / planes given
   const long long NTILE = AXIS == 2 ? (a.lines > 0 ? (a.lines + TL - 1) / TL : mr_tiles<T, N, AXIS, MODE, R2C>())
                         : AXIS == 1 ? (long long)(a.planes > 0 ? a.planes : N) * NZT
@@ -131,8 +132,8 @@ __global__ void __launch_bounds__((MrCfg<T, N, MODE == MR_BIN>::threads), (MrCfg
       o = (AXIS == 1 ? a.px0 : 0) + (int)(tile / nzt);
       z0 = (int)(tile % nzt) * TL;
       nl = NZ - z0 < TL ? NZ - z0 : TL;
-      base = AXIS == 1 ? (size_t)o * N * NZ + z0 : (size_t)o * NZ + z0;
-      es = AXIS == 1 ? (size_t)NZ : (size_t)N * NZ;
+      base = AXIS == 1 ? (size_t)o * N * NZP + z0 : (size_t)o * NZP + z0;
+      es = AXIS == 1 ? (size_t)NZP : (size_t)N * NZP;
     }
     if constexpr (AXIS == 2) {
       // pruned box: a tile none of whose pencils can hold density is skipped
@@ -370,15 +371,15 @@ __global__ void __launch_bounds__((MrCfg<T, N, MODE == MR_BIN>::threads), (MrCfg
       const T sc = (T)a.scale;
       if constexpr (AXIS == 2 && R2C) {
         // unpack each line into its two pencils' half spectra: 2 nl rows of
-        // N/2 + 1 consecutive elements
-        const size_t ob = (size_t)(tile * TL) * 2 * NZ;
+        // N/2 + 1 elements, row pitch NZP
+        const size_t ob = (size_t)(tile * TL) * 2 * NZP;
         for (int i = t; i < 2 * nl * NZ; i += NT) {
           const int j = i / NZ, k = i % NZ;
           const cx<T>* col = lds + (j >> 1) * PS;
           const cx<T> zk = col[pad(k)], zm = col[pad(k == 0 ? 0 : N - k)];
           const cx<T> r = (j & 1) ? mk((zk.y + zm.y) * (T)0.5, (zm.x - zk.x) * (T)0.5)
                                   : mk((zk.x + zm.x) * (T)0.5, (zk.y - zm.y) * (T)0.5);
-          dst[ob + i] = scale(r, sc);
+          dst[ob + (size_t)j * NZP + k] = scale(r, sc);
         }
       } else if constexpr (AXIS == 2) {
         for (int i = t; i < nl * N; i += NT) dst[base + i] = scale(lds[(i / N) * PS + pad(i % N)], sc);
