@@ -1549,14 +1549,14 @@ k_pass_x_adj(XAdjArgs a) {
   if (threadIdx.x == 0) U[a.nbins + 1] = 0x7fffffff;
   __syncthreads();
   const int q = G >= 64 ? __builtin_amdgcn_readfirstlane(threadIdx.x / G) : threadIdx.x / G;
-  const int g = threadIdx.x % G;
+  const int g0 = threadIdx.x % G;
   cx<T>* s = sm + q * PS;
   const cx<T>* tw = (const cx<T>*)a.tw;
 
   // After its forward transform a group issues the loads of its next column,
   // which stay in flight during the weighting, the inverse transform and
   // the write-back of the current one.
-  auto load = [&](long long c, cx<T>* v) {
+  auto load = [&](long long c, cx<T>* v, int g) {
     const cx<T>* src = (const cx<T>*)a.B + (size_t)c * a.bs - a.bx0;
     if constexpr (G >= 64) {
       load_column_u<T, N, UR_LD_SKIP_X>(src, a.xa, a.xb, g, v);
@@ -1573,12 +1573,18 @@ k_pass_x_adj(XAdjArgs a) {
   const long long stride = (long long)gridDim.x * NG;
   long long col = (long long)blockIdx.x * NG + q;
   cx<T> v[E];
-  if (col < a.ncols) load(col, v);
+  if (col < a.ncols) load(col, v, g0);
   for (; col < a.ncols; col += stride) {
+    // UR_XADJ_REFETCH: the lane index is opaque in every column, so the
+    // twiddles of both transforms and the LDS offsets are reloaded and
+    // recomputed per column instead of held in registers across the loop
+    // (1024 points FP32: 126 VGPRs instead of 153, four blocks per CU)
+    int g = g0;
+    if constexpr (UR_XADJ_REFETCH) asm volatile("" : "+v"(g));
     const int kz = (int)(col / N), ky = (int)(col % N);
     cx<T>* src = (cx<T>*)a.B + (size_t)col * a.bs - a.bx0;
     fft_column<T, N, -1>(s, g, tw, v);
-    if (col + stride < a.ncols) load(col + stride, v);
+    if (col + stride < a.ncols) load(col + stride, v, g);
     const int k = sidx(ky, N);
     const int l = a.r2c ? kz : sidx(kz, N);
     const int base = k * k + l * l;

@@ -73,3 +73,9 @@
 #ifndef UR_X_REFETCH
 #define UR_X_REFETCH 0
 #endif
+
+// adjoint x pass: twiddles and LDS offsets reloaded per column (1) or held in
+// registers across the column loop (0)
+#ifndef UR_XADJ_REFETCH
+#define UR_XADJ_REFETCH 0
+#endif

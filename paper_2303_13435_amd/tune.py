@@ -52,6 +52,7 @@ CHOICES = {
     "UR_LD_SKIP_Y": ((1, 0), (5,), ("pass_y",), ("f32", "f64")),
     "UR_LD_SKIP_X": ((0, 1), (3, 4, 6), ("pass_x",), ("f32", "f64")),
     "UR_X_REFETCH": ((0, 1), (3, 4, 6), ("pass_x",), ("f32", "f64")),
+    "UR_XADJ_REFETCH": ((1, 0), (6,), ("fwd_adjoint",), ("f32", "f64")),
 }
 
 
