@@ -108,7 +108,6 @@ struct FinArgs {
   int nbins;
   const double* mom;        // nzb x 2 (may be null)
   int nzb;
-  double* mpart;            // 256 first-level partial sums of rho^2 (workspace)
   const double* f0;
   const double* cnt;        // per-bin voxel counts (geometry, computed with the bins)
   double* sum;
