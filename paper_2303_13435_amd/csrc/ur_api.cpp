@@ -921,7 +921,7 @@ static ur_status run_y_x(ur_plan* p, const FwdGeom& g, char* A, char* B, const L
   FinArgs fa{};
   fa.part = xa.part; fa.nblk = nxb; fa.nbins = p->nbins;
   fa.mom = nzb > 0 ? (const double*)(ws + lay.mom) : nullptr; fa.nzb = nzb;
-  fa.f0 = xa.f0; fa.cnt = p->dCount; fa.sum = h->sum; fa.sumsq = h->sumsq; fa.count = h->count; fa.totals = h->totals; fa.mean = h->mean; fa.sem = h->sem;
+  fa.mpart = (double*)(ws + lay.f0 + 64); fa.f0 = xa.f0; fa.cnt = p->dCount; fa.sum = h->sum; fa.sumsq = h->sumsq; fa.count = h->count; fa.totals = h->totals; fa.mean = h->mean; fa.sem = h->sem;
   {
     PassTimer tm(p, P_FIN, s);
     UR_HIP(launch_finalize(fa, s));
@@ -1007,7 +1007,7 @@ static ur_status mr_finalize(ur_plan* p, const Layout& lay, int nblk, const ur_h
   FinArgs fa{};
   fa.part = (const double*)(p->ws + lay.part); fa.nblk = nblk; fa.nbins = p->nbins;
   fa.mom = nzb > 0 ? (const double*)(p->ws + lay.mom) : nullptr; fa.nzb = nzb;
-  fa.f0 = (const double*)(p->ws + lay.f0); fa.cnt = p->dCount;
+  fa.mpart = (double*)(p->ws + lay.f0 + 64); fa.f0 = (const double*)(p->ws + lay.f0); fa.cnt = p->dCount;
   fa.sum = h->sum; fa.sumsq = h->sumsq; fa.count = h->count; fa.totals = h->totals; fa.mean = h->mean; fa.sem = h->sem;
   PassTimer tm(p, P_FIN, s);
   UR_HIP(launch_finalize(fa, s));
@@ -1594,7 +1594,7 @@ ur_status ur_simulate_host(ur_plan* p, const void* rho_host, int32_t x_lo, int32
   FinArgs fa{};
   fa.part = (const double*)(p->ws + lay.part); fa.nblk = nxb; fa.nbins = p->nbins;
   fa.mom = (const double*)(p->ws + lay.mom); fa.nzb = zb;
-  fa.f0 = (const double*)(p->ws + lay.f0); fa.cnt = p->dCount;
+  fa.mpart = (double*)(p->ws + lay.f0 + 64); fa.f0 = (const double*)(p->ws + lay.f0); fa.cnt = p->dCount;
   fa.sum = h->sum; fa.sumsq = h->sumsq; fa.count = h->count; fa.totals = h->totals; fa.mean = h->mean; fa.sem = h->sem;
   UR_HIP(launch_finalize(fa, s));
   return UR_OK;

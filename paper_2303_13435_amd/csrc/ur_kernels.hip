@@ -1372,12 +1372,28 @@ __global__ void __launch_bounds__(256) k_finalize(FinArgs a) {
     }
   } else {
     for (int i = t; i < a.nbins; i += 256) a.count[i] = a.cnt[i];
-    // sum of rho^2 over the z-pass blocks: thread t takes blocks t, t + 256,
-    // ... (compensated), then thread 0 adds the 256 partials in order; this
-    // block runs beside the ones reducing the bins
+    // sum of rho^2 over the z-pass blocks, beside the blocks reducing the
+    // bins: up to kFoldMoments blocks thread t takes blocks t, t + 256, ...
+    // (eight compensated sums, eight loads in flight), above that the 256
+    // first-level partials of k_moments; then thread 0 adds the 256 partials
+    // in order
     Kahan k;
-    if (a.mom)
-      for (int i = t; i < a.nzb; i += 256) k.add(a.mom[2 * (size_t)i + 1]);
+    if (a.mom && a.nzb > kFoldMoments) {
+      k.add(a.mpart[t]);
+    } else if (a.mom) {
+      Kahan kk[8];
+      int i = t;
+      for (; i + 7 * 256 < a.nzb; i += 8 * 256) {
+        double x[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) x[u] = a.mom[2 * (size_t)(i + u * 256) + 1];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) kk[u].add(x[u]);
+      }
+      for (; i < a.nzb; i += 256) kk[0].add(a.mom[2 * (size_t)i + 1]);
+#pragma unroll
+      for (int u = 0; u < 8; ++u) { k.add(kk[u].s); k.add(kk[u].c); }
+    }
     ls[t] = k.s;
     lc[t] = k.c;
     __syncthreads();
@@ -1386,6 +1402,24 @@ __global__ void __launch_bounds__(256) k_finalize(FinArgs a) {
       for (int i = 0; i < 256; ++i) { r.add(ls[i]); r.add(lc[i]); }
       a.totals[3] = a.mom ? r.val() : 0.0;
     }
+  }
+}
+
+// first level of the sum of rho^2 over many z-pass blocks: block b reduces a
+// contiguous chunk of the per-block moments in a fixed order
+__global__ void __launch_bounds__(256) k_moments(const double* __restrict__ mom, int nzb, double* __restrict__ mpart) {
+  __shared__ double ls[256], lc[256];
+  const int chunk = (nzb + gridDim.x - 1) / gridDim.x;
+  const int lo = blockIdx.x * chunk, hi = min(nzb, lo + chunk);
+  Kahan k;
+  for (int i = lo + threadIdx.x; i < hi; i += 256) k.add(mom[2 * (size_t)i + 1]);
+  ls[threadIdx.x] = k.s;
+  lc[threadIdx.x] = k.c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    Kahan r;
+    for (int i = 0; i < 256; ++i) { r.add(ls[i]); r.add(lc[i]); }
+    mpart[blockIdx.x] = r.val();
   }
 }
 
@@ -2264,6 +2298,11 @@ hipError_t launch_pass_x(int prec, int n, int mode, int dir, const XArgs& a, int
 hipError_t launch_finalize(const FinArgs& a, hipStream_t s) {
   int nv = 2 * a.nbins + 1;
   int nvb = (nv + 7) / 8;
+  if (a.mom && a.nzb > kFoldMoments) {
+    hipLaunchKernelGGL(k_moments, dim3(256), dim3(256), 0, s, a.mom, a.nzb, a.mpart);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   hipLaunchKernelGGL(k_finalize, dim3(nvb + 1), dim3(256), 0, s, a);
   return hipGetLastError();
 }

@@ -12,6 +12,9 @@ namespace ur {
 // kMaxOutOfCore through the out-of-core forward path only.
 constexpr int kMaxInCore = 2048;
 constexpr int kMaxOutOfCore = 4096;
+// z-pass blocks up to which the finalize sums their rho^2 in one block (above:
+// a first-level kernel of 256 blocks, one CU cannot read them fast enough)
+constexpr int kFoldMoments = 32768;
 
 // Density source of the first (z) pass.
 // GEN: ED-1 voxels (block factor 1); ZOOM: block-summed zoom levels.
@@ -108,6 +111,7 @@ struct FinArgs {
   int nbins;
   const double* mom;        // nzb x 2 (may be null)
   int nzb;
+  double* mpart;            // 256 first-level partial sums of rho^2 (workspace), used above kFoldMoments blocks
   const double* f0;
   const double* cnt;        // per-bin voxel counts (geometry, computed with the bins)
   double* sum;
