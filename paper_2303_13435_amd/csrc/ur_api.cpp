@@ -853,9 +853,15 @@ static ur_status prepare_cell(ur_plan* p, const ur_cell* cell, int f, CellTables
   t.cb = b + o_cb;
   t.gcell = base ? nullptr : (double*)(b + o_g);
   t.fold_part = base ? nullptr : (double*)(b + o_fp);
+  const bool spline = oriented(cell) && cell->interp == 3;
   UR_HIP(launch_cell_profiles(cell->c, cell->n_atoms, cell->xyz, cell->sigma, t.prof, s));
+  if (f == 1 && !spline) {
+    // a level of factor 1 needs only the working-precision copy: the sum writes it
+    UR_HIP(launch_cell_sum(cell->c, cell->n_atoms, cell->amp, t.prof, cell->background, t.cell64, s, p->prec, t.cellT));
+    return UR_OK;
+  }
   UR_HIP(launch_cell_sum(cell->c, cell->n_atoms, cell->amp, t.prof, cell->background, t.cell64, s));
-  if (oriented(cell) && cell->interp == 3) UR_HIP(launch_bspline_cell(cell->c, t.cell64, s));   // spline coefficients
+  if (spline) UR_HIP(launch_bspline_cell(cell->c, t.cell64, s));   // spline coefficients
   UR_HIP(launch_cell_tables(p->prec, cell->c, f, t.cell64, t.cellT, t.pre, t.cb, t.cbn, s));
   return UR_OK;
 }

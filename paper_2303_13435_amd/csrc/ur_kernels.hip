@@ -146,18 +146,36 @@ __global__ void k_cell_profiles(int c, int n_atoms, const double* __restrict__ x
   prof[t] = acc;
 }
 
-__global__ void k_cell_sum(int c, int n_atoms, const double* __restrict__ amp,
-                           const double* __restrict__ prof, double bg, double* __restrict__ cell) {
-  long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  long long c3 = (long long)c * c * c;
+// cell = background + sum over atoms of A_a p_x p_y p_z; the profiles (and
+// amplitudes) are staged in LDS when they fit (dynamic LDS of the launch),
+// else read from global memory; with cellT the working-precision copy is
+// written too (the only table of a level of factor 1)
+template <typename T>
+__global__ void __launch_bounds__(256) k_cell_sum(int c, int n_atoms, const double* __restrict__ amp,
+                                                  const double* __restrict__ prof, double bg, double* __restrict__ cell,
+                                                  T* __restrict__ cellT, int staged) {
+  extern __shared__ double lp[];                       // staged: 3 c n_atoms profiles, then n_atoms amplitudes
+  const long long c3 = (long long)c * c * c;
+  const double* P = prof;
+  const double* Am = amp;
+  if (staged) {
+    const int np = 3 * c * n_atoms;
+    for (int i = threadIdx.x; i < np; i += 256) lp[i] = prof[i];
+    for (int i = threadIdx.x; i < n_atoms; i += 256) lp[np + i] = amp[i];
+    __syncthreads();
+    P = lp;
+    Am = lp + np;
+  }
+  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= c3) return;
-  int k = (int)(v % c), j = (int)((v / c) % c), i = (int)(v / ((long long)c * c));
+  const int k = (int)(v % c), j = (int)((v / c) % c), i = (int)(v / ((long long)c * c));
   double acc = bg;
   for (int a = 0; a < n_atoms; ++a) {
-    const double* p = prof + (size_t)a * 3 * c;
-    acc += amp[a] * p[i] * p[c + j] * p[2 * c + k];
+    const double* p = P + (size_t)a * 3 * c;
+    acc += Am[a] * p[i] * p[c + j] * p[2 * c + k];
   }
   cell[v] = acc;
+  if (cellT) cellT[v] = (T)acc;
 }
 
 #endif
@@ -1998,9 +2016,16 @@ hipError_t launch_cell_profiles(int c, int n_atoms, const double* xyz, const dou
   return hipGetLastError();
 }
 
-hipError_t launch_cell_sum(int c, int n_atoms, const double* amp, const double* prof, double bg, double* cell, hipStream_t s) {
-  long long c3 = (long long)c * c * c;
-  hipLaunchKernelGGL(k_cell_sum, dim3(nblk_of(c3, 256)), dim3(256), 0, s, c, n_atoms, amp, prof, bg, cell);
+hipError_t launch_cell_sum(int c, int n_atoms, const double* amp, const double* prof, double bg, double* cell, hipStream_t s,
+                           int prec, void* cellT) {
+  const long long c3 = (long long)c * c * c;
+  const size_t lds = ((size_t)3 * c * n_atoms + n_atoms) * sizeof(double);
+  const int staged = lds <= kCellStageBytes ? 1 : 0;
+  const size_t shm = staged ? lds : 0;
+  if (prec == 1 && cellT)
+    hipLaunchKernelGGL(k_cell_sum<double>, dim3(nblk_of(c3, 256)), dim3(256), shm, s, c, n_atoms, amp, prof, bg, cell, (double*)cellT, staged);
+  else
+    hipLaunchKernelGGL(k_cell_sum<float>, dim3(nblk_of(c3, 256)), dim3(256), shm, s, c, n_atoms, amp, prof, bg, cell, (float*)cellT, staged);
   return hipGetLastError();
 }
 

@@ -15,6 +15,8 @@ constexpr int kMaxOutOfCore = 4096;
 // z-pass blocks up to which the finalize sums their rho^2 in one block (above:
 // a first-level kernel of 256 blocks, one CU cannot read them fast enough)
 constexpr int kFoldMoments = 32768;
+// atom profiles and amplitudes up to this size are staged in LDS by the cell sum
+constexpr size_t kCellStageBytes = 48 * 1024;
 
 // Density source of the first (z) pass.
 // GEN: ED-1 voxels (block factor 1); ZOOM: block-summed zoom levels.
@@ -207,7 +209,8 @@ struct FoldArgs {
 
 // host launchers (return hipError_t of the launch)
 hipError_t launch_cell_profiles(int c, int n_atoms, const double* xyz, const double* sigma, double* prof, hipStream_t s);
-hipError_t launch_cell_sum(int c, int n_atoms, const double* amp, const double* prof, double bg, double* cell, hipStream_t s);
+hipError_t launch_cell_sum(int c, int n_atoms, const double* amp, const double* prof, double bg, double* cell, hipStream_t s,
+                           int prec = 0, void* cellT = nullptr);
 hipError_t launch_cell_tables(int prec, int c, int f, const double* cell, void* cellT, double* pre, void* cb, int cbn, hipStream_t s);
 hipError_t launch_pass_z(int prec, int n, int mode, const ZArgs& a, int nblocks, hipStream_t s);
 hipError_t launch_pass_y(int prec, int n, const YArgs& a, hipStream_t s);
