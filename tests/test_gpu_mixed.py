@@ -447,3 +447,28 @@ def test_maximum_bin_count(ur, orc, n, transform):
     plan.intensity_bin(torch.as_tensor(F, dtype=plan.complex_dtype, device="cuda"), h2)
     torch.cuda.synchronize()
     compare_bins(h2.numpy(), ref, F32_BIN, "4096 bins intensity_bin", n=n)
+
+
+@pytest.mark.parametrize("transform", ["r2c", "c2c"])
+@pytest.mark.parametrize("shape", ["one_voxel", "no_mask", "cube_to_faces", "trunc_oct"])
+def test_mixed_pruning_edges(ur, orc, transform, shape):
+    """The pruned mixed-radix passes (tiles of pencils outside the particle
+    skipped, the y pass over the particle's planes with rows outside each
+    plane's range read as zero, the x pass over those planes) at the edges of
+    the region: a single voxel (one plane, one row), no mask (every plane and
+    row), a cube reaching both faces of the box, a truncated octahedron;
+    ur_simulate against the oracle at 40^3, FP32 and FP64."""
+    import torch
+    from dataclasses import replace
+    masks = {"one_voxel": W.sphere(0.5), "no_mask": W.no_mask(), "cube_to_faces": W.cube(20),
+             "trunc_oct": W.trunc_oct(15.0)}
+    for prec in (0, 1):
+        wl = replace(W.mixed(40, prec, nbins=64), transform=transform, mask=masks[shape])
+        _say(f"pruning edges {shape} {transform} prec={prec}")
+        ref = orc.simulate(wl)
+        plan = ur.Plan(40, wl.voxel, prec, c2c=transform == "c2c")
+        plan.set_bins(wl.edges)
+        h = ur.Hist(wl.nbins)
+        plan.simulate(ur.DeviceCell.from_host(wl.cell), wl.mask, wl.zoom, h)
+        torch.cuda.synchronize()
+        compare_bins(h.numpy(), ref, F32_BIN if prec == 0 else F64_BIN, f"pruning {shape}", n=40)
