@@ -377,6 +377,31 @@ def c4_fwd_adjoint(ur, W, torch, steps):
             "fwd_adjoint_amp_from_held_output_ms": round(ms_keep, 4)}
 
 
+def rotated_lattices(ur, W, torch, plan, wl, hist, steps):
+    """The M1024 box with its lattice rotated (trilinear and cubic B-spline
+    periodic sampling of the cell) and as a polycrystal of 16 grains."""
+    out = {}
+    n = max(3, steps // 2)
+    # the same box with its lattice rotated (trilinear periodic sampling of the cell)
+    rcell = ur.DeviceCell.from_host(wl.cell.with_rot(W.rotation([1.0, 2.0, 3.0], 0.7)))
+    msr, _ = time_steps(lambda: plan.simulate(rcell, wl.mask, wl.zoom, hist), n, 2, torch)
+    out["rotated_lattice"] = {"ms_per_step": round(msr, 4), "voxels_per_s": wl.n ** 3 / (msr * 1e-3),
+                              "pass_z_ms": pass_timing(plan, lambda: plan.simulate(rcell, wl.mask, wl.zoom, hist),
+                                                       5, torch)["pass_z"]["avg_ms"]}
+    # a polycrystalline particle: 16 grains of random orientation (trilinear)
+    gs, gr = W.random_grains(16, 16, 0.35 * wl.n)
+    gcell = ur.DeviceCell.from_host(wl.cell.with_grains(gs, gr, 1))
+    msg, _ = time_steps(lambda: plan.simulate(gcell, wl.mask, wl.zoom, hist), n, 2, torch)
+    out["polycrystal_16_grains"] = {"ms_per_step": round(msg, 4), "voxels_per_s": wl.n ** 3 / (msg * 1e-3)}
+    # the same with the cell sampled by the cubic B-spline (64 coefficients per voxel)
+    ccell = ur.DeviceCell.from_host(wl.cell.with_rot(W.rotation([1.0, 2.0, 3.0], 0.7), 3))
+    msc, _ = time_steps(lambda: plan.simulate(ccell, wl.mask, wl.zoom, hist), n, 2, torch)
+    out["rotated_lattice_cubic"] = {"ms_per_step": round(msc, 4), "voxels_per_s": wl.n ** 3 / (msc * 1e-3),
+                                    "pass_z_ms": pass_timing(plan, lambda: plan.simulate(ccell, wl.mask, wl.zoom, hist),
+                                                             5, torch)["pass_z"]["avg_ms"]}
+    return out
+
+
 def fwd_adjoint(ur, W, torch, plan, cell, wl, hist, steps):
     """Forward + adjoint (chi^2 gradient w.r.t. the atom amplitudes), FP32, at
     the headline box (recomputing passes Z and Y, and from the held y-pass
@@ -481,9 +506,10 @@ def main():
                     help="time only the mixed-radix boxes (1000^3, 2000^3) and print their JSON")
     ap.add_argument("--ooc4096-only", action="store_true",
                     help="only stream the 4096^3 out-of-core box and print its result (the child of the full run)")
-    ap.add_argument("--only", choices=("adjoint", "c3"),
+    ap.add_argument("--only", choices=("adjoint", "c3", "rotated"),
                     help="time only one part and print its JSON: the forward + adjoint measurements "
-                         "(1024^3 and 256^3) or the multi-zoom batch (2048^3 + 1024^3 f4 + 512^3 f16)")
+                         "(1024^3 and 256^3), the multi-zoom batch (2048^3 + 1024^3 f4 + 512^3 f16) or the "
+                         "rotated and polycrystalline lattices (1024^3)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (reference kernel for HBM byte counters)")
     args = ap.parse_args()
@@ -538,6 +564,9 @@ def main():
     if args.only == "adjoint":
         print(json.dumps(fwd_adjoint(ur, W, torch, plan, cell, wl, hist, args.steps)))
         return
+    if args.only == "rotated":
+        print(json.dumps(rotated_lattices(ur, W, torch, plan, wl, hist, args.steps)))
+        return
     ms, wall = time_steps(step, args.steps, args.warmup, torch)
     value = wl.n ** 3 / (ms * 1e-3)
     got32, got64 = hist.numpy(), None
@@ -575,23 +604,7 @@ def main():
         h64 = ur.Hist(wl.nbins)
         ms64, _ = time_steps(lambda: p64.simulate(cell, wl.mask, wl.zoom, h64), max(3, args.steps // 2), 2, torch)
         got64 = h64.numpy()
-        # the same box with its lattice rotated (trilinear periodic sampling of the cell)
-        rcell = ur.DeviceCell.from_host(wl.cell.with_rot(W.rotation([1.0, 2.0, 3.0], 0.7)))
-        msr, _ = time_steps(lambda: plan.simulate(rcell, wl.mask, wl.zoom, hist), max(3, args.steps // 2), 2, torch)
-        extras["rotated_lattice"] = {"ms_per_step": round(msr, 4), "voxels_per_s": wl.n ** 3 / (msr * 1e-3),
-                                     "pass_z_ms": pass_timing(plan, lambda: plan.simulate(rcell, wl.mask, wl.zoom, hist),
-                                                              5, torch)["pass_z"]["avg_ms"]}
-        # a polycrystalline particle: 16 grains of random orientation (trilinear)
-        gs, gr = W.random_grains(16, 16, 0.35 * wl.n)
-        gcell = ur.DeviceCell.from_host(wl.cell.with_grains(gs, gr, 1))
-        msg, _ = time_steps(lambda: plan.simulate(gcell, wl.mask, wl.zoom, hist), max(3, args.steps // 2), 2, torch)
-        extras["polycrystal_16_grains"] = {"ms_per_step": round(msg, 4), "voxels_per_s": wl.n ** 3 / (msg * 1e-3)}
-        # the same with the cell sampled by the cubic B-spline (64 coefficients per voxel)
-        ccell = ur.DeviceCell.from_host(wl.cell.with_rot(W.rotation([1.0, 2.0, 3.0], 0.7), 3))
-        msc, _ = time_steps(lambda: plan.simulate(ccell, wl.mask, wl.zoom, hist), max(3, args.steps // 2), 2, torch)
-        extras["rotated_lattice_cubic"] = {"ms_per_step": round(msc, 4), "voxels_per_s": wl.n ** 3 / (msc * 1e-3),
-                                           "pass_z_ms": pass_timing(plan, lambda: plan.simulate(ccell, wl.mask, wl.zoom, hist),
-                                                                    5, torch)["pass_z"]["avg_ms"]}
+        extras.update(rotated_lattices(ur, W, torch, plan, wl, hist, args.steps))
         extras["fp64"] = {"ms_per_step": round(ms64, 4), "voxels_per_s": wl.n ** 3 / (ms64 * 1e-3),
                           "kernels": pass_timing(p64, lambda: p64.simulate(cell, wl.mask, wl.zoom, h64), args.steps, torch)}
         note("fp64 done")
