@@ -1925,18 +1925,43 @@ __global__ void __launch_bounds__(256) k_fold(FoldArgs a, int n) {
     for (int i = threadIdx.x; i < c3; i += 256) acc[i] = 0.0;
     __syncthreads();
   }
-  for (long long pc = blockIdx.x; pc < a.npencils; pc += gridDim.x) {
-    const long long X = pc / n, Y = pc % n;
-    long long zlo, zhi;
-    col_range(a.L, a.m, X, Y, zlo, zhi);
-    if (zlo > zhi) continue;
-    const int i = pmodi(X - a.L.o - a.L.h, c), j = pmodi(Y - a.L.o - a.L.h, c);
-    const T* gp = (const T*)a.g + (size_t)pc * n;
-    for (long long z = zlo + threadIdx.x; z <= zhi; z += 256) {
-      const int k = pmodi(z - a.L.o - a.L.h, c);
-      const double val = (double)gp[z];
-      if (LDS) atomicAdd(&acc[(i * c + j) * c + k], val);
-      else atomicAdd(&a.gcell[(i * c + j) * c + k], val);
+  if constexpr (LDS) {
+    // cell edges up to 16 (powers of two): 16 threads per pencil, 16 pencils
+    // per block at a time; thread r of a pencil takes z = zlo + r, zlo + r +
+    // 16, ..., all of one cell residue (16 is a multiple of the edge), sums
+    // them in a register and adds the sum to the cell once
+    const int r = threadIdx.x & 15;
+    for (long long pc = (long long)blockIdx.x * 16 + (threadIdx.x >> 4); pc < a.npencils; pc += (long long)gridDim.x * 16) {
+      const long long X = pc / n, Y = pc % n;
+      long long zlo, zhi;
+      col_range(a.L, a.m, X, Y, zlo, zhi);
+      if (zlo > zhi) continue;
+      const int i = pmodi(X - a.L.o - a.L.h, c), j = pmodi(Y - a.L.o - a.L.h, c);
+      const T* gp = (const T*)a.g + (size_t)pc * n;
+      double sum = 0.0;
+      long long z = zlo + r;
+      for (; z + 48 <= zhi; z += 64) {
+        const double v0 = (double)gp[z], v1 = (double)gp[z + 16], v2 = (double)gp[z + 32], v3 = (double)gp[z + 48];
+        sum += v0;
+        sum += v1;
+        sum += v2;
+        sum += v3;
+      }
+      for (; z <= zhi; z += 16) sum += (double)gp[z];
+      if (zlo + r <= zhi) atomicAdd(&acc[(i * c + j) * c + pmodi(zlo + r - a.L.o - a.L.h, c)], sum);
+    }
+  } else {
+    for (long long pc = blockIdx.x; pc < a.npencils; pc += gridDim.x) {
+      const long long X = pc / n, Y = pc % n;
+      long long zlo, zhi;
+      col_range(a.L, a.m, X, Y, zlo, zhi);
+      if (zlo > zhi) continue;
+      const int i = pmodi(X - a.L.o - a.L.h, c), j = pmodi(Y - a.L.o - a.L.h, c);
+      const T* gp = (const T*)a.g + (size_t)pc * n;
+      for (long long z = zlo + threadIdx.x; z <= zhi; z += 256) {
+        const int k = pmodi(z - a.L.o - a.L.h, c);
+        atomicAdd(&a.gcell[(i * c + j) * c + k], (double)gp[z]);
+      }
     }
   }
   if (LDS) {
@@ -1950,8 +1975,21 @@ __global__ void __launch_bounds__(256) k_fold(FoldArgs a, int n) {
 __global__ void k_fold_reduce(int c3, const double* __restrict__ part, int nblk, double* __restrict__ gcell) {
   int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= c3) return;
+  // eight compensated sums (block b to sum b mod 8), eight loads in flight,
+  // then added in order
+  Kahan kk[8];
+  int b = 0;
+  for (; b + 8 <= nblk; b += 8) {
+    double x[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) x[u] = part[(size_t)(b + u) * c3 + v];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) kk[u].add(x[u]);
+  }
+  for (; b < nblk; ++b) kk[b & 7].add(part[(size_t)b * c3 + v]);
   Kahan k;
-  for (int b = 0; b < nblk; ++b) k.add(part[(size_t)b * c3 + v]);
+#pragma unroll
+  for (int u = 0; u < 8; ++u) { k.add(kk[u].s); k.add(kk[u].c); }
   gcell[v] = k.val();
 }
 
