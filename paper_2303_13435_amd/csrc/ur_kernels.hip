@@ -1972,7 +1972,7 @@ __global__ void __launch_bounds__(256) k_fold(FoldArgs a, int n) {
 }
 
 #if UR_IN(0)
-__global__ void k_fold_reduce(int c3, const double* __restrict__ part, int nblk, double* __restrict__ gcell) {
+__global__ void __launch_bounds__(256) k_fold_reduce(int c3, const double* __restrict__ part, int nblk, double* __restrict__ gcell) {
   int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= c3) return;
   // eight compensated sums (block b to sum b mod 8), eight loads in flight,
@@ -1986,7 +1986,9 @@ __global__ void k_fold_reduce(int c3, const double* __restrict__ part, int nblk,
 #pragma unroll
     for (int u = 0; u < 8; ++u) kk[u].add(x[u]);
   }
-  for (; b < nblk; ++b) kk[b & 7].add(part[(size_t)b * c3 + v]);
+#pragma unroll
+  for (int u = 0; u < 8; ++u)                        // the last nblk mod 8 blocks (compile-time indices)
+    if (b + u < nblk) kk[u].add(part[(size_t)(b + u) * c3 + v]);
   Kahan k;
 #pragma unroll
   for (int u = 0; u < 8; ++u) { k.add(kk[u].s); k.add(kk[u].c); }
