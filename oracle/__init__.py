@@ -793,6 +793,28 @@ def fold_to_cell(grad: np.ndarray, n1: int, c: int, mask) -> np.ndarray:
     return out
 
 
+def grad_amp_oriented(grad_rho_field: np.ndarray, cell, mask) -> np.ndarray:
+    """d L / d amp_a for a rotated or polycrystalline lattice (O10 with
+    O2r / O2g): the ED-1 is linear in the cell grid (interpolation is a fixed
+    linear map of the grid) and the grid is background + sum_a amp_a p_a
+    (O1), so d L / d amp_a = sum_x grad_rho(x) rho_a(x), with rho_a the
+    lattice's ED-1 of the grid of atom a alone (unit amplitude, no
+    background)."""
+    n = grad_rho_field.shape[0]
+    P = atom_profiles(cell)
+    interp = int(getattr(cell, "interp", 1))
+    seeds = getattr(cell, "grain_seed", None)
+    out = np.empty(P.shape[0])
+    for a in range(P.shape[0]):
+        grid = P[a, 0][:, None, None] * P[a, 1][None, :, None] * P[a, 2][None, None, :]
+        if seeds is not None:
+            rho_a = ed1_grains(n, grid, mask, seeds, cell.grain_rot, interp)
+        else:
+            rho_a = ed1_rot(n, grid, mask, cell.rot, interp)
+        out[a] = float(np.sum(grad_rho_field * rho_a))
+    return out
+
+
 def grad_amp(grad_rho_field: np.ndarray, cell, mask) -> np.ndarray:
     """d L / d amp_a = sum over inside voxels of grad_rho(x) * p_a(cell(x)),
     p_a the atom's separable voxel profile (O1)."""
