@@ -346,7 +346,12 @@ ur_status ur_host_free(void* ptr);
  *     grad_rho(x) = 2 Re( IFFT( G(q) F(q) ) ),  G(q) = g_bin[b(q)] / count_b,
  * (IFFT carrying 1/n^3, F of eq. 1) and, when a cell is given,
  *     grad_amp[a] = sum over inside voxels of grad_rho(x) p_a(cell(x)),
- * p_a the atom's voxel-integrated profile.  The forward transform is
+ * p_a the atom's voxel-integrated profile.  For a rotated lattice or grains
+ * (real plans) p_a(cell(x)) is the atom's cell grid read with the lattice's
+ * interpolation at the voxel's cell coordinate (the transpose of the
+ * sampler: trilinear weights, or cubic B-spline weights followed by the
+ * spline solve, which is symmetric); their amplitude gradients take cell
+ * edges up to 16 (larger: UR_ERR_UNSUPPORTED).  The forward transform is
  * recomputed, not stored.  Exactly one of rho (DEVICE density) and cell
  * (with mask and zoom factor 1) describes the density.  grad_rho (DEVICE, n^3
  * reals of the plan precision) and grad_amp (DEVICE, n_atoms doubles) may
@@ -359,7 +364,8 @@ ur_status ur_adjoint(ur_plan* plan, const void* rho, const ur_cell* cell, const 
  * the preceding ur_simulate call on this plan left in the workspace instead
  * of recomputing the z and y passes (the forward intermediate is kept rather
  * than recomputed).  Valid when the last call on the plan was ur_simulate of
- * an ED-1 box (zoom factor 1) with a real transform, with the same mask and
+ * an ED-1 box (zoom factor 1) of a lattice aligned with the box (an oriented
+ * cell: UR_ERR_UNSUPPORTED) with a real transform, with the same mask and
  * cell edge (checked: UR_ERR_STATE otherwise) and the same cell contents and
  * amplitudes (the caller's guarantee: device memory is not inspected).  The
  * held output is consumed: a second call needs a new ur_simulate.  Arguments

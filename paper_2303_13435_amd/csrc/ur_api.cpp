@@ -1655,7 +1655,10 @@ static ur_status adjoint_run(ur_plan* p, const void* rho, const ur_cell* cell, c
   if (p->nbins < 1) return fail(UR_ERR_STATE, "no bins set on the plan");
   if ((rho != nullptr) == (cell != nullptr)) return fail(UR_ERR_INVALID, "give exactly one of rho and cell");
   if (grad_amp && !cell) return fail(UR_ERR_INVALID, "grad_amp needs the cell description");
-  if (cell && oriented(cell)) return fail(UR_ERR_UNSUPPORTED, "the adjoint runs for lattices aligned with the box (rot = NULL, no grains)");
+  const bool orient = cell && oriented(cell);
+  if (orient && reuse) return fail(UR_ERR_UNSUPPORTED, "the held forward output is of a lattice aligned with the box");
+  if (orient && grad_amp && cell->c > 16)
+    return fail(UR_ERR_UNSUPPORTED, "amplitude gradients of rotated lattices and grains take cell edges up to 16");
   if (p->dSinc) return fail(UR_ERR_UNSUPPORTED, "the adjoint runs without the voxel form factor and block-transfer correction");
   if (p->mixed) return fail(UR_ERR_UNSUPPORTED, "the adjoint runs on power-of-two boxes");
   if (!grad_rho && !grad_amp) return UR_OK;
@@ -1675,6 +1678,7 @@ static ur_status adjoint_run(ur_plan* p, const void* rho, const ur_cell* cell, c
     UR_TRY(check_cell(cell));
     ur_zoom z1{n, 1};
     UR_TRY(check_level(p, cell, mask, &z1, g.L, g.m));
+    UR_TRY(set_rotation(p, cell, &z1, za));
     UR_TRY(prepare_cell(p, cell, 1, t, s));
     long long xlo, xhi;
     plane_range(g.L, g.m, xlo, xhi);
@@ -1682,7 +1686,8 @@ static ur_status adjoint_run(ur_plan* p, const void* rho, const ur_cell* cell, c
     if (xhi > n - 1) xhi = n - 1;
     g.xlo = (int)xlo; g.xhi = (int)xhi; g.gen = 1;
     za.cellT = t.cellT; za.cb = t.cb; za.pre = t.pre; za.cbn = t.cbn;
-    zmode = c2c ? Z_GEN_C2C : Z_GEN_R2C;
+    zmode = orient ? (za.cubic ? (za.ngrain ? Z_ROT3G_R2C : Z_ROT3_R2C) : (za.ngrain ? Z_ROTG_R2C : Z_ROT_R2C))
+                   : c2c ? Z_GEN_C2C : Z_GEN_R2C;
   } else {
     g.xlo = 0; g.xhi = n - 1; g.gen = 0; g.L = make_level(n, n, 1, 1);
     za.rho = rho; za.rho_x0 = 0;
@@ -1692,7 +1697,7 @@ static ur_status adjoint_run(ur_plan* p, const void* rho, const ur_cell* cell, c
   // Only the amplitude gradient wanted: every inverse pass is pruned to the
   // particle exactly like the forward ones, and the inverse z pass folds
   // straight onto the cell (the n^3 gradient box is never written).
-  const bool amp_only = cell && grad_amp && !grad_rho && !c2c;
+  const bool amp_only = cell && grad_amp && !grad_rho && !c2c && !orient;
   long long bx0 = 0, bs = n, xt0 = 0, xt1 = n / tx - 1;
   if (amp_only && g.xlo <= g.xhi) {
     xt0 = g.xlo / tx;
@@ -1751,7 +1756,15 @@ static ur_status adjoint_run(ur_plan* p, const void* rho, const ur_cell* cell, c
     if (c2c) return fail(UR_ERR_UNSUPPORTED, "amplitude gradients need an UR_R2C plan");
     FoldArgs fo{};
     fo.g = gr; fo.L = g.L; fo.m = g.m; fo.gcell = t.gcell; fo.part = t.fold_part; fo.npencils = n * n;
-    if (c <= 16) {
+    if (orient) {
+      // the sampler's adjoint onto the cell (or its spline coefficients,
+      // then through the spline solve, a symmetric linear map)
+      ZArgs zr = za;
+      zr.L = g.L; zr.m = g.m;
+      UR_HIP(launch_fold_rot(p->prec, n, zr, gr, t.fold_part, kFoldBlocks, s));
+      UR_HIP(launch_fold_reduce(c3, t.fold_part, kFoldBlocks, t.gcell, s));
+      if (za.cubic) UR_HIP(launch_bspline_cell(c, t.gcell, s));
+    } else if (c <= 16) {
       UR_HIP(launch_fold(p->prec, n, fo, kFoldBlocks, s));
       UR_HIP(launch_fold_reduce(c3, t.fold_part, kFoldBlocks, t.gcell, s));
     } else {

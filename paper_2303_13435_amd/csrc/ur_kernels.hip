@@ -1971,6 +1971,78 @@ __global__ void __launch_bounds__(256) k_fold(FoldArgs a, int n) {
   }
 }
 
+// Adjoint of the rotated and polycrystalline ED-1 sampler (factor 1): the
+// gradient at every inside voxel is spread back onto the cell values its
+// interpolation read, with the weights it read them with (trilinear: the
+// eight cell voxels around floor(u), (1 - t) or t per axis; cubic B-spline:
+// the 4 x 4 x 4 coefficients, the product of the three weight sets).  One
+// wavefront per pencil, lanes along z; every block adds into its own FP64
+// c^3 accumulator in LDS (c <= 16) and writes it out as its partial.
+template <typename T, int INTERP, bool GRAINS>
+__global__ void __launch_bounds__(256) k_fold_rot(ZArgs a, const void* __restrict__ gfield, double* __restrict__ part, int n) {
+  extern __shared__ double acc[];
+  __shared__ double grl[GRAINS ? kMaxGrains * 9 : 1];
+  const int c = a.L.c, c3 = c * c * c, cm = c - 1;
+  for (int i = threadIdx.x; i < c3; i += 256) acc[i] = 0.0;
+  if constexpr (GRAINS)
+    for (int i = threadIdx.x; i < 9 * a.ngrain; i += 256) grl[i] = (&a.grot[0][0])[i];
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const long long np = (long long)n * n;
+  for (long long pc = (long long)blockIdx.x * 4 + (threadIdx.x >> 6); pc < np; pc += (long long)gridDim.x * 4) {
+    const long long X = pc / n, Y = pc % n;
+    Pencil<T> p;
+    p.init(a, X, Y);
+    if (p.zlo > p.zhi) continue;                       // wave-uniform
+    if constexpr (GRAINS) { p.GR = grl; p.init_grains(a); }
+    const T* gp = (const T*)gfield + (size_t)pc * n;
+    for (int z = p.zlo + lane; z <= p.zhi; z += 64) {
+      const double gv = (double)gp[z];
+      double u, v, w;
+      p.template coords<GRAINS>(a, z, u, v, w);
+      const double fu = floor(u), fv = floor(v), fw = floor(w);
+      if constexpr (INTERP == 3) {
+        T wu[4], wv[4], ww[4];
+        bspline_weights<T>((T)(u - fu), wu);
+        bspline_weights<T>((T)(v - fv), wv);
+        bspline_weights<T>((T)(w - fw), ww);
+        const int i0 = (int)(long long)fu - 1, j0 = (int)(long long)fv - 1, k0 = (int)(long long)fw - 1;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const double gqr = gv * (double)wu[q] * (double)wv[r];
+            double* row = acc + (((i0 + q) & cm) * c + ((j0 + r) & cm)) * c;
+#pragma unroll
+            for (int m = 0; m < 4; ++m) atomicAdd(&row[(k0 + m) & cm], gqr * (double)ww[m]);
+          }
+      } else {
+        const double tu = (double)(T)(u - fu), tv = (double)(T)(v - fv), tw = (double)(T)(w - fw);
+        const int i0 = (int)(long long)fu & cm, i1 = (i0 + 1) & cm;
+        const int j0 = (int)(long long)fv & cm, j1 = (j0 + 1) & cm;
+        const int k0 = (int)(long long)fw & cm, k1 = (k0 + 1) & cm;
+        const double g0 = gv * (1.0 - tu), g1 = gv * tu;
+        const double g00 = g0 * (1.0 - tv), g01 = g0 * tv, g10 = g1 * (1.0 - tv), g11 = g1 * tv;
+        double* r00 = acc + (i0 * c + j0) * c;
+        double* r01 = acc + (i0 * c + j1) * c;
+        double* r10 = acc + (i1 * c + j0) * c;
+        double* r11 = acc + (i1 * c + j1) * c;
+        atomicAdd(&r00[k0], g00 * (1.0 - tw));
+        atomicAdd(&r00[k1], g00 * tw);
+        atomicAdd(&r01[k0], g01 * (1.0 - tw));
+        atomicAdd(&r01[k1], g01 * tw);
+        atomicAdd(&r10[k0], g10 * (1.0 - tw));
+        atomicAdd(&r10[k1], g10 * tw);
+        atomicAdd(&r11[k0], g11 * (1.0 - tw));
+        atomicAdd(&r11[k1], g11 * tw);
+      }
+    }
+  }
+  __syncthreads();
+  double* out = part + (size_t)blockIdx.x * c3;
+  for (int i = threadIdx.x; i < c3; i += 256) out[i] = acc[i];
+}
+
 #if UR_IN(0)
 __global__ void __launch_bounds__(256) k_fold_reduce(int c3, const double* __restrict__ part, int nblk, double* __restrict__ gcell) {
   int v = blockIdx.x * blockDim.x + threadIdx.x;
@@ -2554,6 +2626,25 @@ hipError_t launch_fold(int prec, int n, const FoldArgs& a, int nblocks, hipStrea
     if (lds) hipLaunchKernelGGL((k_fold<double, true>), dim3(nblocks), dim3(256), shm, s, a, n);
     else hipLaunchKernelGGL((k_fold<double, false>), dim3(nblocks), dim3(256), shm, s, a, n);
   }
+  return hipGetLastError();
+}
+#endif
+
+#if UR_IN(0)
+hipError_t launch_fold_rot(int prec, int n, const ZArgs& a, const void* g, double* part, int nblocks, hipStream_t s) {
+  const int c = a.L.c;
+  if (c > 16 || a.L.f != 1 || !a.rotated) return hipErrorInvalidValue;
+  const size_t shm = (size_t)c * c * c * sizeof(double);
+#define UR_FR(TT, I, G) hipLaunchKernelGGL((k_fold_rot<TT, I, G>), dim3(nblocks), dim3(256), shm, s, a, g, part, n)
+#define UR_FRT(TT)                                        \
+  if (a.cubic) {                                          \
+    if (a.ngrain) UR_FR(TT, 3, true); else UR_FR(TT, 3, false); \
+  } else {                                                \
+    if (a.ngrain) UR_FR(TT, 1, true); else UR_FR(TT, 1, false); \
+  }
+  if (prec == 0) { UR_FRT(float) } else { UR_FRT(double) }
+#undef UR_FRT
+#undef UR_FR
   return hipGetLastError();
 }
 #endif

@@ -311,6 +311,7 @@ hipError_t launch_pass_x_adj(int prec, int n, const XAdjArgs& a, int nblocks, hi
 hipError_t launch_pass_y_inv(int prec, int n, const YInvArgs& a, hipStream_t s);
 hipError_t launch_pass_z_inv(int prec, int n, int c2c, const ZInvArgs& a, hipStream_t s);
 hipError_t launch_fold(int prec, int n, const FoldArgs& a, int nblocks, hipStream_t s);
+hipError_t launch_fold_rot(int prec, int n, const ZArgs& a, const void* g, double* part, int nblocks, hipStream_t s);
 hipError_t launch_pass_z_fold(int prec, int n, const ZFoldArgs& a, int nblocks, hipStream_t s);
 hipError_t launch_fold_reduce_classes(int c, const double* part, int nblk, double* gcell, hipStream_t s);
 hipError_t launch_fold_reduce(int c3, const double* part, int nblk, double* gcell, hipStream_t s);

@@ -282,8 +282,8 @@ def test_rotated_lattice(ur, orc, n, prec, interp, c):
     through the caches): the fused forward path against the whole
     oracle (O2r, then O4-O8), the generated density voxel by voxel (the
     cubic case's spline coefficients, stored in the working precision, are
-    up to 2.4 times the cell's largest value here: same bounds); the adjoint
-    and zoomed levels refuse rotated lattices."""
+    up to 2.4 times the cell's largest value here: same bounds); amplitude
+    gradients of the 32^3 cell are refused (cell edges up to 16)."""
     import torch
     from dataclasses import replace
     base = W.small(n, c=c, n_atoms=9, seed=71, radius=0.4 * n, nbins=60, prec=prec)
@@ -306,8 +306,9 @@ def test_rotated_lattice(ur, orc, n, prec, interp, c):
     h = ur.Hist(wl.nbins)
     g = torch.zeros(wl.nbins, dtype=torch.float64, device="cuda")
     ga = torch.zeros(wl.cell.n_atoms, dtype=torch.float64, device="cuda")
-    with pytest.raises(ur.UltimaError, match="status 2"):
-        plan.adjoint(h, g, cell=cell, mask=wl.mask, grad_amp=ga)
+    if c > 16:
+        with pytest.raises(ur.UltimaError, match="status 2"):
+            plan.adjoint(h, g, cell=cell, mask=wl.mask, grad_amp=ga)
     torch.cuda.synchronize()
 
 

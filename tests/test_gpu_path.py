@@ -89,6 +89,60 @@ def test_adjoint_matches_oracle(ur, orc, prec, n, c, radius):
     assert err2 <= tol
 
 
+@pytest.mark.parametrize("prec", [1, 0])
+@pytest.mark.parametrize("kind,interp,c", [("rot", 1, 8), ("rot", 3, 16), ("grains", 1, 16), ("grains", 3, 8)])
+def test_adjoint_oriented_matches_oracle(ur, orc, prec, kind, interp, c):
+    """Adjoint of a rotated lattice and of a polycrystal (5 grains), trilinear
+    or cubic B-spline sampling, 64^3: grad_rho against the oracle's O10 and
+    grad_amp against the oracle's transpose of O2r / O2g (pinned by central
+    differences on the CPU); then grad_amp alone (the gradient box not
+    written).  The reuse entry refuses an oriented cell."""
+    import torch
+    n = 64
+    base = W.small(n, c=c, n_atoms=5, seed=91 + c, radius=0.4 * n, nbins=48, prec=prec)
+    if kind == "rot":
+        cell_h = base.cell.with_rot(W.rotation([1.0, 2.0, 3.0], 0.7), interp)
+    else:
+        seeds, rots = W.random_grains(93, 5, 0.35 * n)
+        cell_h = base.cell.with_grains(seeds, rots, interp)
+    wl = W.Workload("oriented", base.n, base.voxel, prec, base.transform, cell_h, base.mask, base.zoom, base.edges)
+    _say(f"oriented adjoint {kind} interp={interp} c={c} prec={prec}")
+    ref = orc.simulate(wl, return_fields=True)
+    rng = np.random.default_rng(95 + c)
+    g_bin = rng.standard_normal(wl.nbins) * 1e3
+    g_bin[ref["count"] == 0] = 0.0
+    grad_ref = orc.grad_rho(ref["F"], wl.voxel, wl.edges, ref["count"], g_bin)
+    amp_ref = orc.grad_amp_oriented(grad_ref, wl.cell, wl.mask)
+
+    plan = ur.Plan(n, wl.voxel, prec)
+    plan.set_bins(wl.edges)
+    cell = ur.DeviceCell.from_host(wl.cell)
+    fwd = ur.Hist(wl.nbins)
+    plan.simulate(cell, wl.mask, wl.zoom, fwd)
+    gb = torch.as_tensor(g_bin, device="cuda")
+    grad = torch.empty((n, n, n), dtype=plan.real_dtype, device="cuda")
+    gamp = torch.empty(wl.cell.n_atoms, dtype=torch.float64, device="cuda")
+    plan.adjoint(fwd, gb, cell=cell, mask=wl.mask, grad_rho=grad, grad_amp=gamp)
+    torch.cuda.synchronize()
+    assert np.array_equal(fwd.numpy()["count"], ref["count"])
+    g = grad.cpu().numpy().astype(np.float64)
+    err = np.max(np.abs(g - grad_ref)) / np.max(np.abs(grad_ref))
+    ga = gamp.cpu().numpy()
+    err_a = np.max(np.abs(ga - amp_ref)) / np.max(np.abs(amp_ref))
+    _say(f"  grad_rho rel err {err:.3e}, grad_amp rel err {err_a:.3e}")
+    tol = 1e-10 if prec == 1 else 2e-5
+    assert err <= tol and err_a <= tol
+
+    gamp2 = torch.full_like(gamp, float("nan"))
+    plan.adjoint(fwd, gb, cell=cell, mask=wl.mask, grad_amp=gamp2)
+    torch.cuda.synchronize()
+    err_b = np.max(np.abs(gamp2.cpu().numpy() - amp_ref)) / np.max(np.abs(amp_ref))
+    assert err_b <= tol, err_b
+    with pytest.raises(ur.UltimaError, match="status"):
+        plan.adjoint_reuse(fwd, gb, cell=cell, mask=wl.mask, grad_amp=gamp2)
+    torch.cuda.synchronize()
+
+
 def test_adjoint_dot_product_identity(ur):
     """<d I_b / d rho . v, g> = <v, adjoint(g)>: the adjoint of the linearised
     forward map, checked with the FP64 path by a central difference along v."""
