@@ -399,6 +399,19 @@ def rotated_lattices(ur, W, torch, plan, wl, hist, steps):
     out["rotated_lattice_cubic"] = {"ms_per_step": round(msc, 4), "voxels_per_s": wl.n ** 3 / (msc * 1e-3),
                                     "pass_z_ms": pass_timing(plan, lambda: plan.simulate(ccell, wl.mask, wl.zoom, hist),
                                                              5, torch)["pass_z"]["avg_ms"]}
+    # forward + amplitude gradients (chi^2 bin weights of one) of the rotated
+    # lattice and of the polycrystal: the adjoint recomputes passes Z and Y
+    # and folds through the sampler's transpose
+    import numpy as np
+    plan.simulate(rcell, wl.mask, wl.zoom, hist)
+    g_bin = torch.as_tensor(np.where(hist.numpy()["count"] > 0, 1.0, 0.0), device="cuda")
+    gamp = torch.empty(wl.cell.n_atoms, dtype=torch.float64, device="cuda")
+    for key, dc in (("rotated_fwd_adjoint_ms", rcell), ("polycrystal_fwd_adjoint_ms", gcell)):
+        def fa(dc=dc):
+            plan.simulate(dc, wl.mask, wl.zoom, hist)
+            plan.adjoint(hist, g_bin, cell=dc, mask=wl.mask, grad_amp=gamp)
+        ms, _ = time_steps(fa, n, 2, torch)
+        out[key] = round(ms, 4)
     return out
 
 

@@ -40,8 +40,10 @@ class BinnedIntensity(torch.autograd.Function):
     def backward(ctx, g_mean: torch.Tensor):
         g = torch.where(ctx.hist.count > 0, g_mean.to(torch.float64), torch.zeros_like(g_mean, dtype=torch.float64))
         grad = torch.empty_like(ctx.amp)
-        if ctx.plan.calls == ctx.calls and not ctx.plan.c2c:
-            # nothing ran on the plan since this forward: start from its held output
+        aligned = ctx.cell.rot is None and ctx.cell.grain_seed is None
+        if ctx.plan.calls == ctx.calls and not ctx.plan.c2c and aligned:
+            # nothing ran on the plan since this forward (of a lattice aligned
+            # with the box): start from its held output
             ctx.plan.adjoint_reuse(ctx.hist, g.contiguous(), ctx.cell, ctx.mask, grad, amp=ctx.amp)
         else:
             ctx.plan.adjoint(ctx.hist, g.contiguous(), cell=ctx.cell, mask=ctx.mask, grad_amp=grad, amp=ctx.amp)

@@ -1697,9 +1697,10 @@ static ur_status adjoint_run(ur_plan* p, const void* rho, const ur_cell* cell, c
   // Only the amplitude gradient wanted: every inverse pass is pruned to the
   // particle exactly like the forward ones, and the inverse z pass folds
   // straight onto the cell (the n^3 gradient box is never written).
-  const bool amp_only = cell && grad_amp && !grad_rho && !c2c && !orient;
+  const bool amp_fold = cell && grad_amp && !grad_rho && !c2c;
+  const bool amp_only = amp_fold && !orient;        // fused inverse z pass + fold
   long long bx0 = 0, bs = n, xt0 = 0, xt1 = n / tx - 1;
-  if (amp_only && g.xlo <= g.xhi) {
+  if (amp_fold && g.xlo <= g.xhi) {
     xt0 = g.xlo / tx;
     xt1 = g.xhi / tx;
     bx0 = xt0 * tx;
@@ -1720,18 +1721,18 @@ static ur_status adjoint_run(ur_plan* p, const void* rho, const ur_cell* cell, c
   xj.B = B; xj.bx0 = bx0; xj.bs = bs; xj.tw = p->tw; xj.nkz = p->nkz; xj.r2c = !c2c;
   const long long fx0 = (long long)(g.xlo / tx) * tx;
   xj.xa = (int)fx0; xj.xb = g.xlo <= g.xhi ? (int)((g.xhi / tx) * tx + tx - 1) : -1;
-  xj.oa = amp_only ? (int)bx0 : 0;
-  xj.ob = amp_only ? (int)(bx0 + bs - 1) : n - 1;
+  xj.oa = amp_fold ? (int)bx0 : 0;
+  xj.ob = amp_fold ? (int)(bx0 + bs - 1) : n - 1;
   xj.nbins = p->nbins; xj.U = p->dU; xj.lut = p->dLut; xj.nlut = p->nlut; xj.g_bin = g_bin; xj.count = fwd->count;
   xj.gscale = 2.0 / ((double)n * n * n) / ((double)n * n * n); xj.ncols = p->nkz * n;
   UR_HIP(launch_pass_x_adj(p->prec, n, xj, x_blocks(p, X_ADJ), s));
   YInvArgs yi{};
   yi.B = B; yi.bx0 = bx0; yi.bs = bs; yi.A = A; yi.tw = p->tw; yi.nkz = p->nkz;
   yi.xt0 = (int)xt0; yi.nxt = (int)(xt1 - xt0 + 1);
-  if (amp_only) {          // the fold reads only the particle's row tiles
+  if (amp_fold) {          // the fold reads only the particle's row tiles
     yi.rows = 1; yi.ty = zinv_tile(p->prec, n, 0); yi.L = g.L; yi.m = g.m;
   }
-  if (!amp_only || g.xlo <= g.xhi) UR_HIP(launch_pass_y_inv(p->prec, n, yi, s));
+  if (!amp_fold || g.xlo <= g.xhi) UR_HIP(launch_pass_y_inv(p->prec, n, yi, s));
   const int c = cell ? cell->c : 1, c3 = c * c * c;
   if (amp_only) {
     if (c > 16) UR_HIP(launch_zero(t.gcell, (size_t)c3 * 8, s));
@@ -1751,7 +1752,10 @@ static ur_status adjoint_run(ur_plan* p, const void* rho, const ur_cell* cell, c
   void* gr = grad_rho ? grad_rho : (void*)B;
   ZInvArgs zi{};
   zi.A = A; zi.out = gr; zi.tw = p->tw; zi.nkz = p->nkz; zi.ntiles = n / zinv_tile(p->prec, n, c2c); zi.scale = 1.0;
-  UR_HIP(launch_pass_z_inv(p->prec, n, c2c, zi, s));
+  if (amp_fold) {          // oriented lattices: only the particle's pencils, for the fold
+    zi.x0 = g.xlo; zi.nx = g.xhi - g.xlo + 1; zi.prune = 1; zi.L = g.L; zi.m = g.m;
+  }
+  if (!amp_fold || g.xlo <= g.xhi) UR_HIP(launch_pass_z_inv(p->prec, n, c2c, zi, s));
   if (grad_amp) {
     if (c2c) return fail(UR_ERR_UNSUPPORTED, "amplitude gradients need an UR_R2C plan");
     FoldArgs fo{};

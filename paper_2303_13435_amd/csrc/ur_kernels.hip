@@ -1717,7 +1717,9 @@ k_pass_y_inv(YInvArgs a) {
 
 // ---------------------------------------------------------------------------
 // inverse pass Z: A[x][kz][y] -> inverse transform along z -> real (c2r) or
-// complex box [x][y][z], times `scale`
+// complex box [x][y][z], times `scale`; optionally only a plane range and,
+// within each plane, the y tiles that meet the particle's rows (the pencils
+// an amplitude fold reads; the others are left unwritten)
 // ---------------------------------------------------------------------------
 template <typename T, int N, bool C2C>
 struct ZICfg {
@@ -1740,8 +1742,13 @@ k_pass_z_inv(ZInvArgs a) {
   constexpr int LDS_ELEMS = C2C ? TY * PS : TY * HP + NG * PS;
   __shared__ cx<T> lds[LDS_ELEMS];
   const int tile = blockIdx.x % a.ntiles;
-  const long long X = blockIdx.x / a.ntiles;
+  const long long X = a.x0 + blockIdx.x / a.ntiles;
   const int y0 = tile * TY;
+  if (a.prune) {                                        // block-uniform
+    long long lo, hi;
+    row_range(a.L, a.m, X, lo, hi);
+    if (y0 + TY - 1 < lo || y0 > hi) return;
+  }
   const cx<T>* Ap = (const cx<T>*)a.A + ((size_t)X * a.nkz) * N + y0;
   for (int idx = threadIdx.x; idx < TY * HS; idx += C::threads) {
     const int j = idx % TY, kz = idx / TY;
@@ -2599,7 +2606,8 @@ hipError_t launch_pass_y_inv(int prec, int n, const YInvArgs& a, hipStream_t s) 
 template <typename T, int N>
 static hipError_t pass_z_inv_t(int c2c, const ZInvArgs& a, hipStream_t s) {
   if constexpr (!inv_fits<T, N>()) { return hipErrorNotSupported; } else {
-  unsigned nb = (unsigned)((long long)N * a.ntiles);
+  if (a.x0 < 0 || a.nx < 0 || a.x0 + a.nx > N) return hipErrorInvalidValue;
+  unsigned nb = (unsigned)((long long)(a.nx > 0 ? a.nx : N) * a.ntiles);
   if (c2c) hipLaunchKernelGGL((k_pass_z_inv<T, N, true>), dim3(nb), dim3(ZICfg<T, N, true>::threads), 0, s, a);
   else hipLaunchKernelGGL((k_pass_z_inv<T, N, false>), dim3(nb), dim3(ZICfg<T, N, false>::threads), 0, s, a);
   return hipGetLastError();

@@ -196,6 +196,10 @@ struct ZInvArgs {
   int nkz;
   int ntiles;
   double scale;
+  int x0, nx;               // planes x0 .. x0 + nx - 1 (nx = 0: the whole box)
+  int prune;                // 1: only the y tiles that meet the particle's rows (L, m)
+  Level L;
+  MaskP m;
 };
 
 struct FoldArgs {
