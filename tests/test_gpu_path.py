@@ -143,6 +143,41 @@ def test_adjoint_oriented_matches_oracle(ur, orc, prec, kind, interp, c):
     torch.cuda.synchronize()
 
 
+@pytest.mark.parametrize("prec", [1, 0])
+def test_adjoint_oriented_large_cell(ur, orc, prec):
+    """A rotated lattice with a 32^3 cell (cubic B-spline), 64^3: the voxel
+    gradient (the recomputed oriented forward, then the inverse passes) against
+    the oracle's O10; the amplitude gradient, whose LDS fold takes cells up to
+    16^3, is refused."""
+    import torch
+    n = 64
+    base = W.small(n, c=32, n_atoms=4, seed=99, radius=0.4 * n, nbins=40, prec=prec)
+    cell_h = base.cell.with_rot(W.rotation([2.0, -1.0, 0.5], 1.1), 3)
+    wl = W.Workload("oriented32", base.n, base.voxel, prec, base.transform, cell_h, base.mask, base.zoom, base.edges)
+    _say(f"oriented adjoint, 32^3 cell, prec={prec}")
+    ref = orc.simulate(wl, return_fields=True)
+    rng = np.random.default_rng(101)
+    g_bin = rng.standard_normal(wl.nbins) * 1e3
+    g_bin[ref["count"] == 0] = 0.0
+    grad_ref = orc.grad_rho(ref["F"], wl.voxel, wl.edges, ref["count"], g_bin)
+    plan = ur.Plan(n, wl.voxel, prec)
+    plan.set_bins(wl.edges)
+    cell = ur.DeviceCell.from_host(wl.cell)
+    fwd = ur.Hist(wl.nbins)
+    plan.simulate(cell, wl.mask, wl.zoom, fwd)
+    gb = torch.as_tensor(g_bin, device="cuda")
+    grad = torch.empty((n, n, n), dtype=plan.real_dtype, device="cuda")
+    plan.adjoint(fwd, gb, cell=cell, mask=wl.mask, grad_rho=grad)
+    torch.cuda.synchronize()
+    err = np.max(np.abs(grad.cpu().numpy().astype(np.float64) - grad_ref)) / np.max(np.abs(grad_ref))
+    _say(f"  grad_rho rel err {err:.3e}")
+    assert err <= (1e-10 if prec == 1 else 2e-5)
+    gamp = torch.empty(wl.cell.n_atoms, dtype=torch.float64, device="cuda")
+    with pytest.raises(ur.UltimaError, match="status 2"):
+        plan.adjoint(fwd, gb, cell=cell, mask=wl.mask, grad_amp=gamp)
+    torch.cuda.synchronize()
+
+
 def test_adjoint_dot_product_identity(ur):
     """<d I_b / d rho . v, g> = <v, adjoint(g)>: the adjoint of the linearised
     forward map, checked with the FP64 path by a central difference along v."""
