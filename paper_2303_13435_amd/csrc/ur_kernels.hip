@@ -1985,18 +1985,22 @@ __global__ void __launch_bounds__(256) k_fold(FoldArgs a, int n) {
 // the 4 x 4 x 4 coefficients, the product of the three weight sets).  One
 // wavefront per pencil, lanes along z; every block adds into its own FP64
 // c^3 accumulator in LDS (c <= 16) and writes it out as its partial.
+// Blocks of 16 wavefronts: the partial buffer fixes the grid (one partial
+// per block), so the block size sets how many waves each SIMD runs.
+constexpr int kFoldRotThreads = 1024;
 template <typename T, int INTERP, bool GRAINS>
-__global__ void __launch_bounds__(256) k_fold_rot(ZArgs a, const void* __restrict__ gfield, double* __restrict__ part, int n) {
+__global__ void __launch_bounds__(kFoldRotThreads) k_fold_rot(ZArgs a, const void* __restrict__ gfield, double* __restrict__ part, int n) {
   extern __shared__ double acc[];
   __shared__ double grl[GRAINS ? kMaxGrains * 9 : 1];
   const int c = a.L.c, c3 = c * c * c, cm = c - 1;
-  for (int i = threadIdx.x; i < c3; i += 256) acc[i] = 0.0;
+  for (int i = threadIdx.x; i < c3; i += kFoldRotThreads) acc[i] = 0.0;
   if constexpr (GRAINS)
-    for (int i = threadIdx.x; i < 9 * a.ngrain; i += 256) grl[i] = (&a.grot[0][0])[i];
+    for (int i = threadIdx.x; i < 9 * a.ngrain; i += kFoldRotThreads) grl[i] = (&a.grot[0][0])[i];
   __syncthreads();
   const int lane = threadIdx.x & 63;
   const long long np = (long long)n * n;
-  for (long long pc = (long long)blockIdx.x * 4 + (threadIdx.x >> 6); pc < np; pc += (long long)gridDim.x * 4) {
+  constexpr int WPB = kFoldRotThreads / 64;
+  for (long long pc = (long long)blockIdx.x * WPB + (threadIdx.x >> 6); pc < np; pc += (long long)gridDim.x * WPB) {
     const long long X = pc / n, Y = pc % n;
     Pencil<T> p;
     p.init(a, X, Y);
@@ -2047,7 +2051,7 @@ __global__ void __launch_bounds__(256) k_fold_rot(ZArgs a, const void* __restric
   }
   __syncthreads();
   double* out = part + (size_t)blockIdx.x * c3;
-  for (int i = threadIdx.x; i < c3; i += 256) out[i] = acc[i];
+  for (int i = threadIdx.x; i < c3; i += kFoldRotThreads) out[i] = acc[i];
 }
 
 #if UR_IN(0)
@@ -2643,7 +2647,7 @@ hipError_t launch_fold_rot(int prec, int n, const ZArgs& a, const void* g, doubl
   const int c = a.L.c;
   if (c > 16 || a.L.f != 1 || !a.rotated) return hipErrorInvalidValue;
   const size_t shm = (size_t)c * c * c * sizeof(double);
-#define UR_FR(TT, I, G) hipLaunchKernelGGL((k_fold_rot<TT, I, G>), dim3(nblocks), dim3(256), shm, s, a, g, part, n)
+#define UR_FR(TT, I, G) hipLaunchKernelGGL((k_fold_rot<TT, I, G>), dim3(nblocks), dim3(kFoldRotThreads), shm, s, a, g, part, n)
 #define UR_FRT(TT)                                        \
   if (a.cubic) {                                          \
     if (a.ngrain) UR_FR(TT, 3, true); else UR_FR(TT, 3, false); \
