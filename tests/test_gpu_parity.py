@@ -600,6 +600,35 @@ def test_ewald_image_1024_sampled(ur, orc):
     assert np.all(ratio <= 1.0)
 
 
+def test_grains_1024_forward_matches_generated_density(ur):
+    """16 grains at 1024^3 FP32 (the benchmarked polycrystal): the fused
+    forward path (grains generated inside the z pass) against
+    ur_simulate_rho of the whole box from ur_rho_generate (checked voxel by
+    voxel against the oracle in the sampled test); the two generators must
+    agree on every voxel, so the curves agree to the transform's rounding."""
+    import torch
+    wl = W.m1024()
+    seeds, rots = W.random_grains(16, 16, 0.35 * wl.n)
+    cell = ur.DeviceCell.from_host(wl.cell.with_grains(seeds, rots, 1))
+    _say("grains 1024 forward vs generated density")
+    plan = ur.Plan(wl.n, wl.voxel, 0)
+    plan.set_bins(wl.edges)
+    h1 = ur.Hist(wl.nbins)
+    plan.simulate(cell, wl.mask, wl.zoom, h1)
+    rho = plan.rho_generate(cell, wl.mask, wl.zoom)
+    h2 = ur.Hist(wl.nbins)
+    plan.simulate_rho(rho, h2)
+    torch.cuda.synchronize()
+    a, b = h1.numpy(), h2.numpy()
+    assert np.array_equal(a["count"], b["count"])
+    pop = a["count"] > 0
+    rel = np.abs(a["mean"][pop] - b["mean"][pop]) / np.abs(b["mean"][pop])
+    _say(f"  max rel diff {rel.max():.3e}")
+    assert rel.max() <= 1e-6
+    del rho
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("kind", ["trilinear", "cubic", "grains16"])
 def test_oriented_density_1024_sampled(ur, orc, kind):
     """The rotated samplers at the size the benchmark times them: the 1024^3
