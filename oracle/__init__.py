@@ -753,12 +753,14 @@ def chi2_bin_grad(mean, count, target, rel_sigma: float = 0.01) -> np.ndarray:
 
 
 def grad_rho(F: np.ndarray, voxel: float, edges: np.ndarray, count: np.ndarray,
-             g_bin: np.ndarray) -> np.ndarray:
+             g_bin: np.ndarray, weight: np.ndarray | None = None) -> np.ndarray:
     """Gradient of L(I_b) with respect to every voxel density, given
     g_b = dL/dI_b.  With I_b = (1/count_b) sum_{q in b} |F(q)|^2 and eq. 1,
     dI_b/drho(x) = (2/count_b) sum_q Re(conj F(q) e^{-iqx}) / n^3, hence
     grad = 2 Re(IFFT(G * F)) with G(q) = g_{b(q)}/count_{b(q)} (0 for
-    unbinned q) and IFFT carrying 1/n^3."""
+    unbinned q) and IFFT carrying 1/n^3.  With an intensity weight w(q)
+    (the binned values are w |F|^2: the voxel form factor, O15, makes w the
+    square of voxel_form), the real weight enters the same way: G w F."""
     n = F.shape[0]
     U = thresholds(n, voxel, edges)
     nb = edges.size - 1
@@ -770,6 +772,8 @@ def grad_rho(F: np.ndarray, voxel: float, edges: np.ndarray, count: np.ndarray,
     Gb = np.where(count > 0, g_bin / np.maximum(count, 1.0), 0.0)
     G = np.zeros(n2.shape)
     G[ok] = Gb[b[ok]]
+    if weight is not None:
+        G = G * weight
     H = fft3d(G * F, +1) / float(n) ** 3
     return 2.0 * H.real
 

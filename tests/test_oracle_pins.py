@@ -499,6 +499,39 @@ def test_grad_rho_matches_central_differences(oracle_lib):
         assert abs(fd - grad[x, y, z]) <= 1e-6 * max(1.0, abs(fd)), (x, y, z, fd, grad[x, y, z])
 
 
+def test_grad_rho_with_voxel_form_factor_matches_central_differences(oracle_lib):
+    """The voxel form factor (O15) weights every intensity by the square of
+    voxel_form; the gradient takes that weight (O10), checked against central
+    differences of chi^2 through the weighted forward curve.  The weight is
+    far from 1 near the box's Nyquist frequencies at n = 16, so a dropped or
+    unsquared weight fails."""
+    wl = W.small(16, c=4, n_atoms=3, radius=5.0, nbins=12)
+    g = oracle_lib.cell_synth(wl.cell)
+    rho = oracle_lib.density(wl, g)
+    S = oracle_lib.voxel_form(wl.n)
+
+    def curve(r):
+        F = oracle_lib.forward(r)
+        return F, oracle_lib.bin_spectrum(F * S, wl.voxel, wl.edges)
+
+    rng = np.random.default_rng(2)
+    _, tr = curve(rho * (1 + 0.05 * rng.standard_normal(rho.shape)))
+    T = np.where(tr["count"] > 0, tr["mean"], 1.0)
+    F, r = curve(rho)
+    gb = oracle_lib.chi2_bin_grad(r["mean"], r["count"], T)
+    grad = oracle_lib.grad_rho(F, wl.voxel, wl.edges, r["count"], gb, weight=S * S)
+    plain = oracle_lib.grad_rho(F, wl.voxel, wl.edges, r["count"], gb)
+    assert np.max(np.abs(plain - grad)) > 1e-3 * np.max(np.abs(grad))
+    h = 1e-4
+    for (x, y, z) in [(8, 8, 8), (5, 9, 7), (0, 0, 0), (12, 3, 8)]:
+        rp = rho.copy(); rp[x, y, z] += h
+        rm = rho.copy(); rm[x, y, z] -= h
+        _, a = curve(rp)
+        _, b = curve(rm)
+        fd = (oracle_lib.chi2(a["mean"], a["count"], T) - oracle_lib.chi2(b["mean"], b["count"], T)) / (2 * h)
+        assert abs(fd - grad[x, y, z]) <= 1e-6 * max(1.0, abs(fd)), (x, y, z, fd, grad[x, y, z])
+
+
 def test_grad_amp_matches_central_differences(oracle_lib):
     wl = W.small(16, c=4, n_atoms=3, radius=5.0, nbins=12)
     cell = wl.cell
