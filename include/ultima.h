@@ -302,7 +302,8 @@ ur_status ur_plan_workspace_size_host(const ur_plan* plan, int32_t nbins, int32_
  * sinc(x) = sin(x)/x, for the fused forward paths and ur_intensity_bin
  * (totals[0] then sums I').  A zoom level applies its own voxel.  Allocates
  * a small table (call before capture); enable = 0 frees it.  The adjoint
- * refuses plans with the factor on (UR_ERR_UNSUPPORTED). */
+ * (ur_adjoint, ur_adjoint_reuse) then differentiates the weighted curve:
+ * each element of the weighted spectrum takes S(h) S(k) S(l) as well. */
 ur_status ur_plan_set_voxel_form(ur_plan* plan, int32_t enable);
 
 /* Block-transfer correction of a zoom level (Q-calculation and spherical
@@ -344,7 +345,10 @@ ur_status ur_host_free(void* ptr);
  * g_bin[b] = dL/dI_b (DEVICE, nbins doubles) with I_b = sum/count of the
  * forward histogram `fwd`, computes
  *     grad_rho(x) = 2 Re( IFFT( G(q) F(q) ) ),  G(q) = g_bin[b(q)] / count_b,
- * (IFFT carrying 1/n^3, F of eq. 1) and, when a cell is given,
+ * (IFFT carrying 1/n^3, F of eq. 1; with the plan's voxel form factor on,
+ * G(q) also carries that factor's weight S(h) S(k) S(l), and a plan that
+ * removes a block transfer fails with UR_ERR_UNSUPPORTED) and, when a cell
+ * is given,
  *     grad_amp[a] = sum over inside voxels of grad_rho(x) p_a(cell(x)),
  * p_a the atom's voxel-integrated profile.  For a rotated lattice or grains
  * (real plans) p_a(cell(x)) is the atom's cell grid read with the lattice's

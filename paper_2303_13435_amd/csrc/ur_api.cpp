@@ -1659,7 +1659,7 @@ static ur_status adjoint_run(ur_plan* p, const void* rho, const ur_cell* cell, c
   if (orient && reuse) return fail(UR_ERR_UNSUPPORTED, "the held forward output is of a lattice aligned with the box");
   if (orient && grad_amp && cell->c > 16)
     return fail(UR_ERR_UNSUPPORTED, "amplitude gradients of rotated lattices and grains take cell edges up to 16");
-  if (p->dSinc) return fail(UR_ERR_UNSUPPORTED, "the adjoint runs without the voxel form factor and block-transfer correction");
+  if (p->bt_f > 1) return fail(UR_ERR_UNSUPPORTED, "the adjoint runs without the block-transfer correction");
   if (p->mixed) return fail(UR_ERR_UNSUPPORTED, "the adjoint runs on power-of-two boxes");
   if (!grad_rho && !grad_amp) return UR_OK;
   if (p->n > 1024) return fail(UR_ERR_UNSUPPORTED, "the adjoint runs up to 1024^3");
@@ -1724,7 +1724,7 @@ static ur_status adjoint_run(ur_plan* p, const void* rho, const ur_cell* cell, c
   xj.oa = amp_fold ? (int)bx0 : 0;
   xj.ob = amp_fold ? (int)(bx0 + bs - 1) : n - 1;
   xj.nbins = p->nbins; xj.U = p->dU; xj.lut = p->dLut; xj.nlut = p->nlut; xj.g_bin = g_bin; xj.count = fwd->count;
-  xj.gscale = 2.0 / ((double)n * n * n) / ((double)n * n * n); xj.ncols = p->nkz * n;
+  xj.gscale = 2.0 / ((double)n * n * n) / ((double)n * n * n); xj.ncols = p->nkz * n; xj.sinc = p->dSinc;
   UR_HIP(launch_pass_x_adj(p->prec, n, xj, x_blocks(p, X_ADJ), s));
   YInvArgs yi{};
   yi.B = B; yi.bx0 = bx0; yi.bs = bs; yi.A = A; yi.tw = p->tw; yi.nkz = p->nkz;

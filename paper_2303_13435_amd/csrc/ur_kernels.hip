@@ -1640,25 +1640,38 @@ k_pass_x_adj(XAdjArgs a) {
     // the weight is rounded to the working precision once per bin
     T gv = (T)Gb[b];
     cx<T>* sp = s + pad(hlo);
+    // intensity weight of the forward binning (voxel form factor): the
+    // gradient of w |F|^2 is w times that of |F|^2, so each element's factor
+    // is G(b) S(|k|) S(|l|) S(|h|); the column part is taken in FP64 as in
+    // the forward pass, once per column
+    const T* Sw = (const T*)a.sinc;
+    const T wc = Sw ? (T)((double)Sw[k < 0 ? -k : k] * (double)Sw[l < 0 ? -l : l]) : (T)1;
+    auto weigh = [&](auto wt) {
+      constexpr bool WT = decltype(wt)::value;
 #pragma unroll
-    for (int t = 0; t < NH; ++t) {
-      const int ha = hlo + t;
-      const int n2 = ha * ha + base;
-      while (n2 >= nextU) { ++b; nextU = U[b + 1]; gv = (T)Gb[b]; }
-      cx<T>* p1 = (NH <= 16 || G == 1) ? sp + t + (G == 1 ? (t >> 4) : 0) : s + pad(ha);
-      const cx<T> f = *p1;
-      *p1 = mk(f.x * gv, f.y * gv);
-      if (ha != 0) {
-        const cx<T> f2 = s[pad(N - ha)];
-        s[pad(N - ha)] = mk(f2.x * gv, f2.y * gv);
+      for (int t = 0; t < NH; ++t) {
+        const int ha = hlo + t;
+        const int n2 = ha * ha + base;
+        while (n2 >= nextU) { ++b; nextU = U[b + 1]; gv = (T)Gb[b]; }
+        const T ge = WT ? gv * wc * Sw[ha] : gv;
+        cx<T>* p1 = (NH <= 16 || G == 1) ? sp + t + (G == 1 ? (t >> 4) : 0) : s + pad(ha);
+        const cx<T> f = *p1;
+        *p1 = mk(f.x * ge, f.y * ge);
+        if (ha != 0) {
+          const cx<T> f2 = s[pad(N - ha)];
+          s[pad(N - ha)] = mk(f2.x * ge, f2.y * ge);
+        }
       }
-    }
-    if (g == G - 1) {                                      // |h| = N/2 (kx = N/2 only)
-      const int n2 = (N / 2) * (N / 2) + base;
-      while (n2 >= nextU) { ++b; nextU = U[b + 1]; gv = (T)Gb[b]; }
-      const cx<T> f = s[pad(N / 2)];
-      s[pad(N / 2)] = mk(f.x * gv, f.y * gv);
-    }
+      if (g == G - 1) {                                    // |h| = N/2 (kx = N/2 only)
+        const int n2 = (N / 2) * (N / 2) + base;
+        while (n2 >= nextU) { ++b; nextU = U[b + 1]; gv = (T)Gb[b]; }
+        const T ge = WT ? gv * wc * Sw[N / 2] : gv;
+        const cx<T> f = s[pad(N / 2)];
+        s[pad(N / 2)] = mk(f.x * ge, f.y * ge);
+      }
+    };
+    if (Sw) weigh(std::integral_constant<bool, true>{});
+    else weigh(std::integral_constant<bool, false>{});
     col_sync<G>();
     stages_from<T, N, 1, +1>(s, g, tw);
     for (int i = a.oa + g; i <= a.ob; i += G) src[i] = s[pad(i)];

@@ -159,6 +159,7 @@ struct XAdjArgs {
   const double* count;      // forward bin counts
   double gscale;            // 2 / n^6
   int ncols;
+  const void* sinc;         // per-axis intensity weight S(|m|), m in [0, N/2], working precision, or null
 };
 
 struct YInvArgs {

@@ -395,7 +395,7 @@ def test_polycrystalline_grains(ur, orc, n, prec, interp, c):
 def test_voxel_form_factor(ur, orc, prec):
     """With the voxel form factor on: the fused path, ur_simulate_rho and
     ur_intensity_bin against the oracle with O15 applied; off again gives the
-    plain curve; the adjoint refuses the plan."""
+    plain curve (its adjoint is checked in test_gpu_path)."""
     import torch
     wl = W.small(64, c=8, n_atoms=9, seed=33, radius=22.0, nbins=50, prec=prec)
     _say(f"voxel form factor prec={prec}")
@@ -420,10 +420,6 @@ def test_voxel_form_factor(ur, orc, prec):
     plan.intensity_bin(spec, h2)
     torch.cuda.synchronize()
     compare_bins(h2.numpy(), ref_v, tol, "intensity_bin + voxel form", n=wl.n)
-    g = torch.zeros(wl.nbins, dtype=torch.float64, device="cuda")
-    ga = torch.zeros(wl.cell.n_atoms, dtype=torch.float64, device="cuda")
-    with pytest.raises(ur.UltimaError, match="status 2"):
-        plan.adjoint(h, g, cell=cell, mask=wl.mask, grad_amp=ga)
     plan.set_voxel_form(False)
     h3 = ur.Hist(wl.nbins)
     plan.simulate(cell, wl.mask, wl.zoom, h3)

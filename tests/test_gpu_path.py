@@ -90,6 +90,65 @@ def test_adjoint_matches_oracle(ur, orc, prec, n, c, radius):
 
 
 @pytest.mark.parametrize("prec", [1, 0])
+@pytest.mark.parametrize("n,c,radius", [(64, 16, 24.0), (256, 32, 100.0)])
+def test_adjoint_with_voxel_form_factor(ur, orc, prec, n, c, radius):
+    """Adjoint of the curve of the voxel-uniform density (voxel form factor
+    on): grad_rho and grad_amp against the oracle's O10 with the intensity
+    weight S(h) S(k) S(l) (pinned by central differences on the CPU), through
+    both entry points; a plan that removes a block transfer is refused."""
+    import torch
+    wl = W.small(n, c=c, n_atoms=6, seed=70 + n, radius=radius, nbins=40, prec=prec)
+    _say(f"adjoint with voxel form factor n={n} prec={prec}")
+    ref = orc.simulate(wl, return_fields=True, voxel_form_factor=True)
+    rng = np.random.default_rng(80 + n)
+    g_bin = rng.standard_normal(wl.nbins) * 1e3
+    g_bin[ref["count"] == 0] = 0.0
+    S = orc.voxel_form(n)
+    grad_ref = orc.grad_rho(ref["F"], wl.voxel, wl.edges, ref["count"], g_bin, weight=S * S)
+    amp_ref = orc.grad_amp(grad_ref, wl.cell, wl.mask)
+    plain = orc.grad_rho(ref["F"], wl.voxel, wl.edges, ref["count"], g_bin)
+    del S
+
+    plan = ur.Plan(n, wl.voxel, prec)
+    plan.set_bins(wl.edges)
+    plan.set_voxel_form(True)
+    cell = ur.DeviceCell.from_host(wl.cell)
+    fwd = ur.Hist(wl.nbins)
+    plan.simulate(cell, wl.mask, wl.zoom, fwd)
+    gb = torch.as_tensor(g_bin, device="cuda")
+    grad = torch.empty((n, n, n), dtype=plan.real_dtype, device="cuda")
+    gamp = torch.empty(wl.cell.n_atoms, dtype=torch.float64, device="cuda")
+    plan.adjoint(fwd, gb, cell=cell, mask=wl.mask, grad_rho=grad, grad_amp=gamp)
+    torch.cuda.synchronize()
+    assert np.array_equal(fwd.numpy()["count"], ref["count"])
+    g = grad.cpu().numpy().astype(np.float64)
+    scale = np.max(np.abs(grad_ref))
+    err = np.max(np.abs(g - grad_ref)) / scale
+    err_a = np.max(np.abs(gamp.cpu().numpy() - amp_ref)) / np.max(np.abs(amp_ref))
+    _say(f"  grad_rho rel err {err:.3e}, grad_amp rel err {err_a:.3e}, "
+         f"weight's effect {np.max(np.abs(plain - grad_ref)) / scale:.3e}")
+    tol = 1e-10 if prec == 1 else 2e-5
+    assert err <= tol and err_a <= tol
+    assert np.max(np.abs(plain - grad_ref)) / scale > 10 * tol     # an unweighted gradient would fail here
+
+    # amplitude gradient from the held y-pass output of a forward call
+    plan.simulate(cell, wl.mask, wl.zoom, fwd)
+    gamp2 = torch.empty_like(gamp)
+    plan.adjoint_reuse(fwd, gb, cell, wl.mask, gamp2)
+    torch.cuda.synchronize()
+    err_r = np.max(np.abs(gamp2.cpu().numpy() - amp_ref)) / np.max(np.abs(amp_ref))
+    _say(f"  reuse grad_amp rel err {err_r:.3e}")
+    assert err_r <= tol
+
+    # block-transfer removal stays refused by the adjoint, before any work
+    plan.set_block_transfer(2)
+    with pytest.raises(ur.UltimaError, match="status 2"):
+        plan.adjoint(fwd, gb, cell=cell, mask=wl.mask, grad_rho=grad)
+    plan.set_block_transfer(0)
+    torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("prec", [1, 0])
 @pytest.mark.parametrize("kind,interp,c", [("rot", 1, 8), ("rot", 3, 16), ("grains", 1, 16), ("grains", 3, 8)])
 def test_adjoint_oriented_matches_oracle(ur, orc, prec, kind, interp, c):
     """Adjoint of a rotated lattice and of a polycrystal (5 grains), trilinear
